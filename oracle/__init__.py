@@ -1,0 +1,427 @@
+"""Plain FP64 CPU oracle for the ILE extrinsic-likelihood path.
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product library.  It shares no
+code with the HIP path.  ``ile_oracle.c`` holds the per-sample likelihood of
+eq. (def:lnL:Decomposed), the Monte Carlo estimator of eq. (lnL:MonteCarlo)
+with eq. (neff), the counter-based draws and the Gaussian-mixture density;
+this module wraps it and adds definition-level numpy helpers:
+
+  * ``exact_Q``          - Q_k,lm(tau) as the direct frequency sum of eq. (QUV);
+  * ``lnL_exact``        - lnL with exact Q at the detector times (no window);
+  * ``em_fit``           - weighted EM for the mixture proposal (see its docstring);
+  * ``ln_dist_marg``     - the distance-marginalised likelihood by adaptive quadrature.
+
+Pins: ``tests/test_oracle_pins.py``.  Parity unpinned: EM trajectories with
+more than one component, the in-support mass estimates (Monte Carlo).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+MAXC, MAXD = 16, 7
+C_SI = 299792458.0
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (-O2, OpenMP, no fast-math)."""
+    import subprocess
+    src = os.path.join(_HERE, "ile_oracle.c")
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-std=c11", "-fPIC", "-shared",
+                               "-o", tmp, src, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Problem(C.Structure):
+    _fields_ = [("n_det", C.c_int), ("n_modes", C.c_int), ("n_time", C.c_int),
+                ("mode_l", C.POINTER(C.c_int)), ("mode_m", C.POINTER(C.c_int)),
+                ("det_pos", C.POINTER(C.c_double)), ("det_resp", C.POINTER(C.c_double)),
+                ("gmst", C.c_double), ("tau0", C.c_double), ("dt", C.c_double),
+                ("Q", C.POINTER(C.c_double)), ("U", C.POINTER(C.c_double)),
+                ("V", C.POINTER(C.c_double)), ("d_ref", C.c_double)]
+
+
+class _Marg(C.Structure):
+    _fields_ = [("ln_L", C.c_double), ("ln_sigma", C.c_double), ("n_eff", C.c_double),
+                ("n_ess", C.c_double), ("max_lw", C.c_double), ("argmax", C.c_int64),
+                ("n", C.c_int64), ("n_nonfinite", C.c_int64)]
+
+
+class _Prior(C.Structure):
+    _fields_ = [("t_window", C.c_double), ("d_min", C.c_double), ("d_max", C.c_double),
+                ("dist_marg", C.c_int), ("d_ref", C.c_double)]
+
+
+class _Gmm(C.Structure):
+    _fields_ = [("n_comp", C.c_int), ("n_dim", C.c_int), ("dims", C.c_int * MAXD),
+                ("weight", C.c_double * MAXC), ("mean", (C.c_double * MAXD) * MAXC),
+                ("cov", ((C.c_double * MAXD) * MAXD) * MAXC), ("ln_Z", C.c_double * MAXC),
+                ("eps_def", C.c_double)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"oracle library missing ({_LIB_PATH}); run oracle.build()")
+        L = C.CDLL(_LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.orc_antenna.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_delay.argtypes = [dp, C.c_double, C.c_double, C.c_double]
+        L.orc_delay.restype = C.c_double
+        L.orc_wigner_d.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double]
+        L.orc_wigner_d.restype = C.c_double
+        L.orc_lagrange4.argtypes = [C.c_double, dp]
+        L.orc_sample_tau.argtypes = [C.POINTER(_Problem), dp, dp]
+        L.orc_lnL_qhat.argtypes = [C.POINTER(_Problem), dp, dp, dp, dp, dp]
+        L.orc_lnL.argtypes = [C.POINTER(_Problem), C.c_int64, dp, C.c_int64, dp, dp, dp, C.c_int]
+        L.orc_marginalize.argtypes = [C.c_int64, dp, C.POINTER(_Marg)]
+        L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                        C.POINTER(C.c_uint32)]
+        L.orc_ln_prior.argtypes = [C.POINTER(_Prior), dp]
+        L.orc_ln_prior.restype = C.c_double
+        L.orc_draw_prior.argtypes = [C.POINTER(_Prior), C.c_uint64, C.c_uint32, C.c_int64,
+                                     C.c_int64, dp, C.c_int64, dp]
+        L.orc_gmm_comp_logpdf.argtypes = [C.POINTER(_Prior), C.POINTER(_Gmm), C.c_int, dp]
+        L.orc_gmm_comp_logpdf.restype = C.c_double
+        L.orc_gmm_ln_ps.argtypes = [C.POINTER(_Prior), C.POINTER(_Gmm), dp]
+        L.orc_gmm_ln_ps.restype = C.c_double
+        L.orc_draw_gmm.argtypes = [C.POINTER(_Prior), C.POINTER(_Gmm), C.c_uint64, C.c_uint32,
+                                   C.c_int64, C.c_int64, dp, C.c_int64, dp]
+        L.orc_gmm_inbox_mass.argtypes = [C.POINTER(_Prior), C.POINTER(_Gmm), C.c_int, C.c_uint64,
+                                         C.c_uint32, C.c_int64]
+        L.orc_gmm_inbox_mass.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+# ------------------------------------------------------------------ geometry
+def antenna(resp, ra, dec, psi, gmst):
+    """(F+, Fx) of one detector by the tensor definition."""
+    r = np.ascontiguousarray(resp, dtype=np.float64)
+    fp, fx = C.c_double(), C.c_double()
+    lib().orc_antenna(_dp(r), ra, dec, psi, gmst, C.byref(fp), C.byref(fx))
+    return fp.value, fx.value
+
+
+def delay(pos, ra, dec, gmst):
+    """x . n_hat / c (s); the detector time is t - delay."""
+    p = np.ascontiguousarray(pos, dtype=np.float64)
+    return lib().orc_delay(_dp(p), ra, dec, gmst)
+
+
+def wigner_d(l, mp, m, beta):
+    return lib().orc_wigner_d(l, mp, m, beta)
+
+
+def sylm(l, m, theta, phi):
+    """-2Y_lm(theta, phi)."""
+    return math.sqrt((2 * l + 1) / (4 * math.pi)) * wigner_d(l, m, 2, theta) * complex(
+        math.cos(m * phi), math.sin(m * phi))
+
+
+def lagrange4(f):
+    w = np.zeros(4)
+    lib().orc_lagrange4(f, _dp(w))
+    return w
+
+
+# ------------------------------------------------------------------ problem
+class _Holder:
+    """Keeps the numpy buffers behind an orc_problem alive."""
+
+    def __init__(self, prob):
+        K, n = prob.n_det, prob.n_modes
+        if K > 8 or n > 32:
+            raise ValueError("oracle supports at most 8 detectors and 32 modes")
+        self.ml = np.array([l for l, _ in prob.modes], dtype=np.int32)
+        self.mm = np.array([m for _, m in prob.modes], dtype=np.int32)
+        self.pos = np.ascontiguousarray(prob.det_pos, dtype=np.float64)
+        self.resp = np.ascontiguousarray(prob.det_resp, dtype=np.float64)
+        self.Q = np.ascontiguousarray(np.asarray(prob.Q, dtype=np.complex128)).view(np.float64)
+        self.U = np.ascontiguousarray(np.asarray(prob.U, dtype=np.complex128)).view(np.float64)
+        self.V = None if prob.V is None else np.ascontiguousarray(
+            np.asarray(prob.V, dtype=np.complex128)).view(np.float64)
+        ip = C.POINTER(C.c_int)
+        self.s = _Problem(K, n, prob.Q.shape[-1], self.ml.ctypes.data_as(ip),
+                          self.mm.ctypes.data_as(ip), _dp(self.pos), _dp(self.resp),
+                          prob.gmst, prob.tau0, prob.dt, _dp(self.Q), _dp(self.U),
+                          _dp(self.V) if self.V is not None else C.POINTER(C.c_double)(),
+                          prob.d_ref)
+
+
+def lnL(prob, theta, threads=None, return_terms=False):
+    """Per-sample lnL (window Q, Lagrange cubic).  theta: [7][n] (upcast to FP64)."""
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+    n = th.shape[1]
+    h = _Holder(prob)
+    out = np.empty(n)
+    T1 = np.empty(n) if return_terms else None
+    T2 = np.empty(n) if return_terms else None
+    nt = threads if threads is not None else (os.cpu_count() or 1)
+    lib().orc_lnL(C.byref(h.s), n, _dp(th), n, _dp(out),
+                  _dp(T1) if T1 is not None else C.POINTER(C.c_double)(),
+                  _dp(T2) if T2 is not None else C.POINTER(C.c_double)(), nt)
+    if return_terms:
+        return out, T1, T2
+    return out
+
+
+def sample_tau(prob, th7):
+    h = _Holder(prob)
+    t = np.ascontiguousarray(th7, dtype=np.float64)
+    tau = np.zeros(prob.n_det)
+    lib().orc_sample_tau(C.byref(h.s), _dp(t), _dp(tau))
+    return tau
+
+
+def exact_Q(f, df, hlm, data_k, tau, psd=1.0, f_lo=20.0, f_hi=1024.0):
+    """Q_lm(tau) = 2 sum_f df e^{2 pi i f tau} conj(h~_lm(f)) d~(f) / S over the band (eq. QUV)."""
+    band = (np.abs(f) >= f_lo) & (np.abs(f) <= f_hi)
+    ph = np.exp(2j * np.pi * f[band] * tau)
+    return 2.0 * df * (np.conj(hlm[:, band]) @ (ph * data_k[band])) / psd
+
+
+def lnL_exact(prob, th7, f, df, hlm, data):
+    """lnL at one sample with Q evaluated exactly at each detector time (no window)."""
+    th = np.ascontiguousarray(th7, dtype=np.float64)
+    tau = sample_tau(prob, th)
+    qh = np.stack([exact_Q(f, df, hlm, data[k], tau[k]) for k in range(prob.n_det)])
+    qri = np.ascontiguousarray(qh.astype(np.complex128)).view(np.float64)
+    h = _Holder(prob)
+    l, t1, t2 = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_lnL_qhat(C.byref(h.s), _dp(th), _dp(qri), C.byref(l), C.byref(t1), C.byref(t2))
+    return l.value, t1.value, t2.value
+
+
+# ------------------------------------------------------------- marginalise
+def marginalize(lw):
+    """Monte Carlo estimator of eq. (lnL:MonteCarlo) with eq. (neff) on given log-weights."""
+    a = np.ascontiguousarray(np.asarray(lw, dtype=np.float64))
+    m = _Marg()
+    lib().orc_marginalize(len(a), _dp(a), C.byref(m))
+    return {k: getattr(m, k) for k, _ in _Marg._fields_}
+
+
+# ------------------------------------------------------------------- draws
+def philox(ctr, key):
+    c = (C.c_uint32 * 4)(*ctr)
+    k = (C.c_uint32 * 2)(*key)
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return list(o)
+
+
+def make_prior(t_window=0.028, d_min=1.0, d_max=3000.0, dist_marg=False, d_ref=100.0):
+    return _Prior(t_window, d_min, d_max, int(dist_marg), d_ref)
+
+
+def ln_prior(prior, th7):
+    t = np.ascontiguousarray(th7, dtype=np.float64)
+    return lib().orc_ln_prior(C.byref(prior), _dp(t))
+
+
+def draw_prior(prior, seed, rnd, i0, n):
+    th = np.empty((7, n))
+    lp = np.empty(n)
+    lib().orc_draw_prior(C.byref(prior), seed, rnd, i0, n, _dp(th), n, _dp(lp))
+    return th, lp
+
+
+def make_gmm(weights, means, covs, dims, ln_Z=None, eps_def=0.05):
+    g = _Gmm()
+    nc, nd = len(weights), len(dims)
+    g.n_comp, g.n_dim = nc, nd
+    for a, d in enumerate(dims):
+        g.dims[a] = d
+    for j in range(nc):
+        g.weight[j] = float(weights[j])
+        for a in range(nd):
+            g.mean[j][a] = float(means[j][a])
+            for b in range(nd):
+                g.cov[j][a][b] = float(covs[j][a][b])
+        g.ln_Z[j] = 0.0 if ln_Z is None else float(ln_Z[j])
+    g.eps_def = eps_def
+    return g
+
+
+def gmm_comp_logpdf(prior, g, j, th7):
+    t = np.ascontiguousarray(th7, dtype=np.float64)
+    return lib().orc_gmm_comp_logpdf(C.byref(prior), C.byref(g), j, _dp(t))
+
+
+def gmm_ln_ps(prior, g, th7):
+    t = np.ascontiguousarray(th7, dtype=np.float64)
+    return lib().orc_gmm_ln_ps(C.byref(prior), C.byref(g), _dp(t))
+
+
+def draw_gmm(prior, g, seed, rnd, i0, n):
+    th = np.empty((7, n))
+    lr = np.empty(n)
+    lib().orc_draw_gmm(C.byref(prior), C.byref(g), seed, rnd, i0, n, _dp(th), n, _dp(lr))
+    return th, lr
+
+
+def gmm_inbox_mass(prior, g, j, seed, rnd, m=1 << 16):
+    return lib().orc_gmm_inbox_mass(C.byref(prior), C.byref(g), j, seed, rnd, m)
+
+
+# ----------------------------------------------------------------------- EM
+PERIODS = {0: 2 * math.pi, 5: 2 * math.pi, 6: math.pi}
+
+
+def col_range(col, t_window=0.028, d_min=1.0, d_max=3000.0):
+    return {0: 2 * math.pi, 1: math.pi, 2: 2 * t_window, 3: d_max - d_min, 4: 2.0,
+            5: 2 * math.pi, 6: math.pi}[col]
+
+
+def wrap_diff(d, period):
+    if period <= 0:
+        return d
+    r = d - period * np.floor(d / period)
+    return np.where(r > 0.5 * period, r - period, r)
+
+
+def _wrapped(X, mu, dims):
+    return np.stack([wrap_diff(X[:, a] - mu[a], PERIODS.get(c, 0.0)) for a, c in enumerate(dims)],
+                    axis=1)
+
+
+def _logpdf_rows(D, cov):
+    Lc = np.linalg.cholesky(cov)
+    y = np.linalg.solve(Lc, D.T)
+    return -0.5 * np.sum(y * y, axis=0) - np.sum(np.log(np.diag(Lc))) - 0.5 * D.shape[1] * math.log(2 * math.pi)
+
+
+def em_init(theta, lw, dims, n_comp=8, **rng_kw):
+    """First fit: means at the n_comp highest-weight distinct samples, common
+    weighted covariance (differences wrapped about the best sample), equal weights."""
+    X = np.asarray(theta, dtype=np.float64)[dims].T
+    lw = np.asarray(lw, dtype=np.float64)
+    fin = np.isfinite(lw)
+    w = np.where(fin, np.exp(np.where(fin, lw, -np.inf) - np.max(lw[fin])), 0.0)
+    order = np.argsort(-w, kind="stable")
+    means = []
+    for i in order:
+        if w[i] <= 0:
+            break
+        if any(np.array_equal(X[i], m) for m in means):
+            continue
+        means.append(X[i].copy())
+        if len(means) == n_comp:
+            break
+    while len(means) < n_comp:
+        means.append(means[-1].copy())
+    Dd = _wrapped(X, means[0], dims)
+    wn = w / w.sum()
+    mu = wn @ Dd
+    cov = (Dd * wn[:, None]).T @ Dd - np.outer(mu, mu)
+    cov = cov + np.diag([1e-8 * col_range(c, **rng_kw) ** 2 for c in dims])
+    return (np.full(n_comp, 1.0 / n_comp), np.array(means), np.array([cov] * n_comp))
+
+
+def em_step(theta, lw, dims, weights, means, covs, **rng_kw):
+    """One weighted EM iteration.
+
+    w_i = e^{lw_i - max lw}; responsibilities r_ij from the untruncated
+    components pi_j N(wrap(x_i - mu_j); 0, Sigma_j); M-step with differences
+    wrapped about the current mu_j; Sigma_j += 1e-8 diag(range^2).  A component
+    with zero total weight keeps its mean and covariance.
+    """
+    X = np.asarray(theta, dtype=np.float64)[dims].T
+    lw = np.asarray(lw, dtype=np.float64)
+    fin = np.isfinite(lw)
+    w = np.where(fin, np.exp(np.where(fin, lw, -np.inf) - np.max(lw[fin])), 0.0)
+    nc = len(weights)
+    logr = np.full((X.shape[0], nc), -np.inf)
+    Ds = []
+    for j in range(nc):
+        Dj = _wrapped(X, means[j], dims)
+        Ds.append(Dj)
+        if weights[j] > 0:
+            logr[:, j] = math.log(weights[j]) + _logpdf_rows(Dj, covs[j])
+    mx = np.max(logr, axis=1, keepdims=True)
+    r = np.exp(logr - mx)
+    r /= r.sum(axis=1, keepdims=True)
+    floor = np.diag([1e-8 * col_range(c, **rng_kw) ** 2 for c in dims])
+    W = (w[:, None] * r).sum(axis=0)
+    new_w, new_m, new_c = np.zeros(nc), np.array(means, dtype=float).copy(), np.array(covs, dtype=float).copy()
+    tot = W.sum()
+    for j in range(nc):
+        new_w[j] = W[j] / tot
+        if W[j] <= 0:
+            continue
+        g = w * r[:, j]
+        mj = (g @ Ds[j]) / W[j]
+        dd = Ds[j] - mj
+        new_c[j] = (dd * g[:, None]).T @ dd / W[j] + floor
+        mu = np.array(means[j], dtype=float) + mj
+        for a, c in enumerate(dims):
+            P = PERIODS.get(c, 0.0)
+            if P > 0:
+                mu[a] = mu[a] - P * math.floor(mu[a] / P)
+        new_m[j] = mu
+    return new_w, new_m, new_c
+
+
+def em_fit(theta, lw, dims, state=None, n_iter=8, n_comp=8, **rng_kw):
+    """Warm-started EM: ``n_iter`` iterations from ``state`` (or the first fit)."""
+    if state is None:
+        state = em_init(theta, lw, dims, n_comp=n_comp, **rng_kw)
+    w, m, c = state
+    for _ in range(n_iter):
+        w, m, c = em_step(theta, lw, dims, w, m, c, **rng_kw)
+    return w, m, c
+
+
+# ------------------------------------------------------ distance marginal
+def ln_dist_marg(T1, T2, d_ref=100.0, d_min=1.0, d_max=3000.0, prior="volume"):
+    """ln of the distance integral of exp(s T1 - s^2 T2 / 4), s = d_ref/D,
+    against p(D) = 3 D^2/(Dmax^3 - Dmin^3) ("volume") or uniform in s ("uniform_s").
+    Adaptive quadrature in s, with the exponent shifted by its maximum."""
+    from scipy.integrate import quad
+    s_lo, s_hi = d_ref / d_max, d_ref / d_min
+
+    def expo(s):
+        return s * T1 - s * s * T2 / 4.0
+
+    if prior == "volume":
+        cst = 3.0 * d_ref ** 3 / (d_max ** 3 - d_min ** 3)
+
+        def lnw(s):
+            return math.log(cst) - 4.0 * math.log(s)
+    else:
+        def lnw(s):
+            return -math.log(s_hi - s_lo)
+    grid = np.exp(np.linspace(math.log(s_lo), math.log(s_hi), 4001))
+    vals = np.array([expo(s) + lnw(s) for s in grid])
+    s_star = min(max(2.0 * T1 / T2, s_lo), s_hi) if T2 > 0 else s_hi
+    cands = list(grid) + [s_star]
+    m = max(max(vals), expo(s_star) + lnw(s_star))
+    pts = sorted({s_star, grid[int(np.argmax(vals))]})
+    width = 2.0 / math.sqrt(T2) if T2 > 0 else (s_hi - s_lo)
+    brk = sorted({min(max(p + k * width, s_lo), s_hi) for p in pts for k in (-40, -10, -3, 0, 3, 10, 40)})
+    brk = [b for b in brk if s_lo < b < s_hi]
+    edges = [s_lo] + brk + [s_hi]
+    tot = 0.0
+    for a, b in zip(edges[:-1], edges[1:]):
+        v, _ = quad(lambda s: math.exp(expo(s) + lnw(s) - m), a, b, epsabs=0.0, epsrel=1e-13,
+                    limit=500)
+        tot += v
+    del cands
+    return m + math.log(tot)

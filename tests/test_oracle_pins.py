@@ -1,0 +1,562 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the property it pins and the passage it comes from.  None of
+them re-types an oracle formula: they use closed forms, invariances, a
+brute-force sum, an independent library routine, or the data model.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import chirpgen
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+@pytest.fixture(scope="module")
+def recs():
+    return chirpgen.load_injections()
+
+
+def _event(recs, key, dets, n, mc=30.0, q=2.0, snr=20.0, noise=False, seed=7):
+    probs, ev = chirpgen.build_event(recs[key] if isinstance(key, str) else key, dets, n, mc, q,
+                                     snr, noise_seed=seed, noise=noise)
+    p = probs[0]
+    hlm = chirpgen.modes_fd(ev["f"], p.modes, mc, q, amp0=ev["amp0"])
+    return p, ev, hlm
+
+
+# --------------------------------------------------------------------- P1
+@pytest.mark.parametrize("key,dets,n,q", [("c1", ["H", "L"], 5, 2.0),
+                                          ("c2", ["H", "L", "V"], 9, 3.0),
+                                          ("c3", ["H", "L", "V"], 17, 20.0)])
+def test_P1_injection_lnL_is_half_rho2(orc, recs, key, dets, n, q):
+    """Noiseless injection, exact Q: lnL(theta_inj) = rho^2/2, and the best
+    distance scale 2 T1/T2 equals D_ref/D_inj (eq. def:lnL:Decomposed with the
+    strain model h_k = F+ h+ + Fx hx, h = h+ - i hx).  rho^2 comes from the
+    detector strains alone (no U, no Y).  Fails for F+ - iFx, a dropped V
+    term or a misplaced conjugate."""
+    p, ev, hlm = _event(recs, key, dets, n, q=q)
+    th = np.array(recs[key]["theta"])
+    l, t1, t2 = orc.lnL_exact(p, th, ev["f"], ev["df"], hlm, ev["data"])
+    rho2 = chirpgen.network_snr2(ev["f"], ev["df"], ev["strain"])
+    assert abs(rho2 - 400.0) < 1e-9
+    assert abs(l - rho2 / 2) <= 1e-9 * rho2 / 2
+    assert abs(2 * t1 / t2 - 100.0 / th[3]) <= 1e-9
+
+
+def test_P1_conjugated_response_fails(orc, recs):
+    """A planted mistake in the oracle's inputs (V conjugated, i.e. the
+    V-term written with conj(V)) breaks P1: the pin sees a wrong V term."""
+    p, ev, hlm = _event(recs, "c3", ["H", "L", "V"], 17, q=20.0)
+    th = np.array(recs["c3"]["theta"])
+    rho2 = chirpgen.network_snr2(ev["f"], ev["df"], ev["strain"])
+    bad = p.__class__(**{**p.__dict__})
+    bad.V = np.conj(p.V)   # planted: V conjugated
+    l_bad, _, _ = orc.lnL_exact(bad, th, ev["f"], ev["df"], hlm, ev["data"])
+    assert abs(l_bad - rho2 / 2) > 1e-3
+
+
+# --------------------------------------------------------------------- P2
+def test_P2_interpolant_exact_on_cubics(orc):
+    """Lagrange cubic weights reproduce samples at f = 0 and cubic polynomials."""
+    w0 = orc.lagrange4(0.0)
+    assert np.allclose(w0, [0, 1, 0, 0], atol=0, rtol=0)
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        c = rng.normal(size=4)
+        f = rng.uniform(0, 1)
+        poly = lambda x: c[0] + c[1] * x + c[2] * x * x + c[3] * x ** 3  # noqa: E731
+        w = orc.lagrange4(f)
+        val = sum(w[j] * poly(j - 1) for j in range(4))
+        assert abs(val - poly(f)) <= 1e-12 * (1 + abs(poly(f)))
+    assert abs(orc.lagrange4(0.37).sum() - 1.0) < 1e-15
+
+
+def test_P2_window_lnL_matches_interpolated_exact(orc, recs):
+    """The window path equals lnL with Q from the exact sum at the four stencil
+    times, combined with the Lagrange weights (definition of the interpolant)."""
+    p, ev, hlm = _event(recs, "c1", ["H", "L"], 5, noise=True)
+    rng = np.random.default_rng(3)
+    th = chirpgen.prior_samples(rng, 4)
+    win = orc.lnL(p, th)
+    for i in range(4):
+        t7 = th[:, i]
+        tau = orc.sample_tau(p, t7)
+        qh = []
+        for k in range(p.n_det):
+            u = (tau[k] - p.tau0) / p.dt
+            i0 = math.floor(u)
+            w = orc.lagrange4(u - i0)
+            qs = [orc.exact_Q(ev["f"], ev["df"], hlm, ev["data"][k], p.tau0 + (i0 - 1 + j) * p.dt)
+                  for j in range(4)]
+            qh.append(sum(w[j] * qs[j] for j in range(4)))
+        import ctypes as C
+        qri = np.ascontiguousarray(np.stack(qh).astype(np.complex128)).view(np.float64)
+        h = orc._Holder(p)
+        l = C.c_double()
+        d = C.c_double()
+        orc.lib().orc_lnL_qhat(C.byref(h.s), orc._dp(np.ascontiguousarray(t7)), orc._dp(qri),
+                               C.byref(l), C.byref(d), C.byref(C.c_double()))
+        assert abs(l.value - win[i]) <= 1e-9 * (1 + abs(win[i]))
+
+
+# --------------------------------------------------------------------- P3/P4
+def test_P3_psi_plus_pi_invariance(orc, recs):
+    p, ev, hlm = _event(recs, "c2", ["H", "L", "V"], 9, noise=True)
+    rng = np.random.default_rng(4)
+    th = chirpgen.prior_samples(rng, 2000)
+    th2 = th.copy()
+    th2[6] += math.pi
+    a, b = orc.lnL(p, th), orc.lnL(p, th2)
+    assert np.all(np.abs(a - b) <= 1e-12 * (1 + np.abs(a)))
+
+
+def test_P4_mode_set_invariances(orc):
+    rng = np.random.default_rng(5)
+    # {(2,+-2)}: (psi + pi/2, phi + pi/2) leaves F Y unchanged
+    p = chirpgen.random_problem(rng, 5, ["H", "L", "V"])
+    keep = [0, 4]
+    p.modes = [p.modes[a] for a in keep]
+    p.Q = p.Q[:, keep]
+    p.U = p.U[:, keep][:, :, keep]
+    p.V = p.V[:, keep][:, :, keep]
+    th = chirpgen.prior_samples(rng, 1000)
+    th2 = th.copy()
+    th2[6] += math.pi / 2
+    th2[5] += math.pi / 2
+    a, b = orc.lnL(p, th), orc.lnL(p, th2)
+    assert np.all(np.abs(a - b) <= 1e-11 * (1 + np.abs(a)))
+    # even-m only: phi + pi invariance
+    p = chirpgen.random_problem(rng, 5, ["H", "L"])
+    keep = [0, 2, 4]
+    p.modes = [p.modes[a] for a in keep]
+    p.Q, p.U, p.V = p.Q[:, keep], p.U[:, keep][:, :, keep], p.V[:, keep][:, :, keep]
+    th2 = th.copy()
+    th2[5] += math.pi
+    a, b = orc.lnL(p, th), orc.lnL(p, th2)
+    assert np.all(np.abs(a - b) <= 1e-11 * (1 + np.abs(a)))
+    # and a set with odd m is NOT phi + pi invariant
+    p = chirpgen.random_problem(rng, 5, ["H", "L"])
+    a, b = orc.lnL(p, th), orc.lnL(p, th2)
+    assert np.max(np.abs(a - b)) > 1e-3
+
+
+# --------------------------------------------------------------------- P5
+def test_P5_sylm_closed_forms(orc):
+    """-2Y_2m closed forms (Appendix on frame conventions uses -2Y_lm)."""
+    rng = np.random.default_rng(6)
+    for _ in range(20):
+        th, ph = rng.uniform(0, math.pi), rng.uniform(0, 2 * math.pi)
+        c, s = math.cos(th), math.sin(th)
+        e = lambda m: complex(math.cos(m * ph), math.sin(m * ph))  # noqa: E731
+        ref = {2: math.sqrt(5 / (64 * math.pi)) * (1 + c) ** 2 * e(2),
+               1: math.sqrt(5 / (16 * math.pi)) * s * (1 + c) * e(1),
+               0: math.sqrt(15 / (32 * math.pi)) * s * s,
+               -1: math.sqrt(5 / (16 * math.pi)) * s * (1 - c) * e(-1),
+               -2: math.sqrt(5 / (64 * math.pi)) * (1 - c) ** 2 * e(-2)}
+        for m, v in ref.items():
+            assert abs(orc.sylm(2, m, th, ph) - v) <= 1e-14
+
+
+def test_P5_sylm_sum_rule_and_pole(orc):
+    rng = np.random.default_rng(7)
+    for l in (2, 3, 4):
+        for th in rng.uniform(0, math.pi, 10):
+            tot = sum(abs(orc.sylm(l, m, th, 0.3)) ** 2 for m in range(-l, l + 1))
+            assert abs(tot - (2 * l + 1) / (4 * math.pi)) <= 1e-13
+        for m in range(-l, l + 1):
+            v = orc.sylm(l, m, 0.0, 0.4)
+            if m == 2:
+                assert abs(v) > 0.1
+            else:
+                assert abs(v) <= 1e-15
+
+
+def test_P5_sylm_orthonormal(orc):
+    """Gauss-Legendre in cos(theta) x uniform phi quadrature."""
+    x, w = np.polynomial.legendre.leggauss(24)
+    phis = np.linspace(0, 2 * math.pi, 20, endpoint=False)
+    lms = [(l, m) for l in (2, 3, 4) for m in range(-l, l + 1)]
+    vals = np.array([[[orc.sylm(l, m, math.acos(xi), ph) for ph in phis] for xi in x] for l, m in lms])
+    G = np.einsum("aij,bij,i->ab", np.conj(vals), vals, w) * (2 * math.pi / len(phis))
+    assert np.allclose(G, np.eye(len(lms)), atol=1e-12)
+
+
+# --------------------------------------------------------------------- P6
+def test_P6_antenna_identities(orc):
+    rng = np.random.default_rng(8)
+    for name in ("H", "L", "V"):
+        pos, resp = chirpgen.detector(name)
+        assert abs(np.trace(resp)) < 1e-15 and np.allclose(resp, resp.T)
+        for _ in range(20):
+            ra, dec, psi, g = rng.uniform(0, 6.28), rng.uniform(-1.5, 1.5), rng.uniform(0, 3.14), rng.uniform(0, 6.28)
+            f0 = complex(*orc.antenna(resp, ra, dec, 0.0, g))
+            f1 = complex(*orc.antenna(resp, ra, dec, psi, g))
+            f2 = complex(*orc.antenna(resp, ra, dec, psi + math.pi / 2, g))
+            assert abs(abs(f1) - abs(f0)) < 1e-14
+            assert abs(f2 + f1) < 1e-14
+            assert abs(f1 - f0 * complex(math.cos(2 * psi), -math.sin(2 * psi))) < 1e-14
+
+
+def test_P6_antenna_textbook_detector_frame(orc):
+    """Detector at the pole, arms along x and y: F+^2 + Fx^2 equals the
+    detector-frame closed form (1/4)(1+cos^2 th)^2 cos^2 2ph + cos^2 th sin^2 2ph."""
+    resp = 0.5 * (np.outer([1, 0, 0], [1, 0, 0]) - np.outer([0, 1, 0], [0, 1, 0]))
+    rng = np.random.default_rng(9)
+    for _ in range(50):
+        th, ph, psi = rng.uniform(0, math.pi), rng.uniform(0, 2 * math.pi), rng.uniform(0, math.pi)
+        fp, fx = orc.antenna(resp, ph, math.pi / 2 - th, psi, 0.0)
+        ref = 0.25 * (1 + math.cos(th) ** 2) ** 2 * math.cos(2 * ph) ** 2 + math.cos(th) ** 2 * math.sin(2 * ph) ** 2
+        assert abs(fp * fp + fx * fx - ref) < 1e-14
+    fp, fx = orc.antenna(resp, 0.3, math.pi / 2, 0.2, 0.0)   # zenith
+    assert abs(math.hypot(fp, fx) - 1.0) < 1e-14
+
+
+def test_A3_zenith_arrives_first(orc):
+    """A source at detector k's zenith (geocentric direction of x_k) reaches it
+    |x_k|/c before the geocentre: tau_k - t = -|x_k|/c."""
+    for name in ("H", "L", "V"):
+        pos, _ = chirpgen.detector(name)
+        r = np.linalg.norm(pos)
+        dec = math.asin(pos[2] / r)
+        ra = math.atan2(pos[1], pos[0]) + 1.1
+        d = orc.delay(pos, ra, dec, 1.1)
+        assert abs(d - r / chirpgen.C_SI) < 1e-15
+
+
+# --------------------------------------------------------------------- P7
+def test_P7_exactly_quadratic_in_s(orc, recs):
+    p, ev, hlm = _event(recs, "c2", ["H", "L", "V"], 9, noise=True)
+    rng = np.random.default_rng(10)
+    th = chirpgen.prior_samples(rng, 500)
+    _, T1, T2 = orc.lnL(p, th, return_terms=True)
+    assert np.all(T2 >= -1e-12 * np.abs(T2).max())
+    Ds = [200.0, 700.0, 2500.0]
+    L = []
+    for D in Ds:
+        t = th.copy()
+        t[3] = D
+        L.append(orc.lnL(p, t))
+    s = np.array([100.0 / D for D in Ds])
+    A = np.stack([s, -s * s / 4], axis=1)
+    sol = np.linalg.solve(A[:2], np.stack(L[:2]))
+    assert np.allclose(sol[0], T1, rtol=1e-11, atol=1e-9)
+    assert np.allclose(sol[1], T2, rtol=1e-11, atol=1e-9)
+    pred = s[2] * sol[0] - s[2] ** 2 * sol[1] / 4
+    assert np.allclose(pred, L[2], rtol=1e-11, atol=1e-9)
+
+
+# --------------------------------------------------------------------- P8
+@pytest.mark.slow
+def test_P8_noise_statistics(orc, recs):
+    """Over noise realisations: E lnL(theta_inj) = rho^2/2, Var = rho^2;
+    E |Q_noise|^2 = U_aa (eq. QUV with the stated noise model)."""
+    rec = recs["c1"]
+    th = np.array(rec["theta"])
+    vals, qn = [], []
+    for seed in range(160):
+        p, ev, hlm = _event(recs, "c1", ["H", "L"], 5, noise=True, seed=1000 + seed)
+        vals.append(orc.lnL_exact(p, th, ev["f"], ev["df"], hlm, ev["data"])[0])
+        noise = ev["data"] - ev["strain"]
+        qn.append(orc.exact_Q(ev["f"], ev["df"], hlm, noise[0], 0.0013))
+    vals = np.array(vals)
+    n = len(vals)
+    rho2 = 400.0
+    assert abs(vals.mean() - rho2 / 2) < 4 * math.sqrt(rho2 / n)
+    assert abs(vals.var(ddof=1) / rho2 - 1) < 4 * math.sqrt(2 / (n - 1))
+    e = np.mean(np.abs(np.array(qn)) ** 2, axis=0)
+    U = np.real(np.diag(p.U[0]))
+    assert np.all(np.abs(e / U - 1) < 4 * math.sqrt(1.0 / n) + 0.02)
+
+
+# --------------------------------------------------------------------- P9
+def test_P9_face_on_single_mode_matched_filter(orc, recs):
+    """Mode set {(2,2)}, iota = 0, one detector: V_22,22 = 0 for a one-sided
+    h_22 spectrum, and the maximum of lnL over (D, phi_c) equals the complex
+    matched-filter value |Q|^2/U."""
+    p, ev, hlm = _event(recs, "c1", ["H"], 5, noise=True)
+    a = p.modes.index((2, 2))
+    p.modes = [(2, 2)]
+    p.Q, p.U, p.V = p.Q[:, [a]], p.U[:, [a]][:, :, [a]], p.V[:, [a]][:, :, [a]]
+    assert abs(p.V[0, 0, 0]) < 1e-12 * abs(p.U[0, 0, 0])
+    th = np.array(recs["c1"]["theta"])
+    th[4] = 1.0
+    tau = orc.sample_tau(p, th)[0]
+    u = (tau - p.tau0) / p.dt
+    i0 = math.floor(u)
+    w = orc.lagrange4(u - i0)
+    qh = sum(w[j] * p.Q[0, 0, i0 - 1 + j] for j in range(4))
+    U = p.U[0, 0, 0].real
+    target = abs(qh) ** 2 / U
+    F = complex(*orc.antenna(p.det_resp[0], th[0], th[1], th[6], p.gmst))
+    y = orc.sylm(2, 2, 0.0, 0.0)
+    zstar = 2 * qh / U                       # optimal complex amplitude s F Y
+    s = abs(zstar) / abs(F * y)
+    # Y22(0, -phi) = y e^{-2 i phi}:  arg(F y) - 2 phi = arg(z*)
+    phi = (np.angle(F * y) - np.angle(zstar)) / 2
+    t = th.copy()
+    t[3] = 100.0 / s
+    t[5] = phi % (2 * math.pi)
+    best = orc.lnL(p, t[:, None])[0]
+    assert abs(best - target) <= 1e-10 * target
+    for dphi, ds in [(0.01, 1.0), (0.0, 1.01), (-0.02, 0.99)]:
+        t2 = t.copy()
+        t2[5] = (phi + dphi) % (2 * math.pi)
+        t2[3] = 100.0 / (s * ds)
+        assert orc.lnL(p, t2[:, None])[0] < best
+
+
+# --------------------------------------------------------------------- P10
+def test_P10_logsumexp_vs_mpmath(orc):
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    rng = np.random.default_rng(11)
+    lw = rng.uniform(-1e5, 1e5, 3000)
+    lw[:2000] = rng.uniform(9.99e4, 1e5, 2000)
+    r = orc.marginalize(lw)
+    s1 = mpmath.fsum(mpmath.exp(mpmath.mpf(float(x))) for x in lw)
+    s2 = mpmath.fsum(mpmath.exp(2 * mpmath.mpf(float(x))) for x in lw)
+    ref = mpmath.log(s1) - mpmath.log(len(lw))
+    assert abs(r["ln_L"] - float(ref)) <= 1e-12 * abs(float(ref))
+    m = mpmath.mpf(float(lw.max()))
+    assert abs(r["n_eff"] - float(s1 / mpmath.exp(m))) <= 1e-12 * r["n_eff"]
+    assert abs(r["n_ess"] - float(s1 * s1 / s2)) <= 1e-12 * r["n_ess"]
+    N = len(lw)
+    var = (N * s2 / (s1 * s1) - 1) / (N - 1)
+    assert abs(r["ln_sigma"] - float(ref + mpmath.log(var) / 2)) <= 1e-10
+
+
+def test_P10_neff_special_cases(orc):
+    r = orc.marginalize(np.full(1000, -3.5))
+    assert abs(r["n_eff"] - 1000) < 1e-9 and abs(r["n_ess"] - 1000) < 1e-9
+    assert abs(r["ln_L"] + 3.5) < 1e-12
+    lw = np.full(1000, -800.0)
+    lw[17] = 0.0
+    r = orc.marginalize(lw)
+    assert abs(r["n_eff"] - 1.0) < 1e-12 and r["argmax"] == 17
+    r = orc.marginalize(np.array([-np.inf] * 10))
+    assert r["ln_L"] == -np.inf and r["n_eff"] == 0 and r["n_nonfinite"] == 10
+    r = orc.marginalize(np.array([0.0, -np.inf, np.nan, 0.0]))
+    assert r["n_nonfinite"] == 2 and abs(r["ln_L"] - math.log(2 / 4)) < 1e-15
+    # ties go to the lowest index
+    assert orc.marginalize(np.array([1.0, 3.0, 3.0]))["argmax"] == 1
+
+
+# --------------------------------------------------------------------- P11
+@pytest.mark.slow
+def test_P11_brute_force_quadrature(orc, recs):
+    """Fix (alpha, dec, psi, t) at the injection; the product-grid quadrature
+    over (cos iota, phi_c, D) against the prior agrees with a Monte Carlo
+    estimate of the same integral within 4 sigma, and feeding the grid nodes
+    with ln(weight) as log-weights through the estimator reproduces the grid sum."""
+    p, ev, hlm = _event(recs, "c1", ["H", "L"], 5, noise=True)
+    th0 = np.array(recs["c1"]["theta"])
+    nc, nphi, nD = 64, 64, 256
+    xc, wc = np.polynomial.legendre.leggauss(nc)           # cos iota on [-1,1]
+    phis = np.arange(nphi) * 2 * math.pi / nphi
+    Dlo, Dhi = 100.0, 1500.0
+    xd, wd = np.polynomial.legendre.leggauss(nD)
+    Ds = 0.5 * (Dhi - Dlo) * xd + 0.5 * (Dhi + Dlo)
+    wD = 0.5 * (Dhi - Dlo) * wd
+    pD = 3 * Ds ** 2 / (Dhi ** 3 - Dlo ** 3)
+    C_, P_, D_ = np.meshgrid(np.arange(nc), np.arange(nphi), np.arange(nD), indexing="ij")
+    th = np.tile(th0[:, None], (1, C_.size))
+    th[4] = xc[C_.ravel()]
+    th[5] = phis[P_.ravel()]
+    th[3] = Ds[D_.ravel()]
+    L = orc.lnL(p, th)
+    lnw = (np.log(wc[C_.ravel()] / 2) + math.log(1.0 / nphi) + np.log(wD[D_.ravel()] * pD[D_.ravel()]))
+    grid = np.logaddexp.reduce(L + lnw)
+    r = orc.marginalize(L + lnw)
+    assert abs((r["ln_L"] + math.log(L.size)) - grid) <= 1e-12 * abs(grid)
+    rng = np.random.default_rng(12)
+    N = 400000
+    ths = np.tile(th0[:, None], (1, N))
+    ths[4] = rng.uniform(-1, 1, N)
+    ths[5] = rng.uniform(0, 2 * math.pi, N)
+    ths[3] = np.cbrt(rng.uniform(Dlo ** 3, Dhi ** 3, N))
+    rm = orc.marginalize(orc.lnL(p, ths))
+    sig = math.exp(rm["ln_sigma"] - rm["ln_L"])
+    assert abs(rm["ln_L"] - grid) < 4 * sig + 1e-3
+
+
+# --------------------------------------------------------------------- P12/P13
+def test_P13_em_single_component_is_weighted_moments(orc):
+    rng = np.random.default_rng(13)
+    n = 5000
+    th = chirpgen.prior_samples(rng, n)
+    lw = rng.normal(size=n)
+    dims = [1, 2, 3, 4]
+    X = th[dims].T
+    w = np.exp(lw - lw.max())
+    mu0 = X[0].copy()
+    cov0 = np.diag([0.3, 1e-4, 1e5, 0.2])
+    nw, nm, nc = orc.em_step(th, lw, dims, [1.0], [mu0], [cov0])
+    m = (w @ X) / w.sum()
+    c = ((X - m) * w[:, None]).T @ (X - m) / w.sum()
+    floor = np.diag([1e-8 * orc.col_range(cc) ** 2 for cc in dims])
+    assert np.allclose(nm[0], m, rtol=1e-12, atol=1e-12)
+    assert np.allclose(nc[0], c + floor, rtol=1e-11, atol=1e-14)
+    assert nw[0] == 1.0
+
+
+def test_P13_component_logpdf_matches_scipy(orc):
+    from scipy.stats import multivariate_normal
+    rng = np.random.default_rng(14)
+    prior = orc.make_prior()
+    dims = [1, 2, 3, 4]
+    A = rng.normal(size=(4, 4))
+    R = A @ A.T + 4 * np.eye(4)
+    sd = np.sqrt(np.diag(R))
+    R = R / np.outer(sd, sd)                       # correlation matrix
+    sig = np.array([0.3, 0.5, 2.0, 0.3])
+    cov = R * np.outer(sig, sig)
+    mean = [0.1, 0.001, 500.0, 0.2]  # theta[3] near 500 lies far out: exercises a large Mahalanobis value
+    g = orc.make_gmm([1.0], [mean], [cov], dims)
+    for _ in range(20):
+        th = chirpgen.prior_samples(rng, 1)[:, 0]
+        ref = multivariate_normal(mean=mean, cov=cov).logpdf(th[dims])
+        assert abs(orc.gmm_comp_logpdf(prior, g, 0, th) - ref) <= 1e-10 * (1 + abs(ref))
+
+
+def test_P13_periodic_wrap_logpdf(orc):
+    """Periodic columns use the wrapped difference: a mean near 2 pi and a
+    point near 0 are close."""
+    from scipy.stats import multivariate_normal
+    prior = orc.make_prior()
+    g = orc.make_gmm([1.0], [[6.2, 0.05]], [np.diag([0.04, 0.01])], [0, 6])
+    th = np.zeros(7)
+    th[0], th[6] = 0.05, 3.1
+    ref = multivariate_normal(mean=[0, 0], cov=np.diag([0.04, 0.01])).logpdf(
+        [0.05 + 2 * math.pi - 6.2, 3.1 - math.pi - 0.05])
+    assert abs(orc.gmm_comp_logpdf(prior, g, 0, th) - ref) < 1e-12
+
+
+def test_P12_two_gaussian_recovery(orc):
+    """Two Gaussians, sigma = sqrt(2), centres (+-4, 0, 0) (the hyperpipeline
+    demonstration target): the fitted mixture covers both, and importance
+    sampling from it integrates the normalised target to 1 within 4 sigma."""
+    from scipy.stats import multivariate_normal
+    rng = np.random.default_rng(15)
+    dims = [1, 2, 3]           # three bounded columns used as a plain 3-D space
+    sc = np.array([1.0, 1.0, 1.0])
+    n = 60000
+    X = rng.uniform(-12, 12, size=(n, 3))
+    tgt = lambda Z: np.logaddexp(  # noqa: E731
+        multivariate_normal([4, 0, 0], 2 * np.eye(3)).logpdf(Z),
+        multivariate_normal([-4, 0, 0], 2 * np.eye(3)).logpdf(Z)) + math.log(0.5)
+    lw = tgt(X) - math.log(1 / 24 ** 3)
+    th = np.zeros((7, n))
+    th[dims] = (X * sc).T
+    w, m, c = orc.em_fit(th, lw, dims, n_iter=30, n_comp=8, t_window=100.0, d_min=-100, d_max=100)
+    left = sum(w[j] for j in range(8) if m[j][0] < 0)
+    assert 0.3 < left < 0.7
+    # importance integral of the target under the fitted mixture
+    comp = rng.choice(8, size=40000, p=w / w.sum())
+    Z = np.array([rng.multivariate_normal(m[j], c[j]) for j in comp])
+    lq = np.logaddexp.reduce([math.log(w[j]) + multivariate_normal(m[j], c[j]).logpdf(Z) for j in range(8) if w[j] > 0], axis=0)
+    ratio = np.exp(tgt(Z) - lq)
+    est, err = ratio.mean(), ratio.std() / math.sqrt(len(ratio))
+    assert abs(est - 1) < 4 * err + 1e-3
+
+
+# --------------------------------------------------------------------- P14
+@pytest.mark.parametrize("T1,T2", [(30.0, 900.0), (5.0, 4.0), (-3.0, 50.0), (400.0, 1.6e5)])
+def test_P14_distance_integral_closed_form(orc, T1, T2):
+    """Prior uniform in s: int e^{s T1 - s^2 T2/4} ds has an erf closed form."""
+    from scipy.special import erf, erfc
+    slo, shi = 100 / 3000, 100.0
+    ss = 2 * T1 / T2
+    a = math.sqrt(T2) / 2
+    x1, x2 = a * (slo - ss), a * (shi - ss)
+    # erf(x2) - erf(x1), written with erfc when both arguments are positive
+    diff = erfc(x1) - erfc(x2) if x1 > 0 else erf(x2) - erf(x1)
+    # ln of e^{T1^2/T2} sqrt(pi/T2) diff / (s_hi - s_lo)
+    ref = T1 * T1 / T2 + 0.5 * math.log(math.pi / T2) + math.log(diff) - math.log(shi - slo)
+    got = orc.ln_dist_marg(T1, T2, prior="uniform_s")
+    assert abs(got - ref) <= 1e-11 * max(1, abs(ref))
+
+
+def test_P14_distance_integral_volume_prior_bruteforce(orc):
+    """Volume prior: compare with a dense Simpson rule in log D."""
+    from scipy.integrate import simpson
+    for T1, T2 in [(30.0, 900.0), (2.0, 1.0), (150.0, 2.0e4)]:
+        lD = np.linspace(math.log(1.0), math.log(3000.0), 400001)
+        D = np.exp(lD)
+        s = 100.0 / D
+        e = s * T1 - s * s * T2 / 4
+        m = e.max()
+        integrand = np.exp(e - m) * 3 * D ** 2 / (3000 ** 3 - 1) * D
+        ref = m + math.log(simpson(integrand, x=lD))
+        assert abs(orc.ln_dist_marg(T1, T2) - ref) < 1e-8
+
+
+# --------------------------------------------------------------------- P15
+def test_P15_generator_matrices(recs):
+    probs, _ = chirpgen.build_event(recs["c3"], ["H", "L", "V"], 17, 30.0, 20.0, 100.0, noise_seed=3)
+    p = probs[0]
+    for k in range(p.n_det):
+        assert np.allclose(p.U[k], np.conj(p.U[k].T), atol=1e-12 * np.abs(p.U[k]).max())
+        assert np.allclose(p.V[k], p.V[k].T, atol=1e-12 * np.abs(p.V[k]).max())
+        ev = np.linalg.eigvalsh(p.U[k])
+        assert ev.min() > -1e-10 * ev.max()
+
+
+# --------------------------------------------------------------------- draws
+def test_philox_known_answers(orc):
+    """Philox-4x32-10 known-answer vectors published with the Random123 library
+    (Salmon et al., SC'11); stored in tests/golden/philox_kat.txt."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox_kat.txt")
+    n = 0
+    for line in open(path):
+        if not line.strip() or line.startswith("#"):
+            continue
+        v = [int(x, 16) for x in line.split()]
+        assert orc.philox(v[0:4], v[4:6]) == v[6:10]
+        n += 1
+    assert n == 3
+
+
+def test_prior_draws_distribution(orc):
+    from scipy import stats
+    prior = orc.make_prior()
+    th, lp = orc.draw_prior(prior, 12345, 0, 0, 20000)
+    assert stats.kstest(th[0] / (2 * math.pi), "uniform").pvalue > 1e-4
+    assert stats.kstest((np.sin(th[1]) + 1) / 2, "uniform").pvalue > 1e-4
+    assert stats.kstest((th[3] ** 3 - 1) / (3000 ** 3 - 1), "uniform").pvalue > 1e-4
+    assert stats.kstest((th[4] + 1) / 2, "uniform").pvalue > 1e-4
+    assert stats.kstest(th[6] / math.pi, "uniform").pvalue > 1e-4
+    # ln p integrates: mean of exp(-lnp) over the box volume (importance identity)
+    i = 7
+    ref = (-math.log(2 * math.pi) + math.log(math.cos(th[1, i]) / 2) - math.log(0.056)
+           + math.log(3 * th[3, i] ** 2 / (3000 ** 3 - 1)) - math.log(2) - math.log(2 * math.pi) - math.log(math.pi))
+    assert abs(lp[i] - ref) < 1e-12
+    # counter-based: a later window reproduces the same samples
+    th2, _ = orc.draw_prior(prior, 12345, 0, 100, 50)
+    assert np.array_equal(th2, th[:, 100:150])
+
+
+def test_gmm_draws_follow_ps(orc):
+    """E_{p_s}[p/p_s] = 1 for draws from the proposal (importance identity), and
+    a one-dimensional in-support mass agrees with its erf closed form."""
+    from scipy.special import erf
+    prior = orc.make_prior()
+    dims = [0, 1, 2, 3, 4, 5, 6]
+    rng = np.random.default_rng(16)
+    means = [[6.0, 0.3, 0.01, 500.0, 0.5, 0.1, 3.0], [1.0, -0.5, -0.02, 2500.0, -0.9, 3.0, 0.2]]
+    covs = [np.diag([0.2, 0.1, 1e-4, 1e4, 0.1, 0.3, 0.2]) ** 1, np.diag([0.5, 0.05, 4e-4, 3e5, 0.05, 1.0, 0.5])]
+    g = orc.make_gmm([0.6, 0.4], means, covs, dims)
+    lz = [math.log(orc.gmm_inbox_mass(prior, g, j, 99, 0, 1 << 16)) for j in range(2)]
+    g = orc.make_gmm([0.6, 0.4], means, covs, dims, ln_Z=lz)
+    th, lr = orc.draw_gmm(prior, g, 99, 1, 0, 40000)
+    r = np.exp(lr)
+    assert abs(r.mean() - 1) < 4 * r.std() / math.sqrt(len(r)) + 2e-3
+    del rng
+    # 1-D mass: t column with mean 0.02, sd 0.01 on [-0.028, 0.028]
+    g1 = orc.make_gmm([1.0], [[0.02]], [[[1e-4]]], [2])
+    z = orc.gmm_inbox_mass(prior, g1, 0, 5, 0, 1 << 16)
+    ref = 0.5 * (erf((0.028 - 0.02) / (0.01 * math.sqrt(2))) - erf((-0.028 - 0.02) / (0.01 * math.sqrt(2))))
+    assert abs(z - ref) < 4 * math.sqrt(ref * (1 - ref) / (1 << 16))
