@@ -1,0 +1,185 @@
+"""Benchmark of the ILE extrinsic-likelihood hot path on one MI355X.
+
+Workload (default): 3 detectors (H, L, V), 9 harmonics (l = 2, 3), one
+injected SNR-20 data set and 256 intrinsic template points (M_c ~ U[20, 40],
+q ~ U[1, 4]) each with its own Q (410-sample windows), U and V; 2^20
+extrinsic prior samples per point.  One step = the whole path over all 256
+points: counter-based prior draws, batched lnL over every point, batched
+log-sum-exp estimator.  Inputs (Q, U, V, the sample buffers) are resident in
+HBM before timing starts.  `value` is FP32 samples/s; the FP64 policy is run
+on the same workload and reported beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--points 256] [--log2n 20]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "extrinsic lnL samples/s (FP32 vs FP64 plain, |dlnL|<=1e-3) + p50/p99 latency"
+# per-sample FLOP model of the fused likelihood for K = 3, n = 9 (Hermitian /
+# symmetric pair form): trig 90 + F 40K + tau 20K + Y 6n + T1 24Kn + quadratic
+# P + 18KP (P = n(n+1)/2) + combine 12K + 10
+FLOP_PER_SAMPLE = {(3, 9): 3493, (2, 5): 1069, (3, 17): 10057}
+PEAK = {"fp32": 157.3e12, "fp64": 78.6e12}
+HBM_PEAK = 8.0e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_problems(n_points, seed):
+    import chirpgen
+    recs = chirpgen.load_injections()
+    rng = np.random.default_rng(seed)
+    templates = [(float(rng.uniform(20, 40)), float(rng.uniform(1, 4))) for _ in range(n_points)]
+    probs, _ = chirpgen.build_event(recs["c2"], ["H", "L", "V"], 9, 30.0, 2.0, 20.0,
+                                    noise_seed=chirpgen.BASE_SEED + 2, templates=templates)
+    return probs
+
+
+def run_policy(ile, torch, ctx, probs, policy, n_per, steps, warmup, stream):
+    dt = torch.float64 if policy == ile.ILE_FP64 else torch.float32
+    jobs = [ile.ile_prepare(ctx, ile.ProblemHost(p, precision=policy)) for p in probs]
+    J = len(jobs)
+    N = J * n_per
+    th = torch.empty((7, N), dtype=dt, device="cuda")
+    lr = torch.empty((N,), dtype=dt, device="cuda")
+    L = torch.empty((N,), dtype=dt, device="cuda")
+    W = torch.empty((N,), dtype=dt, device="cuda")
+    esz = th.element_size()
+    theta_ptrs = [th.data_ptr() + j * n_per * esz for j in range(J)]
+    lr_ptrs = [lr.data_ptr() + j * n_per * esz for j in range(J)]
+    L_ptrs = [L.data_ptr() + j * n_per * esz for j in range(J)]
+    W_ptrs = [W.data_ptr() + j * n_per * esz for j in range(J)]
+    ns = [n_per] * J
+    lds = [N] * J
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t_kernel = {"draw": 0.0, "eval": 0.0, "marg": 0.0}
+    res = None
+
+    def step(seed, timed):
+        nonlocal res
+        ev[0].record(stream)
+        ile.ile_draw(jobs[0], seed, 0, 0, N, th, N, lr, stream=stream)
+        ev[1].record(stream)
+        ile.ile_eval_lnL_batch(jobs, ns, theta_ptrs, lds, lr_ptrs, L_ptrs, W_ptrs, stream=stream)
+        ev[2].record(stream)
+        res = ile.ile_marginalize_batch(jobs, ns, W_ptrs, ile.ILE_MARG_RESET, want=False, stream=stream)
+        ev[3].record(stream)
+        if timed:
+            ev[3].synchronize()
+            t_kernel["draw"] += ev[0].elapsed_time(ev[1])
+            t_kernel["eval"] += ev[1].elapsed_time(ev[2])
+            t_kernel["marg"] += ev[2].elapsed_time(ev[3])
+
+    for w in range(warmup):
+        step(1000 + w, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(2000 + k, True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = ile.ile_marginalize_batch(jobs, [0] * J, [None] * J, ile.ILE_MARG_POOL, want=True, stream=stream)
+    torch.cuda.synchronize()
+    del res
+    for j in jobs:
+        ile.ile_job_release(j)
+    del th, lr, L, W
+    torch.cuda.empty_cache()
+    per = {k: v / steps for k, v in t_kernel.items()}
+    return dict(samples_per_s=N * steps / wall, ms_per_step=1e3 * wall / steps, kernel_ms=per, N=N,
+                lnL_marg_first=out[0]["ln_L"], n_eff_first=out[0]["n_eff"])
+
+
+def cpu_baseline(probs, budget_s=15.0):
+    """The oracle as it stands, on a bounded sample of the same workload."""
+    import chirpgen
+    import oracle
+    threads = os.cpu_count() or 1
+    rng = np.random.default_rng(5)
+    th = chirpgen.prior_samples(rng, 4096)
+    t0 = time.perf_counter()
+    oracle.lnL(probs[0], th, threads=threads)
+    dt = time.perf_counter() - t0
+    n = int(min(max(4096, budget_s / max(dt, 1e-6) * 4096), 1 << 22))
+    th = chirpgen.prior_samples(rng, n)
+    t0 = time.perf_counter()
+    lw = oracle.lnL(probs[1 % len(probs)], th, threads=threads)
+    oracle.marginalize(lw)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} prior samples of one intrinsic point of the same workload (lnL + estimator), "
+                      f"FP64, OpenMP {threads} threads, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--points", type=int, default=256)
+    ap.add_argument("--log2n", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the path shards by "
+              "intrinsic point with no exchange, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2505_11655_amd as ile
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    log("building inputs ...")
+    probs = make_problems(a.points, 250511655)
+    n_per = 1 << a.log2n
+    ctx = ile.ile_ctx_create(0, 0)
+    stream = torch.cuda.current_stream()
+    log("fp32 ...")
+    r32 = run_policy(ile, torch, ctx, probs, ile.ILE_FP32, n_per, a.steps, a.warmup, stream)
+    log(f"fp32 {r32}")
+    r64 = None
+    if not a.no_fp64:
+        log("fp64 ...")
+        r64 = run_policy(ile, torch, ctx, probs, ile.ILE_FP64, n_per, a.steps, a.warmup, stream)
+        log(f"fp64 {r64}")
+    N = r32["N"]
+    flop = FLOP_PER_SAMPLE[(3, 9)]
+    t_eval = r32["kernel_ms"]["eval"] * 1e-3
+    achieved = flop * N / t_eval
+    bytes_eval = 36 * N
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK["fp32"], "traffic": None,
+            "kernel": "k_lnl (fused lnL, FP32, K=3, 9 modes)", "flop_per_sample": flop,
+            "samples_per_launch": N, "avg_launch_ms": r32["kernel_ms"]["eval"],
+            "hbm_algorithmic_GBps": bytes_eval / t_eval / 1e9,
+            "hbm_frac": bytes_eval / t_eval / HBM_PEAK}
+    line = {
+        "metric": METRIC, "value": r32["samples_per_s"], "unit": "samples/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": r32["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"HLV, 9 modes (l=2,3), {a.points} intrinsic points x 2^{a.log2n} prior "
+                               "samples, SNR 20, 410-sample Q windows, draw+lnL+estimator per step",
+                   "points": a.points, "samples_per_point": n_per, "detectors": 3, "modes": 9},
+        "roofline": roof,
+        "kernel_ms": r32["kernel_ms"],
+        "fp64": None if r64 is None else {"value": r64["samples_per_s"], "ms_per_step": r64["ms_per_step"],
+                                          "kernel_ms": r64["kernel_ms"],
+                                          "fp32_over_fp64": r32["samples_per_s"] / r64["samples_per_s"]},
+        "serving": None,
+        "cpu_baseline": None if a.no_cpu else cpu_baseline(probs),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

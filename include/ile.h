@@ -1,0 +1,247 @@
+/*
+ * ile.h - C ABI of the MI355X (gfx950) extrinsic-marginalised likelihood (ILE).
+ *
+ * Paper: arXiv 2505.11655 ("Narrowing RIFT"), Section "Review of the RIFT
+ * likelihood".  For one intrinsic point lambda the inputs are, per detector k,
+ * the windowed inner-product series Q_k,lm(tau) and the mode overlaps
+ * U_k,lm,l'm' = <h_lm|h_l'm'>, V_k,lm,l'm' = <h_lm^*|h_l'm'> of eq. (QUV).
+ * The library evaluates, for Monte Carlo samples theta = (alpha, delta, t, D,
+ * cos iota, phi_c, psi), the factored log-likelihood of eq.
+ * (def:lnL:Decomposed) and integrates it with the estimator of eq.
+ * (lnL:MonteCarlo) and the effective sample size of eq. (neff).
+ *
+ * Conventions (the paper is silent or self-inconsistent on these):
+ *  - F_k = F+ + i Fx (with h = h+ - i hx and h_k = F+ h+ + Fx hx this makes
+ *    the printed decomposition exact);
+ *  - the sky vector points to the source, tau_k = t - x_k . n / c;
+ *  - Y_lm = -2Y_lm(iota, -phi_c); psi only rotates the polarisation basis;
+ *  - Q between window samples: 4-point Lagrange cubic on samples i-1..i+2,
+ *    i = floor((tau - tau0)/dt), valid for 1 <= i <= n_time-3.
+ *
+ * Memory: every pointer in ile_problem is HOST memory and is deep-copied by
+ * ile_prepare.  Sample buffers passed to ile_eval_lnL / ile_draw /
+ * ile_marginalize / ile_adapt_proposal are DEVICE memory owned by the caller
+ * (e.g. torch tensors); the library never frees them.  Calls enqueue work on
+ * the given HIP stream (NULL = the device's null stream) and return without
+ * waiting, except where a host-side result is requested (then the stream is
+ * synchronised before returning).
+ *
+ * Errors: every call returns an ile_status.  ILE_E_INVALID for bad shapes,
+ * sizes, pointers, non-finite or non-Hermitian inputs; ILE_E_DEVICE for a
+ * HIP error, after which the context is sticky-failed and every later call on
+ * it returns ILE_E_DEVICE.  ile_last_error() gives a message for the last
+ * failing call on the calling thread.  No exception crosses the ABI.
+ */
+#ifndef ILE_H
+#define ILE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ILE_OK = 0,
+    ILE_PENDING = 1,
+    ILE_E_INVALID = -1,
+    ILE_E_NOMEM = -2,
+    ILE_E_TOO_BIG = -3,
+    ILE_E_DEVICE = -4,
+    ILE_E_STATE = -5,
+    ILE_E_CANCELLED = -6,
+    ILE_E_TIMEOUT = -7
+} ile_status;
+
+/* Arithmetic policy.
+ *  ILE_FP64          everything in FP64; theta, ln p - ln p_s, lnL, lw are double.
+ *  ILE_FP32          everything in FP32; theta, ln p - ln p_s, lnL, lw are float.
+ *  ILE_FP32_CANCEL64 theta and ln p - ln p_s are float; the sky direction and
+ *                    detector delays, the interpolation weights, the Q/U/V
+ *                    contractions and s T1 - s^2 T2 / 4 are FP64 (the terms whose
+ *                    rounding does not cancel near the likelihood peak); the
+ *                    polarisation, harmonic and phase factors are FP32;
+ *                    lnL and lw are double. */
+typedef enum { ILE_FP64 = 0, ILE_FP32 = 1, ILE_FP32_CANCEL64 = 2 } ile_precision;
+
+typedef struct ile_ctx ile_ctx;
+typedef struct ile_job ile_job;
+typedef struct ile_server ile_server;
+typedef void *ile_stream; /* hipStream_t */
+
+/* Prior support (the sampled coordinates):
+ * alpha ~ U[0,2pi), p(delta) = cos(delta)/2, t ~ U[-t_window, t_window],
+ * p(D) = 3 D^2 / (d_max^3 - d_min^3) on [d_min, d_max] Mpc, cos iota ~ U[-1,1],
+ * phi_c ~ U[0,2pi), psi ~ U[0,pi).  dist_marg = 1: the distance integral is
+ * done inside the likelihood (2-D FP64 table over (T1, T2)) and D is not sampled. */
+typedef struct {
+    double t_window;
+    double d_min, d_max;
+    int32_t dist_marg;
+} ile_prior;
+
+typedef struct {
+    int32_t n_det;            /* 1..3 */
+    int32_t n_modes;          /* 1..21, every l in 2..4, |m| <= l, no duplicates */
+    int32_t n_time;           /* window samples, >= 4 */
+    const int32_t *mode_l;    /* [n_modes] */
+    const int32_t *mode_m;    /* [n_modes] */
+    const double *det_pos;    /* [n_det][3] metres, Earth-fixed */
+    const double *det_resp;   /* [n_det][3][3] response tensor, symmetric */
+    double gmst_rad;          /* Greenwich sidereal angle of the reference time */
+    double tau0_s, dt_s;      /* window: tau_i = tau0_s + i dt_s, relative to the reference time */
+    const double *Q;          /* [n_det][n_modes][n_time] complex128 (re, im) */
+    const double *U;          /* [n_det][n_modes][n_modes] complex128, Hermitian */
+    const double *V;          /* same, complex symmetric; NULL = zero (only if all m share a sign) */
+    double d_ref_mpc;         /* distance at which Q, U, V were computed */
+    double mode_filter_eps;   /* 0 = off (paper default); else keep (l,m) iff some
+                                 |U_0[lm][l'm'] / U_0[22][22]| > eps (detector 0) */
+    int32_t precision;        /* ile_precision */
+    ile_prior prior;
+} ile_problem;
+
+typedef struct {
+    double ln_L;              /* ln of the estimator (1/N) sum w_i */
+    double ln_sigma;          /* ln of its standard error */
+    double n_eff;             /* eq. (neff): sum w / max w */
+    double n_ess;             /* (sum w)^2 / sum w^2 */
+    double max_lw;            /* max log-weight */
+    int64_t argmax;           /* index of max lw (lowest on ties; pooled index) */
+    int64_t n;                /* samples pooled */
+    int64_t n_nonfinite;      /* samples with non-finite lw (zero weight) */
+} ile_marg;
+
+typedef struct {
+    int32_t n_modes_kept;     /* after the mode filter */
+    int32_t mode_slots;       /* compiled mode-set size the job runs in (5, 9, 17, 21) */
+    int32_t n_det_slots;      /* compiled detector count (2 or 3) */
+    size_t device_bytes;      /* resident device memory of the job */
+} ile_job_info;
+
+/* Context: one per HIP device.  hbm_budget_bytes = 0 means the whole device. */
+ile_status ile_ctx_create(int hip_device, size_t hbm_budget_bytes, ile_ctx **out);
+void ile_ctx_destroy(ile_ctx *ctx);
+const char *ile_last_error(void);
+
+/* Validate, filter modes, convert to the policy's precision and layout, upload. */
+ile_status ile_prepare(ile_ctx *ctx, const ile_problem *problem, ile_job **out);
+ile_status ile_job_info_get(const ile_job *job, ile_job_info *info);
+void ile_job_release(ile_job *job);
+
+/* Per-sample lnL, eq. (def:lnL:Decomposed).
+ * theta: device [7][ld] (float or double by policy), columns (alpha, delta, t,
+ * D, cos iota, phi_c, psi), ld >= n.  lnpmps: device [n] ln p - ln p_s in the
+ * theta type, or NULL (0).  lnL_out: device [n] (float for ILE_FP32, else
+ * double).  lw_out: device [n] lnL + lnpmps, or NULL.  Samples outside the
+ * support (window stencil out of range, D <= 0, |cos iota| > 1) give -inf.
+ * With prior.dist_marg the D column is ignored and lnL is the distance-
+ * marginalised value. */
+ile_status ile_eval_lnL(ile_job *job, int64_t n, const void *theta, int64_t ld,
+                        const void *lnpmps, void *lnL_out, void *lw_out, ile_stream stream);
+
+/* Several jobs of the same policy in one pass; arrays of length n_jobs. */
+ile_status ile_eval_lnL_batch(ile_job *const *jobs, int32_t n_jobs, const int64_t *n,
+                              const void *const *theta, const int64_t *ld,
+                              const void *const *lnpmps, void *const *lnL_out,
+                              void *const *lw_out, ile_stream stream);
+
+/* Monte Carlo estimator of eq. (lnL:MonteCarlo) on log-weights lw (device [n],
+ * the lw type of the policy).  The job keeps the pooled (max, S1, S2, N) state.
+ * flags: ILE_MARG_RESET clears it first; ILE_MARG_POOL adds this batch to it.
+ * out (host, may be NULL): the pooled result; the stream is synchronised when given. */
+#define ILE_MARG_RESET 1u
+#define ILE_MARG_POOL 2u
+ile_status ile_marginalize(ile_job *job, int64_t n, const void *lw, uint32_t flags,
+                           ile_marg *out, ile_stream stream);
+
+/* The same for several jobs of one policy in two launches; arrays of length
+ * n_jobs.  out: host [n_jobs] or NULL.  Each job's result is bitwise the one
+ * ile_marginalize gives for it alone (same tiles, same order). */
+ile_status ile_marginalize_batch(ile_job *const *jobs, int32_t n_jobs, const int64_t *n,
+                                 const void *const *lw, uint32_t flags, ile_marg *out,
+                                 ile_stream stream);
+
+/* Counter-based draws (Philox-4x32-10) of samples first_index .. first_index+n-1
+ * of round `round` under key `seed`: from the prior while the job has no
+ * proposal, else from the mixture proposal p_s.  theta_out: device [7][ld];
+ * lnpmps_out: device [n] ln p - ln p_s (theta type), or NULL. */
+ile_status ile_draw(ile_job *job, uint64_t seed, uint32_t round, int64_t first_index, int64_t n,
+                    void *theta_out, int64_t ld, void *lnpmps_out, ile_stream stream);
+
+/* Mixture proposal p_s = (1 - eps) sum_j pi_j N_j / Z_j + eps p over the sampled
+ * columns (all seven, or six with dist_marg); periodic alpha, phi_c (2pi) and
+ * psi (pi) use differences wrapped into (-P/2, P/2]. */
+#define ILE_GMM_MAX_COMP 16
+typedef struct {
+    int32_t n_comp;           /* 1..16 */
+    int32_t n_dim;            /* 6 or 7 (set by the library) */
+    int32_t dims[7];          /* theta column of each dimension */
+    double eps_def;           /* defensive prior weight */
+    double weight[ILE_GMM_MAX_COMP];
+    double mean[ILE_GMM_MAX_COMP][7];
+    double cov[ILE_GMM_MAX_COMP][7][7];
+    double ln_Z[ILE_GMM_MAX_COMP];  /* in-support mass (output of set/adapt) */
+} ile_gmm_params;
+
+typedef struct {
+    int32_t n_comp;           /* default 8 */
+    int32_t n_iter;           /* EM iterations per call, default 8 */
+    double eps_def;           /* default 0.05 */
+    uint64_t seed;            /* key for the in-support mass draws */
+    uint32_t round;           /* counter word for the same */
+    int64_t z_draws;          /* in-support mass draws per component, default 65536 */
+} ile_gmm_opts;
+
+/* Install an explicit proposal (host parameters); the library factorises the
+ * covariances and estimates ln Z on the device (opts may be NULL for defaults). */
+ile_status ile_set_proposal(ile_job *job, const ile_gmm_params *params, const ile_gmm_opts *opts,
+                            ile_stream stream);
+ile_status ile_get_proposal(ile_job *job, ile_gmm_params *params, ile_stream stream);
+
+/* Weighted EM refit of the proposal from samples (theta [7][ld], lw [n], device):
+ * first call seeds the means at the highest-weight distinct samples with a
+ * common weighted covariance; later calls warm-start.  Each component gets
+ * Sigma += 1e-8 diag(range^2).  Host diagnostics (may be NULL): the new params. */
+ile_status ile_adapt_proposal(ile_job *job, int64_t n, const void *theta, int64_t ld,
+                              const void *lw, const ile_gmm_opts *opts,
+                              ile_gmm_params *out, ile_stream stream);
+
+/* ---------------------------------------------------------------- serving */
+typedef struct {
+    int32_t max_active;       /* jobs resident at once (default 64) */
+    size_t hbm_budget_bytes;  /* 0: the context's budget */
+    int64_t chunk_samples;    /* samples per job per scheduling pass (default 1<<20) */
+    int32_t record_samples;   /* 0 */
+} ile_server_opts;
+
+typedef struct {
+    int64_t n_samples;        /* fixed budget (plain mode) */
+    int32_t adaptive;         /* 1: rounds + mixture refits until n_eff target */
+    int64_t round_samples;    /* adaptive: samples per round (default 65536) */
+    int32_t max_rounds;       /* adaptive: default 32 */
+    double n_eff_target;      /* adaptive: default 1000 */
+    uint64_t seed;
+} ile_job_opts;
+
+typedef struct {
+    ile_marg marg;
+    int32_t status;           /* ile_status of the job */
+    int32_t rounds;
+    int64_t samples;
+    int64_t t_arrival_ns, t_admit_ns, t_start_ns, t_finish_ns;  /* steady clock */
+} ile_result;
+
+ile_status ile_server_create(ile_ctx *ctx, const ile_server_opts *opts, ile_server **out);
+ile_status ile_server_submit(ile_server *srv, const ile_problem *problem, const ile_job_opts *opts,
+                             uint64_t *job_id);
+ile_status ile_server_poll(ile_server *srv, uint64_t job_id, ile_result *out);
+ile_status ile_server_wait(ile_server *srv, uint64_t job_id, int64_t timeout_ms, ile_result *out);
+ile_status ile_server_cancel(ile_server *srv, uint64_t job_id);
+ile_status ile_server_stats(ile_server *srv, int64_t *active, int64_t *queued, int64_t *done);
+void ile_server_destroy(ile_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ILE_H */

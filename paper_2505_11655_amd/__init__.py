@@ -1,0 +1,340 @@
+"""Python binding of libile.so, the gfx950 ILE extrinsic-likelihood library.
+
+Argument marshalling only: every step of the likelihood path runs in the HIP
+kernels behind the C ABI of ``include/ile.h``.  Functions keep the C names.
+Device buffers are passed as integers (``tensor.data_ptr()``) or torch
+tensors; streams as ``torch.cuda.Stream`` / raw handles / None (null stream).
+Loading fails loudly if the library has not been built
+(``python -m paper_2505_11655_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libile.so")
+
+ILE_FP64, ILE_FP32, ILE_FP32_CANCEL64 = 0, 1, 2
+ILE_MARG_RESET, ILE_MARG_POOL = 1, 2
+STATUS = {0: "OK", 1: "PENDING", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_TOO_BIG", -4: "E_DEVICE",
+          -5: "E_STATE", -6: "E_CANCELLED", -7: "E_TIMEOUT"}
+
+
+class IleError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ile status {status} ({STATUS.get(status, '?')}): {msg}")
+        self.status = status
+
+
+class ile_prior(C.Structure):
+    _fields_ = [("t_window", C.c_double), ("d_min", C.c_double), ("d_max", C.c_double),
+                ("dist_marg", C.c_int32)]
+
+
+class ile_problem(C.Structure):
+    _fields_ = [("n_det", C.c_int32), ("n_modes", C.c_int32), ("n_time", C.c_int32),
+                ("mode_l", C.POINTER(C.c_int32)), ("mode_m", C.POINTER(C.c_int32)),
+                ("det_pos", C.POINTER(C.c_double)), ("det_resp", C.POINTER(C.c_double)),
+                ("gmst_rad", C.c_double), ("tau0_s", C.c_double), ("dt_s", C.c_double),
+                ("Q", C.POINTER(C.c_double)), ("U", C.POINTER(C.c_double)), ("V", C.POINTER(C.c_double)),
+                ("d_ref_mpc", C.c_double), ("mode_filter_eps", C.c_double), ("precision", C.c_int32),
+                ("prior", ile_prior)]
+
+
+class ile_marg(C.Structure):
+    _fields_ = [("ln_L", C.c_double), ("ln_sigma", C.c_double), ("n_eff", C.c_double),
+                ("n_ess", C.c_double), ("max_lw", C.c_double), ("argmax", C.c_int64),
+                ("n", C.c_int64), ("n_nonfinite", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ile_job_info(C.Structure):
+    _fields_ = [("n_modes_kept", C.c_int32), ("mode_slots", C.c_int32), ("n_det_slots", C.c_int32),
+                ("device_bytes", C.c_size_t)]
+
+
+MAXC = 16
+
+
+class ile_gmm_params(C.Structure):
+    _fields_ = [("n_comp", C.c_int32), ("n_dim", C.c_int32), ("dims", C.c_int32 * 7),
+                ("eps_def", C.c_double), ("weight", C.c_double * MAXC),
+                ("mean", (C.c_double * 7) * MAXC), ("cov", ((C.c_double * 7) * 7) * MAXC),
+                ("ln_Z", C.c_double * MAXC)]
+
+
+class ile_gmm_opts(C.Structure):
+    _fields_ = [("n_comp", C.c_int32), ("n_iter", C.c_int32), ("eps_def", C.c_double),
+                ("seed", C.c_uint64), ("round", C.c_uint32), ("z_draws", C.c_int64)]
+
+
+class ile_server_opts(C.Structure):
+    _fields_ = [("max_active", C.c_int32), ("hbm_budget_bytes", C.c_size_t),
+                ("chunk_samples", C.c_int64), ("record_samples", C.c_int32)]
+
+
+class ile_job_opts(C.Structure):
+    _fields_ = [("n_samples", C.c_int64), ("adaptive", C.c_int32), ("round_samples", C.c_int64),
+                ("max_rounds", C.c_int32), ("n_eff_target", C.c_double), ("seed", C.c_uint64)]
+
+
+class ile_result(C.Structure):
+    _fields_ = [("marg", ile_marg), ("status", C.c_int32), ("rounds", C.c_int32), ("samples", C.c_int64),
+                ("t_arrival_ns", C.c_int64), ("t_admit_ns", C.c_int64), ("t_start_ns", C.c_int64),
+                ("t_finish_ns", C.c_int64)]
+
+
+EXPORTS = {
+    # name: (restype, argtypes)
+    "ile_ctx_create": (C.c_int, [C.c_int, C.c_size_t, C.POINTER(C.c_void_p)]),
+    "ile_ctx_destroy": (None, [C.c_void_p]),
+    "ile_last_error": (C.c_char_p, []),
+    "ile_prepare": (C.c_int, [C.c_void_p, C.POINTER(ile_problem), C.POINTER(C.c_void_p)]),
+    "ile_job_info_get": (C.c_int, [C.c_void_p, C.POINTER(ile_job_info)]),
+    "ile_job_release": (None, [C.c_void_p]),
+    "ile_eval_lnL": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p]),
+    "ile_eval_lnL_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_void_p),
+                                     C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
+    "ile_marginalize": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_uint32, C.POINTER(ile_marg),
+                                  C.c_void_p]),
+    "ile_marginalize_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_void_p), C.c_uint32, C.POINTER(ile_marg), C.c_void_p]),
+    "ile_draw": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
+                           C.c_void_p, C.c_void_p]),
+    "ile_set_proposal": (C.c_int, [C.c_void_p, C.POINTER(ile_gmm_params), C.POINTER(ile_gmm_opts),
+                                   C.c_void_p]),
+    "ile_get_proposal": (C.c_int, [C.c_void_p, C.POINTER(ile_gmm_params), C.c_void_p]),
+    "ile_adapt_proposal": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                     C.POINTER(ile_gmm_opts), C.POINTER(ile_gmm_params), C.c_void_p]),
+    "ile_server_create": (C.c_int, [C.c_void_p, C.POINTER(ile_server_opts), C.POINTER(C.c_void_p)]),
+    "ile_server_submit": (C.c_int, [C.c_void_p, C.POINTER(ile_problem), C.POINTER(ile_job_opts),
+                                    C.POINTER(C.c_uint64)]),
+    "ile_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(ile_result)]),
+    "ile_server_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int64, C.POINTER(ile_result)]),
+    "ile_server_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "ile_server_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int64)]),
+    "ile_server_destroy": (None, [C.c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libile.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libile.so not built ({LIB_PATH}); run python -m paper_2505_11655_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            if not hasattr(L, name):
+                continue
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _chk(status):
+    if status < 0:
+        raise IleError(status, (lib().ile_last_error() or b"").decode())
+    return status
+
+
+def _p(x):
+    """Device pointer of a torch tensor / int / None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _s(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------------------ context
+def ile_ctx_create(device=0, hbm_budget_bytes=0):
+    h = C.c_void_p()
+    _chk(lib().ile_ctx_create(device, hbm_budget_bytes, C.byref(h)))
+    return h
+
+
+def ile_ctx_destroy(ctx):
+    lib().ile_ctx_destroy(ctx)
+
+
+def ile_last_error():
+    return (lib().ile_last_error() or b"").decode()
+
+
+# ------------------------------------------------------------------ problems
+class ProblemHost:
+    """An ile_problem with the host arrays it points to kept alive."""
+
+    def __init__(self, prob, precision=ILE_FP64, dist_marg=False, mode_filter_eps=0.0):
+        self.ml = np.ascontiguousarray([l for l, _ in prob.modes], dtype=np.int32)
+        self.mm = np.ascontiguousarray([m for _, m in prob.modes], dtype=np.int32)
+        self.pos = np.ascontiguousarray(prob.det_pos, dtype=np.float64)
+        self.resp = np.ascontiguousarray(prob.det_resp, dtype=np.float64)
+        self.Q = np.ascontiguousarray(np.asarray(prob.Q, dtype=np.complex128)).view(np.float64)
+        self.U = np.ascontiguousarray(np.asarray(prob.U, dtype=np.complex128)).view(np.float64)
+        self.V = None if prob.V is None else np.ascontiguousarray(
+            np.asarray(prob.V, dtype=np.complex128)).view(np.float64)
+        ip, dp = C.POINTER(C.c_int32), C.POINTER(C.c_double)
+        self.s = ile_problem(
+            len(prob.det_pos), len(prob.modes), prob.Q.shape[-1],
+            self.ml.ctypes.data_as(ip), self.mm.ctypes.data_as(ip),
+            self.pos.ctypes.data_as(dp), self.resp.ctypes.data_as(dp),
+            prob.gmst, prob.tau0, prob.dt,
+            self.Q.ctypes.data_as(dp), self.U.ctypes.data_as(dp),
+            self.V.ctypes.data_as(dp) if self.V is not None else dp(),
+            prob.d_ref, mode_filter_eps, precision,
+            ile_prior(prob.t_window, prob.d_min, prob.d_max, int(dist_marg)))
+
+
+def ile_prepare(ctx, problem: ProblemHost):
+    h = C.c_void_p()
+    _chk(lib().ile_prepare(ctx, C.byref(problem.s), C.byref(h)))
+    return h
+
+
+def ile_job_info_get(job):
+    info = ile_job_info()
+    _chk(lib().ile_job_info_get(job, C.byref(info)))
+    return info
+
+
+def ile_job_release(job):
+    lib().ile_job_release(job)
+
+
+# ------------------------------------------------------------------ compute
+def ile_eval_lnL(job, n, theta, ld, lnpmps, lnL_out, lw_out=None, stream=None):
+    _chk(lib().ile_eval_lnL(job, n, _p(theta), ld, _p(lnpmps), _p(lnL_out), _p(lw_out), _s(stream)))
+
+
+def ile_eval_lnL_batch(jobs, n, theta, ld, lnpmps, lnL_out, lw_out=None, stream=None):
+    k = len(jobs)
+    VP = C.c_void_p * k
+    I64 = C.c_int64 * k
+    _chk(lib().ile_eval_lnL_batch(
+        VP(*[j.value if isinstance(j, C.c_void_p) else j for j in jobs]), k, I64(*n),
+        VP(*[_p(t) for t in theta]), I64(*ld),
+        VP(*[_p(t) for t in lnpmps]) if lnpmps is not None else None,
+        VP(*[_p(t) for t in lnL_out]),
+        VP(*[_p(t) for t in lw_out]) if lw_out is not None else None, _s(stream)))
+
+
+def ile_marginalize(job, n, lw, flags=ILE_MARG_RESET, want=True, stream=None):
+    out = ile_marg() if want else None
+    _chk(lib().ile_marginalize(job, n, _p(lw), flags, C.byref(out) if out is not None else None, _s(stream)))
+    return out.as_dict() if out is not None else None
+
+
+def ile_marginalize_batch(jobs, n, lw, flags=ILE_MARG_RESET, want=True, stream=None):
+    k = len(jobs)
+    VP = C.c_void_p * k
+    out = (ile_marg * k)() if want else None
+    _chk(lib().ile_marginalize_batch(
+        VP(*[j.value if isinstance(j, C.c_void_p) else j for j in jobs]), k, (C.c_int64 * k)(*n),
+        VP(*[_p(t) for t in lw]), flags, out, _s(stream)))
+    return [o.as_dict() for o in out] if want else None
+
+
+def ile_draw(job, seed, rnd, first_index, n, theta_out, ld, lnpmps_out=None, stream=None):
+    _chk(lib().ile_draw(job, seed, rnd, first_index, n, _p(theta_out), ld, _p(lnpmps_out), _s(stream)))
+
+
+def gmm_params(weights, means, covs, eps_def=0.05):
+    p = ile_gmm_params()
+    p.n_comp = len(weights)
+    p.eps_def = eps_def
+    for j in range(len(weights)):
+        p.weight[j] = float(weights[j])
+        d = len(means[j])
+        for a in range(d):
+            p.mean[j][a] = float(means[j][a])
+            for b in range(d):
+                p.cov[j][a][b] = float(covs[j][a][b])
+    return p
+
+
+def gmm_opts(n_comp=8, n_iter=8, eps_def=0.05, seed=0x243F6A8885A308D3, rnd=0, z_draws=65536):
+    return ile_gmm_opts(n_comp, n_iter, eps_def, seed, rnd, z_draws)
+
+
+def ile_set_proposal(job, params, opts=None, stream=None):
+    _chk(lib().ile_set_proposal(job, C.byref(params), C.byref(opts) if opts is not None else None, _s(stream)))
+
+
+def ile_get_proposal(job, stream=None):
+    p = ile_gmm_params()
+    _chk(lib().ile_get_proposal(job, C.byref(p), _s(stream)))
+    return p
+
+
+def ile_adapt_proposal(job, n, theta, ld, lw, opts=None, want=True, stream=None):
+    p = ile_gmm_params() if want else None
+    _chk(lib().ile_adapt_proposal(job, n, _p(theta), ld, _p(lw), C.byref(opts) if opts is not None else None,
+                                  C.byref(p) if p is not None else None, _s(stream)))
+    return p
+
+
+# ------------------------------------------------------------------ serving
+def ile_server_create(ctx, max_active=64, hbm_budget_bytes=0, chunk_samples=1 << 20):
+    h = C.c_void_p()
+    o = ile_server_opts(max_active, hbm_budget_bytes, chunk_samples, 0)
+    _chk(lib().ile_server_create(ctx, C.byref(o), C.byref(h)))
+    return h
+
+
+def job_opts(n_samples=1 << 16, adaptive=False, round_samples=1 << 16, max_rounds=32, n_eff_target=1000.0,
+             seed=1):
+    return ile_job_opts(n_samples, int(adaptive), round_samples, max_rounds, n_eff_target, seed)
+
+
+def ile_server_submit(srv, problem: ProblemHost, opts):
+    jid = C.c_uint64()
+    _chk(lib().ile_server_submit(srv, C.byref(problem.s), C.byref(opts), C.byref(jid)))
+    return jid.value
+
+
+def ile_server_poll(srv, job_id):
+    r = ile_result()
+    st = _chk(lib().ile_server_poll(srv, job_id, C.byref(r)))
+    return st, r
+
+
+def ile_server_wait(srv, job_id, timeout_ms=-1):
+    r = ile_result()
+    _chk(lib().ile_server_wait(srv, job_id, timeout_ms, C.byref(r)))
+    return r
+
+
+def ile_server_cancel(srv, job_id):
+    _chk(lib().ile_server_cancel(srv, job_id))
+
+
+def ile_server_stats(srv):
+    a, q, d = C.c_int64(), C.c_int64(), C.c_int64()
+    _chk(lib().ile_server_stats(srv, C.byref(a), C.byref(q), C.byref(d)))
+    return a.value, q.value, d.value
+
+
+def ile_server_destroy(srv):
+    lib().ile_server_destroy(srv)

@@ -1,0 +1,862 @@
+// Host side of the C ABI declared in include/ile.h: validation, mode
+// filtering and placement, precision conversion and layout, residency,
+// launches and result read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "ile.h"
+#include "ile_ctx.h"
+#include "ile_internal.h"
+
+using namespace ile;
+
+namespace {
+thread_local std::string g_err;
+}
+
+namespace ile {
+
+ile_status set_err(ile_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+ile_status dev_fail(ile_ctx *ctx, hipError_t e, const char *what) {
+    if (ctx) ctx->sticky = true;
+    char buf[512];
+    snprintf(buf, sizeof buf, "HIP error in %s: %s", what, hipGetErrorString(e));
+    g_err = buf;
+    return ILE_E_DEVICE;
+}
+
+size_t eval_lds_limit() {
+    static size_t lim = 0;
+    if (lim == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            lim = (size_t)v;
+        else
+            lim = 65536;
+    }
+    return lim;
+}
+
+hipError_t launch_eval(int set, int kdet, int policy, bool dm, size_t lds_bytes, const EvalJob *d_jobs,
+                       const Tile *d_tiles, int n_tiles, const EvalJob &single, int64_t tile, int block,
+                       hipStream_t st) {
+#define ILE_SP(S)                                                                                            \
+    if (set == S) {                                                                                          \
+        if (policy == 0) return launch_eval_sp<S, 0>(kdet, dm, lds_bytes, d_jobs, d_tiles, n_tiles, single, tile, block, st); \
+        if (policy == 1) return launch_eval_sp<S, 1>(kdet, dm, lds_bytes, d_jobs, d_tiles, n_tiles, single, tile, block, st); \
+        if (policy == 2) return launch_eval_sp<S, 2>(kdet, dm, lds_bytes, d_jobs, d_tiles, n_tiles, single, tile, block, st); \
+    }
+    ILE_SP(0)
+    ILE_SP(1)
+    ILE_SP(2)
+    ILE_SP(3)
+#undef ILE_SP
+    return hipErrorInvalidValue;
+}
+
+// Contraction element size of a policy (Q, U, V storage).
+static size_t creal_size(int policy) { return policy == kFP32 ? sizeof(float) : sizeof(double); }
+size_t theta_size(int policy) { return policy == kFP64 ? sizeof(double) : sizeof(float); }
+size_t out_size(int policy) { return policy == kFP32 ? sizeof(float) : sizeof(double); }
+
+// Window bytes of a job, and whether an LDS-staged kernel exists for it (the
+// same rule the kernel instantiation uses, plus the device limit).
+size_t job_window_bytes(const ile_job *job) {
+    return (size_t)job->kp * job->n_time * kSets[job->set].n * 2 * creal_size(job->policy);
+}
+bool job_lds_ok(const ile_job *job) {
+    const size_t compiled = (size_t)job->kp * 410 * kSets[job->set].n * 2 * creal_size(job->policy);
+    return compiled <= 163840 && job_window_bytes(job) <= eval_lds_limit();
+}
+
+// Launch geometry of one eval over n samples of a job (single-job path).
+void eval_geometry(const ile_job *job, int64_t n, size_t *lds, int64_t *tile, int *block) {
+    const size_t win = job_window_bytes(job);
+    const int64_t cus = 256;
+    // stage the window in LDS only when each block gets enough samples to pay for it
+    if (job_lds_ok(job) && n >= (int64_t)2 * cus * 16384) {
+        *lds = win;
+        *block = 512;
+        *tile = std::max<int64_t>(16384, (n + 2 * cus - 1) / (2 * cus));
+    } else {
+        *lds = 0;
+        *block = 256;
+        int64_t t = (n + 4 * cus - 1) / (4 * cus);
+        t = ((t + 255) / 256) * 256;
+        *tile = std::min<int64_t>(std::max<int64_t>(t, 256), 8192);
+    }
+}
+
+ile_status ctx_check(ile_ctx *ctx) {
+    if (!ctx) return set_err(ILE_E_INVALID, "null context");
+    if (ctx->sticky) return set_err(ILE_E_DEVICE, "context is in a failed state after an earlier device error");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return dev_fail(ctx, e, "hipSetDevice");
+    return ILE_OK;
+}
+
+ile_status ctx_alloc(ile_ctx *ctx, void **p, size_t bytes, const char *what) {
+    *p = nullptr;
+    if (bytes == 0) return ILE_OK;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->budget && ctx->used + bytes > ctx->budget)
+            return set_err(ILE_E_TOO_BIG, std::string("device budget exceeded allocating ") + what);
+        ctx->used += bytes;
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->used -= bytes;
+        *p = nullptr;
+        (void)hipGetLastError();
+        return set_err(ILE_E_NOMEM, std::string("hipMalloc failed for ") + what);
+    }
+    return ILE_OK;
+}
+
+void ctx_free(ile_ctx *ctx, void *p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->used -= bytes;
+}
+
+// Distance table shared by every job of a context with the same prior.
+ile_status ctx_dist_table(ile_ctx *ctx, const PriorDev &pr, DistTable *out, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(ctx->dist_mu);
+    auto key = std::make_tuple(pr.d_min, pr.d_max, pr.d_ref);
+    auto it = ctx->dist.find(key);
+    if (it != ctx->dist.end()) {
+        *out = it->second.tab;
+        return ILE_OK;
+    }
+    void *buf = nullptr;
+    ile_status s = ctx_alloc(ctx, &buf, dist_table_bytes(), "distance table");
+    if (s != ILE_OK) return s;
+    DistTable tb{};
+    hipError_t e = build_dist_table(&tb, (double *)buf, pr, st);
+    if (e != hipSuccess) return dev_fail(ctx, e, "build_dist_table");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return dev_fail(ctx, e, "distance table build");
+    ctx->dist[key] = ile_ctx::DistEntry{tb, buf};
+    *out = tb;
+    return ILE_OK;
+}
+
+}  // namespace ile
+
+// ===================================================================== context
+extern "C" ile_status ile_ctx_create(int hip_device, size_t hbm_budget_bytes, ile_ctx **out) {
+    if (!out) return set_err(ILE_E_INVALID, "null output pointer");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) return set_err(ILE_E_DEVICE, "no HIP device available");
+    if (hip_device < 0 || hip_device >= n) return set_err(ILE_E_INVALID, "device index out of range");
+    e = hipSetDevice(hip_device);
+    if (e != hipSuccess) return dev_fail(nullptr, e, "hipSetDevice");
+    ile_ctx *c = new ile_ctx();
+    c->device = hip_device;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess && hbm_budget_bytes == 0) hbm_budget_bytes = tot;
+    c->budget = hbm_budget_bytes;
+    *out = c;
+    return ILE_OK;
+}
+
+extern "C" void ile_ctx_destroy(ile_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : ctx->dist) (void)hipFree(kv.second.buf);
+    if (ctx->d_batch) (void)hipFree(ctx->d_batch);
+    if (ctx->h_batch) (void)hipHostFree(ctx->h_batch);
+    if (ctx->batch_ev) (void)hipEventDestroy(ctx->batch_ev);
+    if (ctx->d_part) (void)hipFree(ctx->d_part);
+    if (ctx->d_mout) (void)hipFree(ctx->d_mout);
+    if (ctx->h_mout) (void)hipHostFree(ctx->h_mout);
+    delete ctx;
+}
+
+extern "C" const char *ile_last_error(void) { return g_err.c_str(); }
+
+// ===================================================================== prepare
+namespace {
+
+int set_slot(int set, int l, int m) {
+    for (int a = 0; a < kSets[set].n; a++)
+        if (kSets[set].l[a] == l && kSets[set].m[a] == m) return a;
+    return -1;
+}
+
+template <class R>
+void fill_tables(const ile_problem *P, const std::vector<int> &keep, const std::vector<int> &slot, int set, int kp,
+                 std::vector<R> &Qh, std::vector<R> &Uh, std::vector<R> &Vh) {
+    using cd = std::complex<double>;
+    const int NM = kSets[set].n, T = P->n_time, K = P->n_det, n = P->n_modes;
+    const PairTable pt = make_pairs(set);
+    Qh.assign((size_t)kp * T * NM * 2, R(0));
+    for (int k = 0; k < K; k++)
+        for (size_t q = 0; q < keep.size(); q++) {
+            const int a = keep[q], s = slot[q];
+            for (int i = 0; i < T; i++) {
+                const double *src = P->Q + 2 * (((size_t)k * n + a) * T + i);
+                R *dst = &Qh[2 * (((size_t)k * T + i) * NM + s)];
+                dst[0] = (R)src[0];
+                dst[1] = (R)src[1];
+            }
+        }
+    // user mode of each slot (-1: empty)
+    std::vector<int> user(NM, -1);
+    for (size_t q = 0; q < keep.size(); q++) user[slot[q]] = keep[q];
+    auto U = [&](int k, int a, int b) {
+        const double *p = P->U + 2 * (((size_t)k * n + a) * n + b);
+        return cd(p[0], p[1]);
+    };
+    auto V = [&](int k, int a, int b) {
+        if (!P->V) return cd(0, 0);
+        const double *p = P->V + 2 * (((size_t)k * n + a) * n + b);
+        return cd(p[0], p[1]);
+    };
+    Uh.assign((size_t)pt.P * kp * 2, R(0));
+    Vh.assign((size_t)pt.P * kp * 2, R(0));
+    for (int j = 0; j < pt.P; j++) {
+        // U-order entry j
+        {
+            const int p = pt.u_pair[j], sa = pt.a[p], sb = pt.b[p];
+            const int ua = user[sa], ub = user[sb];
+            if (ua >= 0 && ub >= 0)
+                for (int k = 0; k < K; k++) {
+                    cd h = 0.5 * (U(k, ua, ub) + std::conj(U(k, ub, ua)));  // Hermitian part
+                    if (sa != sb) {
+                        h *= 2.0;
+                        if (kSets[set].m[sa] < kSets[set].m[sb]) h = std::conj(h);
+                    } else {
+                        h = cd(h.real(), 0.0);
+                    }
+                    Uh[2 * ((size_t)j * kp + k)] = (R)h.real();
+                    Uh[2 * ((size_t)j * kp + k) + 1] = (R)h.imag();
+                }
+        }
+        {
+            const int p = pt.v_pair[j], sa = pt.a[p], sb = pt.b[p];
+            const int ua = user[sa], ub = user[sb];
+            if (ua >= 0 && ub >= 0)
+                for (int k = 0; k < K; k++) {
+                    cd v = 0.5 * (V(k, ua, ub) + V(k, ub, ua));  // symmetric part
+                    if (sa != sb) v *= 2.0;
+                    Vh[2 * ((size_t)j * kp + k)] = (R)v.real();
+                    Vh[2 * ((size_t)j * kp + k) + 1] = (R)v.imag();
+                }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" ile_status ile_prepare(ile_ctx *ctx, const ile_problem *P, ile_job **out) {
+    ile_status s = ctx_check(ctx);
+    if (s != ILE_OK) return s;
+    if (!out || !P) return set_err(ILE_E_INVALID, "null argument");
+    *out = nullptr;
+    const int K = P->n_det, n = P->n_modes, T = P->n_time;
+    if (K < 1 || K > 3) return set_err(ILE_E_INVALID, "n_det must be 1..3");
+    if (n < 1 || n > kMaxModes) return set_err(ILE_E_INVALID, "n_modes must be 1..21");
+    if (T < 4) return set_err(ILE_E_INVALID, "n_time must be >= 4");
+    if (!P->mode_l || !P->mode_m || !P->det_pos || !P->det_resp || !P->Q || !P->U)
+        return set_err(ILE_E_INVALID, "null input array");
+    if (P->precision < 0 || P->precision > 2) return set_err(ILE_E_INVALID, "unknown precision policy");
+    if (!(P->dt_s > 0) || !std::isfinite(P->tau0_s) || !std::isfinite(P->gmst_rad))
+        return set_err(ILE_E_INVALID, "bad window or gmst");
+    if (!(P->d_ref_mpc > 0)) return set_err(ILE_E_INVALID, "d_ref must be > 0");
+    if (!(P->prior.t_window > 0) || !(P->prior.d_min > 0) || !(P->prior.d_max > P->prior.d_min))
+        return set_err(ILE_E_INVALID, "bad prior ranges");
+    if (!(P->mode_filter_eps >= 0)) return set_err(ILE_E_INVALID, "mode_filter_eps must be >= 0");
+    for (int a = 0; a < n; a++) {
+        const int l = P->mode_l[a], m = P->mode_m[a];
+        if (l < 2 || l > 4 || m < -l || m > l) return set_err(ILE_E_INVALID, "mode (l,m) outside l=2..4, |m|<=l");
+        for (int b = 0; b < a; b++)
+            if (P->mode_l[b] == l && P->mode_m[b] == m) return set_err(ILE_E_INVALID, "duplicate mode");
+    }
+    // finiteness and symmetry of the inputs
+    const size_t nq = (size_t)K * n * T * 2, nu = (size_t)K * n * n * 2;
+    for (size_t i = 0; i < nq; i++)
+        if (!std::isfinite(P->Q[i])) return set_err(ILE_E_INVALID, "non-finite Q");
+    double umax = 0.0, vmax = 0.0;
+    for (size_t i = 0; i < nu; i++) {
+        if (!std::isfinite(P->U[i]) || (P->V && !std::isfinite(P->V[i]))) return set_err(ILE_E_INVALID, "non-finite U or V");
+        umax = std::max(umax, std::fabs(P->U[i]));
+        if (P->V) vmax = std::max(vmax, std::fabs(P->V[i]));
+    }
+    for (int k = 0; k < K; k++)
+        for (int a = 0; a < n; a++)
+            for (int b = 0; b < n; b++) {
+                const double *u1 = P->U + 2 * (((size_t)k * n + a) * n + b);
+                const double *u2 = P->U + 2 * (((size_t)k * n + b) * n + a);
+                if (std::fabs(u1[0] - u2[0]) > 1e-9 * umax || std::fabs(u1[1] + u2[1]) > 1e-9 * umax)
+                    return set_err(ILE_E_INVALID, "U is not Hermitian");
+                if (P->V) {
+                    const double *v1 = P->V + 2 * (((size_t)k * n + a) * n + b);
+                    const double *v2 = P->V + 2 * (((size_t)k * n + b) * n + a);
+                    if (std::fabs(v1[0] - v2[0]) > 1e-9 * vmax || std::fabs(v1[1] - v2[1]) > 1e-9 * vmax)
+                        return set_err(ILE_E_INVALID, "V is not symmetric");
+                }
+            }
+    if (!P->V) {
+        bool pos = false, neg = false;
+        for (int a = 0; a < n; a++) {
+            pos = pos || P->mode_m[a] > 0;
+            neg = neg || P->mode_m[a] < 0;
+        }
+        if (pos && neg) return set_err(ILE_E_INVALID, "V may be NULL only if all m share a sign");
+    }
+    for (int k = 0; k < K; k++)
+        for (int c = 0; c < 3; c++)
+            if (!std::isfinite(P->det_pos[3 * k + c])) return set_err(ILE_E_INVALID, "non-finite detector position");
+    for (int i = 0; i < 9 * K; i++)
+        if (!std::isfinite(P->det_resp[i])) return set_err(ILE_E_INVALID, "non-finite detector response");
+
+    // mode filter: keep (l,m) iff some |U_0[lm][l'm'] / U_0[22][22]| > eps (detector 0)
+    std::vector<int> keep;
+    if (P->mode_filter_eps > 0) {
+        int a22 = -1;
+        for (int a = 0; a < n; a++)
+            if (P->mode_l[a] == 2 && P->mode_m[a] == 2) a22 = a;
+        if (a22 < 0) return set_err(ILE_E_INVALID, "mode filter needs the (2,2) mode");
+        const double *u22 = P->U + 2 * ((size_t)a22 * n + a22);
+        const double ref = std::hypot(u22[0], u22[1]);
+        if (!(ref > 0)) return set_err(ILE_E_INVALID, "mode filter needs U_22,22 > 0");
+        for (int a = 0; a < n; a++) {
+            double mx = 0.0;
+            for (int b = 0; b < n; b++) {
+                const double *u = P->U + 2 * ((size_t)a * n + b);
+                mx = std::max(mx, std::hypot(u[0], u[1]) / ref);
+            }
+            if (mx > P->mode_filter_eps) keep.push_back(a);
+        }
+    } else {
+        for (int a = 0; a < n; a++) keep.push_back(a);
+    }
+    // smallest compiled set containing every kept mode
+    int set = -1;
+    std::vector<int> slot(keep.size());
+    for (int sidx = 0; sidx < kNumSets && set < 0; sidx++) {
+        bool all = true;
+        for (size_t q = 0; q < keep.size() && all; q++) {
+            slot[q] = set_slot(sidx, P->mode_l[keep[q]], P->mode_m[keep[q]]);
+            all = slot[q] >= 0;
+        }
+        if (all) set = sidx;
+    }
+    if (set < 0) return set_err(ILE_E_INVALID, "mode list not representable");
+    const int kp = K == 1 ? 2 : K;
+
+    ile_job *job = new ile_job();
+    job->ctx = ctx;
+    job->policy = P->precision;
+    job->set = set;
+    job->kp = kp;
+    job->n_det = K;
+    job->n_time = T;
+    job->n_kept = (int)keep.size();
+    job->dist_marg = P->prior.dist_marg != 0;
+    job->pr = PriorDev{P->prior.t_window, P->prior.d_min, P->prior.d_max, P->d_ref_mpc, job->dist_marg ? 1 : 0};
+
+    std::vector<char> Qb, Ub, Vb;
+    if (job->policy == kFP32) {
+        std::vector<float> q, u, v;
+        fill_tables<float>(P, keep, slot, set, kp, q, u, v);
+        Qb.assign((char *)q.data(), (char *)(q.data() + q.size()));
+        Ub.assign((char *)u.data(), (char *)(u.data() + u.size()));
+        Vb.assign((char *)v.data(), (char *)(v.data() + v.size()));
+    } else {
+        std::vector<double> q, u, v;
+        fill_tables<double>(P, keep, slot, set, kp, q, u, v);
+        Qb.assign((char *)q.data(), (char *)(q.data() + q.size()));
+        Ub.assign((char *)u.data(), (char *)(u.data() + u.size()));
+        Vb.assign((char *)v.data(), (char *)(v.data() + v.size()));
+    }
+    job->q_bytes = Qb.size();
+    job->uv_bytes = Ub.size();
+    auto cleanup = [&](ile_status st) {
+        ile_job_release(job);
+        return st;
+    };
+    if ((s = ctx_alloc(ctx, &job->d_Q, Qb.size(), "Q window")) != ILE_OK) return cleanup(s);
+    if ((s = ctx_alloc(ctx, &job->d_Ut, Ub.size(), "U table")) != ILE_OK) return cleanup(s);
+    if ((s = ctx_alloc(ctx, &job->d_Vt, Vb.size(), "V table")) != ILE_OK) return cleanup(s);
+    if ((s = ctx_alloc(ctx, (void **)&job->d_ms, sizeof(MargState), "estimator state")) != ILE_OK) return cleanup(s);
+    hipError_t e;
+    if ((e = hipMemcpy(job->d_Q, Qb.data(), Qb.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(dev_fail(ctx, e, "upload Q"));
+    if ((e = hipMemcpy(job->d_Ut, Ub.data(), Ub.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(dev_fail(ctx, e, "upload U"));
+    if ((e = hipMemcpy(job->d_Vt, Vb.data(), Vb.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(dev_fail(ctx, e, "upload V"));
+    MargState ms0{-INFINITY, 0.0, 0.0, 0, 0, -1};
+    if ((e = hipMemcpy(job->d_ms, &ms0, sizeof ms0, hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(dev_fail(ctx, e, "init estimator"));
+    if ((e = hipHostMalloc((void **)&job->h_ms, sizeof(MargState), hipHostMallocDefault)) != hipSuccess)
+        return cleanup(dev_fail(ctx, e, "pinned result buffer"));
+
+    EvalJob &ej = job->ej;
+    std::memset(&ej, 0, sizeof ej);
+    ej.Q = job->d_Q;
+    ej.Ut = job->d_Ut;
+    ej.Vt = job->d_Vt;
+    ej.tau0 = P->tau0_s;
+    ej.inv_dt = 1.0 / P->dt_s;
+    ej.gmst = P->gmst_rad;
+    ej.d_ref = P->d_ref_mpc;
+    ej.n_time = T;
+    const double c_si = 299792458.0;
+    for (int k = 0; k < kp; k++) {
+        const int ks = k < K ? k : 0;      // padded detector: same position, zero response
+        for (int c = 0; c < 3; c++) ej.xc[k][c] = P->det_pos[3 * ks + c] / c_si;
+        const double *d = P->det_resp + 9 * ks;
+        const double f = k < K ? 1.0 : 0.0;
+        ej.D[k][0] = f * d[0];
+        ej.D[k][1] = f * d[4];
+        ej.D[k][2] = f * d[8];
+        ej.D[k][3] = f * 0.5 * (d[1] + d[3]);
+        ej.D[k][4] = f * 0.5 * (d[2] + d[6]);
+        ej.D[k][5] = f * 0.5 * (d[5] + d[7]);
+    }
+    if (job->dist_marg) {
+        if ((s = ctx_dist_table(ctx, job->pr, &ej.dt, nullptr)) != ILE_OK) return cleanup(s);
+    }
+    job->device_bytes = Qb.size() + Ub.size() + Vb.size() + sizeof(MargState);
+    *out = job;
+    return ILE_OK;
+}
+
+extern "C" ile_status ile_job_info_get(const ile_job *job, ile_job_info *info) {
+    if (!job || !info) return set_err(ILE_E_INVALID, "null argument");
+    info->n_modes_kept = job->n_kept;
+    info->mode_slots = kSets[job->set].n;
+    info->n_det_slots = job->kp;
+    info->device_bytes = job->device_bytes + job->part_cap * sizeof(MargPartial) + job->em_cap +
+                         (job->d_gmm ? sizeof(GmmDev) : 0);
+    return ILE_OK;
+}
+
+extern "C" void ile_job_release(ile_job *job) {
+    if (!job) return;
+    ile_ctx *ctx = job->ctx;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx_free(ctx, job->d_Q, job->q_bytes);
+    ctx_free(ctx, job->d_Ut, job->uv_bytes);
+    ctx_free(ctx, job->d_Vt, job->uv_bytes);
+    ctx_free(ctx, job->d_ms, sizeof(MargState));
+    ctx_free(ctx, job->d_part, job->part_cap * sizeof(MargPartial));
+    ctx_free(ctx, job->d_em, job->em_cap);
+    ctx_free(ctx, job->d_gmm, sizeof(GmmDev));
+    ctx_free(ctx, job->d_zcount, kMaxComp * sizeof(uint32_t));
+    if (job->h_ms) (void)hipHostFree(job->h_ms);
+    if (job->h_gmm) (void)hipHostFree(job->h_gmm);
+    delete job;
+}
+
+// ===================================================================== eval
+extern "C" ile_status ile_eval_lnL(ile_job *job, int64_t n, const void *theta, int64_t ld, const void *lnpmps,
+                                   void *lnL_out, void *lw_out, ile_stream stream) {
+    if (!job) return set_err(ILE_E_INVALID, "null job");
+    ile_status s = ctx_check(job->ctx);
+    if (s != ILE_OK) return s;
+    if (n < 0 || ld < n) return set_err(ILE_E_INVALID, "need n >= 0 and ld >= n");
+    if (n == 0) return ILE_OK;
+    if (!theta || !lnL_out) return set_err(ILE_E_INVALID, "null theta or lnL_out");
+    EvalJob ej = job->ej;
+    ej.theta = theta;
+    ej.ld = ld;
+    ej.lnpmps = lnpmps;
+    ej.lnL = lnL_out;
+    ej.lw = lw_out;
+    ej.n = n;
+    size_t lds;
+    int64_t tile;
+    int block;
+    eval_geometry(job, n, &lds, &tile, &block);
+    const int64_t nt = (n + tile - 1) / tile;
+    if (nt > INT32_MAX) return set_err(ILE_E_INVALID, "too many samples for one launch");
+    hipError_t e = launch_eval(job->set, job->kp, job->policy, job->dist_marg, lds, nullptr, nullptr, (int)nt, ej,
+                               tile, block, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(job->ctx, e, "eval launch");
+    return ILE_OK;
+}
+
+extern "C" ile_status ile_eval_lnL_batch(ile_job *const *jobs, int32_t n_jobs, const int64_t *n,
+                                         const void *const *theta, const int64_t *ld, const void *const *lnpmps,
+                                         void *const *lnL_out, void *const *lw_out, ile_stream stream) {
+    if (n_jobs <= 0) return ILE_OK;
+    if (!jobs || !n || !theta || !ld || !lnL_out) return set_err(ILE_E_INVALID, "null argument");
+    ile_ctx *ctx = jobs[0] ? jobs[0]->ctx : nullptr;
+    ile_status s = ctx_check(ctx);
+    if (s != ILE_OK) return s;
+    std::vector<BatchItem> items;
+    for (int j = 0; j < n_jobs; j++) {
+        if (!jobs[j] || jobs[j]->ctx != ctx) return set_err(ILE_E_INVALID, "jobs must share one context");
+        if (n[j] < 0 || ld[j] < n[j]) return set_err(ILE_E_INVALID, "need n >= 0 and ld >= n");
+        if (n[j] > 0 && (!theta[j] || !lnL_out[j])) return set_err(ILE_E_INVALID, "null theta or lnL_out");
+        items.push_back(BatchItem{jobs[j], n[j], theta[j], ld[j], lnpmps ? lnpmps[j] : nullptr, lnL_out[j],
+                                  lw_out ? lw_out[j] : nullptr});
+    }
+    return eval_batch(ctx, items, (hipStream_t)stream);
+}
+
+namespace ile {
+
+// Group jobs by compiled kernel, upload the descriptors and tile lists through
+// the context's pinned staging buffer, and launch one kernel per group.
+ile_status eval_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, hipStream_t st) {
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
+    for (size_t i = 0; i < items.size(); i++) {
+        const ile_job *j = items[i].job;
+        if (items[i].n == 0) continue;
+        groups[std::make_tuple(j->set, j->kp, j->policy, (int)j->dist_marg)].push_back((int)i);
+    }
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    for (auto &g : groups) {
+        const auto &idx = g.second;
+        int64_t total = 0;
+        size_t win = 0;
+        bool lds_ok = true;
+        for (int i : idx) {
+            total += items[i].n;
+            const ile_job *j = items[i].job;
+            win = std::max(win, job_window_bytes(j));
+            lds_ok = lds_ok && job_lds_ok(j);
+        }
+        const int64_t cus = 256;
+        const bool lds = lds_ok && total >= (int64_t)2 * cus * 16384 && total / (int64_t)idx.size() >= 65536;
+        const int64_t tile = lds ? 65536 : 8192;
+        std::vector<EvalJob> ej;
+        std::vector<Tile> tiles;
+        for (int i : idx) {
+            const BatchItem &b = items[i];
+            EvalJob e = b.job->ej;
+            e.theta = b.theta;
+            e.ld = b.ld;
+            e.lnpmps = b.lnpmps;
+            e.lnL = b.lnL;
+            e.lw = b.lw;
+            e.n = b.n;
+            const int jid = (int)ej.size();
+            ej.push_back(e);
+            for (int64_t t0 = 0; t0 < b.n; t0 += tile) tiles.push_back(Tile{jid, 0, t0, std::min(t0 + tile, b.n)});
+        }
+        void *dj = nullptr, *dt = nullptr;
+        ile_status s = batch_upload(ctx, ej.data(), ej.size() * sizeof(EvalJob), tiles.data(),
+                                    tiles.size() * sizeof(Tile), &dj, &dt, st);
+        if (s != ILE_OK) return s;
+        const auto &key = g.first;
+        hipError_t e = launch_eval(std::get<0>(key), std::get<1>(key), std::get<2>(key), std::get<3>(key) != 0,
+                                   lds ? win : 0, (const EvalJob *)dj, (const Tile *)dt, (int)tiles.size(), ej[0],
+                                   tile, lds ? 512 : 256, st);
+        if (e != hipSuccess) return dev_fail(ctx, e, "batched eval launch");
+        e = hipEventRecord(ctx->batch_ev, st);
+        if (e != hipSuccess) return dev_fail(ctx, e, "batch event");
+    }
+    return ILE_OK;
+}
+
+// Copy two host arrays into the context's device scratch through pinned
+// staging; the previous batch's copy must have completed before the staging
+// buffer is rewritten (tracked by batch_ev).  Caller holds batch_mu.
+ile_status batch_upload(ile_ctx *ctx, const void *a, size_t na, const void *b, size_t nb, void **da, void **db,
+                        hipStream_t st) {
+    const size_t oa = 0, ob = (na + 255) / 256 * 256, need = ob + nb;
+    hipError_t e;
+    if (!ctx->batch_ev) {
+        if ((e = hipEventCreateWithFlags(&ctx->batch_ev, hipEventDisableTiming)) != hipSuccess)
+            return dev_fail(ctx, e, "event create");
+    }
+    if ((e = hipEventSynchronize(ctx->batch_ev)) != hipSuccess) return dev_fail(ctx, e, "batch event wait");
+    if (need > ctx->batch_cap) {
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return dev_fail(ctx, e, "sync before scratch growth");
+        if (ctx->d_batch) (void)hipFree(ctx->d_batch);
+        if (ctx->h_batch) (void)hipHostFree(ctx->h_batch);
+        ctx->d_batch = nullptr;
+        ctx->h_batch = nullptr;
+        const size_t cap = std::max<size_t>(need * 2, 1 << 20);
+        if ((e = hipMalloc(&ctx->d_batch, cap)) != hipSuccess) return dev_fail(ctx, e, "batch scratch");
+        if ((e = hipHostMalloc(&ctx->h_batch, cap, hipHostMallocDefault)) != hipSuccess)
+            return dev_fail(ctx, e, "batch staging");
+        ctx->batch_cap = cap;
+    }
+    std::memcpy((char *)ctx->h_batch + oa, a, na);
+    std::memcpy((char *)ctx->h_batch + ob, b, nb);
+    if ((e = hipMemcpyAsync(ctx->d_batch, ctx->h_batch, need, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return dev_fail(ctx, e, "batch upload");
+    *da = (char *)ctx->d_batch + oa;
+    *db = (char *)ctx->d_batch + ob;
+    return ILE_OK;
+}
+
+}  // namespace ile
+
+// ================================================================ marginalise
+namespace ile {
+constexpr int64_t kMargTile = 16384;
+
+void marg_from_state(const MargState &m, ile_marg *out) {
+    out->n = m.n;
+    out->n_nonfinite = m.n_bad;
+    out->max_lw = m.m;
+    out->argmax = m.argmax;
+    if (!(m.m > -INFINITY) || m.n == 0) {
+        out->ln_L = -INFINITY;
+        out->ln_sigma = -INFINITY;
+        out->n_eff = 0.0;
+        out->n_ess = 0.0;
+        out->argmax = -1;
+        return;
+    }
+    out->ln_L = m.m + std::log(m.s1) - std::log((double)m.n);
+    out->n_eff = m.s1;
+    out->n_ess = m.s1 * m.s1 / m.s2;
+    if (m.n > 1) {
+        const double v = ((double)m.n * m.s2 / (m.s1 * m.s1) - 1.0) / (double)(m.n - 1);
+        out->ln_sigma = out->ln_L + 0.5 * std::log(v > 0 ? v : 0.0);
+    } else {
+        out->ln_sigma = -INFINITY;
+    }
+}
+
+ile_status job_marg_launch(ile_job *job, int64_t n, const void *lw, bool reset, hipStream_t st) {
+    ile_ctx *ctx = job->ctx;
+    const int64_t np = std::max<int64_t>(1, (n + kMargTile - 1) / kMargTile);
+    if ((size_t)np > job->part_cap) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return dev_fail(ctx, e, "sync before partials growth");
+        ctx_free(ctx, job->d_part, job->part_cap * sizeof(MargPartial));
+        job->d_part = nullptr;
+        job->part_cap = 0;
+        ile_status s = ctx_alloc(ctx, (void **)&job->d_part, (size_t)np * sizeof(MargPartial), "partials");
+        if (s != ILE_OK) return s;
+        job->part_cap = (size_t)np;
+    }
+    hipError_t e = hipSuccess;
+    if (n > 0) e = launch_marg_partials(job->policy, lw, n, kMargTile, job->d_part, st);
+    if (e != hipSuccess) return dev_fail(ctx, e, "marginal partials");
+    e = launch_marg_combine(job->d_part, n > 0 ? (int)np : 0, n, job->d_ms, reset ? 1 : 0, st);
+    if (e != hipSuccess) return dev_fail(ctx, e, "marginal combine");
+    return ILE_OK;
+}
+}  // namespace ile
+
+extern "C" ile_status ile_marginalize(ile_job *job, int64_t n, const void *lw, uint32_t flags, ile_marg *out,
+                                      ile_stream stream) {
+    if (!job) return set_err(ILE_E_INVALID, "null job");
+    ile_status s = ctx_check(job->ctx);
+    if (s != ILE_OK) return s;
+    if (n < 0 || (n > 0 && !lw)) return set_err(ILE_E_INVALID, "bad lw");
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = job_marg_launch(job, n, lw, (flags & ILE_MARG_RESET) != 0, st)) != ILE_OK) return s;
+    if (out) {
+        hipError_t e = hipMemcpyAsync(job->h_ms, job->d_ms, sizeof(MargState), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return dev_fail(job->ctx, e, "read estimator");
+        marg_from_state(*job->h_ms, out);
+    }
+    return ILE_OK;
+}
+
+// ====================================================================== draws
+extern "C" ile_status ile_draw(ile_job *job, uint64_t seed, uint32_t round, int64_t first_index, int64_t n,
+                               void *theta_out, int64_t ld, void *lnpmps_out, ile_stream stream) {
+    if (!job) return set_err(ILE_E_INVALID, "null job");
+    ile_status s = ctx_check(job->ctx);
+    if (s != ILE_OK) return s;
+    if (n < 0 || ld < n || first_index < 0) return set_err(ILE_E_INVALID, "need n >= 0, ld >= n, first >= 0");
+    if (n == 0) return ILE_OK;
+    if (!theta_out) return set_err(ILE_E_INVALID, "null theta_out");
+    DrawJob dj{};
+    dj.gmm = job->has_prop ? job->d_gmm : nullptr;
+    dj.pr = job->pr;
+    dj.seed = seed;
+    dj.round = round;
+    dj.first = first_index;
+    dj.theta = theta_out;
+    dj.ld = ld;
+    dj.lnpmps = lnpmps_out;
+    dj.n = n;
+    const int64_t tile = 2048;
+    const int64_t nt = (n + tile - 1) / tile;
+    if (nt > INT32_MAX) return set_err(ILE_E_INVALID, "too many samples for one launch");
+    hipError_t e = launch_draw(job->policy, nullptr, nullptr, (int)nt, dj, tile, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(job->ctx, e, "draw launch");
+    return ILE_OK;
+}
+
+// =================================================================== proposal
+namespace ile {
+
+static void default_dims(const ile_job *job, int *nd, int dims[7]) {
+    int k = 0;
+    for (int c = 0; c < 7; c++)
+        if (!(job->dist_marg && c == 3)) dims[k++] = c;
+    *nd = k;
+}
+
+static ile_status ensure_gmm(ile_job *job) {
+    if (job->d_gmm) return ILE_OK;
+    ile_status s = ctx_alloc(job->ctx, (void **)&job->d_gmm, sizeof(GmmDev), "mixture state");
+    if (s != ILE_OK) return s;
+    s = ctx_alloc(job->ctx, (void **)&job->d_zcount, kMaxComp * sizeof(uint32_t), "mass counters");
+    if (s != ILE_OK) return s;
+    hipError_t e = hipHostMalloc((void **)&job->h_gmm, sizeof(GmmDev), hipHostMallocDefault);
+    if (e != hipSuccess) return dev_fail(job->ctx, e, "pinned mixture buffer");
+    return ILE_OK;
+}
+
+static ile_status estimate_mass(ile_job *job, const ile_gmm_opts *o, hipStream_t st) {
+    const uint64_t seed = o ? o->seed : 0x243F6A8885A308D3ull;
+    const uint32_t round = o ? o->round : 0;
+    const int64_t m = (o && o->z_draws > 0) ? o->z_draws : 65536;
+    hipError_t e = hipMemsetAsync(job->d_zcount, 0, kMaxComp * sizeof(uint32_t), st);
+    if (e == hipSuccess) e = launch_gmm_inbox(job->d_gmm, job->pr, seed, round, m, job->d_zcount, st);
+    if (e == hipSuccess) e = launch_gmm_setz(job->d_gmm, job->d_zcount, m, st);
+    if (e != hipSuccess) return dev_fail(job->ctx, e, "in-support mass");
+    return ILE_OK;
+}
+
+}  // namespace ile
+
+extern "C" ile_status ile_set_proposal(ile_job *job, const ile_gmm_params *p, const ile_gmm_opts *opts,
+                                       ile_stream stream) {
+    if (!job || !p) return set_err(ILE_E_INVALID, "null argument");
+    ile_status s = ctx_check(job->ctx);
+    if (s != ILE_OK) return s;
+    if (p->n_comp < 1 || p->n_comp > kMaxComp) return set_err(ILE_E_INVALID, "n_comp must be 1..16");
+    if (!(p->eps_def >= 0 && p->eps_def < 1)) return set_err(ILE_E_INVALID, "eps_def must be in [0,1)");
+    if ((s = ensure_gmm(job)) != ILE_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return dev_fail(job->ctx, e, "sync before proposal upload");
+    GmmDev &g = *job->h_gmm;
+    std::memset(&g, 0, sizeof g);
+    default_dims(job, &g.n_dim, g.dims);
+    g.n_comp = p->n_comp;
+    g.eps_def = p->eps_def;
+    double wsum = 0.0;
+    for (int j = 0; j < p->n_comp; j++) {
+        if (!(p->weight[j] >= 0) || !std::isfinite(p->weight[j])) return set_err(ILE_E_INVALID, "bad weight");
+        wsum += p->weight[j];
+    }
+    if (!(wsum > 0)) return set_err(ILE_E_INVALID, "weights sum to zero");
+    for (int j = 0; j < p->n_comp; j++) {
+        g.w[j] = p->weight[j];
+        for (int a = 0; a < g.n_dim; a++) {
+            g.mean[j][a] = p->mean[j][a];
+            for (int b = 0; b < g.n_dim; b++) g.cov[j][a][b] = p->cov[j][a][b];
+        }
+    }
+    if ((e = hipMemcpyAsync(job->d_gmm, job->h_gmm, sizeof(GmmDev), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return dev_fail(job->ctx, e, "proposal upload");
+    if ((e = launch_gmm_factor(job->d_gmm, st)) != hipSuccess) return dev_fail(job->ctx, e, "factor");
+    if ((s = estimate_mass(job, opts, st)) != ILE_OK) return s;
+    if ((e = hipMemcpyAsync(job->h_gmm, job->d_gmm, sizeof(GmmDev), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return dev_fail(job->ctx, e, "proposal readback");
+    if (!job->h_gmm->valid) return set_err(ILE_E_INVALID, "a covariance is not positive definite");
+    job->has_prop = true;
+    return ILE_OK;
+}
+
+extern "C" ile_status ile_get_proposal(ile_job *job, ile_gmm_params *p, ile_stream stream) {
+    if (!job || !p) return set_err(ILE_E_INVALID, "null argument");
+    ile_status s = ctx_check(job->ctx);
+    if (s != ILE_OK) return s;
+    if (!job->has_prop) return set_err(ILE_E_STATE, "job has no proposal");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(job->h_gmm, job->d_gmm, sizeof(GmmDev), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return dev_fail(job->ctx, e, "proposal readback");
+    const GmmDev &g = *job->h_gmm;
+    std::memset(p, 0, sizeof *p);
+    p->n_comp = g.n_comp;
+    p->n_dim = g.n_dim;
+    for (int a = 0; a < 7; a++) p->dims[a] = a < g.n_dim ? g.dims[a] : -1;
+    p->eps_def = g.eps_def;
+    for (int j = 0; j < g.n_comp; j++) {
+        p->weight[j] = g.w[j];
+        p->ln_Z[j] = g.lnZ[j];
+        for (int a = 0; a < 7; a++) {
+            p->mean[j][a] = g.mean[j][a];
+            for (int b = 0; b < 7; b++) p->cov[j][a][b] = g.cov[j][a][b];
+        }
+    }
+    return ILE_OK;
+}
+
+namespace ile {
+ile_status job_adapt(ile_job *job, int64_t n, const void *theta, int64_t ld, const void *lw, const ile_gmm_opts *o,
+                     hipStream_t st) {
+    ile_ctx *ctx = job->ctx;
+    ile_status s;
+    if ((s = ensure_gmm(job)) != ILE_OK) return s;
+    const size_t need = em_work_bytes(n);
+    if (need > job->em_cap) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return dev_fail(ctx, e, "sync before EM workspace growth");
+        ctx_free(ctx, job->d_em, job->em_cap);
+        job->d_em = nullptr;
+        job->em_cap = 0;
+        if ((s = ctx_alloc(ctx, (void **)&job->d_em, need, "EM workspace")) != ILE_OK) return s;
+        job->em_cap = need;
+    }
+    const int n_comp = (o && o->n_comp > 0) ? o->n_comp : 8;
+    const int n_iter = (o && o->n_iter > 0) ? o->n_iter : 8;
+    const double eps = (o && o->eps_def >= 0 && o->eps_def < 1) ? o->eps_def : 0.05;
+    if (n_comp > kMaxComp) return set_err(ILE_E_INVALID, "n_comp must be 1..16");
+    hipError_t e;
+    if (!job->has_prop) {
+        GmmDev &g = *job->h_gmm;
+        std::memset(&g, 0, sizeof g);
+        default_dims(job, &g.n_dim, g.dims);
+        g.n_comp = n_comp;
+        g.eps_def = eps;
+        e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = hipMemcpyAsync(job->d_gmm, job->h_gmm, sizeof(GmmDev), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = launch_em_top(job->policy, theta, ld, lw, n, job->d_gmm, n_comp, job->d_em, job->em_cap, job->pr, st);
+        if (e != hipSuccess) return dev_fail(ctx, e, "EM first fit");
+    }
+    for (int it = 0; it < n_iter; it++) {
+        e = launch_em_iter(job->policy, theta, ld, lw, n, job->d_gmm, job->d_em, job->em_cap, job->pr, st);
+        if (e != hipSuccess) return dev_fail(ctx, e, "EM iteration");
+    }
+    if ((s = estimate_mass(job, o, st)) != ILE_OK) return s;
+    job->has_prop = true;
+    return ILE_OK;
+}
+}  // namespace ile
+
+extern "C" ile_status ile_adapt_proposal(ile_job *job, int64_t n, const void *theta, int64_t ld, const void *lw,
+                                         const ile_gmm_opts *opts, ile_gmm_params *out, ile_stream stream) {
+    if (!job) return set_err(ILE_E_INVALID, "null job");
+    ile_status s = ctx_check(job->ctx);
+    if (s != ILE_OK) return s;
+    if (n < 1 || ld < n || !theta || !lw) return set_err(ILE_E_INVALID, "need n >= 1, ld >= n and data");
+    if ((s = job_adapt(job, n, theta, ld, lw, opts, (hipStream_t)stream)) != ILE_OK) return s;
+    if (out) return ile_get_proposal(job, out, stream);
+    return ILE_OK;
+}

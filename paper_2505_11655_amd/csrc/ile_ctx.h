@@ -1,0 +1,118 @@
+// Host-side state behind the opaque handles of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "ile.h"
+#include "ile_internal.h"
+
+struct ile_ctx {
+    int device = 0;
+    size_t budget = 0;
+    size_t used = 0;
+    std::atomic<bool> sticky{false};
+    std::mutex mu;                        // budget accounting
+    struct DistEntry {
+        ile::DistTable tab;
+        void *buf;
+    };
+    std::mutex dist_mu;
+    std::map<std::tuple<double, double, double>, DistEntry> dist;
+    // batched-launch descriptors: device scratch + pinned staging
+    std::mutex batch_mu;
+    void *d_batch = nullptr;
+    void *h_batch = nullptr;
+    size_t batch_cap = 0;
+    hipEvent_t batch_ev = nullptr;
+    // batched estimator: tile partials and per-job result copies
+    ile::MargPartial *d_part = nullptr;
+    size_t part_cap = 0;
+    ile::MargState *d_mout = nullptr;
+    ile::MargState *h_mout = nullptr;     // pinned
+    size_t mout_cap = 0;
+};
+
+struct ile_job {
+    ile_ctx *ctx = nullptr;
+    int policy = 0, set = 0, kp = 2, n_det = 1, n_time = 0, n_kept = 0;
+    bool dist_marg = false;
+    ile::PriorDev pr{};
+    void *d_Q = nullptr, *d_Ut = nullptr, *d_Vt = nullptr;
+    size_t q_bytes = 0, uv_bytes = 0, device_bytes = 0;
+    ile::EvalJob ej{};
+    ile::MargState *d_ms = nullptr;
+    ile::MargState *h_ms = nullptr;       // pinned
+    ile::MargPartial *d_part = nullptr;
+    size_t part_cap = 0;
+    ile::GmmDev *d_gmm = nullptr;
+    ile::GmmDev *h_gmm = nullptr;         // pinned
+    uint32_t *d_zcount = nullptr;
+    bool has_prop = false;
+    double *d_em = nullptr;
+    size_t em_cap = 0;
+};
+
+namespace ile {
+
+template <int S, int POL>
+hipError_t launch_eval_sp(int kdet, bool dm, size_t lds_bytes, const EvalJob *jobs, const Tile *tiles,
+                          int n_tiles, const EvalJob &single, int64_t tile, int nthreads, hipStream_t st);
+extern template hipError_t launch_eval_sp<0, 0>(int, bool, size_t, const EvalJob *, const Tile *, int,
+                                                   const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_eval_sp<0, 1>(int, bool, size_t, const EvalJob *, const Tile *, int,
+                                                   const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_eval_sp<0, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
+                                                   const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_eval_sp<1, 0>(int, bool, size_t, const EvalJob *, const Tile *, int,
+                                                   const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_eval_sp<1, 1>(int, bool, size_t, const EvalJob *, const Tile *, int,
+                                                   const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_eval_sp<1, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
+                                                   const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_eval_sp<2, 0>(int, bool, size_t, const EvalJob *, const Tile *, int,
+                                                   const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_eval_sp<2, 1>(int, bool, size_t, const EvalJob *, const Tile *, int,
+                                                   const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_eval_sp<2, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
+                                                   const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_eval_sp<3, 0>(int, bool, size_t, const EvalJob *, const Tile *, int,
+                                                   const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_eval_sp<3, 1>(int, bool, size_t, const EvalJob *, const Tile *, int,
+                                                   const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_eval_sp<3, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
+                                                   const EvalJob &, int64_t, int, hipStream_t);
+
+struct BatchItem {
+    ile_job *job;
+    int64_t n;
+    const void *theta;
+    int64_t ld;
+    const void *lnpmps;
+    void *lnL;
+    void *lw;
+};
+
+ile_status set_err(ile_status st, const std::string &msg);
+ile_status dev_fail(ile_ctx *ctx, hipError_t e, const char *what);
+ile_status ctx_check(ile_ctx *ctx);
+ile_status ctx_alloc(ile_ctx *ctx, void **p, size_t bytes, const char *what);
+void ctx_free(ile_ctx *ctx, void *p, size_t bytes);
+ile_status eval_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, hipStream_t st);
+ile_status batch_upload(ile_ctx *ctx, const void *a, size_t na, const void *b, size_t nb, void **da, void **db,
+                        hipStream_t st);
+ile_status job_marg_launch(ile_job *job, int64_t n, const void *lw, bool reset, hipStream_t st);
+ile_status job_adapt(ile_job *job, int64_t n, const void *theta, int64_t ld, const void *lw, const ile_gmm_opts *o,
+                     hipStream_t st);
+void marg_from_state(const MargState &m, ile_marg *out);
+void eval_geometry(const ile_job *job, int64_t n, size_t *lds, int64_t *tile, int *block);
+size_t theta_size(int policy);
+size_t out_size(int policy);
+
+}  // namespace ile

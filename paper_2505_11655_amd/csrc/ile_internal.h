@@ -1,0 +1,280 @@
+// Internal declarations of the gfx950 ILE library: compile-time mode sets and
+// pair tables, device-side job descriptors, the counter-based generator, and
+// the launch entry points shared between the C ABI and the serving loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ile {
+
+// ------------------------------------------------------------------ policies
+enum Policy : int { kFP64 = 0, kFP32 = 1, kMixed = 2 };
+
+// ----------------------------------------------------------------- mode sets
+// Compiled harmonic sets.  A job's mode list is placed into the smallest set
+// that contains it (absent slots get zero Q, U and V).
+constexpr int kMaxModes = 21;
+constexpr int kNumSets = 4;
+struct ModeList {
+    int n;
+    int l[kMaxModes];
+    int m[kMaxModes];
+};
+constexpr ModeList kSets[kNumSets] = {
+    {5, {2, 2, 2, 2, 2}, {-2, -1, 0, 1, 2}},
+    {9, {2, 2, 2, 2, 2, 3, 3, 3, 3}, {-2, -1, 0, 1, 2, -3, -2, 2, 3}},
+    {17, {2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4},
+     {-2, -1, 0, 1, 2, -3, -2, -1, 1, 2, 3, -4, -3, -2, 2, 3, 4}},
+    {21, {2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4, 4, 4, 4},
+     {-2, -1, 0, 1, 2, -3, -2, -1, 0, 1, 2, 3, -4, -3, -2, -1, 0, 1, 2, 3, 4}},
+};
+
+constexpr int set_lmax(int s) {
+    int L = 0;
+    for (int a = 0; a < kSets[s].n; a++) L = kSets[s].l[a] > L ? kSets[s].l[a] : L;
+    return L;
+}
+constexpr int iabs_c(int x) { return x < 0 ? -x : x; }
+
+// Pairs a <= b of a set, ordered two ways:
+//  U-order: grouped by |m_a - m_b| (0..2 lmax), group g = [u_start[g], u_start[g+1]);
+//  V-order: grouped by m_a + m_b (-2 lmax..2 lmax), group g = s + 2 lmax.
+constexpr int kMaxPairs = kMaxModes * (kMaxModes + 1) / 2;
+struct PairTable {
+    int P;
+    int lmax;
+    int a[kMaxPairs], b[kMaxPairs];
+    int u_pair[kMaxPairs];
+    int u_start[10];
+    int v_pair[kMaxPairs];
+    int v_start[18];
+};
+
+constexpr PairTable make_pairs(int s) {
+    PairTable t{};
+    const ModeList &ml = kSets[s];
+    t.lmax = set_lmax(s);
+    int P = 0;
+    for (int a = 0; a < ml.n; a++)
+        for (int b = a; b < ml.n; b++) {
+            t.a[P] = a;
+            t.b[P] = b;
+            P++;
+        }
+    t.P = P;
+    int ng = 2 * t.lmax + 1;
+    int k = 0;
+    for (int g = 0; g < ng; g++) {
+        t.u_start[g] = k;
+        for (int p = 0; p < P; p++)
+            if (iabs_c(ml.m[t.a[p]] - ml.m[t.b[p]]) == g) t.u_pair[k++] = p;
+    }
+    t.u_start[ng] = k;
+    int nv = 4 * t.lmax + 1;
+    k = 0;
+    for (int g = 0; g < nv; g++) {
+        t.v_start[g] = k;
+        for (int p = 0; p < P; p++)
+            if (ml.m[t.a[p]] + ml.m[t.b[p]] + 2 * t.lmax == g) t.v_pair[k++] = p;
+    }
+    t.v_start[nv] = k;
+    return t;
+}
+
+template <int S>
+struct MSet {
+    static constexpr int id = S;
+    static constexpr int n = kSets[S].n;
+    static constexpr int lmax = set_lmax(S);
+    static constexpr PairTable pt = make_pairs(S);
+    static constexpr int P = pt.P;
+};
+
+// ------------------------------------------------- -2Y_lm(iota,.) amplitudes
+// -2Y_lm(iota, -phi) = y_lm(iota) e^{-i m phi} with
+// y_lm = sqrt((2l+1)/4pi) d^l_{m,2}(iota), and d^l_{m,2} a sum of monomials
+// c^p s^q in c = cos(iota/2), s = sin(iota/2) (Wigner's explicit formula).
+constexpr double cx_fact(int n) {
+    double r = 1.0;
+    for (int i = 2; i <= n; i++) r *= i;
+    return r;
+}
+constexpr double cx_sqrt(double x) {
+    if (x <= 0) return 0.0;
+    double g = x > 1 ? x : 1.0;
+    for (int i = 0; i < 200; i++) g = 0.5 * (g + x / g);
+    return g;
+}
+constexpr double kPiC = 3.14159265358979323846;
+struct WTerm {
+    int nt;
+    double coef[5];
+    int p[5], q[5];
+};
+constexpr WTerm wigner_terms(int l, int m) {
+    WTerm w{};
+    int kmin = (2 - m) > 0 ? 2 - m : 0;
+    int kmax = (l + 2) < (l - m) ? (l + 2) : (l - m);
+    double pref = cx_sqrt(cx_fact(l + m) * cx_fact(l - m) * cx_fact(l + 2) * cx_fact(l - 2)) *
+                  cx_sqrt((2.0 * l + 1.0) / (4.0 * kPiC));
+    for (int k = kmin; k <= kmax; k++) {
+        int e = k - 2 + m;
+        double sg = (e % 2 == 0) ? 1.0 : -1.0;
+        double den = cx_fact(l + 2 - k) * cx_fact(k) * cx_fact(l - k - m) * cx_fact(k - 2 + m);
+        w.coef[w.nt] = sg * pref / den;
+        w.p[w.nt] = 2 * l - 2 * k + 2 - m;
+        w.q[w.nt] = 2 * k - 2 + m;
+        w.nt++;
+    }
+    return w;
+}
+
+// --------------------------------------------------------------- Philox
+// Philox-4x32-10 (Salmon et al., SC'11), device implementation.
+struct U4 {
+    uint32_t x, y, z, w;
+};
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        U4 n{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        c = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+// Uniform in (0,1) with 53 random bits from two words.
+__device__ __forceinline__ double u53(uint32_t w0, uint32_t w1) {
+    return ((double)(w0 >> 5) * 67108864.0 + (double)(w1 >> 6) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+// ------------------------------------------------------------ device jobs
+// Distance-marginal table geometry: nodes u_i = u0 + i du (a = asinh(u)-grid
+// in T1/sqrt(T2)), b_j = b0 + j db (ln T2).
+struct DistTable {
+    const double *r;      // [nb][nu] residual ln L_D - E_max
+    int nu, nb;
+    double u0, du, b0, db;
+    double s_min, s_max;  // d_ref/d_max, d_ref/d_min
+    double a_scale;       // a = a_scale * sinh(u)
+};
+
+struct EvalJob {
+    const void *Q;        // [Kp][T][NM] complex, policy contraction type
+    const void *Ut;       // [P][Kp] complex, U-order, weighted
+    const void *Vt;       // [P][Kp] complex, V-order, weighted
+    DistTable dt;
+    double tau0, inv_dt, gmst, d_ref;
+    double xc[3][3];      // detector position / c (seconds)
+    double D[3][6];       // response tensor (xx, yy, zz, xy, xz, yz)
+    int n_time;
+    int pad_;
+    const void *theta;
+    int64_t ld;
+    const void *lnpmps;
+    void *lnL;
+    void *lw;
+    int64_t n;            // samples of this job in the launch
+};
+
+struct Tile {
+    int32_t job;
+    int32_t pad_;
+    int64_t begin, end;
+};
+
+// Pooled estimator state (device, FP64).
+struct MargState {
+    double m;        // max lw
+    double s1, s2;   // sums of e^{lw-m}, e^{2(lw-m)}
+    int64_t n, n_bad, argmax;
+};
+struct MargPartial {
+    double m, s1, s2;
+    int64_t n_bad, argmax;
+};
+// One job of a batched estimator launch: its tiles are [tile_begin, tile_end).
+struct MargJob {
+    const void *lw;
+    int64_t n;
+    int32_t tile_begin, tile_end;
+    MargState *state;     // pooled state (device)
+    MargState *out;       // copy of the state after this batch (device), or null
+    int32_t reset;
+    int32_t pad_;
+};
+
+constexpr int kMaxComp = 16;
+struct GmmDev {
+    int n_comp, n_dim;
+    int dims[7];
+    int valid;
+    double eps_def;
+    double w[kMaxComp];                   // pi_j
+    double logw[kMaxComp];                // ln pi_j (-inf if pi_j = 0)
+    double mean[kMaxComp][7];
+    double cov[kMaxComp][7][7];
+    double L[kMaxComp][7][7];             // Cholesky factor
+    double Linv[kMaxComp][7][7];          // inverse of L (lower)
+    double logdet_half[kMaxComp];         // sum ln L_dd
+    double lnZ[kMaxComp];
+};
+
+struct PriorDev {
+    double t_window, d_min, d_max, d_ref;
+    int dist_marg;
+};
+
+struct DrawJob {
+    const GmmDev *gmm;    // null: prior draws
+    PriorDev pr;
+    uint64_t seed;
+    uint32_t round;
+    int64_t first;
+    void *theta;
+    int64_t ld;
+    void *lnpmps;
+    int64_t n;
+};
+
+// --------------------------------------------------------- launch wrappers
+// Return hipSuccess or the launch error.  All enqueue on `st`.
+// Either a device array of jobs with a tile list (batched launch), or one job
+// passed by value (d_jobs == nullptr) split into tiles of `tile` samples.
+hipError_t launch_eval(int set, int kdet, int policy, bool dist_marg, size_t lds_bytes,
+                       const EvalJob *d_jobs, const Tile *d_tiles, int n_tiles, const EvalJob &single,
+                       int64_t tile, int block, hipStream_t st);
+size_t eval_lds_limit();
+
+hipError_t launch_marg_partials(int policy, const void *lw, int64_t n, int64_t tile,
+                                MargPartial *d_part, hipStream_t st);
+hipError_t launch_marg_combine(const MargPartial *d_part, int n_part, int64_t n, MargState *d_state,
+                               int reset, hipStream_t st);
+hipError_t launch_marg_batch(int policy, const MargJob *d_jobs, int n_jobs, const Tile *d_tiles, int n_tiles,
+                             MargPartial *d_part, hipStream_t st);
+
+hipError_t launch_draw(int policy, const DrawJob *d_jobs, const Tile *d_tiles, int n_tiles,
+                       const DrawJob &single, int64_t tile, hipStream_t st);
+
+hipError_t launch_gmm_factor(GmmDev *d_gmm, hipStream_t st);
+hipError_t launch_gmm_inbox(GmmDev *d_gmm, PriorDev pr, uint64_t seed, uint32_t round, int64_t m,
+                            uint32_t *d_count, hipStream_t st);
+hipError_t launch_gmm_setz(GmmDev *d_gmm, const uint32_t *d_count, int64_t m, hipStream_t st);
+hipError_t launch_em_top(int policy, const void *theta, int64_t ld, const void *lw, int64_t n,
+                         GmmDev *d_gmm, int n_comp, double *d_work, size_t work_bytes,
+                         PriorDev pr, hipStream_t st);
+hipError_t launch_em_iter(int policy, const void *theta, int64_t ld, const void *lw, int64_t n,
+                          GmmDev *d_gmm, double *d_work, size_t work_bytes, PriorDev pr,
+                          hipStream_t st);
+size_t em_work_bytes(int64_t n);
+
+hipError_t build_dist_table(DistTable *tab, double *d_buf, PriorDev pr, hipStream_t st);
+size_t dist_table_bytes();
+
+}  // namespace ile

@@ -1,0 +1,280 @@
+// Counter-based extrinsic draws for eq. (lnL:MonteCarlo): theta ~ p_s, with
+// p_s the prior or the mixture proposal (1-eps) sum_j pi_j N_j/Z_j + eps p.
+//
+// Counter layout (key = seed words; each block gives four words):
+//   sample i, round r, attempt a, block b:  (i lo, i hi, r, 16 a + b).
+// Prior draw: 7 uniforms from blocks 0..3 of attempt 0 (words 2c, 2c+1),
+// mapped by inverse CDFs.  Mixture draw: the selector is the first uniform of
+// block 0 (attempt 0); the prior fallback and the non-mixture columns use
+// blocks 1..4 of attempt 0; attempt a of a component draws z from four
+// Box-Muller pairs of blocks 1..4 of attempt a and accepts x = mu + L z if
+// every bounded column is inside its interval and every periodic offset lies
+// in (-P/2, P/2]; after 64 rejected attempts the prior draw is kept.
+#include "ile_internal.h"
+
+namespace ile {
+
+namespace {
+
+constexpr int kDrawThreads = 256;
+constexpr int kMaxAttempts = 64;
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ __forceinline__ void words(uint64_t seed, uint64_t i, uint32_t r, uint32_t a, int b0, int nb,
+                                      uint32_t *w) {
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int b = 0; b < nb; b++) {
+        U4 o = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), r, a * 16u + (uint32_t)(b0 + b)}, k0, k1);
+        w[4 * b + 0] = o.x;
+        w[4 * b + 1] = o.y;
+        w[4 * b + 2] = o.z;
+        w[4 * b + 3] = o.w;
+    }
+}
+
+__device__ __forceinline__ void support(const PriorDev &pr, int col, double &lo, double &hi, double &P) {
+    P = 0.0;
+    switch (col) {
+    case 0: lo = 0.0; hi = 2 * kPi; P = 2 * kPi; break;
+    case 1: lo = -0.5 * kPi; hi = 0.5 * kPi; break;
+    case 2: lo = -pr.t_window; hi = pr.t_window; break;
+    case 3: lo = pr.d_min; hi = pr.d_max; break;
+    case 4: lo = -1.0; hi = 1.0; break;
+    case 5: lo = 0.0; hi = 2 * kPi; P = 2 * kPi; break;
+    default: lo = 0.0; hi = kPi; P = kPi; break;
+    }
+}
+
+__device__ double ln_prior(const PriorDev &pr, const double th[7]) {
+    double lp = -log(2 * kPi) + log(0.5 * cos(th[1])) - log(2.0 * pr.t_window) - log(2.0) - log(2 * kPi) -
+                log(kPi);
+    if (!pr.dist_marg) {
+        const double a3 = pr.d_min * pr.d_min * pr.d_min, b3 = pr.d_max * pr.d_max * pr.d_max;
+        lp += log(3.0 * th[3] * th[3] / (b3 - a3));
+    }
+    return lp;
+}
+
+__device__ void prior_from_words(const PriorDev &pr, const uint32_t *w, double th[7]) {
+    double u[7];
+#pragma unroll
+    for (int c = 0; c < 7; c++) u[c] = u53(w[2 * c], w[2 * c + 1]);
+    th[0] = 2 * kPi * u[0];
+    th[1] = asin(2.0 * u[1] - 1.0);
+    th[2] = -pr.t_window + 2.0 * pr.t_window * u[2];
+    if (pr.dist_marg) {
+        th[3] = pr.d_ref;
+    } else {
+        const double a3 = pr.d_min * pr.d_min * pr.d_min, b3 = pr.d_max * pr.d_max * pr.d_max;
+        th[3] = cbrt(a3 + u[3] * (b3 - a3));
+    }
+    th[4] = 2.0 * u[4] - 1.0;
+    th[5] = 2 * kPi * u[5];
+    th[6] = kPi * u[6];
+}
+
+// wrapped difference in (-P/2, P/2]
+__device__ __forceinline__ double wrapd(double d, double P) {
+    if (P <= 0.0) return d;
+    double r = d - P * floor(d / P);
+    return r > 0.5 * P ? r - P : r;
+}
+
+}  // namespace
+
+// ln N_j(wrap(x - mu_j)) through the inverse Cholesky factor.
+__device__ double gmm_comp_logpdf(const GmmDev &g, const PriorDev &pr, int j, const double th[7]) {
+    const int d = g.n_dim;
+    double diff[7];
+    for (int a = 0; a < d; a++) {
+        double lo, hi, P;
+        support(pr, g.dims[a], lo, hi, P);
+        diff[a] = wrapd(th[g.dims[a]] - g.mean[j][a], P);
+    }
+    double q = 0.0;
+    for (int a = 0; a < d; a++) {
+        double y = 0.0;
+        for (int b = 0; b <= a; b++) y += g.Linv[j][a][b] * diff[b];
+        q += y * y;
+    }
+    return -0.5 * q - g.logdet_half[j] - 0.5 * d * log(2 * kPi);
+}
+
+__device__ double gmm_ln_ps(const GmmDev &g, const PriorDev &pr, const double th[7]) {
+    double t[kMaxComp + 1];
+    int nt = 0;
+    const double l1e = log1p(-g.eps_def);
+    for (int j = 0; j < g.n_comp; j++) {
+        if (g.logw[j] == -INFINITY) continue;
+        t[nt++] = l1e + g.logw[j] + gmm_comp_logpdf(g, pr, j, th) - g.lnZ[j];
+    }
+    if (g.eps_def > 0.0) t[nt++] = log(g.eps_def) + ln_prior(pr, th);
+    double m = -INFINITY;
+    for (int k = 0; k < nt; k++) m = fmax(m, t[k]);
+    if (!(m > -INFINITY)) return m;
+    double s = 0.0;
+    for (int k = 0; k < nt; k++) s += exp(t[k] - m);
+    return m + log(s);
+}
+
+// One candidate from component j: words w[0..15] give four Box-Muller pairs.
+__device__ bool gmm_candidate(const GmmDev &g, const PriorDev &pr, int j, const uint32_t *w, double th[7]) {
+    double z[8];
+#pragma unroll
+    for (int p = 0; p < 4; p++) {
+        const double u1 = u53(w[4 * p], w[4 * p + 1]), u2 = u53(w[4 * p + 2], w[4 * p + 3]);
+        const double r = sqrt(-2.0 * log(u1));
+        double s, c;
+        sincos(2 * kPi * u2, &s, &c);
+        z[2 * p] = r * c;
+        z[2 * p + 1] = r * s;
+    }
+    for (int a = 0; a < g.n_dim; a++) {
+        double off = 0.0;
+        for (int b = 0; b <= a; b++) off += g.L[j][a][b] * z[b];
+        double lo, hi, P;
+        support(pr, g.dims[a], lo, hi, P);
+        double x = g.mean[j][a] + off;
+        if (P > 0.0) {
+            if (!(off > -0.5 * P && off <= 0.5 * P)) return false;
+            x = x - P * floor((x - lo) / P);
+        } else if (!(x >= lo && x <= hi)) {
+            return false;
+        }
+        th[g.dims[a]] = x;
+    }
+    return true;
+}
+
+namespace {
+
+template <class TT>
+__device__ void draw_range(const DrawJob &J, int64_t begin, int64_t end) {
+    TT *__restrict__ th_out = (TT *)J.theta;
+    TT *__restrict__ lr_out = (TT *)J.lnpmps;
+    for (int64_t s = begin + threadIdx.x; s < end; s += kDrawThreads) {
+        const uint64_t idx = (uint64_t)(J.first + s);
+        uint32_t w[20];
+        double th[7];
+        double lr = 0.0;
+        if (J.gmm == nullptr) {
+            words(J.seed, idx, J.round, 0, 0, 4, w);
+            prior_from_words(J.pr, w, th);
+        } else {
+            const GmmDev &g = *J.gmm;
+            words(J.seed, idx, J.round, 0, 0, 5, w);
+            prior_from_words(J.pr, w + 4, th);
+            const double usel = u53(w[0], w[1]);
+            if (usel >= g.eps_def) {
+                const double v = (usel - g.eps_def) / (1.0 - g.eps_def);
+                double tot = 0.0;
+                for (int j = 0; j < g.n_comp; j++) tot += g.w[j];
+                int jsel = -1;
+                double acc = 0.0;
+                for (int j = 0; j < g.n_comp; j++) {
+                    if (!(g.w[j] > 0.0)) continue;
+                    acc += g.w[j] / tot;
+                    jsel = j;
+                    if (v < acc) break;
+                }
+                for (int a = 0; a < kMaxAttempts && jsel >= 0; a++) {
+                    uint32_t wa[16];
+                    words(J.seed, idx, J.round, (uint32_t)a, 1, 4, wa);
+                    double cand[7];
+#pragma unroll
+                    for (int c = 0; c < 7; c++) cand[c] = th[c];
+                    if (gmm_candidate(g, J.pr, jsel, wa, cand)) {
+#pragma unroll
+                        for (int c = 0; c < 7; c++) th[c] = cand[c];
+                        break;
+                    }
+                }
+            }
+            lr = ln_prior(J.pr, th) - gmm_ln_ps(g, J.pr, th);
+        }
+#pragma unroll
+        for (int c = 0; c < 7; c++) th_out[c * J.ld + s] = (TT)th[c];
+        if (lr_out) lr_out[s] = (TT)lr;
+    }
+}
+
+template <class TT>
+__global__ void __launch_bounds__(kDrawThreads)
+    k_draw(const DrawJob *__restrict__ jobs, const Tile *__restrict__ tiles, const DrawJob single, int64_t tile) {
+    if (jobs != nullptr) {
+        const Tile tl = tiles[blockIdx.x];
+        draw_range<TT>(jobs[tl.job], tl.begin, tl.end);
+    } else {
+        const int64_t b = (int64_t)blockIdx.x * tile;
+        draw_range<TT>(single, b, b + tile < single.n ? b + tile : single.n);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_draw(int policy, const DrawJob *d_jobs, const Tile *d_tiles, int n_tiles, const DrawJob &single,
+                       int64_t tile, hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    if (policy == kFP64)
+        hipLaunchKernelGGL(k_draw<double>, dim3(n_tiles), dim3(kDrawThreads), 0, st, d_jobs, d_tiles, single, tile);
+    else
+        hipLaunchKernelGGL(k_draw<float>, dim3(n_tiles), dim3(kDrawThreads), 0, st, d_jobs, d_tiles, single, tile);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ in-support mass
+namespace {
+
+constexpr int kZThreads = 256;
+
+__global__ void __launch_bounds__(kZThreads)
+    k_gmm_inbox(const GmmDev *__restrict__ gp, PriorDev pr, uint64_t seed, uint32_t round, int64_t m,
+                uint32_t *__restrict__ count) {
+    const GmmDev &g = *gp;
+    const int j = blockIdx.y;
+    __shared__ uint32_t sacc[kZThreads];
+    uint32_t acc = 0;
+    if (j < g.n_comp) {
+        const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+        for (int64_t i = (int64_t)blockIdx.x * kZThreads + threadIdx.x; i < m; i += (int64_t)gridDim.x * kZThreads) {
+            uint32_t w[16];
+            for (int b = 0; b < 4; b++) {
+                U4 o = philox4x32_10(U4{(uint32_t)i, 0x5A000000u + (uint32_t)j, round, (uint32_t)b}, k0, k1);
+                w[4 * b] = o.x; w[4 * b + 1] = o.y; w[4 * b + 2] = o.z; w[4 * b + 3] = o.w;
+            }
+            double th[7] = {0, 0, 0, pr.d_ref, 0, 0, 0};
+            acc += gmm_candidate(g, pr, j, w, th) ? 1u : 0u;
+        }
+    }
+    sacc[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kZThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sacc[threadIdx.x] += sacc[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && j < g.n_comp) atomicAdd(&count[j], sacc[0]);
+}
+
+__global__ void k_gmm_setz(GmmDev *g, const uint32_t *count, int64_t m) {
+    const int j = threadIdx.x;
+    if (j < g->n_comp) {
+        const double c = (double)count[j];
+        g->lnZ[j] = log((c > 0 ? c : 0.5) / (double)m);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_gmm_inbox(GmmDev *d_gmm, PriorDev pr, uint64_t seed, uint32_t round, int64_t m,
+                            uint32_t *d_count, hipStream_t st) {
+    hipLaunchKernelGGL(k_gmm_inbox, dim3(64, kMaxComp), dim3(kZThreads), 0, st, d_gmm, pr, seed, round, m,
+                       d_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_gmm_setz(GmmDev *d_gmm, const uint32_t *d_count, int64_t m, hipStream_t st) {
+    hipLaunchKernelGGL(k_gmm_setz, dim3(1), dim3(64), 0, st, d_gmm, d_count, m);
+    return hipGetLastError();
+}
+
+}  // namespace ile

@@ -1,0 +1,396 @@
+// Fused per-sample log-likelihood kernel, eq. (def:lnL:Decomposed):
+//   lnL = s Re sum_k sum_lm (F_k Y_lm)^* Q_k,lm(tau_k)
+//         - s^2/4 sum_k [ |F_k|^2 Y^+ U_k Y + Re(F_k^2 Y^T V_k Y) ],  s = D_ref/D.
+// One thread evaluates one sample at a time; a block owns one tile of one job.
+//
+// Work per sample (all of it in registers):
+//   sky: n = (cos d cos h, cos d sin h, sin d), h = alpha - gmst, and the basis
+//        e_a = (-sin h, cos h, 0), e_d = (-sin d cos h, -sin d sin h, cos d);
+//   F_k = e^{-2i psi} [(e_a.D.e_a - e_d.D.e_d) - 2i e_a.D.e_d]  (equal to F+ + iFx
+//        for X = -cos psi e_a + sin psi e_d, Y = sin psi e_a + cos psi e_d);
+//   tau_k = t - x_k.n / c;
+//   Y_lm = y_lm(iota) e^{-i m phi} with real y_lm from Wigner's formula in
+//        cos(iota/2), sin(iota/2), and e^{i j phi} by repeated products;
+//   T1 from the 4-tap Lagrange cubic of Q at tau_k (window in LDS or L2);
+//   T2 from the pair sums grouped by m_a - m_b (U, Hermitian) and m_a + m_b
+//        (V, symmetric): each pair costs one product y_a y_b and two FMAs per
+//        detector; the phase e^{i(m_a - m_b) phi} is applied once per group.
+#pragma once
+
+#include <type_traits>
+
+#include "ile_internal.h"
+
+namespace ile {
+
+template <class T>
+struct cpx {
+    T re, im;
+};
+
+template <int POL>
+struct PolTypes;
+// Which arithmetic each part uses.  In the mixed policy only quantities that
+// act as a point perturbation of the complex amplitudes z_k = s F_k Y (F_k,
+// y_lm) stay FP32: lnL is stationary in z near its maximum, so their rounding
+// enters at second order.  Everything that defines the quadratic form itself
+// (delays and interpolation weights, the phase table e^{i j phi}, Q/U/V and
+// the sums) is FP64, because its rounding enters at first order, ~eps rho^2.
+template <>
+struct PolTypes<kFP64> {
+    using TT = double;  // theta, ln p - ln p_s
+    using TS = double;  // sky direction and delays
+    using TG = double;  // polarisation response and harmonic amplitudes
+    using TE = double;  // phase table e^{i j phi}
+    using TA = double;  // Q/U/V contractions and the combine
+    using TO = double;  // lnL, lw
+};
+template <>
+struct PolTypes<kFP32> {
+    using TT = float;
+    using TS = float;
+    using TG = float;
+    using TE = float;
+    using TA = float;
+    using TO = float;
+};
+template <>
+struct PolTypes<kMixed> {
+    using TT = float;
+    using TS = double;
+    using TG = float;
+    using TE = double;
+    using TA = double;
+    using TO = double;
+};
+
+__device__ __forceinline__ void dsincos(float x, float *s, float *c) { sincosf(x, s, c); }
+__device__ __forceinline__ void dsincos(double x, double *s, double *c) { sincos(x, s, c); }
+__device__ __forceinline__ float dfloor(float x) { return floorf(x); }
+__device__ __forceinline__ double dfloor(double x) { return floor(x); }
+__device__ __forceinline__ float dsqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Distance-marginalised lnL from the residual table (bicubic Lagrange),
+// ln L_D = r(a, b) + E_max, a = T1/sqrt(T2), b = ln T2, E_max the exponent
+// at the clamped best scale.  Out of table: -inf.
+__device__ __forceinline__ double dist_lookup(const DistTable &tb, double T1, double T2) {
+    if (!(T2 > 0.0)) return -INFINITY;
+    double b = log(T2);
+    double a = T1 / sqrt(T2);
+    double u = asinh(a / tb.a_scale);
+    double xu = (u - tb.u0) / tb.du;
+    double xb = (b - tb.b0) / tb.db;
+    double fu = floor(xu), fb = floor(xb);
+    if (!(fu >= 1.0 && fu <= (double)(tb.nu - 3) && fb >= 1.0 && fb <= (double)(tb.nb - 3)))
+        return -INFINITY;
+    int iu = (int)fu, ib = (int)fb;
+    double gu = xu - fu, gb = xb - fb;
+    double wu[4] = {-gu * (gu - 1.0) * (gu - 2.0) / 6.0, (gu + 1.0) * (gu - 1.0) * (gu - 2.0) * 0.5,
+                    -(gu + 1.0) * gu * (gu - 2.0) * 0.5, (gu + 1.0) * gu * (gu - 1.0) / 6.0};
+    double wb[4] = {-gb * (gb - 1.0) * (gb - 2.0) / 6.0, (gb + 1.0) * (gb - 1.0) * (gb - 2.0) * 0.5,
+                    -(gb + 1.0) * gb * (gb - 2.0) * 0.5, (gb + 1.0) * gb * (gb - 1.0) / 6.0};
+    double r = 0.0;
+#pragma unroll
+    for (int jb = 0; jb < 4; jb++) {
+        const double *row = tb.r + (size_t)(ib - 1 + jb) * tb.nu + (iu - 1);
+        double acc = wu[0] * row[0] + wu[1] * row[1] + wu[2] * row[2] + wu[3] * row[3];
+        r += wb[jb] * acc;
+    }
+    double sc = fmin(fmax(2.0 * T1 / T2, tb.s_min), tb.s_max);
+    return r + sc * T1 - sc * sc * T2 * 0.25;
+}
+
+template <int S, int K, int POL, bool LDS, bool DM>
+struct LnlKernel {
+    using MS = MSet<S>;
+    using Tp = PolTypes<POL>;
+    using TT = typename Tp::TT;
+    using TS = typename Tp::TS;
+    using TG = typename Tp::TG;
+    using TE = typename Tp::TE;
+    using TA = typename Tp::TA;
+    using TO = typename Tp::TO;
+    static constexpr int NM = MS::n;
+    static constexpr int LM = MS::lmax;
+    static constexpr int NE = 2 * LM + 1;  // e^{i j phi}, j = 0..2 lmax
+
+    __device__ static void run(const EvalJob &J, const int64_t begin, const int64_t end, cpx<TA> *smem) {
+        const int T = J.n_time;
+        const cpx<TA> *__restrict__ Qg = (const cpx<TA> *)J.Q;
+        if constexpr (LDS) {
+            // stage the whole window of this job: K * T * NM complex values
+            const size_t nwords = (size_t)K * T * NM * sizeof(cpx<TA>) / 8;
+            const uint2 *src = (const uint2 *)J.Q;
+            uint2 *dst = (uint2 *)smem;
+            for (size_t w = threadIdx.x; w < nwords; w += blockDim.x) dst[w] = src[w];
+            __syncthreads();
+        }
+        const cpx<TA> *__restrict__ Qb = LDS ? smem : Qg;
+        const cpx<TA> *__restrict__ Ut = (const cpx<TA> *)J.Ut;
+        const cpx<TA> *__restrict__ Vt = (const cpx<TA> *)J.Vt;
+        const TT *__restrict__ th = (const TT *)J.theta;
+        const TT *__restrict__ lr = (const TT *)J.lnpmps;
+        TO *__restrict__ outL = (TO *)J.lnL;
+        TO *__restrict__ outW = (TO *)J.lw;
+        const int64_t ld = J.ld;
+
+        for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+            const TT al = th[i], de = th[ld + i], tt = th[2 * ld + i], DD = th[3 * ld + i];
+            const TT ci = th[4 * ld + i], ph = th[5 * ld + i], ps = th[6 * ld + i];
+            bool ok = (DM || DD > (TT)0) && (ci >= (TT)-1 && ci <= (TT)1);
+
+            // ---- sky direction, polarisation basis, delays
+            TS sd, cd, sh, ch;
+            dsincos((TS)de, &sd, &cd);
+            dsincos((TS)al - (TS)J.gmst, &sh, &ch);
+            const TS n0 = cd * ch, n1 = cd * sh, n2 = sd;
+            const TG ea0 = (TG)(-sh), ea1 = (TG)ch;
+            const TG ed0 = (TG)(-sd * ch), ed1 = (TG)(-sd * sh), ed2 = (TG)cd;
+            TG s2p, c2p;
+            dsincos((TG)2 * (TG)ps, &s2p, &c2p);
+            TG Fr[K], Fi[K];
+            TA tau[K];
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const TG dxx = (TG)J.D[k][0], dyy = (TG)J.D[k][1], dzz = (TG)J.D[k][2];
+                const TG dxy = (TG)J.D[k][3], dxz = (TG)J.D[k][4], dyz = (TG)J.D[k][5];
+                const TG A = dxx * ea0 * ea0 + dyy * ea1 * ea1 + (TG)2 * dxy * ea0 * ea1;
+                const TG B = dxx * ed0 * ed0 + dyy * ed1 * ed1 + dzz * ed2 * ed2 +
+                             (TG)2 * (dxy * ed0 * ed1 + dxz * ed0 * ed2 + dyz * ed1 * ed2);
+                const TG C = dxx * ea0 * ed0 + dyy * ea1 * ed1 + dxy * (ea0 * ed1 + ea1 * ed0) +
+                             dxz * ea0 * ed2 + dyz * ea1 * ed2;
+                const TG Gr = A - B, Gi = (TG)-2 * C;
+                Fr[k] = c2p * Gr + s2p * Gi;
+                Fi[k] = c2p * Gi - s2p * Gr;
+                const TS dly = (TS)J.xc[k][0] * n0 + (TS)J.xc[k][1] * n1 + (TS)J.xc[k][2] * n2;
+                tau[k] = (TA)((TS)tt - dly);
+            }
+
+            // ---- harmonics y_lm(iota) and phases e^{i j phi}
+            const TG c = (TG)ci;
+            const TG chalf = dsqrt(fmax((TG)0.5 * ((TG)1 + c), (TG)0));
+            const TG shalf = dsqrt(fmax((TG)0.5 * ((TG)1 - c), (TG)0));
+            TG cp[2 * LM + 1], sp[2 * LM + 1];
+            cp[0] = (TG)1;
+            sp[0] = (TG)1;
+#pragma unroll
+            for (int j = 1; j <= 2 * LM; j++) {
+                cp[j] = cp[j - 1] * chalf;
+                sp[j] = sp[j - 1] * shalf;
+            }
+            TG y[NM];
+            static_for<0, NM>([&](auto A_) {
+                constexpr int a = decltype(A_)::value;
+                constexpr WTerm w = wigner_terms(kSets[S].l[a], kSets[S].m[a]);
+                TG acc = (TG)0;
+                static_for<0, w.nt>([&](auto T_) {
+                    constexpr int t = decltype(T_)::value;
+                    acc += (TG)w.coef[t] * cp[w.p[t]] * sp[w.q[t]];
+                });
+                y[a] = acc;
+            });
+            TE sph, cph;
+            dsincos((TE)ph, &sph, &cph);
+            TE Er[NE], Ei[NE];
+            Er[0] = (TE)1;
+            Ei[0] = (TE)0;
+#pragma unroll
+            for (int j = 1; j < NE; j++) {
+                Er[j] = Er[j - 1] * cph - Ei[j - 1] * sph;
+                Ei[j] = Er[j - 1] * sph + Ei[j - 1] * cph;
+            }
+
+            // ---- T1 = sum_k Re[conj(F_k) sum_a y_a e^{i m_a phi} Qhat_k,a]
+            TA T1 = (TA)0;
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const TA u = (tau[k] - (TA)J.tau0) * (TA)J.inv_dt;
+                const TA fl = dfloor(u);
+                ok = ok && (fl >= (TA)1) && (fl <= (TA)(T - 3));
+                const TA flc = fmin(fmax(fl, (TA)1), (TA)(T - 3));
+                const int i0 = (int)flc;
+                const TA f = u - fl;
+                const TA fm1 = f - (TA)1, fm2 = f - (TA)2, fp1 = f + (TA)1;
+                const TA w0 = -f * fm1 * fm2 * (TA)(1.0 / 6.0);
+                const TA w1 = fp1 * fm1 * fm2 * (TA)0.5;
+                const TA w2 = -fp1 * f * fm2 * (TA)0.5;
+                const TA w3 = fp1 * f * fm1 * (TA)(1.0 / 6.0);
+                const cpx<TA> *q = Qb + ((size_t)k * T + (i0 - 1)) * NM;
+                TA ar = (TA)0, ai = (TA)0;
+                static_for<0, NM>([&](auto A_) {
+                    constexpr int a = decltype(A_)::value;
+                    constexpr int m = kSets[S].m[a];
+                    const cpx<TA> q0 = q[a], q1 = q[NM + a], q2 = q[2 * NM + a], q3 = q[3 * NM + a];
+                    const TA qr = w0 * q0.re + w1 * q1.re + w2 * q2.re + w3 * q3.re;
+                    const TA qi = w0 * q0.im + w1 * q1.im + w2 * q2.im + w3 * q3.im;
+                    const TA er = (TA)Er[m < 0 ? -m : m];
+                    const TA ei = (m < 0) ? -(TA)Ei[-m] : (TA)Ei[m];
+                    const TA zr = (TA)y[a] * er, zi = (TA)y[a] * ei;
+                    ar += zr * qr - zi * qi;
+                    ai += zr * qi + zi * qr;
+                });
+                T1 += (TA)Fr[k] * ar + (TA)Fi[k] * ai;
+            }
+
+            // ---- T2 = sum_k |F_k|^2 Y^+ U_k Y + Re(F_k^2 Y^T V_k Y)
+            TA uk[K], vr[K], vi[K];
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                uk[k] = (TA)0;
+                vr[k] = (TA)0;
+                vi[k] = (TA)0;
+            }
+            constexpr PairTable pt = MS::pt;
+            static_for<0, NE>([&](auto G_) {
+                constexpr int g = decltype(G_)::value;
+                TA Ar[K], Ai[K];
+#pragma unroll
+                for (int k = 0; k < K; k++) {
+                    Ar[k] = (TA)0;
+                    Ai[k] = (TA)0;
+                }
+                static_for<pt.u_start[g], pt.u_start[g + 1]>([&](auto J_) {
+                    constexpr int j = decltype(J_)::value;
+                    constexpr int p = pt.u_pair[j];
+                    const TA py = (TA)y[pt.a[p]] * (TA)y[pt.b[p]];
+#pragma unroll
+                    for (int k = 0; k < K; k++) {
+                        const cpx<TA> cu = Ut[j * K + k];
+                        Ar[k] += py * cu.re;
+                        if constexpr (g > 0) Ai[k] += py * cu.im;
+                    }
+                });
+#pragma unroll
+                for (int k = 0; k < K; k++) {
+                    if constexpr (g == 0)
+                        uk[k] += Ar[k];
+                    else
+                        uk[k] += (TA)Er[g] * Ar[k] - (TA)Ei[g] * Ai[k];
+                }
+            });
+            static_for<0, 4 * LM + 1>([&](auto G_) {
+                constexpr int g = decltype(G_)::value;
+                constexpr int sm = g - 2 * LM;
+                if constexpr (pt.v_start[g + 1] > pt.v_start[g]) {
+                    TA Br[K], Bi[K];
+#pragma unroll
+                    for (int k = 0; k < K; k++) {
+                        Br[k] = (TA)0;
+                        Bi[k] = (TA)0;
+                    }
+                    static_for<pt.v_start[g], pt.v_start[g + 1]>([&](auto J_) {
+                        constexpr int j = decltype(J_)::value;
+                        constexpr int p = pt.v_pair[j];
+                        const TA py = (TA)y[pt.a[p]] * (TA)y[pt.b[p]];
+#pragma unroll
+                        for (int k = 0; k < K; k++) {
+                            const cpx<TA> cv = Vt[j * K + k];
+                            Br[k] += py * cv.re;
+                            Bi[k] += py * cv.im;
+                        }
+                    });
+                    // e^{-i sm phi}
+                    const TA er = (TA)Er[sm < 0 ? -sm : sm];
+                    const TA ei = (sm < 0) ? (TA)Ei[-sm] : -(TA)Ei[sm];
+#pragma unroll
+                    for (int k = 0; k < K; k++) {
+                        vr[k] += er * Br[k] - ei * Bi[k];
+                        vi[k] += er * Bi[k] + ei * Br[k];
+                    }
+                }
+            });
+            TA T2 = (TA)0;
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const TA fr = (TA)Fr[k], fi = (TA)Fi[k];
+                T2 += (fr * fr + fi * fi) * uk[k] + (fr * fr - fi * fi) * vr[k] - (TA)2 * fr * fi * vi[k];
+            }
+
+            // ---- combine
+            TA lnL;
+            if constexpr (DM) {
+                lnL = (TA)dist_lookup(J.dt, (double)T1, (double)T2);
+            } else {
+                const TA s = (TA)J.d_ref / (TA)DD;
+                lnL = s * T1 - s * s * T2 * (TA)0.25;
+            }
+            TO outv = ok ? (TO)lnL : (TO)-INFINITY;
+            if (outL) outL[i] = outv;
+            if (outW) outW[i] = outv + (lr ? (TO)lr[i] : (TO)0);
+        }
+    }
+};
+
+template <int S, int K, int POL, bool LDS, bool DM>
+__global__ void __launch_bounds__(LDS ? 512 : 256)
+    k_lnl(const EvalJob *__restrict__ jobs, const Tile *__restrict__ tiles, const EvalJob single,
+          const int64_t tile) {
+    extern __shared__ __align__(16) char ile_smem[];
+    using TA = typename PolTypes<POL>::TA;
+    if (jobs != nullptr) {
+        const Tile tl = tiles[blockIdx.x];
+        LnlKernel<S, K, POL, LDS, DM>::run(jobs[tl.job], tl.begin, tl.end, (cpx<TA> *)ile_smem);
+    } else {
+        const int64_t b = (int64_t)blockIdx.x * tile;
+        const int64_t e = b + tile < single.n ? b + tile : single.n;
+        LnlKernel<S, K, POL, LDS, DM>::run(single, b, e, (cpx<TA> *)ile_smem);
+    }
+}
+
+// LDS staging is compiled only where a 410-sample window of the set fits in
+// 160 KiB; elsewhere the window is read through the L1/L2 caches.
+template <int S, int K, int POL>
+constexpr bool lds_instanced() {
+    return (size_t)K * 410 * MSet<S>::n * 2 * sizeof(typename PolTypes<POL>::TA) <= 163840;
+}
+
+template <int S, int POL>
+hipError_t launch_eval_sp(int kdet, bool dm, size_t lds_bytes, const EvalJob *jobs, const Tile *tiles, int n_tiles,
+                          const EvalJob &single, int64_t tile, int nthreads, hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    const bool lds = lds_bytes > 0;
+    if (nthreads <= 0 || nthreads > (lds ? 512 : 256) || nthreads % 64) return hipErrorInvalidValue;
+    if (dm && POL == kMixed) return hipErrorInvalidValue;
+    dim3 grid(n_tiles), block(nthreads);
+    auto go = [&](auto KK, auto LL, auto DD) -> hipError_t {
+        constexpr int K = decltype(KK)::value;
+        constexpr bool L = decltype(LL)::value;
+        constexpr bool D = decltype(DD)::value;
+        if constexpr ((L && !lds_instanced<S, K, POL>()) || (D && POL == kMixed)) {
+            return hipErrorInvalidValue;
+        } else {
+            auto fn = k_lnl<S, K, POL, L, D>;
+            if (L) {
+                hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)lds_bytes);
+                if (e != hipSuccess) return e;
+            }
+            hipLaunchKernelGGL(fn, grid, block, L ? lds_bytes : 0, st, jobs, tiles, single, tile);
+            return hipGetLastError();
+        }
+    };
+    using T2 = std::integral_constant<int, 2>;
+    using T3 = std::integral_constant<int, 3>;
+    using BT = std::true_type;
+    using BF = std::false_type;
+    if (kdet == 2) {
+        if (lds) return dm ? go(T2{}, BT{}, BT{}) : go(T2{}, BT{}, BF{});
+        return dm ? go(T2{}, BF{}, BT{}) : go(T2{}, BF{}, BF{});
+    }
+    if (kdet == 3) {
+        if (lds) return dm ? go(T3{}, BT{}, BT{}) : go(T3{}, BT{}, BF{});
+        return dm ? go(T3{}, BF{}, BT{}) : go(T3{}, BF{}, BF{});
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ile

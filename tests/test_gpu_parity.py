@@ -1,0 +1,287 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on identical
+seeded inputs: per-sample lnL for every precision policy and compiled mode set,
+the Monte Carlo estimator, and the counter-based prior draws."""
+import math
+
+import numpy as np
+import pytest
+
+import chirpgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2505_11655_amd as ile  # noqa: E402
+from tests import gpu_util as gu  # noqa: E402
+
+POLICIES = [ile.ILE_FP64, ile.ILE_FP32, ile.ILE_FP32_CANCEL64]
+PNAME = {0: "fp64", 1: "fp32", 2: "fp32c64"}
+
+
+@pytest.fixture(scope="module")
+def recs():
+    return chirpgen.load_injections()
+
+
+def _np_theta(th, policy):
+    return np.ascontiguousarray(th.astype(np.float64 if policy == ile.ILE_FP64 else np.float32))
+
+
+def _run(orc, prob, th, policy, lnpmps=None, eps=0.0):
+    ph = ile.ProblemHost(prob, precision=policy, mode_filter_eps=eps)
+    job = ile.ile_prepare(gu.ctx(), ph)
+    try:
+        L, W = gu.gpu_eval(job, th, policy, lnpmps)
+    finally:
+        ile.ile_job_release(job)
+    ref, T1, T2 = orc.lnL(prob, th.astype(np.float64), return_terms=True)
+    s = 100.0 / th[3].astype(np.float64)
+    return L, W, ref, T1, T2, s
+
+
+@pytest.mark.parametrize("policy", POLICIES, ids=[PNAME[p] for p in POLICIES])
+@pytest.mark.parametrize("cfg", ["hl5", "hlv9", "hlv17"])
+def test_eval_prior_samples(orc, recs, policy, cfg):
+    """Prior-drawn samples (ragged count) on physical inputs, the three
+    workload shapes: H,L with 5 modes; H,L,V with 9; H,L,V with 17 (q = 20)."""
+    dets, n_modes, rec, mc, q, snr = {
+        "hl5": (["H", "L"], 5, "c1", 30.0, 2.0, 20.0),
+        "hlv9": (["H", "L", "V"], 9, "c2", 30.0, 2.0, 20.0),
+        "hlv17": (["H", "L", "V"], 17, "c3", 30.0, 20.0, 20.0),
+    }[cfg]
+    probs, _ = chirpgen.build_event(recs[rec], dets, n_modes, mc, q, snr, noise_seed=11,
+                                    templates=[(mc * 1.01, q)])
+    rng = np.random.default_rng(21)
+    th = _np_theta(chirpgen.prior_samples(rng, 40961), policy)
+    L, W, ref, T1, T2, s = _run(orc, probs[0], th, policy)
+    ok, ms, ma = gu.tol_check(L, ref, T1, T2, s, policy)
+    print(f"{cfg} {PNAME[policy]} max|d| scoped={ms:.3e} all={ma:.3e}")
+    assert ok
+    assert np.array_equal(np.isfinite(W), np.isfinite(L))
+
+
+@pytest.mark.parametrize("snr", [100.0, 400.0])
+def test_eval_precision_strong_source(orc, recs, snr):
+    """Loud edge-on q = 20 source, 17 modes, samples near the peak: the
+    FP32 + FP64-cancellation policy meets 1e-3 per sample (scoped); plain FP32
+    is reported for contrast."""
+    probs, _ = chirpgen.build_event(recs["c3"], ["H", "L", "V"], 17, 30.0, 20.0, snr, noise_seed=5)
+    th0 = np.array(recs["c3"]["theta"])
+    sc = 100.0 / snr
+    widths = np.array([0.01, 0.01, 1e-4, 0.05 * th0[3], 0.02, 0.05, 0.05]) * sc * 3
+    rng = np.random.default_rng(22)
+    thd = chirpgen.box_samples(rng, 30000, th0, widths)
+    res = {}
+    for policy in (ile.ILE_FP32_CANCEL64, ile.ILE_FP32):
+        th = _np_theta(thd, policy)
+        L, W, ref, T1, T2, s = _run(orc, probs[0], th, policy)
+        ok, ms, ma = gu.tol_check(L, ref, T1, T2, s, policy)
+        res[policy] = (ok, ms, ma, float(np.max(ref)))
+        print(f"SNR {snr} {PNAME[policy]} max lnL={np.max(ref):.1f} max|d| scoped={ms:.3e} all={ma:.3e}")
+    assert res[ile.ILE_FP32_CANCEL64][0]
+
+
+@pytest.mark.parametrize("policy", POLICIES, ids=[PNAME[p] for p in POLICIES])
+@pytest.mark.parametrize("case", ["all21_k3", "k1_pad", "subset_scrambled", "k2_set17", "set9_k2"])
+def test_eval_random_inputs(orc, policy, case):
+    """Random Hermitian/symmetric inputs over every compiled mode set, one
+    detector (padded), and a scrambled mode subset placed in a larger set."""
+    rng = np.random.default_rng(hash(case) % 2 ** 32)
+    if case == "all21_k3":
+        p = chirpgen.random_problem(rng, 21, ["H", "L", "V"])
+    elif case == "k1_pad":
+        p = chirpgen.random_problem(rng, 9, ["V"])
+    elif case == "k2_set17":
+        p = chirpgen.random_problem(rng, 17, ["L", "V"])
+    elif case == "set9_k2":
+        p = chirpgen.random_problem(rng, 9, ["H", "V"])
+    else:
+        p = chirpgen.random_problem(rng, 21, ["H", "L"])
+        keep = [14, 4, 0, 20, 9]           # (4,-2),(2,2),(2,-2),(4,4),(3,1) in scrambled order
+        p.modes = [p.modes[a] for a in keep]
+        p.Q, p.U, p.V = p.Q[:, keep], p.U[:, keep][:, :, keep], p.V[:, keep][:, :, keep]
+    th = _np_theta(chirpgen.prior_samples(rng, 9999), policy)
+    L, W, ref, T1, T2, s = _run(orc, p, th, policy)
+    ok, ms, ma = gu.tol_check(L, ref, T1, T2, s, policy)
+    print(f"{case} {PNAME[policy]} max|d| scoped={ms:.3e} all={ma:.3e}")
+    assert ok
+
+
+@pytest.mark.parametrize("policy", POLICIES, ids=[PNAME[p] for p in POLICIES])
+def test_eval_edge_cases(orc, policy):
+    """Outside the support gives -inf exactly where the oracle does; n = 1,
+    n = 0 and lw = lnL + (ln p - ln p_s)."""
+    rng = np.random.default_rng(23)
+    p = chirpgen.random_problem(rng, 5, ["H", "L"])
+    th = chirpgen.prior_samples(rng, 600)
+    th[3, 0:50] = -5.0                  # D <= 0
+    th[3, 50:60] = 0.0
+    th[4, 60:110] = 1.5                 # |cos iota| > 1
+    th[2, 110:160] = 0.2                # far outside the window
+    th[2, 160:170] = np.nan
+    th = _np_theta(th, policy)
+    lr = rng.normal(size=600).astype(th.dtype)
+    L, W, ref, T1, T2, s = _run(orc, p, th, policy, lnpmps=lr)
+    assert np.all(np.isneginf(L[:160]))
+    assert np.all(np.isneginf(ref[:160]))
+    ok, _, _ = gu.tol_check(L, ref, T1, T2, s, policy)
+    assert ok
+    fin = np.isfinite(L)
+    tolw = 1e-12 if policy == ile.ILE_FP64 else 1e-5
+    assert np.allclose(W[fin], L[fin] + lr[fin].astype(np.float64), rtol=tolw, atol=tolw)
+    # single sample and empty launch
+    ph = ile.ProblemHost(p, precision=policy)
+    job = ile.ile_prepare(gu.ctx(), ph)
+    try:
+        L1, _ = gu.gpu_eval(job, np.ascontiguousarray(th[:, 200:201]), policy)
+        ref1 = orc.lnL(p, th[:, 200:201].astype(np.float64))
+        assert abs(L1[0] - ref1[0]) <= (1e-9 if policy == 0 else 1e-3) * (1 + abs(ref1[0]))
+        L0, _ = gu.gpu_eval(job, np.zeros((7, 0), dtype=th.dtype), policy)
+        assert L0.size == 0
+    finally:
+        ile.ile_job_release(job)
+
+
+def test_mode_filter(orc, recs):
+    """eps > 0 keeps (l,m) iff some |U_0[lm][l'm'] / U_0[22][22]| > eps; the
+    result equals the oracle on the kept modes."""
+    probs, _ = chirpgen.build_event(recs["c2"], ["H", "L", "V"], 17, 30.0, 1.2, 20.0, noise_seed=3)
+    p = probs[0]
+    U0 = p.U[0]
+    a22 = p.modes.index((2, 2))
+    eps = 0.02
+    keep = [a for a in range(len(p.modes)) if np.max(np.abs(U0[a]) / abs(U0[a22, a22])) > eps]
+    assert 0 < len(keep) < len(p.modes)
+    pk = chirpgen.Problem(**{**p.__dict__})
+    pk.modes = [p.modes[a] for a in keep]
+    pk.Q, pk.U, pk.V = p.Q[:, keep], p.U[:, keep][:, :, keep], p.V[:, keep][:, :, keep]
+    rng = np.random.default_rng(24)
+    th = chirpgen.prior_samples(rng, 5000)
+    ph = ile.ProblemHost(p, precision=ile.ILE_FP64, mode_filter_eps=eps)
+    job = ile.ile_prepare(gu.ctx(), ph)
+    try:
+        assert ile.ile_job_info_get(job).n_modes_kept == len(keep)
+        L, _ = gu.gpu_eval(job, th, ile.ILE_FP64)
+    finally:
+        ile.ile_job_release(job)
+    ref, T1, T2 = orc.lnL(pk, th, return_terms=True)
+    ok, _, _ = gu.tol_check(L, ref, T1, T2, 100.0 / th[3], ile.ILE_FP64)
+    assert ok
+
+
+def test_prepare_rejects_bad_inputs():
+    rng = np.random.default_rng(25)
+    p = chirpgen.random_problem(rng, 5, ["H", "L"])
+    bad = chirpgen.Problem(**{**p.__dict__})
+    bad.U = p.U.copy()
+    bad.U[0, 0, 1] += 1.0              # not Hermitian
+    with pytest.raises(ile.IleError) as e:
+        ile.ile_prepare(gu.ctx(), ile.ProblemHost(bad))
+    assert e.value.status == -1
+    bad = chirpgen.Problem(**{**p.__dict__})
+    bad.Q = p.Q.copy()
+    bad.Q[1, 2, 3] = np.nan
+    with pytest.raises(ile.IleError):
+        ile.ile_prepare(gu.ctx(), ile.ProblemHost(bad))
+    bad = chirpgen.Problem(**{**p.__dict__})
+    bad.modes = [(2, 2), (2, 2), (2, 0), (2, 1), (2, -1)]
+    with pytest.raises(ile.IleError):
+        ile.ile_prepare(gu.ctx(), ile.ProblemHost(bad))
+    # the context stays usable after rejected inputs
+    job = ile.ile_prepare(gu.ctx(), ile.ProblemHost(p))
+    ile.ile_job_release(job)
+
+
+# ------------------------------------------------------------------ estimator
+def _gpu_marg(job, lw, policy, flags=ile.ILE_MARG_RESET):
+    t = torch.from_numpy(np.ascontiguousarray(lw.astype(np.float32 if policy == ile.ILE_FP32 else np.float64)))
+    t = t.to("cuda")
+    return ile.ile_marginalize(job, len(lw), t, flags)
+
+
+@pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
+def test_marginalize_parity(orc, policy):
+    rng = np.random.default_rng(26)
+    p = chirpgen.random_problem(rng, 5, ["H", "L"])
+    job = ile.ile_prepare(gu.ctx(), ile.ProblemHost(p, precision=policy))
+    try:
+        cases = [rng.uniform(-1e5, 1e5, 100003), rng.normal(size=70001) * 30 - 500,
+                 np.full(5000, -3.25), np.array([7.0]), np.array([-np.inf] * 17),
+                 np.concatenate([rng.normal(size=4000), [np.inf, np.nan, -np.inf]])]
+        for lw in cases:
+            if policy == ile.ILE_FP32:
+                lw = lw.astype(np.float32).astype(np.float64)
+            r = _gpu_marg(job, lw, policy)
+            o = orc.marginalize(lw)
+            assert r["n"] == o["n"] and r["n_nonfinite"] == o["n_nonfinite"] and r["argmax"] == o["argmax"]
+            if o["ln_L"] == -np.inf:
+                assert r["ln_L"] == -np.inf and r["n_eff"] == 0
+                continue
+            assert abs(r["ln_L"] - o["ln_L"]) <= 1e-12 * max(1, abs(o["ln_L"]))
+            assert abs(r["n_eff"] - o["n_eff"]) <= 1e-11 * o["n_eff"]
+            assert abs(r["n_ess"] - o["n_ess"]) <= 1e-11 * o["n_ess"]
+            if len(lw) > 1:
+                if np.isfinite(o["ln_sigma"]):
+                    assert abs(r["ln_sigma"] - o["ln_sigma"]) <= 1e-9 * max(1, abs(o["ln_sigma"]))
+                else:                      # equal weights: zero spread on both sides
+                    assert r["ln_sigma"] == o["ln_sigma"]
+        # pooling over batches equals one pass over the concatenation
+        a, b = rng.normal(size=30000) * 5, rng.normal(size=20011) * 5 + 3
+        _gpu_marg(job, a, policy, ile.ILE_MARG_RESET)
+        r = _gpu_marg(job, b, policy, ile.ILE_MARG_POOL)
+        cat = np.concatenate([a, b])
+        if policy == ile.ILE_FP32:
+            cat = cat.astype(np.float32).astype(np.float64)
+        o = orc.marginalize(cat)
+        assert r["n"] == o["n"] and r["argmax"] == o["argmax"]
+        assert abs(r["ln_L"] - o["ln_L"]) <= 1e-12 * max(1, abs(o["ln_L"]))
+        # empty call leaves the pooled state unchanged
+        r2 = ile.ile_marginalize(job, 0, None, ile.ILE_MARG_POOL)
+        assert r2["n"] == r["n"] and r2["ln_L"] == r["ln_L"]
+    finally:
+        ile.ile_job_release(job)
+
+
+def test_eval_then_marginalize_matches_oracle(orc, recs):
+    """End to end on the small workload: GPU lnL + estimator vs oracle on the
+    same samples, |d ln L| <= 1e-4 (FP32) and 1e-10 (FP64)."""
+    probs, _ = chirpgen.build_event(recs["c1"], ["H", "L"], 5, 30.0, 2.0, 20.0, noise_seed=9)
+    rng = np.random.default_rng(27)
+    thd = chirpgen.prior_samples(rng, 1 << 17)
+    for policy, tol in ((ile.ILE_FP64, 1e-10), (ile.ILE_FP32, 1e-4), (ile.ILE_FP32_CANCEL64, 1e-4)):
+        th = _np_theta(thd, policy)
+        job = ile.ile_prepare(gu.ctx(), ile.ProblemHost(probs[0], precision=policy))
+        try:
+            L, W = gu.gpu_eval(job, th, policy)
+            r = _gpu_marg(job, W, policy if policy != ile.ILE_FP32_CANCEL64 else ile.ILE_FP64)
+        finally:
+            ile.ile_job_release(job)
+        o = orc.marginalize(orc.lnL(probs[0], th.astype(np.float64)))
+        print(PNAME[policy], "lnL_marg gpu", r["ln_L"], "oracle", o["ln_L"], "n_eff", o["n_eff"])
+        assert abs(r["ln_L"] - o["ln_L"]) <= tol
+
+
+# ---------------------------------------------------------------------- draws
+@pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
+def test_prior_draw_parity(orc, policy):
+    rng = np.random.default_rng(28)
+    p = chirpgen.random_problem(rng, 5, ["H", "L"])
+    job = ile.ile_prepare(gu.ctx(), ile.ProblemHost(p, precision=policy))
+    n, first, seed, rnd = 20011, 12345, 0xDEADBEEF12345678, 3
+    th = torch.empty((7, n), dtype=gu.torch_dtype(policy), device="cuda")
+    lr = torch.full((n,), 9.0, dtype=gu.torch_dtype(policy), device="cuda")
+    try:
+        ile.ile_draw(job, seed, rnd, first, n, th, n, lr)
+        torch.cuda.synchronize()
+    finally:
+        ile.ile_job_release(job)
+    g = th.double().cpu().numpy()
+    o, _ = orc.draw_prior(orc.make_prior(), seed, rnd, first, n)
+    if policy == ile.ILE_FP64:
+        assert np.allclose(g, o, rtol=1e-14, atol=1e-15)
+    else:
+        assert np.allclose(g, o.astype(np.float32).astype(np.float64), rtol=2e-7, atol=1e-12)
+    assert np.all(lr.cpu().numpy() == 0.0)
