@@ -101,6 +101,64 @@ def run_policy(ile, torch, ctx, probs, policy, n_per, steps, warmup, stream):
                 lnL_marg_first=out[0]["ln_L"], n_eff_first=out[0]["n_eff"])
 
 
+def serving_pool(per_class, seed):
+    """Events of every (modes, detectors) class; each job of the stream picks one."""
+    import chirpgen
+    recs = chirpgen.load_injections()["pool"]
+    rng = np.random.default_rng(seed)
+    pool = []
+    classes = [(n, d) for n in (5, 9, 17) for d in (("H", "L"), ("H", "L", "V"))]
+    for ci, (n, dets) in enumerate(classes):
+        for e in range(per_class):
+            rec = recs[(ci * per_class + e) % len(recs)]
+            snr = float(np.exp(rng.uniform(np.log(10), np.log(100))))
+            probs, _ = chirpgen.build_event(rec, list(dets), n, float(rng.uniform(20, 40)),
+                                            float(rng.uniform(1, 4)), snr, noise_seed=int(rng.integers(1 << 30)))
+            pool.append(probs[0])
+    return pool
+
+
+def serving_leg(ile, ctx, pool, n_jobs, adaptive, seed, policy, budget=0, rate=None):
+    """Submit a job stream with Poisson arrivals; returns throughput and latency.
+    rate=None: all jobs at once (saturated)."""
+    rng = np.random.default_rng(seed)
+    hosts = {}
+    srv = ile.ile_server_create(ctx, max_active=64, hbm_budget_bytes=budget, chunk_samples=1 << 20)
+    sizes = np.exp(rng.uniform(np.log(2 ** 14), np.log(2 ** 20), n_jobs)).astype(np.int64)
+    picks = rng.integers(0, len(pool), n_jobs)
+    gaps = rng.exponential(1.0 / rate, n_jobs) if rate else np.zeros(n_jobs)
+    ids = []
+    t0 = time.perf_counter()
+    t_next = t0
+    for k in range(n_jobs):
+        t_next += gaps[k]
+        while rate and time.perf_counter() < t_next:
+            pass
+        pi = int(picks[k])
+        if pi not in hosts:
+            hosts[pi] = ile.ProblemHost(pool[pi], precision=policy, dist_marg=adaptive)
+        jo = ile.job_opts(n_samples=int(sizes[k]), adaptive=adaptive, round_samples=1 << 16, max_rounds=32,
+                          n_eff_target=1000.0, seed=int(seed * 100003 + k))
+        ids.append(ile.ile_server_submit(srv, hosts[pi], jo))
+    res = [ile.ile_server_wait(srv, i, -1) for i in ids]
+    t1 = time.perf_counter()
+    ile.ile_server_destroy(srv)
+    lat = np.array([(r.t_finish_ns - r.t_arrival_ns) * 1e-6 for r in res])
+    waits = np.array([(r.t_admit_ns - r.t_arrival_ns) * 1e-6 for r in res])
+    samples = sum(r.samples for r in res)
+    first = min(r.t_arrival_ns for r in res)
+    last = max(r.t_finish_ns for r in res)
+    out = {"jobs": n_jobs, "samples": int(samples), "samples_per_s": samples / ((last - first) * 1e-9),
+           "wall_s": t1 - t0, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "admit_wait_p99_ms": float(np.percentile(waits, 99)),
+           "failed": int(sum(r.status != 0 for r in res))}
+    if adaptive:
+        rounds = np.array([r.rounds for r in res])
+        out.update({"rounds_mean": float(rounds.mean()),
+                    "frac_reached_neff": float(np.mean([r.marg.n_eff >= 1000.0 for r in res]))})
+    return out
+
+
 def cpu_baseline(probs, budget_s=15.0):
     """The oracle as it stands, on a bounded sample of the same workload."""
     import chirpgen
@@ -131,6 +189,9 @@ def main():
     ap.add_argument("--log2n", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=10000)
+    ap.add_argument("--adaptive-jobs", type=int, default=500)
+    ap.add_argument("--no-serving", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the path shards by "
@@ -152,6 +213,22 @@ def main():
         log("fp64 ...")
         r64 = run_policy(ile, torch, ctx, probs, ile.ILE_FP64, n_per, a.steps, a.warmup, stream)
         log(f"fp64 {r64}")
+    serving = None
+    if not a.no_serving:
+        log("serving pool ...")
+        pool = serving_pool(8, 250511655 + 4)
+        sat = serving_leg(ile, ctx, pool, min(2000, a.serving_jobs), False, 11, ile.ILE_FP32)
+        log(f"saturated {sat}")
+        e_n = (2 ** 20 - 2 ** 14) / math.log(2 ** 6)
+        rate = 0.7 * sat["samples_per_s"] / e_n
+        pois = serving_leg(ile, ctx, pool, a.serving_jobs, False, 12, ile.ILE_FP32, rate=rate)
+        log(f"poisson {pois}")
+        serving = {"plain_poisson_0.7": pois, "plain_saturated": sat, "arrival_rate_per_s": rate,
+                   "pool": f"{len(pool)} events (8 per (modes, detectors) class, SNR log-uniform 10-100), reused"}
+        if a.adaptive_jobs > 0:
+            ada = serving_leg(ile, ctx, pool, a.adaptive_jobs, True, 13, ile.ILE_FP32)
+            log(f"adaptive {ada}")
+            serving["adaptive_saturated"] = ada
     N = r32["N"]
     flop = FLOP_PER_SAMPLE[(3, 9)]
     t_eval = r32["kernel_ms"]["eval"] * 1e-3
@@ -175,7 +252,7 @@ def main():
         "fp64": None if r64 is None else {"value": r64["samples_per_s"], "ms_per_step": r64["ms_per_step"],
                                           "kernel_ms": r64["kernel_ms"],
                                           "fp32_over_fp64": r32["samples_per_s"] / r64["samples_per_s"]},
-        "serving": None,
+        "serving": serving,
         "cpu_baseline": None if a.no_cpu else cpu_baseline(probs),
     }
     print(json.dumps(line), flush=True)

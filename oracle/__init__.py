@@ -309,16 +309,18 @@ def _logpdf_rows(D, cov):
 
 
 def em_init(theta, lw, dims, n_comp=8, **rng_kw):
-    """First fit: means at the n_comp highest-weight distinct samples, common
-    weighted covariance (differences wrapped about the best sample), equal weights."""
+    """First fit: means at the highest-weight distinct samples among the
+    2 n_comp highest-weight ones (ties: lower index first), common weighted
+    covariance (differences wrapped about the best sample), equal weights."""
     X = np.asarray(theta, dtype=np.float64)[dims].T
     lw = np.asarray(lw, dtype=np.float64)
     fin = np.isfinite(lw)
     w = np.where(fin, np.exp(np.where(fin, lw, -np.inf) - np.max(lw[fin])), 0.0)
-    order = np.argsort(-w, kind="stable")
+    key = np.where(fin, lw, -np.inf)
+    order = np.argsort(-key, kind="stable")[:2 * n_comp]
     means = []
     for i in order:
-        if w[i] <= 0:
+        if not fin[i]:
             break
         if any(np.array_equal(X[i], m) for m in means):
             continue

@@ -185,12 +185,11 @@ extern "C" void ile_ctx_destroy(ile_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (auto &kv : ctx->dist) (void)hipFree(kv.second.buf);
-    if (ctx->d_batch) (void)hipFree(ctx->d_batch);
-    if (ctx->h_batch) (void)hipHostFree(ctx->h_batch);
-    if (ctx->batch_ev) (void)hipEventDestroy(ctx->batch_ev);
-    if (ctx->d_part) (void)hipFree(ctx->d_part);
-    if (ctx->d_mout) (void)hipFree(ctx->d_mout);
-    if (ctx->h_mout) (void)hipHostFree(ctx->h_mout);
+    for (auto &sl : ctx->slots) {
+        if (sl.d) (void)hipFree(sl.d);
+        if (sl.h) (void)hipHostFree(sl.h);
+        if (sl.ev) (void)hipEventDestroy(sl.ev);
+    }
     delete ctx;
 }
 
@@ -563,51 +562,80 @@ ile_status eval_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, hipStre
             for (int64_t t0 = 0; t0 < b.n; t0 += tile) tiles.push_back(Tile{jid, 0, t0, std::min(t0 + tile, b.n)});
         }
         void *dj = nullptr, *dt = nullptr;
+        int slot = -1;
         ile_status s = batch_upload(ctx, ej.data(), ej.size() * sizeof(EvalJob), tiles.data(),
-                                    tiles.size() * sizeof(Tile), &dj, &dt, st);
+                                    tiles.size() * sizeof(Tile), &dj, &dt, &slot, st);
         if (s != ILE_OK) return s;
         const auto &key = g.first;
         hipError_t e = launch_eval(std::get<0>(key), std::get<1>(key), std::get<2>(key), std::get<3>(key) != 0,
                                    lds ? win : 0, (const EvalJob *)dj, (const Tile *)dt, (int)tiles.size(), ej[0],
                                    tile, lds ? 512 : 256, st);
         if (e != hipSuccess) return dev_fail(ctx, e, "batched eval launch");
-        e = hipEventRecord(ctx->batch_ev, st);
-        if (e != hipSuccess) return dev_fail(ctx, e, "batch event");
+        if ((s = batch_done(ctx, slot, st)) != ILE_OK) return s;
     }
     return ILE_OK;
 }
 
-// Copy two host arrays into the context's device scratch through pinned
-// staging; the previous batch's copy must have completed before the staging
-// buffer is rewritten (tracked by batch_ev).  Caller holds batch_mu.
 ile_status batch_upload(ile_ctx *ctx, const void *a, size_t na, const void *b, size_t nb, void **da, void **db,
-                        hipStream_t st) {
-    const size_t oa = 0, ob = (na + 255) / 256 * 256, need = ob + nb;
+                        int *slot_out, hipStream_t st, size_t extra, void **dextra, void **hextra) {
+    const size_t oa = 0, ob = (na + 255) / 256 * 256, copy = ob + nb;
+    const size_t oe = (copy + 255) / 256 * 256, need = oe + extra;
+    const int si = ctx->next_slot;
+    ctx->next_slot = (si + 1) % ile_ctx::kSlots;
+    ile_ctx::Slot &sl = ctx->slots[si];
     hipError_t e;
-    if (!ctx->batch_ev) {
-        if ((e = hipEventCreateWithFlags(&ctx->batch_ev, hipEventDisableTiming)) != hipSuccess)
-            return dev_fail(ctx, e, "event create");
-    }
-    if ((e = hipEventSynchronize(ctx->batch_ev)) != hipSuccess) return dev_fail(ctx, e, "batch event wait");
-    if (need > ctx->batch_cap) {
-        if ((e = hipDeviceSynchronize()) != hipSuccess) return dev_fail(ctx, e, "sync before scratch growth");
-        if (ctx->d_batch) (void)hipFree(ctx->d_batch);
-        if (ctx->h_batch) (void)hipHostFree(ctx->h_batch);
-        ctx->d_batch = nullptr;
-        ctx->h_batch = nullptr;
-        const size_t cap = std::max<size_t>(need * 2, 1 << 20);
-        if ((e = hipMalloc(&ctx->d_batch, cap)) != hipSuccess) return dev_fail(ctx, e, "batch scratch");
-        if ((e = hipHostMalloc(&ctx->h_batch, cap, hipHostMallocDefault)) != hipSuccess)
+    if (!sl.ev && (e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming)) != hipSuccess)
+        return dev_fail(ctx, e, "event create");
+    if (sl.armed && (e = hipEventSynchronize(sl.ev)) != hipSuccess) return dev_fail(ctx, e, "scratch slot wait");
+    sl.armed = false;
+    if (need > sl.cap) {
+        if (sl.d) (void)hipFree(sl.d);
+        if (sl.h) (void)hipHostFree(sl.h);
+        sl.d = nullptr;
+        sl.h = nullptr;
+        sl.cap = 0;
+        const size_t cap = std::max<size_t>(need * 2, 1 << 16);
+        if ((e = hipMalloc(&sl.d, cap)) != hipSuccess) return dev_fail(ctx, e, "batch scratch");
+        if ((e = hipHostMalloc(&sl.h, cap, hipHostMallocDefault)) != hipSuccess)
             return dev_fail(ctx, e, "batch staging");
-        ctx->batch_cap = cap;
+        sl.cap = cap;
     }
-    std::memcpy((char *)ctx->h_batch + oa, a, na);
-    std::memcpy((char *)ctx->h_batch + ob, b, nb);
-    if ((e = hipMemcpyAsync(ctx->d_batch, ctx->h_batch, need, hipMemcpyHostToDevice, st)) != hipSuccess)
+    std::memcpy((char *)sl.h + oa, a, na);
+    if (nb) std::memcpy((char *)sl.h + ob, b, nb);
+    if ((e = hipMemcpyAsync(sl.d, sl.h, copy, hipMemcpyHostToDevice, st)) != hipSuccess)
         return dev_fail(ctx, e, "batch upload");
-    *da = (char *)ctx->d_batch + oa;
-    *db = (char *)ctx->d_batch + ob;
+    *da = (char *)sl.d + oa;
+    *db = (char *)sl.d + ob;
+    if (dextra) *dextra = (char *)sl.d + oe;
+    if (hextra) *hextra = (char *)sl.h + oe;
+    *slot_out = si;
     return ILE_OK;
+}
+
+ile_status batch_done(ile_ctx *ctx, int slot, hipStream_t st) {
+    ile_ctx::Slot &sl = ctx->slots[slot];
+    hipError_t e = hipEventRecord(sl.ev, st);
+    if (e != hipSuccess) return dev_fail(ctx, e, "slot event");
+    sl.armed = true;
+    return ILE_OK;
+}
+
+// Counter-based draws for several jobs of one theta type in one launch.
+ile_status draw_batch(ile_ctx *ctx, int policy, const std::vector<DrawJob> &jobs, hipStream_t st) {
+    const int64_t tile = 2048;
+    std::vector<Tile> tiles;
+    for (size_t j = 0; j < jobs.size(); j++)
+        for (int64_t t = 0; t < jobs[j].n; t += tile) tiles.push_back(Tile{(int32_t)j, 0, t, std::min(t + tile, jobs[j].n)});
+    if (tiles.empty()) return ILE_OK;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    void *dj = nullptr, *dt = nullptr;
+    int slot = -1;
+    ile_status s = batch_upload(ctx, jobs.data(), jobs.size() * sizeof(DrawJob), tiles.data(),
+                                tiles.size() * sizeof(Tile), &dj, &dt, &slot, st);
+    if (s != ILE_OK) return s;
+    hipError_t e = launch_draw(policy, (const DrawJob *)dj, (const Tile *)dt, (int)tiles.size(), jobs[0], tile, st);
+    if (e != hipSuccess) return dev_fail(ctx, e, "batched draw");
+    return batch_done(ctx, slot, st);
 }
 
 }  // namespace ile

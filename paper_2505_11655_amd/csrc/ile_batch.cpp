@@ -1,6 +1,8 @@
 // Batched estimator entry point: many jobs' log-weights reduced in one
 // partials launch and one combine launch, each job with the same tile
 // decomposition as its single-job reduction (bitwise-identical results).
+// Descriptors, tile partials and the per-job result copies live in one
+// scratch slot of the context.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,7 +18,7 @@ namespace ile {
 constexpr int64_t kMargTileB = 16384;  // must equal the single-job tile
 
 ile_status marg_batch(ile_ctx *ctx, ile_job *const *jobs, int n_jobs, const int64_t *n, const void *const *lw,
-                      uint32_t flags, ile_marg *out, hipStream_t st) {
+                      const uint32_t *flags, ile_marg *out, hipStream_t st) {
     std::vector<MargJob> mj(n_jobs);
     std::vector<Tile> tiles;
     const int policy = jobs[0]->policy == kFP32 ? kFP32 : kFP64;
@@ -29,51 +31,31 @@ ile_status marg_batch(ile_ctx *ctx, ile_job *const *jobs, int n_jobs, const int6
         for (int64_t t = 0; t < n[j]; t += kMargTileB) tiles.push_back(Tile{j, 0, t, std::min(t + kMargTileB, n[j])});
         mj[j].tile_end = (int32_t)tiles.size();
         mj[j].state = jobs[j]->d_ms;
-        mj[j].out = nullptr;
-        mj[j].reset = (flags & ILE_MARG_RESET) ? 1 : 0;
+        mj[j].out_idx = out ? j : -1;
+        mj[j].reset = (flags[j] & ILE_MARG_RESET) ? 1 : 0;
     }
+    const size_t part_bytes = std::max<size_t>(tiles.size(), 1) * sizeof(MargPartial);
+    const size_t off_out = (part_bytes + 255) / 256 * 256;
+    const size_t extra = off_out + (size_t)n_jobs * sizeof(MargState);
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
-    hipError_t e;
-    if (tiles.size() > ctx->part_cap || (size_t)n_jobs > ctx->mout_cap) {
-        if ((e = hipDeviceSynchronize()) != hipSuccess) return dev_fail(ctx, e, "sync before growth");
-        if (tiles.size() > ctx->part_cap) {
-            if (ctx->d_part) (void)hipFree(ctx->d_part);
-            ctx->d_part = nullptr;
-            const size_t cap = std::max<size_t>(tiles.size() * 2, 4096);
-            if ((e = hipMalloc((void **)&ctx->d_part, cap * sizeof(MargPartial))) != hipSuccess)
-                return dev_fail(ctx, e, "partials");
-            ctx->part_cap = cap;
-        }
-        if ((size_t)n_jobs > ctx->mout_cap) {
-            if (ctx->d_mout) (void)hipFree(ctx->d_mout);
-            if (ctx->h_mout) (void)hipHostFree(ctx->h_mout);
-            ctx->d_mout = nullptr;
-            ctx->h_mout = nullptr;
-            const size_t cap = std::max<size_t>((size_t)n_jobs * 2, 256);
-            if ((e = hipMalloc((void **)&ctx->d_mout, cap * sizeof(MargState))) != hipSuccess)
-                return dev_fail(ctx, e, "result copies");
-            if ((e = hipHostMalloc((void **)&ctx->h_mout, cap * sizeof(MargState), hipHostMallocDefault)) !=
-                hipSuccess)
-                return dev_fail(ctx, e, "pinned results");
-            ctx->mout_cap = cap;
-        }
-    }
-    if (out)
-        for (int j = 0; j < n_jobs; j++) mj[j].out = ctx->d_mout + j;
-    void *dj = nullptr, *dt = nullptr;
+    void *dj = nullptr, *dt = nullptr, *dx = nullptr, *hx = nullptr;
+    int slot = -1;
     ile_status s = batch_upload(ctx, mj.data(), mj.size() * sizeof(MargJob), tiles.data(), tiles.size() * sizeof(Tile),
-                                &dj, &dt, st);
+                                &dj, &dt, &slot, st, extra, &dx, &hx);
     if (s != ILE_OK) return s;
-    e = launch_marg_batch(policy, (const MargJob *)dj, n_jobs, (const Tile *)dt, (int)tiles.size(), ctx->d_part, st);
+    MargPartial *d_part = (MargPartial *)dx;
+    MargState *d_out = (MargState *)((char *)dx + off_out);
+    MargState *h_out = (MargState *)((char *)hx + off_out);
+    hipError_t e = launch_marg_batch(policy, (const MargJob *)dj, n_jobs, (const Tile *)dt, (int)tiles.size(), d_part,
+                                     out ? d_out : nullptr, st);
     if (e != hipSuccess) return dev_fail(ctx, e, "batched estimator");
-    if ((e = hipEventRecord(ctx->batch_ev, st)) != hipSuccess) return dev_fail(ctx, e, "batch event");
     if (out) {
-        e = hipMemcpyAsync(ctx->h_mout, ctx->d_mout, (size_t)n_jobs * sizeof(MargState), hipMemcpyDeviceToHost, st);
+        e = hipMemcpyAsync(h_out, d_out, (size_t)n_jobs * sizeof(MargState), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return dev_fail(ctx, e, "read batched estimator");
-        for (int j = 0; j < n_jobs; j++) marg_from_state(ctx->h_mout[j], &out[j]);
+        for (int j = 0; j < n_jobs; j++) marg_from_state(h_out[j], &out[j]);
     }
-    return ILE_OK;
+    return batch_done(ctx, slot, st);
 }
 }  // namespace ile
 
@@ -88,5 +70,6 @@ extern "C" ile_status ile_marginalize_batch(ile_job *const *jobs, int32_t n_jobs
         if (!jobs[j] || jobs[j]->ctx != ctx) return set_err(ILE_E_INVALID, "jobs must share one context");
         if (n[j] < 0 || (n[j] > 0 && !lw[j])) return set_err(ILE_E_INVALID, "bad lw");
     }
-    return marg_batch(ctx, jobs, n_jobs, n, lw, flags, out, (hipStream_t)stream);
+    std::vector<uint32_t> fl(n_jobs, flags);
+    return marg_batch(ctx, jobs, n_jobs, n, lw, fl.data(), out, (hipStream_t)stream);
 }

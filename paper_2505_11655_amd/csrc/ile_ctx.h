@@ -25,18 +25,19 @@ struct ile_ctx {
     };
     std::mutex dist_mu;
     std::map<std::tuple<double, double, double>, DistEntry> dist;
-    // batched-launch descriptors: device scratch + pinned staging
+    // batched-launch descriptors: a ring of device scratch slots with pinned
+    // staging; a slot is reused only after the kernel that read it finished.
+    struct Slot {
+        void *d = nullptr;
+        void *h = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool armed = false;
+    };
+    static constexpr int kSlots = 8;
     std::mutex batch_mu;
-    void *d_batch = nullptr;
-    void *h_batch = nullptr;
-    size_t batch_cap = 0;
-    hipEvent_t batch_ev = nullptr;
-    // batched estimator: tile partials and per-job result copies
-    ile::MargPartial *d_part = nullptr;
-    size_t part_cap = 0;
-    ile::MargState *d_mout = nullptr;
-    ile::MargState *h_mout = nullptr;     // pinned
-    size_t mout_cap = 0;
+    Slot slots[kSlots];
+    int next_slot = 0;
 };
 
 struct ile_job {
@@ -105,8 +106,17 @@ ile_status ctx_check(ile_ctx *ctx);
 ile_status ctx_alloc(ile_ctx *ctx, void **p, size_t bytes, const char *what);
 void ctx_free(ile_ctx *ctx, void *p, size_t bytes);
 ile_status eval_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, hipStream_t st);
+// Copy two host arrays into a scratch slot (caller holds batch_mu); after
+// enqueueing the kernel that reads them, call batch_done with the slot.
+// `extra` bytes of device scratch (and the same of pinned host staging) follow
+// the copied arrays in the slot, for kernel outputs read back by the caller.
 ile_status batch_upload(ile_ctx *ctx, const void *a, size_t na, const void *b, size_t nb, void **da, void **db,
-                        hipStream_t st);
+                        int *slot, hipStream_t st, size_t extra = 0, void **dextra = nullptr,
+                        void **hextra = nullptr);
+ile_status batch_done(ile_ctx *ctx, int slot, hipStream_t st);
+ile_status draw_batch(ile_ctx *ctx, int policy, const std::vector<DrawJob> &jobs, hipStream_t st);
+ile_status marg_batch(ile_ctx *ctx, ile_job *const *jobs, int n_jobs, const int64_t *n, const void *const *lw,
+                      const uint32_t *flags, ile_marg *out, hipStream_t st);
 ile_status job_marg_launch(ile_job *job, int64_t n, const void *lw, bool reset, hipStream_t st);
 ile_status job_adapt(ile_job *job, int64_t n, const void *theta, int64_t ld, const void *lw, const ile_gmm_opts *o,
                      hipStream_t st);

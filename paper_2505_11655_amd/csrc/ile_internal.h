@@ -205,9 +205,8 @@ struct MargJob {
     int64_t n;
     int32_t tile_begin, tile_end;
     MargState *state;     // pooled state (device)
-    MargState *out;       // copy of the state after this batch (device), or null
+    int32_t out_idx;      // slot of the state copy in the launch's output array, or -1
     int32_t reset;
-    int32_t pad_;
 };
 
 constexpr int kMaxComp = 16;
@@ -257,7 +256,7 @@ hipError_t launch_marg_partials(int policy, const void *lw, int64_t n, int64_t t
 hipError_t launch_marg_combine(const MargPartial *d_part, int n_part, int64_t n, MargState *d_state,
                                int reset, hipStream_t st);
 hipError_t launch_marg_batch(int policy, const MargJob *d_jobs, int n_jobs, const Tile *d_tiles, int n_tiles,
-                             MargPartial *d_part, hipStream_t st);
+                             MargPartial *d_part, MargState *d_out, hipStream_t st);
 
 hipError_t launch_draw(int policy, const DrawJob *d_jobs, const Tile *d_tiles, int n_tiles,
                        const DrawJob &single, int64_t tile, hipStream_t st);

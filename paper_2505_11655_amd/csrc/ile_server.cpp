@@ -1,0 +1,424 @@
+// Continuous-batching server for marginal-likelihood jobs.
+//
+// A job is one intrinsic point: its Q/U/V inputs (copied at submit), a sample
+// budget (plain) or a round size with a refit rule (adaptive).  One scheduler
+// thread owns a HIP stream and loops:
+//   1. admit queued jobs in arrival order while a slot is free and the job's
+//      device footprint fits the budget (prepare: upload and keep resident);
+//   2. build one pass over every admitted job: its next chunk (plain) or round
+//      (adaptive) of samples;
+//   3. launch, for all of them together, one counter-based draw, one lnL
+//      launch per compiled kernel class, and one estimator launch; read back
+//      the per-job pooled estimator states (the only host sync per pass);
+//   4. finish jobs whose budget is spent or whose n_eff reached the target (or
+//      whose round cap is hit), refit the proposal of the others from this
+//      round's samples, free finished jobs' memory, post their results.
+// Jobs that arrive while a pass runs are admitted in the next pass, so their
+// work overlaps with the jobs already on the device.  Every quantity a job
+// computes depends only on its own inputs, key and chunk sizes (draw counters,
+// per-sample likelihood, fixed estimator tiles), so its result is bitwise the
+// same alone or in any mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "ile.h"
+#include "ile_ctx.h"
+#include "ile_internal.h"
+
+using namespace ile;
+
+namespace {
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+enum ReqState { kQueued, kActive, kDone };
+
+struct Req {
+    uint64_t id = 0;
+    // host copy of the problem
+    std::vector<int32_t> ml, mm;
+    std::vector<double> pos, resp, Q, U, V;
+    ile_problem prob{};
+    ile_job_opts jo{};
+    size_t footprint = 0;
+    // device state while admitted
+    ile_job *job = nullptr;
+    void *d_theta = nullptr, *d_lr = nullptr, *d_lw = nullptr;
+    size_t buf_bytes = 0;
+    int64_t chunk = 0;        // samples per pass
+    int64_t done = 0;         // samples evaluated
+    int32_t rounds = 0;
+    ReqState state = kQueued;
+    bool cancel = false;
+    ile_result res{};
+};
+
+}  // namespace
+
+struct ile_server {
+    ile_ctx *ctx = nullptr;
+    ile_server_opts opts{};
+    size_t budget = 0, used = 0;
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    uint64_t next_id = 1;
+    std::deque<Req *> queue;
+    std::vector<Req *> active;
+    std::unordered_map<uint64_t, std::unique_ptr<Req>> all;
+    int64_t n_done = 0;
+    hipStream_t stream = nullptr;
+    bool failed = false;
+};
+
+namespace {
+
+size_t theta_bytes(int policy) { return policy == kFP64 ? 8 : 4; }
+size_t lw_bytes(int policy) { return policy == kFP32 ? 4 : 8; }
+
+int64_t chunk_of(const ile_server *s, const Req *r) {
+    if (r->jo.adaptive) return r->jo.round_samples > 0 ? r->jo.round_samples : 65536;
+    const int64_t c = s->opts.chunk_samples > 0 ? s->opts.chunk_samples : (1 << 20);
+    return std::max<int64_t>(1, std::min(c, r->jo.n_samples));
+}
+
+// Device bytes a job holds while admitted (inputs in the policy's precision,
+// sample buffers for one pass, estimator partials, mixture and EM workspace).
+size_t footprint_of(const ile_server *s, const Req *r) {
+    const ile_problem &P = r->prob;
+    const int policy = P.precision;
+    const size_t cr = policy == kFP32 ? 4 : 8;
+    const int kp = P.n_det == 1 ? 2 : P.n_det;
+    const int nm = 21;   // upper bound on compiled slots
+    const size_t inputs = (size_t)kp * P.n_time * nm * 2 * cr + 2 * (size_t)(nm * (nm + 1) / 2) * kp * 2 * cr;
+    const int64_t c = chunk_of(s, r);
+    const size_t bufs = (size_t)c * (8 * theta_bytes(policy) + lw_bytes(policy));
+    size_t extra = sizeof(MargState) + ((size_t)c / 16384 + 1) * sizeof(MargPartial);
+    if (r->jo.adaptive) extra += sizeof(GmmDev) + em_work_bytes(c) + 64 * sizeof(uint32_t);
+    return inputs + bufs + extra;
+}
+
+void finish(ile_server *s, Req *r, int status, const ile_marg *m) {
+    r->res.status = status;
+    if (m) r->res.marg = *m;
+    r->res.rounds = r->rounds;
+    r->res.samples = r->done;
+    r->res.t_finish_ns = now_ns();
+    if (r->job) {
+        const int policy = r->prob.precision;
+        ctx_free(s->ctx, r->d_theta, (size_t)7 * r->chunk * theta_bytes(policy));
+        ctx_free(s->ctx, r->d_lr, (size_t)r->chunk * theta_bytes(policy));
+        ctx_free(s->ctx, r->d_lw, (size_t)r->chunk * lw_bytes(policy));
+        r->d_theta = r->d_lr = r->d_lw = nullptr;
+        ile_job_release(r->job);
+        r->job = nullptr;
+    }
+    s->used -= std::min(s->used, r->footprint);
+    r->state = kDone;
+    s->n_done++;
+    // the host copy of the inputs is no longer needed
+    r->Q.clear(); r->Q.shrink_to_fit();
+    r->U.clear(); r->U.shrink_to_fit();
+    r->V.clear(); r->V.shrink_to_fit();
+}
+
+// Admit one request: prepare its job and allocate its pass buffers.
+ile_status admit(ile_server *s, Req *r) {
+    ile_job *job = nullptr;
+    ile_status st = ile_prepare(s->ctx, &r->prob, &job);
+    if (st != ILE_OK) return st;
+    r->job = job;
+    r->chunk = chunk_of(s, r);
+    const int policy = r->prob.precision;
+    const size_t tb = theta_bytes(policy);
+    if ((st = ctx_alloc(s->ctx, &r->d_theta, (size_t)7 * r->chunk * tb, "theta")) != ILE_OK) return st;
+    if ((st = ctx_alloc(s->ctx, &r->d_lr, (size_t)r->chunk * tb, "ln p - ln ps")) != ILE_OK) return st;
+    if ((st = ctx_alloc(s->ctx, &r->d_lw, (size_t)r->chunk * lw_bytes(policy), "lw")) != ILE_OK) return st;
+    r->res.t_admit_ns = now_ns();
+    return ILE_OK;
+}
+
+// One scheduling pass over the active set.  Returns false on a device error.
+bool run_pass(ile_server *s, std::vector<Req *> &act) {
+    hipStream_t st = s->stream;
+    const int64_t t_start = now_ns();
+    // draws, grouped by theta type
+    std::vector<DrawJob> d32, d64;
+    std::vector<BatchItem> items;
+    std::vector<int64_t> nthis(act.size());
+    for (size_t i = 0; i < act.size(); i++) {
+        Req *r = act[i];
+        if (r->res.t_start_ns == 0) r->res.t_start_ns = t_start;
+        const int64_t n = r->jo.adaptive ? r->chunk : std::min(r->chunk, r->jo.n_samples - r->done);
+        nthis[i] = n;
+        DrawJob dj{};
+        dj.gmm = r->job->has_prop ? r->job->d_gmm : nullptr;
+        dj.pr = r->job->pr;
+        dj.seed = r->jo.seed;
+        dj.round = r->jo.adaptive ? (uint32_t)r->rounds : 0u;
+        dj.first = r->jo.adaptive ? 0 : r->done;
+        dj.theta = r->d_theta;
+        dj.ld = n;
+        dj.lnpmps = r->d_lr;
+        dj.n = n;
+        (r->prob.precision == kFP64 ? d64 : d32).push_back(dj);
+        items.push_back(BatchItem{r->job, n, r->d_theta, n, r->d_lr, nullptr, r->d_lw});
+    }
+    if (!d32.empty() && draw_batch(s->ctx, kFP32, d32, st) != ILE_OK) return false;
+    if (!d64.empty() && draw_batch(s->ctx, kFP64, d64, st) != ILE_OK) return false;
+    if (eval_batch(s->ctx, items, st) != ILE_OK) return false;
+    // estimator, grouped by lw type (float for FP32, double otherwise)
+    std::vector<ile_marg> res(act.size());
+    for (int g = 0; g < 2; g++) {
+        std::vector<ile_job *> jobs;
+        std::vector<int64_t> ns;
+        std::vector<const void *> lws;
+        std::vector<uint32_t> fl;
+        std::vector<size_t> idx;
+        for (size_t i = 0; i < act.size(); i++) {
+            const bool f32 = act[i]->prob.precision == kFP32;
+            if ((g == 0) != f32) continue;
+            jobs.push_back(act[i]->job);
+            ns.push_back(nthis[i]);
+            lws.push_back(act[i]->d_lw);
+            fl.push_back(act[i]->done == 0 && act[i]->rounds == 0 ? ILE_MARG_RESET : ILE_MARG_POOL);
+            idx.push_back(i);
+        }
+        if (jobs.empty()) continue;
+        std::vector<ile_marg> out(jobs.size());
+        if (marg_batch(s->ctx, jobs.data(), (int)jobs.size(), ns.data(), lws.data(), fl.data(), out.data(), st) !=
+            ILE_OK)
+            return false;
+        for (size_t q = 0; q < idx.size(); q++) res[idx[q]] = out[q];
+    }
+    // completion and refits
+    std::vector<Req *> refit;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (size_t i = 0; i < act.size(); i++) {
+            Req *r = act[i];
+            r->done += nthis[i];
+            r->rounds += 1;
+            bool fin;
+            if (r->jo.adaptive) {
+                const int maxr = r->jo.max_rounds > 0 ? r->jo.max_rounds : 32;
+                const double tgt = r->jo.n_eff_target > 0 ? r->jo.n_eff_target : 1000.0;
+                fin = res[i].n_eff >= tgt || r->rounds >= maxr;
+            } else {
+                fin = r->done >= r->jo.n_samples;
+            }
+            if (r->cancel) {
+                finish(s, r, ILE_E_CANCELLED, &res[i]);
+            } else if (fin) {
+                finish(s, r, ILE_OK, &res[i]);
+            } else if (r->jo.adaptive) {
+                refit.push_back(r);
+            }
+        }
+        s->active.erase(std::remove_if(s->active.begin(), s->active.end(), [](Req *r) { return r->state == kDone; }),
+                        s->active.end());
+    }
+    s->cv_done.notify_all();
+    for (Req *r : refit) {
+        ile_gmm_opts o{};
+        o.n_comp = 8;
+        o.n_iter = 8;
+        o.eps_def = 0.05;
+        o.seed = r->jo.seed ^ 0x9E3779B97F4A7C15ull;
+        o.round = (uint32_t)r->rounds;
+        o.z_draws = 65536;
+        if (job_adapt(r->job, r->chunk, r->d_theta, r->chunk, r->d_lw, &o, st) != ILE_OK) return false;
+    }
+    return true;
+}
+
+void scheduler(ile_server *s) {
+    (void)hipSetDevice(s->ctx->device);
+    for (;;) {
+        std::vector<Req *> act;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
+            if (s->stop) break;
+            // cancelled jobs still in the queue
+            for (auto it = s->queue.begin(); it != s->queue.end();) {
+                if ((*it)->cancel) {
+                    finish(s, *it, ILE_E_CANCELLED, nullptr);
+                    it = s->queue.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+            const int maxa = s->opts.max_active > 0 ? s->opts.max_active : 64;
+            while (!s->queue.empty() && (int)s->active.size() < maxa && !s->failed) {
+                Req *r = s->queue.front();
+                if (s->used + r->footprint > s->budget) break;   // arrival order: wait for memory
+                s->queue.pop_front();
+                s->used += r->footprint;
+                lk.unlock();
+                ile_status st = admit(s, r);
+                lk.lock();
+                if (st != ILE_OK) {
+                    finish(s, r, st, nullptr);
+                    continue;
+                }
+                r->state = kActive;
+                s->active.push_back(r);
+            }
+            act = s->active;
+        }
+        s->cv_done.notify_all();
+        if (act.empty()) continue;
+        if (!run_pass(s, act)) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->failed = true;
+            for (Req *r : s->active) finish(s, r, ILE_E_DEVICE, nullptr);
+            s->active.clear();
+            for (Req *r : s->queue) finish(s, r, ILE_E_DEVICE, nullptr);
+            s->queue.clear();
+            s->cv_done.notify_all();
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" ile_status ile_server_create(ile_ctx *ctx, const ile_server_opts *opts, ile_server **out) {
+    ile_status st = ctx_check(ctx);
+    if (st != ILE_OK) return st;
+    if (!out) return set_err(ILE_E_INVALID, "null output");
+    ile_server *s = new ile_server();
+    s->ctx = ctx;
+    if (opts) s->opts = *opts;
+    s->budget = s->opts.hbm_budget_bytes ? s->opts.hbm_budget_bytes : ctx->budget;
+    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete s;
+        return dev_fail(ctx, e, "server stream");
+    }
+    s->th = std::thread(scheduler, s);
+    *out = s;
+    return ILE_OK;
+}
+
+extern "C" ile_status ile_server_submit(ile_server *s, const ile_problem *P, const ile_job_opts *jo,
+                                        uint64_t *job_id) {
+    if (!s || !P || !jo || !job_id) return set_err(ILE_E_INVALID, "null argument");
+    if (P->n_det < 1 || P->n_det > 3 || P->n_modes < 1 || P->n_modes > kMaxModes || P->n_time < 4 || !P->Q ||
+        !P->U || !P->mode_l || !P->mode_m || !P->det_pos || !P->det_resp)
+        return set_err(ILE_E_INVALID, "bad problem shape");
+    if (!jo->adaptive && jo->n_samples < 1) return set_err(ILE_E_INVALID, "n_samples must be >= 1");
+    auto r = std::make_unique<Req>();
+    const int K = P->n_det, n = P->n_modes, T = P->n_time;
+    r->ml.assign(P->mode_l, P->mode_l + n);
+    r->mm.assign(P->mode_m, P->mode_m + n);
+    r->pos.assign(P->det_pos, P->det_pos + 3 * K);
+    r->resp.assign(P->det_resp, P->det_resp + 9 * K);
+    r->Q.assign(P->Q, P->Q + (size_t)K * n * T * 2);
+    r->U.assign(P->U, P->U + (size_t)K * n * n * 2);
+    if (P->V) r->V.assign(P->V, P->V + (size_t)K * n * n * 2);
+    r->prob = *P;
+    r->prob.mode_l = r->ml.data();
+    r->prob.mode_m = r->mm.data();
+    r->prob.det_pos = r->pos.data();
+    r->prob.det_resp = r->resp.data();
+    r->prob.Q = r->Q.data();
+    r->prob.U = r->U.data();
+    r->prob.V = P->V ? r->V.data() : nullptr;
+    r->jo = *jo;
+    r->footprint = footprint_of(s, r.get());
+    if (r->footprint > s->budget) return set_err(ILE_E_TOO_BIG, "job footprint exceeds the server budget");
+    r->res.t_arrival_ns = now_ns();
+    r->res.status = ILE_PENDING;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->failed) return set_err(ILE_E_DEVICE, "server failed after a device error");
+    r->id = s->next_id++;
+    *job_id = r->id;
+    s->queue.push_back(r.get());
+    s->all[r->id] = std::move(r);
+    s->cv_work.notify_one();
+    return ILE_OK;
+}
+
+extern "C" ile_status ile_server_poll(ile_server *s, uint64_t id, ile_result *out) {
+    if (!s || !out) return set_err(ILE_E_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(id);
+    if (it == s->all.end()) return set_err(ILE_E_INVALID, "unknown job id");
+    *out = it->second->res;
+    return it->second->state == kDone ? ILE_OK : ILE_PENDING;
+}
+
+extern "C" ile_status ile_server_wait(ile_server *s, uint64_t id, int64_t timeout_ms, ile_result *out) {
+    if (!s || !out) return set_err(ILE_E_INVALID, "null argument");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(id);
+    if (it == s->all.end()) return set_err(ILE_E_INVALID, "unknown job id");
+    Req *r = it->second.get();
+    auto pred = [&] { return r->state == kDone; };
+    if (timeout_ms < 0) {
+        s->cv_done.wait(lk, pred);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred)) {
+        *out = r->res;
+        return set_err(ILE_E_TIMEOUT, "wait timed out");
+    }
+    *out = r->res;
+    return ILE_OK;
+}
+
+extern "C" ile_status ile_server_cancel(ile_server *s, uint64_t id) {
+    if (!s) return set_err(ILE_E_INVALID, "null server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(id);
+    if (it == s->all.end()) return set_err(ILE_E_INVALID, "unknown job id");
+    it->second->cancel = true;
+    s->cv_work.notify_one();
+    return ILE_OK;
+}
+
+extern "C" ile_status ile_server_stats(ile_server *s, int64_t *active, int64_t *queued, int64_t *done) {
+    if (!s) return set_err(ILE_E_INVALID, "null server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (active) *active = (int64_t)s->active.size();
+    if (queued) *queued = (int64_t)s->queue.size();
+    if (done) *done = s->n_done;
+    return ILE_OK;
+}
+
+extern "C" void ile_server_destroy(ile_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        for (Req *r : s->queue) r->cancel = true;
+        for (Req *r : s->active) r->cancel = true;
+    }
+    s->cv_work.notify_all();
+    if (s->th.joinable()) s->th.join();
+    (void)hipSetDevice(s->ctx->device);
+    (void)hipStreamSynchronize(s->stream);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (Req *r : s->active) finish(s, r, ILE_E_CANCELLED, nullptr);
+        for (Req *r : s->queue) finish(s, r, ILE_E_CANCELLED, nullptr);
+        s->active.clear();
+        s->queue.clear();
+    }
+    s->cv_done.notify_all();
+    (void)hipStreamDestroy(s->stream);
+    delete s;
+}

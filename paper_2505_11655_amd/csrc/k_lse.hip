@@ -159,7 +159,8 @@ __global__ void __launch_bounds__(kLseThreads)
 }
 
 __global__ void __launch_bounds__(kLseThreads) k_marg_combine_batch(const MargJob *__restrict__ jobs,
-                                                                    const MargPartial *__restrict__ part) {
+                                                                    const MargPartial *__restrict__ part,
+                                                                    MargState *__restrict__ out) {
     const MargJob &J = jobs[blockIdx.x];
     Acc a{-INFINITY, 0.0, 0.0, 0, INT64_MAX};
     const int np = J.tile_end - J.tile_begin;
@@ -182,14 +183,14 @@ __global__ void __launch_bounds__(kLseThreads) k_marg_combine_batch(const MargJo
         st->m = old.m; st->s1 = old.s1; st->s2 = old.s2; st->n_bad = old.bad;
         st->argmax = (old.m == -INFINITY) ? -1 : old.am;
         st->n += J.n;
-        if (J.out) *J.out = *st;
+        if (out && J.out_idx >= 0) out[J.out_idx] = *st;
     }
 }
 
 }  // namespace
 
 hipError_t launch_marg_batch(int policy, const MargJob *d_jobs, int n_jobs, const Tile *d_tiles, int n_tiles,
-                             MargPartial *d_part, hipStream_t st) {
+                             MargPartial *d_part, MargState *d_out, hipStream_t st) {
     if (n_tiles > 0) {
         if (policy == kFP32)
             hipLaunchKernelGGL(k_marg_partials_batch<float>, dim3(n_tiles), dim3(kLseThreads), 0, st, d_jobs,
@@ -199,7 +200,7 @@ hipError_t launch_marg_batch(int policy, const MargJob *d_jobs, int n_jobs, cons
                                d_tiles, d_part);
     }
     if (n_jobs > 0)
-        hipLaunchKernelGGL(k_marg_combine_batch, dim3(n_jobs), dim3(kLseThreads), 0, st, d_jobs, d_part);
+        hipLaunchKernelGGL(k_marg_combine_batch, dim3(n_jobs), dim3(kLseThreads), 0, st, d_jobs, d_part, d_out);
     return hipGetLastError();
 }
 

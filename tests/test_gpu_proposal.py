@@ -1,0 +1,155 @@
+"""Mixture proposal on the GPU vs the oracle: in-support masses, proposal
+draws and ln p - ln p_s, the weighted EM refit; and the distance-marginalised
+likelihood against adaptive quadrature."""
+import math
+
+import numpy as np
+import pytest
+
+import chirpgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2505_11655_amd as ile  # noqa: E402
+from tests import gpu_util as gu  # noqa: E402
+
+MEANS = [[6.0, 0.3, 0.01, 500.0, 0.5, 0.1, 3.0], [1.0, -0.5, -0.02, 2500.0, -0.9, 3.0, 0.2]]
+COVS = [np.diag([0.2, 0.1, 1e-4, 1e4, 0.1, 0.3, 0.2]), np.diag([0.5, 0.05, 4e-4, 3e5, 0.05, 1.0, 0.5])]
+COVS[0][0, 1] = COVS[0][1, 0] = 0.05
+COVS[1][4, 5] = COVS[1][5, 4] = 0.1
+
+
+def _job(policy, dist_marg=False):
+    rng = np.random.default_rng(40)
+    p = chirpgen.random_problem(rng, 5, ["H", "L"])
+    return ile.ile_prepare(gu.ctx(), ile.ProblemHost(p, precision=policy, dist_marg=dist_marg)), p
+
+
+@pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
+def test_proposal_mass_and_draws(orc, policy):
+    job, _ = _job(policy)
+    zseed, zround, m = 1234567, 2, 1 << 16
+    try:
+        ile.ile_set_proposal(job, ile.gmm_params([0.6, 0.4], MEANS, COVS), ile.gmm_opts(seed=zseed, rnd=zround,
+                                                                                       z_draws=m))
+        got = ile.ile_get_proposal(job)
+        prior = orc.make_prior()
+        g = orc.make_gmm([0.6, 0.4], MEANS, COVS, list(range(7)))
+        lz = []
+        for j in range(2):
+            z = orc.gmm_inbox_mass(prior, g, j, zseed, zround, m)
+            lz.append(math.log(max(z, 0.5 / m)))
+            assert abs(got.ln_Z[j] - lz[j]) <= 1e-12, (got.ln_Z[j], lz[j])
+        g = orc.make_gmm([0.6, 0.4], MEANS, COVS, list(range(7)), ln_Z=lz)
+        n, seed, rnd, first = 30011, 99, 1, 777
+        th = torch.empty((7, n), dtype=gu.torch_dtype(policy), device="cuda")
+        lr = torch.empty((n,), dtype=gu.torch_dtype(policy), device="cuda")
+        ile.ile_draw(job, seed, rnd, first, n, th, n, lr)
+        torch.cuda.synchronize()
+    finally:
+        ile.ile_job_release(job)
+    o, olr = orc.draw_gmm(prior, g, seed, rnd, first, n)
+    gth, glr = th.double().cpu().numpy(), lr.double().cpu().numpy()
+    if policy == ile.ILE_FP64:
+        assert np.allclose(gth, o, rtol=1e-12, atol=1e-13)
+        assert np.allclose(glr, olr, rtol=1e-10, atol=1e-10)
+    else:
+        assert np.allclose(gth, o.astype(np.float32), rtol=3e-7, atol=1e-9)
+        assert np.allclose(glr, olr.astype(np.float32), rtol=1e-6, atol=1e-5)
+    # a fair check of the density itself: E_{p_s}[p / p_s] = 1
+    r = np.exp(olr)
+    assert abs(r.mean() - 1) < 4 * r.std() / math.sqrt(n) + 2e-3
+
+
+def _weighted_samples(n, seed, policy):
+    """Prior samples with log-weights from a two-blob target (as input data)."""
+    rng = np.random.default_rng(seed)
+    th = chirpgen.prior_samples(rng, n)
+    c1 = np.array([2.0, 0.4, 0.01, 800.0, 0.3, 1.0, 0.5])
+    c2 = np.array([4.5, -0.3, -0.01, 1500.0, -0.5, 4.0, 2.5])
+    sd = np.array([0.4, 0.2, 0.005, 200.0, 0.2, 0.5, 0.4])
+    l1 = -0.5 * np.sum(((th - c1[:, None]) / sd[:, None]) ** 2, axis=0)
+    l2 = -0.5 * np.sum(((th - c2[:, None]) / sd[:, None]) ** 2, axis=0) + 0.3
+    lw = np.logaddexp(l1, l2)
+    th = th.astype(np.float64 if policy == ile.ILE_FP64 else np.float32)
+    lw = lw.astype(np.float32 if policy == ile.ILE_FP32 else np.float64)
+    return th, lw
+
+
+@pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
+def test_em_single_component(orc, policy):
+    """One component, one iteration after the first fit: weighted moments."""
+    th, lw = _weighted_samples(20000, 41, policy)
+    job, _ = _job(policy)
+    try:
+        p = ile.ile_adapt_proposal(job, th.shape[1], torch.from_numpy(th).cuda(), th.shape[1],
+                                   torch.from_numpy(lw).cuda(), ile.gmm_opts(n_comp=1, n_iter=1))
+    finally:
+        ile.ile_job_release(job)
+    w, m, c = orc.em_fit(th.astype(np.float64), lw.astype(np.float64), list(range(7)), n_iter=1, n_comp=1)
+    gm = np.array([[p.mean[0][a] for a in range(7)]])
+    gc = np.array([[[p.cov[0][a][b] for b in range(7)] for a in range(7)]])
+    assert abs(p.weight[0] - 1.0) < 1e-15
+    assert np.allclose(gm, m, rtol=1e-10, atol=1e-12)
+    assert np.allclose(gc, c, rtol=1e-8, atol=1e-14)
+
+
+@pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
+def test_em_mixture_matches_oracle(orc, policy):
+    """Eight components, first fit + 8 warm iterations, then 8 more (warm start)."""
+    th, lw = _weighted_samples(1 << 16, 42, policy)
+    job, _ = _job(policy)
+    try:
+        tt, ll = torch.from_numpy(th).cuda(), torch.from_numpy(lw).cuda()
+        p1 = ile.ile_adapt_proposal(job, th.shape[1], tt, th.shape[1], ll, ile.gmm_opts(n_comp=8, n_iter=8))
+        p2 = ile.ile_adapt_proposal(job, th.shape[1], tt, th.shape[1], ll, ile.gmm_opts(n_comp=8, n_iter=8))
+    finally:
+        ile.ile_job_release(job)
+    th64, lw64 = th.astype(np.float64), lw.astype(np.float64)
+    s1 = orc.em_fit(th64, lw64, list(range(7)), n_iter=8, n_comp=8)
+    s2 = orc.em_fit(th64, lw64, list(range(7)), state=s1, n_iter=8, n_comp=8)
+    for p, (w, m, c) in ((p1, s1), (p2, s2)):
+        gw = np.array([p.weight[j] for j in range(8)])
+        gm = np.array([[p.mean[j][a] for a in range(7)] for j in range(8)])
+        gc = np.array([[[p.cov[j][a][b] for b in range(7)] for a in range(7)] for j in range(8)])
+        assert np.allclose(gw, w, rtol=1e-7, atol=1e-10)
+        assert np.allclose(gm, m, rtol=1e-7, atol=1e-9)
+        assert np.allclose(gc, c, rtol=1e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
+def test_distance_marginalised_lnL(orc, recs_c1, policy):
+    """lnL with distance integrated by the FP64 table vs adaptive quadrature of
+    the same integral, on prior samples and on samples near the peak."""
+    prob = recs_c1
+    job = ile.ile_prepare(gu.ctx(), ile.ProblemHost(prob, precision=policy, dist_marg=True))
+    rng = np.random.default_rng(43)
+    th0 = np.array(prob.meta["theta_inj"])
+    thd = np.concatenate([chirpgen.prior_samples(rng, 300),
+                          chirpgen.box_samples(rng, 300, th0, [0.05, 0.05, 5e-4, 0, 0.1, 0.2, 0.2])], axis=1)
+    thd[3] = 100.0
+    th = thd.astype(np.float64 if policy == ile.ILE_FP64 else np.float32)
+    try:
+        L, _ = gu.gpu_eval(job, th, policy)
+    finally:
+        ile.ile_job_release(job)
+    _, T1, T2 = orc.lnL(prob, th.astype(np.float64), return_terms=True)
+    ref = np.array([orc.ln_dist_marg(a, b) for a, b in zip(T1, T2)])
+    d = np.abs(L - ref)
+    top = ref >= ref.max() - 50
+    print(f"dist-marg policy {policy}: max|d| all={d.max():.2e} near-peak={d[top].max():.2e} max lnL_D={ref.max():.1f}")
+    if policy == ile.ILE_FP64:
+        assert np.all(d <= 1e-6 * (1 + np.abs(ref)))
+    else:
+        assert np.all(d[top] <= 1e-3) and np.all(d <= 1e-3 + 1e-5 * np.abs(ref))
+
+
+@pytest.fixture(scope="module")
+def recs_c1():
+    recs = chirpgen.load_injections()
+    probs, _ = chirpgen.build_event(recs["c1"], ["H", "L"], 5, 30.0, 2.0, 20.0, noise_seed=13)
+    return probs[0]

@@ -1,0 +1,170 @@
+"""The continuous-batching server: every job's result is the same alone and in
+a mix; plain jobs equal the oracle on the same (reproduced) draws; admission by
+device footprint queues jobs under a small budget and rejects oversize ones;
+cancellation; adaptive jobs stop at the n_eff target or the round cap."""
+import time
+
+import numpy as np
+import pytest
+
+import chirpgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2505_11655_amd as ile  # noqa: E402
+from tests import gpu_util as gu  # noqa: E402
+
+FIELDS = ["ln_L", "ln_sigma", "n_eff", "n_ess", "max_lw", "argmax", "n", "n_nonfinite"]
+
+
+@pytest.fixture(scope="module")
+def pool():
+    """A small pool of events of every (modes, detectors) class."""
+    recs = chirpgen.load_injections()["pool"]
+    out = []
+    rng = np.random.default_rng(50)
+    for i, (n, dets) in enumerate([(5, ["H", "L"]), (9, ["H", "L", "V"]), (17, ["H", "L", "V"]),
+                                   (5, ["H", "L", "V"]), (9, ["H", "L"]), (17, ["L", "V"])]):
+        snr = float(np.exp(rng.uniform(np.log(10), np.log(40))))
+        probs, _ = chirpgen.build_event(recs[i], dets, n, float(rng.uniform(20, 40)), float(rng.uniform(1, 4)), snr,
+                                        noise_seed=100 + i)
+        out.append(probs[0])
+    return out
+
+
+def _specs(pool):
+    rng = np.random.default_rng(51)
+    specs = []
+    for i in range(14):
+        p = pool[i % len(pool)]
+        policy = [ile.ILE_FP32, ile.ILE_FP64, ile.ILE_FP32_CANCEL64][i % 3]
+        adaptive = i % 4 == 3
+        n = int(2 ** rng.uniform(14, 17))
+        specs.append((p, policy, adaptive, n, 1000 + i))
+    return specs
+
+
+def _submit(srv, spec):
+    p, policy, adaptive, n, seed = spec
+    ph = ile.ProblemHost(p, precision=policy)
+    jo = ile.job_opts(n_samples=n, adaptive=adaptive, round_samples=1 << 14, max_rounds=6, n_eff_target=300.0,
+                      seed=seed)
+    return ile.ile_server_submit(srv, ph, jo), ph
+
+
+def _res(r):
+    return {f: getattr(r.marg, f) for f in FIELDS} | {"status": r.status, "rounds": r.rounds, "samples": r.samples}
+
+
+def test_mixed_equals_alone(pool):
+    specs = _specs(pool)
+    srv = ile.ile_server_create(gu.ctx(), max_active=64, chunk_samples=1 << 15)
+    try:
+        ids = [_submit(srv, s)[0] for s in specs]
+        mixed = [_res(ile.ile_server_wait(srv, i, 120000)) for i in ids]
+    finally:
+        ile.ile_server_destroy(srv)
+    for k, s in enumerate(specs):
+        solo = ile.ile_server_create(gu.ctx(), max_active=1, chunk_samples=1 << 15)
+        try:
+            jid, _ = _submit(solo, s)
+            alone = _res(ile.ile_server_wait(solo, jid, 120000))
+        finally:
+            ile.ile_server_destroy(solo)
+        assert mixed[k]["status"] == 0 and alone["status"] == 0
+        for f in FIELDS + ["rounds", "samples"]:
+            a, b = mixed[k][f], alone[f]
+            assert a == b or (isinstance(a, float) and np.isnan(a) and np.isnan(b)), (k, f, a, b)
+
+
+@pytest.mark.parametrize("policy,tol", [(ile.ILE_FP64, 1e-10), (ile.ILE_FP32, 1e-4)])
+def test_plain_job_matches_oracle(orc, pool, policy, tol):
+    """The server's draws are reproduced by the oracle's generator (same key,
+    round 0, indices 0..n-1); the served ln L equals the oracle estimator."""
+    p = pool[1]
+    n, seed = 3 * (1 << 14) + 123, 777
+    srv = ile.ile_server_create(gu.ctx(), chunk_samples=1 << 14)
+    try:
+        ph = ile.ProblemHost(p, precision=policy)
+        jid = ile.ile_server_submit(srv, ph, ile.job_opts(n_samples=n, seed=seed))
+        r = ile.ile_server_wait(srv, jid, 60000)
+    finally:
+        ile.ile_server_destroy(srv)
+    th, _ = orc.draw_prior(orc.make_prior(), seed, 0, 0, n)
+    if policy != ile.ILE_FP64:
+        th = th.astype(np.float32).astype(np.float64)
+    o = orc.marginalize(orc.lnL(p, th))
+    assert r.status == 0 and r.marg.n == n
+    assert abs(r.marg.ln_L - o["ln_L"]) <= tol, (r.marg.ln_L, o["ln_L"])
+
+
+def test_budget_queueing_and_admission(pool):
+    p = pool[0]
+    ph = ile.ProblemHost(p, precision=ile.ILE_FP32)
+    tiny = ile.ile_server_create(gu.ctx(), hbm_budget_bytes=256 << 10, chunk_samples=1 << 15)
+    try:
+        with pytest.raises(ile.IleError) as e:
+            ile.ile_server_submit(tiny, ph, ile.job_opts(n_samples=1 << 16, seed=1))
+        assert e.value.status == -3
+    finally:
+        ile.ile_server_destroy(tiny)
+    srv = ile.ile_server_create(gu.ctx(), max_active=64, hbm_budget_bytes=3 << 20, chunk_samples=1 << 15)
+    try:
+        ids =[ile.ile_server_submit(srv, ph, ile.job_opts(n_samples=1 << 16, seed=10 + i)) for i in range(8)]
+        seen_queue = 0
+        for _ in range(200):
+            a, q, d = ile.ile_server_stats(srv)
+            seen_queue = max(seen_queue, q)
+            if d >= 8:
+                break
+            time.sleep(0.005)
+        res = [ile.ile_server_wait(srv, i, 60000) for i in ids]
+    finally:
+        ile.ile_server_destroy(srv)
+    assert all(r.status == 0 for r in res)
+    assert seen_queue > 0
+    admits = [r.t_admit_ns for r in res]
+    assert admits == sorted(admits)           # arrival order under memory pressure
+
+
+def test_cancel(pool):
+    p = pool[2]
+    ph = ile.ProblemHost(p, precision=ile.ILE_FP64)
+    srv = ile.ile_server_create(gu.ctx(), max_active=4, chunk_samples=1 << 14)
+    try:
+        big = ile.ile_server_submit(srv, ph, ile.job_opts(n_samples=1 << 26, seed=3))
+        small = ile.ile_server_submit(srv, ph, ile.job_opts(n_samples=1 << 14, seed=4))
+        time.sleep(0.05)
+        ile.ile_server_cancel(srv, big)
+        rb = ile.ile_server_wait(srv, big, 60000)
+        rs = ile.ile_server_wait(srv, small, 60000)
+    finally:
+        ile.ile_server_destroy(srv)
+    assert rb.status == -6 and rb.samples < (1 << 26)
+    assert rs.status == 0
+
+
+def test_adaptive_job(pool):
+    """Adaptive rounds: stops at n_eff >= target or at the round cap; the
+    estimate agrees with a long plain run within the combined errors."""
+    p = pool[0]
+    ph = ile.ProblemHost(p, precision=ile.ILE_FP32)
+    srv = ile.ile_server_create(gu.ctx())
+    try:
+        ja = ile.ile_server_submit(srv, ph, ile.job_opts(adaptive=True, round_samples=1 << 16, max_rounds=32,
+                                                         n_eff_target=1000.0, seed=5))
+        jp = ile.ile_server_submit(srv, ph, ile.job_opts(n_samples=1 << 24, seed=6))
+        ra = ile.ile_server_wait(srv, ja, 120000)
+        rp = ile.ile_server_wait(srv, jp, 120000)
+    finally:
+        ile.ile_server_destroy(srv)
+    assert ra.status == 0 and rp.status == 0
+    assert ra.rounds <= 32 and (ra.marg.n_eff >= 1000.0 or ra.rounds == 32)
+    sa = np.exp(ra.marg.ln_sigma - ra.marg.ln_L)
+    sp = np.exp(rp.marg.ln_sigma - rp.marg.ln_L)
+    print("adaptive", ra.rounds, ra.marg.n_eff, ra.marg.ln_L, "+-", sa, "plain", rp.marg.ln_L, "+-", sp)
+    assert abs(ra.marg.ln_L - rp.marg.ln_L) < 5 * np.hypot(sa, sp) + 0.05
