@@ -165,11 +165,13 @@ def cpu_baseline(probs, budget_s=15.0):
     import oracle
     threads = os.cpu_count() or 1
     rng = np.random.default_rng(5)
-    th = chirpgen.prior_samples(rng, 4096)
+    oracle.lnL(probs[0], chirpgen.prior_samples(rng, 4096), threads=threads)   # thread start-up
+    m = 1 << 17
+    th = chirpgen.prior_samples(rng, m)
     t0 = time.perf_counter()
     oracle.lnL(probs[0], th, threads=threads)
     dt = time.perf_counter() - t0
-    n = int(min(max(4096, budget_s / max(dt, 1e-6) * 4096), 1 << 22))
+    n = int(min(max(m, budget_s / max(dt, 1e-6) * m), 1 << 26))
     th = chirpgen.prior_samples(rng, n)
     t0 = time.perf_counter()
     lw = oracle.lnL(probs[1 % len(probs)], th, threads=threads)
@@ -192,6 +194,8 @@ def main():
     ap.add_argument("--serving-jobs", type=int, default=10000)
     ap.add_argument("--adaptive-jobs", type=int, default=500)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="counter probe: one 1 GiB device copy (known bytes) then one FP32 step")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the path shards by "
@@ -205,6 +209,15 @@ def main():
     n_per = 1 << a.log2n
     ctx = ile.ile_ctx_create(0, 0)
     stream = torch.cuda.current_stream()
+    if a.probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)                      # reference kernel: reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
+        r = run_policy(ile, torch, ctx, probs, ile.ILE_FP32, n_per, 1, 0, stream)
+        print(json.dumps({"probe": True, "samples": r["N"], "kernel_ms": r["kernel_ms"]}), flush=True)
+        return
     log("fp32 ...")
     r32 = run_policy(ile, torch, ctx, probs, ile.ILE_FP32, n_per, a.steps, a.warmup, stream)
     log(f"fp32 {r32}")

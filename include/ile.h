@@ -191,6 +191,9 @@ typedef struct {
     uint64_t seed;            /* key for the in-support mass draws */
     uint32_t round;           /* counter word for the same */
     int64_t z_draws;          /* in-support mass draws per component, default 65536 */
+    double temper_ess;        /* 0: EM on the weights w; f in (0,1]: EM on w^beta with beta
+                                 the largest of 2^(-k/4), k = 0..47, whose effective sample
+                                 size (sum w^beta)^2 / sum w^(2 beta) >= f * (finite samples) */
 } ile_gmm_opts;
 
 /* Install an explicit proposal (host parameters); the library factorises the

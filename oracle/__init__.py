@@ -381,8 +381,27 @@ def em_step(theta, lw, dims, weights, means, covs, **rng_kw):
     return new_w, new_m, new_c
 
 
-def em_fit(theta, lw, dims, state=None, n_iter=8, n_comp=8, **rng_kw):
-    """Warm-started EM: ``n_iter`` iterations from ``state`` (or the first fit)."""
+def temper_beta(lw, frac):
+    """Largest beta = 2^(-k/4), k = 0..47, with (sum w^beta)^2 / sum w^(2 beta)
+    >= frac * (finite samples), w = e^{lw - max lw}; frac <= 0 gives 1."""
+    if not frac > 0:
+        return 1.0
+    lw = np.asarray(lw, dtype=np.float64)
+    fin = np.isfinite(lw)
+    x = lw[fin] - np.max(lw[fin])
+    target = frac * fin.sum()
+    for k in range(48):
+        b = 2.0 ** (-k / 4.0)
+        w = np.exp(b * x)
+        if w.sum() ** 2 / (w * w).sum() >= target:
+            return b
+    return 2.0 ** (-47 / 4.0)
+
+
+def em_fit(theta, lw, dims, state=None, n_iter=8, n_comp=8, temper_ess=0.0, **rng_kw):
+    """Warm-started EM: ``n_iter`` iterations from ``state`` (or the first fit),
+    on the tempered log-weights beta * lw (beta from ``temper_beta``)."""
+    lw = np.asarray(lw, dtype=np.float64) * temper_beta(lw, temper_ess)
     if state is None:
         state = em_init(theta, lw, dims, n_comp=n_comp, **rng_kw)
     w, m, c = state

@@ -70,7 +70,8 @@ class ile_gmm_params(C.Structure):
 
 class ile_gmm_opts(C.Structure):
     _fields_ = [("n_comp", C.c_int32), ("n_iter", C.c_int32), ("eps_def", C.c_double),
-                ("seed", C.c_uint64), ("round", C.c_uint32), ("z_draws", C.c_int64)]
+                ("seed", C.c_uint64), ("round", C.c_uint32), ("z_draws", C.c_int64),
+                ("temper_ess", C.c_double)]
 
 
 class ile_server_opts(C.Structure):
@@ -274,8 +275,8 @@ def gmm_params(weights, means, covs, eps_def=0.05):
     return p
 
 
-def gmm_opts(n_comp=8, n_iter=8, eps_def=0.05, seed=0x243F6A8885A308D3, rnd=0, z_draws=65536):
-    return ile_gmm_opts(n_comp, n_iter, eps_def, seed, rnd, z_draws)
+def gmm_opts(n_comp=8, n_iter=8, eps_def=0.05, seed=0x243F6A8885A308D3, rnd=0, z_draws=65536, temper_ess=0.0):
+    return ile_gmm_opts(n_comp, n_iter, eps_def, seed, rnd, z_draws, temper_ess)
 
 
 def ile_set_proposal(job, params, opts=None, stream=None):

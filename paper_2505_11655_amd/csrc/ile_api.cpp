@@ -91,7 +91,7 @@ void eval_geometry(const ile_job *job, int64_t n, size_t *lds, int64_t *tile, in
     // stage the window in LDS only when each block gets enough samples to pay for it
     if (job_lds_ok(job) && n >= (int64_t)2 * cus * 16384) {
         *lds = win;
-        *block = 512;
+        *block = lds_block_threads(job->policy);
         *tile = std::max<int64_t>(16384, (n + 2 * cus - 1) / (2 * cus));
     } else {
         *lds = 0;
@@ -436,7 +436,13 @@ extern "C" ile_status ile_prepare(ile_ctx *ctx, const ile_problem *P, ile_job **
         ej.D[k][3] = f * 0.5 * (d[1] + d[3]);
         ej.D[k][4] = f * 0.5 * (d[2] + d[6]);
         ej.D[k][5] = f * 0.5 * (d[5] + d[7]);
+        for (int c = 0; c < 3; c++) ej.xcf[k][c] = (float)ej.xc[k][c];
+        for (int c = 0; c < 6; c++) ej.Df[k][c] = (float)ej.D[k][c];
     }
+    ej.gmstf = (float)ej.gmst;
+    ej.tau0f = (float)ej.tau0;
+    ej.inv_dtf = (float)ej.inv_dt;
+    ej.d_reff = (float)ej.d_ref;
     if (job->dist_marg) {
         if ((s = ctx_dist_table(ctx, job->pr, &ej.dt, nullptr)) != ILE_OK) return cleanup(s);
     }
@@ -569,7 +575,7 @@ ile_status eval_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, hipStre
         const auto &key = g.first;
         hipError_t e = launch_eval(std::get<0>(key), std::get<1>(key), std::get<2>(key), std::get<3>(key) != 0,
                                    lds ? win : 0, (const EvalJob *)dj, (const Tile *)dt, (int)tiles.size(), ej[0],
-                                   tile, lds ? 512 : 256, st);
+                                   tile, lds ? lds_block_threads(std::get<2>(key)) : 256, st);
         if (e != hipSuccess) return dev_fail(ctx, e, "batched eval launch");
         if ((s = batch_done(ctx, slot, st)) != ILE_OK) return s;
     }
@@ -855,7 +861,9 @@ ile_status job_adapt(ile_job *job, int64_t n, const void *theta, int64_t ld, con
     const int n_iter = (o && o->n_iter > 0) ? o->n_iter : 8;
     const double eps = (o && o->eps_def >= 0 && o->eps_def < 1) ? o->eps_def : 0.05;
     if (n_comp > kMaxComp) return set_err(ILE_E_INVALID, "n_comp must be 1..16");
-    hipError_t e;
+    const double temper = (o && o->temper_ess > 0) ? std::min(o->temper_ess, 1.0) : 0.0;
+    hipError_t e = launch_em_prepare(job->policy, lw, n, job->d_em, job->em_cap, temper, st);
+    if (e != hipSuccess) return dev_fail(ctx, e, "EM weights");
     if (!job->has_prop) {
         GmmDev &g = *job->h_gmm;
         std::memset(&g, 0, sizeof g);

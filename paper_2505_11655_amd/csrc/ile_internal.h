@@ -13,6 +13,10 @@ namespace ile {
 // ------------------------------------------------------------------ policies
 enum Policy : int { kFP64 = 0, kFP32 = 1, kMixed = 2 };
 
+// Threads per block of the LDS-staged likelihood kernel: one window per CU,
+// as many waves as the policy's register use allows without spilling.
+constexpr int lds_block_threads(int policy) { return policy == kFP32 ? 1024 : 512; }
+
 // ----------------------------------------------------------------- mode sets
 // Compiled harmonic sets.  A job's mode list is placed into the smallest set
 // that contains it (absent slots get zero Q, U and V).
@@ -173,6 +177,10 @@ struct EvalJob {
     double tau0, inv_dt, gmst, d_ref;
     double xc[3][3];      // detector position / c (seconds)
     double D[3][6];       // response tensor (xx, yy, zz, xy, xz, yz)
+    // FP32 copies of the same constants for the FP32 parts of the policies
+    float xcf[3][3];
+    float Df[3][6];
+    float gmstf, tau0f, inv_dtf, d_reff;
     int n_time;
     int pad_;
     const void *theta;
@@ -265,6 +273,9 @@ hipError_t launch_gmm_factor(GmmDev *d_gmm, hipStream_t st);
 hipError_t launch_gmm_inbox(GmmDev *d_gmm, PriorDev pr, uint64_t seed, uint32_t round, int64_t m,
                             uint32_t *d_count, hipStream_t st);
 hipError_t launch_gmm_setz(GmmDev *d_gmm, const uint32_t *d_count, int64_t m, hipStream_t st);
+// max lw and the tempering exponent of this sample set (must precede em_top/em_iter)
+hipError_t launch_em_prepare(int policy, const void *lw, int64_t n, double *d_work, size_t work_bytes,
+                             double temper_frac, hipStream_t st);
 hipError_t launch_em_top(int policy, const void *theta, int64_t ld, const void *lw, int64_t n,
                          GmmDev *d_gmm, int n_comp, double *d_work, size_t work_bytes,
                          PriorDev pr, hipStream_t st);

@@ -241,6 +241,7 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
         o.seed = r->jo.seed ^ 0x9E3779B97F4A7C15ull;
         o.round = (uint32_t)r->rounds;
         o.z_draws = 65536;
+        o.temper_ess = 1.0 / 16.0;
         if (job_adapt(r->job, r->chunk, r->d_theta, r->chunk, r->d_lw, &o, st) != ILE_OK) return false;
     }
     return true;

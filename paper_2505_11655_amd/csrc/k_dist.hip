@@ -3,18 +3,21 @@
 // and the distance-marginalised value is
 //   L_D(T1, T2) = int p(D) exp(s T1 - s^2 T2 / 4) dD,   p(D) = 3 D^2 / (Dmax^3 - Dmin^3).
 // In v = ln s this is C int exp(-3 v + E(e^v)) dv, C = 3 D_ref^3 / (Dmax^3 - Dmin^3),
-// E(s) = s T1 - s^2 T2 / 4.  The table stores the smooth residual
-//   r = ln L_D - E_max,   E_max = E(clamp(2 T1 / T2, s_min, s_max)),
-// on nodes (u, b): a = T1 / sqrt(T2) = a_scale sinh(u), b = ln T2.  Each node is
-// one FP64 composite Gauss-Legendre quadrature with breakpoints placed at
-// geometric multiples of the local width around the maximum of the integrand.
+// E(s) = s T1 - s^2 T2 / 4.  The table stores the residual
+//   r = ln L_D - a^2,   a = T1 / sqrt(T2)   (a^2 = T1^2/T2 = max over all s of E),
+// which is analytic in (T1, T2); a reference clamped to [s_min, s_max] would
+// have a curvature jump where the best scale crosses a bound.  Nodes (u, b):
+// a = a_scale sinh(u), b = ln T2.  Each node is one FP64 composite
+// Gauss-Legendre quadrature (integrand scaled by its maximum over the range)
+// with breakpoints at geometric multiples of the local width around the
+// maximum of the integrand.
 #include "ile_internal.h"
 
 namespace ile {
 
 namespace {
 
-constexpr int kNu = 1024, kNb = 512;
+constexpr int kNu = 2048, kNb = 2048;
 constexpr double kAMax = 200.0, kAScale = 1.0;
 constexpr double kB0 = -13.815510557964274;   // ln 1e-6
 constexpr double kB1 = 23.025850929940457;    // ln 1e10
@@ -83,7 +86,7 @@ __global__ void __launch_bounds__(256) k_dist_table(double *tab, double s_min, d
             }
         }
     }
-    tab[idx] = lnC + log(acc);
+    tab[idx] = lnC + log(acc) + Emax - T1 * T1 / T2;
 }
 
 }  // namespace

@@ -45,9 +45,11 @@ __device__ __forceinline__ double wrapd(double d, double P) {
 }
 
 // Work buffer (doubles):
-//   [0] max lw   [1] index of the max   [8 .. 8+16*8) old means
-//   [256 ..) per-component offsets m_j (16*8)   [512 ..) partials
-constexpr int kWMax = 0, kWOldMean = 8, kWOff = 256, kWPart = 512;
+//   [0] max lw   [1] index of the max   [2] tempering exponent beta
+//   [8 .. 8+16*8) old means   [256 ..) per-component offsets m_j (16*8)
+//   [512 ..) partials
+constexpr int kWMax = 0, kWBeta = 2, kWOldMean = 8, kWOff = 256, kWPart = 512;
+constexpr int kBetaGrid = 48;   // beta_k = 2^(-k/4)
 
 __device__ void factor_one(GmmDev &g, int j) {
     const int d = g.n_dim;
@@ -193,8 +195,64 @@ __device__ void block_sum(double (&v)[NV], double *out) {
     }
 }
 
-__device__ __forceinline__ double sample_weight(double lwv, double mlw) {
-    return (lwv > -INFINITY && lwv < INFINITY) ? exp(lwv - mlw) : 0.0;
+__device__ __forceinline__ double sample_weight(double lwv, double mlw, double beta) {
+    return (lwv > -INFINITY && lwv < INFINITY) ? exp(beta * (lwv - mlw)) : 0.0;
+}
+
+// Tempering exponent: the largest beta_k = 2^(-k/4) whose tempered weights
+// have (sum w^beta)^2 / sum w^(2 beta) >= frac * (finite samples); frac <= 0
+// gives beta = 1.  One block; each grid value is a fixed-order block sum.
+template <class TL>
+__global__ void __launch_bounds__(kEmThreads)
+    k_em_beta(const TL *__restrict__ lw, int64_t n, double frac, double *work) {
+    __shared__ double r1[kEmThreads], r2[kEmThreads];
+    __shared__ double cnt_s;
+    const double mlw = work[kWMax];
+    if (!(frac > 0.0)) {
+        if (threadIdx.x == 0) work[kWBeta] = 1.0;
+        return;
+    }
+    double c = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kEmThreads) {
+        const double v = (double)lw[i];
+        c += (v > -INFINITY && v < INFINITY) ? 1.0 : 0.0;
+    }
+    r1[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = kEmThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) r1[threadIdx.x] += r1[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cnt_s = r1[0];
+    __syncthreads();
+    const double target = frac * cnt_s;
+    double beta = exp2(-(double)(kBetaGrid - 1) / 4.0);
+    for (int k = 0; k < kBetaGrid; k++) {
+        const double b = exp2(-(double)k / 4.0);
+        double s1 = 0.0, s2 = 0.0;
+        for (int64_t i = threadIdx.x; i < n; i += kEmThreads) {
+            const double e = sample_weight((double)lw[i], mlw, b);
+            s1 += e;
+            s2 += e * e;
+        }
+        r1[threadIdx.x] = s1;
+        r2[threadIdx.x] = s2;
+        __syncthreads();
+        for (int w = kEmThreads / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                r1[threadIdx.x] += r1[threadIdx.x + w];
+                r2[threadIdx.x] += r2[threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        const bool ok = r1[0] * r1[0] / r2[0] >= target;
+        __syncthreads();
+        if (ok) {
+            beta = b;
+            break;
+        }
+    }
+    if (threadIdx.x == 0) work[kWBeta] = beta;
 }
 
 // first fit: weighted moments of the differences about the best sample
@@ -203,12 +261,12 @@ __global__ void __launch_bounds__(kEmThreads)
     k_em_init_part(const TT *__restrict__ th, int64_t ld, const TL *__restrict__ lw, int64_t n, const GmmDev *g,
                    PriorDev pr, double *work) {
     const int d = g->n_dim;
-    const double mlw = work[kWMax];
+    const double mlw = work[kWMax], beta = work[kWBeta];
     double acc[36];
     for (int c = 0; c < 36; c++) acc[c] = 0.0;
     const int64_t b0 = (int64_t)blockIdx.x * kEmTile, b1 = min(b0 + kEmTile, n);
     for (int64_t i = b0 + threadIdx.x; i < b1; i += kEmThreads) {
-        const double w = sample_weight((double)lw[i], mlw);
+        const double w = sample_weight((double)lw[i], mlw, beta);
         double x[7];
         for (int a = 0; a < d; a++) {
             const int col = g->dims[a];
@@ -257,9 +315,9 @@ __global__ void __launch_bounds__(kEmThreads)
     k_em_resp(const TT *__restrict__ th, int64_t ld, const TL *__restrict__ lw, int64_t n, const GmmDev *g,
               double *work, double *R) {
     const int d = g->n_dim, nc = g->n_comp;
-    const double mlw = work[kWMax];
+    const double mlw = work[kWMax], beta = work[kWBeta];
     for (int64_t i = (int64_t)blockIdx.x * kEmThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kEmThreads) {
-        const double w = sample_weight((double)lw[i], mlw);
+        const double w = sample_weight((double)lw[i], mlw, beta);
         double x[7];
         for (int a = 0; a < d; a++) x[a] = load_col(th, ld, g->dims[a], i);
         double lr[kMaxComp];
@@ -420,6 +478,16 @@ hipError_t launch_gmm_factor(GmmDev *d_gmm, hipStream_t st) {
         }                                        \
     } while (0)
 
+hipError_t launch_em_prepare(int policy, const void *lw, int64_t n, double *d_work, size_t work_bytes,
+                             double temper_frac, hipStream_t st) {
+    if (work_bytes < em_work_bytes(n)) return hipErrorInvalidValue;
+    ILE_DISPATCH_TL(policy, {
+        hipLaunchKernelGGL((k_em_max<TL>), dim3(1), dim3(kEmThreads), 0, st, (const TL *)lw, n, d_work);
+        hipLaunchKernelGGL((k_em_beta<TL>), dim3(1), dim3(kEmThreads), 0, st, (const TL *)lw, n, temper_frac, d_work);
+    });
+    return hipGetLastError();
+}
+
 hipError_t launch_em_top(int policy, const void *theta, int64_t ld, const void *lw, int64_t n, GmmDev *d_gmm,
                          int n_comp, double *d_work, size_t work_bytes, PriorDev pr, hipStream_t st) {
     if (work_bytes < em_work_bytes(n)) return hipErrorInvalidValue;
@@ -443,7 +511,6 @@ hipError_t launch_em_iter(int policy, const void *theta, int64_t ld, const void 
     const int64_t rb = (n + kEmThreads - 1) / kEmThreads;
     const int rblk = (int)(rb < 4096 ? rb : 4096);
     ILE_DISPATCH_TL(policy, {
-        hipLaunchKernelGGL((k_em_max<TL>), dim3(1), dim3(kEmThreads), 0, st, (const TL *)lw, n, d_work);
         hipLaunchKernelGGL((k_em_resp<TT, TL>), dim3(rblk), dim3(kEmThreads), 0, st, (const TT *)theta, ld,
                            (const TL *)lw, n, d_gmm, d_work, R);
         hipLaunchKernelGGL((k_em_stat1<TT>), dim3(nblk, kMaxComp), dim3(kEmThreads), 0, st, (const TT *)theta, ld,

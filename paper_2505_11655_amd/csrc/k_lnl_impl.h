@@ -71,6 +71,20 @@ __device__ __forceinline__ double dfloor(double x) { return floor(x); }
 __device__ __forceinline__ float dsqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
 
+// A job constant in the requested precision (FP32 copies are made on the host).
+template <class T>
+__device__ __forceinline__ T pick(double d, float f) {
+    if constexpr (std::is_same<T, float>::value)
+        return f;
+    else
+        return d;
+}
+
+// Compiler-only ordering point (emits no instruction): memory operations are
+// not moved across it, which bounds how many loads the scheduler keeps in
+// flight (and in registers) at once.
+__device__ __forceinline__ void fence() { asm volatile("" ::: "memory"); }
+
 template <int B, int E, class F>
 __device__ __forceinline__ void static_for(F &&f) {
     if constexpr (B < E) {
@@ -80,8 +94,7 @@ __device__ __forceinline__ void static_for(F &&f) {
 }
 
 // Distance-marginalised lnL from the residual table (bicubic Lagrange),
-// ln L_D = r(a, b) + E_max, a = T1/sqrt(T2), b = ln T2, E_max the exponent
-// at the clamped best scale.  Out of table: -inf.
+// ln L_D = r(a, b) + a^2, a = T1/sqrt(T2), b = ln T2.  Out of table: -inf.
 __device__ __forceinline__ double dist_lookup(const DistTable &tb, double T1, double T2) {
     if (!(T2 > 0.0)) return -INFINITY;
     double b = log(T2);
@@ -105,8 +118,7 @@ __device__ __forceinline__ double dist_lookup(const DistTable &tb, double T1, do
         double acc = wu[0] * row[0] + wu[1] * row[1] + wu[2] * row[2] + wu[3] * row[3];
         r += wb[jb] * acc;
     }
-    double sc = fmin(fmax(2.0 * T1 / T2, tb.s_min), tb.s_max);
-    return r + sc * T1 - sc * sc * T2 * 0.25;
+    return r + a * a;
 }
 
 template <int S, int K, int POL, bool LDS, bool DM>
@@ -123,7 +135,8 @@ struct LnlKernel {
     static constexpr int LM = MS::lmax;
     static constexpr int NE = 2 * LM + 1;  // e^{i j phi}, j = 0..2 lmax
 
-    __device__ static void run(const EvalJob &J, const int64_t begin, const int64_t end, cpx<TA> *smem) {
+    __device__ __forceinline__ static void run(const EvalJob &J, const int64_t begin, const int64_t end,
+                                               cpx<TA> *smem) {
         const int T = J.n_time;
         const cpx<TA> *__restrict__ Qg = (const cpx<TA> *)J.Q;
         if constexpr (LDS) {
@@ -135,8 +148,13 @@ struct LnlKernel {
             __syncthreads();
         }
         const cpx<TA> *__restrict__ Qb = LDS ? smem : Qg;
-        const cpx<TA> *__restrict__ Ut = (const cpx<TA> *)J.Ut;
-        const cpx<TA> *__restrict__ Vt = (const cpx<TA> *)J.Vt;
+        // The pair tables are read-only for the whole launch and every lane of
+        // a block reads the same entry: reading them through the constant
+        // address space lets them come through the scalar cache into SGPRs
+        // (operands of the FMAs) instead of per-sample vector loads.
+        typedef __attribute__((address_space(4))) const cpx<TA> ccpx;
+        ccpx *Ut = (ccpx *)J.Ut;
+        ccpx *Vt = (ccpx *)J.Vt;
         const TT *__restrict__ th = (const TT *)J.theta;
         const TT *__restrict__ lr = (const TT *)J.lnpmps;
         TO *__restrict__ outL = (TO *)J.lnL;
@@ -144,6 +162,10 @@ struct LnlKernel {
         const int64_t ld = J.ld;
 
         for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+            // Empty statement (emits no instruction): the table pointers look
+            // loop-variant, so the scalar loads stream per sample instead of
+            // being hoisted into more SGPRs than exist (which spills them).
+            asm volatile("" : "+s"(Ut), "+s"(Vt));
             const TT al = th[i], de = th[ld + i], tt = th[2 * ld + i], DD = th[3 * ld + i];
             const TT ci = th[4 * ld + i], ph = th[5 * ld + i], ps = th[6 * ld + i];
             bool ok = (DM || DD > (TT)0) && (ci >= (TT)-1 && ci <= (TT)1);
@@ -151,7 +173,7 @@ struct LnlKernel {
             // ---- sky direction, polarisation basis, delays
             TS sd, cd, sh, ch;
             dsincos((TS)de, &sd, &cd);
-            dsincos((TS)al - (TS)J.gmst, &sh, &ch);
+            dsincos((TS)al - pick<TS>(J.gmst, J.gmstf), &sh, &ch);
             const TS n0 = cd * ch, n1 = cd * sh, n2 = sd;
             const TG ea0 = (TG)(-sh), ea1 = (TG)ch;
             const TG ed0 = (TG)(-sd * ch), ed1 = (TG)(-sd * sh), ed2 = (TG)cd;
@@ -161,8 +183,9 @@ struct LnlKernel {
             TA tau[K];
 #pragma unroll
             for (int k = 0; k < K; k++) {
-                const TG dxx = (TG)J.D[k][0], dyy = (TG)J.D[k][1], dzz = (TG)J.D[k][2];
-                const TG dxy = (TG)J.D[k][3], dxz = (TG)J.D[k][4], dyz = (TG)J.D[k][5];
+                const TG dxx = pick<TG>(J.D[k][0], J.Df[k][0]), dyy = pick<TG>(J.D[k][1], J.Df[k][1]);
+                const TG dzz = pick<TG>(J.D[k][2], J.Df[k][2]), dxy = pick<TG>(J.D[k][3], J.Df[k][3]);
+                const TG dxz = pick<TG>(J.D[k][4], J.Df[k][4]), dyz = pick<TG>(J.D[k][5], J.Df[k][5]);
                 const TG A = dxx * ea0 * ea0 + dyy * ea1 * ea1 + (TG)2 * dxy * ea0 * ea1;
                 const TG B = dxx * ed0 * ed0 + dyy * ed1 * ed1 + dzz * ed2 * ed2 +
                              (TG)2 * (dxy * ed0 * ed1 + dxz * ed0 * ed2 + dyz * ed1 * ed2);
@@ -171,7 +194,8 @@ struct LnlKernel {
                 const TG Gr = A - B, Gi = (TG)-2 * C;
                 Fr[k] = c2p * Gr + s2p * Gi;
                 Fi[k] = c2p * Gi - s2p * Gr;
-                const TS dly = (TS)J.xc[k][0] * n0 + (TS)J.xc[k][1] * n1 + (TS)J.xc[k][2] * n2;
+                const TS dly = pick<TS>(J.xc[k][0], J.xcf[k][0]) * n0 + pick<TS>(J.xc[k][1], J.xcf[k][1]) * n1 +
+                               pick<TS>(J.xc[k][2], J.xcf[k][2]) * n2;
                 tau[k] = (TA)((TS)tt - dly);
             }
 
@@ -213,7 +237,8 @@ struct LnlKernel {
             TA T1 = (TA)0;
 #pragma unroll
             for (int k = 0; k < K; k++) {
-                const TA u = (tau[k] - (TA)J.tau0) * (TA)J.inv_dt;
+                fence();
+                const TA u = (tau[k] - pick<TA>(J.tau0, J.tau0f)) * pick<TA>(J.inv_dt, J.inv_dtf);
                 const TA fl = dfloor(u);
                 ok = ok && (fl >= (TA)1) && (fl <= (TA)(T - 3));
                 const TA flc = fmin(fmax(fl, (TA)1), (TA)(T - 3));
@@ -252,6 +277,7 @@ struct LnlKernel {
             constexpr PairTable pt = MS::pt;
             static_for<0, NE>([&](auto G_) {
                 constexpr int g = decltype(G_)::value;
+                fence();
                 TA Ar[K], Ai[K];
 #pragma unroll
                 for (int k = 0; k < K; k++) {
@@ -264,9 +290,8 @@ struct LnlKernel {
                     const TA py = (TA)y[pt.a[p]] * (TA)y[pt.b[p]];
 #pragma unroll
                     for (int k = 0; k < K; k++) {
-                        const cpx<TA> cu = Ut[j * K + k];
-                        Ar[k] += py * cu.re;
-                        if constexpr (g > 0) Ai[k] += py * cu.im;
+                        Ar[k] += py * Ut[j * K + k].re;
+                        if constexpr (g > 0) Ai[k] += py * Ut[j * K + k].im;
                     }
                 });
 #pragma unroll
@@ -279,6 +304,7 @@ struct LnlKernel {
             });
             static_for<0, 4 * LM + 1>([&](auto G_) {
                 constexpr int g = decltype(G_)::value;
+                fence();
                 constexpr int sm = g - 2 * LM;
                 if constexpr (pt.v_start[g + 1] > pt.v_start[g]) {
                     TA Br[K], Bi[K];
@@ -293,9 +319,8 @@ struct LnlKernel {
                         const TA py = (TA)y[pt.a[p]] * (TA)y[pt.b[p]];
 #pragma unroll
                         for (int k = 0; k < K; k++) {
-                            const cpx<TA> cv = Vt[j * K + k];
-                            Br[k] += py * cv.re;
-                            Bi[k] += py * cv.im;
+                            Br[k] += py * Vt[j * K + k].re;
+                            Bi[k] += py * Vt[j * K + k].im;
                         }
                     });
                     // e^{-i sm phi}
@@ -320,7 +345,7 @@ struct LnlKernel {
             if constexpr (DM) {
                 lnL = (TA)dist_lookup(J.dt, (double)T1, (double)T2);
             } else {
-                const TA s = (TA)J.d_ref / (TA)DD;
+                const TA s = pick<TA>(J.d_ref, J.d_reff) / (TA)DD;
                 lnL = s * T1 - s * s * T2 * (TA)0.25;
             }
             TO outv = ok ? (TO)lnL : (TO)-INFINITY;
@@ -330,8 +355,16 @@ struct LnlKernel {
     }
 };
 
+// Minimum waves per SIMD asked of the register allocator: two, except for the
+// 17/21-mode sets with FP64 contractions, whose live state does not fit in
+// 256 VGPRs without spilling.
+template <int S, int POL>
+constexpr int lnl_min_waves() {
+    return (S >= 2 && POL != kFP32) ? 1 : 2;
+}
+
 template <int S, int K, int POL, bool LDS, bool DM>
-__global__ void __launch_bounds__(LDS ? 512 : 256)
+__global__ void __launch_bounds__(LDS ? lds_block_threads(POL) : 256, (lnl_min_waves<S, POL>()))
     k_lnl(const EvalJob *__restrict__ jobs, const Tile *__restrict__ tiles, const EvalJob single,
           const int64_t tile) {
     extern __shared__ __align__(16) char ile_smem[];
@@ -358,7 +391,7 @@ hipError_t launch_eval_sp(int kdet, bool dm, size_t lds_bytes, const EvalJob *jo
                           const EvalJob &single, int64_t tile, int nthreads, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
     const bool lds = lds_bytes > 0;
-    if (nthreads <= 0 || nthreads > (lds ? 512 : 256) || nthreads % 64) return hipErrorInvalidValue;
+    if (nthreads <= 0 || nthreads > (lds ? lds_block_threads(POL) : 256) || nthreads % 64) return hipErrorInvalidValue;
     if (dm && POL == kMixed) return hipErrorInvalidValue;
     dim3 grid(n_tiles), block(nthreads);
     auto go = [&](auto KK, auto LL, auto DD) -> hipError_t {

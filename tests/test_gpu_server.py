@@ -81,10 +81,12 @@ def test_mixed_equals_alone(pool):
             assert a == b or (isinstance(a, float) and np.isnan(a) and np.isnan(b)), (k, f, a, b)
 
 
-@pytest.mark.parametrize("policy,tol", [(ile.ILE_FP64, 1e-10), (ile.ILE_FP32, 1e-4)])
+@pytest.mark.parametrize("policy,tol", [(ile.ILE_FP64, 1e-10), (ile.ILE_FP32_CANCEL64, 1e-4), (ile.ILE_FP32, 1e-3)])
 def test_plain_job_matches_oracle(orc, pool, policy, tol):
     """The server's draws are reproduced by the oracle's generator (same key,
-    round 0, indices 0..n-1); the served ln L equals the oracle estimator."""
+    round 0, indices 0..n-1); the served ln L equals the oracle estimator:
+    1e-10 in FP64, 1e-4 with the FP64 cancellation terms, 1e-3 in plain FP32
+    (the pool's sources reach SNR 40, where FP32 rounding is ~eps rho^2)."""
     p = pool[1]
     n, seed = 3 * (1 << 14) + 123, 777
     srv = ile.ile_server_create(gu.ctx(), chunk_samples=1 << 14)
@@ -148,10 +150,15 @@ def test_cancel(pool):
     assert rs.status == 0
 
 
-def test_adaptive_job(pool):
+def test_adaptive_job():
     """Adaptive rounds: stops at n_eff >= target or at the round cap; the
-    estimate agrees with a long plain run within the combined errors."""
-    p = pool[0]
+    estimate agrees with a long plain prior run within the combined errors.
+    The source is quiet (SNR 10) so that the plain run is a valid reference
+    (its own relative error is checked first); a loud source's posterior is
+    too small a fraction of the prior for 2^24 prior draws."""
+    rec = chirpgen.load_injections()["pool"][7]
+    probs, _ = chirpgen.build_event(rec, ["H", "L"], 5, 25.0, 1.5, 10.0, noise_seed=77)
+    p = probs[0]
     ph = ile.ProblemHost(p, precision=ile.ILE_FP32)
     srv = ile.ile_server_create(gu.ctx())
     try:
@@ -166,5 +173,7 @@ def test_adaptive_job(pool):
     assert ra.rounds <= 32 and (ra.marg.n_eff >= 1000.0 or ra.rounds == 32)
     sa = np.exp(ra.marg.ln_sigma - ra.marg.ln_L)
     sp = np.exp(rp.marg.ln_sigma - rp.marg.ln_L)
-    print("adaptive", ra.rounds, ra.marg.n_eff, ra.marg.ln_L, "+-", sa, "plain", rp.marg.ln_L, "+-", sp)
+    print("adaptive", ra.rounds, ra.marg.n_eff, ra.marg.ln_L, "+-", sa, "plain", rp.marg.ln_L, "+-", sp,
+          "plain n_eff", rp.marg.n_eff)
+    assert sp < 0.2, "reference run not converged"
     assert abs(ra.marg.ln_L - rp.marg.ln_L) < 5 * np.hypot(sa, sp) + 0.05

@@ -421,6 +421,23 @@ def test_P13_component_logpdf_matches_scipy(orc):
         assert abs(orc.gmm_comp_logpdf(prior, g, 0, th) - ref) <= 1e-10 * (1 + abs(ref))
 
 
+def test_temper_beta_gaussian_closed_form(orc):
+    """For log-weights ~ N(0, s^2), (sum w^b)^2 / sum w^(2b) / N -> e^{-b^2 s^2};
+    the rule picks the largest grid value 2^(-k/4) meeting the target."""
+    rng = np.random.default_rng(17)
+    s = 10.0
+    lw = rng.normal(0.0, s, 1 << 20)
+    frac = 1.0 / 16.0
+    b = orc.temper_beta(lw, frac)
+    bstar = math.sqrt(math.log(1.0 / frac)) / s
+    grid = [2.0 ** (-k / 4.0) for k in range(48)]
+    expect = max(g for g in grid if g <= bstar)
+    assert b == expect
+    assert orc.temper_beta(lw, 0.0) == 1.0
+    # all weights equal: beta = 1 already has full ESS
+    assert orc.temper_beta(np.zeros(100), 0.5) == 1.0
+
+
 def test_P13_periodic_wrap_logpdf(orc):
     """Periodic columns use the wrapped difference: a mean near 2 pi and a
     point near 0 are close."""
