@@ -110,31 +110,101 @@ ile_status ctx_check(ile_ctx *ctx) {
     return ILE_OK;
 }
 
+// Power-of-two size class (at least 4 KiB) of a request.
+static size_t size_class(size_t bytes) {
+    size_t c = 4096;
+    while (c < bytes) c <<= 1;
+    return c;
+}
+
+// Return every cached buffer to the runtime (caller holds ctx->mu).
+static void pool_trim_locked(ile_ctx *ctx) {
+    for (auto &kv : ctx->dev_pool)
+        for (void *q : kv.second) {
+            (void)hipFree(q);
+            ctx->used -= kv.first;
+        }
+    ctx->dev_pool.clear();
+    ctx->pool_cached = 0;
+}
+
+// Device allocation through the context's pool.  The budget counts a buffer
+// from its first allocation until the pool is trimmed (cached buffers stay
+// counted, and are trimmed when a new class would not fit).
 ile_status ctx_alloc(ile_ctx *ctx, void **p, size_t bytes, const char *what) {
     *p = nullptr;
     if (bytes == 0) return ILE_OK;
+    const size_t cls = size_class(bytes);
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
-        if (ctx->budget && ctx->used + bytes > ctx->budget)
+        auto it = ctx->dev_pool.find(cls);
+        if (it != ctx->dev_pool.end() && !it->second.empty()) {
+            *p = it->second.back();
+            it->second.pop_back();
+            ctx->pool_cached -= cls;
+            return ILE_OK;
+        }
+        if (ctx->budget && ctx->used + cls > ctx->budget) pool_trim_locked(ctx);
+        if (ctx->budget && ctx->used + cls > ctx->budget)
             return set_err(ILE_E_TOO_BIG, std::string("device budget exceeded allocating ") + what);
-        ctx->used += bytes;
+        ctx->used += cls;
     }
-    hipError_t e = hipMalloc(p, bytes);
+    hipError_t e = hipMalloc(p, cls);
     if (e != hipSuccess) {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        ctx->used -= bytes;
-        *p = nullptr;
         (void)hipGetLastError();
-        return set_err(ILE_E_NOMEM, std::string("hipMalloc failed for ") + what);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        pool_trim_locked(ctx);
+        e = hipMalloc(p, cls);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->used -= cls;
+            *p = nullptr;
+            return set_err(ILE_E_NOMEM, std::string("hipMalloc failed for ") + what);
+        }
     }
     return ILE_OK;
 }
 
+// Back to the pool; the caller guarantees no queued work still uses it.
 void ctx_free(ile_ctx *ctx, void *p, size_t bytes) {
     if (!p) return;
-    (void)hipFree(p);
+    const size_t cls = size_class(bytes);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->used -= bytes;
+    ctx->dev_pool[cls].push_back(p);
+    ctx->pool_cached += cls;
+}
+
+void *pin_alloc(ile_ctx *ctx, size_t bytes) {
+    const size_t cls = size_class(bytes);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->pin_pool.find(cls);
+        if (it != ctx->pin_pool.end() && !it->second.empty()) {
+            void *p = it->second.back();
+            it->second.pop_back();
+            return p;
+        }
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, cls, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void pin_free(ile_ctx *ctx, void *p, size_t bytes) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->pin_pool[size_class(bytes)].push_back(p);
+}
+
+void ctx_pool_release(ile_ctx *ctx) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    pool_trim_locked(ctx);
+    for (auto &kv : ctx->pin_pool)
+        for (void *q : kv.second) (void)hipHostFree(q);
+    ctx->pin_pool.clear();
 }
 
 // Distance table shared by every job of a context with the same prior.
@@ -190,6 +260,7 @@ extern "C" void ile_ctx_destroy(ile_ctx *ctx) {
         if (sl.h) (void)hipHostFree(sl.h);
         if (sl.ev) (void)hipEventDestroy(sl.ev);
     }
+    ctx_pool_release(ctx);
     delete ctx;
 }
 
@@ -270,6 +341,10 @@ void fill_tables(const ile_problem *P, const std::vector<int> &keep, const std::
 }  // namespace
 
 extern "C" ile_status ile_prepare(ile_ctx *ctx, const ile_problem *P, ile_job **out) {
+    return job_create(ctx, P, out, nullptr, false);
+}
+
+ile_status ile::job_create(ile_ctx *ctx, const ile_problem *P, ile_job **out, hipStream_t st, bool async) {
     ile_status s = ctx_check(ctx);
     if (s != ILE_OK) return s;
     if (!out || !P) return set_err(ILE_E_INVALID, "null argument");
@@ -393,26 +468,31 @@ extern "C" ile_status ile_prepare(ile_ctx *ctx, const ile_problem *P, ile_job **
     }
     job->q_bytes = Qb.size();
     job->uv_bytes = Ub.size();
-    auto cleanup = [&](ile_status st) {
-        ile_job_release(job);
-        return st;
+    auto cleanup = [&](ile_status stt) {
+        job_release_nosync(job);
+        return stt;
     };
-    if ((s = ctx_alloc(ctx, &job->d_Q, Qb.size(), "Q window")) != ILE_OK) return cleanup(s);
-    if ((s = ctx_alloc(ctx, &job->d_Ut, Ub.size(), "U table")) != ILE_OK) return cleanup(s);
-    if ((s = ctx_alloc(ctx, &job->d_Vt, Vb.size(), "V table")) != ILE_OK) return cleanup(s);
-    if ((s = ctx_alloc(ctx, (void **)&job->d_ms, sizeof(MargState), "estimator state")) != ILE_OK) return cleanup(s);
-    hipError_t e;
-    if ((e = hipMemcpy(job->d_Q, Qb.data(), Qb.size(), hipMemcpyHostToDevice)) != hipSuccess)
-        return cleanup(dev_fail(ctx, e, "upload Q"));
-    if ((e = hipMemcpy(job->d_Ut, Ub.data(), Ub.size(), hipMemcpyHostToDevice)) != hipSuccess)
-        return cleanup(dev_fail(ctx, e, "upload U"));
-    if ((e = hipMemcpy(job->d_Vt, Vb.data(), Vb.size(), hipMemcpyHostToDevice)) != hipSuccess)
-        return cleanup(dev_fail(ctx, e, "upload V"));
-    MargState ms0{-INFINITY, 0.0, 0.0, 0, 0, -1};
-    if ((e = hipMemcpy(job->d_ms, &ms0, sizeof ms0, hipMemcpyHostToDevice)) != hipSuccess)
-        return cleanup(dev_fail(ctx, e, "init estimator"));
-    if ((e = hipHostMalloc((void **)&job->h_ms, sizeof(MargState), hipHostMallocDefault)) != hipSuccess)
-        return cleanup(dev_fail(ctx, e, "pinned result buffer"));
+    // one blob [Q | U table | V table | estimator state], 256-byte aligned parts
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t oQ = 0, oU = al(Qb.size()), oV = oU + al(Ub.size()), oM = oV + al(Vb.size());
+    job->blob_bytes = oM + al(sizeof(MargState));
+    if ((s = ctx_alloc(ctx, &job->d_blob, job->blob_bytes, "job inputs")) != ILE_OK) return cleanup(s);
+    job->h_blob = pin_alloc(ctx, job->blob_bytes);
+    job->h_ms = (MargState *)pin_alloc(ctx, sizeof(MargState));
+    if (!job->h_blob || !job->h_ms) return cleanup(set_err(ILE_E_NOMEM, "pinned staging"));
+    char *hb = (char *)job->h_blob;
+    std::memcpy(hb + oQ, Qb.data(), Qb.size());
+    std::memcpy(hb + oU, Ub.data(), Ub.size());
+    std::memcpy(hb + oV, Vb.data(), Vb.size());
+    const MargState ms0{-INFINITY, 0.0, 0.0, 0, 0, -1};
+    std::memcpy(hb + oM, &ms0, sizeof ms0);
+    job->d_Q = (char *)job->d_blob + oQ;
+    job->d_Ut = (char *)job->d_blob + oU;
+    job->d_Vt = (char *)job->d_blob + oV;
+    job->d_ms = (MargState *)((char *)job->d_blob + oM);
+    hipError_t e = hipMemcpyAsync(job->d_blob, job->h_blob, job->blob_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !async) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return cleanup(dev_fail(ctx, e, "upload job inputs"));
 
     EvalJob &ej = job->ej;
     std::memset(&ej, 0, sizeof ej);
@@ -461,22 +541,25 @@ extern "C" ile_status ile_job_info_get(const ile_job *job, ile_job_info *info) {
     return ILE_OK;
 }
 
-extern "C" void ile_job_release(ile_job *job) {
+void ile::job_release_nosync(ile_job *job) {
     if (!job) return;
     ile_ctx *ctx = job->ctx;
-    (void)hipSetDevice(ctx->device);
-    (void)hipDeviceSynchronize();
-    ctx_free(ctx, job->d_Q, job->q_bytes);
-    ctx_free(ctx, job->d_Ut, job->uv_bytes);
-    ctx_free(ctx, job->d_Vt, job->uv_bytes);
-    ctx_free(ctx, job->d_ms, sizeof(MargState));
+    ctx_free(ctx, job->d_blob, job->blob_bytes);
     ctx_free(ctx, job->d_part, job->part_cap * sizeof(MargPartial));
     ctx_free(ctx, job->d_em, job->em_cap);
     ctx_free(ctx, job->d_gmm, sizeof(GmmDev));
     ctx_free(ctx, job->d_zcount, kMaxComp * sizeof(uint32_t));
-    if (job->h_ms) (void)hipHostFree(job->h_ms);
-    if (job->h_gmm) (void)hipHostFree(job->h_gmm);
+    pin_free(ctx, job->h_blob, job->blob_bytes);
+    pin_free(ctx, job->h_ms, sizeof(MargState));
+    pin_free(ctx, job->h_gmm, sizeof(GmmDev));
     delete job;
+}
+
+extern "C" void ile_job_release(ile_job *job) {
+    if (!job) return;
+    (void)hipSetDevice(job->ctx->device);
+    (void)hipDeviceSynchronize();   // the caller's queued work may still use the buffers
+    job_release_nosync(job);
 }
 
 // ===================================================================== eval
@@ -756,8 +839,8 @@ static ile_status ensure_gmm(ile_job *job) {
     if (s != ILE_OK) return s;
     s = ctx_alloc(job->ctx, (void **)&job->d_zcount, kMaxComp * sizeof(uint32_t), "mass counters");
     if (s != ILE_OK) return s;
-    hipError_t e = hipHostMalloc((void **)&job->h_gmm, sizeof(GmmDev), hipHostMallocDefault);
-    if (e != hipSuccess) return dev_fail(job->ctx, e, "pinned mixture buffer");
+    job->h_gmm = (GmmDev *)pin_alloc(job->ctx, sizeof(GmmDev));
+    if (!job->h_gmm) return set_err(ILE_E_NOMEM, "pinned mixture buffer");
     return ILE_OK;
 }
 

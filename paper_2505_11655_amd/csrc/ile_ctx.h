@@ -18,7 +18,11 @@ struct ile_ctx {
     size_t budget = 0;
     size_t used = 0;
     std::atomic<bool> sticky{false};
-    std::mutex mu;                        // budget accounting
+    std::mutex mu;                        // budget accounting and the pools below
+    // device and pinned-host buffers recycled by power-of-two size class; a
+    // buffer goes back to its pool only when no queued work can still use it
+    std::map<size_t, std::vector<void *>> dev_pool, pin_pool;
+    size_t pool_cached = 0;
     struct DistEntry {
         ile::DistTable tab;
         void *buf;
@@ -45,6 +49,9 @@ struct ile_job {
     int policy = 0, set = 0, kp = 2, n_det = 1, n_time = 0, n_kept = 0;
     bool dist_marg = false;
     ile::PriorDev pr{};
+    // resident inputs: one device blob [Q | U table | V table | estimator state]
+    void *d_blob = nullptr, *h_blob = nullptr;   // h_blob: pinned staging of the upload
+    size_t blob_bytes = 0;
     void *d_Q = nullptr, *d_Ut = nullptr, *d_Vt = nullptr;
     size_t q_bytes = 0, uv_bytes = 0, device_bytes = 0;
     ile::EvalJob ej{};
@@ -105,6 +112,15 @@ ile_status dev_fail(ile_ctx *ctx, hipError_t e, const char *what);
 ile_status ctx_check(ile_ctx *ctx);
 ile_status ctx_alloc(ile_ctx *ctx, void **p, size_t bytes, const char *what);
 void ctx_free(ile_ctx *ctx, void *p, size_t bytes);
+void *pin_alloc(ile_ctx *ctx, size_t bytes);
+void pin_free(ile_ctx *ctx, void *p, size_t bytes);
+void ctx_pool_release(ile_ctx *ctx);
+// Build and upload a job; with a stream the upload is asynchronous on it
+// (the pinned staging stays with the job until release).
+ile_status job_create(ile_ctx *ctx, const ile_problem *P, ile_job **out, hipStream_t st, bool async);
+// Release without a device-wide sync: the caller guarantees no queued work
+// still uses the job's buffers.
+void job_release_nosync(ile_job *job);
 ile_status eval_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, hipStream_t st);
 // Copy two host arrays into a scratch slot (caller holds batch_mu); after
 // enqueueing the kernel that reads them, call batch_done with the slot.

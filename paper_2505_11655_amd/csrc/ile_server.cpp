@@ -124,7 +124,7 @@ void finish(ile_server *s, Req *r, int status, const ile_marg *m) {
         ctx_free(s->ctx, r->d_lr, (size_t)r->chunk * theta_bytes(policy));
         ctx_free(s->ctx, r->d_lw, (size_t)r->chunk * lw_bytes(policy));
         r->d_theta = r->d_lr = r->d_lw = nullptr;
-        ile_job_release(r->job);
+        job_release_nosync(r->job);   // the server stream has no queued work for it
         r->job = nullptr;
     }
     s->used -= std::min(s->used, r->footprint);
@@ -139,7 +139,7 @@ void finish(ile_server *s, Req *r, int status, const ile_marg *m) {
 // Admit one request: prepare its job and allocate its pass buffers.
 ile_status admit(ile_server *s, Req *r) {
     ile_job *job = nullptr;
-    ile_status st = ile_prepare(s->ctx, &r->prob, &job);
+    ile_status st = job_create(s->ctx, &r->prob, &job, s->stream, true);
     if (st != ILE_OK) return st;
     r->job = job;
     r->chunk = chunk_of(s, r);
@@ -264,7 +264,7 @@ void scheduler(ile_server *s) {
                     ++it;
                 }
             }
-            const int maxa = s->opts.max_active > 0 ? s->opts.max_active : 64;
+            const int maxa = s->opts.max_active > 0 ? s->opts.max_active : 256;
             while (!s->queue.empty() && (int)s->active.size() < maxa && !s->failed) {
                 Req *r = s->queue.front();
                 if (s->used + r->footprint > s->budget) break;   // arrival order: wait for memory
@@ -285,6 +285,7 @@ void scheduler(ile_server *s) {
         s->cv_done.notify_all();
         if (act.empty()) continue;
         if (!run_pass(s, act)) {
+            (void)hipStreamSynchronize(s->stream);   // nothing queued may still use freed buffers
             std::lock_guard<std::mutex> lk(s->mu);
             s->failed = true;
             for (Req *r : s->active) finish(s, r, ILE_E_DEVICE, nullptr);
