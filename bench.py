@@ -30,6 +30,33 @@ METRIC = "extrinsic lnL samples/s (FP32 vs FP64 plain, |dlnL|<=1e-3) + p50/p99 l
 FLOP_PER_SAMPLE = {(3, 9): 3493, (2, 5): 1069, (3, 17): 10057}
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12}
 HBM_PEAK = 8.0e12
+# algorithmic HBM bytes per sample of the lnL kernel: 7 theta + ln p - ln p_s
+# read, lnL + lw written (FP32: 4 B each; FP64: 8 B)
+LNL_BYTES = {"fp32": 40, "fp64": 80}
+# Measured HBM traffic of the FP32 lnL kernel on this workload: two
+# `rocprofv3 --pmc` runs of `bench.py --probe` (FETCH_SIZE, then WRITE_SIZE,
+# KiB per dispatch), each scaled by the same counter's reading for the probe's
+# 1 GiB device copy (FETCH_SIZE reads half the bytes: x2.000; WRITE_SIZE x1.000).
+# The figures hold only for the kernel source they were taken on.
+# SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32 of the same probe give the FLOPs the
+# kernel executes (64 lanes x (add + mul + 2 fma + trans) per wave instruction).
+LNL_TRAFFIC = {"fetch_B_per_sample": 32.717, "write_B_per_sample": 8.000, "executed_flop_per_sample": 2527.0,
+               "src_sha256": "29d2382eadc7f69057bf016eb1509a0307dd5e89ee4293937f71859d16526347"}
+# algorithmic HBM bytes per sample of the draw (7 theta + ln p - ln p_s
+# written) and estimator (lw read) kernels
+DRAW_BYTES = {"fp32": 32, "fp64": 64}
+MARG_BYTES = {"fp32": 4, "fp64": 8}
+LNL_SOURCES = ["paper_2505_11655_amd/csrc/k_lnl_impl.h", "paper_2505_11655_amd/csrc/ile_internal.h",
+               "paper_2505_11655_amd/csrc/k_lnl_s1_p1.hip"]
+
+
+def lnl_src_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in LNL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def log(msg):
@@ -216,7 +243,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         r = run_policy(ile, torch, ctx, probs, ile.ILE_FP32, n_per, 1, 0, stream)
-        print(json.dumps({"probe": True, "samples": r["N"], "kernel_ms": r["kernel_ms"]}), flush=True)
+        print(json.dumps({"probe": True, "samples": r["N"], "kernel_ms": r["kernel_ms"],
+                          "lnl_src_sha256": lnl_src_sha256()}), flush=True)
         return
     log("fp32 ...")
     r32 = run_policy(ile, torch, ctx, probs, ile.ILE_FP32, n_per, a.steps, a.warmup, stream)
@@ -246,13 +274,33 @@ def main():
     flop = FLOP_PER_SAMPLE[(3, 9)]
     t_eval = r32["kernel_ms"]["eval"] * 1e-3
     achieved = flop * N / t_eval
-    bytes_eval = 36 * N
+    bytes_eval = LNL_BYTES["fp32"] * N
+    traffic = None
+    executed = None
+    if LNL_TRAFFIC["src_sha256"] is not None and LNL_TRAFFIC["src_sha256"] == lnl_src_sha256():
+        traffic = (LNL_TRAFFIC["fetch_B_per_sample"] + LNL_TRAFFIC["write_B_per_sample"]) * N
+        executed = LNL_TRAFFIC["executed_flop_per_sample"] * N / t_eval / 1e12
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK["fp32"], "traffic": None,
+            "frac": achieved / PEAK["fp32"], "traffic": traffic, "traffic_unit": "bytes per launch",
+            "algorithmic_bytes_per_launch": bytes_eval,
             "kernel": "k_lnl (fused lnL, FP32, K=3, 9 modes)", "flop_per_sample": flop,
             "samples_per_launch": N, "avg_launch_ms": r32["kernel_ms"]["eval"],
             "hbm_algorithmic_GBps": bytes_eval / t_eval / 1e9,
-            "hbm_frac": bytes_eval / t_eval / HBM_PEAK}
+            "hbm_frac": bytes_eval / t_eval / HBM_PEAK,
+            "executed_TFLOPs": executed,
+            "executed_frac_of_nonpacked_fp32": None if executed is None else executed / 78.6}
+
+    def hbm(per_sample, r, key):
+        t = r["kernel_ms"][key] * 1e-3
+        return {"ms": r["kernel_ms"][key], "bytes": per_sample * r["N"],
+                "GBps": per_sample * r["N"] / t / 1e9, "hbm_frac": per_sample * r["N"] / t / HBM_PEAK}
+    kernels = {"fp32": {"draw": hbm(DRAW_BYTES["fp32"], r32, "draw"),
+                        "lnl": hbm(LNL_BYTES["fp32"], r32, "eval"),
+                        "marg": hbm(MARG_BYTES["fp32"], r32, "marg")}}
+    if r64 is not None:
+        kernels["fp64"] = {"draw": hbm(DRAW_BYTES["fp64"], r64, "draw"),
+                           "lnl": hbm(LNL_BYTES["fp64"], r64, "eval"),
+                           "marg": hbm(MARG_BYTES["fp64"], r64, "marg")}
     line = {
         "metric": METRIC, "value": r32["samples_per_s"], "unit": "samples/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": r32["ms_per_step"], "higher_is_better": True,
@@ -262,6 +310,7 @@ def main():
                    "points": a.points, "samples_per_point": n_per, "detectors": 3, "modes": 9},
         "roofline": roof,
         "kernel_ms": r32["kernel_ms"],
+        "kernels_hbm": kernels,
         "fp64": None if r64 is None else {"value": r64["samples_per_s"], "ms_per_step": r64["ms_per_step"],
                                           "kernel_ms": r64["kernel_ms"],
                                           "fp32_over_fp64": r32["samples_per_s"] / r64["samples_per_s"]},

@@ -722,7 +722,10 @@ ile_status draw_batch(ile_ctx *ctx, int policy, const std::vector<DrawJob> &jobs
     ile_status s = batch_upload(ctx, jobs.data(), jobs.size() * sizeof(DrawJob), tiles.data(),
                                 tiles.size() * sizeof(Tile), &dj, &dt, &slot, st);
     if (s != ILE_OK) return s;
-    hipError_t e = launch_draw(policy, (const DrawJob *)dj, (const Tile *)dt, (int)tiles.size(), jobs[0], tile, st);
+    bool mix = false;
+    for (const DrawJob &j : jobs) mix = mix || j.gmm != nullptr;
+    hipError_t e =
+        launch_draw(policy, (const DrawJob *)dj, (const Tile *)dt, (int)tiles.size(), jobs[0], tile, mix, st);
     if (e != hipSuccess) return dev_fail(ctx, e, "batched draw");
     return batch_done(ctx, slot, st);
 }
@@ -818,7 +821,8 @@ extern "C" ile_status ile_draw(ile_job *job, uint64_t seed, uint32_t round, int6
     const int64_t tile = 2048;
     const int64_t nt = (n + tile - 1) / tile;
     if (nt > INT32_MAX) return set_err(ILE_E_INVALID, "too many samples for one launch");
-    hipError_t e = launch_draw(job->policy, nullptr, nullptr, (int)nt, dj, tile, (hipStream_t)stream);
+    hipError_t e =
+        launch_draw(job->policy, nullptr, nullptr, (int)nt, dj, tile, dj.gmm != nullptr, (hipStream_t)stream);
     if (e != hipSuccess) return dev_fail(job->ctx, e, "draw launch");
     return ILE_OK;
 }

@@ -144,8 +144,10 @@ struct U4 {
 __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; r++) {
-        uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        // one 32x32->64 product per multiplier (a single v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         U4 n{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
         c = n;
         k0 += 0x9E3779B9u;
@@ -266,8 +268,9 @@ hipError_t launch_marg_combine(const MargPartial *d_part, int n_part, int64_t n,
 hipError_t launch_marg_batch(int policy, const MargJob *d_jobs, int n_jobs, const Tile *d_tiles, int n_tiles,
                              MargPartial *d_part, MargState *d_out, hipStream_t st);
 
+// `mix`: some job carries a mixture proposal (otherwise the prior-only kernel).
 hipError_t launch_draw(int policy, const DrawJob *d_jobs, const Tile *d_tiles, int n_tiles,
-                       const DrawJob &single, int64_t tile, hipStream_t st);
+                       const DrawJob &single, int64_t tile, bool mix, hipStream_t st);
 
 hipError_t launch_gmm_factor(GmmDev *d_gmm, hipStream_t st);
 hipError_t launch_gmm_inbox(GmmDev *d_gmm, PriorDev pr, uint64_t seed, uint32_t round, int64_t m,

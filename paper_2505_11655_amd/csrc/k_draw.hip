@@ -10,6 +10,11 @@
 // Box-Muller pairs of blocks 1..4 of attempt a and accepts x = mu + L z if
 // every bounded column is inside its interval and every periodic offset lies
 // in (-P/2, P/2]; after 64 rejected attempts the prior draw is kept.
+//
+// Two instantiations per sample type: prior-only launches (no mixture code,
+// so the kernel stays small and occupancy high) and launches where some job
+// carries a mixture.  Mixture columns are addressed through select chains on
+// the (uniform) column index, so every per-sample array stays in registers.
 #include "ile_internal.h"
 
 namespace ile {
@@ -23,6 +28,7 @@ constexpr double kPi = 3.14159265358979323846;
 __device__ __forceinline__ void words(uint64_t seed, uint64_t i, uint32_t r, uint32_t a, int b0, int nb,
                                       uint32_t *w) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
     for (int b = 0; b < nb; b++) {
         U4 o = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), r, a * 16u + (uint32_t)(b0 + b)}, k0, k1);
         w[4 * b + 0] = o.x;
@@ -45,7 +51,15 @@ __device__ __forceinline__ void support(const PriorDev &pr, int col, double &lo,
     }
 }
 
-__device__ double ln_prior(const PriorDev &pr, const double th[7]) {
+// v[c] for a uniform column index c, without dynamic register indexing
+__device__ __forceinline__ double pick7(const double v[7], int c) {
+    double r = v[0];
+#pragma unroll
+    for (int k = 1; k < 7; k++) r = (c == k) ? v[k] : r;
+    return r;
+}
+
+__device__ __forceinline__ double ln_prior(const PriorDev &pr, const double th[7]) {
     double lp = -log(2 * kPi) + log(0.5 * cos(th[1])) - log(2.0 * pr.t_window) - log(2.0) - log(2 * kPi) -
                 log(kPi);
     if (!pr.dist_marg) {
@@ -55,7 +69,7 @@ __device__ double ln_prior(const PriorDev &pr, const double th[7]) {
     return lp;
 }
 
-__device__ void prior_from_words(const PriorDev &pr, const uint32_t *w, double th[7]) {
+__device__ __forceinline__ void prior_from_words(const PriorDev &pr, const uint32_t *w, double th[7]) {
     double u[7];
 #pragma unroll
     for (int c = 0; c < 7; c++) u[c] = u53(w[2 * c], w[2 * c + 1]);
@@ -80,45 +94,61 @@ __device__ __forceinline__ double wrapd(double d, double P) {
     return r > 0.5 * P ? r - P : r;
 }
 
-}  // namespace
-
 // ln N_j(wrap(x - mu_j)) through the inverse Cholesky factor.
-__device__ double gmm_comp_logpdf(const GmmDev &g, const PriorDev &pr, int j, const double th[7]) {
+__device__ __forceinline__ double gmm_comp_logpdf(const GmmDev &g, const PriorDev &pr, int j, const double th[7]) {
     const int d = g.n_dim;
     double diff[7];
-    for (int a = 0; a < d; a++) {
-        double lo, hi, P;
-        support(pr, g.dims[a], lo, hi, P);
-        diff[a] = wrapd(th[g.dims[a]] - g.mean[j][a], P);
+#pragma unroll
+    for (int a = 0; a < 7; a++) {
+        diff[a] = 0.0;
+        if (a < d) {
+            double lo, hi, P;
+            const int c = g.dims[a];
+            support(pr, c, lo, hi, P);
+            diff[a] = wrapd(pick7(th, c) - g.mean[j][a], P);
+        }
     }
     double q = 0.0;
-    for (int a = 0; a < d; a++) {
-        double y = 0.0;
-        for (int b = 0; b <= a; b++) y += g.Linv[j][a][b] * diff[b];
-        q += y * y;
+#pragma unroll
+    for (int a = 0; a < 7; a++) {
+        if (a < d) {
+            double y = 0.0;
+#pragma unroll
+            for (int b = 0; b <= a; b++) y += g.Linv[j][a][b] * diff[b];
+            q += y * y;
+        }
     }
     return -0.5 * q - g.logdet_half[j] - 0.5 * d * log(2 * kPi);
 }
 
-__device__ double gmm_ln_ps(const GmmDev &g, const PriorDev &pr, const double th[7]) {
-    double t[kMaxComp + 1];
-    int nt = 0;
+// ln p_s(x) by a running log-sum-exp over the live components and the
+// defensive prior term.
+__device__ __noinline__ double gmm_ln_ps(const GmmDev &g, const PriorDev &pr, const double th[7]) {
+    double m = -INFINITY, s = 0.0;
+    auto add = [&](double t) {
+        if (!(t > -INFINITY)) return;
+        if (t > m) {
+            s = s * exp(m - t) + 1.0;
+            m = t;
+        } else {
+            s += exp(t - m);
+        }
+    };
     const double l1e = log1p(-g.eps_def);
     for (int j = 0; j < g.n_comp; j++) {
         if (g.logw[j] == -INFINITY) continue;
-        t[nt++] = l1e + g.logw[j] + gmm_comp_logpdf(g, pr, j, th) - g.lnZ[j];
+        add(l1e + g.logw[j] + gmm_comp_logpdf(g, pr, j, th) - g.lnZ[j]);
     }
-    if (g.eps_def > 0.0) t[nt++] = log(g.eps_def) + ln_prior(pr, th);
-    double m = -INFINITY;
-    for (int k = 0; k < nt; k++) m = fmax(m, t[k]);
+    if (g.eps_def > 0.0) add(log(g.eps_def) + ln_prior(pr, th));
     if (!(m > -INFINITY)) return m;
-    double s = 0.0;
-    for (int k = 0; k < nt; k++) s += exp(t[k] - m);
     return m + log(s);
 }
 
 // One candidate from component j: words w[0..15] give four Box-Muller pairs.
-__device__ bool gmm_candidate(const GmmDev &g, const PriorDev &pr, int j, const uint32_t *w, double th[7]) {
+// On acceptance the mixture columns of th are overwritten; on rejection th is
+// left as it was.
+__device__ __forceinline__ bool gmm_candidate(const GmmDev &g, const PriorDev &pr, int j, const uint32_t *w,
+                                              double th[7]) {
     double z[8];
 #pragma unroll
     for (int p = 0; p < 4; p++) {
@@ -129,68 +159,80 @@ __device__ bool gmm_candidate(const GmmDev &g, const PriorDev &pr, int j, const 
         z[2 * p] = r * c;
         z[2 * p + 1] = r * s;
     }
-    for (int a = 0; a < g.n_dim; a++) {
-        double off = 0.0;
-        for (int b = 0; b <= a; b++) off += g.L[j][a][b] * z[b];
-        double lo, hi, P;
-        support(pr, g.dims[a], lo, hi, P);
-        double x = g.mean[j][a] + off;
-        if (P > 0.0) {
-            if (!(off > -0.5 * P && off <= 0.5 * P)) return false;
-            x = x - P * floor((x - lo) / P);
-        } else if (!(x >= lo && x <= hi)) {
-            return false;
+    const int d = g.n_dim;
+    double x[7];
+#pragma unroll
+    for (int a = 0; a < 7; a++) {
+        x[a] = 0.0;
+        if (a < d) {
+            double off = 0.0;
+#pragma unroll
+            for (int b = 0; b <= a; b++) off += g.L[j][a][b] * z[b];
+            double lo, hi, P;
+            support(pr, g.dims[a], lo, hi, P);
+            double v = g.mean[j][a] + off;
+            if (P > 0.0) {
+                if (!(off > -0.5 * P && off <= 0.5 * P)) return false;
+                v = v - P * floor((v - lo) / P);
+            } else if (!(v >= lo && v <= hi)) {
+                return false;
+            }
+            x[a] = v;
         }
-        th[g.dims[a]] = x;
+    }
+#pragma unroll
+    for (int a = 0; a < 7; a++) {
+        if (a < d) {
+            const int c = g.dims[a];
+#pragma unroll
+            for (int k = 0; k < 7; k++) th[k] = (c == k) ? x[a] : th[k];
+        }
     }
     return true;
 }
 
-namespace {
+// Mixture draw of sample idx: th and ln p - ln p_s.
+__device__ __noinline__ void draw_mix(const DrawJob &J, uint64_t idx, double th[7], double &lr) {
+    const GmmDev &g = *J.gmm;
+    uint32_t w[20];
+    words(J.seed, idx, J.round, 0, 0, 5, w);
+    prior_from_words(J.pr, w + 4, th);
+    const double usel = u53(w[0], w[1]);
+    if (usel >= g.eps_def) {
+        const double v = (usel - g.eps_def) / (1.0 - g.eps_def);
+        double tot = 0.0;
+        for (int j = 0; j < g.n_comp; j++) tot += g.w[j];
+        int jsel = -1;
+        double acc = 0.0;
+        for (int j = 0; j < g.n_comp; j++) {
+            if (!(g.w[j] > 0.0)) continue;
+            acc += g.w[j] / tot;
+            jsel = j;
+            if (v < acc) break;
+        }
+        for (int a = 0; a < kMaxAttempts && jsel >= 0; a++) {
+            uint32_t wa[16];
+            words(J.seed, idx, J.round, (uint32_t)a, 1, 4, wa);
+            if (gmm_candidate(g, J.pr, jsel, wa, th)) break;
+        }
+    }
+    lr = ln_prior(J.pr, th) - gmm_ln_ps(g, J.pr, th);
+}
 
-template <class TT>
-__device__ void draw_range(const DrawJob &J, int64_t begin, int64_t end) {
+template <class TT, bool MIX>
+__device__ __forceinline__ void draw_range(const DrawJob &J, int64_t begin, int64_t end) {
     TT *__restrict__ th_out = (TT *)J.theta;
     TT *__restrict__ lr_out = (TT *)J.lnpmps;
     for (int64_t s = begin + threadIdx.x; s < end; s += kDrawThreads) {
         const uint64_t idx = (uint64_t)(J.first + s);
-        uint32_t w[20];
         double th[7];
         double lr = 0.0;
-        if (J.gmm == nullptr) {
+        if (!MIX || J.gmm == nullptr) {
+            uint32_t w[16];
             words(J.seed, idx, J.round, 0, 0, 4, w);
             prior_from_words(J.pr, w, th);
         } else {
-            const GmmDev &g = *J.gmm;
-            words(J.seed, idx, J.round, 0, 0, 5, w);
-            prior_from_words(J.pr, w + 4, th);
-            const double usel = u53(w[0], w[1]);
-            if (usel >= g.eps_def) {
-                const double v = (usel - g.eps_def) / (1.0 - g.eps_def);
-                double tot = 0.0;
-                for (int j = 0; j < g.n_comp; j++) tot += g.w[j];
-                int jsel = -1;
-                double acc = 0.0;
-                for (int j = 0; j < g.n_comp; j++) {
-                    if (!(g.w[j] > 0.0)) continue;
-                    acc += g.w[j] / tot;
-                    jsel = j;
-                    if (v < acc) break;
-                }
-                for (int a = 0; a < kMaxAttempts && jsel >= 0; a++) {
-                    uint32_t wa[16];
-                    words(J.seed, idx, J.round, (uint32_t)a, 1, 4, wa);
-                    double cand[7];
-#pragma unroll
-                    for (int c = 0; c < 7; c++) cand[c] = th[c];
-                    if (gmm_candidate(g, J.pr, jsel, wa, cand)) {
-#pragma unroll
-                        for (int c = 0; c < 7; c++) th[c] = cand[c];
-                        break;
-                    }
-                }
-            }
-            lr = ln_prior(J.pr, th) - gmm_ln_ps(g, J.pr, th);
+            draw_mix(J, idx, th, lr);
         }
 #pragma unroll
         for (int c = 0; c < 7; c++) th_out[c * J.ld + s] = (TT)th[c];
@@ -198,27 +240,38 @@ __device__ void draw_range(const DrawJob &J, int64_t begin, int64_t end) {
     }
 }
 
-template <class TT>
+template <class TT, bool MIX>
 __global__ void __launch_bounds__(kDrawThreads)
     k_draw(const DrawJob *__restrict__ jobs, const Tile *__restrict__ tiles, const DrawJob single, int64_t tile) {
     if (jobs != nullptr) {
         const Tile tl = tiles[blockIdx.x];
-        draw_range<TT>(jobs[tl.job], tl.begin, tl.end);
+        draw_range<TT, MIX>(jobs[tl.job], tl.begin, tl.end);
     } else {
         const int64_t b = (int64_t)blockIdx.x * tile;
-        draw_range<TT>(single, b, b + tile < single.n ? b + tile : single.n);
+        draw_range<TT, MIX>(single, b, b + tile < single.n ? b + tile : single.n);
     }
+}
+
+template <class TT>
+void launch_draw_t(bool mix, const DrawJob *d_jobs, const Tile *d_tiles, int n_tiles, const DrawJob &single,
+                   int64_t tile, hipStream_t st) {
+    if (mix)
+        hipLaunchKernelGGL((k_draw<TT, true>), dim3(n_tiles), dim3(kDrawThreads), 0, st, d_jobs, d_tiles, single,
+                           tile);
+    else
+        hipLaunchKernelGGL((k_draw<TT, false>), dim3(n_tiles), dim3(kDrawThreads), 0, st, d_jobs, d_tiles, single,
+                           tile);
 }
 
 }  // namespace
 
 hipError_t launch_draw(int policy, const DrawJob *d_jobs, const Tile *d_tiles, int n_tiles, const DrawJob &single,
-                       int64_t tile, hipStream_t st) {
+                       int64_t tile, bool mix, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
     if (policy == kFP64)
-        hipLaunchKernelGGL(k_draw<double>, dim3(n_tiles), dim3(kDrawThreads), 0, st, d_jobs, d_tiles, single, tile);
+        launch_draw_t<double>(mix, d_jobs, d_tiles, n_tiles, single, tile, st);
     else
-        hipLaunchKernelGGL(k_draw<float>, dim3(n_tiles), dim3(kDrawThreads), 0, st, d_jobs, d_tiles, single, tile);
+        launch_draw_t<float>(mix, d_jobs, d_tiles, n_tiles, single, tile, st);
     return hipGetLastError();
 }
 
@@ -238,6 +291,7 @@ __global__ void __launch_bounds__(kZThreads)
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
         for (int64_t i = (int64_t)blockIdx.x * kZThreads + threadIdx.x; i < m; i += (int64_t)gridDim.x * kZThreads) {
             uint32_t w[16];
+#pragma unroll
             for (int b = 0; b < 4; b++) {
                 U4 o = philox4x32_10(U4{(uint32_t)i, 0x5A000000u + (uint32_t)j, round, (uint32_t)b}, k0, k1);
                 w[4 * b] = o.x; w[4 * b + 1] = o.y; w[4 * b + 2] = o.z; w[4 * b + 3] = o.w;

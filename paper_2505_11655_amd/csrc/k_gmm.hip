@@ -481,10 +481,16 @@ hipError_t launch_gmm_factor(GmmDev *d_gmm, hipStream_t st) {
 hipError_t launch_em_prepare(int policy, const void *lw, int64_t n, double *d_work, size_t work_bytes,
                              double temper_frac, hipStream_t st) {
     if (work_bytes < em_work_bytes(n)) return hipErrorInvalidValue;
-    ILE_DISPATCH_TL(policy, {
-        hipLaunchKernelGGL((k_em_max<TL>), dim3(1), dim3(kEmThreads), 0, st, (const TL *)lw, n, d_work);
-        hipLaunchKernelGGL((k_em_beta<TL>), dim3(1), dim3(kEmThreads), 0, st, (const TL *)lw, n, temper_frac, d_work);
-    });
+    // only the weight type matters here (FP64 for the FP64 and mixed policies)
+    if (policy == kFP32) {
+        hipLaunchKernelGGL((k_em_max<float>), dim3(1), dim3(kEmThreads), 0, st, (const float *)lw, n, d_work);
+        hipLaunchKernelGGL((k_em_beta<float>), dim3(1), dim3(kEmThreads), 0, st, (const float *)lw, n, temper_frac,
+                           d_work);
+    } else {
+        hipLaunchKernelGGL((k_em_max<double>), dim3(1), dim3(kEmThreads), 0, st, (const double *)lw, n, d_work);
+        hipLaunchKernelGGL((k_em_beta<double>), dim3(1), dim3(kEmThreads), 0, st, (const double *)lw, n,
+                           temper_frac, d_work);
+    }
     return hipGetLastError();
 }
 

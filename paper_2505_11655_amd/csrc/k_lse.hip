@@ -2,10 +2,13 @@
 // deterministic two-stage reduction in FP64 of the 4-tuple
 //   (m = max lw, S1 = sum e^{lw-m}, S2 = sum e^{2(lw-m)}, argmax)
 // plus the count of non-finite lw (zero weight).  Stage 1: one block per tile
-// of consecutive samples, each thread a running (m, S1, S2) over a strided
-// subset, then a fixed-shape tree in LDS.  Stage 2: one block combines the
-// tiles in index order and pools the result into the job's state.  The result
-// depends only on n and the tile size, never on scheduling.
+// of consecutive samples; each lane reads 16-byte chunks (8 samples per lane
+// per step, each wave-wide load one contiguous kilobyte), rescales its running
+// (m, S1, S2) once per step to the step's maximum and then adds one
+// exponential per sample; a fixed-shape tree in LDS combines the lanes.
+// Stage 2: one block combines the tiles in index order and pools the result
+// into the job's state.  The result depends only on n and the tile size,
+// never on scheduling.
 #include "ile_internal.h"
 
 namespace ile {
@@ -19,23 +22,79 @@ struct Acc {
     int64_t bad, am;
 };
 
-__device__ __forceinline__ void acc_push(Acc &a, double x, int64_t i) {
-    if (!(x > -INFINITY && x < INFINITY)) {  // -inf, +inf and NaN carry no weight
-        a.bad++;
-        return;
+// Terms with lw - m below -kSkip are under 2^-54 of the largest term and do
+// not change an FP64 sum that holds it; their exponential is not evaluated.
+constexpr double kSkip = 37.5;
+
+// Push B samples x[0..B) with indices idx[k] (increasing): one rescale to the
+// batch maximum, then one exponential per sample.
+template <int B>
+__device__ __forceinline__ void acc_batch(Acc &a, const double *x, const int64_t *idx) {
+    double bm = -INFINITY;
+    int64_t bi = INT64_MAX;
+#pragma unroll
+    for (int k = 0; k < B; k++) {
+        if (!(x[k] > -INFINITY && x[k] < INFINITY)) {
+            a.bad++;
+        } else if (x[k] > bm) {
+            bm = x[k];
+            bi = idx[k];
+        }
     }
-    if (x > a.m) {
-        const double r = exp(a.m - x);   // 0 when a.m = -inf
-        a.s1 = a.s1 * r + 1.0;
-        a.s2 = a.s2 * r * r + 1.0;
-        a.m = x;
-        a.am = i;
-    } else {
-        const double e = exp(x - a.m);
-        a.s1 += e;
-        a.s2 += e * e;
-        if (x == a.m && i < a.am) a.am = i;
+    if (bm > a.m) {
+        const double r = exp(a.m - bm);   // 0 when a.m = -inf
+        a.s1 *= r;
+        a.s2 *= r * r;
+        a.m = bm;
+        a.am = bi;
+    } else if (bm == a.m && bi < a.am) {
+        a.am = bi;
     }
+#pragma unroll
+    for (int k = 0; k < B; k++) {
+        const double d = x[k] - a.m;
+        if (d > -kSkip && x[k] < INFINITY) {
+            const double e = exp(d);
+            a.s1 += e;
+            a.s2 += e * e;
+        }
+    }
+}
+
+// Stage-1 reduction of lw[begin, end) for the calling thread.
+template <class TL>
+__device__ __forceinline__ Acc tile_scan(const TL *lw, int64_t begin, int64_t end) {
+    typedef __attribute__((address_space(1))) const TL gTL;
+    constexpr int kEpc = 16 / (int)sizeof(TL);   // elements per 16-byte chunk
+    constexpr int kNch = 8 / kEpc;               // chunks per lane per step (8 samples)
+    constexpr int64_t kStep = (int64_t)kLseThreads * kNch * kEpc;
+    Acc a{-INFINITY, 0.0, 0.0, 0, INT64_MAX};
+    const int t = threadIdx.x;
+    int64_t i = begin;
+    if ((((uintptr_t)(lw + begin)) & 15) == 0) {
+        gTL *g = (gTL *)lw;
+        for (; i + kStep <= end; i += kStep) {
+            double x[8];
+            int64_t ix[8];
+#pragma unroll
+            for (int c = 0; c < kNch; c++) {
+                const int64_t e0 = i + ((int64_t)c * kLseThreads + t) * kEpc;
+                typedef TL vec_t __attribute__((ext_vector_type(kEpc)));
+                typedef __attribute__((address_space(1))) const vec_t gvec_t;
+                const vec_t v = *(gvec_t *)(g + e0);
+#pragma unroll
+                for (int e = 0; e < kEpc; e++) x[kEpc * c + e] = (double)v[e];
+#pragma unroll
+                for (int e = 0; e < kEpc; e++) ix[kEpc * c + e] = e0 + e;
+            }
+            acc_batch<8>(a, x, ix);
+        }
+    }
+    for (int64_t j = i + t; j < end; j += kLseThreads) {
+        const double x = (double)lw[j];
+        acc_batch<1>(a, &x, &j);
+    }
+    return a;
 }
 
 // Combine b into a (a holds the lower sample indices on ties).
@@ -83,8 +142,7 @@ __global__ void __launch_bounds__(kLseThreads)
     k_marg_partials(const TL *__restrict__ lw, int64_t n, int64_t tile, MargPartial *__restrict__ part) {
     const int64_t b0 = (int64_t)blockIdx.x * tile;
     const int64_t b1 = min(b0 + tile, n);
-    Acc a{-INFINITY, 0.0, 0.0, 0, INT64_MAX};
-    for (int64_t i = b0 + threadIdx.x; i < b1; i += kLseThreads) acc_push(a, (double)lw[i], i);
+    Acc a = tile_scan<TL>(lw, b0, b1);
     block_reduce(a);
     if (threadIdx.x == 0) part[blockIdx.x] = MargPartial{a.m, a.s1, a.s2, a.bad, a.am};
 }
@@ -152,8 +210,7 @@ __global__ void __launch_bounds__(kLseThreads)
                           MargPartial *__restrict__ part) {
     const Tile tl = tiles[blockIdx.x];
     const TL *__restrict__ lw = (const TL *)jobs[tl.job].lw;
-    Acc a{-INFINITY, 0.0, 0.0, 0, INT64_MAX};
-    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kLseThreads) acc_push(a, (double)lw[i], i);
+    Acc a = tile_scan<TL>(lw, tl.begin, tl.end);
     block_reduce(a);
     if (threadIdx.x == 0) part[blockIdx.x] = MargPartial{a.m, a.s1, a.s2, a.bad, a.am};
 }

@@ -196,10 +196,14 @@ def test_prepare_rejects_bad_inputs():
 
 
 # ------------------------------------------------------------------ estimator
-def _gpu_marg(job, lw, policy, flags=ile.ILE_MARG_RESET):
-    t = torch.from_numpy(np.ascontiguousarray(lw.astype(np.float32 if policy == ile.ILE_FP32 else np.float64)))
-    t = t.to("cuda")
-    return ile.ile_marginalize(job, len(lw), t, flags)
+def _gpu_marg(job, lw, policy, flags=ile.ILE_MARG_RESET, offset=0):
+    """`offset` > 0 places lw that many elements into its buffer (an input
+    that is not 16-byte aligned)."""
+    dt = np.float32 if policy == ile.ILE_FP32 else np.float64
+    buf = np.zeros(len(lw) + offset, dtype=dt)
+    buf[offset:] = lw
+    t = torch.from_numpy(buf).to("cuda")
+    return ile.ile_marginalize(job, len(lw), t[offset:], flags)
 
 
 @pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
@@ -208,13 +212,19 @@ def test_marginalize_parity(orc, policy):
     p = chirpgen.random_problem(rng, 5, ["H", "L"])
     job = ile.ile_prepare(gu.ctx(), ile.ProblemHost(p, precision=policy))
     try:
-        cases = [rng.uniform(-1e5, 1e5, 100003), rng.normal(size=70001) * 30 - 500,
-                 np.full(5000, -3.25), np.array([7.0]), np.array([-np.inf] * 17),
-                 np.concatenate([rng.normal(size=4000), [np.inf, np.nan, -np.inf]])]
-        for lw in cases:
+        inner = rng.normal(size=40000) * 50
+        inner[[100, 2049, 9000]] = [np.inf, np.nan, -np.inf]      # inside full vector steps
+        inner[[777, 30000]] = 400.0                              # tied maxima: the lower index wins
+        far = rng.normal(size=60000) - 200.0                     # most terms below the skip cut
+        far[[5, 33333]] = [-150.0, 10.0]
+        cases = [(rng.uniform(-1e5, 1e5, 100003), 0), (rng.normal(size=70001) * 30 - 500, 0),
+                 (np.full(5000, -3.25), 0), (np.array([7.0]), 0), (np.array([-np.inf] * 17), 0),
+                 (np.concatenate([rng.normal(size=4000), [np.inf, np.nan, -np.inf]]), 0),
+                 (inner, 0), (far, 0), (rng.normal(size=50007) * 10, 1), (inner, 3)]
+        for lw, off in cases:
             if policy == ile.ILE_FP32:
                 lw = lw.astype(np.float32).astype(np.float64)
-            r = _gpu_marg(job, lw, policy)
+            r = _gpu_marg(job, lw, policy, offset=off)
             o = orc.marginalize(lw)
             assert r["n"] == o["n"] and r["n_nonfinite"] == o["n_nonfinite"] and r["argmax"] == o["argmax"]
             if o["ln_L"] == -np.inf:
