@@ -222,7 +222,10 @@ def main():
     ap.add_argument("--adaptive-jobs", type=int, default=500)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--probe", action="store_true",
-                    help="counter probe: one 1 GiB device copy (known bytes) then one FP32 step")
+                    help="counter probe: one 1 GiB device copy (known bytes) then one step")
+    ap.add_argument("--probe-policy", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--adaptive-only", action="store_true",
+                    help="run only the adaptive serving leg (--adaptive-jobs jobs) and print its summary")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the path shards by "
@@ -242,9 +245,15 @@ def main():
         dst.copy_(src)                      # reference kernel: reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del src, dst
-        r = run_policy(ile, torch, ctx, probs, ile.ILE_FP32, n_per, 1, 0, stream)
-        print(json.dumps({"probe": True, "samples": r["N"], "kernel_ms": r["kernel_ms"],
+        pol = ile.ILE_FP32 if a.probe_policy == "fp32" else ile.ILE_FP64
+        r = run_policy(ile, torch, ctx, probs, pol, n_per, 1, 0, stream)
+        print(json.dumps({"probe": True, "policy": a.probe_policy, "samples": r["N"], "kernel_ms": r["kernel_ms"],
                           "lnl_src_sha256": lnl_src_sha256()}), flush=True)
+        return
+    if a.adaptive_only:
+        pool = serving_pool(8, 250511655 + 4)
+        ada = serving_leg(ile, ctx, pool, a.adaptive_jobs, True, 13, ile.ILE_FP32)
+        print(json.dumps({"adaptive_saturated": ada}), flush=True)
         return
     log("fp32 ...")
     r32 = run_policy(ile, torch, ctx, probs, ile.ILE_FP32, n_per, a.steps, a.warmup, stream)

@@ -91,7 +91,7 @@ void eval_geometry(const ile_job *job, int64_t n, size_t *lds, int64_t *tile, in
     // stage the window in LDS only when each block gets enough samples to pay for it
     if (job_lds_ok(job) && n >= (int64_t)2 * cus * 16384) {
         *lds = win;
-        *block = lds_block_threads(job->policy);
+        *block = lds_block_threads(job->set, job->policy);
         *tile = std::max<int64_t>(16384, (n + 2 * cus - 1) / (2 * cus));
     } else {
         *lds = 0;
@@ -658,7 +658,7 @@ ile_status eval_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, hipStre
         const auto &key = g.first;
         hipError_t e = launch_eval(std::get<0>(key), std::get<1>(key), std::get<2>(key), std::get<3>(key) != 0,
                                    lds ? win : 0, (const EvalJob *)dj, (const Tile *)dt, (int)tiles.size(), ej[0],
-                                   tile, lds ? lds_block_threads(std::get<2>(key)) : 256, st);
+                                   tile, lds ? lds_block_threads(std::get<0>(key), std::get<2>(key)) : 256, st);
         if (e != hipSuccess) return dev_fail(ctx, e, "batched eval launch");
         if ((s = batch_done(ctx, slot, st)) != ILE_OK) return s;
     }
@@ -848,15 +848,25 @@ static ile_status ensure_gmm(ile_job *job) {
     return ILE_OK;
 }
 
-static ile_status estimate_mass(ile_job *job, const ile_gmm_opts *o, hipStream_t st) {
-    const uint64_t seed = o ? o->seed : 0x243F6A8885A308D3ull;
-    const uint32_t round = o ? o->round : 0;
-    const int64_t m = (o && o->z_draws > 0) ? o->z_draws : 65536;
-    hipError_t e = hipMemsetAsync(job->d_zcount, 0, kMaxComp * sizeof(uint32_t), st);
-    if (e == hipSuccess) e = launch_gmm_inbox(job->d_gmm, job->pr, seed, round, m, job->d_zcount, st);
-    if (e == hipSuccess) e = launch_gmm_setz(job->d_gmm, job->d_zcount, m, st);
-    if (e != hipSuccess) return dev_fail(job->ctx, e, "in-support mass");
-    return ILE_OK;
+// Factor the job's uploaded mixture and estimate its in-support masses.
+static ile_status factor_and_mass(ile_job *job, const ile_gmm_opts *o, hipStream_t st) {
+    ile_ctx *ctx = job->ctx;
+    EmJob e{};
+    e.gmm = job->d_gmm;
+    e.zcount = job->d_zcount;
+    e.pr = job->pr;
+    e.z_seed = o ? o->seed : 0x243F6A8885A308D3ull;
+    e.z_round = o ? o->round : 0;
+    e.z_draws = (o && o->z_draws > 0) ? o->z_draws : 65536;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    void *dj = nullptr, *dn = nullptr;
+    int slot = -1;
+    ile_status s = batch_upload(ctx, &e, sizeof e, nullptr, 0, &dj, &dn, &slot, st);
+    if (s != ILE_OK) return s;
+    hipError_t err = launch_gmm_factor((const EmJob *)dj, 1, st);
+    if (err == hipSuccess) err = launch_gmm_mass((const EmJob *)dj, 1, st);
+    if (err != hipSuccess) return dev_fail(ctx, err, "factor and in-support mass");
+    return batch_done(ctx, slot, st);
 }
 
 }  // namespace ile
@@ -892,8 +902,7 @@ extern "C" ile_status ile_set_proposal(ile_job *job, const ile_gmm_params *p, co
     }
     if ((e = hipMemcpyAsync(job->d_gmm, job->h_gmm, sizeof(GmmDev), hipMemcpyHostToDevice, st)) != hipSuccess)
         return dev_fail(job->ctx, e, "proposal upload");
-    if ((e = launch_gmm_factor(job->d_gmm, st)) != hipSuccess) return dev_fail(job->ctx, e, "factor");
-    if ((s = estimate_mass(job, opts, st)) != ILE_OK) return s;
+    if ((s = factor_and_mass(job, opts, st)) != ILE_OK) return s;
     if ((e = hipMemcpyAsync(job->h_gmm, job->d_gmm, sizeof(GmmDev), hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
         return dev_fail(job->ctx, e, "proposal readback");
@@ -929,47 +938,71 @@ extern "C" ile_status ile_get_proposal(ile_job *job, ile_gmm_params *p, ile_stre
 }
 
 namespace ile {
-ile_status job_adapt(ile_job *job, int64_t n, const void *theta, int64_t ld, const void *lw, const ile_gmm_opts *o,
-                     hipStream_t st) {
-    ile_ctx *ctx = job->ctx;
-    ile_status s;
-    if ((s = ensure_gmm(job)) != ILE_OK) return s;
-    const size_t need = em_work_bytes(n);
-    if (need > job->em_cap) {
-        hipError_t e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return dev_fail(ctx, e, "sync before EM workspace growth");
-        ctx_free(ctx, job->d_em, job->em_cap);
-        job->d_em = nullptr;
-        job->em_cap = 0;
-        if ((s = ctx_alloc(ctx, (void **)&job->d_em, need, "EM workspace")) != ILE_OK) return s;
-        job->em_cap = need;
-    }
+ile_status adapt_batch(ile_ctx *ctx, int policy, const std::vector<AdaptItem> &items, const ile_gmm_opts *o,
+                       hipStream_t st) {
+    if (items.empty()) return ILE_OK;
     const int n_comp = (o && o->n_comp > 0) ? o->n_comp : 8;
     const int n_iter = (o && o->n_iter > 0) ? o->n_iter : 8;
     const double eps = (o && o->eps_def >= 0 && o->eps_def < 1) ? o->eps_def : 0.05;
     if (n_comp > kMaxComp) return set_err(ILE_E_INVALID, "n_comp must be 1..16");
+    if (n_iter > 1000) return set_err(ILE_E_INVALID, "n_iter must be at most 1000");
     const double temper = (o && o->temper_ess > 0) ? std::min(o->temper_ess, 1.0) : 0.0;
-    hipError_t e = launch_em_prepare(job->policy, lw, n, job->d_em, job->em_cap, temper, st);
-    if (e != hipSuccess) return dev_fail(ctx, e, "EM weights");
-    if (!job->has_prop) {
-        GmmDev &g = *job->h_gmm;
-        std::memset(&g, 0, sizeof g);
-        default_dims(job, &g.n_dim, g.dims);
-        g.n_comp = n_comp;
-        g.eps_def = eps;
-        e = hipStreamSynchronize(st);
-        if (e == hipSuccess) e = hipMemcpyAsync(job->d_gmm, job->h_gmm, sizeof(GmmDev), hipMemcpyHostToDevice, st);
-        if (e == hipSuccess)
-            e = launch_em_top(job->policy, theta, ld, lw, n, job->d_gmm, n_comp, job->d_em, job->em_cap, job->pr, st);
-        if (e != hipSuccess) return dev_fail(ctx, e, "EM first fit");
+    const int64_t z_draws = (o && o->z_draws > 0) ? o->z_draws : 65536;
+    if (items.size() > 65535) return set_err(ILE_E_INVALID, "too many jobs in one refit");
+    std::vector<EmJob> ej(items.size());
+    for (size_t k = 0; k < items.size(); k++) {
+        const AdaptItem &it = items[k];
+        ile_job *job = it.job;
+        if (job->policy != policy) return set_err(ILE_E_INVALID, "refit batch mixes precision policies");
+        ile_status s;
+        if ((s = ensure_gmm(job)) != ILE_OK) return s;
+        const size_t need = em_work_bytes(it.n);
+        if (need > job->em_cap) {
+            hipError_t e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return dev_fail(ctx, e, "sync before EM workspace growth");
+            ctx_free(ctx, job->d_em, job->em_cap);
+            job->d_em = nullptr;
+            job->em_cap = 0;
+            if ((s = ctx_alloc(ctx, (void **)&job->d_em, need, "EM workspace")) != ILE_OK) return s;
+            job->em_cap = need;
+        }
+        EmJob &e = ej[k];
+        e.theta = it.theta;
+        e.ld = it.ld;
+        e.lw = it.lw;
+        e.n = it.n;
+        e.gmm = job->d_gmm;
+        e.work = job->d_em;
+        e.zcount = job->d_zcount;
+        e.pr = job->pr;
+        e.n_comp = n_comp;
+        e.first = job->has_prop ? 0 : 1;
+        default_dims(job, &e.n_dim, e.dims);
+        e.eps_def = eps;
+        e.temper = temper;
+        e.z_seed = it.z_seed;
+        e.z_round = it.z_round;
+        e.z_draws = z_draws;
     }
-    for (int it = 0; it < n_iter; it++) {
-        e = launch_em_iter(job->policy, theta, ld, lw, n, job->d_gmm, job->d_em, job->em_cap, job->pr, st);
-        if (e != hipSuccess) return dev_fail(ctx, e, "EM iteration");
+    {
+        std::lock_guard<std::mutex> lk(ctx->batch_mu);
+        void *dj = nullptr, *dn = nullptr;
+        int slot = -1;
+        ile_status s = batch_upload(ctx, ej.data(), ej.size() * sizeof(EmJob), nullptr, 0, &dj, &dn, &slot, st);
+        if (s != ILE_OK) return s;
+        hipError_t e = launch_em_batch(policy, (const EmJob *)dj, ej.data(), (int)ej.size(), n_iter, st);
+        if (e == hipSuccess) e = launch_gmm_mass((const EmJob *)dj, (int)ej.size(), st);
+        if (e != hipSuccess) return dev_fail(ctx, e, "batched mixture refit");
+        if ((s = batch_done(ctx, slot, st)) != ILE_OK) return s;
     }
-    if ((s = estimate_mass(job, o, st)) != ILE_OK) return s;
-    job->has_prop = true;
+    for (const AdaptItem &it : items) it.job->has_prop = true;
     return ILE_OK;
+}
+
+ile_status job_adapt(ile_job *job, int64_t n, const void *theta, int64_t ld, const void *lw, const ile_gmm_opts *o,
+                     hipStream_t st) {
+    AdaptItem it{job, n, theta, ld, lw, o ? o->seed : 0x243F6A8885A308D3ull, o ? o->round : 0u};
+    return adapt_batch(job->ctx, job->policy, std::vector<AdaptItem>{it}, o, st);
 }
 }  // namespace ile
 

@@ -136,6 +136,21 @@ ile_status marg_batch(ile_ctx *ctx, ile_job *const *jobs, int n_jobs, const int6
 ile_status job_marg_launch(ile_job *job, int64_t n, const void *lw, bool reset, hipStream_t st);
 ile_status job_adapt(ile_job *job, int64_t n, const void *theta, int64_t ld, const void *lw, const ile_gmm_opts *o,
                      hipStream_t st);
+// One job of a batched refit: its samples and the key/round of its in-support
+// mass draws.
+struct AdaptItem {
+    ile_job *job;
+    int64_t n;
+    const void *theta;
+    int64_t ld;
+    const void *lw;
+    uint64_t z_seed;
+    uint32_t z_round;
+};
+// Refit the mixtures of several jobs of one precision policy with the same
+// options: every EM stage and the mass estimate are one launch for all jobs.
+ile_status adapt_batch(ile_ctx *ctx, int policy, const std::vector<AdaptItem> &items, const ile_gmm_opts *o,
+                       hipStream_t st);
 void marg_from_state(const MargState &m, ile_marg *out);
 void eval_geometry(const ile_job *job, int64_t n, size_t *lds, int64_t *tile, int *block);
 size_t theta_size(int policy);

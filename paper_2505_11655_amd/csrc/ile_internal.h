@@ -14,8 +14,13 @@ namespace ile {
 enum Policy : int { kFP64 = 0, kFP32 = 1, kMixed = 2 };
 
 // Threads per block of the LDS-staged likelihood kernel: one window per CU,
-// as many waves as the policy's register use allows without spilling.
-constexpr int lds_block_threads(int policy) { return policy == kFP32 ? 1024 : 512; }
+// as many waves as the register use of the mode set (index 0..3, 5/9/17/21
+// modes) and policy allows without spilling: 1024 (128 VGPRs) only for FP32
+// with up to 9 modes, 256 for the 21-mode set (its window leaves room for one
+// block per CU anyway), 512 otherwise.
+constexpr int lds_block_threads(int set, int policy) {
+    return (policy == kFP32 && set <= 1) ? 1024 : (set >= 3 ? 256 : 512);
+}
 
 // ----------------------------------------------------------------- mode sets
 // Compiled harmonic sets.  A job's mode list is placed into the smallest set
@@ -169,6 +174,7 @@ struct DistTable {
     double u0, du, b0, db;
     double s_min, s_max;  // d_ref/d_max, d_ref/d_min
     double a_scale;       // a = a_scale * sinh(u)
+    double inv_du, inv_db, inv_a_scale;
 };
 
 struct EvalJob {
@@ -272,19 +278,36 @@ hipError_t launch_marg_batch(int policy, const MargJob *d_jobs, int n_jobs, cons
 hipError_t launch_draw(int policy, const DrawJob *d_jobs, const Tile *d_tiles, int n_tiles,
                        const DrawJob &single, int64_t tile, bool mix, hipStream_t st);
 
-hipError_t launch_gmm_factor(GmmDev *d_gmm, hipStream_t st);
-hipError_t launch_gmm_inbox(GmmDev *d_gmm, PriorDev pr, uint64_t seed, uint32_t round, int64_t m,
-                            uint32_t *d_count, hipStream_t st);
-hipError_t launch_gmm_setz(GmmDev *d_gmm, const uint32_t *d_count, int64_t m, hipStream_t st);
-// max lw and the tempering exponent of this sample set (must precede em_top/em_iter)
-hipError_t launch_em_prepare(int policy, const void *lw, int64_t n, double *d_work, size_t work_bytes,
-                             double temper_frac, hipStream_t st);
-hipError_t launch_em_top(int policy, const void *theta, int64_t ld, const void *lw, int64_t n,
-                         GmmDev *d_gmm, int n_comp, double *d_work, size_t work_bytes,
-                         PriorDev pr, hipStream_t st);
-hipError_t launch_em_iter(int policy, const void *theta, int64_t ld, const void *lw, int64_t n,
-                          GmmDev *d_gmm, double *d_work, size_t work_bytes, PriorDev pr,
-                          hipStream_t st);
+// One job of a batched mixture refit or mass estimate.  Every stage is one
+// launch over all jobs of the batch (one sample type per launch).
+struct EmJob {
+    const void *theta;    // [7][ld] samples (policy theta type)
+    int64_t ld;
+    const void *lw;       // [n] log-weights (policy weight type)
+    int64_t n;
+    GmmDev *gmm;
+    double *work;         // em_work_bytes(n) bytes
+    uint32_t *zcount;     // [kMaxComp] in-support counters
+    PriorDev pr;
+    int n_comp;           // first fit: components
+    int first;            // 1: first fit from the highest-weight samples
+    int n_dim;            // first fit: mixture columns
+    int dims[7];
+    double eps_def;       // first fit: defensive prior fraction
+    double temper;        // ESS fraction of the tempering rule (<= 0: beta = 1)
+    uint64_t z_seed;      // in-support mass: Philox key, round, number of draws
+    uint32_t z_round;
+    int64_t z_draws;
+};
+
+// Factor every job's mixture (Cholesky, inverse, log-weights).
+hipError_t launch_gmm_factor(const EmJob *d_jobs, int n_jobs, hipStream_t st);
+// In-support masses Z_j of every job's mixture from z_draws candidates each.
+hipError_t launch_gmm_mass(const EmJob *d_jobs, int n_jobs, hipStream_t st);
+// Weighted EM refit of every job: max and tempering exponent, first fit for
+// jobs with `first`, then n_iter iterations.  h_jobs: host copy of d_jobs.
+hipError_t launch_em_batch(int policy, const EmJob *d_jobs, const EmJob *h_jobs, int n_jobs, int n_iter,
+                           hipStream_t st);
 size_t em_work_bytes(int64_t n);
 
 hipError_t build_dist_table(DistTable *tab, double *d_buf, PriorDev pr, hipStream_t st);

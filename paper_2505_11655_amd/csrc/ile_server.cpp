@@ -233,16 +233,21 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
                         s->active.end());
     }
     s->cv_done.notify_all();
-    for (Req *r : refit) {
-        ile_gmm_opts o{};
-        o.n_comp = 8;
-        o.n_iter = 8;
-        o.eps_def = 0.05;
-        o.seed = r->jo.seed ^ 0x9E3779B97F4A7C15ull;
-        o.round = (uint32_t)r->rounds;
-        o.z_draws = 65536;
-        o.temper_ess = 1.0 / 16.0;
-        if (job_adapt(r->job, r->chunk, r->d_theta, r->chunk, r->d_lw, &o, st) != ILE_OK) return false;
+    // one batched refit per precision policy; each job's mass draws use its
+    // own key and round
+    ile_gmm_opts o{};
+    o.n_comp = 8;
+    o.n_iter = 8;
+    o.eps_def = 0.05;
+    o.z_draws = 65536;
+    o.temper_ess = 1.0 / 16.0;
+    for (int pol = 0; pol < 3; pol++) {
+        std::vector<AdaptItem> items;
+        for (Req *r : refit)
+            if (r->job->policy == pol)
+                items.push_back(AdaptItem{r->job, r->chunk, r->d_theta, r->chunk, r->d_lw,
+                                          r->jo.seed ^ 0x9E3779B97F4A7C15ull, (uint32_t)r->rounds});
+        if (!items.empty() && adapt_batch(s->ctx, pol, items, &o, st) != ILE_OK) return false;
     }
     return true;
 }

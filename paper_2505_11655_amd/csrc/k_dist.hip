@@ -108,6 +108,9 @@ hipError_t build_dist_table(DistTable *tb, double *d_buf, PriorDev pr, hipStream
     tb->s_min = s_min;
     tb->s_max = s_max;
     tb->a_scale = kAScale;
+    tb->inv_du = 1.0 / tb->du;
+    tb->inv_db = 1.0 / tb->db;
+    tb->inv_a_scale = 1.0 / kAScale;
     return hipGetLastError();
 }
 

@@ -87,10 +87,17 @@ __device__ __forceinline__ void prior_from_words(const PriorDev &pr, const uint3
     th[6] = kPi * u[6];
 }
 
-// wrapped difference in (-P/2, P/2]
+// wrapped difference in (-P/2, P/2]: d - P floor(d/P), folded; for |d| < P
+// the same value without the division
 __device__ __forceinline__ double wrapd(double d, double P) {
     if (P <= 0.0) return d;
-    double r = d - P * floor(d / P);
+    double r;
+    if (d >= 0.0 && d < P)
+        r = d;
+    else if (d < 0.0 && d >= -P)
+        r = d + P;
+    else
+        r = d - P * floor(d / P);
     return r > 0.5 * P ? r - P : r;
 }
 
@@ -276,28 +283,35 @@ hipError_t launch_draw(int policy, const DrawJob *d_jobs, const Tile *d_tiles, i
 }
 
 // ------------------------------------------------------------------ in-support mass
+// Z_j of each job's mixture: the fraction of z_draws candidates of component j
+// (Philox counter (i, 0x5A000000 + j, round, block)) that fall in the support.
 namespace {
 
 constexpr int kZThreads = 256;
+constexpr int kZBlocks = 64;
 
-__global__ void __launch_bounds__(kZThreads)
-    k_gmm_inbox(const GmmDev *__restrict__ gp, PriorDev pr, uint64_t seed, uint32_t round, int64_t m,
-                uint32_t *__restrict__ count) {
-    const GmmDev &g = *gp;
+__global__ void k_gmm_zero(const EmJob *__restrict__ jobs) {
+    if (threadIdx.x < kMaxComp) jobs[blockIdx.z].zcount[threadIdx.x] = 0u;
+}
+
+__global__ void __launch_bounds__(kZThreads) k_gmm_inbox(const EmJob *__restrict__ jobs) {
+    const EmJob &J = jobs[blockIdx.z];
+    const GmmDev &g = *J.gmm;
     const int j = blockIdx.y;
     __shared__ uint32_t sacc[kZThreads];
     uint32_t acc = 0;
     if (j < g.n_comp) {
-        const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-        for (int64_t i = (int64_t)blockIdx.x * kZThreads + threadIdx.x; i < m; i += (int64_t)gridDim.x * kZThreads) {
+        const uint32_t k0 = (uint32_t)J.z_seed, k1 = (uint32_t)(J.z_seed >> 32);
+        for (int64_t i = (int64_t)blockIdx.x * kZThreads + threadIdx.x; i < J.z_draws;
+             i += (int64_t)gridDim.x * kZThreads) {
             uint32_t w[16];
 #pragma unroll
             for (int b = 0; b < 4; b++) {
-                U4 o = philox4x32_10(U4{(uint32_t)i, 0x5A000000u + (uint32_t)j, round, (uint32_t)b}, k0, k1);
+                U4 o = philox4x32_10(U4{(uint32_t)i, 0x5A000000u + (uint32_t)j, J.z_round, (uint32_t)b}, k0, k1);
                 w[4 * b] = o.x; w[4 * b + 1] = o.y; w[4 * b + 2] = o.z; w[4 * b + 3] = o.w;
             }
-            double th[7] = {0, 0, 0, pr.d_ref, 0, 0, 0};
-            acc += gmm_candidate(g, pr, j, w, th) ? 1u : 0u;
+            double th[7] = {0, 0, 0, J.pr.d_ref, 0, 0, 0};
+            acc += gmm_candidate(g, J.pr, j, w, th) ? 1u : 0u;
         }
     }
     sacc[threadIdx.x] = acc;
@@ -306,28 +320,27 @@ __global__ void __launch_bounds__(kZThreads)
         if (threadIdx.x < w) sacc[threadIdx.x] += sacc[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && j < g.n_comp) atomicAdd(&count[j], sacc[0]);
+    if (threadIdx.x == 0 && j < g.n_comp) atomicAdd(&J.zcount[j], sacc[0]);
 }
 
-__global__ void k_gmm_setz(GmmDev *g, const uint32_t *count, int64_t m) {
+__global__ void k_gmm_setz(const EmJob *__restrict__ jobs) {
+    const EmJob &J = jobs[blockIdx.z];
+    GmmDev *g = J.gmm;
     const int j = threadIdx.x;
     if (j < g->n_comp) {
-        const double c = (double)count[j];
-        g->lnZ[j] = log((c > 0 ? c : 0.5) / (double)m);
+        const double c = (double)J.zcount[j];
+        g->lnZ[j] = log((c > 0 ? c : 0.5) / (double)J.z_draws);
     }
 }
 
 }  // namespace
 
-hipError_t launch_gmm_inbox(GmmDev *d_gmm, PriorDev pr, uint64_t seed, uint32_t round, int64_t m,
-                            uint32_t *d_count, hipStream_t st) {
-    hipLaunchKernelGGL(k_gmm_inbox, dim3(64, kMaxComp), dim3(kZThreads), 0, st, d_gmm, pr, seed, round, m,
-                       d_count);
-    return hipGetLastError();
-}
-
-hipError_t launch_gmm_setz(GmmDev *d_gmm, const uint32_t *d_count, int64_t m, hipStream_t st) {
-    hipLaunchKernelGGL(k_gmm_setz, dim3(1), dim3(64), 0, st, d_gmm, d_count, m);
+hipError_t launch_gmm_mass(const EmJob *d_jobs, int n_jobs, hipStream_t st) {
+    if (n_jobs <= 0) return hipSuccess;
+    if (n_jobs > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gmm_zero, dim3(1, 1, n_jobs), dim3(64), 0, st, d_jobs);
+    hipLaunchKernelGGL(k_gmm_inbox, dim3(kZBlocks, kMaxComp, n_jobs), dim3(kZThreads), 0, st, d_jobs);
+    hipLaunchKernelGGL(k_gmm_setz, dim3(1, 1, n_jobs), dim3(64), 0, st, d_jobs);
     return hipGetLastError();
 }
 

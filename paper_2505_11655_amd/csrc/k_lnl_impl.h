@@ -95,30 +95,45 @@ __device__ __forceinline__ void static_for(F &&f) {
 
 // Distance-marginalised lnL from the residual table (bicubic Lagrange),
 // ln L_D = r(a, b) + a^2, a = T1/sqrt(T2), b = ln T2.  Out of table: -inf.
-__device__ __forceinline__ double dist_lookup(const DistTable &tb, double T1, double T2) {
-    if (!(T2 > 0.0)) return -INFINITY;
-    double b = log(T2);
-    double a = T1 / sqrt(T2);
-    double u = asinh(a / tb.a_scale);
-    double xu = (u - tb.u0) / tb.du;
-    double xb = (b - tb.b0) / tb.db;
-    double fu = floor(xu), fb = floor(xb);
-    if (!(fu >= 1.0 && fu <= (double)(tb.nu - 3) && fb >= 1.0 && fb <= (double)(tb.nb - 3)))
-        return -INFINITY;
-    int iu = (int)fu, ib = (int)fb;
-    double gu = xu - fu, gb = xb - fb;
-    double wu[4] = {-gu * (gu - 1.0) * (gu - 2.0) / 6.0, (gu + 1.0) * (gu - 1.0) * (gu - 2.0) * 0.5,
-                    -(gu + 1.0) * gu * (gu - 2.0) * 0.5, (gu + 1.0) * gu * (gu - 1.0) / 6.0};
-    double wb[4] = {-gb * (gb - 1.0) * (gb - 2.0) / 6.0, (gb + 1.0) * (gb - 1.0) * (gb - 2.0) * 0.5,
-                    -(gb + 1.0) * gb * (gb - 2.0) * 0.5, (gb + 1.0) * gb * (gb - 1.0) / 6.0};
+// The table coordinates are computed in TC (the policy's contraction type:
+// FP32 for the FP32 policy, where T1 and T2 are FP32 values themselves);
+// the FP64 table values are interpolated in FP64.
+template <class TC>
+__device__ __forceinline__ double dist_lookup(const DistTable &tb, TC T1, TC T2) {
+    // branch-free: an input outside the table (or T2 <= 0, or NaN) reads the
+    // clamped first cell and returns -inf
+    const bool pos = T2 > (TC)0;
+    const TC T2s = pos ? T2 : (TC)1;
+    TC b, a, u;
+    if constexpr (sizeof(TC) == 4) {
+        b = logf(T2s);
+        a = T1 / sqrtf(T2s);
+        u = asinhf(a * (float)tb.inv_a_scale);
+    } else {
+        b = log(T2s);
+        a = T1 / sqrt(T2s);
+        u = asinh(a * tb.inv_a_scale);
+    }
+    const TC xu = (u - (TC)tb.u0) * (TC)tb.inv_du;
+    const TC xb = (b - (TC)tb.b0) * (TC)tb.inv_db;
+    TC fu = floor(xu), fb = floor(xb);
+    const bool in = pos && fu >= (TC)1 && fu <= (TC)(tb.nu - 3) && fb >= (TC)1 && fb <= (TC)(tb.nb - 3);
+    fu = in ? fu : (TC)1;
+    fb = in ? fb : (TC)1;
+    const int iu = (int)fu, ib = (int)fb;
+    const double gu = (double)(xu - fu), gb = (double)(xb - fb);
+    const double wu[4] = {-gu * (gu - 1.0) * (gu - 2.0) / 6.0, (gu + 1.0) * (gu - 1.0) * (gu - 2.0) * 0.5,
+                          -(gu + 1.0) * gu * (gu - 2.0) * 0.5, (gu + 1.0) * gu * (gu - 1.0) / 6.0};
+    const double wb[4] = {-gb * (gb - 1.0) * (gb - 2.0) / 6.0, (gb + 1.0) * (gb - 1.0) * (gb - 2.0) * 0.5,
+                          -(gb + 1.0) * gb * (gb - 2.0) * 0.5, (gb + 1.0) * gb * (gb - 1.0) / 6.0};
     double r = 0.0;
 #pragma unroll
     for (int jb = 0; jb < 4; jb++) {
         const double *row = tb.r + (size_t)(ib - 1 + jb) * tb.nu + (iu - 1);
-        double acc = wu[0] * row[0] + wu[1] * row[1] + wu[2] * row[2] + wu[3] * row[3];
+        const double acc = wu[0] * row[0] + wu[1] * row[1] + wu[2] * row[2] + wu[3] * row[3];
         r += wb[jb] * acc;
     }
-    return r + a * a;
+    return in ? r + (double)a * (double)a : -INFINITY;
 }
 
 template <int S, int K, int POL, bool LDS, bool DM>
@@ -343,7 +358,7 @@ struct LnlKernel {
             // ---- combine
             TA lnL;
             if constexpr (DM) {
-                lnL = (TA)dist_lookup(J.dt, (double)T1, (double)T2);
+                lnL = (TA)dist_lookup<TA>(J.dt, T1, T2);
             } else {
                 const TA s = pick<TA>(J.d_ref, J.d_reff) / (TA)DD;
                 lnL = s * T1 - s * s * T2 * (TA)0.25;
@@ -356,15 +371,15 @@ struct LnlKernel {
 };
 
 // Minimum waves per SIMD asked of the register allocator: two, except for the
-// 17/21-mode sets with FP64 contractions, whose live state does not fit in
-// 256 VGPRs without spilling.
+// 17/21-mode sets with FP64 contractions and the 21-mode set in FP32, whose
+// live state does not fit in 256 VGPRs without spilling.
 template <int S, int POL>
 constexpr int lnl_min_waves() {
-    return (S >= 2 && POL != kFP32) ? 1 : 2;
+    return ((S >= 2 && POL != kFP32) || S == 3) ? 1 : 2;
 }
 
 template <int S, int K, int POL, bool LDS, bool DM>
-__global__ void __launch_bounds__(LDS ? lds_block_threads(POL) : 256, (lnl_min_waves<S, POL>()))
+__global__ void __launch_bounds__(LDS ? lds_block_threads(S, POL) : 256, (lnl_min_waves<S, POL>()))
     k_lnl(const EvalJob *__restrict__ jobs, const Tile *__restrict__ tiles, const EvalJob single,
           const int64_t tile) {
     extern __shared__ __align__(16) char ile_smem[];
@@ -391,7 +406,7 @@ hipError_t launch_eval_sp(int kdet, bool dm, size_t lds_bytes, const EvalJob *jo
                           const EvalJob &single, int64_t tile, int nthreads, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
     const bool lds = lds_bytes > 0;
-    if (nthreads <= 0 || nthreads > (lds ? lds_block_threads(POL) : 256) || nthreads % 64) return hipErrorInvalidValue;
+    if (nthreads <= 0 || nthreads > (lds ? lds_block_threads(S, POL) : 256) || nthreads % 64) return hipErrorInvalidValue;
     if (dm && POL == kMixed) return hipErrorInvalidValue;
     dim3 grid(n_tiles), block(nthreads);
     auto go = [&](auto KK, auto LL, auto DD) -> hipError_t {
