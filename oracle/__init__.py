@@ -182,6 +182,36 @@ def lnL(prob, theta, threads=None, return_terms=False):
     return out
 
 
+def tmarg_grid(prob, oversample=4):
+    """Nodes of the time integral: t_j = j dt/R, |j| <= floor(R t_w / dt)
+    (relative to the reference time), each with weight dt / (R 2 t_w) against
+    the uniform time prior on [-t_w, t_w]."""
+    R = int(oversample)
+    J = int(math.floor(R * prob.t_window / prob.dt + 1e-9))
+    j = np.arange(-J, J + 1)
+    return j * (prob.dt / R), math.log(prob.dt / (R * 2.0 * prob.t_window))
+
+
+def lnL_tmarg(prob, theta, oversample=4, threads=None):
+    """Time-marginalised likelihood: the (time) x (extrinsic) array of
+    eq. (lnL:MatrixForm) integrated over the geocentric time prior by the
+    rectangle rule on the nodes of ``tmarg_grid``:
+        ln L_t = ln sum_j (dt / (R 2 t_w)) exp lnL(theta with t = t_j).
+    The t row of theta is ignored.  Every node is the pointwise oracle lnL."""
+    th = np.asarray(theta, dtype=np.float64)
+    n = th.shape[1]
+    tj, lnw = tmarg_grid(prob, oversample)
+    nt = len(tj)
+    big = np.repeat(th, nt, axis=1)
+    big[2] = np.tile(tj, n)
+    L = lnL(prob, big, threads=threads).reshape(n, nt)
+    m = np.max(L, axis=1)
+    out = np.full(n, -np.inf)
+    fin = np.isfinite(m)
+    out[fin] = m[fin] + np.log(np.sum(np.exp(L[fin] - m[fin, None]), axis=1)) + lnw
+    return out
+
+
 def sample_tau(prob, th7):
     h = _Holder(prob)
     t = np.ascontiguousarray(th7, dtype=np.float64)
