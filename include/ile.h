@@ -146,6 +146,28 @@ ile_status ile_eval_lnL_batch(ile_job *const *jobs, int32_t n_jobs, const int64_
                               const void *const *lnpmps, void *const *lnL_out,
                               void *const *lw_out, ile_stream stream);
 
+/* Time-marginalised likelihood per extrinsic sample: the (time) x (extrinsic)
+ * array of eq. (lnL:MatrixForm) integrated over the geocentric time prior
+ * U[-t_window, t_window] by the rectangle rule on the nodes t_j = j dt / R,
+ * |j| <= floor(R t_window / dt) (dt = the window's sample step), each weighted
+ * dt / (R 2 t_window):
+ *     lnL_t = ln sum_j (dt / (R 2 t_window)) exp lnL(theta with t = t_j).
+ * The t column of theta is ignored; all other arguments are those of
+ * ile_eval_lnL (lw_out = lnL_t + lnpmps).  oversample R: 1 or 4 (R = 4 resolves
+ * a likelihood peak narrower than dt; the rule's error is O((dt/R)^2)).
+ * ILE_FP32 and ILE_FP64 jobs without dist_marg only; other jobs, or another R,
+ * give ILE_E_INVALID.  A node whose stencil leaves the window contributes 0;
+ * no valid node gives -inf. */
+ile_status ile_eval_lnL_tmarg(ile_job *job, int64_t n, const void *theta, int64_t ld,
+                              const void *lnpmps, void *lnL_out, void *lw_out, int32_t oversample,
+                              ile_stream stream);
+
+/* The same for several jobs in one pass per compiled kernel; arrays of length n_jobs. */
+ile_status ile_eval_lnL_tmarg_batch(ile_job *const *jobs, int32_t n_jobs, const int64_t *n,
+                                    const void *const *theta, const int64_t *ld,
+                                    const void *const *lnpmps, void *const *lnL_out,
+                                    void *const *lw_out, int32_t oversample, ile_stream stream);
+
 /* Monte Carlo estimator of eq. (lnL:MonteCarlo) on log-weights lw (device [n],
  * the lw type of the policy).  The job keeps the pooled (max, S1, S2, N) state.
  * flags: ILE_MARG_RESET clears it first; ILE_MARG_POOL adds this batch to it.

@@ -103,6 +103,11 @@ EXPORTS = {
     "ile_eval_lnL_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int64),
                                      C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_void_p),
                                      C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
+    "ile_eval_lnL_tmarg": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_int32, C.c_void_p]),
+    "ile_eval_lnL_tmarg_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int64),
+                                           C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_void_p),
+                                           C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32, C.c_void_p]),
     "ile_marginalize": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_uint32, C.POINTER(ile_marg),
                                   C.c_void_p]),
     "ile_marginalize_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int64),
@@ -239,6 +244,23 @@ def ile_eval_lnL_batch(jobs, n, theta, ld, lnpmps, lnL_out, lw_out=None, stream=
         VP(*[_p(t) for t in lnpmps]) if lnpmps is not None else None,
         VP(*[_p(t) for t in lnL_out]),
         VP(*[_p(t) for t in lw_out]) if lw_out is not None else None, _s(stream)))
+
+
+def ile_eval_lnL_tmarg(job, n, theta, ld, lnpmps, lnL_out, lw_out=None, oversample=4, stream=None):
+    _chk(lib().ile_eval_lnL_tmarg(job, n, _p(theta), ld, _p(lnpmps), _p(lnL_out), _p(lw_out), oversample,
+                                  _s(stream)))
+
+
+def ile_eval_lnL_tmarg_batch(jobs, n, theta, ld, lnpmps, lnL_out, lw_out=None, oversample=4, stream=None):
+    k = len(jobs)
+    VP = C.c_void_p * k
+    I64 = C.c_int64 * k
+    _chk(lib().ile_eval_lnL_tmarg_batch(
+        VP(*[j.value if isinstance(j, C.c_void_p) else j for j in jobs]), k, I64(*n),
+        VP(*[_p(t) for t in theta]), I64(*ld),
+        VP(*[_p(t) for t in lnpmps]) if lnpmps is not None else None,
+        VP(*[_p(t) for t in lnL_out]),
+        VP(*[_p(t) for t in lw_out]) if lw_out is not None else None, oversample, _s(stream)))
 
 
 def ile_marginalize(job, n, lw, flags=ILE_MARG_RESET, want=True, stream=None):

@@ -69,6 +69,22 @@ hipError_t launch_eval(int set, int kdet, int policy, bool dm, size_t lds_bytes,
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_tmarg(int set, int kdet, int policy, int R, size_t lds_bytes, const EvalJob *d_jobs,
+                        const Tile *d_tiles, int n_tiles, const EvalJob &single, int64_t tile, int block,
+                        hipStream_t st) {
+#define ILE_TM(S)                                                                                             \
+    if (set == S) {                                                                                           \
+        if (policy == 0) return launch_tmarg_sp<S, 0>(kdet, R, lds_bytes, d_jobs, d_tiles, n_tiles, single, tile, block, st); \
+        if (policy == 1) return launch_tmarg_sp<S, 1>(kdet, R, lds_bytes, d_jobs, d_tiles, n_tiles, single, tile, block, st); \
+    }
+    ILE_TM(0)
+    ILE_TM(1)
+    ILE_TM(2)
+    ILE_TM(3)
+#undef ILE_TM
+    return hipErrorInvalidValue;
+}
+
 // Contraction element size of a policy (Q, U, V storage).
 static size_t creal_size(int policy) { return policy == kFP32 ? sizeof(float) : sizeof(double); }
 size_t theta_size(int policy) { return policy == kFP64 ? sizeof(double) : sizeof(float); }
@@ -609,7 +625,92 @@ extern "C" ile_status ile_eval_lnL_batch(ile_job *const *jobs, int32_t n_jobs, c
     return eval_batch(ctx, items, (hipStream_t)stream);
 }
 
+extern "C" ile_status ile_eval_lnL_tmarg(ile_job *job, int64_t n, const void *theta, int64_t ld,
+                                         const void *lnpmps, void *lnL_out, void *lw_out, int32_t oversample,
+                                         ile_stream stream) {
+    if (!job) return set_err(ILE_E_INVALID, "null job");
+    return ile_eval_lnL_tmarg_batch(&job, 1, &n, &theta, &ld, &lnpmps, &lnL_out, &lw_out, oversample, stream);
+}
+
+extern "C" ile_status ile_eval_lnL_tmarg_batch(ile_job *const *jobs, int32_t n_jobs, const int64_t *n,
+                                               const void *const *theta, const int64_t *ld,
+                                               const void *const *lnpmps, void *const *lnL_out,
+                                               void *const *lw_out, int32_t oversample, ile_stream stream) {
+    if (n_jobs <= 0) return ILE_OK;
+    if (!jobs || !n || !theta || !ld || !lnL_out) return set_err(ILE_E_INVALID, "null argument");
+    ile_ctx *ctx = jobs[0] ? jobs[0]->ctx : nullptr;
+    ile_status s = ctx_check(ctx);
+    if (s != ILE_OK) return s;
+    std::vector<BatchItem> items;
+    for (int j = 0; j < n_jobs; j++) {
+        if (!jobs[j] || jobs[j]->ctx != ctx) return set_err(ILE_E_INVALID, "jobs must share one context");
+        if (n[j] < 0 || ld[j] < n[j]) return set_err(ILE_E_INVALID, "need n >= 0 and ld >= n");
+        if (n[j] > 0 && (!theta[j] || !lnL_out[j])) return set_err(ILE_E_INVALID, "null theta or lnL_out");
+        items.push_back(BatchItem{jobs[j], n[j], theta[j], ld[j], lnpmps ? lnpmps[j] : nullptr, lnL_out[j],
+                                  lw_out ? lw_out[j] : nullptr});
+    }
+    return tmarg_batch(ctx, items, oversample, (hipStream_t)stream);
+}
+
 namespace ile {
+
+// Time-marginalised evaluation: jobs grouped by compiled kernel, the window
+// staged in LDS whenever it fits (each sample does hundreds of nodes of work).
+ile_status tmarg_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, int R, hipStream_t st) {
+    if (R != 1 && R != 4) return set_err(ILE_E_INVALID, "oversample must be 1 or 4");
+    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+    for (size_t i = 0; i < items.size(); i++) {
+        const ile_job *j = items[i].job;
+        if (j->policy == kMixed) return set_err(ILE_E_INVALID, "time marginalisation supports FP32 and FP64 jobs");
+        if (j->dist_marg) return set_err(ILE_E_INVALID, "time marginalisation needs the distance column");
+        if (items[i].n == 0) continue;
+        groups[std::make_tuple(j->set, j->kp, j->policy)].push_back((int)i);
+    }
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    for (auto &g : groups) {
+        const auto &idx = g.second;
+        size_t win = 0;
+        bool lds = true;
+        for (int i : idx) {
+            win = std::max(win, job_window_bytes(items[i].job));
+            lds = lds && job_lds_ok(items[i].job);
+        }
+        const int policy = std::get<2>(g.first);
+        const int block = tmarg_block_threads(policy);
+        const int64_t tile = lds ? 4 * block : block;
+        std::vector<EvalJob> ej;
+        std::vector<Tile> tiles;
+        for (int i : idx) {
+            const BatchItem &b = items[i];
+            EvalJob e = b.job->ej;
+            e.theta = b.theta;
+            e.ld = b.ld;
+            e.lnpmps = b.lnpmps;
+            e.lnL = b.lnL;
+            e.lw = b.lw;
+            e.n = b.n;
+            const double dt = 1.0 / e.inv_dt, tw = b.job->pr.t_window;
+            const double half = std::floor(R * tw / dt + 1e-9);
+            if (!(half >= 0 && half < 1e6)) return set_err(ILE_E_INVALID, "time window too long for marginalisation");
+            e.tm_half = (int)half;
+            e.tm_lnw = std::log(dt / (R * 2.0 * tw));
+            const int jid = (int)ej.size();
+            ej.push_back(e);
+            for (int64_t t0 = 0; t0 < b.n; t0 += tile) tiles.push_back(Tile{jid, 0, t0, std::min(t0 + tile, b.n)});
+        }
+        if (tiles.size() > (size_t)INT32_MAX) return set_err(ILE_E_INVALID, "too many samples for one launch");
+        void *dj = nullptr, *dt = nullptr;
+        int slot = -1;
+        ile_status s = batch_upload(ctx, ej.data(), ej.size() * sizeof(EvalJob), tiles.data(),
+                                    tiles.size() * sizeof(Tile), &dj, &dt, &slot, st);
+        if (s != ILE_OK) return s;
+        hipError_t e = launch_tmarg(std::get<0>(g.first), std::get<1>(g.first), policy, R, lds ? win : 0,
+                                    (const EvalJob *)dj, (const Tile *)dt, (int)tiles.size(), ej[0], tile, block, st);
+        if (e != hipSuccess) return dev_fail(ctx, e, "time-marginalised eval launch");
+        if ((s = batch_done(ctx, slot, st)) != ILE_OK) return s;
+    }
+    return ILE_OK;
+}
 
 // Group jobs by compiled kernel, upload the descriptors and tile lists through
 // the context's pinned staging buffer, and launch one kernel per group.

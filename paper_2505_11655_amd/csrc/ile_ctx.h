@@ -97,6 +97,26 @@ extern template hipError_t launch_eval_sp<3, 1>(int, bool, size_t, const EvalJob
 extern template hipError_t launch_eval_sp<3, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
                                                    const EvalJob &, int64_t, int, hipStream_t);
 
+template <int S, int POL>
+hipError_t launch_tmarg_sp(int kdet, int R, size_t lds_bytes, const EvalJob *jobs, const Tile *tiles, int n_tiles,
+                           const EvalJob &single, int64_t tile, int nthreads, hipStream_t st);
+extern template hipError_t launch_tmarg_sp<0, 0>(int, int, size_t, const EvalJob *, const Tile *, int,
+                                                     const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_tmarg_sp<0, 1>(int, int, size_t, const EvalJob *, const Tile *, int,
+                                                     const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_tmarg_sp<1, 0>(int, int, size_t, const EvalJob *, const Tile *, int,
+                                                     const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_tmarg_sp<1, 1>(int, int, size_t, const EvalJob *, const Tile *, int,
+                                                     const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_tmarg_sp<2, 0>(int, int, size_t, const EvalJob *, const Tile *, int,
+                                                     const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_tmarg_sp<2, 1>(int, int, size_t, const EvalJob *, const Tile *, int,
+                                                     const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_tmarg_sp<3, 0>(int, int, size_t, const EvalJob *, const Tile *, int,
+                                                     const EvalJob &, int64_t, int, hipStream_t);
+extern template hipError_t launch_tmarg_sp<3, 1>(int, int, size_t, const EvalJob *, const Tile *, int,
+                                                     const EvalJob &, int64_t, int, hipStream_t);
+
 struct BatchItem {
     ile_job *job;
     int64_t n;
@@ -122,6 +142,8 @@ ile_status job_create(ile_ctx *ctx, const ile_problem *P, ile_job **out, hipStre
 // still uses the job's buffers.
 void job_release_nosync(ile_job *job);
 ile_status eval_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, hipStream_t st);
+// Time-marginalised evaluation of several jobs (oversampling R = 1 or 4).
+ile_status tmarg_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, int R, hipStream_t st);
 // Copy two host arrays into a scratch slot (caller holds batch_mu); after
 // enqueueing the kernel that reads them, call batch_done with the slot.
 // `extra` bytes of device scratch (and the same of pinned host staging) follow

@@ -21,6 +21,9 @@ enum Policy : int { kFP64 = 0, kFP32 = 1, kMixed = 2 };
 constexpr int lds_block_threads(int set, int policy) {
     return (policy == kFP32 && set <= 1) ? 1024 : (set >= 3 ? 256 : 512);
 }
+// Threads per block of the time-marginalised kernel (its per-sample state is
+// larger than the pointwise kernel's: two waves per SIMD in FP32, one in FP64).
+constexpr int tmarg_block_threads(int policy) { return policy == kFP32 ? 512 : 256; }
 
 // ----------------------------------------------------------------- mode sets
 // Compiled harmonic sets.  A job's mode list is placed into the smallest set
@@ -190,13 +193,14 @@ struct EvalJob {
     float Df[3][6];
     float gmstf, tau0f, inv_dtf, d_reff;
     int n_time;
-    int pad_;
+    int tm_half;          // time-marginalised launches: nodes j = -tm_half..tm_half
     const void *theta;
     int64_t ld;
     const void *lnpmps;
     void *lnL;
     void *lw;
     int64_t n;            // samples of this job in the launch
+    double tm_lnw;        // time-marginalised launches: ln(dt / (R 2 t_w)) per node
 };
 
 struct Tile {

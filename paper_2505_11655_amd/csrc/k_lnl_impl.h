@@ -150,6 +150,151 @@ struct LnlKernel {
     static constexpr int LM = MS::lmax;
     static constexpr int NE = 2 * LM + 1;  // e^{i j phi}, j = 0..2 lmax
 
+    // Sky direction, polarisation response F_k, delays tau_k (at time tt),
+    // harmonic amplitudes y_lm(iota) and the phase table e^{i j phi}.
+    __device__ __forceinline__ static void geometry(const EvalJob &J, const TT al, const TT de, const TT tt,
+                                                    const TT ci, const TT ph, const TT ps, TG (&Fr)[K], TG (&Fi)[K],
+                                                    TA (&tau)[K], TG (&y)[NM], TE (&Er)[NE], TE (&Ei)[NE]) {
+        // ---- sky direction, polarisation basis, delays
+        TS sd, cd, sh, ch;
+        dsincos((TS)de, &sd, &cd);
+        dsincos((TS)al - pick<TS>(J.gmst, J.gmstf), &sh, &ch);
+        const TS n0 = cd * ch, n1 = cd * sh, n2 = sd;
+        const TG ea0 = (TG)(-sh), ea1 = (TG)ch;
+        const TG ed0 = (TG)(-sd * ch), ed1 = (TG)(-sd * sh), ed2 = (TG)cd;
+        TG s2p, c2p;
+        dsincos((TG)2 * (TG)ps, &s2p, &c2p);
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const TG dxx = pick<TG>(J.D[k][0], J.Df[k][0]), dyy = pick<TG>(J.D[k][1], J.Df[k][1]);
+            const TG dzz = pick<TG>(J.D[k][2], J.Df[k][2]), dxy = pick<TG>(J.D[k][3], J.Df[k][3]);
+            const TG dxz = pick<TG>(J.D[k][4], J.Df[k][4]), dyz = pick<TG>(J.D[k][5], J.Df[k][5]);
+            const TG A = dxx * ea0 * ea0 + dyy * ea1 * ea1 + (TG)2 * dxy * ea0 * ea1;
+            const TG B = dxx * ed0 * ed0 + dyy * ed1 * ed1 + dzz * ed2 * ed2 +
+                         (TG)2 * (dxy * ed0 * ed1 + dxz * ed0 * ed2 + dyz * ed1 * ed2);
+            const TG C = dxx * ea0 * ed0 + dyy * ea1 * ed1 + dxy * (ea0 * ed1 + ea1 * ed0) +
+                         dxz * ea0 * ed2 + dyz * ea1 * ed2;
+            const TG Gr = A - B, Gi = (TG)-2 * C;
+            Fr[k] = c2p * Gr + s2p * Gi;
+            Fi[k] = c2p * Gi - s2p * Gr;
+            const TS dly = pick<TS>(J.xc[k][0], J.xcf[k][0]) * n0 + pick<TS>(J.xc[k][1], J.xcf[k][1]) * n1 +
+                           pick<TS>(J.xc[k][2], J.xcf[k][2]) * n2;
+            tau[k] = (TA)((TS)tt - dly);
+        }
+
+        // ---- harmonics y_lm(iota) and phases e^{i j phi}
+        const TG c = (TG)ci;
+        const TG chalf = dsqrt(fmax((TG)0.5 * ((TG)1 + c), (TG)0));
+        const TG shalf = dsqrt(fmax((TG)0.5 * ((TG)1 - c), (TG)0));
+        TG cp[2 * LM + 1], sp[2 * LM + 1];
+        cp[0] = (TG)1;
+        sp[0] = (TG)1;
+#pragma unroll
+        for (int j = 1; j <= 2 * LM; j++) {
+            cp[j] = cp[j - 1] * chalf;
+            sp[j] = sp[j - 1] * shalf;
+        }
+        static_for<0, NM>([&](auto A_) {
+            constexpr int a = decltype(A_)::value;
+            constexpr WTerm w = wigner_terms(kSets[S].l[a], kSets[S].m[a]);
+            TG acc = (TG)0;
+            static_for<0, w.nt>([&](auto T_) {
+                constexpr int t = decltype(T_)::value;
+                acc += (TG)w.coef[t] * cp[w.p[t]] * sp[w.q[t]];
+            });
+            y[a] = acc;
+        });
+        TE sph, cph;
+        dsincos((TE)ph, &sph, &cph);
+        Er[0] = (TE)1;
+        Ei[0] = (TE)0;
+#pragma unroll
+        for (int j = 1; j < NE; j++) {
+            Er[j] = Er[j - 1] * cph - Ei[j - 1] * sph;
+            Ei[j] = Er[j - 1] * sph + Ei[j - 1] * cph;
+        }
+    }
+
+    // The quadratic form T2 from the pair tables (read through the scalar cache).
+    typedef __attribute__((address_space(4))) const cpx<TA> ccpx;
+    __device__ __forceinline__ static TA quad_T2(const TG (&Fr)[K], const TG (&Fi)[K], const TG (&y)[NM],
+                                                 const TE (&Er)[NE], const TE (&Ei)[NE], ccpx *Ut, ccpx *Vt) {
+        // ---- T2 = sum_k |F_k|^2 Y^+ U_k Y + Re(F_k^2 Y^T V_k Y)
+        TA uk[K], vr[K], vi[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            uk[k] = (TA)0;
+            vr[k] = (TA)0;
+            vi[k] = (TA)0;
+        }
+        constexpr PairTable pt = MS::pt;
+        static_for<0, NE>([&](auto G_) {
+            constexpr int g = decltype(G_)::value;
+            fence();
+            TA Ar[K], Ai[K];
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                Ar[k] = (TA)0;
+                Ai[k] = (TA)0;
+            }
+            static_for<pt.u_start[g], pt.u_start[g + 1]>([&](auto J_) {
+                constexpr int j = decltype(J_)::value;
+                constexpr int p = pt.u_pair[j];
+                const TA py = (TA)y[pt.a[p]] * (TA)y[pt.b[p]];
+#pragma unroll
+                for (int k = 0; k < K; k++) {
+                    Ar[k] += py * Ut[j * K + k].re;
+                    if constexpr (g > 0) Ai[k] += py * Ut[j * K + k].im;
+                }
+            });
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                if constexpr (g == 0)
+                    uk[k] += Ar[k];
+                else
+                    uk[k] += (TA)Er[g] * Ar[k] - (TA)Ei[g] * Ai[k];
+            }
+        });
+        static_for<0, 4 * LM + 1>([&](auto G_) {
+            constexpr int g = decltype(G_)::value;
+            fence();
+            constexpr int sm = g - 2 * LM;
+            if constexpr (pt.v_start[g + 1] > pt.v_start[g]) {
+                TA Br[K], Bi[K];
+#pragma unroll
+                for (int k = 0; k < K; k++) {
+                    Br[k] = (TA)0;
+                    Bi[k] = (TA)0;
+                }
+                static_for<pt.v_start[g], pt.v_start[g + 1]>([&](auto J_) {
+                    constexpr int j = decltype(J_)::value;
+                    constexpr int p = pt.v_pair[j];
+                    const TA py = (TA)y[pt.a[p]] * (TA)y[pt.b[p]];
+#pragma unroll
+                    for (int k = 0; k < K; k++) {
+                        Br[k] += py * Vt[j * K + k].re;
+                        Bi[k] += py * Vt[j * K + k].im;
+                    }
+                });
+                // e^{-i sm phi}
+                const TA er = (TA)Er[sm < 0 ? -sm : sm];
+                const TA ei = (sm < 0) ? (TA)Ei[-sm] : -(TA)Ei[sm];
+#pragma unroll
+                for (int k = 0; k < K; k++) {
+                    vr[k] += er * Br[k] - ei * Bi[k];
+                    vi[k] += er * Bi[k] + ei * Br[k];
+                }
+            }
+        });
+        TA T2 = (TA)0;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const TA fr = (TA)Fr[k], fi = (TA)Fi[k];
+            T2 += (fr * fr + fi * fi) * uk[k] + (fr * fr - fi * fi) * vr[k] - (TA)2 * fr * fi * vi[k];
+        }
+        return T2;
+    }
+
     __device__ __forceinline__ static void run(const EvalJob &J, const int64_t begin, const int64_t end,
                                                cpx<TA> *smem) {
         const int T = J.n_time;
@@ -167,7 +312,6 @@ struct LnlKernel {
         // a block reads the same entry: reading them through the constant
         // address space lets them come through the scalar cache into SGPRs
         // (operands of the FMAs) instead of per-sample vector loads.
-        typedef __attribute__((address_space(4))) const cpx<TA> ccpx;
         ccpx *Ut = (ccpx *)J.Ut;
         ccpx *Vt = (ccpx *)J.Vt;
         const TT *__restrict__ th = (const TT *)J.theta;
@@ -185,68 +329,11 @@ struct LnlKernel {
             const TT ci = th[4 * ld + i], ph = th[5 * ld + i], ps = th[6 * ld + i];
             bool ok = (DM || DD > (TT)0) && (ci >= (TT)-1 && ci <= (TT)1);
 
-            // ---- sky direction, polarisation basis, delays
-            TS sd, cd, sh, ch;
-            dsincos((TS)de, &sd, &cd);
-            dsincos((TS)al - pick<TS>(J.gmst, J.gmstf), &sh, &ch);
-            const TS n0 = cd * ch, n1 = cd * sh, n2 = sd;
-            const TG ea0 = (TG)(-sh), ea1 = (TG)ch;
-            const TG ed0 = (TG)(-sd * ch), ed1 = (TG)(-sd * sh), ed2 = (TG)cd;
-            TG s2p, c2p;
-            dsincos((TG)2 * (TG)ps, &s2p, &c2p);
             TG Fr[K], Fi[K];
             TA tau[K];
-#pragma unroll
-            for (int k = 0; k < K; k++) {
-                const TG dxx = pick<TG>(J.D[k][0], J.Df[k][0]), dyy = pick<TG>(J.D[k][1], J.Df[k][1]);
-                const TG dzz = pick<TG>(J.D[k][2], J.Df[k][2]), dxy = pick<TG>(J.D[k][3], J.Df[k][3]);
-                const TG dxz = pick<TG>(J.D[k][4], J.Df[k][4]), dyz = pick<TG>(J.D[k][5], J.Df[k][5]);
-                const TG A = dxx * ea0 * ea0 + dyy * ea1 * ea1 + (TG)2 * dxy * ea0 * ea1;
-                const TG B = dxx * ed0 * ed0 + dyy * ed1 * ed1 + dzz * ed2 * ed2 +
-                             (TG)2 * (dxy * ed0 * ed1 + dxz * ed0 * ed2 + dyz * ed1 * ed2);
-                const TG C = dxx * ea0 * ed0 + dyy * ea1 * ed1 + dxy * (ea0 * ed1 + ea1 * ed0) +
-                             dxz * ea0 * ed2 + dyz * ea1 * ed2;
-                const TG Gr = A - B, Gi = (TG)-2 * C;
-                Fr[k] = c2p * Gr + s2p * Gi;
-                Fi[k] = c2p * Gi - s2p * Gr;
-                const TS dly = pick<TS>(J.xc[k][0], J.xcf[k][0]) * n0 + pick<TS>(J.xc[k][1], J.xcf[k][1]) * n1 +
-                               pick<TS>(J.xc[k][2], J.xcf[k][2]) * n2;
-                tau[k] = (TA)((TS)tt - dly);
-            }
-
-            // ---- harmonics y_lm(iota) and phases e^{i j phi}
-            const TG c = (TG)ci;
-            const TG chalf = dsqrt(fmax((TG)0.5 * ((TG)1 + c), (TG)0));
-            const TG shalf = dsqrt(fmax((TG)0.5 * ((TG)1 - c), (TG)0));
-            TG cp[2 * LM + 1], sp[2 * LM + 1];
-            cp[0] = (TG)1;
-            sp[0] = (TG)1;
-#pragma unroll
-            for (int j = 1; j <= 2 * LM; j++) {
-                cp[j] = cp[j - 1] * chalf;
-                sp[j] = sp[j - 1] * shalf;
-            }
             TG y[NM];
-            static_for<0, NM>([&](auto A_) {
-                constexpr int a = decltype(A_)::value;
-                constexpr WTerm w = wigner_terms(kSets[S].l[a], kSets[S].m[a]);
-                TG acc = (TG)0;
-                static_for<0, w.nt>([&](auto T_) {
-                    constexpr int t = decltype(T_)::value;
-                    acc += (TG)w.coef[t] * cp[w.p[t]] * sp[w.q[t]];
-                });
-                y[a] = acc;
-            });
-            TE sph, cph;
-            dsincos((TE)ph, &sph, &cph);
             TE Er[NE], Ei[NE];
-            Er[0] = (TE)1;
-            Ei[0] = (TE)0;
-#pragma unroll
-            for (int j = 1; j < NE; j++) {
-                Er[j] = Er[j - 1] * cph - Ei[j - 1] * sph;
-                Ei[j] = Er[j - 1] * sph + Ei[j - 1] * cph;
-            }
+            geometry(J, al, de, tt, ci, ph, ps, Fr, Fi, tau, y, Er, Ei);
 
             // ---- T1 = sum_k Re[conj(F_k) sum_a y_a e^{i m_a phi} Qhat_k,a]
             TA T1 = (TA)0;
@@ -281,79 +368,7 @@ struct LnlKernel {
                 T1 += (TA)Fr[k] * ar + (TA)Fi[k] * ai;
             }
 
-            // ---- T2 = sum_k |F_k|^2 Y^+ U_k Y + Re(F_k^2 Y^T V_k Y)
-            TA uk[K], vr[K], vi[K];
-#pragma unroll
-            for (int k = 0; k < K; k++) {
-                uk[k] = (TA)0;
-                vr[k] = (TA)0;
-                vi[k] = (TA)0;
-            }
-            constexpr PairTable pt = MS::pt;
-            static_for<0, NE>([&](auto G_) {
-                constexpr int g = decltype(G_)::value;
-                fence();
-                TA Ar[K], Ai[K];
-#pragma unroll
-                for (int k = 0; k < K; k++) {
-                    Ar[k] = (TA)0;
-                    Ai[k] = (TA)0;
-                }
-                static_for<pt.u_start[g], pt.u_start[g + 1]>([&](auto J_) {
-                    constexpr int j = decltype(J_)::value;
-                    constexpr int p = pt.u_pair[j];
-                    const TA py = (TA)y[pt.a[p]] * (TA)y[pt.b[p]];
-#pragma unroll
-                    for (int k = 0; k < K; k++) {
-                        Ar[k] += py * Ut[j * K + k].re;
-                        if constexpr (g > 0) Ai[k] += py * Ut[j * K + k].im;
-                    }
-                });
-#pragma unroll
-                for (int k = 0; k < K; k++) {
-                    if constexpr (g == 0)
-                        uk[k] += Ar[k];
-                    else
-                        uk[k] += (TA)Er[g] * Ar[k] - (TA)Ei[g] * Ai[k];
-                }
-            });
-            static_for<0, 4 * LM + 1>([&](auto G_) {
-                constexpr int g = decltype(G_)::value;
-                fence();
-                constexpr int sm = g - 2 * LM;
-                if constexpr (pt.v_start[g + 1] > pt.v_start[g]) {
-                    TA Br[K], Bi[K];
-#pragma unroll
-                    for (int k = 0; k < K; k++) {
-                        Br[k] = (TA)0;
-                        Bi[k] = (TA)0;
-                    }
-                    static_for<pt.v_start[g], pt.v_start[g + 1]>([&](auto J_) {
-                        constexpr int j = decltype(J_)::value;
-                        constexpr int p = pt.v_pair[j];
-                        const TA py = (TA)y[pt.a[p]] * (TA)y[pt.b[p]];
-#pragma unroll
-                        for (int k = 0; k < K; k++) {
-                            Br[k] += py * Vt[j * K + k].re;
-                            Bi[k] += py * Vt[j * K + k].im;
-                        }
-                    });
-                    // e^{-i sm phi}
-                    const TA er = (TA)Er[sm < 0 ? -sm : sm];
-                    const TA ei = (sm < 0) ? (TA)Ei[-sm] : -(TA)Ei[sm];
-#pragma unroll
-                    for (int k = 0; k < K; k++) {
-                        vr[k] += er * Br[k] - ei * Bi[k];
-                        vi[k] += er * Bi[k] + ei * Br[k];
-                    }
-                }
-            });
-            TA T2 = (TA)0;
-#pragma unroll
-            for (int k = 0; k < K; k++) {
-                const TA fr = (TA)Fr[k], fi = (TA)Fi[k];
-                T2 += (fr * fr + fi * fi) * uk[k] + (fr * fr - fi * fi) * vr[k] - (TA)2 * fr * fi * vi[k];
-            }
+            const TA T2 = quad_T2(Fr, Fi, y, Er, Ei, Ut, Vt);
 
             // ---- combine
             TA lnL;

@@ -1,7 +1,10 @@
-// Instantiations of the fused likelihood kernel: compiled mode set 3, FP32 policy.
+// Instantiations of the fused likelihood kernels (pointwise and time-marginalised): compiled mode set 3, FP32 policy.
 #include "k_lnl_impl.h"
+#include "k_tmarg_impl.h"
 
 namespace ile {
 template hipError_t launch_eval_sp<3, 1>(int, bool, size_t, const EvalJob *, const Tile *, int,
                                            const EvalJob &, int64_t, int, hipStream_t);
+template hipError_t launch_tmarg_sp<3, 1>(int, int, size_t, const EvalJob *, const Tile *, int,
+                                             const EvalJob &, int64_t, int, hipStream_t);
 }  // namespace ile
