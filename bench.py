@@ -40,8 +40,8 @@ LNL_BYTES = {"fp32": 40, "fp64": 80}
 # The figures hold only for the kernel source they were taken on.
 # SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32 of the same probe give the FLOPs the
 # kernel executes (64 lanes x (add + mul + 2 fma + trans) per wave instruction).
-LNL_TRAFFIC = {"fetch_B_per_sample": 32.717, "write_B_per_sample": 8.000, "executed_flop_per_sample": 2527.0,
-               "src_sha256": "29d2382eadc7f69057bf016eb1509a0307dd5e89ee4293937f71859d16526347"}
+LNL_TRAFFIC = {"fetch_B_per_sample": 32.720, "write_B_per_sample": 8.000, "executed_flop_per_sample": 2527.0,
+               "src_sha256": "cbc3b82185da8c9a14847cc26060453d898fb317cede1bb5c4d872450c26e085"}
 # algorithmic HBM bytes per sample of the draw (7 theta + ln p - ln p_s
 # written) and estimator (lw read) kernels
 DRAW_BYTES = {"fp32": 32, "fp64": 64}
@@ -73,7 +73,8 @@ def make_problems(n_points, seed):
     return probs
 
 
-def run_policy(ile, torch, ctx, probs, policy, n_per, steps, warmup, stream):
+def run_policy(ile, torch, ctx, probs, policy, n_per, steps, warmup, stream, tmarg_R=None):
+    """One step = draws + batched lnL (time-marginalised when tmarg_R is set) + batched estimator."""
     dt = torch.float64 if policy == ile.ILE_FP64 else torch.float32
     jobs = [ile.ile_prepare(ctx, ile.ProblemHost(p, precision=policy)) for p in probs]
     J = len(jobs)
@@ -98,7 +99,11 @@ def run_policy(ile, torch, ctx, probs, policy, n_per, steps, warmup, stream):
         ev[0].record(stream)
         ile.ile_draw(jobs[0], seed, 0, 0, N, th, N, lr, stream=stream)
         ev[1].record(stream)
-        ile.ile_eval_lnL_batch(jobs, ns, theta_ptrs, lds, lr_ptrs, L_ptrs, W_ptrs, stream=stream)
+        if tmarg_R is None:
+            ile.ile_eval_lnL_batch(jobs, ns, theta_ptrs, lds, lr_ptrs, L_ptrs, W_ptrs, stream=stream)
+        else:
+            ile.ile_eval_lnL_tmarg_batch(jobs, ns, theta_ptrs, lds, lr_ptrs, L_ptrs, W_ptrs, oversample=tmarg_R,
+                                         stream=stream)
         ev[2].record(stream)
         res = ile.ile_marginalize_batch(jobs, ns, W_ptrs, ile.ILE_MARG_RESET, want=False, stream=stream)
         ev[3].record(stream)
@@ -221,9 +226,15 @@ def main():
     ap.add_argument("--serving-jobs", type=int, default=10000)
     ap.add_argument("--adaptive-jobs", type=int, default=500)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-tmarg", action="store_true")
+    ap.add_argument("--tmarg-log2n", type=int, default=16,
+                    help="extrinsic samples per point of the time-marginalised leg (log2)")
+    ap.add_argument("--tmarg-steps", type=int, default=5)
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: one 1 GiB device copy (known bytes) then one step")
     ap.add_argument("--probe-policy", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--probe-tmarg", action="store_true",
+                    help="the probe's step uses the time-marginalised likelihood (R = 4, 2^tmarg-log2n per point)")
     ap.add_argument("--adaptive-only", action="store_true",
                     help="run only the adaptive serving leg (--adaptive-jobs jobs) and print its summary")
     a = ap.parse_args()
@@ -246,7 +257,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         pol = ile.ILE_FP32 if a.probe_policy == "fp32" else ile.ILE_FP64
-        r = run_policy(ile, torch, ctx, probs, pol, n_per, 1, 0, stream)
+        if a.probe_tmarg:
+            r = run_policy(ile, torch, ctx, probs, pol, 1 << a.tmarg_log2n, 1, 0, stream, tmarg_R=4)
+        else:
+            r = run_policy(ile, torch, ctx, probs, pol, n_per, 1, 0, stream)
         print(json.dumps({"probe": True, "policy": a.probe_policy, "samples": r["N"], "kernel_ms": r["kernel_ms"],
                           "lnl_src_sha256": lnl_src_sha256()}), flush=True)
         return
@@ -263,6 +277,21 @@ def main():
         log("fp64 ...")
         r64 = run_policy(ile, torch, ctx, probs, ile.ILE_FP64, n_per, a.steps, a.warmup, stream)
         log(f"fp64 {r64}")
+    tmarg = None
+    if not a.no_tmarg:
+        R = 4
+        tw = probs[0].t_window
+        nodes = 2 * int(math.floor(R * tw / probs[0].dt + 1e-9)) + 1
+        tmarg = {"oversample": R, "nodes_per_sample": nodes, "samples_per_point": 1 << a.tmarg_log2n}
+        for name, pol in (("fp32", ile.ILE_FP32), ("fp64", ile.ILE_FP64)):
+            if name == "fp64" and a.no_fp64:
+                continue
+            log(f"time-marginalised {name} ...")
+            rt = run_policy(ile, torch, ctx, probs, pol, 1 << a.tmarg_log2n, a.tmarg_steps, 1, stream, tmarg_R=R)
+            log(f"tmarg {name} {rt}")
+            tmarg[name] = {"samples_per_s": rt["samples_per_s"], "nodes_per_s": rt["samples_per_s"] * nodes,
+                           "ms_per_step": rt["ms_per_step"], "kernel_ms": rt["kernel_ms"],
+                           "lnL_marg_first": rt["lnL_marg_first"]}
     serving = None
     if not a.no_serving:
         log("serving pool ...")
@@ -323,6 +352,7 @@ def main():
         "fp64": None if r64 is None else {"value": r64["samples_per_s"], "ms_per_step": r64["ms_per_step"],
                                           "kernel_ms": r64["kernel_ms"],
                                           "fp32_over_fp64": r32["samples_per_s"] / r64["samples_per_s"]},
+        "time_marginalised": tmarg,
         "serving": serving,
         "cpu_baseline": None if a.no_cpu else cpu_baseline(probs),
     }
