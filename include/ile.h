@@ -247,6 +247,9 @@ typedef struct {
     int32_t max_rounds;       /* adaptive: default 32 */
     double n_eff_target;      /* adaptive: default 1000 */
     uint64_t seed;
+    int32_t tmarg_oversample; /* 0: pointwise lnL; 1 or 4: time-marginalised lnL (ile_eval_lnL_tmarg with
+                                 this R; plain ILE_FP32/ILE_FP64 jobs without dist_marg only), with
+                                 chunk_samples/16 samples per pass */
 } ile_job_opts;
 
 typedef struct {

@@ -81,7 +81,8 @@ class ile_server_opts(C.Structure):
 
 class ile_job_opts(C.Structure):
     _fields_ = [("n_samples", C.c_int64), ("adaptive", C.c_int32), ("round_samples", C.c_int64),
-                ("max_rounds", C.c_int32), ("n_eff_target", C.c_double), ("seed", C.c_uint64)]
+                ("max_rounds", C.c_int32), ("n_eff_target", C.c_double), ("seed", C.c_uint64),
+                ("tmarg_oversample", C.c_int32)]
 
 
 class ile_result(C.Structure):
@@ -327,8 +328,8 @@ def ile_server_create(ctx, max_active=64, hbm_budget_bytes=0, chunk_samples=1 <<
 
 
 def job_opts(n_samples=1 << 16, adaptive=False, round_samples=1 << 16, max_rounds=32, n_eff_target=1000.0,
-             seed=1):
-    return ile_job_opts(n_samples, int(adaptive), round_samples, max_rounds, n_eff_target, seed)
+             seed=1, tmarg_oversample=0):
+    return ile_job_opts(n_samples, int(adaptive), round_samples, max_rounds, n_eff_target, seed, tmarg_oversample)
 
 
 def ile_server_submit(srv, problem: ProblemHost, opts):

@@ -92,7 +92,9 @@ size_t lw_bytes(int policy) { return policy == kFP32 ? 4 : 8; }
 
 int64_t chunk_of(const ile_server *s, const Req *r) {
     if (r->jo.adaptive) return r->jo.round_samples > 0 ? r->jo.round_samples : 65536;
-    const int64_t c = s->opts.chunk_samples > 0 ? s->opts.chunk_samples : (1 << 20);
+    int64_t c = s->opts.chunk_samples > 0 ? s->opts.chunk_samples : (1 << 20);
+    // a time-marginalised sample costs ~30-50x a pointwise one
+    if (r->jo.tmarg_oversample) c = std::max<int64_t>(1, c / 16);
     return std::max<int64_t>(1, std::min(c, r->jo.n_samples));
 }
 
@@ -158,7 +160,7 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
     const int64_t t_start = now_ns();
     // draws, grouped by theta type
     std::vector<DrawJob> d32, d64;
-    std::vector<BatchItem> items;
+    std::vector<BatchItem> items, tm1, tm4;   // pointwise; time-marginalised with R = 1, 4
     std::vector<int64_t> nthis(act.size());
     for (size_t i = 0; i < act.size(); i++) {
         Req *r = act[i];
@@ -176,11 +178,14 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
         dj.lnpmps = r->d_lr;
         dj.n = n;
         (r->prob.precision == kFP64 ? d64 : d32).push_back(dj);
-        items.push_back(BatchItem{r->job, n, r->d_theta, n, r->d_lr, nullptr, r->d_lw});
+        const BatchItem bi{r->job, n, r->d_theta, n, r->d_lr, nullptr, r->d_lw};
+        (r->jo.tmarg_oversample == 4 ? tm4 : r->jo.tmarg_oversample == 1 ? tm1 : items).push_back(bi);
     }
     if (!d32.empty() && draw_batch(s->ctx, kFP32, d32, st) != ILE_OK) return false;
     if (!d64.empty() && draw_batch(s->ctx, kFP64, d64, st) != ILE_OK) return false;
-    if (eval_batch(s->ctx, items, st) != ILE_OK) return false;
+    if (!items.empty() && eval_batch(s->ctx, items, st) != ILE_OK) return false;
+    if (!tm1.empty() && tmarg_batch(s->ctx, tm1, 1, st) != ILE_OK) return false;
+    if (!tm4.empty() && tmarg_batch(s->ctx, tm4, 4, st) != ILE_OK) return false;
     // estimator, grouped by lw type (float for FP32, double otherwise)
     std::vector<ile_marg> res(act.size());
     for (int g = 0; g < 2; g++) {
@@ -329,6 +334,12 @@ extern "C" ile_status ile_server_submit(ile_server *s, const ile_problem *P, con
         !P->U || !P->mode_l || !P->mode_m || !P->det_pos || !P->det_resp)
         return set_err(ILE_E_INVALID, "bad problem shape");
     if (!jo->adaptive && jo->n_samples < 1) return set_err(ILE_E_INVALID, "n_samples must be >= 1");
+    if (jo->tmarg_oversample != 0) {
+        if (jo->tmarg_oversample != 1 && jo->tmarg_oversample != 4)
+            return set_err(ILE_E_INVALID, "tmarg_oversample must be 0, 1 or 4");
+        if (jo->adaptive || P->prior.dist_marg || (P->precision != ILE_FP32 && P->precision != ILE_FP64))
+            return set_err(ILE_E_INVALID, "time-marginalised jobs are plain FP32/FP64 jobs without dist_marg");
+    }
     auto r = std::make_unique<Req>();
     const int K = P->n_det, n = P->n_modes, T = P->n_time;
     r->ml.assign(P->mode_l, P->mode_l + n);

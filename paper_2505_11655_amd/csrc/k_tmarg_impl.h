@@ -32,6 +32,12 @@ struct TmargKernel {
     static constexpr int NM = LK::NM;
     static constexpr int NE = LK::NE;
     static constexpr bool kT2First = sizeof(TA) == 8;
+    // With the window in LDS the G rows (a different row per lane) load the
+    // LDS beyond its bandwidth; reading the first detector through L1/L2
+    // instead balances the two paths (measured, 256 x 2^16 samples: HLV 9
+    // modes 33.8 -> 25.5 ms, two of three detectors through L1/L2 39.5 ms;
+    // HL 5 modes 16.0 -> 14.5 ms).
+    static constexpr int kGlobalDets = LDS ? 1 : 0;
 
     __device__ __forceinline__ static TA expT(TA x) {
         if constexpr (sizeof(TA) == 4)
@@ -137,7 +143,7 @@ struct TmargKernel {
             }
             auto Gk = [&](int k, int idx) -> TA {
                 const int ic = min(max(idx, 0), T - 1);
-                const cpx<TA> *q = Qb + ((size_t)k * T + ic) * NM;
+                const cpx<TA> *q = (k < kGlobalDets ? Qg : Qb) + ((size_t)k * T + ic) * NM;
                 TA g = (TA)0;
                 static_for<0, NM>([&](auto A_) {
                     constexpr int a = decltype(A_)::value;

@@ -43,16 +43,17 @@ def _specs(pool):
         p = pool[i % len(pool)]
         policy = [ile.ILE_FP32, ile.ILE_FP64, ile.ILE_FP32_CANCEL64][i % 3]
         adaptive = i % 4 == 3
+        tm = 4 if (i % 5 == 4 and not adaptive and policy != ile.ILE_FP32_CANCEL64) else 0
         n = int(2 ** rng.uniform(14, 17))
-        specs.append((p, policy, adaptive, n, 1000 + i))
+        specs.append((p, policy, adaptive, n, 1000 + i, tm))
     return specs
 
 
 def _submit(srv, spec):
-    p, policy, adaptive, n, seed = spec
+    p, policy, adaptive, n, seed, tm = spec
     ph = ile.ProblemHost(p, precision=policy)
     jo = ile.job_opts(n_samples=n, adaptive=adaptive, round_samples=1 << 14, max_rounds=6, n_eff_target=300.0,
-                      seed=seed)
+                      seed=seed, tmarg_oversample=tm)
     return ile.ile_server_submit(srv, ph, jo), ph
 
 
@@ -102,6 +103,45 @@ def test_plain_job_matches_oracle(orc, pool, policy, tol):
     o = orc.marginalize(orc.lnL(p, th))
     assert r.status == 0 and r.marg.n == n
     assert abs(r.marg.ln_L - o["ln_L"]) <= tol, (r.marg.ln_L, o["ln_L"])
+
+
+@pytest.mark.parametrize("policy,tol", [(ile.ILE_FP64, 1e-9), (ile.ILE_FP32, 2e-3)])
+def test_tmarg_job_matches_oracle(orc, pool, policy, tol):
+    """A time-marginalised job (R = 4): the served ln L equals the oracle
+    estimator over the oracle's time-marginalised likelihood of the same
+    draws (the t column of the draws is ignored on both sides)."""
+    p = pool[0]
+    n, seed = 2 * (1 << 12) + 77, 4242
+    srv = ile.ile_server_create(gu.ctx(), chunk_samples=1 << 14)
+    try:
+        ph = ile.ProblemHost(p, precision=policy)
+        jid = ile.ile_server_submit(srv, ph, ile.job_opts(n_samples=n, seed=seed, tmarg_oversample=4))
+        r = ile.ile_server_wait(srv, jid, 60000)
+    finally:
+        ile.ile_server_destroy(srv)
+    th, _ = orc.draw_prior(orc.make_prior(), seed, 0, 0, n)
+    if policy != ile.ILE_FP64:
+        th = th.astype(np.float32).astype(np.float64)
+    o = orc.marginalize(orc.lnL_tmarg(p, th, oversample=4))
+    assert r.status == 0 and r.marg.n == n
+    assert abs(r.marg.ln_L - o["ln_L"]) <= tol, (r.marg.ln_L, o["ln_L"])
+
+
+def test_tmarg_job_rejects(pool):
+    p = pool[0]
+    srv = ile.ile_server_create(gu.ctx())
+    try:
+        bad = [(ile.ProblemHost(p, precision=ile.ILE_FP32), ile.job_opts(n_samples=100, tmarg_oversample=2)),
+               (ile.ProblemHost(p, precision=ile.ILE_FP32), ile.job_opts(adaptive=True, tmarg_oversample=4)),
+               (ile.ProblemHost(p, precision=ile.ILE_FP32_CANCEL64), ile.job_opts(n_samples=100, tmarg_oversample=4)),
+               (ile.ProblemHost(p, precision=ile.ILE_FP32, dist_marg=True),
+                ile.job_opts(n_samples=100, tmarg_oversample=4))]
+        for ph, jo in bad:
+            with pytest.raises(ile.IleError) as e:
+                ile.ile_server_submit(srv, ph, jo)
+            assert e.value.status == -1
+    finally:
+        ile.ile_server_destroy(srv)
 
 
 def test_budget_queueing_and_admission(pool):
