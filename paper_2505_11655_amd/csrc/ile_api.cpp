@@ -90,22 +90,30 @@ static size_t creal_size(int policy) { return policy == kFP32 ? sizeof(float) : 
 size_t theta_size(int policy) { return policy == kFP64 ? sizeof(double) : sizeof(float); }
 size_t out_size(int policy) { return policy == kFP32 ? sizeof(float) : sizeof(double); }
 
-// Window bytes of a job, and whether an LDS-staged kernel exists for it (the
-// same rule the kernel instantiation uses, plus the device limit).
-size_t job_window_bytes(const ile_job *job) {
-    return (size_t)job->kp * job->n_time * kSets[job->set].n * 2 * creal_size(job->policy);
+// Detectors of a job read through L1/L2 by the LDS-staged kernel (the same
+// rule as the kernels' instantiation), the bytes of the other detectors'
+// windows that it stages, and whether such a kernel exists for the job and
+// its staged part fits the device.
+static int job_global_dets(const ile_job *job, bool tmarg) {
+    return tmarg ? tmarg_global_dets(job->set, job->kp, job->policy)
+                 : lds_global_dets(job->set, job->kp, job->policy);
 }
-bool job_lds_ok(const ile_job *job) {
-    const size_t compiled = (size_t)job->kp * 410 * kSets[job->set].n * 2 * creal_size(job->policy);
-    return compiled <= 163840 && job_window_bytes(job) <= eval_lds_limit();
+size_t job_window_bytes(const ile_job *job, bool tmarg) {
+    const int staged = job->kp - job_global_dets(job, tmarg);
+    return (size_t)std::max(staged, 0) * job->n_time * kSets[job->set].n * 2 * creal_size(job->policy);
+}
+bool job_lds_ok(const ile_job *job, bool tmarg) {
+    const bool compiled = tmarg ? tmarg_lds_compiled(job->set, job->kp, job->policy)
+                                : lnl_lds_compiled(job->set, job->kp, job->policy);
+    return compiled && job_window_bytes(job, tmarg) <= eval_lds_limit();
 }
 
 // Launch geometry of one eval over n samples of a job (single-job path).
 void eval_geometry(const ile_job *job, int64_t n, size_t *lds, int64_t *tile, int *block) {
-    const size_t win = job_window_bytes(job);
+    const size_t win = job_window_bytes(job, false);
     const int64_t cus = 256;
     // stage the window in LDS only when each block gets enough samples to pay for it
-    if (job_lds_ok(job) && n >= (int64_t)2 * cus * 16384) {
+    if (job_lds_ok(job, false) && n >= (int64_t)2 * cus * 16384) {
         *lds = win;
         *block = lds_block_threads(job->set, job->policy);
         *tile = std::max<int64_t>(16384, (n + 2 * cus - 1) / (2 * cus));
@@ -672,8 +680,8 @@ ile_status tmarg_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, int R,
         size_t win = 0;
         bool lds = true;
         for (int i : idx) {
-            win = std::max(win, job_window_bytes(items[i].job));
-            lds = lds && job_lds_ok(items[i].job);
+            win = std::max(win, job_window_bytes(items[i].job, true));
+            lds = lds && job_lds_ok(items[i].job, true);
         }
         const int policy = std::get<2>(g.first);
         const int block = tmarg_block_threads(policy);
@@ -730,8 +738,8 @@ ile_status eval_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, hipStre
         for (int i : idx) {
             total += items[i].n;
             const ile_job *j = items[i].job;
-            win = std::max(win, job_window_bytes(j));
-            lds_ok = lds_ok && job_lds_ok(j);
+            win = std::max(win, job_window_bytes(j, false));
+            lds_ok = lds_ok && job_lds_ok(j, false);
         }
         const int64_t cus = 256;
         const bool lds = lds_ok && total >= (int64_t)2 * cus * 16384 && total / (int64_t)idx.size() >= 65536;

@@ -19,7 +19,7 @@ enum Policy : int { kFP64 = 0, kFP32 = 1, kMixed = 2 };
 // with up to 9 modes, 256 for the 21-mode set (its window leaves room for one
 // block per CU anyway), 512 otherwise.
 constexpr int lds_block_threads(int set, int policy) {
-    return (policy == kFP32 && set <= 1) ? 1024 : (set >= 3 ? 256 : 512);
+    return (policy == kFP32 && set <= 1) ? 1024 : ((set >= 3 || (set == 2 && policy != kFP32)) ? 256 : 512);
 }
 // Threads per block of the time-marginalised kernel (its per-sample state is
 // larger than the pointwise kernel's: two waves per SIMD in FP32, one in FP64).
@@ -43,6 +43,31 @@ constexpr ModeList kSets[kNumSets] = {
     {21, {2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4, 4, 4, 4},
      {-2, -1, 0, 1, 2, -3, -2, -1, 0, 1, 2, 3, -4, -3, -2, -1, 0, 1, 2, 3, 4}},
 };
+
+// Detectors whose Q window an LDS-staged likelihood kernel reads through
+// L1/L2 instead of LDS: the fewest that bring the staged part of the compiled
+// 410-sample windows within 160 KiB (kp: compiled detector count; kp when not
+// even one detector fits).
+constexpr int lds_global_dets(int set, int kp, int policy) {
+    const long per = 410L * kSets[set].n * 2 * (policy == kFP32 ? 4 : 8);
+    for (int g = 0; g < kp; g++)
+        if ((kp - g) * per <= 163840L) return g;
+    return kp;
+}
+// The time-marginalised kernel always reads at least the first detector
+// through L1/L2 (its per-lane row reads exceed the LDS bandwidth otherwise).
+constexpr int tmarg_global_dets(int set, int kp, int policy) {
+    const int g = lds_global_dets(set, kp, policy);
+    return g > 1 ? g : 1;
+}
+// Whether an LDS-staged variant is compiled: for the pointwise kernel wherever
+// one detector's window fits; for the time-marginalised kernel only up to the
+// 9-mode set in FP64 (beyond it the staged variant runs out of scalar
+// registers and gains nothing over L1/L2).
+constexpr bool lnl_lds_compiled(int set, int kp, int policy) { return lds_global_dets(set, kp, policy) < kp; }
+constexpr bool tmarg_lds_compiled(int set, int kp, int policy) {
+    return tmarg_global_dets(set, kp, policy) < kp && (set <= 1 || policy == kFP32);
+}
 
 constexpr int set_lmax(int s) {
     int L = 0;

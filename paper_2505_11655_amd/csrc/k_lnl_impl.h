@@ -149,6 +149,9 @@ struct LnlKernel {
     static constexpr int NM = MS::n;
     static constexpr int LM = MS::lmax;
     static constexpr int NE = 2 * LM + 1;  // e^{i j phi}, j = 0..2 lmax
+    // detectors read through L1/L2 by the LDS-staged variant (their windows
+    // do not fit next to the others)
+    static constexpr int kG = LDS ? lds_global_dets(S, K, POL) : 0;
 
     // Sky direction, polarisation response F_k, delays tau_k (at time tt),
     // harmonic amplitudes y_lm(iota) and the phase table e^{i j phi}.
@@ -300,14 +303,13 @@ struct LnlKernel {
         const int T = J.n_time;
         const cpx<TA> *__restrict__ Qg = (const cpx<TA> *)J.Q;
         if constexpr (LDS) {
-            // stage the whole window of this job: K * T * NM complex values
-            const size_t nwords = (size_t)K * T * NM * sizeof(cpx<TA>) / 8;
-            const uint2 *src = (const uint2 *)J.Q;
+            // stage the windows of detectors kG..K-1 of this job
+            const size_t nwords = (size_t)(K - kG) * T * NM * sizeof(cpx<TA>) / 8;
+            const uint2 *src = (const uint2 *)(Qg + (size_t)kG * T * NM);
             uint2 *dst = (uint2 *)smem;
             for (size_t w = threadIdx.x; w < nwords; w += blockDim.x) dst[w] = src[w];
             __syncthreads();
         }
-        const cpx<TA> *__restrict__ Qb = LDS ? smem : Qg;
         // The pair tables are read-only for the whole launch and every lane of
         // a block reads the same entry: reading them through the constant
         // address space lets them come through the scalar cache into SGPRs
@@ -351,7 +353,8 @@ struct LnlKernel {
                 const TA w1 = fp1 * fm1 * fm2 * (TA)0.5;
                 const TA w2 = -fp1 * f * fm2 * (TA)0.5;
                 const TA w3 = fp1 * f * fm1 * (TA)(1.0 / 6.0);
-                const cpx<TA> *q = Qb + ((size_t)k * T + (i0 - 1)) * NM;
+                const cpx<TA> *q = (LDS && k >= kG) ? smem + ((size_t)(k - kG) * T + (i0 - 1)) * NM
+                                                    : Qg + ((size_t)k * T + (i0 - 1)) * NM;
                 TA ar = (TA)0, ai = (TA)0;
                 static_for<0, NM>([&](auto A_) {
                     constexpr int a = decltype(A_)::value;
@@ -409,12 +412,6 @@ __global__ void __launch_bounds__(LDS ? lds_block_threads(S, POL) : 256, (lnl_mi
     }
 }
 
-// LDS staging is compiled only where a 410-sample window of the set fits in
-// 160 KiB; elsewhere the window is read through the L1/L2 caches.
-template <int S, int K, int POL>
-constexpr bool lds_instanced() {
-    return (size_t)K * 410 * MSet<S>::n * 2 * sizeof(typename PolTypes<POL>::TA) <= 163840;
-}
 
 template <int S, int POL>
 hipError_t launch_eval_sp(int kdet, bool dm, size_t lds_bytes, const EvalJob *jobs, const Tile *tiles, int n_tiles,
@@ -428,7 +425,7 @@ hipError_t launch_eval_sp(int kdet, bool dm, size_t lds_bytes, const EvalJob *jo
         constexpr int K = decltype(KK)::value;
         constexpr bool L = decltype(LL)::value;
         constexpr bool D = decltype(DD)::value;
-        if constexpr ((L && !lds_instanced<S, K, POL>()) || (D && POL == kMixed)) {
+        if constexpr ((L && !lnl_lds_compiled(S, K, POL)) || (D && POL == kMixed)) {
             return hipErrorInvalidValue;
         } else {
             auto fn = k_lnl<S, K, POL, L, D>;

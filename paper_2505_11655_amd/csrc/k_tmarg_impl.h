@@ -36,8 +36,8 @@ struct TmargKernel {
     // LDS beyond its bandwidth; reading the first detector through L1/L2
     // instead balances the two paths (measured, 256 x 2^16 samples: HLV 9
     // modes 33.8 -> 25.5 ms, two of three detectors through L1/L2 39.5 ms;
-    // HL 5 modes 16.0 -> 14.5 ms).
-    static constexpr int kGlobalDets = LDS ? 1 : 0;
+    // HL 5 modes 16.0 -> 14.5 ms).  Only the other detectors are staged.
+    static constexpr int kGlobalDets = LDS ? tmarg_global_dets(S, K, POL) : K;
 
     __device__ __forceinline__ static TA expT(TA x) {
         if constexpr (sizeof(TA) == 4)
@@ -51,13 +51,12 @@ struct TmargKernel {
         const int T = J.n_time;
         const cpx<TA> *__restrict__ Qg = (const cpx<TA> *)J.Q;
         if constexpr (LDS) {
-            const size_t nwords = (size_t)K * T * NM * sizeof(cpx<TA>) / 8;
-            const uint2 *src = (const uint2 *)J.Q;
+            const size_t nwords = (size_t)(K - kGlobalDets) * T * NM * sizeof(cpx<TA>) / 8;
+            const uint2 *src = (const uint2 *)(Qg + (size_t)kGlobalDets * T * NM);
             uint2 *dst = (uint2 *)smem;
             for (size_t w = threadIdx.x; w < nwords; w += blockDim.x) dst[w] = src[w];
             __syncthreads();
         }
-        const cpx<TA> *__restrict__ Qb = LDS ? smem : Qg;
         ccpx *Ut = (ccpx *)J.Ut;
         ccpx *Vt = (ccpx *)J.Vt;
         const TT *__restrict__ th = (const TT *)J.theta;
@@ -143,7 +142,9 @@ struct TmargKernel {
             }
             auto Gk = [&](int k, int idx) -> TA {
                 const int ic = min(max(idx, 0), T - 1);
-                const cpx<TA> *q = (k < kGlobalDets ? Qg : Qb) + ((size_t)k * T + ic) * NM;
+                const cpx<TA> *q = (k < kGlobalDets ? Qg + (size_t)k * T * NM
+                                                    : smem + (size_t)(k - kGlobalDets) * T * NM) +
+                                   (size_t)ic * NM;
                 TA g = (TA)0;
                 static_for<0, NM>([&](auto A_) {
                     constexpr int a = decltype(A_)::value;
@@ -241,7 +242,7 @@ hipError_t launch_tmarg_sp(int kdet, int R, size_t lds_bytes, const EvalJob *job
         constexpr int K = decltype(KK)::value;
         constexpr bool L = decltype(LL)::value;
         constexpr int RV = decltype(RR)::value;
-        if constexpr (L && !lds_instanced<S, K, POL>()) {
+        if constexpr (L && !tmarg_lds_compiled(S, K, POL)) {
             return hipErrorInvalidValue;
         } else {
             auto fn = k_lnl_tmarg<S, K, POL, L, RV>;
