@@ -10,7 +10,9 @@ this module wraps it and adds definition-level numpy helpers:
   * ``exact_Q``          - Q_k,lm(tau) as the direct frequency sum of eq. (QUV);
   * ``lnL_exact``        - lnL with exact Q at the detector times (no window);
   * ``em_fit``           - weighted EM for the mixture proposal (see its docstring);
-  * ``ln_dist_marg``     - the distance-marginalised likelihood by adaptive quadrature.
+  * ``ln_dist_marg``     - the distance-marginalised likelihood by adaptive quadrature;
+  * ``draw_av``, ``av_threshold``, ``av_refine_bins``, ``av_cells``, ``av_update``
+                         - the adaptive-volume integrator (its readings are listed there).
 
 Pins: ``tests/test_oracle_pins.py``.  Parity unpinned: EM trajectories with
 more than one component, the in-support mass estimates (Monte Carlo).
@@ -93,6 +95,9 @@ def lib():
         L.orc_ln_prior.restype = C.c_double
         L.orc_draw_prior.argtypes = [C.POINTER(_Prior), C.c_uint64, C.c_uint32, C.c_int64,
                                      C.c_int64, dp, C.c_int64, dp]
+        L.orc_draw_av.argtypes = [C.POINTER(_Prior), C.c_int, C.POINTER(C.c_int), C.c_int, C.c_int64,
+                                  C.POINTER(C.c_int32), C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, dp,
+                                  C.c_int64, dp]
         L.orc_gmm_comp_logpdf.argtypes = [C.POINTER(_Prior), C.POINTER(_Gmm), C.c_int, dp]
         L.orc_gmm_comp_logpdf.restype = C.c_double
         L.orc_gmm_ln_ps.argtypes = [C.POINTER(_Prior), C.POINTER(_Gmm), dp]
@@ -309,6 +314,124 @@ def draw_gmm(prior, g, seed, rnd, i0, n):
 
 def gmm_inbox_mass(prior, g, j, seed, rnd, m=1 << 16):
     return lib().orc_gmm_inbox_mass(C.byref(prior), C.byref(g), j, seed, rnd, m)
+
+
+# ---------------------------------------------------------- adaptive volume
+# Section "Adaptive volume integration" (the AV integrator), in the prior's
+# CDF coordinates u in [0,1)^d (theta = inverse-CDF map of u): a grid of nb
+# bins per sampled dimension, a set of active cells, samples uniform over the
+# active cells (so ln p - ln p_s = ln V, V the active volume), and after each
+# round a likelihood threshold, a refined bin count (eq. nbins_V) and the new
+# active cells.  Readings where the section is silent:
+#   * the live points of an update are the n samples of the round just drawn;
+#   * the enclosed probability is measured on the fixed-point masses
+#     q_i = floor(exp(lnL_i - max lnL) 2^40) (integer sums, so the threshold
+#     does not depend on summation order);
+#   * the threshold is the largest lnL value at or above which both at least
+#     p_thr of the total mass and at least min(n_min_live, n_finite) samples
+#     lie (the "fixed large number of highest points" of early iterations);
+#   * n_bins = ceil((1/dV)^(1/d)), clamped to [1, max_bins], with
+#     dV = V n_min / (n sqrt(n_min)) the Monte Carlo error of the live volume;
+#   * the new active cells are the cells of the refined grid holding a sample
+#     at or above the threshold, in order of their first such sample.
+AV_MASS_BITS = 40
+
+
+class AvGrid:
+    def __init__(self, nb, cells, dims):
+        self.nb = int(nb)
+        self.cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, len(dims)))
+        self.dims = list(dims)
+
+    @property
+    def d(self):
+        return len(self.dims)
+
+    @property
+    def n_cells(self):
+        return self.cells.shape[0]
+
+    @property
+    def ln_vol(self):
+        return math.log(self.n_cells) - self.d * math.log(self.nb)
+
+
+def av_dims(dist_marg=False):
+    return [0, 1, 2, 4, 5, 6] if dist_marg else list(range(7))
+
+
+def av_init(dist_marg=False):
+    """The whole cube: one cell of a one-bin grid."""
+    dims = av_dims(dist_marg)
+    return AvGrid(1, np.zeros((1, len(dims)), dtype=np.int32), dims)
+
+
+def draw_av(prior, grid, seed, rnd, i0, n):
+    """Samples uniform over the active cells (orc_draw_av): theta [7][n] and u [d][n]."""
+    th = np.empty((7, n))
+    u = np.empty((grid.d, n))
+    dims = (C.c_int * grid.d)(*grid.dims)
+    cells = np.ascontiguousarray(grid.cells, dtype=np.int32)
+    lib().orc_draw_av(C.byref(prior), grid.d, dims, grid.nb, grid.n_cells,
+                      cells.ctypes.data_as(C.POINTER(C.c_int32)), seed, rnd, i0, n, _dp(th), n, _dp(u))
+    return th, u
+
+
+def av_mass(lnL_finite):
+    m = float(np.max(lnL_finite))
+    return np.floor(np.exp(lnL_finite - m) * float(1 << AV_MASS_BITS)).astype(np.uint64)
+
+
+def av_threshold(lnL, p_thr, n_min_live):
+    """Likelihood threshold of one round: (lnL_thr, n_min), or None when no
+    sample is finite.  Sorts the finite samples by lnL (descending) and takes
+    the lower of the value where the cumulative fixed-point mass first reaches
+    ceil(p_thr * total) and the k-th largest value, k = min(n_min_live, n)."""
+    lnL = np.asarray(lnL, dtype=np.float64)
+    x = lnL[np.isfinite(lnL)]
+    if x.size == 0:
+        return None
+    q = av_mass(x)
+    order = np.argsort(-x, kind="stable")
+    cum = np.cumsum(q[order], dtype=np.uint64)
+    target = np.uint64(math.ceil(p_thr * float(cum[-1])))
+    k_mass = int(np.argmax(cum >= target))
+    k = min(int(n_min_live), x.size)
+    thr = min(float(x[order[k_mass]]), float(x[order[k - 1]]))
+    return thr, int(np.count_nonzero(x >= thr))
+
+
+def av_refine_bins(n_min, n, ln_vol, d, max_bins):
+    """eq. (nbins_V) with dV = V n_min / (n sqrt(n_min))."""
+    ln_dv = ln_vol + 0.5 * math.log(n_min) - math.log(n)
+    x = math.exp(-ln_dv / d)
+    return int(min(max(math.ceil(x - 1e-9), 1), max_bins))
+
+
+def av_cells(u_top, nb):
+    """Cells of the nb-bin grid holding the points u_top [d][m] (index order),
+    each once, in order of first appearance."""
+    if u_top.shape[1] == 0:
+        return np.zeros((0, u_top.shape[0]), dtype=np.int32)
+    c = np.minimum(np.floor(u_top * nb), nb - 1).astype(np.int32).T
+    _, first = np.unique(c, axis=0, return_index=True)
+    return c[np.sort(first)]
+
+
+def av_update(grid, u, lnL, p_thr=0.999, n_min_live=1000, max_bins=511):
+    """One refinement from a round's n samples (u [d][n], lnL [n]).  Returns
+    (new grid, info); the grid is unchanged when no sample is finite."""
+    lnL = np.asarray(lnL, dtype=np.float64)
+    n = lnL.size
+    r = av_threshold(lnL, p_thr, n_min_live)
+    if r is None:
+        return grid, {"lnL_thr": -math.inf, "n_min": 0, "n_live": n, "vol_mc": 0.0}
+    thr, n_min = r
+    nb = av_refine_bins(n_min, n, grid.ln_vol, grid.d, max_bins)
+    top = np.nonzero(np.isfinite(lnL) & (lnL >= thr))[0]
+    cells = av_cells(np.asarray(u)[:, top], nb)
+    info = {"lnL_thr": thr, "n_min": n_min, "n_live": n, "vol_mc": math.exp(grid.ln_vol) * n_min / n}
+    return AvGrid(nb, cells, grid.dims), info
 
 
 # ----------------------------------------------------------------------- EM

@@ -385,6 +385,40 @@ void orc_draw_prior(const orc_prior *pr, uint64_t seed, uint32_t round, int64_t 
     }
 }
 
+/* ------------------------------------------------- adaptive-volume draws */
+/*
+ * Adaptive volume integration (Section "Adaptive volume integration"): the
+ * sampler is uniform over a set of active hypercubes of the unit cube of the
+ * prior's CDF coordinates u (theta = inverse-CDF map of u, as for the prior
+ * draw), so p(theta)/p_s(theta) = V, the active volume.
+ * Grid: nb bins per dimension over the n_dim sampled columns dims[]; cells
+ * [n_cells][n_dim] integer coordinates.  Sample i of round r uses the words of
+ * the prior draw (attempt 0, blocks 0..3): the cell is the floor of
+ * u53(w14, w15) * n_cells (at most n_cells - 1), and column c of the cell's
+ * k-th dimension takes u_c = (cell_k + u53(w[2c], w[2c+1])) / nb.  With one
+ * cell and nb = 1 this is the prior draw itself.  u_out: [n_dim][n] or NULL.
+ */
+void orc_draw_av(const orc_prior *pr, int n_dim, const int *dims, int nb, int64_t n_cells, const int32_t *cells,
+                 uint64_t seed, uint32_t round, int64_t i0, int64_t n, double *theta, int64_t ld, double *u_out)
+{
+    for (int64_t s = 0; s < n; s++) {
+        uint32_t w[16];
+        orc_words(seed, (uint64_t)(i0 + s), round, 0, 4, w);
+        double sel = floor(orc_u53(w[14], w[15]) * (double)n_cells);
+        int64_t j = (int64_t)sel;
+        if (j > n_cells - 1) j = n_cells - 1;
+        double u[7], th[7];
+        for (int c = 0; c < 7; c++) u[c] = orc_u53(w[2 * c], w[2 * c + 1]);
+        for (int k = 0; k < n_dim; k++) {
+            int c = dims[k];
+            u[c] = ((double)cells[j * n_dim + k] + orc_u53(w[2 * c], w[2 * c + 1])) / (double)nb;
+            if (u_out) u_out[(int64_t)k * n + s] = u[c];
+        }
+        orc_prior_from_u(pr, u, th);
+        for (int c = 0; c < 7; c++) theta[c * ld + s] = th[c];
+    }
+}
+
 /* ---------------------------------------------------------- Gaussian mixture */
 
 #define ORC_GMM_MAXC 16

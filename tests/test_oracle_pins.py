@@ -638,3 +638,167 @@ def test_PT2_node_sum_converges_to_quadrature(orc, recs):
     fine = orc.lnL_tmarg(p, th, oversample=16)
     assert np.max(np.abs(got - ref)) < 1e-2, np.max(np.abs(got - ref))
     assert np.max(np.abs(fine - ref)) < 1e-3, np.max(np.abs(fine - ref))
+
+
+# ------------------------------------------------------------------ AV (f2)
+# Section "Adaptive volume integration": hypercube refinement of the unit cube
+# of the prior's CDF coordinates.
+def test_PA1_av_one_cell_is_the_prior_draw(orc):
+    """With the whole cube as the single active cell of a one-bin grid the
+    sampler is the prior itself: the same draws, and ln p - ln p_s = ln V = 0."""
+    pr = orc.make_prior()
+    g = orc.av_init()
+    th, u = orc.draw_av(pr, g, 0xABCDEF, 3, 1000, 5000)
+    tp, _ = orc.draw_prior(pr, 0xABCDEF, 3, 1000, 5000)
+    assert np.array_equal(th, tp)
+    assert g.ln_vol == 0.0
+    gd = orc.av_init(dist_marg=True)
+    prd = orc.make_prior(dist_marg=True)
+    th2, u2 = orc.draw_av(prd, gd, 5, 0, 0, 100)
+    assert u2.shape == (6, 100) and np.all(th2[3] == 100.0)
+
+
+def test_PA2_av_draws_uniform_over_active_cells(orc):
+    """Every draw lies in an active cell, the cells are used equally often
+    (chi-square) and positions inside a cell are uniform (Kolmogorov-Smirnov)."""
+    from scipy import stats
+    rng = np.random.default_rng(80)
+    nb, d = 4, 7
+    ids = rng.choice(nb ** d, size=37, replace=False)
+    cells = np.array([[(i // nb ** k) % nb for k in range(d)] for i in ids], dtype=np.int32)
+    g = orc.AvGrid(nb, cells, list(range(7)))
+    n = 200000
+    _, u = orc.draw_av(orc.make_prior(), g, 99, 1, 0, n)
+    c = np.floor(u * nb).astype(np.int64)
+    key = sum(c[k] * nb ** k for k in range(d))
+    pos = {int(i): j for j, i in enumerate(ids)}
+    assert all(int(x) in pos for x in np.unique(key))
+    counts = np.bincount([pos[int(x)] for x in key], minlength=len(ids))
+    assert stats.chisquare(counts).pvalue > 1e-4
+    frac = (u * nb - c).ravel()
+    assert stats.kstest(frac, "uniform").pvalue > 1e-4
+    assert abs(g.ln_vol - math.log(37 / nb ** d)) < 1e-12
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_PA3_av_threshold_is_the_largest_feasible_value(orc, case):
+    """The threshold is the largest finite lnL value v such that the samples at
+    or above v hold at least ceil(p_thr * total) of the fixed-point mass and
+    number at least min(n_min_live, n_finite): found here by trying every
+    distinct value, against the oracle's sorted cumulative sum."""
+    rng = np.random.default_rng(81 + case)
+    n = [50, 400, 3000, 3000, 17, 1000][case]
+    x = rng.normal(0, [3.0, 10.0, 0.5, 30.0, 1.0, 5.0][case], n)
+    x = np.round(x, [6, 1, 2, 3, 6, 0][case])          # ties
+    x[rng.choice(n, n // 10, replace=False)] = -np.inf
+    x[rng.choice(n, 2, replace=False)] = np.nan
+    fin = x[np.isfinite(x)]
+    m = fin.max()
+    q = [int(math.floor(math.exp(v - m) * 2.0 ** 40)) for v in fin]
+    total = sum(q)
+    for p_thr, k in [(0.999, 1), (0.9, 10), (0.5, 100), (1.0, 5), (0.99, 10 ** 6), (1e-9, 1)]:
+        target = math.ceil(p_thr * float(total))
+        kk = min(k, fin.size)
+        best = None
+        for v in np.unique(fin)[::-1]:
+            sel = fin >= v
+            if sum(qq for qq, s in zip(q, sel) if s) >= target and int(sel.sum()) >= kk:
+                best = float(v)
+                break
+        thr, n_min = orc.av_threshold(x, p_thr, k)
+        assert thr == best, (p_thr, k, thr, best)
+        assert n_min == int(np.count_nonzero(fin >= best))
+    assert orc.av_threshold(np.full(5, -np.inf), 0.9, 3) is None
+
+
+def test_PA5_nbins_worked_examples(orc):
+    """eq. (nbins_V) by hand: d = 2, V = 1, 100 of 10^4 live points above the
+    threshold: V' = 0.01, dV = 0.001, (1/dV)^(1/2) = 31.6 -> 32 bins; d = 7,
+    1000 of 2^16: dV = (1000/65536)/sqrt(1000) = 4.83e-4, 2071^(1/7) = 2.98 ->
+    3 bins; every one of 10^6 points kept, d = 7: dV = 1e-3, 1000^(1/7) = 2.68
+    -> 3; and the clamp at max_bins."""
+    assert orc.av_refine_bins(100, 10000, 0.0, 2, 511) == 32
+    assert orc.av_refine_bins(1000, 65536, 0.0, 7, 511) == 3
+    assert orc.av_refine_bins(10 ** 6, 10 ** 6, 0.0, 7, 511) == 3
+    assert orc.av_refine_bins(4, 10 ** 6, math.log(1e-3), 2, 511) == 511
+
+
+def _gauss_cell_integral(cells, nb, mu, sig):
+    """Exact integral of prod_k N(u_k; mu_k, sig_k) over a union of cells."""
+    from scipy.special import ndtr
+    lo = cells / nb
+    hi = (cells + 1) / nb
+    per = ndtr((hi - mu) / sig) - ndtr((lo - mu) / sig)
+    return float(np.sum(np.prod(per, axis=1)))
+
+
+def test_PA4_av_estimator_is_unbiased_on_the_active_volume(orc):
+    """A product Gaussian over the seven unit-cube coordinates, integrated by
+    rounds of AV draws: each round's samples weighted by the active volume V
+    (ln p - ln p_s = ln V) estimate the exact integral over that round's active
+    cells (a closed form per cell), so the pooled estimator agrees within 4
+    sigma with the sample-weighted mean of those exact integrals; the active
+    cells keep >= 99 % of the whole integral."""
+    rng = np.random.default_rng(84)
+    mu = rng.uniform(0.35, 0.65, 7)
+    sig = np.full(7, 0.08)
+    norm = -0.5 * 7 * math.log(2 * math.pi) - float(np.sum(np.log(sig)))
+    full = _gauss_cell_integral(np.zeros((1, 7), dtype=np.int32), 1, mu, sig)
+    pr = orc.make_prior()
+    g = orc.av_init()
+    n, lws, expect, vols = 40000, [], 0.0, []
+    for r in range(5):
+        _, u = orc.draw_av(pr, g, 2024, r, 0, n)
+        lnL = norm - 0.5 * np.sum(((u.T - mu) / sig) ** 2, axis=1)
+        lws.append(lnL + g.ln_vol)
+        exact_r = _gauss_cell_integral(g.cells, g.nb, mu, sig)
+        assert exact_r >= 0.99 * full
+        expect += n * exact_r
+        vols.append(g.ln_vol)
+        g, _ = orc.av_update(g, u, lnL, p_thr=0.999, n_min_live=2000)
+    o = orc.marginalize(np.concatenate(lws))
+    expect = math.log(expect / (n * len(lws)))
+    sigma = math.exp(o["ln_sigma"] - o["ln_L"])
+    assert abs(o["ln_L"] - expect) <= 4 * sigma, (o["ln_L"], expect, sigma)
+    assert vols[-1] < math.log(0.05)          # the active volume shrank around the peak
+
+
+def test_PA6_av_rosenbrock_sampling_efficiency(orc):
+    """The paper's Rosenbrock demonstration: a grid over two unit-cube
+    coordinates (the other columns drawn from the prior, the volume counted
+    over the grid's dimensions only); the AV rounds sample far more
+    efficiently than the prior (n_eff/N of the last round vs the first)."""
+    pr = orc.make_prior()
+    g = orc.AvGrid(1, np.zeros((1, 2), dtype=np.int32), [0, 1])
+    n, eff = 20000, []
+    for r in range(5):
+        _, u = orc.draw_av(pr, g, 77, r, 0, n)
+        x, y = 4.0 * u[0] - 2.0, 4.0 * u[1] - 1.0
+        lnL = -((1.0 - x) ** 2 + 100.0 * (y - x * x) ** 2)
+        eff.append(orc.marginalize(lnL + g.ln_vol)["n_eff"] / n)
+        g, _ = orc.av_update(g, u, lnL, p_thr=0.999, n_min_live=1000)
+    assert eff[-1] > 5 * eff[0], eff
+
+
+def test_PA7_av_new_cells_hold_exactly_the_top_samples(orc):
+    """After an update every sample at or above the threshold lies in a listed
+    cell of the refined grid, every listed cell holds one, no cell is listed
+    twice, and the list follows the first such sample of each cell."""
+    pr = orc.make_prior()
+    g = orc.av_init()
+    rng = np.random.default_rng(85)
+    _, u = orc.draw_av(pr, g, 31, 0, 0, 30000)
+    lnL = -np.sum(((u.T - 0.4) / 0.15) ** 2, axis=1) + rng.normal(0, 0.1, 30000)
+    lnL[:100] = -np.inf
+    g2, info = orc.av_update(g, u, lnL, p_thr=0.99, n_min_live=300)
+    top = np.nonzero(lnL >= info["lnL_thr"])[0]
+    assert top.size == info["n_min"] >= 300
+    c = np.minimum(np.floor(u[:, top] * g2.nb), g2.nb - 1).astype(np.int64).T
+    listed = {tuple(x) for x in g2.cells}
+    assert len(listed) == g2.n_cells
+    assert {tuple(x) for x in c} == listed
+    first = []
+    for x in map(tuple, c):
+        if x not in first:
+            first.append(x)
+    assert [tuple(x) for x in g2.cells] == first
