@@ -232,6 +232,69 @@ ile_status ile_adapt_proposal(ile_job *job, int64_t n, const void *theta, int64_
                               const void *lw, const ile_gmm_opts *opts,
                               ile_gmm_params *out, ile_stream stream);
 
+/* ------------------------------------------------------- adaptive volume */
+/* The adaptive-volume (AV) integrator of Section "Adaptive volume
+ * integration": samples uniform over a set of active hypercubes of a grid of
+ * n_bins bins per sampled column, in the unit cube of the prior's CDF
+ * coordinates u (theta = the prior's inverse-CDF map of u), so that
+ * ln p - ln p_s = ln V for every sample, V = n_cells / n_bins^n_dim the active
+ * volume.  Each update takes one round's log-weights, sets a likelihood
+ * threshold, refines the bin count by eq. (nbins_V) and keeps the cells that
+ * hold a sample at or above the threshold.  The grid lives in device memory
+ * with the job; draws and updates are asynchronous on the stream and read it
+ * there (no host synchronisation). */
+typedef struct {
+    double p_thr;             /* enclosed probability the threshold keeps, (0, 1]; default 0.999 */
+    int64_t n_min_live;       /* at least this many highest samples kept; default 1000 */
+    int32_t max_bins;         /* cap on bins per dimension, 1..511; default 511 */
+} ile_av_opts;
+
+typedef struct {
+    int32_t n_dim;            /* sampled columns */
+    int32_t dims[7];          /* their theta columns (increasing), -1 beyond n_dim */
+    int32_t n_bins;           /* current grid */
+    int64_t n_cells;
+    double ln_vol;            /* ln V = ln n_cells - n_dim ln n_bins */
+    double lnL_thr;           /* last update: threshold (log-weight; -inf if none) */
+    int64_t n_min;            /*   samples at or above it */
+    int64_t n_live;           /*   samples of the round */
+    double vol_mc;            /*   Monte Carlo estimate V n_min / n_live of the volume above it */
+} ile_av_state;
+
+/* Start over from the whole cube (one cell, n_bins = 1) over the given theta
+ * columns (n_dim = 0: every sampled column, i.e. all seven, or six with
+ * dist_marg).  Columns outside the grid are drawn from the prior.  Errors:
+ * ILE_E_INVALID for columns not strictly increasing in 0..6 or column 3 with
+ * dist_marg. */
+ile_status ile_av_reset(ile_job *job, int32_t n_dim, const int32_t *dims, ile_stream stream);
+
+/* Draws of samples first_index .. first_index+n-1 of round `round` under key
+ * `seed`, uniform over the active cells (Philox-4x32-10 with the prior draw's
+ * counters: on the one-cell grid the draws are the prior draws).
+ * theta_out: device [7][ld] (theta type); lnpmps_out: device [n] = ln V, or
+ * NULL.  The first AV call on a job resets it (n_dim = 0). */
+ile_status ile_av_draw(ile_job *job, uint64_t seed, uint32_t round, int64_t first_index, int64_t n,
+                       void *theta_out, int64_t ld, void *lnpmps_out, ile_stream stream);
+
+/* Refine the grid from the samples of one ile_av_draw call (the same seed,
+ * round, first_index and n, with the grid unchanged since): lw device [n]
+ * log-weights (or log-likelihoods: only differences matter) in the policy's
+ * output type.  The threshold is the largest lw value v such that the samples
+ * at or above v hold at least min(ceil(p_thr total), total) of the fixed-point
+ * masses floor(exp(lw - max lw) 2^40) and number at least
+ * min(n_min_live, finite samples).  n_bins' = ceil((1/dV)^(1/n_dim)) clamped to
+ * [1, max_bins], dV = V n_min / (n sqrt(n_min)); the new cells are those of
+ * the n_bins' grid holding a sample at or above the threshold, in order of
+ * their first such sample.  With no finite lw the grid is kept.  opts may be
+ * NULL; out (host, may be NULL) synchronises the stream.  n < 2^31. */
+ile_status ile_av_update(ile_job *job, uint64_t seed, uint32_t round, int64_t first_index, int64_t n,
+                         const void *lw, const ile_av_opts *opts, ile_av_state *out, ile_stream stream);
+
+/* Current grid and last update (synchronises the stream).  cells: host
+ * [cap][n_dim] int32 cell coordinates in list order, or NULL; at most cap rows
+ * are written. */
+ile_status ile_av_get(ile_job *job, ile_av_state *out, int32_t *cells, int64_t cap, ile_stream stream);
+
 /* ---------------------------------------------------------------- serving */
 typedef struct {
     int32_t max_active;       /* jobs resident at once (default 64) */
@@ -250,7 +313,12 @@ typedef struct {
     int32_t tmarg_oversample; /* 0: pointwise lnL; 1 or 4: time-marginalised lnL (ile_eval_lnL_tmarg with
                                  this R; plain ILE_FP32/ILE_FP64 jobs without dist_marg only), with
                                  chunk_samples/16 samples per pass */
+    int32_t integrator;       /* adaptive: ILE_INT_GMM (mixture refits) or ILE_INT_AV (adaptive volume,
+                                 ile_av_update with default options after each round) */
 } ile_job_opts;
+
+#define ILE_INT_GMM 0
+#define ILE_INT_AV 1
 
 typedef struct {
     ile_marg marg;

@@ -328,8 +328,10 @@ def gmm_inbox_mass(prior, g, j, seed, rnd, m=1 << 16):
 #     q_i = floor(exp(lnL_i - max lnL) 2^40) (integer sums, so the threshold
 #     does not depend on summation order);
 #   * the threshold is the largest lnL value at or above which both at least
-#     p_thr of the total mass and at least min(n_min_live, n_finite) samples
-#     lie (the "fixed large number of highest points" of early iterations);
+#     min(ceil(p_thr * total), total) of the fixed-point mass (p_thr * total
+#     is formed in FP64, whose rounding can exceed the integer total) and at
+#     least min(n_min_live, n_finite) samples lie (the "fixed large number of
+#     highest points" of early iterations);
 #   * n_bins = ceil((1/dV)^(1/d)), clamped to [1, max_bins], with
 #     dV = V n_min / (n sqrt(n_min)) the Monte Carlo error of the live volume;
 #   * the new active cells are the cells of the refined grid holding a sample
@@ -394,7 +396,7 @@ def av_threshold(lnL, p_thr, n_min_live):
     q = av_mass(x)
     order = np.argsort(-x, kind="stable")
     cum = np.cumsum(q[order], dtype=np.uint64)
-    target = np.uint64(math.ceil(p_thr * float(cum[-1])))
+    target = min(np.uint64(math.ceil(p_thr * float(cum[-1]))), cum[-1])
     k_mass = int(np.argmax(cum >= target))
     k = min(int(n_min_live), x.size)
     thr = min(float(x[order[k_mass]]), float(x[order[k - 1]]))

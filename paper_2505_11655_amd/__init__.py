@@ -82,7 +82,25 @@ class ile_server_opts(C.Structure):
 class ile_job_opts(C.Structure):
     _fields_ = [("n_samples", C.c_int64), ("adaptive", C.c_int32), ("round_samples", C.c_int64),
                 ("max_rounds", C.c_int32), ("n_eff_target", C.c_double), ("seed", C.c_uint64),
-                ("tmarg_oversample", C.c_int32)]
+                ("tmarg_oversample", C.c_int32), ("integrator", C.c_int32)]
+
+
+ILE_INT_GMM, ILE_INT_AV = 0, 1
+
+
+class ile_av_opts(C.Structure):
+    _fields_ = [("p_thr", C.c_double), ("n_min_live", C.c_int64), ("max_bins", C.c_int32)]
+
+
+class ile_av_state(C.Structure):
+    _fields_ = [("n_dim", C.c_int32), ("dims", C.c_int32 * 7), ("n_bins", C.c_int32), ("n_cells", C.c_int64),
+                ("ln_vol", C.c_double), ("lnL_thr", C.c_double), ("n_min", C.c_int64), ("n_live", C.c_int64),
+                ("vol_mc", C.c_double)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "dims"}
+        d["dims"] = [self.dims[k] for k in range(self.n_dim)]
+        return d
 
 
 class ile_result(C.Structure):
@@ -120,6 +138,13 @@ EXPORTS = {
     "ile_get_proposal": (C.c_int, [C.c_void_p, C.POINTER(ile_gmm_params), C.c_void_p]),
     "ile_adapt_proposal": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                      C.POINTER(ile_gmm_opts), C.POINTER(ile_gmm_params), C.c_void_p]),
+    "ile_av_reset": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_void_p]),
+    "ile_av_draw": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
+                              C.c_void_p, C.c_void_p]),
+    "ile_av_update": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, C.c_void_p,
+                                C.POINTER(ile_av_opts), C.POINTER(ile_av_state), C.c_void_p]),
+    "ile_av_get": (C.c_int, [C.c_void_p, C.POINTER(ile_av_state), C.POINTER(C.c_int32), C.c_int64,
+                             C.c_void_p]),
     "ile_server_create": (C.c_int, [C.c_void_p, C.POINTER(ile_server_opts), C.POINTER(C.c_void_p)]),
     "ile_server_submit": (C.c_int, [C.c_void_p, C.POINTER(ile_problem), C.POINTER(ile_job_opts),
                                     C.POINTER(C.c_uint64)]),
@@ -319,6 +344,42 @@ def ile_adapt_proposal(job, n, theta, ld, lw, opts=None, want=True, stream=None)
     return p
 
 
+# ---------------------------------------------------------- adaptive volume
+def av_opts(p_thr=0.999, n_min_live=1000, max_bins=511):
+    return ile_av_opts(p_thr, n_min_live, max_bins)
+
+
+def ile_av_reset(job, dims=None, stream=None):
+    if dims is None:
+        _chk(lib().ile_av_reset(job, 0, None, _s(stream)))
+    else:
+        arr = (C.c_int32 * max(len(dims), 1))(*dims)
+        _chk(lib().ile_av_reset(job, len(dims), arr, _s(stream)))
+
+
+def ile_av_draw(job, seed, rnd, first_index, n, theta_out, ld, lnpmps_out=None, stream=None):
+    _chk(lib().ile_av_draw(job, seed, rnd, first_index, n, _p(theta_out), ld, _p(lnpmps_out), _s(stream)))
+
+
+def ile_av_update(job, seed, rnd, first_index, n, lw, opts=None, want=True, stream=None):
+    out = ile_av_state() if want else None
+    _chk(lib().ile_av_update(job, seed, rnd, first_index, n, _p(lw), C.byref(opts) if opts is not None else None,
+                             C.byref(out) if out is not None else None, _s(stream)))
+    return out.as_dict() if out is not None else None
+
+
+def ile_av_get(job, cells=True, stream=None):
+    """(state dict, cells [n_cells][n_dim] int32 numpy array or None)."""
+    import numpy as np
+    st = ile_av_state()
+    _chk(lib().ile_av_get(job, C.byref(st), None, 0, _s(stream)))
+    if not cells:
+        return st.as_dict(), None
+    arr = np.zeros((max(st.n_cells, 1), max(st.n_dim, 1)), dtype=np.int32)
+    _chk(lib().ile_av_get(job, C.byref(st), arr.ctypes.data_as(C.POINTER(C.c_int32)), st.n_cells, _s(stream)))
+    return st.as_dict(), arr[:st.n_cells, :st.n_dim]
+
+
 # ------------------------------------------------------------------ serving
 def ile_server_create(ctx, max_active=64, hbm_budget_bytes=0, chunk_samples=1 << 20):
     h = C.c_void_p()
@@ -328,8 +389,9 @@ def ile_server_create(ctx, max_active=64, hbm_budget_bytes=0, chunk_samples=1 <<
 
 
 def job_opts(n_samples=1 << 16, adaptive=False, round_samples=1 << 16, max_rounds=32, n_eff_target=1000.0,
-             seed=1, tmarg_oversample=0):
-    return ile_job_opts(n_samples, int(adaptive), round_samples, max_rounds, n_eff_target, seed, tmarg_oversample)
+             seed=1, tmarg_oversample=0, integrator=ILE_INT_GMM):
+    return ile_job_opts(n_samples, int(adaptive), round_samples, max_rounds, n_eff_target, seed, tmarg_oversample,
+                        integrator)
 
 
 def ile_server_submit(srv, problem: ProblemHost, opts):

@@ -561,7 +561,7 @@ extern "C" ile_status ile_job_info_get(const ile_job *job, ile_job_info *info) {
     info->mode_slots = kSets[job->set].n;
     info->n_det_slots = job->kp;
     info->device_bytes = job->device_bytes + job->part_cap * sizeof(MargPartial) + job->em_cap +
-                         (job->d_gmm ? sizeof(GmmDev) : 0);
+                         (job->d_gmm ? sizeof(GmmDev) : 0) + job->av_bytes;
     return ILE_OK;
 }
 
@@ -573,6 +573,8 @@ void ile::job_release_nosync(ile_job *job) {
     ctx_free(ctx, job->d_em, job->em_cap);
     ctx_free(ctx, job->d_gmm, sizeof(GmmDev));
     ctx_free(ctx, job->d_zcount, kMaxComp * sizeof(uint32_t));
+    ctx_free(ctx, job->av_mem, job->av_bytes);
+    pin_free(ctx, job->h_av, sizeof(AvDev));
     pin_free(ctx, job->h_blob, job->blob_bytes);
     pin_free(ctx, job->h_ms, sizeof(MargState));
     pin_free(ctx, job->h_gmm, sizeof(GmmDev));

@@ -65,6 +65,13 @@ struct ile_job {
     bool has_prop = false;
     double *d_em = nullptr;
     size_t em_cap = 0;
+    // adaptive-volume grid and update workspace (one allocation, made on
+    // first use and grown with the largest update)
+    ile::AvBufs av{};
+    void *av_mem = nullptr;
+    size_t av_bytes = 0;
+    int64_t av_cap = 0;
+    ile::AvDev *h_av = nullptr;           // pinned readback
 };
 
 namespace ile {
@@ -174,6 +181,11 @@ struct AdaptItem {
 ile_status adapt_batch(ile_ctx *ctx, int policy, const std::vector<AdaptItem> &items, const ile_gmm_opts *o,
                        hipStream_t st);
 void marg_from_state(const MargState &m, ile_marg *out);
+// Adaptive volume: buffers for updates of up to `cap` samples (the first call
+// also installs the whole-cube grid over the job's sampled columns); bytes a
+// job's AV buffers take for that cap.
+ile_status av_ensure(ile_job *job, int64_t cap, hipStream_t st);
+size_t av_bytes_for(int64_t cap);
 void eval_geometry(const ile_job *job, int64_t n, size_t *lds, int64_t *tile, int *block);
 size_t theta_size(int policy);
 size_t out_size(int policy);

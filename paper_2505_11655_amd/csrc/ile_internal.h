@@ -275,6 +275,26 @@ struct PriorDev {
     int dist_marg;
 };
 
+// Inverse-CDF map of seven uniforms onto the prior: alpha ~ U[0, 2pi),
+// p(dec) = cos(dec)/2, t ~ U[-t_w, t_w], p(D) = 3 D^2/(D_max^3 - D_min^3)
+// (D = d_ref when the distance is marginalised), cos(iota) ~ U[-1, 1],
+// phi_c ~ U[0, 2pi), psi ~ U[0, pi).
+__device__ __forceinline__ void prior_map(const PriorDev &pr, const double u[7], double th[7]) {
+    constexpr double kPiM = 3.14159265358979323846;
+    th[0] = 2 * kPiM * u[0];
+    th[1] = asin(2.0 * u[1] - 1.0);
+    th[2] = -pr.t_window + 2.0 * pr.t_window * u[2];
+    if (pr.dist_marg) {
+        th[3] = pr.d_ref;
+    } else {
+        const double a3 = pr.d_min * pr.d_min * pr.d_min, b3 = pr.d_max * pr.d_max * pr.d_max;
+        th[3] = cbrt(a3 + u[3] * (b3 - a3));
+    }
+    th[4] = 2.0 * u[4] - 1.0;
+    th[5] = 2 * kPiM * u[5];
+    th[6] = kPiM * u[6];
+}
+
 struct DrawJob {
     const GmmDev *gmm;    // null: prior draws
     PriorDev pr;
@@ -333,6 +353,53 @@ struct EmJob {
 hipError_t launch_gmm_factor(const EmJob *d_jobs, int n_jobs, hipStream_t st);
 // In-support masses Z_j of every job's mixture from z_draws candidates each.
 hipError_t launch_gmm_mass(const EmJob *d_jobs, int n_jobs, hipStream_t st);
+
+// ------------------------------------------------------- adaptive volume
+// Section "Adaptive volume integration": samples uniform over the active
+// hypercubes of a grid of nb bins per sampled column, in the unit cube of the
+// prior's CDF coordinates; after each round a likelihood threshold, a refined
+// bin count (eq. nbins_V) and the cells holding the samples above it.
+constexpr int kAvMaxBins = 511;
+constexpr int kAvMassBits = 40;
+struct AvDev {
+    int32_t d;            // sampled columns
+    int32_t dims[7];      // their theta columns (increasing)
+    int32_t kcol[7];      // grid dimension of each theta column, -1: drawn from the prior
+    int32_t nb;           // bins per dimension of the current grid
+    int32_t nb_next;      // of the grid the last update built
+    int32_t cur;          // which cell buffer holds the current grid
+    int32_t valid;        // the last update found a finite sample
+    int32_t pad_;
+    int64_t n_cells, n_cells_next;
+    double ln_vol;        // ln V = ln n_cells - d ln nb
+    // last update
+    double thr;           // threshold (log-weight)
+    int64_t n_min, n_live;
+    double vol_mc;        // V n_min / n_live
+    // threshold selection (radix select over order-preserving keys): chain 0
+    // follows the enclosed mass, chain 1 the count
+    double vmax;
+    unsigned long long key_max, n_fin, total;
+    unsigned long long prefix[2], above_cnt[2], above_mass[2], target[2], last_cnt[2];
+    unsigned long long thr_key;
+};
+struct AvBufs {
+    AvDev *st;
+    uint16_t *cells[2];           // [cap][8] cell coordinates, two buffers
+    unsigned long long *hkey;     // [hcap] cell ids of the open-addressing set
+    uint32_t *hidx;               // [hcap] first sample index of each cell
+    uint64_t hmask;               // hcap - 1
+    uint32_t *slot;               // [cap] set slot of each sample above the threshold
+    uint32_t *bcnt;               // [cap / 256 + 1] per-block counts, then offsets
+    unsigned long long *hist;     // [2 chains][256 digits][count, mass]
+};
+// Initial grid: one cell, nb = 1, over the given columns.
+hipError_t launch_av_reset(const AvBufs &b, int d, const int *dims, hipStream_t st);
+hipError_t launch_av_draw(int policy, const AvBufs &b, const PriorDev &pr, uint64_t seed, uint32_t round,
+                          int64_t first, int64_t n, void *theta, int64_t ld, void *lnpmps, hipStream_t st);
+// lw: [n] the round's log-weights in the policy's output type.
+hipError_t launch_av_update(int policy, const AvBufs &b, uint64_t seed, uint32_t round, int64_t first, int64_t n,
+                            const void *lw, double p_thr, int64_t n_min_live, int max_bins, hipStream_t st);
 // Weighted EM refit of every job: max and tempering exponent, first fit for
 // jobs with `first`, then n_iter iterations.  h_jobs: host copy of d_jobs.
 hipError_t launch_em_batch(int policy, const EmJob *d_jobs, const EmJob *h_jobs, int n_jobs, int n_iter,

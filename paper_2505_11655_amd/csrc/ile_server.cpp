@@ -110,7 +110,10 @@ size_t footprint_of(const ile_server *s, const Req *r) {
     const int64_t c = chunk_of(s, r);
     const size_t bufs = (size_t)c * (8 * theta_bytes(policy) + lw_bytes(policy));
     size_t extra = sizeof(MargState) + ((size_t)c / 16384 + 1) * sizeof(MargPartial);
-    if (r->jo.adaptive) extra += sizeof(GmmDev) + em_work_bytes(c) + 64 * sizeof(uint32_t);
+    if (r->jo.adaptive && r->jo.integrator == ILE_INT_AV)
+        extra += av_bytes_for(c);
+    else if (r->jo.adaptive)
+        extra += sizeof(GmmDev) + em_work_bytes(c) + 64 * sizeof(uint32_t);
     return inputs + bufs + extra;
 }
 
@@ -147,6 +150,8 @@ ile_status admit(ile_server *s, Req *r) {
     r->chunk = chunk_of(s, r);
     const int policy = r->prob.precision;
     const size_t tb = theta_bytes(policy);
+    if (r->jo.adaptive && r->jo.integrator == ILE_INT_AV && (st = av_ensure(job, r->chunk, s->stream)) != ILE_OK)
+        return st;
     if ((st = ctx_alloc(s->ctx, &r->d_theta, (size_t)7 * r->chunk * tb, "theta")) != ILE_OK) return st;
     if ((st = ctx_alloc(s->ctx, &r->d_lr, (size_t)r->chunk * tb, "ln p - ln ps")) != ILE_OK) return st;
     if ((st = ctx_alloc(s->ctx, &r->d_lw, (size_t)r->chunk * lw_bytes(policy), "lw")) != ILE_OK) return st;
@@ -167,6 +172,17 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
         if (r->res.t_start_ns == 0) r->res.t_start_ns = t_start;
         const int64_t n = r->jo.adaptive ? r->chunk : std::min(r->chunk, r->jo.n_samples - r->done);
         nthis[i] = n;
+        const BatchItem bi{r->job, n, r->d_theta, n, r->d_lr, nullptr, r->d_lw};
+        (r->jo.tmarg_oversample == 4 ? tm4 : r->jo.tmarg_oversample == 1 ? tm1 : items).push_back(bi);
+        if (r->jo.adaptive && r->jo.integrator == ILE_INT_AV) {
+            const hipError_t e = launch_av_draw(r->job->policy, r->job->av, r->job->pr, r->jo.seed,
+                                                (uint32_t)r->rounds, 0, n, r->d_theta, n, r->d_lr, st);
+            if (e != hipSuccess) {
+                dev_fail(s->ctx, e, "adaptive-volume draw");
+                return false;
+            }
+            continue;
+        }
         DrawJob dj{};
         dj.gmm = r->job->has_prop ? r->job->d_gmm : nullptr;
         dj.pr = r->job->pr;
@@ -178,8 +194,6 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
         dj.lnpmps = r->d_lr;
         dj.n = n;
         (r->prob.precision == kFP64 ? d64 : d32).push_back(dj);
-        const BatchItem bi{r->job, n, r->d_theta, n, r->d_lr, nullptr, r->d_lw};
-        (r->jo.tmarg_oversample == 4 ? tm4 : r->jo.tmarg_oversample == 1 ? tm1 : items).push_back(bi);
     }
     if (!d32.empty() && draw_batch(s->ctx, kFP32, d32, st) != ILE_OK) return false;
     if (!d64.empty() && draw_batch(s->ctx, kFP64, d64, st) != ILE_OK) return false;
@@ -238,6 +252,17 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
                         s->active.end());
     }
     s->cv_done.notify_all();
+    // adaptive-volume jobs: refine the grid from the round just evaluated
+    // (drawn with round index rounds - 1)
+    for (Req *r : refit) {
+        if (r->jo.integrator != ILE_INT_AV) continue;
+        const hipError_t e = launch_av_update(r->job->policy, r->job->av, r->jo.seed, (uint32_t)(r->rounds - 1), 0,
+                                              r->chunk, r->d_lw, 0.999, 1000, kAvMaxBins, st);
+        if (e != hipSuccess) {
+            dev_fail(s->ctx, e, "adaptive-volume update");
+            return false;
+        }
+    }
     // one batched refit per precision policy; each job's mass draws use its
     // own key and round
     ile_gmm_opts o{};
@@ -249,7 +274,7 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
     for (int pol = 0; pol < 3; pol++) {
         std::vector<AdaptItem> items;
         for (Req *r : refit)
-            if (r->job->policy == pol)
+            if (r->job->policy == pol && r->jo.integrator != ILE_INT_AV)
                 items.push_back(AdaptItem{r->job, r->chunk, r->d_theta, r->chunk, r->d_lw,
                                           r->jo.seed ^ 0x9E3779B97F4A7C15ull, (uint32_t)r->rounds});
         if (!items.empty() && adapt_batch(s->ctx, pol, items, &o, st) != ILE_OK) return false;
@@ -334,6 +359,10 @@ extern "C" ile_status ile_server_submit(ile_server *s, const ile_problem *P, con
         !P->U || !P->mode_l || !P->mode_m || !P->det_pos || !P->det_resp)
         return set_err(ILE_E_INVALID, "bad problem shape");
     if (!jo->adaptive && jo->n_samples < 1) return set_err(ILE_E_INVALID, "n_samples must be >= 1");
+    if (jo->integrator != ILE_INT_GMM && jo->integrator != ILE_INT_AV)
+        return set_err(ILE_E_INVALID, "integrator must be ILE_INT_GMM or ILE_INT_AV");
+    if (jo->adaptive && jo->round_samples >= ((int64_t)1 << 31))
+        return set_err(ILE_E_INVALID, "round_samples must be below 2^31");
     if (jo->tmarg_oversample != 0) {
         if (jo->tmarg_oversample != 1 && jo->tmarg_oversample != 4)
             return set_err(ILE_E_INVALID, "tmarg_oversample must be 0, 1 or 4");

@@ -1,0 +1,475 @@
+// Adaptive volume integration (Section "Adaptive volume integration") on the
+// GPU: the sampler is uniform over a set of active hypercubes of a grid of nb
+// bins per sampled column, in the unit cube of the prior's CDF coordinates u
+// (theta = inverse-CDF map of u), so ln p - ln p_s = ln V with V the active
+// volume.  After a round of n samples with log-weights lw:
+//   1. threshold: the largest lw value v such that the samples at or above v
+//      hold at least min(ceil(p_thr * total), total) of the fixed-point masses
+//      q_i = floor(exp(lw_i - max lw) 2^40) and number at least
+//      min(n_min_live, n_finite).  Found by two radix selects (one on the
+//      enclosed mass, one on the count) over order-preserving integer keys of
+//      lw, eight bits per pass; integer sums make it independent of the order
+//      of accumulation.
+//   2. refinement, eq. (nbins_V): nb' = ceil((1/dV)^(1/d)) with
+//      dV = V n_min / (n sqrt(n_min)), clamped to [1, max_bins].
+//   3. the new active cells: the cells of the nb' grid holding a sample at or
+//      above the threshold, each listed once, in order of its first such
+//      sample (an open-addressing set keeps each cell's lowest sample index;
+//      a block-count scan compacts the first samples in index order).
+// A sample's u is regenerated from its Philox counter and the grid it was
+// drawn from, so the update needs no stored coordinates.
+//
+// Counter layout (the prior draw's): sample i of round r uses blocks 0..3 of
+// attempt 0, ctr = (i lo, i hi, r, b); column c takes u53(w[2c], w[2c+1]) and
+// the cell is floor(u53(w14, w15) n_cells) (at most n_cells - 1), so the
+// one-cell grid draws exactly the prior.
+#include "ile_internal.h"
+
+namespace ile {
+
+namespace {
+
+constexpr int kAvThreads = 256;
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+constexpr unsigned long long kEmpty = ~0ull;
+
+__device__ __forceinline__ void av_words(uint64_t seed, uint64_t i, uint32_t r, uint32_t *w) {
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+        const U4 o = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), r, (uint32_t)b}, k0, k1);
+        w[4 * b + 0] = o.x;
+        w[4 * b + 1] = o.y;
+        w[4 * b + 2] = o.z;
+        w[4 * b + 3] = o.w;
+    }
+}
+
+// Unit-cube coordinates of one sample drawn from the grid (nb, n_cells, cells).
+__device__ __forceinline__ void av_unit(const AvDev &S, const uint16_t *cells, const uint32_t *w, double u[7]) {
+    const double sel = floor(u53(w[14], w[15]) * (double)S.n_cells);
+    int64_t j = (int64_t)sel;
+    if (j > S.n_cells - 1) j = S.n_cells - 1;
+    const uint16_t *cj = cells + j * 8;
+    const double nbd = (double)S.nb;
+#pragma unroll
+    for (int c = 0; c < 7; c++) {
+        const double U = u53(w[2 * c], w[2 * c + 1]);
+        const int k = S.kcol[c];
+        u[c] = k >= 0 ? ((double)cj[k] + U) / nbd : U;
+    }
+}
+
+__device__ __forceinline__ const uint16_t *cur_cells(const AvBufs &b, const AvDev &S) {
+    return S.cur ? b.cells[1] : b.cells[0];
+}
+
+// Order-preserving keys: key(a) < key(b) iff a < b for finite values (-0 is
+// taken as +0 first).
+__device__ __forceinline__ unsigned long long okey(float v) {
+    const uint32_t bits = __float_as_uint(v + 0.0f);
+    return (unsigned long long)((bits & 0x80000000u) ? ~bits : (bits | 0x80000000u));
+}
+__device__ __forceinline__ unsigned long long okey(double v) {
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v + 0.0);
+    return (bits >> 63) ? ~bits : (bits | (1ull << 63));
+}
+__device__ __forceinline__ double key_value(unsigned long long k, int nbits) {
+    if (nbits == 32) {
+        const uint32_t kk = (uint32_t)k;
+        const uint32_t bits = (kk & 0x80000000u) ? (kk & 0x7FFFFFFFu) : ~kk;
+        return (double)__uint_as_float(bits);
+    }
+    const unsigned long long bits = (k >> 63) ? (k & ~(1ull << 63)) : ~k;
+    return __longlong_as_double((long long)bits);
+}
+
+__device__ __forceinline__ unsigned long long mass_fx(double v, double vmax) {
+    return (unsigned long long)floor(exp(v - vmax) * (double)(1ull << kAvMassBits));
+}
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
+    x ^= x >> 30;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 27;
+    x *= 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return x;
+}
+
+__global__ void k_av_reset(AvBufs b, int d, int d0, int d1, int d2, int d3, int d4, int d5, int d6) {
+    if (threadIdx.x != 0) return;
+    AvDev &S = *b.st;
+    const int dims[7] = {d0, d1, d2, d3, d4, d5, d6};
+    S.d = d;
+    for (int c = 0; c < 7; c++) S.kcol[c] = -1;
+    for (int k = 0; k < 7; k++) {
+        S.dims[k] = k < d ? dims[k] : -1;
+        if (k < d) S.kcol[dims[k]] = k;
+    }
+    S.nb = 1;
+    S.nb_next = 1;
+    S.cur = 0;
+    S.valid = 0;
+    S.n_cells = 1;
+    S.n_cells_next = 1;
+    S.ln_vol = 0.0;
+    S.thr = -INFINITY;
+    S.n_min = 0;
+    S.n_live = 0;
+    S.vol_mc = 0.0;
+    for (int k = 0; k < 8; k++) b.cells[0][k] = 0;
+}
+
+template <class TT>
+__global__ void __launch_bounds__(kAvThreads)
+    k_av_draw(AvBufs b, PriorDev pr, uint64_t seed, uint32_t round, int64_t first, int64_t n,
+              TT *__restrict__ th_out, int64_t ld, TT *__restrict__ lr_out) {
+    const AvDev &S = *b.st;
+    const uint16_t *cells = cur_cells(b, S);
+    const double lnv = S.ln_vol;
+    for (int64_t s = (int64_t)blockIdx.x * kAvThreads + threadIdx.x; s < n; s += (int64_t)gridDim.x * kAvThreads) {
+        uint32_t w[16];
+        av_words(seed, (uint64_t)(first + s), round, w);
+        double u[7], th[7];
+        av_unit(S, cells, w, u);
+        prior_map(pr, u, th);
+#pragma unroll
+        for (int c = 0; c < 7; c++) th_out[c * ld + s] = (TT)th[c];
+        if (lr_out) lr_out[s] = (TT)lnv;
+    }
+}
+
+__global__ void k_av_begin(AvBufs b) {
+    AvDev &S = *b.st;
+    if (threadIdx.x == 0) {
+        S.key_max = 0;
+        S.n_fin = 0;
+        S.total = 0;
+        for (int c = 0; c < 2; c++) {
+            S.prefix[c] = 0;
+            S.above_cnt[c] = 0;
+            S.above_mass[c] = 0;
+            S.target[c] = 0;
+            S.last_cnt[c] = 0;
+        }
+        S.valid = 0;
+        S.thr = -INFINITY;
+        S.n_min = 0;
+        S.vol_mc = 0.0;
+    }
+    for (int i = threadIdx.x; i < 2 * 256 * 2; i += blockDim.x) b.hist[i] = 0;
+}
+
+template <class TO>
+__global__ void __launch_bounds__(kAvThreads) k_av_max(AvBufs b, const TO *__restrict__ lw, int64_t n) {
+    unsigned long long km = 0, cnt = 0;
+    for (int64_t s = (int64_t)blockIdx.x * kAvThreads + threadIdx.x; s < n; s += (int64_t)gridDim.x * kAvThreads) {
+        const TO v = lw[s];
+        if (isfinite(v)) {
+            const unsigned long long k = okey(v);
+            km = k > km ? k : km;
+            cnt += 1;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long k2 = __shfl_xor(km, o);
+        km = k2 > km ? k2 : km;
+        cnt += __shfl_xor(cnt, o);
+    }
+    __shared__ unsigned long long smk[kAvThreads / 64], smc[kAvThreads / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        smk[wv] = km;
+        smc[wv] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kAvThreads / 64; i++) {
+            km = smk[i] > km ? smk[i] : km;
+            cnt += smc[i];
+        }
+        if (cnt) {
+            atomicMax(&b.st->key_max, km);
+            atomicAdd(&b.st->n_fin, cnt);
+        }
+    }
+}
+
+// One radix-select pass: digit (key >> shift) & 255 of every finite sample
+// whose higher digits match the chain's prefix; chain 0 counts and sums the
+// fixed-point masses, chain 1 counts.
+template <class TO>
+__global__ void __launch_bounds__(kAvThreads) k_av_hist(AvBufs b, const TO *__restrict__ lw, int64_t n, int shift) {
+    const AvDev &S = *b.st;
+    if (S.n_fin == 0) return;
+    __shared__ unsigned long long h[2 * 256 * 2];
+    for (int i = threadIdx.x; i < 2 * 256 * 2; i += kAvThreads) h[i] = 0;
+    __syncthreads();
+    constexpr int nbits = sizeof(TO) * 8;
+    const bool top = shift + 8 == nbits;
+    const unsigned long long p0 = top ? 0 : (S.prefix[0] >> (shift + 8));
+    const unsigned long long p1 = top ? 0 : (S.prefix[1] >> (shift + 8));
+    const double vmax = key_value(S.key_max, nbits);
+    for (int64_t s = (int64_t)blockIdx.x * kAvThreads + threadIdx.x; s < n; s += (int64_t)gridDim.x * kAvThreads) {
+        const TO v = lw[s];
+        if (!isfinite(v)) continue;
+        const unsigned long long k = okey(v);
+        const unsigned long long hi = top ? 0 : (k >> (shift + 8));
+        const int dg = (int)((k >> shift) & 255u);
+        if (hi == p0) {
+            atomicAdd(&h[(0 * 256 + dg) * 2 + 0], 1ull);
+            atomicAdd(&h[(0 * 256 + dg) * 2 + 1], mass_fx((double)v, vmax));
+        }
+        if (hi == p1) atomicAdd(&h[(1 * 256 + dg) * 2 + 0], 1ull);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * 256 * 2; i += kAvThreads)
+        if (h[i]) atomicAdd(&b.hist[i], h[i]);
+}
+
+// Choose each chain's digit, clear the histogram; after the last pass, the
+// threshold, n_min and the refined bin count of eq. (nbins_V).
+__global__ void k_av_pick(AvBufs b, int shift, int nbits, double p_thr, long long n_min_live, int max_bins,
+                          long long n) {
+    AvDev &S = *b.st;
+    if (threadIdx.x == 0 && S.n_fin > 0) {
+        const unsigned long long *H = b.hist;
+        if (shift + 8 == nbits) {
+            unsigned long long tot = 0;
+            for (int d = 0; d < 256; d++) tot += H[(0 * 256 + d) * 2 + 1];
+            S.total = tot;
+            const unsigned long long tm = (unsigned long long)ceil(p_thr * (double)tot);
+            S.target[0] = tm < tot ? tm : tot;
+            S.target[1] = (unsigned long long)n_min_live < S.n_fin ? (unsigned long long)n_min_live : S.n_fin;
+            S.valid = 1;
+        }
+        for (int c = 0; c < 2; c++) {
+            unsigned long long acc_c = 0, acc_m = 0;
+            int pick = 0;
+            for (int d = 255; d >= 0; d--) {
+                const unsigned long long cc = H[(c * 256 + d) * 2 + 0], mm = H[(c * 256 + d) * 2 + 1];
+                const bool hit = c == 0 ? (S.above_mass[0] + acc_m + mm >= S.target[0])
+                                        : (S.above_cnt[1] + acc_c + cc >= S.target[1]);
+                if (hit) {
+                    pick = d;
+                    S.last_cnt[c] = cc;
+                    break;
+                }
+                acc_c += cc;
+                acc_m += mm;
+            }
+            S.above_cnt[c] += acc_c;
+            S.above_mass[c] += acc_m;
+            S.prefix[c] |= (unsigned long long)pick << shift;
+        }
+        if (shift == 0) {
+            const int c = S.prefix[0] <= S.prefix[1] ? 0 : 1;
+            S.thr_key = S.prefix[c];
+            S.n_min = (int64_t)(S.above_cnt[c] + S.last_cnt[c]);
+            S.thr = key_value(S.thr_key, nbits);
+            S.vol_mc = exp(S.ln_vol) * (double)S.n_min / (double)n;
+            const double ln_dv = S.ln_vol + 0.5 * log((double)S.n_min) - log((double)n);
+            const double x = exp(-ln_dv / (double)S.d);
+            double nbd = ceil(x - 1e-9);
+            nbd = nbd < 1.0 ? 1.0 : (nbd > (double)max_bins ? (double)max_bins : nbd);
+            S.nb_next = (int)nbd;
+        }
+    }
+    if (threadIdx.x == 0) S.n_live = n;
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * 256 * 2; i += blockDim.x) b.hist[i] = 0;
+}
+
+__global__ void __launch_bounds__(kAvThreads) k_av_hclear(AvBufs b) {
+    const AvDev &S = *b.st;
+    if (!S.valid) return;
+    for (uint64_t i = (uint64_t)blockIdx.x * kAvThreads + threadIdx.x; i <= b.hmask;
+         i += (uint64_t)gridDim.x * kAvThreads) {
+        b.hkey[i] = kEmpty;
+        b.hidx[i] = kNoSlot;
+    }
+}
+
+// Cells (of the refined grid) of the samples at or above the threshold, into
+// the set; each slot keeps the lowest sample index that reached it.
+template <class TO>
+__global__ void __launch_bounds__(kAvThreads)
+    k_av_insert(AvBufs b, uint64_t seed, uint32_t round, int64_t first, const TO *__restrict__ lw, int64_t n) {
+    const AvDev &S = *b.st;
+    if (!S.valid) return;
+    const unsigned long long thr = S.thr_key;
+    const unsigned long long nb2 = (unsigned long long)S.nb_next;
+    const double nb2d = (double)S.nb_next;
+    const uint16_t *cells = cur_cells(b, S);
+    for (int64_t s = (int64_t)blockIdx.x * kAvThreads + threadIdx.x; s < n; s += (int64_t)gridDim.x * kAvThreads) {
+        const TO v = lw[s];
+        uint32_t sl = kNoSlot;
+        if (isfinite(v) && okey(v) >= thr) {
+            uint32_t w[16];
+            av_words(seed, (uint64_t)(first + s), round, w);
+            double u[7];
+            av_unit(S, cells, w, u);
+            unsigned long long id = 0;
+#pragma unroll
+            for (int c = 6; c >= 0; c--) {
+                if (S.kcol[c] >= 0) {
+                    double f = floor(u[c] * nb2d);
+                    f = f > nb2d - 1.0 ? nb2d - 1.0 : f;
+                    id = id * nb2 + (unsigned long long)f;
+                }
+            }
+            uint64_t h = mix64(id) & b.hmask;
+            for (uint64_t probe = 0; probe <= b.hmask; probe++) {
+                const unsigned long long prev = atomicCAS(&b.hkey[h], kEmpty, id);
+                if (prev == kEmpty || prev == id) {
+                    atomicMin(&b.hidx[h], (uint32_t)s);
+                    sl = (uint32_t)h;
+                    break;
+                }
+                h = (h + 1) & b.hmask;
+            }
+        }
+        b.slot[s] = sl;
+    }
+}
+
+// The sample is the first (lowest index) of its cell.
+__device__ __forceinline__ bool av_first(const AvBufs &b, int64_t s, int64_t n) {
+    if (s >= n) return false;
+    const uint32_t sl = b.slot[s];
+    return sl != kNoSlot && b.hidx[sl] == (uint32_t)s;
+}
+
+__global__ void __launch_bounds__(kAvThreads) k_av_count(AvBufs b, int64_t n) {
+    const AvDev &S = *b.st;
+    if (!S.valid) return;
+    const int64_t s = (int64_t)blockIdx.x * kAvThreads + threadIdx.x;
+    const int c = __syncthreads_count(av_first(b, s, n));
+    if (threadIdx.x == 0) b.bcnt[blockIdx.x] = (uint32_t)c;
+}
+
+// Exclusive scan of the per-block counts in place; the total is the new
+// number of cells.
+constexpr int kScanThreads = 1024;
+__global__ void __launch_bounds__(kScanThreads) k_av_scan(AvBufs b, int nblk) {
+    AvDev &S = *b.st;
+    if (!S.valid) return;
+    __shared__ unsigned long long sm[kScanThreads];
+    const int per = (nblk + kScanThreads - 1) / kScanThreads;
+    const int lo = threadIdx.x * per, hi = lo + per < nblk ? lo + per : nblk;
+    unsigned long long loc = 0;
+    for (int i = lo; i < hi; i++) loc += b.bcnt[i];
+    sm[threadIdx.x] = loc;
+    __syncthreads();
+    for (int o = 1; o < kScanThreads; o <<= 1) {
+        const unsigned long long add = threadIdx.x >= (unsigned)o ? sm[threadIdx.x - o] : 0ull;
+        __syncthreads();
+        sm[threadIdx.x] += add;
+        __syncthreads();
+    }
+    unsigned long long run = sm[threadIdx.x] - loc;
+    for (int i = lo; i < hi; i++) {
+        const uint32_t c = b.bcnt[i];
+        b.bcnt[i] = (uint32_t)run;
+        run += c;
+    }
+    if (threadIdx.x == kScanThreads - 1) S.n_cells_next = (int64_t)sm[kScanThreads - 1];
+}
+
+__global__ void __launch_bounds__(kAvThreads) k_av_compact(AvBufs b, int64_t n) {
+    const AvDev &S = *b.st;
+    if (!S.valid) return;
+    const int64_t s = (int64_t)blockIdx.x * kAvThreads + threadIdx.x;
+    const bool f = av_first(b, s, n);
+    const unsigned long long m = __ballot(f);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ int wc[kAvThreads / 64];
+    if (lane == 0) wc[wv] = __popcll(m);
+    __syncthreads();
+    if (!f) return;
+    int off = 0;
+    for (int i = 0; i < wv; i++) off += wc[i];
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    const int64_t pos = (int64_t)b.bcnt[blockIdx.x] + off + rank;
+    uint16_t *out = (S.cur ? b.cells[0] : b.cells[1]) + pos * 8;
+    unsigned long long id = b.hkey[b.slot[s]];
+    const unsigned long long nb2 = (unsigned long long)S.nb_next;
+    for (int k = 0; k < 8; k++) {
+        if (k < S.d) {
+            out[k] = (uint16_t)(id % nb2);
+            id /= nb2;
+        } else {
+            out[k] = 0;
+        }
+    }
+}
+
+__global__ void k_av_finish(AvBufs b) {
+    if (threadIdx.x != 0) return;
+    AvDev &S = *b.st;
+    if (!S.valid) return;
+    S.cur ^= 1;
+    S.nb = S.nb_next;
+    S.n_cells = S.n_cells_next;
+    S.ln_vol = log((double)S.n_cells) - S.d * log((double)S.nb);
+}
+
+int grid_for(int64_t n, int per_thread) {
+    const int64_t g = (n + (int64_t)kAvThreads * per_thread - 1) / ((int64_t)kAvThreads * per_thread);
+    return (int)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+}
+
+template <class TO>
+hipError_t av_update_t(const AvBufs &b, uint64_t seed, uint32_t round, int64_t first, int64_t n, const TO *lw,
+                       double p_thr, int64_t n_min_live, int max_bins, hipStream_t st) {
+    constexpr int nbits = sizeof(TO) * 8;
+    hipLaunchKernelGGL(k_av_begin, dim3(1), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_av_max<TO>, dim3(grid_for(n, 16)), dim3(kAvThreads), 0, st, b, lw, n);
+    for (int shift = nbits - 8; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(k_av_hist<TO>, dim3(grid_for(n, 16)), dim3(kAvThreads), 0, st, b, lw, n, shift);
+        hipLaunchKernelGGL(k_av_pick, dim3(1), dim3(256), 0, st, b, shift, nbits, p_thr, (long long)n_min_live,
+                           max_bins, (long long)n);
+    }
+    hipLaunchKernelGGL(k_av_hclear, dim3(grid_for((int64_t)b.hmask + 1, 4)), dim3(kAvThreads), 0, st, b);
+    hipLaunchKernelGGL(k_av_insert<TO>, dim3(grid_for(n, 4)), dim3(kAvThreads), 0, st, b, seed, round, first, lw,
+                       n);
+    const int nblk = (int)((n + kAvThreads - 1) / kAvThreads);
+    hipLaunchKernelGGL(k_av_count, dim3(nblk), dim3(kAvThreads), 0, st, b, n);
+    hipLaunchKernelGGL(k_av_scan, dim3(1), dim3(kScanThreads), 0, st, b, nblk);
+    hipLaunchKernelGGL(k_av_compact, dim3(nblk), dim3(kAvThreads), 0, st, b, n);
+    hipLaunchKernelGGL(k_av_finish, dim3(1), dim3(64), 0, st, b);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_av_reset(const AvBufs &b, int d, const int *dims, hipStream_t st) {
+    int dd[7] = {-1, -1, -1, -1, -1, -1, -1};
+    for (int k = 0; k < d && k < 7; k++) dd[k] = dims[k];
+    hipLaunchKernelGGL(k_av_reset, dim3(1), dim3(64), 0, st, b, d, dd[0], dd[1], dd[2], dd[3], dd[4], dd[5], dd[6]);
+    return hipGetLastError();
+}
+
+hipError_t launch_av_draw(int policy, const AvBufs &b, const PriorDev &pr, uint64_t seed, uint32_t round,
+                          int64_t first, int64_t n, void *theta, int64_t ld, void *lnpmps, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (policy == kFP64)
+        hipLaunchKernelGGL(k_av_draw<double>, dim3(grid_for(n, 4)), dim3(kAvThreads), 0, st, b, pr, seed, round,
+                           first, n, (double *)theta, ld, (double *)lnpmps);
+    else
+        hipLaunchKernelGGL(k_av_draw<float>, dim3(grid_for(n, 4)), dim3(kAvThreads), 0, st, b, pr, seed, round,
+                           first, n, (float *)theta, ld, (float *)lnpmps);
+    return hipGetLastError();
+}
+
+hipError_t launch_av_update(int policy, const AvBufs &b, uint64_t seed, uint32_t round, int64_t first, int64_t n,
+                            const void *lw, double p_thr, int64_t n_min_live, int max_bins, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (policy == kFP32)
+        return av_update_t<float>(b, seed, round, first, n, (const float *)lw, p_thr, n_min_live, max_bins, st);
+    return av_update_t<double>(b, seed, round, first, n, (const double *)lw, p_thr, n_min_live, max_bins, st);
+}
+
+}  // namespace ile

@@ -73,18 +73,7 @@ __device__ __forceinline__ void prior_from_words(const PriorDev &pr, const uint3
     double u[7];
 #pragma unroll
     for (int c = 0; c < 7; c++) u[c] = u53(w[2 * c], w[2 * c + 1]);
-    th[0] = 2 * kPi * u[0];
-    th[1] = asin(2.0 * u[1] - 1.0);
-    th[2] = -pr.t_window + 2.0 * pr.t_window * u[2];
-    if (pr.dist_marg) {
-        th[3] = pr.d_ref;
-    } else {
-        const double a3 = pr.d_min * pr.d_min * pr.d_min, b3 = pr.d_max * pr.d_max * pr.d_max;
-        th[3] = cbrt(a3 + u[3] * (b3 - a3));
-    }
-    th[4] = 2.0 * u[4] - 1.0;
-    th[5] = 2 * kPi * u[5];
-    th[6] = kPi * u[6];
+    prior_map(pr, u, th);
 }
 
 // wrapped difference in (-P/2, P/2]: d - P floor(d/P), folded; for |d| < P

@@ -217,3 +217,43 @@ def test_adaptive_job():
           "plain n_eff", rp.marg.n_eff)
     assert sp < 0.2, "reference run not converged"
     assert abs(ra.marg.ln_L - rp.marg.ln_L) < 5 * np.hypot(sa, sp) + 0.05
+
+
+def test_av_job_matches_oracle_loop(orc, pool):
+    """An adaptive-volume job (FP64) runs the same rounds as an oracle loop of
+    AV draws, oracle likelihood and AV updates with the server's options
+    (p_thr 0.999, 1000 highest samples, 511 bins): same round count, pooled
+    estimate to 1e-9; alone and in a mix of other jobs it gives bitwise the
+    same result."""
+    p = pool[0]
+    ph = ile.ProblemHost(p, precision=ile.ILE_FP64)
+    n, seed, max_rounds, target = 1 << 14, 606, 6, 2000.0
+    jo = ile.job_opts(adaptive=True, round_samples=n, max_rounds=max_rounds, n_eff_target=target, seed=seed,
+                      integrator=ile.ILE_INT_AV)
+    srv = ile.ile_server_create(gu.ctx())
+    try:
+        alone = ile.ile_server_wait(srv, ile.ile_server_submit(srv, ph, jo), 120000)
+        others = [_submit(srv, s) for s in _specs(pool)[:6]]
+        jid = ile.ile_server_submit(srv, ph, jo)
+        mixed = ile.ile_server_wait(srv, jid, 120000)
+        for j, _ in others:
+            ile.ile_server_wait(srv, j, 120000)
+    finally:
+        ile.ile_server_destroy(srv)
+    assert alone.status == 0 and mixed.status == 0
+    assert _res(alone) == _res(mixed)
+    pr = orc.make_prior(t_window=p.t_window, d_min=p.d_min, d_max=p.d_max)
+    g = orc.av_init()
+    lws = []
+    for rnd in range(max_rounds):
+        th, u = orc.draw_av(pr, g, seed, rnd, 0, n)
+        lw = orc.lnL(p, th) + g.ln_vol
+        lws.append(lw)
+        o = orc.marginalize(np.concatenate(lws))
+        if o["n_eff"] >= target or rnd + 1 == max_rounds:
+            break
+        g, _ = orc.av_update(g, u, lw)
+    print("AV job", alone.rounds, alone.marg.ln_L, alone.marg.n_eff, "oracle", len(lws), o["ln_L"], o["n_eff"])
+    assert alone.rounds == len(lws)
+    assert abs(alone.marg.ln_L - o["ln_L"]) <= 1e-9 * max(1.0, abs(o["ln_L"]))
+    assert abs(alone.marg.n_eff - o["n_eff"]) <= 1e-8 * o["n_eff"]

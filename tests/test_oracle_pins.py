@@ -683,7 +683,8 @@ def test_PA2_av_draws_uniform_over_active_cells(orc):
 @pytest.mark.parametrize("case", range(6))
 def test_PA3_av_threshold_is_the_largest_feasible_value(orc, case):
     """The threshold is the largest finite lnL value v such that the samples at
-    or above v hold at least ceil(p_thr * total) of the fixed-point mass and
+    or above v hold at least min(ceil(p_thr * total), total) of the fixed-point
+    mass and
     number at least min(n_min_live, n_finite): found here by trying every
     distinct value, against the oracle's sorted cumulative sum."""
     rng = np.random.default_rng(81 + case)
@@ -697,7 +698,7 @@ def test_PA3_av_threshold_is_the_largest_feasible_value(orc, case):
     q = [int(math.floor(math.exp(v - m) * 2.0 ** 40)) for v in fin]
     total = sum(q)
     for p_thr, k in [(0.999, 1), (0.9, 10), (0.5, 100), (1.0, 5), (0.99, 10 ** 6), (1e-9, 1)]:
-        target = math.ceil(p_thr * float(total))
+        target = min(math.ceil(p_thr * float(total)), total)
         kk = min(k, fin.size)
         best = None
         for v in np.unique(fin)[::-1]:
@@ -802,3 +803,15 @@ def test_PA7_av_new_cells_hold_exactly_the_top_samples(orc):
         if x not in first:
             first.append(x)
     assert [tuple(x) for x in g2.cells] == first
+
+
+def test_PA3_av_threshold_total_beyond_double_precision(orc):
+    """p_thr = 1 with a total fixed-point mass of 2^54 + 3 (2^14 samples of
+    mass 2^40 and three of mass 1): in FP64 the total rounds up to 2^54 + 4,
+    beyond every cumulative sum; the target is clamped to the total, so the
+    threshold reaches the three light samples."""
+    x = np.zeros((1 << 14) + 3)
+    x[-3:] = -27.6                 # exp(-27.6) 2^40 = 1.1 -> mass 1
+    assert int(np.sum(orc.av_mass(x))) == (1 << 54) + 3
+    thr, n_min = orc.av_threshold(x, 1.0, 1)
+    assert n_min == x.size and thr == -27.6
