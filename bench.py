@@ -150,9 +150,10 @@ def serving_pool(per_class, seed):
     return pool
 
 
-def serving_leg(ile, ctx, pool, n_jobs, adaptive, seed, policy, budget=0, rate=None):
+def serving_leg(ile, ctx, pool, n_jobs, adaptive, seed, policy, budget=0, rate=None, integrator=0):
     """Submit a job stream with Poisson arrivals; returns throughput and latency.
-    rate=None: all jobs at once (saturated)."""
+    rate=None: all jobs at once (saturated).  integrator: the adaptive jobs'
+    proposal (0: mixture refits, 1: adaptive volume)."""
     rng = np.random.default_rng(seed)
     hosts = {}
     srv = ile.ile_server_create(ctx, max_active=64, hbm_budget_bytes=budget, chunk_samples=1 << 20)
@@ -170,7 +171,7 @@ def serving_leg(ile, ctx, pool, n_jobs, adaptive, seed, policy, budget=0, rate=N
         if pi not in hosts:
             hosts[pi] = ile.ProblemHost(pool[pi], precision=policy, dist_marg=adaptive)
         jo = ile.job_opts(n_samples=int(sizes[k]), adaptive=adaptive, round_samples=1 << 16, max_rounds=32,
-                          n_eff_target=1000.0, seed=int(seed * 100003 + k))
+                          n_eff_target=1000.0, seed=int(seed * 100003 + k), integrator=integrator)
         ids.append(ile.ile_server_submit(srv, hosts[pi], jo))
     res = [ile.ile_server_wait(srv, i, -1) for i in ids]
     t1 = time.perf_counter()
@@ -186,8 +187,12 @@ def serving_leg(ile, ctx, pool, n_jobs, adaptive, seed, policy, budget=0, rate=N
            "failed": int(sum(r.status != 0 for r in res))}
     if adaptive:
         rounds = np.array([r.rounds for r in res])
-        out.update({"rounds_mean": float(rounds.mean()),
-                    "frac_reached_neff": float(np.mean([r.marg.n_eff >= 1000.0 for r in res]))})
+        neff = np.array([r.marg.n_eff for r in res])
+        out.update({"integrator": "adaptive volume" if integrator == 1 else "mixture",
+                    "rounds_mean": float(rounds.mean()),
+                    "frac_reached_neff": float(np.mean(neff >= 1000.0)),
+                    "n_eff_median": float(np.median(neff)),
+                    "n_eff_per_sample_median": float(np.median(neff / np.maximum(1, [r.samples for r in res])))})
     return out
 
 
@@ -237,6 +242,8 @@ def main():
                     help="the probe's step uses the time-marginalised likelihood (R = 4, 2^tmarg-log2n per point)")
     ap.add_argument("--adaptive-only", action="store_true",
                     help="run only the adaptive serving leg (--adaptive-jobs jobs) and print its summary")
+    ap.add_argument("--adaptive-integrator", choices=["gmm", "av", "both"], default="both",
+                    help="proposal of the adaptive serving leg(s)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the path shards by "
@@ -264,10 +271,14 @@ def main():
         print(json.dumps({"probe": True, "policy": a.probe_policy, "samples": r["N"], "kernel_ms": r["kernel_ms"],
                           "lnl_src_sha256": lnl_src_sha256()}), flush=True)
         return
+    integrators = {"gmm": [0], "av": [1], "both": [0, 1]}[a.adaptive_integrator]
     if a.adaptive_only:
         pool = serving_pool(8, 250511655 + 4)
-        ada = serving_leg(ile, ctx, pool, a.adaptive_jobs, True, 13, ile.ILE_FP32)
-        print(json.dumps({"adaptive_saturated": ada}), flush=True)
+        out = {}
+        for it in integrators:
+            out["adaptive_av_saturated" if it else "adaptive_saturated"] = serving_leg(
+                ile, ctx, pool, a.adaptive_jobs, True, 13, ile.ILE_FP32, integrator=it)
+        print(json.dumps(out), flush=True)
         return
     log("fp32 ...")
     r32 = run_policy(ile, torch, ctx, probs, ile.ILE_FP32, n_per, a.steps, a.warmup, stream)
@@ -305,9 +316,10 @@ def main():
         serving = {"plain_poisson_0.7": pois, "plain_saturated": sat, "arrival_rate_per_s": rate,
                    "pool": f"{len(pool)} events (8 per (modes, detectors) class, SNR log-uniform 10-100), reused"}
         if a.adaptive_jobs > 0:
-            ada = serving_leg(ile, ctx, pool, a.adaptive_jobs, True, 13, ile.ILE_FP32)
-            log(f"adaptive {ada}")
-            serving["adaptive_saturated"] = ada
+            for it in integrators:
+                ada = serving_leg(ile, ctx, pool, a.adaptive_jobs, True, 13, ile.ILE_FP32, integrator=it)
+                log(f"adaptive {'av' if it else 'gmm'} {ada}")
+                serving["adaptive_av_saturated" if it else "adaptive_saturated"] = ada
     N = r32["N"]
     flop = FLOP_PER_SAMPLE[(3, 9)]
     t_eval = r32["kernel_ms"]["eval"] * 1e-3

@@ -100,6 +100,22 @@ ile_status av_readback(ile_job *job, hipStream_t st) {
 
 }  // namespace
 
+// One launch per stage for all jobs (theta type for draws, log-weight type
+// for updates: `policy` names it); descriptors go through a scratch slot.
+ile_status av_batch(ile_ctx *ctx, bool update, int policy, const std::vector<AvJob> &jobs, hipStream_t st) {
+    if (jobs.empty()) return ILE_OK;
+    if (jobs.size() > 65535) return set_err(ILE_E_INVALID, "too many jobs in one adaptive-volume launch");
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    void *dj = nullptr, *dn = nullptr;
+    int slot = -1;
+    ile_status s = batch_upload(ctx, jobs.data(), jobs.size() * sizeof(AvJob), nullptr, 0, &dj, &dn, &slot, st);
+    if (s != ILE_OK) return s;
+    const hipError_t e = update ? launch_av_update(policy, (const AvJob *)dj, jobs.data(), (int)jobs.size(), st)
+                                : launch_av_draw(policy, (const AvJob *)dj, jobs.data(), (int)jobs.size(), st);
+    if (e != hipSuccess) return dev_fail(ctx, e, update ? "adaptive-volume update" : "adaptive-volume draw");
+    return batch_done(ctx, slot, st);
+}
+
 size_t av_bytes_for(int64_t cap) { return av_layout(std::max<int64_t>(cap, 4096)).total; }
 
 ile_status av_ensure(ile_job *job, int64_t cap, hipStream_t st) {
@@ -179,10 +195,17 @@ extern "C" ile_status ile_av_draw(ile_job *job, uint64_t seed, uint32_t round, i
     if (!theta_out) return set_err(ILE_E_INVALID, "null theta_out");
     hipStream_t st = (hipStream_t)stream;
     if ((s = av_ensure(job, 1, st)) != ILE_OK) return s;
-    hipError_t e = launch_av_draw(job->policy, job->av, job->pr, seed, round, first_index, n, theta_out, ld,
-                                  lnpmps_out, st);
-    if (e != hipSuccess) return dev_fail(job->ctx, e, "adaptive-volume draw");
-    return ILE_OK;
+    AvJob j{};
+    j.b = job->av;
+    j.pr = job->pr;
+    j.seed = seed;
+    j.round = round;
+    j.first = first_index;
+    j.n = n;
+    j.theta = theta_out;
+    j.ld = ld;
+    j.lnpmps = lnpmps_out;
+    return av_batch(job->ctx, false, job->policy, {j}, st);
 }
 
 extern "C" ile_status ile_av_update(ile_job *job, uint64_t seed, uint32_t round, int64_t first_index, int64_t n,
@@ -203,9 +226,17 @@ extern "C" ile_status ile_av_update(ile_job *job, uint64_t seed, uint32_t round,
     if ((s = av_ensure(job, std::max<int64_t>(n, 1), st)) != ILE_OK) return s;
     if (n > 0) {
         if (!lw) return set_err(ILE_E_INVALID, "null lw");
-        hipError_t e =
-            launch_av_update(job->policy, job->av, seed, round, first_index, n, lw, p_thr, n_min_live, max_bins, st);
-        if (e != hipSuccess) return dev_fail(job->ctx, e, "adaptive-volume update");
+        AvJob j{};
+        j.b = job->av;
+        j.seed = seed;
+        j.round = round;
+        j.first = first_index;
+        j.n = n;
+        j.lw = lw;
+        j.p_thr = p_thr;
+        j.n_min_live = n_min_live;
+        j.max_bins = max_bins;
+        if ((s = av_batch(job->ctx, true, job->policy, {j}, st)) != ILE_OK) return s;
     }
     if (out) {
         if ((s = av_readback(job, st)) != ILE_OK) return s;

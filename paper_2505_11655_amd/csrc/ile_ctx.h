@@ -186,6 +186,9 @@ void marg_from_state(const MargState &m, ile_marg *out);
 // job's AV buffers take for that cap.
 ile_status av_ensure(ile_job *job, int64_t cap, hipStream_t st);
 size_t av_bytes_for(int64_t cap);
+// Batched AV draws (update = false; policy: the jobs' policy, theta type) or
+// updates (update = true; log-weight type) of several jobs.
+ile_status av_batch(ile_ctx *ctx, bool update, int policy, const std::vector<AvJob> &jobs, hipStream_t st);
 void eval_geometry(const ile_job *job, int64_t n, size_t *lds, int64_t *tile, int *block);
 size_t theta_size(int policy);
 size_t out_size(int policy);

@@ -393,13 +393,28 @@ struct AvBufs {
     uint32_t *bcnt;               // [cap / 256 + 1] per-block counts, then offsets
     unsigned long long *hist;     // [2 chains][256 digits][count, mass]
 };
+// One job of a batched AV draw or update (blockIdx.z selects the job).
+struct AvJob {
+    AvBufs b;
+    PriorDev pr;          // draws
+    uint64_t seed;
+    uint32_t round;
+    int64_t first;
+    int64_t n;
+    void *theta;          // draws: [7][ld] theta type, and [n] ln p - ln p_s (or null)
+    int64_t ld;
+    void *lnpmps;
+    const void *lw;       // updates: [n] log-weights in the policy's output type
+    double p_thr;
+    int64_t n_min_live;
+    int max_bins;
+};
 // Initial grid: one cell, nb = 1, over the given columns.
 hipError_t launch_av_reset(const AvBufs &b, int d, const int *dims, hipStream_t st);
-hipError_t launch_av_draw(int policy, const AvBufs &b, const PriorDev &pr, uint64_t seed, uint32_t round,
-                          int64_t first, int64_t n, void *theta, int64_t ld, void *lnpmps, hipStream_t st);
-// lw: [n] the round's log-weights in the policy's output type.
-hipError_t launch_av_update(int policy, const AvBufs &b, uint64_t seed, uint32_t round, int64_t first, int64_t n,
-                            const void *lw, double p_thr, int64_t n_min_live, int max_bins, hipStream_t st);
+// d_jobs: device copy of h_jobs (all of one theta type for draws, of one
+// log-weight type for updates: `policy` names it).
+hipError_t launch_av_draw(int policy, const AvJob *d_jobs, const AvJob *h_jobs, int n_jobs, hipStream_t st);
+hipError_t launch_av_update(int policy, const AvJob *d_jobs, const AvJob *h_jobs, int n_jobs, hipStream_t st);
 // Weighted EM refit of every job: max and tempering exponent, first fit for
 // jobs with `first`, then n_iter iterations.  h_jobs: host copy of d_jobs.
 hipError_t launch_em_batch(int policy, const EmJob *d_jobs, const EmJob *h_jobs, int n_jobs, int n_iter,

@@ -165,6 +165,7 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
     const int64_t t_start = now_ns();
     // draws, grouped by theta type
     std::vector<DrawJob> d32, d64;
+    std::vector<AvJob> av32, av64;   // adaptive-volume draws by theta type
     std::vector<BatchItem> items, tm1, tm4;   // pointwise; time-marginalised with R = 1, 4
     std::vector<int64_t> nthis(act.size());
     for (size_t i = 0; i < act.size(); i++) {
@@ -175,12 +176,16 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
         const BatchItem bi{r->job, n, r->d_theta, n, r->d_lr, nullptr, r->d_lw};
         (r->jo.tmarg_oversample == 4 ? tm4 : r->jo.tmarg_oversample == 1 ? tm1 : items).push_back(bi);
         if (r->jo.adaptive && r->jo.integrator == ILE_INT_AV) {
-            const hipError_t e = launch_av_draw(r->job->policy, r->job->av, r->job->pr, r->jo.seed,
-                                                (uint32_t)r->rounds, 0, n, r->d_theta, n, r->d_lr, st);
-            if (e != hipSuccess) {
-                dev_fail(s->ctx, e, "adaptive-volume draw");
-                return false;
-            }
+            AvJob aj{};
+            aj.b = r->job->av;
+            aj.pr = r->job->pr;
+            aj.seed = r->jo.seed;
+            aj.round = (uint32_t)r->rounds;
+            aj.n = n;
+            aj.theta = r->d_theta;
+            aj.ld = n;
+            aj.lnpmps = r->d_lr;
+            (r->prob.precision == kFP64 ? av64 : av32).push_back(aj);
             continue;
         }
         DrawJob dj{};
@@ -197,6 +202,8 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
     }
     if (!d32.empty() && draw_batch(s->ctx, kFP32, d32, st) != ILE_OK) return false;
     if (!d64.empty() && draw_batch(s->ctx, kFP64, d64, st) != ILE_OK) return false;
+    if (av_batch(s->ctx, false, kFP32, av32, st) != ILE_OK) return false;
+    if (av_batch(s->ctx, false, kFP64, av64, st) != ILE_OK) return false;
     if (!items.empty() && eval_batch(s->ctx, items, st) != ILE_OK) return false;
     if (!tm1.empty() && tmarg_batch(s->ctx, tm1, 1, st) != ILE_OK) return false;
     if (!tm4.empty() && tmarg_batch(s->ctx, tm4, 4, st) != ILE_OK) return false;
@@ -254,14 +261,23 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
     s->cv_done.notify_all();
     // adaptive-volume jobs: refine the grid from the round just evaluated
     // (drawn with round index rounds - 1)
-    for (Req *r : refit) {
-        if (r->jo.integrator != ILE_INT_AV) continue;
-        const hipError_t e = launch_av_update(r->job->policy, r->job->av, r->jo.seed, (uint32_t)(r->rounds - 1), 0,
-                                              r->chunk, r->d_lw, 0.999, 1000, kAvMaxBins, st);
-        if (e != hipSuccess) {
-            dev_fail(s->ctx, e, "adaptive-volume update");
-            return false;
+    {
+        std::vector<AvJob> u32, u64;   // by log-weight type
+        for (Req *r : refit) {
+            if (r->jo.integrator != ILE_INT_AV) continue;
+            AvJob aj{};
+            aj.b = r->job->av;
+            aj.seed = r->jo.seed;
+            aj.round = (uint32_t)(r->rounds - 1);
+            aj.n = r->chunk;
+            aj.lw = r->d_lw;
+            aj.p_thr = 0.999;
+            aj.n_min_live = 1000;
+            aj.max_bins = kAvMaxBins;
+            (r->prob.precision == kFP32 ? u32 : u64).push_back(aj);
         }
+        if (av_batch(s->ctx, true, kFP32, u32, st) != ILE_OK) return false;
+        if (av_batch(s->ctx, true, kFP64, u64, st) != ILE_OK) return false;
     }
     // one batched refit per precision policy; each job's mass draws use its
     // own key and round

@@ -121,27 +121,34 @@ __global__ void k_av_reset(AvBufs b, int d, int d0, int d1, int d2, int d3, int 
     for (int k = 0; k < 8; k++) b.cells[0][k] = 0;
 }
 
+// Samples of job blockIdx.z: each block strides over its job's samples.
+#define AV_JOB const AvJob &J = jobs[blockIdx.z]
+#define AV_SAMPLES(s) \
+    for (int64_t s = (int64_t)blockIdx.x * kAvThreads + threadIdx.x; s < J.n; s += (int64_t)gridDim.x * kAvThreads)
+
 template <class TT>
-__global__ void __launch_bounds__(kAvThreads)
-    k_av_draw(AvBufs b, PriorDev pr, uint64_t seed, uint32_t round, int64_t first, int64_t n,
-              TT *__restrict__ th_out, int64_t ld, TT *__restrict__ lr_out) {
-    const AvDev &S = *b.st;
-    const uint16_t *cells = cur_cells(b, S);
+__global__ void __launch_bounds__(kAvThreads) k_av_draw(const AvJob *__restrict__ jobs) {
+    AV_JOB;
+    const AvDev &S = *J.b.st;
+    const uint16_t *cells = cur_cells(J.b, S);
     const double lnv = S.ln_vol;
-    for (int64_t s = (int64_t)blockIdx.x * kAvThreads + threadIdx.x; s < n; s += (int64_t)gridDim.x * kAvThreads) {
+    TT *th_out = (TT *)J.theta;
+    TT *lr_out = (TT *)J.lnpmps;
+    AV_SAMPLES(s) {
         uint32_t w[16];
-        av_words(seed, (uint64_t)(first + s), round, w);
+        av_words(J.seed, (uint64_t)(J.first + s), J.round, w);
         double u[7], th[7];
         av_unit(S, cells, w, u);
-        prior_map(pr, u, th);
+        prior_map(J.pr, u, th);
 #pragma unroll
-        for (int c = 0; c < 7; c++) th_out[c * ld + s] = (TT)th[c];
+        for (int c = 0; c < 7; c++) th_out[c * J.ld + s] = (TT)th[c];
         if (lr_out) lr_out[s] = (TT)lnv;
     }
 }
 
-__global__ void k_av_begin(AvBufs b) {
-    AvDev &S = *b.st;
+__global__ void k_av_begin(const AvJob *__restrict__ jobs) {
+    AV_JOB;
+    AvDev &S = *J.b.st;
     if (threadIdx.x == 0) {
         S.key_max = 0;
         S.n_fin = 0;
@@ -156,15 +163,18 @@ __global__ void k_av_begin(AvBufs b) {
         S.valid = 0;
         S.thr = -INFINITY;
         S.n_min = 0;
+        S.n_live = J.n;
         S.vol_mc = 0.0;
     }
-    for (int i = threadIdx.x; i < 2 * 256 * 2; i += blockDim.x) b.hist[i] = 0;
+    for (int i = threadIdx.x; i < 2 * 256 * 2; i += blockDim.x) J.b.hist[i] = 0;
 }
 
 template <class TO>
-__global__ void __launch_bounds__(kAvThreads) k_av_max(AvBufs b, const TO *__restrict__ lw, int64_t n) {
+__global__ void __launch_bounds__(kAvThreads) k_av_max(const AvJob *__restrict__ jobs) {
+    AV_JOB;
+    const TO *lw = (const TO *)J.lw;
     unsigned long long km = 0, cnt = 0;
-    for (int64_t s = (int64_t)blockIdx.x * kAvThreads + threadIdx.x; s < n; s += (int64_t)gridDim.x * kAvThreads) {
+    AV_SAMPLES(s) {
         const TO v = lw[s];
         if (isfinite(v)) {
             const unsigned long long k = okey(v);
@@ -191,8 +201,8 @@ __global__ void __launch_bounds__(kAvThreads) k_av_max(AvBufs b, const TO *__res
             cnt += smc[i];
         }
         if (cnt) {
-            atomicMax(&b.st->key_max, km);
-            atomicAdd(&b.st->n_fin, cnt);
+            atomicMax(&J.b.st->key_max, km);
+            atomicAdd(&J.b.st->n_fin, cnt);
         }
     }
 }
@@ -201,9 +211,10 @@ __global__ void __launch_bounds__(kAvThreads) k_av_max(AvBufs b, const TO *__res
 // whose higher digits match the chain's prefix; chain 0 counts and sums the
 // fixed-point masses, chain 1 counts.
 template <class TO>
-__global__ void __launch_bounds__(kAvThreads) k_av_hist(AvBufs b, const TO *__restrict__ lw, int64_t n, int shift) {
-    const AvDev &S = *b.st;
-    if (S.n_fin == 0) return;
+__global__ void __launch_bounds__(kAvThreads) k_av_hist(const AvJob *__restrict__ jobs, int shift) {
+    AV_JOB;
+    const AvDev &S = *J.b.st;
+    if (S.n_fin == 0 || (int64_t)blockIdx.x * kAvThreads >= J.n) return;
     __shared__ unsigned long long h[2 * 256 * 2];
     for (int i = threadIdx.x; i < 2 * 256 * 2; i += kAvThreads) h[i] = 0;
     __syncthreads();
@@ -212,7 +223,8 @@ __global__ void __launch_bounds__(kAvThreads) k_av_hist(AvBufs b, const TO *__re
     const unsigned long long p0 = top ? 0 : (S.prefix[0] >> (shift + 8));
     const unsigned long long p1 = top ? 0 : (S.prefix[1] >> (shift + 8));
     const double vmax = key_value(S.key_max, nbits);
-    for (int64_t s = (int64_t)blockIdx.x * kAvThreads + threadIdx.x; s < n; s += (int64_t)gridDim.x * kAvThreads) {
+    const TO *lw = (const TO *)J.lw;
+    AV_SAMPLES(s) {
         const TO v = lw[s];
         if (!isfinite(v)) continue;
         const unsigned long long k = okey(v);
@@ -226,89 +238,138 @@ __global__ void __launch_bounds__(kAvThreads) k_av_hist(AvBufs b, const TO *__re
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 2 * 256 * 2; i += kAvThreads)
-        if (h[i]) atomicAdd(&b.hist[i], h[i]);
+        if (h[i]) atomicAdd(&J.b.hist[i], h[i]);
 }
 
-// Choose each chain's digit, clear the histogram; after the last pass, the
-// threshold, n_min and the refined bin count of eq. (nbins_V).
-__global__ void k_av_pick(AvBufs b, int shift, int nbits, double p_thr, long long n_min_live, int max_bins,
-                          long long n) {
-    AvDev &S = *b.st;
-    if (threadIdx.x == 0 && S.n_fin > 0) {
-        const unsigned long long *H = b.hist;
-        if (shift + 8 == nbits) {
-            unsigned long long tot = 0;
-            for (int d = 0; d < 256; d++) tot += H[(0 * 256 + d) * 2 + 1];
+// Each chain's digit: thread d holds bucket d; suffix sums from the top
+// bucket down give the enclosed count and mass at and above each bucket, and
+// the chosen digit is the highest bucket where the chain's target is reached.
+// After the last pass: the threshold, n_min and eq. (nbins_V).  The selection
+// state is read once, carried in LDS between threads, and written back.
+__global__ void __launch_bounds__(256) k_av_pick(const AvJob *__restrict__ jobs, int shift, int nbits) {
+    AV_JOB;
+    AvDev &S = *J.b.st;
+    if (S.n_fin == 0) return;
+    unsigned long long *H = J.b.hist;
+    const int d = threadIdx.x;
+    __shared__ unsigned long long sc[256], sm[256];
+    __shared__ unsigned long long t_target[2], t_acnt[2], t_amass[2], t_prefix[2], t_last[2];
+    __shared__ int pick;
+    if (d < 2) {
+        t_target[d] = S.target[d];
+        t_acnt[d] = S.above_cnt[d];
+        t_amass[d] = S.above_mass[d];
+        t_prefix[d] = S.prefix[d];
+        t_last[d] = S.last_cnt[d];
+    }
+    if (shift + 8 == nbits) {
+        sm[d] = H[(0 * 256 + d) * 2 + 1];
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (d < o) sm[d] += sm[d + o];
+            __syncthreads();
+        }
+        if (d == 0) {
+            const unsigned long long tot = sm[0], nfin = S.n_fin;
+            const unsigned long long tm = (unsigned long long)ceil(J.p_thr * (double)tot);
+            t_target[0] = tm < tot ? tm : tot;
+            t_target[1] = (unsigned long long)J.n_min_live < nfin ? (unsigned long long)J.n_min_live : nfin;
             S.total = tot;
-            const unsigned long long tm = (unsigned long long)ceil(p_thr * (double)tot);
-            S.target[0] = tm < tot ? tm : tot;
-            S.target[1] = (unsigned long long)n_min_live < S.n_fin ? (unsigned long long)n_min_live : S.n_fin;
+            S.target[0] = t_target[0];
+            S.target[1] = t_target[1];
             S.valid = 1;
         }
-        for (int c = 0; c < 2; c++) {
-            unsigned long long acc_c = 0, acc_m = 0;
-            int pick = 0;
-            for (int d = 255; d >= 0; d--) {
-                const unsigned long long cc = H[(c * 256 + d) * 2 + 0], mm = H[(c * 256 + d) * 2 + 1];
-                const bool hit = c == 0 ? (S.above_mass[0] + acc_m + mm >= S.target[0])
-                                        : (S.above_cnt[1] + acc_c + cc >= S.target[1]);
-                if (hit) {
-                    pick = d;
-                    S.last_cnt[c] = cc;
-                    break;
-                }
-                acc_c += cc;
-                acc_m += mm;
-            }
-            S.above_cnt[c] += acc_c;
-            S.above_mass[c] += acc_m;
-            S.prefix[c] |= (unsigned long long)pick << shift;
-        }
-        if (shift == 0) {
-            const int c = S.prefix[0] <= S.prefix[1] ? 0 : 1;
-            S.thr_key = S.prefix[c];
-            S.n_min = (int64_t)(S.above_cnt[c] + S.last_cnt[c]);
-            S.thr = key_value(S.thr_key, nbits);
-            S.vol_mc = exp(S.ln_vol) * (double)S.n_min / (double)n;
-            const double ln_dv = S.ln_vol + 0.5 * log((double)S.n_min) - log((double)n);
-            const double x = exp(-ln_dv / (double)S.d);
-            double nbd = ceil(x - 1e-9);
-            nbd = nbd < 1.0 ? 1.0 : (nbd > (double)max_bins ? (double)max_bins : nbd);
-            S.nb_next = (int)nbd;
-        }
     }
-    if (threadIdx.x == 0) S.n_live = n;
     __syncthreads();
-    for (int i = threadIdx.x; i < 2 * 256 * 2; i += blockDim.x) b.hist[i] = 0;
+    for (int c = 0; c < 2; c++) {
+        // suffix sums: position r = 255 - d holds bucket d, inclusive prefix over r
+        const unsigned long long cc = H[(c * 256 + d) * 2 + 0], mm = H[(c * 256 + d) * 2 + 1];
+        sc[255 - d] = cc;
+        sm[255 - d] = mm;
+        if (d == 0) pick = -1;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const unsigned long long ac = d >= o ? sc[d - o] : 0ull, am = d >= o ? sm[d - o] : 0ull;
+            __syncthreads();
+            sc[d] += ac;
+            sm[d] += am;
+            __syncthreads();
+        }
+        const unsigned long long suf_c = sc[255 - d], suf_m = sm[255 - d];
+        const bool hit = c == 0 ? (t_amass[0] + suf_m >= t_target[0]) : (t_acnt[1] + suf_c >= t_target[1]);
+        if (hit) atomicMax(&pick, d);
+        __syncthreads();
+        if (d == pick) {
+            t_last[c] = cc;
+            t_acnt[c] += suf_c - cc;
+            t_amass[c] += suf_m - mm;
+            t_prefix[c] |= (unsigned long long)d << shift;
+        }
+        __syncthreads();
+    }
+    if (d < 2) {
+        S.above_cnt[d] = t_acnt[d];
+        S.above_mass[d] = t_amass[d];
+        S.prefix[d] = t_prefix[d];
+        S.last_cnt[d] = t_last[d];
+    }
+    if (d == 0 && shift == 0) {
+        const int c = t_prefix[0] <= t_prefix[1] ? 0 : 1;
+        const int64_t n_min = (int64_t)(t_acnt[c] + t_last[c]);
+        const double ln_vol = S.ln_vol;
+        S.thr_key = t_prefix[c];
+        S.n_min = n_min;
+        S.thr = key_value(t_prefix[c], nbits);
+        S.vol_mc = exp(ln_vol) * (double)n_min / (double)J.n;
+        const double ln_dv = ln_vol + 0.5 * log((double)n_min) - log((double)J.n);
+        const double x = exp(-ln_dv / (double)S.d);
+        double nbd = ceil(x - 1e-9);
+        nbd = nbd < 1.0 ? 1.0 : (nbd > (double)J.max_bins ? (double)J.max_bins : nbd);
+        S.nb_next = (int)nbd;
+    }
+    for (int i = d; i < 2 * 256 * 2; i += 256) H[i] = 0;
 }
 
-__global__ void __launch_bounds__(kAvThreads) k_av_hclear(AvBufs b) {
-    const AvDev &S = *b.st;
+__global__ void __launch_bounds__(kAvThreads) k_av_hclear(const AvJob *__restrict__ jobs) {
+    AV_JOB;
+    const AvDev &S = *J.b.st;
     if (!S.valid) return;
-    for (uint64_t i = (uint64_t)blockIdx.x * kAvThreads + threadIdx.x; i <= b.hmask;
-         i += (uint64_t)gridDim.x * kAvThreads) {
-        b.hkey[i] = kEmpty;
-        b.hidx[i] = kNoSlot;
+    // only the part of the set an update of J.n samples can use (>= 2 J.n slots)
+    uint64_t used = 1024;
+    while (used < (uint64_t)2 * (uint64_t)J.n) used <<= 1;
+    used = used - 1 < J.b.hmask ? used : J.b.hmask + 1;
+    for (uint64_t i = (uint64_t)blockIdx.x * kAvThreads + threadIdx.x; i < used; i += (uint64_t)gridDim.x * kAvThreads) {
+        J.b.hkey[i] = kEmpty;
+        J.b.hidx[i] = kNoSlot;
     }
+}
+
+// The set of one update uses its first `used` slots (a power of two >= 2n).
+__device__ __forceinline__ uint64_t av_set_mask(const AvJob &J) {
+    uint64_t used = 1024;
+    while (used < (uint64_t)2 * (uint64_t)J.n) used <<= 1;
+    return (used - 1 < J.b.hmask ? used : J.b.hmask + 1) - 1;
 }
 
 // Cells (of the refined grid) of the samples at or above the threshold, into
 // the set; each slot keeps the lowest sample index that reached it.
 template <class TO>
-__global__ void __launch_bounds__(kAvThreads)
-    k_av_insert(AvBufs b, uint64_t seed, uint32_t round, int64_t first, const TO *__restrict__ lw, int64_t n) {
-    const AvDev &S = *b.st;
+__global__ void __launch_bounds__(kAvThreads) k_av_insert(const AvJob *__restrict__ jobs) {
+    AV_JOB;
+    const AvDev &S = *J.b.st;
     if (!S.valid) return;
     const unsigned long long thr = S.thr_key;
     const unsigned long long nb2 = (unsigned long long)S.nb_next;
     const double nb2d = (double)S.nb_next;
-    const uint16_t *cells = cur_cells(b, S);
-    for (int64_t s = (int64_t)blockIdx.x * kAvThreads + threadIdx.x; s < n; s += (int64_t)gridDim.x * kAvThreads) {
+    const uint16_t *cells = cur_cells(J.b, S);
+    const uint64_t mask = av_set_mask(J);
+    const TO *lw = (const TO *)J.lw;
+    AV_SAMPLES(s) {
         const TO v = lw[s];
         uint32_t sl = kNoSlot;
         if (isfinite(v) && okey(v) >= thr) {
             uint32_t w[16];
-            av_words(seed, (uint64_t)(first + s), round, w);
+            av_words(J.seed, (uint64_t)(J.first + s), J.round, w);
             double u[7];
             av_unit(S, cells, w, u);
             unsigned long long id = 0;
@@ -320,47 +381,50 @@ __global__ void __launch_bounds__(kAvThreads)
                     id = id * nb2 + (unsigned long long)f;
                 }
             }
-            uint64_t h = mix64(id) & b.hmask;
-            for (uint64_t probe = 0; probe <= b.hmask; probe++) {
-                const unsigned long long prev = atomicCAS(&b.hkey[h], kEmpty, id);
+            uint64_t h = mix64(id) & mask;
+            for (uint64_t probe = 0; probe <= mask; probe++) {
+                const unsigned long long prev = atomicCAS(&J.b.hkey[h], kEmpty, id);
                 if (prev == kEmpty || prev == id) {
-                    atomicMin(&b.hidx[h], (uint32_t)s);
+                    atomicMin(&J.b.hidx[h], (uint32_t)s);
                     sl = (uint32_t)h;
                     break;
                 }
-                h = (h + 1) & b.hmask;
+                h = (h + 1) & mask;
             }
         }
-        b.slot[s] = sl;
+        J.b.slot[s] = sl;
     }
 }
 
 // The sample is the first (lowest index) of its cell.
-__device__ __forceinline__ bool av_first(const AvBufs &b, int64_t s, int64_t n) {
-    if (s >= n) return false;
-    const uint32_t sl = b.slot[s];
-    return sl != kNoSlot && b.hidx[sl] == (uint32_t)s;
+__device__ __forceinline__ bool av_first(const AvJob &J, int64_t s) {
+    if (s >= J.n) return false;
+    const uint32_t sl = J.b.slot[s];
+    return sl != kNoSlot && J.b.hidx[sl] == (uint32_t)s;
 }
 
-__global__ void __launch_bounds__(kAvThreads) k_av_count(AvBufs b, int64_t n) {
-    const AvDev &S = *b.st;
-    if (!S.valid) return;
+__global__ void __launch_bounds__(kAvThreads) k_av_count(const AvJob *__restrict__ jobs) {
+    AV_JOB;
+    const AvDev &S = *J.b.st;
+    if (!S.valid || (int64_t)blockIdx.x * kAvThreads >= J.n) return;
     const int64_t s = (int64_t)blockIdx.x * kAvThreads + threadIdx.x;
-    const int c = __syncthreads_count(av_first(b, s, n));
-    if (threadIdx.x == 0) b.bcnt[blockIdx.x] = (uint32_t)c;
+    const int c = __syncthreads_count(av_first(J, s));
+    if (threadIdx.x == 0) J.b.bcnt[blockIdx.x] = (uint32_t)c;
 }
 
 // Exclusive scan of the per-block counts in place; the total is the new
 // number of cells.
 constexpr int kScanThreads = 1024;
-__global__ void __launch_bounds__(kScanThreads) k_av_scan(AvBufs b, int nblk) {
-    AvDev &S = *b.st;
+__global__ void __launch_bounds__(kScanThreads) k_av_scan(const AvJob *__restrict__ jobs) {
+    AV_JOB;
+    AvDev &S = *J.b.st;
     if (!S.valid) return;
+    const int nblk = (int)((J.n + kAvThreads - 1) / kAvThreads);
     __shared__ unsigned long long sm[kScanThreads];
     const int per = (nblk + kScanThreads - 1) / kScanThreads;
     const int lo = threadIdx.x * per, hi = lo + per < nblk ? lo + per : nblk;
     unsigned long long loc = 0;
-    for (int i = lo; i < hi; i++) loc += b.bcnt[i];
+    for (int i = lo; i < hi; i++) loc += J.b.bcnt[i];
     sm[threadIdx.x] = loc;
     __syncthreads();
     for (int o = 1; o < kScanThreads; o <<= 1) {
@@ -371,18 +435,19 @@ __global__ void __launch_bounds__(kScanThreads) k_av_scan(AvBufs b, int nblk) {
     }
     unsigned long long run = sm[threadIdx.x] - loc;
     for (int i = lo; i < hi; i++) {
-        const uint32_t c = b.bcnt[i];
-        b.bcnt[i] = (uint32_t)run;
+        const uint32_t c = J.b.bcnt[i];
+        J.b.bcnt[i] = (uint32_t)run;
         run += c;
     }
     if (threadIdx.x == kScanThreads - 1) S.n_cells_next = (int64_t)sm[kScanThreads - 1];
 }
 
-__global__ void __launch_bounds__(kAvThreads) k_av_compact(AvBufs b, int64_t n) {
-    const AvDev &S = *b.st;
-    if (!S.valid) return;
+__global__ void __launch_bounds__(kAvThreads) k_av_compact(const AvJob *__restrict__ jobs) {
+    AV_JOB;
+    const AvDev &S = *J.b.st;
+    if (!S.valid || (int64_t)blockIdx.x * kAvThreads >= J.n) return;
     const int64_t s = (int64_t)blockIdx.x * kAvThreads + threadIdx.x;
-    const bool f = av_first(b, s, n);
+    const bool f = av_first(J, s);
     const unsigned long long m = __ballot(f);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __shared__ int wc[kAvThreads / 64];
@@ -392,9 +457,9 @@ __global__ void __launch_bounds__(kAvThreads) k_av_compact(AvBufs b, int64_t n) 
     int off = 0;
     for (int i = 0; i < wv; i++) off += wc[i];
     const int rank = __popcll(m & ((1ull << lane) - 1ull));
-    const int64_t pos = (int64_t)b.bcnt[blockIdx.x] + off + rank;
-    uint16_t *out = (S.cur ? b.cells[0] : b.cells[1]) + pos * 8;
-    unsigned long long id = b.hkey[b.slot[s]];
+    const int64_t pos = (int64_t)J.b.bcnt[blockIdx.x] + off + rank;
+    uint16_t *out = (S.cur ? J.b.cells[0] : J.b.cells[1]) + pos * 8;
+    unsigned long long id = J.b.hkey[J.b.slot[s]];
     const unsigned long long nb2 = (unsigned long long)S.nb_next;
     for (int k = 0; k < 8; k++) {
         if (k < S.d) {
@@ -406,9 +471,10 @@ __global__ void __launch_bounds__(kAvThreads) k_av_compact(AvBufs b, int64_t n) 
     }
 }
 
-__global__ void k_av_finish(AvBufs b) {
+__global__ void k_av_finish(const AvJob *__restrict__ jobs) {
+    AV_JOB;
     if (threadIdx.x != 0) return;
-    AvDev &S = *b.st;
+    AvDev &S = *J.b.st;
     if (!S.valid) return;
     S.cur ^= 1;
     S.nb = S.nb_next;
@@ -422,25 +488,31 @@ int grid_for(int64_t n, int per_thread) {
 }
 
 template <class TO>
-hipError_t av_update_t(const AvBufs &b, uint64_t seed, uint32_t round, int64_t first, int64_t n, const TO *lw,
-                       double p_thr, int64_t n_min_live, int max_bins, hipStream_t st) {
+hipError_t av_update_t(const AvJob *d, int n_jobs, int64_t nmax, hipStream_t st) {
     constexpr int nbits = sizeof(TO) * 8;
-    hipLaunchKernelGGL(k_av_begin, dim3(1), dim3(256), 0, st, b);
-    hipLaunchKernelGGL(k_av_max<TO>, dim3(grid_for(n, 16)), dim3(kAvThreads), 0, st, b, lw, n);
+    const unsigned nz = (unsigned)n_jobs;
+    hipLaunchKernelGGL(k_av_begin, dim3(1, 1, nz), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_av_max<TO>, dim3(grid_for(nmax, 16), 1, nz), dim3(kAvThreads), 0, st, d);
     for (int shift = nbits - 8; shift >= 0; shift -= 8) {
-        hipLaunchKernelGGL(k_av_hist<TO>, dim3(grid_for(n, 16)), dim3(kAvThreads), 0, st, b, lw, n, shift);
-        hipLaunchKernelGGL(k_av_pick, dim3(1), dim3(256), 0, st, b, shift, nbits, p_thr, (long long)n_min_live,
-                           max_bins, (long long)n);
+        hipLaunchKernelGGL(k_av_hist<TO>, dim3(grid_for(nmax, 16), 1, nz), dim3(kAvThreads), 0, st, d, shift);
+        hipLaunchKernelGGL(k_av_pick, dim3(1, 1, nz), dim3(256), 0, st, d, shift, nbits);
     }
-    hipLaunchKernelGGL(k_av_hclear, dim3(grid_for((int64_t)b.hmask + 1, 4)), dim3(kAvThreads), 0, st, b);
-    hipLaunchKernelGGL(k_av_insert<TO>, dim3(grid_for(n, 4)), dim3(kAvThreads), 0, st, b, seed, round, first, lw,
-                       n);
-    const int nblk = (int)((n + kAvThreads - 1) / kAvThreads);
-    hipLaunchKernelGGL(k_av_count, dim3(nblk), dim3(kAvThreads), 0, st, b, n);
-    hipLaunchKernelGGL(k_av_scan, dim3(1), dim3(kScanThreads), 0, st, b, nblk);
-    hipLaunchKernelGGL(k_av_compact, dim3(nblk), dim3(kAvThreads), 0, st, b, n);
-    hipLaunchKernelGGL(k_av_finish, dim3(1), dim3(64), 0, st, b);
+    uint64_t used = 1024;
+    while (used < (uint64_t)2 * (uint64_t)nmax) used <<= 1;
+    hipLaunchKernelGGL(k_av_hclear, dim3(grid_for((int64_t)used, 4), 1, nz), dim3(kAvThreads), 0, st, d);
+    hipLaunchKernelGGL(k_av_insert<TO>, dim3(grid_for(nmax, 4), 1, nz), dim3(kAvThreads), 0, st, d);
+    const int nblk = (int)((nmax + kAvThreads - 1) / kAvThreads);
+    hipLaunchKernelGGL(k_av_count, dim3(nblk, 1, nz), dim3(kAvThreads), 0, st, d);
+    hipLaunchKernelGGL(k_av_scan, dim3(1, 1, nz), dim3(kScanThreads), 0, st, d);
+    hipLaunchKernelGGL(k_av_compact, dim3(nblk, 1, nz), dim3(kAvThreads), 0, st, d);
+    hipLaunchKernelGGL(k_av_finish, dim3(1, 1, nz), dim3(64), 0, st, d);
     return hipGetLastError();
+}
+
+int64_t max_n(const AvJob *h, int n_jobs) {
+    int64_t m = 0;
+    for (int k = 0; k < n_jobs; k++) m = h[k].n > m ? h[k].n : m;
+    return m;
 }
 
 }  // namespace
@@ -452,24 +524,22 @@ hipError_t launch_av_reset(const AvBufs &b, int d, const int *dims, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_av_draw(int policy, const AvBufs &b, const PriorDev &pr, uint64_t seed, uint32_t round,
-                          int64_t first, int64_t n, void *theta, int64_t ld, void *lnpmps, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
+hipError_t launch_av_draw(int policy, const AvJob *d_jobs, const AvJob *h_jobs, int n_jobs, hipStream_t st) {
+    const int64_t nmax = max_n(h_jobs, n_jobs);
+    if (n_jobs <= 0 || nmax <= 0) return hipSuccess;
+    const dim3 grid(grid_for(nmax, 4), 1, (unsigned)n_jobs);
     if (policy == kFP64)
-        hipLaunchKernelGGL(k_av_draw<double>, dim3(grid_for(n, 4)), dim3(kAvThreads), 0, st, b, pr, seed, round,
-                           first, n, (double *)theta, ld, (double *)lnpmps);
+        hipLaunchKernelGGL(k_av_draw<double>, grid, dim3(kAvThreads), 0, st, d_jobs);
     else
-        hipLaunchKernelGGL(k_av_draw<float>, dim3(grid_for(n, 4)), dim3(kAvThreads), 0, st, b, pr, seed, round,
-                           first, n, (float *)theta, ld, (float *)lnpmps);
+        hipLaunchKernelGGL(k_av_draw<float>, grid, dim3(kAvThreads), 0, st, d_jobs);
     return hipGetLastError();
 }
 
-hipError_t launch_av_update(int policy, const AvBufs &b, uint64_t seed, uint32_t round, int64_t first, int64_t n,
-                            const void *lw, double p_thr, int64_t n_min_live, int max_bins, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    if (policy == kFP32)
-        return av_update_t<float>(b, seed, round, first, n, (const float *)lw, p_thr, n_min_live, max_bins, st);
-    return av_update_t<double>(b, seed, round, first, n, (const double *)lw, p_thr, n_min_live, max_bins, st);
+hipError_t launch_av_update(int policy, const AvJob *d_jobs, const AvJob *h_jobs, int n_jobs, hipStream_t st) {
+    const int64_t nmax = max_n(h_jobs, n_jobs);
+    if (n_jobs <= 0 || nmax <= 0) return hipSuccess;
+    if (policy == kFP32) return av_update_t<float>(d_jobs, n_jobs, nmax, st);
+    return av_update_t<double>(d_jobs, n_jobs, nmax, st);
 }
 
 }  // namespace ile
