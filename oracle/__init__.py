@@ -12,7 +12,8 @@ this module wraps it and adds definition-level numpy helpers:
   * ``em_fit``           - weighted EM for the mixture proposal (see its docstring);
   * ``ln_dist_marg``     - the distance-marginalised likelihood by adaptive quadrature;
   * ``draw_av``, ``av_threshold``, ``av_refine_bins``, ``av_cells``, ``av_update``
-                         - the adaptive-volume integrator (its readings are listed there).
+                         - the adaptive-volume integrator (its readings are listed there);
+  * ``fair_draw``        - fair draws from weighted samples.
 
 Pins: ``tests/test_oracle_pins.py``.  Parity unpinned: EM trajectories with
 more than one component, the in-support mass estimates (Monte Carlo).
@@ -434,6 +435,39 @@ def av_update(grid, u, lnL, p_thr=0.999, n_min_live=1000, max_bins=511):
     cells = av_cells(np.asarray(u)[:, top], nb)
     info = {"lnL_thr": thr, "n_min": n_min, "n_live": n, "vol_mc": math.exp(grid.ln_vol) * n_min / n}
     return AvGrid(nb, cells, grid.dims), info
+
+
+# --------------------------------------------------------------- fair draws
+# A fair draw from weighted samples (the final step of an ILE run and of the
+# posterior construction: sample locations with weights w, then a fair draw
+# from them).  Reading: k independent draws with replacement, index i with
+# probability q_i / sum q, q_i = floor(exp(lw_i - max lw) 2^40) the same
+# fixed-point masses as the AV threshold (0 for non-finite lw).  Draw j uses
+# the Philox words of counter (j lo, j hi, round, 16 * 5 + 0) under the key:
+# r = w0 2^32 + w1 (64 bits), target = floor(r * total / 2^64), and the index
+# is the first i whose inclusive cumulative mass exceeds the target.
+FAIR_ATTEMPT = 5
+
+
+def fair_draw(lw, seed, rnd, k):
+    """Indices [k] (int64); -1 for every draw when no sample has mass."""
+    lw = np.asarray(lw, dtype=np.float64)
+    fin = np.isfinite(lw)
+    q = np.zeros(lw.size, dtype=np.uint64)
+    if fin.any():
+        q[fin] = av_mass(lw[fin])
+    cum = np.cumsum(q, dtype=np.uint64)
+    total = int(cum[-1]) if cum.size else 0
+    out = np.full(k, -1, dtype=np.int64)
+    if total == 0:
+        return out
+    key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    for j in range(k):
+        w = philox((j & 0xFFFFFFFF, (j >> 32) & 0xFFFFFFFF, rnd, 16 * FAIR_ATTEMPT), key)
+        r = (w[0] << 32) | w[1]
+        target = (r * total) >> 64
+        out[j] = int(np.searchsorted(cum, np.uint64(target), side="right"))
+    return out
 
 
 # ----------------------------------------------------------------------- EM

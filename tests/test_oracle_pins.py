@@ -815,3 +815,45 @@ def test_PA3_av_threshold_total_beyond_double_precision(orc):
     assert int(np.sum(orc.av_mass(x))) == (1 << 54) + 3
     thr, n_min = orc.av_threshold(x, 1.0, 1)
     assert n_min == x.size and thr == -27.6
+
+
+# ------------------------------------------------------------- fair draws (f3)
+def test_PF1_fair_draw_frequencies_follow_the_weights(orc):
+    """Draw counts over 40,000 fair draws match the normalised weights
+    (chi-square over the indices with expected count >= 5); a sample with
+    zero or non-finite weight is never drawn."""
+    from scipy import stats
+    rng = np.random.default_rng(86)
+    lw = rng.normal(0, 2, 600)
+    lw[:7] = -np.inf
+    lw[7] = np.nan
+    idx = orc.fair_draw(lw, 1234, 2, 40000)
+    assert idx.min() >= 8
+    w = np.where(np.isfinite(lw), np.exp(lw - np.nanmax(lw[np.isfinite(lw)])), 0.0)
+    p = w / w.sum()
+    cnt = np.bincount(idx, minlength=lw.size)
+    m = p * idx.size >= 5
+    assert stats.chisquare(cnt[m], p[m] / p[m].sum() * cnt[m].sum()).pvalue > 1e-4
+
+
+def test_PF2_fair_draw_degenerate_cases(orc):
+    """One finite sample is drawn every time; no finite sample gives -1."""
+    lw = np.full(50, -np.inf)
+    assert np.all(orc.fair_draw(lw, 1, 0, 10) == -1)
+    lw[31] = -5.0
+    assert np.all(orc.fair_draw(lw, 1, 0, 10) == 31)
+
+
+def test_PF3_fair_draws_reproduce_the_target_distribution(orc):
+    """Importance samples of a truncated normal on [0, 1] (uniform proposal,
+    lw = ln of the density) fairly redrawn follow that truncated normal
+    (Kolmogorov-Smirnov against scipy's CDF): the check that extrinsic
+    samples resampled from an ILE run reproduce its posterior."""
+    from scipy import stats
+    rng = np.random.default_rng(87)
+    u = rng.uniform(0, 1, 200000)
+    mu, sig = 0.4, 0.05
+    lw = -0.5 * ((u - mu) / sig) ** 2
+    idx = orc.fair_draw(lw, 99, 0, 3000)
+    tn = stats.truncnorm((0 - mu) / sig, (1 - mu) / sig, loc=mu, scale=sig)
+    assert stats.kstest(u[idx], tn.cdf).pvalue > 1e-3
