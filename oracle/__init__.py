@@ -13,6 +13,7 @@ this module wraps it and adds definition-level numpy helpers:
   * ``ln_dist_marg``     - the distance-marginalised likelihood by adaptive quadrature;
   * ``draw_av``, ``av_threshold``, ``av_refine_bins``, ``av_cells``, ``av_update``
                          - the adaptive-volume integrator (its readings are listed there);
+  * ``draw_ac``, ``ac_update`` - the product-form adaptive Cartesian sampler;
   * ``fair_draw``        - fair draws from weighted samples.
 
 Pins: ``tests/test_oracle_pins.py``.  Parity unpinned: EM trajectories with
@@ -99,6 +100,9 @@ def lib():
         L.orc_draw_av.argtypes = [C.POINTER(_Prior), C.c_int, C.POINTER(C.c_int), C.c_int, C.c_int64,
                                   C.POINTER(C.c_int32), C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, dp,
                                   C.c_int64, dp]
+        L.orc_draw_ac.argtypes = [C.POINTER(_Prior), C.c_int, C.POINTER(C.c_int), C.c_int, dp, dp, dp,
+                                  C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, dp, C.c_int64, dp,
+                                  C.POINTER(C.c_int32)]
         L.orc_gmm_comp_logpdf.argtypes = [C.POINTER(_Prior), C.POINTER(_Gmm), C.c_int, dp]
         L.orc_gmm_comp_logpdf.restype = C.c_double
         L.orc_gmm_ln_ps.argtypes = [C.POINTER(_Prior), C.POINTER(_Gmm), dp]
@@ -435,6 +439,68 @@ def av_update(grid, u, lnL, p_thr=0.999, n_min_live=1000, max_bins=511):
     cells = av_cells(np.asarray(u)[:, top], nb)
     info = {"lnL_thr": thr, "n_min": n_min, "n_live": n, "vol_mc": math.exp(grid.ln_vol) * n_min / n}
     return AvGrid(nb, cells, grid.dims), info
+
+
+# ------------------------------------------------------ adaptive Cartesian
+# The product-form adaptive Cartesian (AC) sampler: one adaptive histogram per
+# sampled coordinate of the prior's CDF cube (nb = 64 equal bins), drawn by
+# the inverse CDF of each piecewise-constant marginal, so p_s / p is the
+# product of nb pi[k][b_k].  Readings (the paper only says each marginal is
+# updated after a block of evaluations to follow the integrand's support):
+#   * the update replaces every marginal by the histogram of the round's
+#     fixed-point masses q_i (the AV/fair-draw masses) over that coordinate's
+#     bins, mixed with the uniform: pi = (1 - floor) h / total + floor / nb,
+#     floor = 0.1 (p_s stays positive everywhere, so every round is unbiased);
+#   * cumulative sums are sequential in bin order with the last set to 1;
+#   * with no finite sample the marginals are kept.
+AC_BINS = 64
+
+
+class AcState:
+    def __init__(self, pi, dims):
+        self.pi = np.ascontiguousarray(np.asarray(pi, dtype=np.float64).reshape(len(dims), AC_BINS))
+        self.dims = list(dims)
+        c = np.cumsum(self.pi, axis=1)
+        c[:, -1] = 1.0
+        self.cum = np.ascontiguousarray(c)
+        self.lnbp = np.ascontiguousarray(np.log(AC_BINS * self.pi))
+
+    @property
+    def d(self):
+        return len(self.dims)
+
+
+def ac_init(dist_marg=False, dims=None):
+    dims = av_dims(dist_marg) if dims is None else list(dims)
+    return AcState(np.full((len(dims), AC_BINS), 1.0 / AC_BINS), dims)
+
+
+def draw_ac(prior, st, seed, rnd, i0, n):
+    """theta [7][n], ln p - ln p_s [n], bins [d][n]."""
+    th = np.empty((7, n))
+    lr = np.empty(n)
+    bins = np.empty((st.d, n), dtype=np.int32)
+    dims = (C.c_int * st.d)(*st.dims)
+    lib().orc_draw_ac(C.byref(prior), st.d, dims, AC_BINS, _dp(st.pi), _dp(st.cum), _dp(st.lnbp), seed, rnd,
+                      i0, n, _dp(th), n, _dp(lr), bins.ctypes.data_as(C.POINTER(C.c_int32)))
+    return th, lr, bins
+
+
+def ac_update(st, bins, lw, floor=0.1):
+    """New marginals from one round's bins [d][n] and log-weights [n]."""
+    lw = np.asarray(lw, dtype=np.float64)
+    fin = np.isfinite(lw)
+    if not fin.any():
+        return st
+    q = np.zeros(lw.size, dtype=np.uint64)
+    q[fin] = av_mass(lw[fin])
+    total = int(np.sum(q, dtype=np.uint64))
+    pi = np.empty((st.d, AC_BINS))
+    for k in range(st.d):
+        h = np.zeros(AC_BINS, dtype=np.uint64)
+        np.add.at(h, bins[k], q)
+        pi[k] = (1.0 - floor) * (h.astype(np.float64) / float(total)) + floor / AC_BINS
+    return AcState(pi, st.dims)
 
 
 # --------------------------------------------------------------- fair draws

@@ -419,6 +419,43 @@ void orc_draw_av(const orc_prior *pr, int n_dim, const int *dims, int nb, int64_
     }
 }
 
+/* ------------------------------------------- adaptive Cartesian draws */
+/*
+ * Product-form adaptive Cartesian (AC) sampling prior (the sampler with one
+ * adaptive one-dimensional marginal per coordinate, Section "Evaluating the
+ * marginalized likelihood"), in the prior's CDF coordinates: each sampled
+ * column k has nb equal bins with probabilities pi[k][b] and cumulative sums
+ * cum[k][b] (cum[k][nb-1] = 1).  Sample i of round r uses the prior draw's
+ * words; column c's uniform U = u53(w[2c], w[2c+1]) selects the first bin b
+ * with cum > U and x = (b + (U - cum[b-1]) / pi[b]) / nb (the inverse CDF of
+ * the piecewise-constant density).  ln p - ln p_s = -sum_k ln(nb pi[k][b_k]),
+ * with lnbp[k][b] = ln(nb pi[k][b]) given.  bins_out: [n_dim][n] or NULL.
+ */
+void orc_draw_ac(const orc_prior *pr, int n_dim, const int *dims, int nb, const double *pi, const double *cum,
+                 const double *lnbp, uint64_t seed, uint32_t round, int64_t i0, int64_t n, double *theta,
+                 int64_t ld, double *lnpmps, int32_t *bins_out)
+{
+    for (int64_t s = 0; s < n; s++) {
+        uint32_t w[16];
+        orc_words(seed, (uint64_t)(i0 + s), round, 0, 4, w);
+        double u[7], th[7], lr = 0.0;
+        for (int c = 0; c < 7; c++) u[c] = orc_u53(w[2 * c], w[2 * c + 1]);
+        for (int k = 0; k < n_dim; k++) {
+            const int c = dims[k];
+            const double U = u[c];
+            int b = 0;
+            while (b < nb - 1 && !(cum[k * nb + b] > U)) b++;
+            const double lo = b > 0 ? cum[k * nb + b - 1] : 0.0;
+            u[c] = ((double)b + (U - lo) / pi[k * nb + b]) / (double)nb;
+            lr -= lnbp[k * nb + b];
+            if (bins_out) bins_out[(int64_t)k * n + s] = b;
+        }
+        orc_prior_from_u(pr, u, th);
+        for (int c = 0; c < 7; c++) theta[c * ld + s] = th[c];
+        if (lnpmps) lnpmps[s] = lr;
+    }
+}
+
 /* ---------------------------------------------------------- Gaussian mixture */
 
 #define ORC_GMM_MAXC 16
