@@ -153,7 +153,7 @@ def serving_pool(per_class, seed):
 def serving_leg(ile, ctx, pool, n_jobs, adaptive, seed, policy, budget=0, rate=None, integrator=0):
     """Submit a job stream with Poisson arrivals; returns throughput and latency.
     rate=None: all jobs at once (saturated).  integrator: the adaptive jobs'
-    proposal (0: mixture refits, 1: adaptive volume)."""
+    proposal (0: mixture refits, 1: adaptive volume, 2: adaptive Cartesian)."""
     rng = np.random.default_rng(seed)
     hosts = {}
     srv = ile.ile_server_create(ctx, max_active=64, hbm_budget_bytes=budget, chunk_samples=1 << 20)
@@ -188,7 +188,7 @@ def serving_leg(ile, ctx, pool, n_jobs, adaptive, seed, policy, budget=0, rate=N
     if adaptive:
         rounds = np.array([r.rounds for r in res])
         neff = np.array([r.marg.n_eff for r in res])
-        out.update({"integrator": "adaptive volume" if integrator == 1 else "mixture",
+        out.update({"integrator": {0: "mixture", 1: "adaptive volume", 2: "adaptive Cartesian"}[integrator],
                     "rounds_mean": float(rounds.mean()),
                     "frac_reached_neff": float(np.mean(neff >= 1000.0)),
                     "n_eff_median": float(np.median(neff)),
@@ -242,7 +242,7 @@ def main():
                     help="the probe's step uses the time-marginalised likelihood (R = 4, 2^tmarg-log2n per point)")
     ap.add_argument("--adaptive-only", action="store_true",
                     help="run only the adaptive serving leg (--adaptive-jobs jobs) and print its summary")
-    ap.add_argument("--adaptive-integrator", choices=["gmm", "av", "both"], default="both",
+    ap.add_argument("--adaptive-integrator", choices=["gmm", "av", "ac", "all"], default="all",
                     help="proposal of the adaptive serving leg(s)")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -271,12 +271,13 @@ def main():
         print(json.dumps({"probe": True, "policy": a.probe_policy, "samples": r["N"], "kernel_ms": r["kernel_ms"],
                           "lnl_src_sha256": lnl_src_sha256()}), flush=True)
         return
-    integrators = {"gmm": [0], "av": [1], "both": [0, 1]}[a.adaptive_integrator]
+    integrators = {"gmm": [0], "av": [1], "ac": [2], "all": [0, 1, 2]}[a.adaptive_integrator]
+    leg_name = {0: "adaptive_saturated", 1: "adaptive_av_saturated", 2: "adaptive_ac_saturated"}
     if a.adaptive_only:
         pool = serving_pool(8, 250511655 + 4)
         out = {}
         for it in integrators:
-            out["adaptive_av_saturated" if it else "adaptive_saturated"] = serving_leg(
+            out[leg_name[it]] = serving_leg(
                 ile, ctx, pool, a.adaptive_jobs, True, 13, ile.ILE_FP32, integrator=it)
         print(json.dumps(out), flush=True)
         return
@@ -318,8 +319,8 @@ def main():
         if a.adaptive_jobs > 0:
             for it in integrators:
                 ada = serving_leg(ile, ctx, pool, a.adaptive_jobs, True, 13, ile.ILE_FP32, integrator=it)
-                log(f"adaptive {'av' if it else 'gmm'} {ada}")
-                serving["adaptive_av_saturated" if it else "adaptive_saturated"] = ada
+                log(f"{leg_name[it]} {ada}")
+                serving[leg_name[it]] = ada
     N = r32["N"]
     flop = FLOP_PER_SAMPLE[(3, 9)]
     t_eval = r32["kernel_ms"]["eval"] * 1e-3

@@ -295,6 +295,45 @@ ile_status ile_av_update(ile_job *job, uint64_t seed, uint32_t round, int64_t fi
  * are written. */
 ile_status ile_av_get(ile_job *job, ile_av_state *out, int32_t *cells, int64_t cap, ile_stream stream);
 
+/* ---------------------------------------------------- adaptive Cartesian */
+/* The product-form adaptive Cartesian (AC) sampling prior: one adaptive
+ * 64-bin piecewise-constant marginal per sampled column of the prior's CDF
+ * cube (all seven columns, or six with dist_marg, or a chosen subset; other
+ * columns are drawn from the prior).  A draw inverts each marginal's CDF at
+ * the prior draw's uniform for that column, so uniform marginals draw exactly
+ * the prior; ln p - ln p_s = -sum_k ln(64 pi_k(bin)).  An update replaces each
+ * marginal by the histogram, over its bins, of the round's fixed-point masses
+ * floor(exp(lw - max lw) 2^40), mixed with the uniform:
+ * pi = (1 - floor) h / total + floor / 64 (floor 0 means 0.1); with no finite
+ * lw the marginals are kept.  The update must follow the draw it refers to
+ * (same seed, round, first_index, n) with the marginals unchanged since.
+ * The state lives in device memory with the job; draws and updates are
+ * asynchronous on the stream. */
+ile_status ile_ac_reset(ile_job *job, int32_t n_dim, const int32_t *dims, ile_stream stream);
+ile_status ile_ac_draw(ile_job *job, uint64_t seed, uint32_t round, int64_t first_index, int64_t n,
+                       void *theta_out, int64_t ld, void *lnpmps_out, ile_stream stream);
+ile_status ile_ac_update(ile_job *job, uint64_t seed, uint32_t round, int64_t first_index, int64_t n,
+                         const void *lw, double floor_frac, ile_stream stream);
+/* Marginals (synchronises the stream): n_dim, dims[7] (-1 beyond n_dim) and
+ * pi host [n_dim][64]; any output may be NULL. */
+ile_status ile_ac_get(ile_job *job, int32_t *n_dim, int32_t *dims, double *pi, ile_stream stream);
+
+/* ------------------------------------------------------------ fair draws */
+/* Fair draws from weighted samples: the final extrinsic samples of an ILE run
+ * are drawn fairly from its weighted Monte Carlo samples (and the posterior
+ * from CIP's weighted samples the same way).  k independent draws with
+ * replacement: index i with probability q_i / sum q, q_i =
+ * floor(exp(lw_i - max lw) 2^40) (0 for non-finite lw).  Draw j uses Philox
+ * counter (j lo, j hi, round, 80) under `seed`: r = w0 2^32 + w1, target =
+ * floor(r total / 2^64), index = the first i whose cumulative mass exceeds
+ * it; -1 when no sample has mass.  lw: device [n], the policy's output type.
+ * idx_out: device [k] int64 or NULL.  theta (device [7][ld], theta type) and
+ * theta_out (device [7][ld_out], ld_out >= k) are optional: theta_out gets the
+ * drawn samples (NaN for index -1).  Asynchronous on the stream. */
+ile_status ile_fair_draw(ile_job *job, int64_t n, const void *lw, uint64_t seed, uint32_t round, int64_t k,
+                         int64_t *idx_out, const void *theta, int64_t ld, void *theta_out, int64_t ld_out,
+                         ile_stream stream);
+
 /* ---------------------------------------------------------------- serving */
 typedef struct {
     int32_t max_active;       /* jobs resident at once (default 64) */
@@ -313,12 +352,14 @@ typedef struct {
     int32_t tmarg_oversample; /* 0: pointwise lnL; 1 or 4: time-marginalised lnL (ile_eval_lnL_tmarg with
                                  this R; plain ILE_FP32/ILE_FP64 jobs without dist_marg only), with
                                  chunk_samples/16 samples per pass */
-    int32_t integrator;       /* adaptive: ILE_INT_GMM (mixture refits) or ILE_INT_AV (adaptive volume,
-                                 ile_av_update with default options after each round) */
+    int32_t integrator;       /* adaptive: ILE_INT_GMM (mixture refits), ILE_INT_AV (adaptive volume,
+                                 ile_av_update with default options after each round) or ILE_INT_AC
+                                 (adaptive Cartesian, ile_ac_update with floor 0.1 after each round) */
 } ile_job_opts;
 
 #define ILE_INT_GMM 0
 #define ILE_INT_AV 1
+#define ILE_INT_AC 2
 
 typedef struct {
     ile_marg marg;

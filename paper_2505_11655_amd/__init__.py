@@ -85,7 +85,8 @@ class ile_job_opts(C.Structure):
                 ("tmarg_oversample", C.c_int32), ("integrator", C.c_int32)]
 
 
-ILE_INT_GMM, ILE_INT_AV = 0, 1
+ILE_INT_GMM, ILE_INT_AV, ILE_INT_AC = 0, 1, 2
+AC_BINS = 64
 
 
 class ile_av_opts(C.Structure):
@@ -145,6 +146,15 @@ EXPORTS = {
                                 C.POINTER(ile_av_opts), C.POINTER(ile_av_state), C.c_void_p]),
     "ile_av_get": (C.c_int, [C.c_void_p, C.POINTER(ile_av_state), C.POINTER(C.c_int32), C.c_int64,
                              C.c_void_p]),
+    "ile_ac_reset": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_void_p]),
+    "ile_ac_draw": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
+                              C.c_void_p, C.c_void_p]),
+    "ile_ac_update": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, C.c_void_p, C.c_double,
+                                C.c_void_p]),
+    "ile_ac_get": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                             C.c_void_p]),
+    "ile_fair_draw": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_uint64, C.c_uint32, C.c_int64, C.c_void_p,
+                                C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "ile_server_create": (C.c_int, [C.c_void_p, C.POINTER(ile_server_opts), C.POINTER(C.c_void_p)]),
     "ile_server_submit": (C.c_int, [C.c_void_p, C.POINTER(ile_problem), C.POINTER(ile_job_opts),
                                     C.POINTER(C.c_uint64)]),
@@ -378,6 +388,37 @@ def ile_av_get(job, cells=True, stream=None):
     arr = np.zeros((max(st.n_cells, 1), max(st.n_dim, 1)), dtype=np.int32)
     _chk(lib().ile_av_get(job, C.byref(st), arr.ctypes.data_as(C.POINTER(C.c_int32)), st.n_cells, _s(stream)))
     return st.as_dict(), arr[:st.n_cells, :st.n_dim]
+
+
+def ile_ac_reset(job, dims=None, stream=None):
+    if dims is None:
+        _chk(lib().ile_ac_reset(job, 0, None, _s(stream)))
+    else:
+        arr = (C.c_int32 * max(len(dims), 1))(*dims)
+        _chk(lib().ile_ac_reset(job, len(dims), arr, _s(stream)))
+
+
+def ile_ac_draw(job, seed, rnd, first_index, n, theta_out, ld, lnpmps_out=None, stream=None):
+    _chk(lib().ile_ac_draw(job, seed, rnd, first_index, n, _p(theta_out), ld, _p(lnpmps_out), _s(stream)))
+
+
+def ile_ac_update(job, seed, rnd, first_index, n, lw, floor=0.1, stream=None):
+    _chk(lib().ile_ac_update(job, seed, rnd, first_index, n, _p(lw), floor, _s(stream)))
+
+
+def ile_ac_get(job, stream=None):
+    """(dims list, pi [n_dim][64] numpy array)."""
+    import numpy as np
+    nd = C.c_int32()
+    dims = (C.c_int32 * 7)()
+    pi = np.zeros((7, AC_BINS))
+    _chk(lib().ile_ac_get(job, C.byref(nd), dims, pi.ctypes.data_as(C.POINTER(C.c_double)), _s(stream)))
+    return [dims[k] for k in range(nd.value)], pi[:nd.value]
+
+
+def ile_fair_draw(job, n, lw, seed, rnd, k, idx_out=None, theta=None, ld=0, theta_out=None, ld_out=0, stream=None):
+    _chk(lib().ile_fair_draw(job, n, _p(lw), seed, rnd, k, _p(idx_out), _p(theta), ld, _p(theta_out), ld_out,
+                             _s(stream)))
 
 
 # ------------------------------------------------------------------ serving

@@ -561,7 +561,8 @@ extern "C" ile_status ile_job_info_get(const ile_job *job, ile_job_info *info) {
     info->mode_slots = kSets[job->set].n;
     info->n_det_slots = job->kp;
     info->device_bytes = job->device_bytes + job->part_cap * sizeof(MargPartial) + job->em_cap +
-                         (job->d_gmm ? sizeof(GmmDev) : 0) + job->av_bytes;
+                         (job->d_gmm ? sizeof(GmmDev) : 0) + job->av_bytes + job->fair_cap +
+                         (job->d_ac ? sizeof(AcDev) : 0);
     return ILE_OK;
 }
 
@@ -574,6 +575,8 @@ void ile::job_release_nosync(ile_job *job) {
     ctx_free(ctx, job->d_gmm, sizeof(GmmDev));
     ctx_free(ctx, job->d_zcount, kMaxComp * sizeof(uint32_t));
     ctx_free(ctx, job->av_mem, job->av_bytes);
+    ctx_free(ctx, job->fair_mem, job->fair_cap);
+    ctx_free(ctx, job->d_ac, sizeof(AcDev));
     pin_free(ctx, job->h_av, sizeof(AvDev));
     pin_free(ctx, job->h_blob, job->blob_bytes);
     pin_free(ctx, job->h_ms, sizeof(MargState));

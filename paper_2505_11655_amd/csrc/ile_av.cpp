@@ -265,3 +265,31 @@ extern "C" ile_status ile_av_get(ile_job *job, ile_av_state *out, int32_t *cells
     }
     return ILE_OK;
 }
+
+extern "C" ile_status ile_fair_draw(ile_job *job, int64_t n, const void *lw, uint64_t seed, uint32_t round,
+                                    int64_t k, int64_t *idx_out, const void *theta, int64_t ld, void *theta_out,
+                                    int64_t ld_out, ile_stream stream) {
+    if (!job) return set_err(ILE_E_INVALID, "null job");
+    ile_status s = ctx_check(job->ctx);
+    if (s != ILE_OK) return s;
+    if (n < 1 || k < 0) return set_err(ILE_E_INVALID, "need n >= 1 and k >= 0");
+    if (!lw) return set_err(ILE_E_INVALID, "null lw");
+    if (theta_out && (!theta || ld < n || ld_out < k)) return set_err(ILE_E_INVALID, "theta_out needs theta, ld >= n, ld_out >= k");
+    if (!idx_out && !theta_out) return set_err(ILE_E_INVALID, "no output");
+    if (k == 0) return ILE_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t need = fair_scratch_bytes(n);
+    if (need > job->fair_cap) {
+        hipError_t e = hipStreamSynchronize(st);   // queued draws may still read the old scratch
+        if (e != hipSuccess) return dev_fail(job->ctx, e, "sync before fair-draw scratch growth");
+        ctx_free(job->ctx, job->fair_mem, job->fair_cap);
+        job->fair_mem = nullptr;
+        job->fair_cap = 0;
+        if ((s = ctx_alloc(job->ctx, &job->fair_mem, need, "fair-draw scratch")) != ILE_OK) return s;
+        job->fair_cap = need;
+    }
+    hipError_t e = launch_fair_draw(job->policy, lw, n, seed, round, k, idx_out, theta, ld, theta_out, ld_out,
+                                    job->fair_mem, st);
+    if (e != hipSuccess) return dev_fail(job->ctx, e, "fair draw");
+    return ILE_OK;
+}

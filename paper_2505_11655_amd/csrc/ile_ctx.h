@@ -72,6 +72,11 @@ struct ile_job {
     size_t av_bytes = 0;
     int64_t av_cap = 0;
     ile::AvDev *h_av = nullptr;           // pinned readback
+    // adaptive Cartesian marginals (allocated on first use)
+    ile::AcDev *d_ac = nullptr;
+    // fair-draw scratch (prefix sums of the sample masses), grown as needed
+    void *fair_mem = nullptr;
+    size_t fair_cap = 0;
 };
 
 namespace ile {
@@ -189,6 +194,10 @@ size_t av_bytes_for(int64_t cap);
 // Batched AV draws (update = false; policy: the jobs' policy, theta type) or
 // updates (update = true; log-weight type) of several jobs.
 ile_status av_batch(ile_ctx *ctx, bool update, int policy, const std::vector<AvJob> &jobs, hipStream_t st);
+// Adaptive Cartesian: the job's marginals (uniform over the sampled columns
+// on first use), and batched draws / updates as for AV.
+ile_status ac_ensure(ile_job *job, hipStream_t st);
+ile_status ac_batch(ile_ctx *ctx, bool update, int policy, const std::vector<AcJob> &jobs, hipStream_t st);
 void eval_geometry(const ile_job *job, int64_t n, size_t *lds, int64_t *tile, int *block);
 size_t theta_size(int policy);
 size_t out_size(int policy);

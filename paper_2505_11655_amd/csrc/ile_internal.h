@@ -409,6 +409,46 @@ struct AvJob {
     int64_t n_min_live;
     int max_bins;
 };
+// ------------------------------------------------- adaptive Cartesian
+// Product-form adaptive Cartesian sampler: one kAcBins-bin histogram marginal
+// per sampled coordinate of the prior's CDF cube.
+constexpr int kAcBins = 64;
+struct AcDev {
+    int32_t d;            // sampled columns
+    int32_t dims[7];
+    int32_t kcol[7];      // marginal of each theta column, -1: drawn from the prior
+    int32_t pad_;
+    double pi[7][kAcBins];      // bin probabilities
+    double cum[7][kAcBins];     // sequential cumulative sums, cum[k][nb-1] = 1
+    double lnbp[7][kAcBins];    // ln(nb pi)
+    unsigned long long key_max, n_fin;
+    unsigned long long hist[7][kAcBins];   // update: fixed-point masses per bin
+};
+struct AcJob {
+    AcDev *st;
+    PriorDev pr;          // draws
+    uint64_t seed;
+    uint32_t round;
+    int64_t first;
+    int64_t n;
+    void *theta;          // draws: [7][ld] theta type; [n] ln p - ln p_s or null
+    int64_t ld;
+    void *lnpmps;
+    const void *lw;       // updates: [n] log-weights (the policy's output type)
+    double floor;         // updates: uniform fraction mixed into each marginal
+};
+hipError_t launch_ac_reset(AcDev *st, int d, const int *dims, hipStream_t st_);
+hipError_t launch_ac_draw(int policy, const AcJob *d_jobs, const AcJob *h_jobs, int n_jobs, hipStream_t st);
+hipError_t launch_ac_update(int policy, const AcJob *d_jobs, const AcJob *h_jobs, int n_jobs, hipStream_t st);
+
+// Fair draws from weighted samples (k_fair.hip): scratch of
+// fair_scratch_bytes(n) bytes; lw in the policy's output type, theta in its
+// theta type.
+size_t fair_scratch_bytes(int64_t n);
+hipError_t launch_fair_draw(int policy, const void *lw, int64_t n, uint64_t seed, uint32_t round, int64_t k,
+                            int64_t *idx, const void *theta, int64_t ld, void *theta_out, int64_t ld_out,
+                            void *scratch, hipStream_t st);
+
 // Initial grid: one cell, nb = 1, over the given columns.
 hipError_t launch_av_reset(const AvBufs &b, int d, const int *dims, hipStream_t st);
 // d_jobs: device copy of h_jobs (all of one theta type for draws, of one

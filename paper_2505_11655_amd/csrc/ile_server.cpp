@@ -112,6 +112,8 @@ size_t footprint_of(const ile_server *s, const Req *r) {
     size_t extra = sizeof(MargState) + ((size_t)c / 16384 + 1) * sizeof(MargPartial);
     if (r->jo.adaptive && r->jo.integrator == ILE_INT_AV)
         extra += av_bytes_for(c);
+    else if (r->jo.adaptive && r->jo.integrator == ILE_INT_AC)
+        extra += sizeof(AcDev);
     else if (r->jo.adaptive)
         extra += sizeof(GmmDev) + em_work_bytes(c) + 64 * sizeof(uint32_t);
     return inputs + bufs + extra;
@@ -152,6 +154,7 @@ ile_status admit(ile_server *s, Req *r) {
     const size_t tb = theta_bytes(policy);
     if (r->jo.adaptive && r->jo.integrator == ILE_INT_AV && (st = av_ensure(job, r->chunk, s->stream)) != ILE_OK)
         return st;
+    if (r->jo.adaptive && r->jo.integrator == ILE_INT_AC && (st = ac_ensure(job, s->stream)) != ILE_OK) return st;
     if ((st = ctx_alloc(s->ctx, &r->d_theta, (size_t)7 * r->chunk * tb, "theta")) != ILE_OK) return st;
     if ((st = ctx_alloc(s->ctx, &r->d_lr, (size_t)r->chunk * tb, "ln p - ln ps")) != ILE_OK) return st;
     if ((st = ctx_alloc(s->ctx, &r->d_lw, (size_t)r->chunk * lw_bytes(policy), "lw")) != ILE_OK) return st;
@@ -166,6 +169,7 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
     // draws, grouped by theta type
     std::vector<DrawJob> d32, d64;
     std::vector<AvJob> av32, av64;   // adaptive-volume draws by theta type
+    std::vector<AcJob> ac32, ac64;   // adaptive Cartesian draws by theta type
     std::vector<BatchItem> items, tm1, tm4;   // pointwise; time-marginalised with R = 1, 4
     std::vector<int64_t> nthis(act.size());
     for (size_t i = 0; i < act.size(); i++) {
@@ -188,6 +192,19 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
             (r->prob.precision == kFP64 ? av64 : av32).push_back(aj);
             continue;
         }
+        if (r->jo.adaptive && r->jo.integrator == ILE_INT_AC) {
+            AcJob cj{};
+            cj.st = r->job->d_ac;
+            cj.pr = r->job->pr;
+            cj.seed = r->jo.seed;
+            cj.round = (uint32_t)r->rounds;
+            cj.n = n;
+            cj.theta = r->d_theta;
+            cj.ld = n;
+            cj.lnpmps = r->d_lr;
+            (r->prob.precision == kFP64 ? ac64 : ac32).push_back(cj);
+            continue;
+        }
         DrawJob dj{};
         dj.gmm = r->job->has_prop ? r->job->d_gmm : nullptr;
         dj.pr = r->job->pr;
@@ -204,6 +221,8 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
     if (!d64.empty() && draw_batch(s->ctx, kFP64, d64, st) != ILE_OK) return false;
     if (av_batch(s->ctx, false, kFP32, av32, st) != ILE_OK) return false;
     if (av_batch(s->ctx, false, kFP64, av64, st) != ILE_OK) return false;
+    if (ac_batch(s->ctx, false, kFP32, ac32, st) != ILE_OK) return false;
+    if (ac_batch(s->ctx, false, kFP64, ac64, st) != ILE_OK) return false;
     if (!items.empty() && eval_batch(s->ctx, items, st) != ILE_OK) return false;
     if (!tm1.empty() && tmarg_batch(s->ctx, tm1, 1, st) != ILE_OK) return false;
     if (!tm4.empty() && tmarg_batch(s->ctx, tm4, 4, st) != ILE_OK) return false;
@@ -278,6 +297,20 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
         }
         if (av_batch(s->ctx, true, kFP32, u32, st) != ILE_OK) return false;
         if (av_batch(s->ctx, true, kFP64, u64, st) != ILE_OK) return false;
+        std::vector<AcJob> c32, c64;
+        for (Req *r : refit) {
+            if (r->jo.integrator != ILE_INT_AC) continue;
+            AcJob cj{};
+            cj.st = r->job->d_ac;
+            cj.seed = r->jo.seed;
+            cj.round = (uint32_t)(r->rounds - 1);
+            cj.n = r->chunk;
+            cj.lw = r->d_lw;
+            cj.floor = 0.1;
+            (r->prob.precision == kFP32 ? c32 : c64).push_back(cj);
+        }
+        if (ac_batch(s->ctx, true, kFP32, c32, st) != ILE_OK) return false;
+        if (ac_batch(s->ctx, true, kFP64, c64, st) != ILE_OK) return false;
     }
     // one batched refit per precision policy; each job's mass draws use its
     // own key and round
@@ -290,7 +323,7 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
     for (int pol = 0; pol < 3; pol++) {
         std::vector<AdaptItem> items;
         for (Req *r : refit)
-            if (r->job->policy == pol && r->jo.integrator != ILE_INT_AV)
+            if (r->job->policy == pol && r->jo.integrator == ILE_INT_GMM)
                 items.push_back(AdaptItem{r->job, r->chunk, r->d_theta, r->chunk, r->d_lw,
                                           r->jo.seed ^ 0x9E3779B97F4A7C15ull, (uint32_t)r->rounds});
         if (!items.empty() && adapt_batch(s->ctx, pol, items, &o, st) != ILE_OK) return false;
@@ -375,8 +408,8 @@ extern "C" ile_status ile_server_submit(ile_server *s, const ile_problem *P, con
         !P->U || !P->mode_l || !P->mode_m || !P->det_pos || !P->det_resp)
         return set_err(ILE_E_INVALID, "bad problem shape");
     if (!jo->adaptive && jo->n_samples < 1) return set_err(ILE_E_INVALID, "n_samples must be >= 1");
-    if (jo->integrator != ILE_INT_GMM && jo->integrator != ILE_INT_AV)
-        return set_err(ILE_E_INVALID, "integrator must be ILE_INT_GMM or ILE_INT_AV");
+    if (jo->integrator != ILE_INT_GMM && jo->integrator != ILE_INT_AV && jo->integrator != ILE_INT_AC)
+        return set_err(ILE_E_INVALID, "integrator must be ILE_INT_GMM, ILE_INT_AV or ILE_INT_AC");
     if (jo->adaptive && jo->round_samples >= ((int64_t)1 << 31))
         return set_err(ILE_E_INVALID, "round_samples must be below 2^31");
     if (jo->tmarg_oversample != 0) {
