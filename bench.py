@@ -196,6 +196,36 @@ def serving_leg(ile, ctx, pool, n_jobs, adaptive, seed, policy, budget=0, rate=N
     return out
 
 
+def fair_leg(ile, torch, ctx, prob, stream, log2n=26, log2k=20, reps=5):
+    """Fair draws of 2^log2k samples from 2^log2n weighted ones (FP32 weights
+    of a spread like a prior run's, seeded), the drawn theta copied out: the
+    final-draw step of an ILE run at the scale of one benchmark step."""
+    n, k = 1 << log2n, 1 << log2k
+    job = ile.ile_prepare(ctx, ile.ProblemHost(prob, precision=ile.ILE_FP32))
+    g = torch.Generator(device="cuda").manual_seed(7)
+    lw = torch.randn(n, device="cuda", generator=g) * 30.0
+    th = torch.randn((7, n), device="cuda", generator=g)
+    idx = torch.empty(k, dtype=torch.int64, device="cuda")
+    out = torch.empty((7, k), device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ile.ile_fair_draw(job, n, lw, 1, 0, k, idx, th, n, out, k, stream=stream)
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for r in range(reps):
+        ile.ile_fair_draw(job, n, lw, 1, r, k, idx, th, n, out, k, stream=stream)
+    ev[1].record(stream)
+    ev[1].synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    ile.ile_job_release(job)
+    del lw, th, idx, out
+    torch.cuda.empty_cache()
+    # HBM: lw read twice (tile sums, prefix sums), the prefix sums written once;
+    # each draw reads ~log2 n prefix entries and copies 7 theta values
+    bytes_ = n * (4 + 4 + 8) + k * (7 * 4 * 2 + 8)
+    return {"n": n, "k": k, "ms": ms, "samples_per_s": n / (ms * 1e-3), "draws_per_s": k / (ms * 1e-3),
+            "hbm_GBps_algorithmic": bytes_ / (ms * 1e-3) / 1e9, "hbm_frac": bytes_ / (ms * 1e-3) / HBM_PEAK}
+
+
 def cpu_baseline(probs, budget_s=15.0):
     """The oracle as it stands, on a bounded sample of the same workload."""
     import chirpgen
@@ -304,6 +334,9 @@ def main():
             tmarg[name] = {"samples_per_s": rt["samples_per_s"], "nodes_per_s": rt["samples_per_s"] * nodes,
                            "ms_per_step": rt["ms_per_step"], "kernel_ms": rt["kernel_ms"],
                            "lnL_marg_first": rt["lnL_marg_first"]}
+    log("fair draws ...")
+    fair = fair_leg(ile, torch, ctx, probs[0], stream)
+    log(f"fair {fair}")
     serving = None
     if not a.no_serving:
         log("serving pool ...")
@@ -366,6 +399,7 @@ def main():
                                           "kernel_ms": r64["kernel_ms"],
                                           "fp32_over_fp64": r32["samples_per_s"] / r64["samples_per_s"]},
         "time_marginalised": tmarg,
+        "fair_draws": fair,
         "serving": serving,
         "cpu_baseline": None if a.no_cpu else cpu_baseline(probs),
     }
