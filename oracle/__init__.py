@@ -14,7 +14,8 @@ this module wraps it and adds definition-level numpy helpers:
   * ``draw_av``, ``av_threshold``, ``av_refine_bins``, ``av_cells``, ``av_update``
                          - the adaptive-volume integrator (its readings are listed there);
   * ``draw_ac``, ``ac_update`` - the product-form adaptive Cartesian sampler;
-  * ``fair_draw``        - fair draws from weighted samples.
+  * ``fair_draw``        - fair draws from weighted samples;
+  * ``overlaps_qv``      - Q, U, V of eq. (QUV) from modes and data.
 
 Pins: ``tests/test_oracle_pins.py``.  Parity unpinned: EM trajectories with
 more than one component, the in-support mass estimates (Monte Carlo).
@@ -501,6 +502,42 @@ def ac_update(st, bins, lw, floor=0.1):
         np.add.at(h, bins[k], q)
         pi[k] = (1.0 - floor) * (h.astype(np.float64) / float(total)) + floor / AC_BINS
     return AcState(pi, st.dims)
+
+
+# ------------------------------------------------------ Q, U, V precompute
+def overlaps_qv(hlm, data, inv_psd, df, f_lo, f_hi, n_time, win_half):
+    """The inner products of eq. (QUV) from the modes and the data, by their
+    definitions over the two-sided frequency grid f_m = m' df (m' the signed
+    index of FFT order), restricted to f_lo <= |f| <= f_hi, with
+    <a|b>_k = 2 df sum_f conj(a(f)) b(f) w_k(f), w_k = 1/S_k (None: 1):
+      Q[k][a][i] = 2 df sum_f e^{2 pi i f tau_i} conj(h_a(f)) d_k(f) w_k(f),
+                   tau_i = (i - win_half) / (n df), the phase taken as
+                   2 pi ((m' (i - win_half)) mod n) / n;
+      U[k][a][b] = <h_a|h_b>_k;
+      V[k][a][b] = <h_a^*|h_b>_k = 2 df sum_f h_a(-f) h_b(f) w_k(f).
+    hlm [n_modes][n], data [n_det][n] (complex), inv_psd [n_det][n] or None."""
+    hlm = np.asarray(hlm, dtype=np.complex128)
+    data = np.asarray(data, dtype=np.complex128)
+    na, n = hlm.shape
+    nd = data.shape[0]
+    w = np.ones((nd, n)) if inv_psd is None else np.asarray(inv_psd, dtype=np.float64)
+    ms = np.fft.fftfreq(n, d=1.0 / n).round().astype(np.int64)
+    f = ms * df
+    band = np.nonzero((np.abs(f) >= f_lo) & (np.abs(f) <= f_hi))[0]
+    neg = (n - band) % n
+    j = np.arange(n_time, dtype=np.int64) - win_half
+    E = np.exp(2j * np.pi * ((np.outer(j, ms[band]) % n) / n))
+    Q = np.empty((nd, na, n_time), dtype=np.complex128)
+    U = np.empty((nd, na, na), dtype=np.complex128)
+    V = np.empty((nd, na, na), dtype=np.complex128)
+    hb = hlm[:, band]
+    for k in range(nd):
+        wk = w[k, band]
+        x = 2.0 * df * np.conj(hb) * (data[k, band] * wk)[None, :]
+        Q[k] = (E @ x.T).T
+        U[k] = 2.0 * df * (np.conj(hb) * wk) @ hb.T
+        V[k] = 2.0 * df * (hlm[:, neg] * wk) @ hb.T
+    return Q, U, V
 
 
 # --------------------------------------------------------------- fair draws

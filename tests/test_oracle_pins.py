@@ -935,3 +935,60 @@ def test_PC4_ac_update_histogram_closed_form(orc):
     assert abs(st2.cum[0, -1] - 1.0) == 0.0
     st3 = orc.ac_update(st, bins, np.full(50000, -np.inf))
     assert np.array_equal(st3.pi, st.pi)
+
+
+# ------------------------------------------------------- Q, U, V precompute (f4)
+def test_PQ1_window_Q_is_the_exact_Q_at_the_sample_times(orc, recs):
+    """The windowed Q of the precompute equals the direct frequency sum of
+    eq. (QUV) at each window time tau_i = (i - 205)/4096 (exact_Q, pinned by
+    P1), for every detector, mode and time."""
+    p, ev, hlm = _event(recs, "c2", ["H", "L", "V"], 9, q=3.0, noise=True, seed=5)
+    Q, U, V = orc.overlaps_qv(hlm, ev["data"], None, ev["df"], 20.0, 1024.0, 410, 205)
+    for k in range(3):
+        for i in (0, 1, 137, 205, 409):
+            ref = orc.exact_Q(ev["f"], ev["df"], hlm, ev["data"][k], (i - 205) / 4096.0)
+            assert np.allclose(Q[k, :, i], ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("key,dets,n,q", [("c1", ["H", "L"], 5, 2.0), ("c3", ["H", "L", "V"], 17, 20.0)])
+def test_PQ2_precomputed_U_V_give_rho2_over_2(orc, recs, key, dets, n, q):
+    """With U and V from the precompute, the noiseless injection's lnL (exact
+    Q) is rho^2/2 from the strains alone (P1), and U is Hermitian positive
+    semi-definite, V symmetric; V built without the frequency reversal (a
+    planted mistake: <h_a|h_b> in place of <h_a^*|h_b>) fails."""
+    p, ev, hlm = _event(recs, key, dets, n, q=q)
+    th = np.array(recs[key]["theta"])
+    rho2 = chirpgen.network_snr2(ev["f"], ev["df"], ev["strain"])
+    Q, U, V = orc.overlaps_qv(hlm, ev["data"], None, ev["df"], 20.0, 1024.0, 410, 205)
+    for k in range(len(dets)):
+        assert np.allclose(U[k], np.conj(U[k]).T, rtol=0, atol=1e-12 * np.abs(U[k]).max())
+        assert np.allclose(V[k], V[k].T, rtol=0, atol=1e-12 * np.abs(V[k]).max())
+        assert np.linalg.eigvalsh(U[k]).min() > -1e-10 * np.abs(U[k]).max()
+    p2 = p.__class__(**{**p.__dict__})
+    p2.U, p2.V = U, V
+    l, _, _ = orc.lnL_exact(p2, th, ev["f"], ev["df"], hlm, ev["data"])
+    assert abs(l - rho2 / 2) <= 1e-9 * rho2 / 2
+    bad = p.__class__(**{**p.__dict__})
+    bad.U, bad.V = U, U.copy()
+    lb, _, _ = orc.lnL_exact(bad, th, ev["f"], ev["df"], hlm, ev["data"])
+    assert abs(lb - rho2 / 2) > 1e-3
+
+
+def test_PQ3_single_frequency_closed_form(orc):
+    """One mode and one detector with a single band frequency f0 (and its
+    mirror for V): Q(tau) = 2 df conj(h) d e^{2 pi i f0 tau}, U = 2 df |h|^2,
+    V = 2 df h(-f0) h(f0); a PSD weight scales all three."""
+    n, df = 4096, 0.5
+    m0 = 300                                   # f0 = 150 Hz
+    h = np.zeros((1, n), complex)
+    d = np.zeros((1, n), complex)
+    h[0, m0] = 0.3 - 0.4j
+    h[0, n - m0] = 0.1 + 0.2j
+    d[0, m0] = 1.5 + 0.5j
+    w = np.full((1, n), 2.0)
+    Q, U, V = orc.overlaps_qv(h, d, w, df, 20.0, 1024.0, 64, 32)
+    tau = (np.arange(64) - 32) / (n * df)
+    want = 2 * df * np.conj(h[0, m0]) * d[0, m0] * 2.0 * np.exp(2j * np.pi * 150.0 * tau)
+    assert np.allclose(Q[0, 0], want, rtol=1e-13, atol=1e-15)
+    assert abs(U[0, 0, 0] - 2 * df * 2.0 * (abs(h[0, m0]) ** 2 + abs(h[0, n - m0]) ** 2)) < 1e-14
+    assert abs(V[0, 0, 0] - 2 * df * 2.0 * 2 * h[0, n - m0] * h[0, m0]) < 1e-14
