@@ -318,6 +318,31 @@ ile_status ile_ac_update(ile_job *job, uint64_t seed, uint32_t round, int64_t fi
  * pi host [n_dim][64]; any output may be NULL. */
 ile_status ile_ac_get(ile_job *job, int32_t *n_dim, int32_t *dims, double *pi, ile_stream stream);
 
+/* ---------------------------------------------------- Q, U, V precompute */
+/* The inner products of eq. (QUV) on the device, in FP64, for n_points
+ * intrinsic points (mode sets) sharing one data set:
+ *   Q[p][k][a][i] = 2 df sum_f e^{2 pi i f tau_i} conj(h_pa(f)) d_k(f) w_k(f),
+ *   U[p][k][a][b] = 2 df sum_f conj(h_pa(f)) h_pb(f) w_k(f),
+ *   V[p][k][a][b] = 2 df sum_f h_pa(-f) h_pb(f) w_k(f),
+ * over f_lo <= |f| <= f_hi of the two-sided grid f_m = m' df (m' the signed
+ * index in FFT order: 0..n/2-1, then -n/2..-1), tau_i = (i - win_half)/(n df)
+ * with the phase taken exactly as 2 pi ((m' (i - win_half)) mod n)/n.  U is
+ * formed for a <= b and mirrored (U_ba = conj U_ab, V_ba = V_ab).  The Q and
+ * U, V layouts are those ile_problem takes, one block per point. */
+typedef struct {
+    int32_t n_points, n_modes, n_det;
+    int64_t n_freq;           /* grid length n */
+    double df, f_lo, f_hi;
+    int32_t n_time, win_half; /* Q window */
+} ile_qv_shape;
+/* hlm: device [n_points][n_modes][n_freq] complex128; data: device
+ * [n_det][n_freq] complex128; inv_psd: device [n_det][n_freq] 1/S_k(|f|) or
+ * NULL (flat, 1); Q: device [n_points][n_det][n_modes][n_time] complex128;
+ * U, V: device [n_points][n_det][n_modes][n_modes] complex128.  Synchronises
+ * the stream (its scratch is released on return). */
+ile_status ile_overlaps(ile_ctx *ctx, const ile_qv_shape *shape, const void *hlm, const void *data,
+                        const double *inv_psd, void *Q, void *U, void *V, ile_stream stream);
+
 /* ------------------------------------------------------------ fair draws */
 /* Fair draws from weighted samples: the final extrinsic samples of an ILE run
  * are drawn fairly from its weighted Monte Carlo samples (and the posterior

@@ -89,6 +89,12 @@ ILE_INT_GMM, ILE_INT_AV, ILE_INT_AC = 0, 1, 2
 AC_BINS = 64
 
 
+class ile_qv_shape(C.Structure):
+    _fields_ = [("n_points", C.c_int32), ("n_modes", C.c_int32), ("n_det", C.c_int32), ("n_freq", C.c_int64),
+                ("df", C.c_double), ("f_lo", C.c_double), ("f_hi", C.c_double), ("n_time", C.c_int32),
+                ("win_half", C.c_int32)]
+
+
 class ile_av_opts(C.Structure):
     _fields_ = [("p_thr", C.c_double), ("n_min_live", C.c_int64), ("max_bins", C.c_int32)]
 
@@ -153,6 +159,8 @@ EXPORTS = {
                                 C.c_void_p]),
     "ile_ac_get": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                              C.c_void_p]),
+    "ile_overlaps": (C.c_int, [C.c_void_p, C.POINTER(ile_qv_shape), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_void_p]),
     "ile_fair_draw": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_uint64, C.c_uint32, C.c_int64, C.c_void_p,
                                 C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "ile_server_create": (C.c_int, [C.c_void_p, C.POINTER(ile_server_opts), C.POINTER(C.c_void_p)]),
@@ -414,6 +422,13 @@ def ile_ac_get(job, stream=None):
     pi = np.zeros((7, AC_BINS))
     _chk(lib().ile_ac_get(job, C.byref(nd), dims, pi.ctypes.data_as(C.POINTER(C.c_double)), _s(stream)))
     return [dims[k] for k in range(nd.value)], pi[:nd.value]
+
+
+def ile_overlaps(ctx, hlm, data, df, f_lo, f_hi, n_time, win_half, Q, U, V, inv_psd=None, stream=None):
+    """hlm: device [n_points][n_modes][n] complex128 (a 2-D [n_modes][n] array is one point)."""
+    n_points, n_modes, n = (1,) + tuple(hlm.shape) if hlm.dim() == 2 else tuple(hlm.shape)
+    sh = ile_qv_shape(n_points, n_modes, data.shape[0], n, df, f_lo, f_hi, n_time, win_half)
+    _chk(lib().ile_overlaps(ctx, C.byref(sh), _p(hlm), _p(data), _p(inv_psd), _p(Q), _p(U), _p(V), _s(stream)))
 
 
 def ile_fair_draw(job, n, lw, seed, rnd, k, idx_out=None, theta=None, ld=0, theta_out=None, ld_out=0, stream=None):

@@ -141,3 +141,37 @@ extern "C" ile_status ile_ac_get(ile_job *job, int32_t *n_dim, int32_t *dims, do
             for (int b = 0; b < kAcBins; b++) pi[k * kAcBins + b] = S.pi[k][b];
     return ILE_OK;
 }
+
+extern "C" ile_status ile_overlaps(ile_ctx *ctx, const ile_qv_shape *sh, const void *hlm, const void *data,
+                                   const double *inv_psd, void *Q, void *U, void *V, ile_stream stream) {
+    if (!ctx || !sh) return set_err(ILE_E_INVALID, "null argument");
+    ile_status s = ctx_check(ctx);
+    if (s != ILE_OK) return s;
+    if (sh->n_points < 1 || sh->n_modes < 1 || sh->n_det < 1 || sh->n_freq < 4 || sh->n_time < 1 ||
+        sh->n_time > sh->n_freq || !(sh->df > 0) || !(sh->f_hi >= sh->f_lo) || sh->f_lo < 0)
+        return set_err(ILE_E_INVALID, "bad overlap shape");
+    if (!hlm || !data || !Q || !U || !V) return set_err(ILE_E_INVALID, "null array");
+    const int64_t n = sh->n_freq;
+    std::vector<int64_t> band, msig;
+    for (int64_t m = 0; m < n; m++) {
+        const int64_t ms = m < (n + 1) / 2 ? m : m - n;   // FFT-order signed index
+        const double af = std::fabs((double)ms * sh->df);
+        if (af >= sh->f_lo && af <= sh->f_hi) {
+            band.push_back(m);
+            msig.push_back(ms);
+        }
+    }
+    if (band.empty()) return set_err(ILE_E_INVALID, "no grid frequency inside the band");
+    const int64_t cols = (int64_t)sh->n_points * sh->n_det * sh->n_modes;
+    const int ns = qv_slices((int64_t)band.size(), cols, sh->n_time);
+    const size_t need = qv_scratch_bytes(n, (int64_t)band.size(), cols, sh->n_time, ns);
+    void *scratch = nullptr;
+    if ((s = ctx_alloc(ctx, &scratch, need, "overlap scratch")) != ILE_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_qv(hlm, data, inv_psd, n, sh->n_modes, sh->n_det, sh->n_points, sh->df, band.data(),
+                             msig.data(), (int64_t)band.size(), sh->n_time, sh->win_half, Q, U, V, scratch, ns, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the band lists and the scratch are released below
+    ctx_free(ctx, scratch, need);
+    if (e != hipSuccess) return dev_fail(ctx, e, "overlaps");
+    return ILE_OK;
+}

@@ -441,6 +441,14 @@ hipError_t launch_ac_reset(AcDev *st, int d, const int *dims, hipStream_t st_);
 hipError_t launch_ac_draw(int policy, const AcJob *d_jobs, const AcJob *h_jobs, int n_jobs, hipStream_t st);
 hipError_t launch_ac_update(int policy, const AcJob *d_jobs, const AcJob *h_jobs, int n_jobs, hipStream_t st);
 
+// Q, U, V of eq. (QUV) from modes and data (k_qv.hip).  h_band / h_msig:
+// host lists of the band's grid indices and their signed frequency indices.
+int qv_slices(int64_t n_band, int64_t cols, int n_time);
+size_t qv_scratch_bytes(int64_t n, int64_t n_band, int64_t cols, int n_time, int n_slices);
+hipError_t launch_qv(const void *hlm, const void *data, const double *inv_psd, int64_t n, int na, int nd, int np,
+                     double df, const int64_t *h_band, const int64_t *h_msig, int64_t n_band, int n_time,
+                     int win_half, void *Q, void *U, void *V, void *scratch, int n_slices, hipStream_t st);
+
 // Fair draws from weighted samples (k_fair.hip): scratch of
 // fair_scratch_bytes(n) bytes; lw in the policy's output type, theta in its
 // theta type.

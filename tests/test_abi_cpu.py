@@ -40,7 +40,7 @@ def test_struct_layouts_match_header(tmp_path):
                "ile_job_info": ile.ile_job_info, "ile_gmm_params": ile.ile_gmm_params,
                "ile_gmm_opts": ile.ile_gmm_opts, "ile_server_opts": ile.ile_server_opts,
                "ile_job_opts": ile.ile_job_opts, "ile_result": ile.ile_result, "ile_av_opts": ile.ile_av_opts,
-               "ile_av_state": ile.ile_av_state}
+               "ile_av_state": ile.ile_av_state, "ile_qv_shape": ile.ile_qv_shape}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ile.h"', "int main(void){"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
