@@ -299,6 +299,8 @@ def main():
                     help="the probe's step uses the time-marginalised likelihood (R = 4, 2^tmarg-log2n per point)")
     ap.add_argument("--adaptive-only", action="store_true",
                     help="run only the adaptive serving leg (--adaptive-jobs jobs) and print its summary")
+    ap.add_argument("--overlaps-only", action="store_true",
+                    help="run only the Q, U, V precompute leg (256 points) and print its summary")
     ap.add_argument("--adaptive-integrator", choices=["gmm", "av", "ac", "all"], default="all",
                     help="proposal of the adaptive serving leg(s)")
     a = ap.parse_args()
@@ -327,6 +329,9 @@ def main():
             r = run_policy(ile, torch, ctx, probs, pol, n_per, 1, 0, stream)
         print(json.dumps({"probe": True, "policy": a.probe_policy, "samples": r["N"], "kernel_ms": r["kernel_ms"],
                           "lnl_src_sha256": lnl_src_sha256()}), flush=True)
+        return
+    if a.overlaps_only:
+        print(json.dumps({"overlaps": overlaps_leg(ile, torch, ctx, stream)}), flush=True)
         return
     integrators = {"gmm": [0], "av": [1], "ac": [2], "all": [0, 1, 2]}[a.adaptive_integrator]
     leg_name = {0: "adaptive_saturated", 1: "adaptive_av_saturated", 2: "adaptive_ac_saturated"}
