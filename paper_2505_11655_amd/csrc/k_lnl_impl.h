@@ -153,20 +153,6 @@ struct LnlKernel {
     // do not fit next to the others)
     static constexpr int kG = LDS ? lds_global_dets(S, K, POL) : 0;
 
-    // sin and cos of the four geometry angles.  The FP32 policy uses the
-    // hardware sine/cosine (arguments here stay within a few turns, where its
-    // error of order 1e-6 moves lnL by at most ~rho sqrt(2 Delta) 1e-6, well
-    // inside its 1e-3 tolerance); the other policies use the library's
-    // correctly reduced functions, since their F_k / y_lm errors meet rho^2 up
-    // to SNR 400.
-    template <class T>
-    __device__ __forceinline__ static void geo_sincos(T x, T *s, T *c) {
-        if constexpr (POL == kFP32)
-            __sincosf(x, s, c);
-        else
-            dsincos(x, s, c);
-    }
-
     // Sky direction, polarisation response F_k, delays tau_k (at time tt),
     // harmonic amplitudes y_lm(iota) and the phase table e^{i j phi}.
     __device__ __forceinline__ static void geometry(const EvalJob &J, const TT al, const TT de, const TT tt,
@@ -174,13 +160,13 @@ struct LnlKernel {
                                                     TA (&tau)[K], TG (&y)[NM], TE (&Er)[NE], TE (&Ei)[NE]) {
         // ---- sky direction, polarisation basis, delays
         TS sd, cd, sh, ch;
-        geo_sincos((TS)de, &sd, &cd);
-        geo_sincos((TS)al - pick<TS>(J.gmst, J.gmstf), &sh, &ch);
+        dsincos((TS)de, &sd, &cd);
+        dsincos((TS)al - pick<TS>(J.gmst, J.gmstf), &sh, &ch);
         const TS n0 = cd * ch, n1 = cd * sh, n2 = sd;
         const TG ea0 = (TG)(-sh), ea1 = (TG)ch;
         const TG ed0 = (TG)(-sd * ch), ed1 = (TG)(-sd * sh), ed2 = (TG)cd;
         TG s2p, c2p;
-        geo_sincos((TG)2 * (TG)ps, &s2p, &c2p);
+        dsincos((TG)2 * (TG)ps, &s2p, &c2p);
 #pragma unroll
         for (int k = 0; k < K; k++) {
             const TG dxx = pick<TG>(J.D[k][0], J.Df[k][0]), dyy = pick<TG>(J.D[k][1], J.Df[k][1]);
@@ -222,7 +208,7 @@ struct LnlKernel {
             y[a] = acc;
         });
         TE sph, cph;
-        geo_sincos((TE)ph, &sph, &cph);
+        dsincos((TE)ph, &sph, &cph);
         Er[0] = (TE)1;
         Ei[0] = (TE)0;
 #pragma unroll
