@@ -255,11 +255,14 @@ def test_marginalize_parity(orc, policy):
         ile.ile_job_release(job)
 
 
-def test_eval_then_marginalize_matches_oracle(orc, recs):
+@pytest.mark.parametrize("noise_seed", [9, 1, 4])
+def test_eval_then_marginalize_matches_oracle(orc, recs, noise_seed):
     """End to end on the small workload: GPU lnL + estimator vs oracle on the
-    same samples, |d ln L| <= 1e-4 (FP32) and 1e-10 (FP64)."""
-    probs, _ = chirpgen.build_event(recs["c1"], ["H", "L"], 5, 30.0, 2.0, 20.0, noise_seed=9)
-    rng = np.random.default_rng(27)
+    same samples, |d ln L| <= 1e-4 (FP32) and 1e-10 (FP64), over three noise
+    realisations (the marginal is dominated by a few samples near the peak,
+    so its FP32 error varies with the realisation)."""
+    probs, _ = chirpgen.build_event(recs["c1"], ["H", "L"], 5, 30.0, 2.0, 20.0, noise_seed=noise_seed)
+    rng = np.random.default_rng(27 + noise_seed)
     thd = chirpgen.prior_samples(rng, 1 << 17)
     for policy, tol in ((ile.ILE_FP64, 1e-10), (ile.ILE_FP32, 1e-4), (ile.ILE_FP32_CANCEL64, 1e-4)):
         th = _np_theta(thd, policy)
