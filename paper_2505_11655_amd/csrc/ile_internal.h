@@ -449,6 +449,29 @@ hipError_t launch_qv(const void *hlm, const void *data, const double *inv_psd, i
                      double df, const int64_t *h_band, const int64_t *h_msig, int64_t n_band, int n_time,
                      int win_half, void *Q, void *U, void *V, void *scratch, int n_slices, hipStream_t st);
 
+// Order-preserving integer keys of finite values (key(a) < key(b) iff
+// a < b; -0 is taken as +0), their inverse, and the fixed-point sample mass
+// floor(exp(v - vmax) 2^40) shared by the AV threshold, the AC histograms and
+// the fair draws.
+__device__ __forceinline__ unsigned long long ord_key(float v) {
+    const uint32_t bits = __float_as_uint(v + 0.0f);
+    return (unsigned long long)((bits & 0x80000000u) ? ~bits : (bits | 0x80000000u));
+}
+__device__ __forceinline__ unsigned long long ord_key(double v) {
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v + 0.0);
+    return (bits >> 63) ? ~bits : (bits | (1ull << 63));
+}
+__device__ __forceinline__ double ord_value(unsigned long long k, int nbits) {
+    if (nbits == 32) {
+        const uint32_t kk = (uint32_t)k;
+        return (double)__uint_as_float((kk & 0x80000000u) ? (kk & 0x7FFFFFFFu) : ~kk);
+    }
+    return __longlong_as_double((long long)((k >> 63) ? (k & ~(1ull << 63)) : ~k));
+}
+__device__ __forceinline__ unsigned long long mass_fx(double v, double vmax) {
+    return (unsigned long long)floor(exp(v - vmax) * (double)(1ull << kAvMassBits));
+}
+
 // Fair draws from weighted samples (k_fair.hip): scratch of
 // fair_scratch_bytes(n) bytes; lw in the policy's output type, theta in its
 // theta type.

@@ -66,22 +66,6 @@ __device__ __forceinline__ double ac_unit(const AcDev &S, const uint32_t *w, dou
     return lr;
 }
 
-__device__ __forceinline__ unsigned long long akey(float v) {
-    const uint32_t bits = __float_as_uint(v + 0.0f);
-    return (unsigned long long)((bits & 0x80000000u) ? ~bits : (bits | 0x80000000u));
-}
-__device__ __forceinline__ unsigned long long akey(double v) {
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(v + 0.0);
-    return (bits >> 63) ? ~bits : (bits | (1ull << 63));
-}
-__device__ __forceinline__ double akey_value(unsigned long long k, int nbits) {
-    if (nbits == 32) {
-        const uint32_t kk = (uint32_t)k;
-        return (double)__uint_as_float((kk & 0x80000000u) ? (kk & 0x7FFFFFFFu) : ~kk);
-    }
-    return __longlong_as_double((long long)((k >> 63) ? (k & ~(1ull << 63)) : ~k));
-}
-
 // Cumulative sums and ln(nb pi) of marginal k from its pi (one thread).
 __device__ __forceinline__ void ac_derive(AcDev &S, int k) {
     double run = 0.0;
@@ -152,7 +136,7 @@ __global__ void __launch_bounds__(kAcThreads) k_ac_max(const AcJob *__restrict__
     AC_SAMPLES(s) {
         const TO v = lw[s];
         if (isfinite(v)) {
-            const unsigned long long k = akey(v);
+            const unsigned long long k = ord_key(v);
             km = k > km ? k : km;
             cnt += 1;
         }
@@ -178,13 +162,12 @@ __global__ void __launch_bounds__(kAcThreads) k_ac_hist(const AcJob *__restrict_
     for (int i = threadIdx.x; i < 7 * kAcBins; i += kAcThreads) h[i] = 0;
     __syncthreads();
     constexpr int nbits = sizeof(TO) * 8;
-    const double vmax = akey_value(S.key_max, nbits);
+    const double vmax = ord_value(S.key_max, nbits);
     const TO *lw = (const TO *)J.lw;
     AC_SAMPLES(s) {
         const TO v = lw[s];
         if (!isfinite(v)) continue;
-        const unsigned long long q =
-            (unsigned long long)floor(exp((double)v - vmax) * (double)(1ull << kAvMassBits));
+        const unsigned long long q = mass_fx((double)v, vmax);
         if (q == 0) continue;
         uint32_t w[16];
         ac_words(J.seed, (uint64_t)(J.first + s), J.round, w);

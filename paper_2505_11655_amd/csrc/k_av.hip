@@ -64,30 +64,6 @@ __device__ __forceinline__ const uint16_t *cur_cells(const AvBufs &b, const AvDe
     return S.cur ? b.cells[1] : b.cells[0];
 }
 
-// Order-preserving keys: key(a) < key(b) iff a < b for finite values (-0 is
-// taken as +0 first).
-__device__ __forceinline__ unsigned long long okey(float v) {
-    const uint32_t bits = __float_as_uint(v + 0.0f);
-    return (unsigned long long)((bits & 0x80000000u) ? ~bits : (bits | 0x80000000u));
-}
-__device__ __forceinline__ unsigned long long okey(double v) {
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(v + 0.0);
-    return (bits >> 63) ? ~bits : (bits | (1ull << 63));
-}
-__device__ __forceinline__ double key_value(unsigned long long k, int nbits) {
-    if (nbits == 32) {
-        const uint32_t kk = (uint32_t)k;
-        const uint32_t bits = (kk & 0x80000000u) ? (kk & 0x7FFFFFFFu) : ~kk;
-        return (double)__uint_as_float(bits);
-    }
-    const unsigned long long bits = (k >> 63) ? (k & ~(1ull << 63)) : ~k;
-    return __longlong_as_double((long long)bits);
-}
-
-__device__ __forceinline__ unsigned long long mass_fx(double v, double vmax) {
-    return (unsigned long long)floor(exp(v - vmax) * (double)(1ull << kAvMassBits));
-}
-
 __device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
     x ^= x >> 30;
     x *= 0xBF58476D1CE4E5B9ull;
@@ -177,7 +153,7 @@ __global__ void __launch_bounds__(kAvThreads) k_av_max(const AvJob *__restrict__
     AV_SAMPLES(s) {
         const TO v = lw[s];
         if (isfinite(v)) {
-            const unsigned long long k = okey(v);
+            const unsigned long long k = ord_key(v);
             km = k > km ? k : km;
             cnt += 1;
         }
@@ -222,12 +198,12 @@ __global__ void __launch_bounds__(kAvThreads) k_av_hist(const AvJob *__restrict_
     const bool top = shift + 8 == nbits;
     const unsigned long long p0 = top ? 0 : (S.prefix[0] >> (shift + 8));
     const unsigned long long p1 = top ? 0 : (S.prefix[1] >> (shift + 8));
-    const double vmax = key_value(S.key_max, nbits);
+    const double vmax = ord_value(S.key_max, nbits);
     const TO *lw = (const TO *)J.lw;
     AV_SAMPLES(s) {
         const TO v = lw[s];
         if (!isfinite(v)) continue;
-        const unsigned long long k = okey(v);
+        const unsigned long long k = ord_key(v);
         const unsigned long long hi = top ? 0 : (k >> (shift + 8));
         const int dg = (int)((k >> shift) & 255u);
         if (hi == p0) {
@@ -319,7 +295,7 @@ __global__ void __launch_bounds__(256) k_av_pick(const AvJob *__restrict__ jobs,
         const double ln_vol = S.ln_vol;
         S.thr_key = t_prefix[c];
         S.n_min = n_min;
-        S.thr = key_value(t_prefix[c], nbits);
+        S.thr = ord_value(t_prefix[c], nbits);
         S.vol_mc = exp(ln_vol) * (double)n_min / (double)J.n;
         const double ln_dv = ln_vol + 0.5 * log((double)n_min) - log((double)J.n);
         const double x = exp(-ln_dv / (double)S.d);
@@ -367,7 +343,7 @@ __global__ void __launch_bounds__(kAvThreads) k_av_insert(const AvJob *__restric
     AV_SAMPLES(s) {
         const TO v = lw[s];
         uint32_t sl = kNoSlot;
-        if (isfinite(v) && okey(v) >= thr) {
+        if (isfinite(v) && ord_key(v) >= thr) {
             uint32_t w[16];
             av_words(J.seed, (uint64_t)(J.first + s), J.round, w);
             double u[7];

@@ -21,28 +21,12 @@ constexpr int kFairPer = 16;                       // samples per thread of a ti
 constexpr int kFairTile = kFairThreads * kFairPer;
 constexpr uint32_t kFairAttempt = 5;
 
-__device__ __forceinline__ unsigned long long fkey(float v) {
-    const uint32_t bits = __float_as_uint(v + 0.0f);
-    return (unsigned long long)((bits & 0x80000000u) ? ~bits : (bits | 0x80000000u));
-}
-__device__ __forceinline__ unsigned long long fkey(double v) {
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(v + 0.0);
-    return (bits >> 63) ? ~bits : (bits | (1ull << 63));
-}
-__device__ __forceinline__ double fkey_value(unsigned long long k, int nbits) {
-    if (nbits == 32) {
-        const uint32_t kk = (uint32_t)k;
-        return (double)__uint_as_float((kk & 0x80000000u) ? (kk & 0x7FFFFFFFu) : ~kk);
-    }
-    return __longlong_as_double((long long)((k >> 63) ? (k & ~(1ull << 63)) : ~k));
-}
-
 template <class TO>
 __device__ __forceinline__ unsigned long long fmass(const TO *lw, int64_t i, int64_t n, double vmax) {
     if (i >= n) return 0ull;
     const TO v = lw[i];
     if (!isfinite(v)) return 0ull;
-    return (unsigned long long)floor(exp((double)v - vmax) * (double)(1ull << kAvMassBits));
+    return mass_fx((double)v, vmax);
 }
 
 // scratch: [0] max key, [1] total, [2 ..] per-tile sums / offsets
@@ -60,7 +44,7 @@ __global__ void __launch_bounds__(kFairThreads) k_fair_max(const TO *__restrict_
     for (int64_t i = (int64_t)blockIdx.x * kFairThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kFairThreads) {
         const TO v = lw[i];
         if (isfinite(v)) {
-            const unsigned long long k = fkey(v);
+            const unsigned long long k = ord_key(v);
             km = k > km ? k : km;
         }
     }
@@ -90,7 +74,7 @@ __global__ void __launch_bounds__(kFairThreads) k_fair_tiles(const TO *__restric
                                                              unsigned long long *scratch) {
     if (scratch[0] == 0) return;   // no finite sample
     constexpr int nbits = sizeof(TO) * 8;
-    const double vmax = fkey_value(scratch[0], nbits);
+    const double vmax = ord_value(scratch[0], nbits);
     const int64_t base = (int64_t)blockIdx.x * kFairTile + (int64_t)threadIdx.x * kFairPer;
     unsigned long long s = 0;
     for (int k = 0; k < kFairPer; k++) s += fmass(lw, base + k, n, vmax);
@@ -132,7 +116,7 @@ __global__ void __launch_bounds__(kFairThreads) k_fair_cum(const TO *__restrict_
                                                            unsigned long long *__restrict__ cum) {
     if (scratch[0] == 0) return;
     constexpr int nbits = sizeof(TO) * 8;
-    const double vmax = fkey_value(scratch[0], nbits);
+    const double vmax = ord_value(scratch[0], nbits);
     const int64_t base = (int64_t)blockIdx.x * kFairTile + (int64_t)threadIdx.x * kFairPer;
     unsigned long long q[kFairPer], s = 0;
 #pragma unroll
