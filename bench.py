@@ -123,6 +123,7 @@ def run_policy(ile, torch, ctx, probs, policy, n_per, steps, warmup, stream, tma
     wall = time.perf_counter() - t0
     out = ile.ile_marginalize_batch(jobs, [0] * J, [None] * J, ile.ILE_MARG_POOL, want=True, stream=stream)
     torch.cuda.synchronize()
+    ln_marg = [o["ln_L"] for o in out]
     del res
     for j in jobs:
         ile.ile_job_release(j)
@@ -130,7 +131,7 @@ def run_policy(ile, torch, ctx, probs, policy, n_per, steps, warmup, stream, tma
     torch.cuda.empty_cache()
     per = {k: v / steps for k, v in t_kernel.items()}
     return dict(samples_per_s=N * steps / wall, ms_per_step=1e3 * wall / steps, kernel_ms=per, N=N,
-                lnL_marg_first=out[0]["ln_L"], n_eff_first=out[0]["n_eff"])
+                lnL_marg_first=out[0]["ln_L"], n_eff_first=out[0]["n_eff"], lnL_marg=ln_marg)
 
 
 def serving_pool(per_class, seed):
@@ -345,12 +346,17 @@ def main():
         return
     log("fp32 ...")
     r32 = run_policy(ile, torch, ctx, probs, ile.ILE_FP32, n_per, a.steps, a.warmup, stream)
-    log(f"fp32 {r32}")
+    log(f"fp32 {dict((k, v) for k, v in r32.items() if k != 'lnL_marg')}")
     r64 = None
     if not a.no_fp64:
         log("fp64 ...")
         r64 = run_policy(ile, torch, ctx, probs, ile.ILE_FP64, n_per, a.steps, a.warmup, stream)
-        log(f"fp64 {r64}")
+        log(f"fp64 {dict((k, v) for k, v in r64.items() if k != 'lnL_marg')}")
+    rmx = None
+    if not a.no_fp64:
+        log("fp32 + fp64 cancellation ...")
+        rmx = run_policy(ile, torch, ctx, probs, ile.ILE_FP32_CANCEL64, n_per, a.steps, a.warmup, stream)
+        log(f"fp32c64 {dict((k, v) for k, v in rmx.items() if k != 'lnL_marg')}")
     tmarg = None
     if not a.no_tmarg:
         R = 4
@@ -362,7 +368,7 @@ def main():
                 continue
             log(f"time-marginalised {name} ...")
             rt = run_policy(ile, torch, ctx, probs, pol, 1 << a.tmarg_log2n, a.tmarg_steps, 1, stream, tmarg_R=R)
-            log(f"tmarg {name} {rt}")
+            log(f"tmarg {name} {dict((k, v) for k, v in rt.items() if k != 'lnL_marg')}")
             tmarg[name] = {"samples_per_s": rt["samples_per_s"], "nodes_per_s": rt["samples_per_s"] * nodes,
                            "ms_per_step": rt["ms_per_step"], "kernel_ms": rt["kernel_ms"],
                            "lnL_marg_first": rt["lnL_marg_first"]}
@@ -432,7 +438,15 @@ def main():
         "kernels_hbm": kernels,
         "fp64": None if r64 is None else {"value": r64["samples_per_s"], "ms_per_step": r64["ms_per_step"],
                                           "kernel_ms": r64["kernel_ms"],
-                                          "fp32_over_fp64": r32["samples_per_s"] / r64["samples_per_s"]},
+                                          "fp32_over_fp64": r32["samples_per_s"] / r64["samples_per_s"],
+                                          # the same seeds draw the same samples in every policy (rounded
+                                          # to float in the FP32 ones): the marginal ln L of each point
+                                          # compares directly
+                                          "max_abs_dlnL_marg_fp32_vs_fp64": float(np.max(np.abs(
+                                              np.array(r32["lnL_marg"]) - np.array(r64["lnL_marg"]))))},
+        "fp32_cancel64": None if rmx is None else {
+            "value": rmx["samples_per_s"], "ms_per_step": rmx["ms_per_step"], "kernel_ms": rmx["kernel_ms"],
+            "max_abs_dlnL_marg_vs_fp64": float(np.max(np.abs(np.array(rmx["lnL_marg"]) - np.array(r64["lnL_marg"]))))},
         "time_marginalised": tmarg,
         "fair_draws": fair,
         "overlaps": qv,
