@@ -75,19 +75,22 @@ def make_problems(n_points, seed):
 
 def run_policy(ile, torch, ctx, probs, policy, n_per, steps, warmup, stream, tmarg_R=None):
     """One step = draws + batched lnL (time-marginalised when tmarg_R is set) + batched estimator."""
+    # theta (and ln p - ln p_s) in the policy's theta type; lnL and lw in its
+    # output type (FP64 for the FP64 and the FP32 + FP64-cancellation policies)
     dt = torch.float64 if policy == ile.ILE_FP64 else torch.float32
+    ot = torch.float32 if policy == ile.ILE_FP32 else torch.float64
     jobs = [ile.ile_prepare(ctx, ile.ProblemHost(p, precision=policy)) for p in probs]
     J = len(jobs)
     N = J * n_per
     th = torch.empty((7, N), dtype=dt, device="cuda")
     lr = torch.empty((N,), dtype=dt, device="cuda")
-    L = torch.empty((N,), dtype=dt, device="cuda")
-    W = torch.empty((N,), dtype=dt, device="cuda")
-    esz = th.element_size()
+    L = torch.empty((N,), dtype=ot, device="cuda")
+    W = torch.empty((N,), dtype=ot, device="cuda")
+    esz, osz = th.element_size(), L.element_size()
     theta_ptrs = [th.data_ptr() + j * n_per * esz for j in range(J)]
     lr_ptrs = [lr.data_ptr() + j * n_per * esz for j in range(J)]
-    L_ptrs = [L.data_ptr() + j * n_per * esz for j in range(J)]
-    W_ptrs = [W.data_ptr() + j * n_per * esz for j in range(J)]
+    L_ptrs = [L.data_ptr() + j * n_per * osz for j in range(J)]
+    W_ptrs = [W.data_ptr() + j * n_per * osz for j in range(J)]
     ns = [n_per] * J
     lds = [N] * J
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
