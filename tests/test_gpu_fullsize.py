@@ -22,7 +22,7 @@ from tests import gpu_util as gu  # noqa: E402
 
 N_POINTS = 256
 N_PER = 1 << 20
-PNAME = {0: "fp64", 1: "fp32"}
+PNAME = {0: "fp64", 1: "fp32", 2: "fp32c64"}
 
 
 @pytest.fixture(scope="module")
@@ -43,7 +43,7 @@ def _sample_index(rng, n_per):
     return np.unique(idx[(idx >= 0) & (idx < n_per)])
 
 
-@pytest.mark.parametrize("policy", [ile.ILE_FP32, ile.ILE_FP64], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("policy", [ile.ILE_FP32, ile.ILE_FP64, ile.ILE_FP32_CANCEL64], ids=["fp32", "fp64", "fp32c64"])
 def test_fullsize_draw_and_lnL(orc, problems, policy):
     dt = gu.torch_dtype(policy)
     jobs = [ile.ile_prepare(gu.ctx(), ile.ProblemHost(p, precision=policy)) for p in problems]
