@@ -10,12 +10,12 @@
 // Q is a dense complex product [window times] x [band] . [band] x [(p, k, a)]:
 // X = 2 df conj(h) d w is formed once per band bin and column, the phases come
 // from a table e^{2 pi i r / n} at r = (m' j) mod n (exact integer phase), and
-// a register-tiled kernel (4 x 4 outputs per thread, LDS-staged tiles of
-// phases and X) accumulates over a slice of the band; slices are summed in
-// order by a second kernel (deterministic).  On this chip FP64 matrix cores
-// have the same peak as the FP64 vector ALUs, so the product stays on the
-// VALU.  U and V use the symmetries U_ba = conj(U_ab), V_ba = V_ab: only
-// a <= b is summed (one block per pair, fixed-order tree reduction).
+// the product runs on the FP64 matrix cores (16 x 16 x 4 steps, the operands
+// held in registers so that each LDS or memory read feeds several matrix
+// steps) over a slice of the band; slices are summed in order by a second
+// kernel (deterministic).  U and V use the symmetries U_ba = conj(U_ab),
+// V_ba = V_ab: only a <= b is summed (one block per pair, fixed-order tree
+// reduction).
 #include "ile_internal.h"
 
 namespace ile {
@@ -23,13 +23,10 @@ namespace ile {
 namespace {
 
 constexpr int kQvThreads = 256;
-constexpr int kQvTT = 64;     // window times per tile
-constexpr int kQvTC = 64;     // columns per tile
-constexpr int kQvMB = 16;     // band bins per LDS stage
-
-struct z2 {
-    double re, im;
-};
+constexpr int kQvTT = 64;     // window times per block tile
+constexpr int kQvNS = 4;      // 16-column tiles per wave
+constexpr int kQvTC = 32 * kQvNS;   // columns per block tile (two waves across)
+constexpr int kQvKB = 32;     // band bins per LDS stage of phases
 
 __global__ void k_qv_twiddle(double2 *__restrict__ tw, int64_t n) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
@@ -60,81 +57,154 @@ __global__ void k_qv_x(const double2 *__restrict__ hlm, const double2 *__restric
     }
 }
 
-// Partial Q of one (time tile, column tile, band slice).
+// Partial Q of one (time tile, column tile, band slice) on the FP64 matrix
+// cores.  A block of four waves covers 64 window times x 128 columns; each
+// wave a 32 x 64 sub-tile as 2 x 4 tiles of 16 x 16 (kQvNS = 4 column
+// tiles), with the real and the imaginary part of every tile in its own
+// accumulator.  One step of
+// v_mfma_f64_16x16x4f64 takes four band bins: lane l holds the A element
+// (time l % 16, bin l / 16) and the B element (bin l / 16, column l % 16),
+// and its four results are times l / 16 + 4 r (r = 0..3) of column l % 16.
+// Each complex product is four real ones, Re += Er Xr - Ei Xi,
+// Im += Er Xi + Ei Xr.  The phases of a stage of 32 bins x 64 times sit in
+// LDS (the two column waves of a time range share them), double-buffered:
+// every thread reads its eight phases of the next stage (one bin, eight
+// consecutive times: one 64-bit remainder, then r += m' mod n per time) from
+// the table before the stage's matrix steps and writes them after.  X is read by each wave straight from memory
+// (no other wave of the block uses it), one step ahead.  Blocks are numbered
+// so that the time tiles of one column tile run on one XCD and share its L2.
+typedef double qv_d4 __attribute__((ext_vector_type(4)));
+
 __global__ void __launch_bounds__(kQvThreads)
     k_qv_q(const double2 *__restrict__ X, const double2 *__restrict__ tw, const int64_t *__restrict__ msig,
-           int64_t n_band, int64_t n, int64_t cols, int n_time, int win_half, int64_t slice,
+           int64_t n_band, int64_t n, int64_t cols, int n_time, int win_half, int64_t slice, int n_tt, int n_tc,
            double2 *__restrict__ part) {
-    __shared__ z2 sE[kQvMB][kQvTT];
-    __shared__ z2 sX[kQvMB][kQvTC];
-    const int t0 = blockIdx.x * kQvTT;
-    const int64_t c0 = (int64_t)blockIdx.y * kQvTC;
-    const int64_t b_lo = (int64_t)blockIdx.z * slice;
+    __shared__ double2 sE[2][kQvKB][kQvTT];
+    const int64_t nb = gridDim.x;
+    const int64_t h = blockIdx.x;
+    const int64_t lid = nb % 8 == 0 ? (h % 8) * (nb / 8) + h / 8 : h;
+    const int tt = (int)(lid % n_tt);
+    const int tc = (int)((lid / n_tt) % n_tc);
+    const int64_t z = lid / ((int64_t)n_tt * n_tc);
+    const int64_t b_lo = z * slice;
     const int64_t b_hi = b_lo + slice < n_band ? b_lo + slice : n_band;
-    const int tid = threadIdx.x;
-    const int ti = tid & 15, tc = tid >> 4;
-    double ar[4][4], ai[4][4];
+    const int t0 = tt * kQvTT;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int wt = 32 * (wv & 1);                        // the wave's first time within the tile
+    const int64_t cw = (int64_t)tc * kQvTC + 16 * kQvNS * (wv >> 1);   // the wave's first column
+    // this thread's share of a phase stage: bin gb, times gt .. gt + 7
+    const int gb = threadIdx.x >> 3, gt = (threadIdx.x & 7) * 8;
+    static_assert(kQvThreads * 8 == kQvKB * kQvTT, "eight phases per thread and stage");
+    // m' of the thread's bin in the stage at bb; a bin past the slice gets
+    // m' = 0 and a zero phase (its X, read at a clamped index, is then
+    // multiplied by 0)
+    auto bin_m = [&](int64_t bb, double &f) -> int64_t {
+        const int64_t b = bb + gb;
+        f = b < b_hi ? 1.0 : 0.0;
+        return b < b_hi ? msig[b] : 0;
+    };
+    // The thread's eight phases for bin m', r = m' (t - win_half) mod n,
+    // then r += m' mod n per time (r stays in [0, n)).  Rows past the window
+    // need no mask: they are never stored.
+    auto phase_get = [&](int64_t m, double f, double2 (&pv)[8]) {
+        int64_t r = (m * (int64_t)(t0 + gt - win_half)) % n;
+        r = r < 0 ? r + n : r;
+        int64_t step = m % n;
+        step = step < 0 ? step + n : step;
 #pragma unroll
-    for (int r = 0; r < 4; r++)
-#pragma unroll
-        for (int s = 0; s < 4; s++) {
-            ar[r][s] = 0.0;
-            ai[r][s] = 0.0;
+        for (int q = 0; q < 8; q++) {
+            const double2 w = tw[r];
+            pv[q] = make_double2(w.x * f, w.y * f);
+            r += step;
+            r = r >= n ? r - n : r;
         }
-    for (int64_t bb = b_lo; bb < b_hi; bb += kQvMB) {
-        // stage: 16 band bins x 64 times of phases, 16 x 64 of X
-        for (int e = tid; e < kQvMB * kQvTT; e += kQvThreads) {
-            const int lb = e / kQvTT, lt = e % kQvTT;
-            const int64_t b = bb + lb;
-            const int t = t0 + lt;
-            z2 v{0.0, 0.0};
-            if (b < b_hi && t < n_time) {
-                const int64_t j = (int64_t)(t - win_half);
-                int64_t r = (msig[b] * j) % n;
-                r = r < 0 ? r + n : r;
-                const double2 w = tw[r];
-                v = z2{w.x, w.y};
+    };
+    qv_d4 accR[2][kQvNS], accI[2][kQvNS];
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int s = 0; s < kQvNS; s++) {
+            accR[r][s] = qv_d4{0.0, 0.0, 0.0, 0.0};
+            accI[r][s] = qv_d4{0.0, 0.0, 0.0, 0.0};
+        }
+    // X of one step of four bins: the lane's bin b4 + lk, its columns.
+    // Indices past the slice or the columns are clamped to a valid element
+    // (unconditional loads): such a bin has a zero phase, such a column is
+    // never stored.
+    auto load_x = [&](int64_t b4, double2 (&x)[kQvNS]) {
+        const int64_t b = b4 + lk;
+        const int64_t bc = b < b_hi ? b : b_hi - 1;
+#pragma unroll
+        for (int s = 0; s < kQvNS; s++) {
+            const int64_t c = cw + 16 * s + li;
+            const double2 w = X[bc * cols + (c < cols ? c : cols - 1)];
+            x[s] = make_double2(w.x, w.y);
+        }
+    };
+    {
+        double2 pv[8];
+        double f;
+        const int64_t m = bin_m(b_lo, f);
+        phase_get(m, f, pv);
+#pragma unroll
+        for (int q = 0; q < 8; q++) sE[0][gb][gt + q] = pv[q];
+    }
+    double f_next;
+    int64_t m_next = bin_m(b_lo + kQvKB, f_next);   // read one stage before it is used
+    double2 xc[kQvNS];
+    load_x(b_lo, xc);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t bb = b_lo; bb < b_hi; bb += kQvKB) {
+        const int nk = b_hi - bb < kQvKB ? (int)(b_hi - bb) : kQvKB;
+        const bool more = bb + kQvKB < b_hi;
+        double2 pv[8];
+        for (int ks = 0; ks < nk; ks += 4) {
+            // the next step's X is in flight while this step's products run
+            double2 xn[kQvNS];
+            load_x(bb + ks + 4, xn);
+            // the next stage's phases: read during the first step, written
+            // after the last
+            if (more && ks == 0) {
+                phase_get(m_next, f_next, pv);
+                m_next = bin_m(bb + 2 * kQvKB, f_next);
             }
-            sE[lb][lt] = v;
-        }
-        for (int e = tid; e < kQvMB * kQvTC; e += kQvThreads) {
-            const int lb = e / kQvTC, lc = e % kQvTC;
-            const int64_t b = bb + lb;
-            const int64_t c = c0 + lc;
-            z2 v{0.0, 0.0};
-            if (b < b_hi && c < cols) {
-                const double2 x = X[b * cols + c];
-                v = z2{x.x, x.y};
-            }
-            sX[lb][lc] = v;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int lb = 0; lb < kQvMB; lb++) {
-            z2 e[4], x[4];
+            double2 e[2];
 #pragma unroll
-            for (int r = 0; r < 4; r++) e[r] = sE[lb][ti + 16 * r];
+            for (int r = 0; r < 2; r++) e[r] = sE[buf][ks + lk][wt + 16 * r + li];
 #pragma unroll
-            for (int s = 0; s < 4; s++) x[s] = sX[lb][tc + 16 * s];
+            for (int r = 0; r < 2; r++) {
+                const double ni = -e[r].y;
 #pragma unroll
-            for (int r = 0; r < 4; r++)
-#pragma unroll
-                for (int s = 0; s < 4; s++) {
-                    ar[r][s] = fma(e[r].re, x[s].re, fma(-e[r].im, x[s].im, ar[r][s]));
-                    ai[r][s] = fma(e[r].re, x[s].im, fma(e[r].im, x[s].re, ai[r][s]));
+                for (int s = 0; s < kQvNS; s++) {
+                    accR[r][s] = __builtin_amdgcn_mfma_f64_16x16x4f64(e[r].x, xc[s].x, accR[r][s], 0, 0, 0);
+                    accR[r][s] = __builtin_amdgcn_mfma_f64_16x16x4f64(ni, xc[s].y, accR[r][s], 0, 0, 0);
+                    accI[r][s] = __builtin_amdgcn_mfma_f64_16x16x4f64(e[r].x, xc[s].y, accI[r][s], 0, 0, 0);
+                    accI[r][s] = __builtin_amdgcn_mfma_f64_16x16x4f64(e[r].y, xc[s].x, accI[r][s], 0, 0, 0);
                 }
+            }
+#pragma unroll
+            for (int s = 0; s < kQvNS; s++) xc[s] = xn[s];
+        }
+        if (more) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) sE[buf ^ 1][gb][gt + q] = pv[q];
         }
         __syncthreads();
+        buf ^= 1;
     }
 #pragma unroll
-    for (int r = 0; r < 4; r++)
+    for (int r = 0; r < 2; r++)
 #pragma unroll
-        for (int s = 0; s < 4; s++) {
-            const int t = t0 + ti + 16 * r;
-            const int64_t c = c0 + tc + 16 * s;
-            if (t < n_time && c < cols)
-                part[((int64_t)blockIdx.z * cols + c) * n_time + t] = make_double2(ar[r][s], ai[r][s]);
-        }
+        for (int s = 0; s < kQvNS; s++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int t = t0 + wt + 16 * r + lk + 4 * q;
+                const int64_t c = cw + 16 * s + li;
+                if (t < n_time && c < cols)
+                    part[(z * cols + c) * n_time + t] = make_double2(accR[r][s][q], accI[r][s][q]);
+            }
 }
 
 // Q[col][t] = sum over slices in order.
@@ -210,12 +280,27 @@ size_t qv_scratch_bytes(int64_t n, int64_t n_band, int64_t cols, int n_time, int
            al((size_t)n_slices * cols * n_time * 16);
 }
 
+// Band slices per call: at least two rounds of resident blocks (256 CUs x 2
+// blocks of k_qv_q), at least 128 bins per slice, and the fewest slices whose
+// last round is at least 90 % full.
 int qv_slices(int64_t n_band, int64_t cols, int n_time) {
+    constexpr int64_t kResident = 256 * 2;
     const int64_t tiles = (int64_t)((n_time + kQvTT - 1) / kQvTT) * ((cols + kQvTC - 1) / kQvTC);
-    int64_t s = (1024 + tiles - 1) / tiles;
-    const int64_t smax = (n_band + 63) / 64;
-    s = s > smax ? smax : s;
-    return (int)(s < 1 ? 1 : s);
+    int64_t smax = (n_band + 127) / 128;
+    smax = smax < 1 ? 1 : smax;
+    int64_t best = 1;
+    double best_eff = -1.0;
+    for (int64_t s = 1; s <= smax && s <= 64; s++) {
+        const int64_t blocks = tiles * s;
+        const int64_t rounds = (blocks + kResident - 1) / kResident;
+        const double eff = (double)blocks / (double)(rounds * kResident);
+        if (blocks >= 2 * kResident && eff >= 0.9) return (int)s;
+        if (eff > best_eff + 1e-9) {
+            best_eff = eff;
+            best = s;
+        }
+    }
+    return (int)best;
 }
 
 hipError_t launch_qv(const void *hlm, const void *data, const double *inv_psd, int64_t n, int na, int nd, int np,
@@ -240,11 +325,12 @@ hipError_t launch_qv(const void *hlm, const void *data, const double *inv_psd, i
     const int64_t xe = n_band * cols;
     hipLaunchKernelGGL(k_qv_x, dim3((unsigned)std::min<int64_t>((xe + 255) / 256, 65536)), dim3(256), 0, st,
                        (const double2 *)hlm, (const double2 *)data, inv_psd, band, n_band, n, na, nd, np, df, X);
-    const int64_t slice = ((n_band + n_slices - 1) / n_slices + kQvMB - 1) / kQvMB * kQvMB;
+    const int64_t slice = ((n_band + n_slices - 1) / n_slices + kQvKB - 1) / kQvKB * kQvKB;
     const int ns = (int)((n_band + slice - 1) / slice);
-    dim3 grid((unsigned)((n_time + kQvTT - 1) / kQvTT), (unsigned)((cols + kQvTC - 1) / kQvTC), (unsigned)ns);
-    hipLaunchKernelGGL(k_qv_q, grid, dim3(kQvThreads), 0, st, X, tw, msig, n_band, n, cols, n_time, win_half, slice,
-                       part);
+    const int n_tt = (n_time + kQvTT - 1) / kQvTT;
+    const int n_tc = (int)((cols + kQvTC - 1) / kQvTC);
+    hipLaunchKernelGGL(k_qv_q, dim3((unsigned)((int64_t)n_tt * n_tc * ns)), dim3(kQvThreads), 0, st, X, tw, msig,
+                       n_band, n, cols, n_time, win_half, slice, n_tt, n_tc, part);
     const int64_t qe = cols * n_time;
     hipLaunchKernelGGL(k_qv_reduce, dim3((unsigned)std::min<int64_t>((qe + 255) / 256, 65536)), dim3(256), 0, st,
                        part, ns, cols, n_time, (double2 *)Q);
