@@ -328,7 +328,8 @@ ile_status ile_ac_get(ile_job *job, int32_t *n_dim, int32_t *dims, double *pi, i
  * index in FFT order: 0..n/2-1, then -n/2..-1), tau_i = (i - win_half)/(n df)
  * with the phase taken exactly as 2 pi ((m' (i - win_half)) mod n)/n.  U is
  * formed for a <= b and mirrored (U_ba = conj U_ab, V_ba = V_ab).  The Q and
- * U, V layouts are those ile_problem takes, one block per point. */
+ * U, V layouts are those ile_problem takes, one block per point.  At most
+ * 1000 modes (ILE_E_INVALID beyond). */
 typedef struct {
     int32_t n_points, n_modes, n_det;
     int64_t n_freq;           /* grid length n */

@@ -148,7 +148,7 @@ extern "C" ile_status ile_overlaps(ile_ctx *ctx, const ile_qv_shape *sh, const v
     ile_status s = ctx_check(ctx);
     if (s != ILE_OK) return s;
     if (sh->n_points < 1 || sh->n_modes < 1 || sh->n_det < 1 || sh->n_freq < 4 || sh->n_time < 1 ||
-        sh->n_time > sh->n_freq || !(sh->df > 0) || !(sh->f_hi >= sh->f_lo) || sh->f_lo < 0)
+        sh->n_time > sh->n_freq || sh->n_modes > 1000 || !(sh->df > 0) || !(sh->f_hi >= sh->f_lo) || sh->f_lo < 0)
         return set_err(ILE_E_INVALID, "bad overlap shape");
     if (!hlm || !data || !Q || !U || !V) return set_err(ILE_E_INVALID, "null array");
     const int64_t n = sh->n_freq;

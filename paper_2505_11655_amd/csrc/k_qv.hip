@@ -37,23 +37,34 @@ __global__ void k_qv_twiddle(double2 *__restrict__ tw, int64_t n) {
 }
 
 // X[b][col] = 2 df conj(h_pa(f_b)) d_k(f_b) w_k(f_b), col = (p * nd + k) * na + a.
-__global__ void k_qv_x(const double2 *__restrict__ hlm, const double2 *__restrict__ data,
-                       const double *__restrict__ inv_psd, const int64_t *__restrict__ band, int64_t n_band,
-                       int64_t n, int na, int nd, int np, double df, double2 *__restrict__ X) {
+// One column per thread (its (p, k, a) decoded once), kQvXRun consecutive
+// bins per block row: the writes are coalesced along the columns, and each
+// cache line of a mode row serves several bins.
+constexpr int kQvXRun = 16;
+__global__ void __launch_bounds__(kQvThreads)
+    k_qv_x(const double2 *__restrict__ hlm, const double2 *__restrict__ data, const double *__restrict__ inv_psd,
+           const int64_t *__restrict__ band, int64_t n_band, int64_t n, int na, int nd, int np, double df,
+           double2 *__restrict__ X) {
     const int64_t cols = (int64_t)np * nd * na;
-    const int64_t total = n_band * cols;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = e / cols, col = e % cols;
-        const int a = (int)(col % na);
-        const int k = (int)((col / na) % nd);
-        const int64_t p = col / ((int64_t)na * nd);
-        const int64_t m = band[b];
-        const double2 h = hlm[(p * na + a) * n + m];
-        const double2 d = data[(int64_t)k * n + m];
-        const double w = 2.0 * df * (inv_psd ? inv_psd[(int64_t)k * n + m] : 1.0);
-        // conj(h) d
-        const double re = h.x * d.x + h.y * d.y, im = h.x * d.y - h.y * d.x;
-        X[e] = make_double2(re * w, im * w);
+    const int64_t col = (int64_t)blockIdx.x * kQvThreads + threadIdx.x;
+    if (col >= cols) return;
+    const int a = (int)(col % na);
+    const int k = (int)((col / na) % nd);
+    const int64_t p = col / ((int64_t)na * nd);
+    const double2 *h = hlm + (p * na + a) * n;
+    const double2 *dk = data + (int64_t)k * n;
+    const double *wk = inv_psd ? inv_psd + (int64_t)k * n : nullptr;
+    for (int64_t b0 = (int64_t)blockIdx.y * kQvXRun; b0 < n_band; b0 += (int64_t)gridDim.y * kQvXRun) {
+        const int64_t b1 = b0 + kQvXRun < n_band ? b0 + kQvXRun : n_band;
+        for (int64_t b = b0; b < b1; b++) {
+            const int64_t m = band[b];
+            const double2 hv = h[m];
+            const double2 d = dk[m];
+            const double w = 2.0 * df * (wk ? wk[m] : 1.0);
+            // conj(h) d
+            const double re = hv.x * d.x + hv.y * d.y, im = hv.x * d.y - hv.y * d.x;
+            X[b * cols + col] = make_double2(re * w, im * w);
+        }
     }
 }
 
@@ -222,53 +233,136 @@ __global__ void k_qv_reduce(const double2 *__restrict__ part, int n_slices, int6
     }
 }
 
-// U and V of one (point, detector, pair a <= b): a fixed-order tree reduction.
-__global__ void __launch_bounds__(kQvThreads)
-    k_qv_uv(const double2 *__restrict__ hlm, const double *__restrict__ inv_psd, const int64_t *__restrict__ band,
-            int64_t n_band, int64_t n, int na, int nd, double df, double2 *__restrict__ U, double2 *__restrict__ V) {
-    const int npair = na * (na + 1) / 2;
-    const int pk = blockIdx.x / npair;     // p * nd + k
-    int q = blockIdx.x % npair;
-    int a = 0;
+// U and V: a block per (point, band slice, detector group of up to kUvDet,
+// pair group of up to kQvThreads pairs a <= b).  The block stages chunks of
+// its band slice in LDS: h_a(f) and h_a(-f) of every mode and w_k(f) of its
+// detectors.  Each thread accumulates one pair for all the group's detectors
+// over every G-th bin of a chunk (G bin lanes per pair); the lanes are summed
+// in lane order, and the slices in slice order by k_qv_uv_sum (with one slice
+// the block writes U and V itself).  Deterministic for a given launch shape.
+constexpr int kUvDet = 4;
+constexpr int kUvChunk = 32;   // bins per LDS chunk (fewer for many modes)
+
+__device__ __forceinline__ void uv_pair(int q, int na, int &a, int &b) {
+    a = 0;
     while (q >= na - a) {
         q -= na - a;
         a++;
     }
-    const int b = a + q;
-    const int k = pk % nd;
-    const int64_t p = pk / nd;
-    const double2 *ha = hlm + (p * na + a) * n;
-    const double2 *hb = hlm + (p * na + b) * n;
-    double ur = 0.0, ui = 0.0, vr = 0.0, vi = 0.0;
-    for (int64_t e = threadIdx.x; e < n_band; e += kQvThreads) {
-        const int64_t m = band[e];
-        const int64_t mn = m == 0 ? 0 : n - m;
-        const double w = inv_psd ? inv_psd[(int64_t)k * n + m] : 1.0;
-        const double2 x = ha[m], y = hb[m], z = ha[mn];
-        ur += w * (x.x * y.x + x.y * y.y);
-        ui += w * (x.x * y.y - x.y * y.x);
-        vr += w * (z.x * y.x - z.y * y.y);
-        vi += w * (z.x * y.y + z.y * y.x);
-    }
-    __shared__ double s[4][kQvThreads];
-    s[0][threadIdx.x] = ur;
-    s[1][threadIdx.x] = ui;
-    s[2][threadIdx.x] = vr;
-    s[3][threadIdx.x] = vi;
-    __syncthreads();
-    for (int o = kQvThreads / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o)
-            for (int c = 0; c < 4; c++) s[c][threadIdx.x] += s[c][threadIdx.x + o];
+    b = a + q;
+}
+
+__device__ __forceinline__ void uv_store(double2 *U, double2 *V, int64_t base, int na, int a, int b, double f,
+                                         const double (&s)[4]) {
+    const double ui = a == b ? 0.0 : f * s[1];   // the diagonal <h_a|h_a> is real
+    U[base + a * na + b] = make_double2(f * s[0], ui);
+    U[base + b * na + a] = make_double2(f * s[0], -ui);
+    V[base + a * na + b] = make_double2(f * s[2], f * s[3]);
+    V[base + b * na + a] = make_double2(f * s[2], f * s[3]);
+}
+
+__global__ void __launch_bounds__(kQvThreads)
+    k_qv_uv(const double2 *__restrict__ hlm, const double *__restrict__ inv_psd, const int64_t *__restrict__ band,
+            int64_t n_band, int64_t n, int na, int nd, double df, int64_t slice, int n_sl, int cb, int n_dg,
+            double *__restrict__ partial, double2 *__restrict__ U, double2 *__restrict__ V) {
+    extern __shared__ double uv_lds[];
+    const int npair = na * (na + 1) / 2;
+    const int64_t p = blockIdx.x;
+    const int sl = blockIdx.y;
+    const int dg = (int)(blockIdx.z % n_dg), pg = (int)(blockIdx.z / n_dg);
+    const int k0 = dg * kUvDet;
+    const int nk = nd - k0 < kUvDet ? nd - k0 : kUvDet;
+    const int pair0 = pg * kQvThreads;
+    const int np_here = npair - pair0 < kQvThreads ? npair - pair0 : kQvThreads;
+    const int G = kQvThreads / np_here;
+    const int tid = threadIdx.x;
+    const bool active = tid < np_here * G;
+    const int lp = tid % np_here, g = tid / np_here;
+    int a = 0, b = 0;
+    uv_pair(pair0 + lp, na, a, b);
+    double2 *sH = (double2 *)uv_lds;            // [na][cb]  h_a(f)
+    double2 *sM = sH + (size_t)na * cb;         // [na][cb]  h_a(-f)
+    double *sW = (double *)(sM + (size_t)na * cb);   // [kUvDet][cb]
+    double acc[kUvDet][4];
+#pragma unroll
+    for (int kk = 0; kk < kUvDet; kk++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) acc[kk][c] = 0.0;
+    const int64_t e_lo = (int64_t)sl * slice;
+    const int64_t e_hi = e_lo + slice < n_band ? e_lo + slice : n_band;
+    for (int64_t eb = e_lo; eb < e_hi; eb += cb) {
+        const int ncb = e_hi - eb < cb ? (int)(e_hi - eb) : cb;
         __syncthreads();
+        for (int s = tid; s < na * ncb; s += kQvThreads) {
+            const int am = s / ncb, c = s % ncb;
+            const int64_t m = band[eb + c];
+            const int64_t mn = m == 0 ? 0 : n - m;
+            const double2 *h = hlm + (p * na + am) * n;
+            sH[am * cb + c] = h[m];
+            sM[am * cb + c] = h[mn];
+        }
+        for (int s = tid; s < nk * ncb; s += kQvThreads) {
+            const int kk = s / ncb, c = s % ncb;
+            sW[kk * cb + c] = inv_psd ? inv_psd[(int64_t)(k0 + kk) * n + band[eb + c]] : 1.0;
+        }
+        __syncthreads();
+        if (active) {
+            for (int c = g; c < ncb; c += G) {
+                const double2 x = sH[a * cb + c], y = sH[b * cb + c], z = sM[a * cb + c];
+                const double p0 = x.x * y.x + x.y * y.y, p1 = x.x * y.y - x.y * y.x;   // conj(h_a) h_b
+                const double p2 = z.x * y.x - z.y * y.y, p3 = z.x * y.y + z.y * y.x;   // h_a(-f) h_b
+#pragma unroll
+                for (int kk = 0; kk < kUvDet; kk++) {
+                    if (kk < nk) {
+                        const double w = sW[kk * cb + c];
+                        acc[kk][0] += w * p0;
+                        acc[kk][1] += w * p1;
+                        acc[kk][2] += w * p2;
+                        acc[kk][3] += w * p3;
+                    }
+                }
+            }
+        }
     }
-    if (threadIdx.x == 0) {
-        const double f = 2.0 * df;
-        const int64_t base = (int64_t)pk * na * na;
-        const double ui_ab = a == b ? 0.0 : f * s[1][0];   // the diagonal <h_a|h_a> is real
-        U[base + a * na + b] = make_double2(f * s[0][0], ui_ab);
-        U[base + b * na + a] = make_double2(f * s[0][0], -ui_ab);
-        V[base + a * na + b] = make_double2(f * s[2][0], f * s[3][0]);
-        V[base + b * na + a] = make_double2(f * s[2][0], f * s[3][0]);
+    // bin lanes summed in lane order
+    __syncthreads();
+    double *red = uv_lds;   // [kQvThreads][kUvDet * 4]
+#pragma unroll
+    for (int kk = 0; kk < kUvDet; kk++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) red[tid * kUvDet * 4 + kk * 4 + c] = acc[kk][c];
+    __syncthreads();
+    if (!active || g != 0) return;
+    for (int kk = 0; kk < nk; kk++) {
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int gg = 0; gg < G; gg++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) s[c] += red[(gg * np_here + lp) * kUvDet * 4 + kk * 4 + c];
+        const int64_t pk = p * nd + k0 + kk;
+        if (n_sl == 1) {
+            uv_store(U, V, pk * na * na, na, a, b, 2.0 * df, s);
+        } else {
+            double *o = partial + ((pk * npair + pair0 + lp) * n_sl + sl) * 4;
+#pragma unroll
+            for (int c = 0; c < 4; c++) o[c] = s[c];
+        }
+    }
+}
+
+// U and V from the slice partials, summed in slice order.
+__global__ void k_qv_uv_sum(const double *__restrict__ partial, int64_t n_pk, int na, int n_sl, double df,
+                            double2 *__restrict__ U, double2 *__restrict__ V) {
+    const int npair = na * (na + 1) / 2;
+    const int64_t total = n_pk * npair;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pk = e / npair;
+        int a, b;
+        uv_pair((int)(e % npair), na, a, b);
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int sl = 0; sl < n_sl; sl++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) s[c] += partial[(e * n_sl + sl) * 4 + c];
+        uv_store(U, V, pk * na * na, na, a, b, 2.0 * df, s);
     }
 }
 
@@ -322,9 +416,10 @@ hipError_t launch_qv(const void *hlm, const void *data, const double *inv_psd, i
     if (e == hipSuccess) e = hipMemcpyAsync(msig, h_msig, (size_t)n_band * 8, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_qv_twiddle, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tw, n);
-    const int64_t xe = n_band * cols;
-    hipLaunchKernelGGL(k_qv_x, dim3((unsigned)std::min<int64_t>((xe + 255) / 256, 65536)), dim3(256), 0, st,
-                       (const double2 *)hlm, (const double2 *)data, inv_psd, band, n_band, n, na, nd, np, df, X);
+    const int64_t xruns = std::min<int64_t>((n_band + kQvXRun - 1) / kQvXRun, 65535);
+    hipLaunchKernelGGL(k_qv_x, dim3((unsigned)((cols + kQvThreads - 1) / kQvThreads), (unsigned)xruns),
+                       dim3(kQvThreads), 0, st, (const double2 *)hlm, (const double2 *)data, inv_psd, band, n_band, n,
+                       na, nd, np, df, X);
     const int64_t slice = ((n_band + n_slices - 1) / n_slices + kQvKB - 1) / kQvKB * kQvKB;
     const int ns = (int)((n_band + slice - 1) / slice);
     const int n_tt = (n_time + kQvTT - 1) / kQvTT;
@@ -334,9 +429,28 @@ hipError_t launch_qv(const void *hlm, const void *data, const double *inv_psd, i
     const int64_t qe = cols * n_time;
     hipLaunchKernelGGL(k_qv_reduce, dim3((unsigned)std::min<int64_t>((qe + 255) / 256, 65536)), dim3(256), 0, st,
                        part, ns, cols, n_time, (double2 *)Q);
+    // U, V: band slices so that the grid has about 1024 blocks, the slice
+    // partials held in the Q partial buffer (free once k_qv_reduce has run)
     const int npair = na * (na + 1) / 2;
-    hipLaunchKernelGGL(k_qv_uv, dim3((unsigned)((int64_t)np * nd * npair)), dim3(kQvThreads), 0, st,
-                       (const double2 *)hlm, inv_psd, band, n_band, n, na, nd, df, (double2 *)U, (double2 *)V);
+    const int n_dg = (nd + kUvDet - 1) / kUvDet;
+    const int n_pg = (npair + kQvThreads - 1) / kQvThreads;
+    const int cb = (int)std::max<int64_t>(1, std::min<int64_t>(kUvChunk, 32768 / ((int64_t)na * 32 + kUvDet * 8)));
+    const int64_t blocks1 = (int64_t)np * n_dg * n_pg;
+    int64_t n_sl = std::max<int64_t>(1, std::min<int64_t>((1024 + blocks1 - 1) / blocks1, (n_band + 4 * cb - 1) / (4 * cb)));
+    const int64_t part_bytes = (int64_t)ns * cols * n_time * 16;
+    const int64_t per_sl = (int64_t)np * nd * npair * 32;
+    n_sl = std::min<int64_t>(n_sl, std::max<int64_t>(1, part_bytes / per_sl));
+    const int64_t uslice = (n_band + n_sl - 1) / n_sl;
+    n_sl = (n_band + uslice - 1) / uslice;
+    const size_t lds = std::max<size_t>((size_t)cb * ((size_t)na * 32 + kUvDet * 8), (size_t)kQvThreads * kUvDet * 4 * 8);
+    hipLaunchKernelGGL(k_qv_uv, dim3((unsigned)np, (unsigned)n_sl, (unsigned)(n_dg * n_pg)), dim3(kQvThreads), lds, st,
+                       (const double2 *)hlm, inv_psd, band, n_band, n, na, nd, df, uslice, (int)n_sl, cb, n_dg,
+                       (double *)part, (double2 *)U, (double2 *)V);
+    if (n_sl > 1) {
+        const int64_t ue = (int64_t)np * nd * npair;
+        hipLaunchKernelGGL(k_qv_uv_sum, dim3((unsigned)std::min<int64_t>((ue + 255) / 256, 65536)), dim3(256), 0, st,
+                           (const double *)part, (int64_t)np * nd, na, (int)n_sl, df, (double2 *)U, (double2 *)V);
+    }
     return hipGetLastError();
 }
 

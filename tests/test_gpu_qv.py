@@ -107,3 +107,37 @@ def test_overlaps_feed_the_likelihood(orc):
     fin = np.isfinite(ref)
     assert np.array_equal(fin, np.isfinite(L))
     assert np.allclose(L[fin], ref[fin], rtol=1e-9, atol=1e-9)
+
+
+def test_overlaps_one_slice_and_short_window(orc):
+    """A one-sample window over a short band (102 bins, fewer than one band
+    slice): U and V come from a single slice written directly, Q from a
+    single time tile."""
+    rng = np.random.default_rng(133)
+    n, df = 200, 1.0
+    hl = rng.normal(size=(2, 4, n)) + 1j * rng.normal(size=(2, 4, n))
+    data = rng.normal(size=(2, n)) + 1j * rng.normal(size=(2, n))
+    Qg, Ug, Vg = _gpu(hl, data, df, 10.0, 60.0, 1, 0)
+    for p in range(2):
+        Qo, Uo, Vo = orc.overlaps_qv(hl[p], data, None, df, 10.0, 60.0, 1, 0)
+        _close(Qg[p], Qo)
+        _close(Ug[p], Uo)
+        _close(Vg[p], Vo)
+
+
+def test_overlaps_many_modes_and_detectors(orc):
+    """24 modes (300 pairs: two pair groups of U, V blocks) and 5 detectors
+    (two detector groups) with a PSD weight; several band slices."""
+    rng = np.random.default_rng(134)
+    n, df = 1024, 2.0
+    hl = rng.normal(size=(24, n)) + 1j * rng.normal(size=(24, n))
+    data = rng.normal(size=(5, n)) + 1j * rng.normal(size=(5, n))
+    f = np.fft.fftfreq(n, 1.0 / (n * df))
+    w = 1.0 / (1.0 + (np.abs(f)[None, :] / 300.0) ** 2) * rng.uniform(0.5, 1.5, (5, 1))
+    Qg, Ug, Vg = _gpu(hl, data, df, 20.0, 900.0, 33, 16, inv_psd=w)
+    Qo, Uo, Vo = orc.overlaps_qv(hl, data, w, df, 20.0, 900.0, 33, 16)
+    _close(Qg[0], Qo)
+    _close(Ug[0], Uo)
+    _close(Vg[0], Vo)
+    assert np.array_equal(Ug[0], np.conj(np.transpose(Ug[0], (0, 2, 1))))
+    assert np.array_equal(Vg[0], np.transpose(Vg[0], (0, 2, 1)))
