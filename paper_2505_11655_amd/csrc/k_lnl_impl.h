@@ -252,10 +252,12 @@ struct LnlKernel {
             });
 #pragma unroll
             for (int k = 0; k < K; k++) {
-                if constexpr (g == 0)
+                if constexpr (g == 0) {
                     uk[k] += Ar[k];
-                else
-                    uk[k] += (TA)Er[g] * Ar[k] - (TA)Ei[g] * Ai[k];
+                } else {
+                    uk[k] = fma((TA)Er[g], Ar[k], uk[k]);
+                    uk[k] = fma(-(TA)Ei[g], Ai[k], uk[k]);
+                }
             }
         });
         static_for<0, 4 * LM + 1>([&](auto G_) {
@@ -284,8 +286,10 @@ struct LnlKernel {
                 const TA ei = (sm < 0) ? (TA)Ei[-sm] : -(TA)Ei[sm];
 #pragma unroll
                 for (int k = 0; k < K; k++) {
-                    vr[k] += er * Br[k] - ei * Bi[k];
-                    vi[k] += er * Bi[k] + ei * Br[k];
+                    vr[k] = fma(er, Br[k], vr[k]);
+                    vr[k] = fma(-ei, Bi[k], vr[k]);
+                    vi[k] = fma(er, Bi[k], vi[k]);
+                    vi[k] = fma(ei, Br[k], vi[k]);
                 }
             }
         });
@@ -365,10 +369,15 @@ struct LnlKernel {
                     const TA er = (TA)Er[m < 0 ? -m : m];
                     const TA ei = (m < 0) ? -(TA)Ei[-m] : (TA)Ei[m];
                     const TA zr = (TA)y[a] * er, zi = (TA)y[a] * ei;
-                    ar += zr * qr - zi * qi;
-                    ai += zr * qi + zi * qr;
+                    // explicit FMA chains: ar + (zr qr - zi qi) written as
+                    // such costs a multiply, an FMA and an add
+                    ar = fma(zr, qr, ar);
+                    ar = fma(-zi, qi, ar);
+                    ai = fma(zr, qi, ai);
+                    ai = fma(zi, qr, ai);
                 });
-                T1 += (TA)Fr[k] * ar + (TA)Fi[k] * ai;
+                T1 = fma((TA)Fr[k], ar, T1);
+                T1 = fma((TA)Fi[k], ai, T1);
             }
 
             const TA T2 = quad_T2(Fr, Fi, y, Er, Ei, Ut, Vt);
