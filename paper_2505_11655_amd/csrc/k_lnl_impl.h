@@ -219,7 +219,12 @@ struct LnlKernel {
     }
 
     // The quadratic form T2 from the pair tables (read through the scalar cache).
+    // CHAIN: the phase rotations of the pair groups as explicit FMA chains
+    // (two instructions where acc + (x y - z w) costs three); off for the
+    // time-marginalised kernel, whose register budget the chained form
+    // exceeds (it then spills).
     typedef __attribute__((address_space(4))) const cpx<TA> ccpx;
+    template <bool CHAIN = true>
     __device__ __forceinline__ static TA quad_T2(const TG (&Fr)[K], const TG (&Fi)[K], const TG (&y)[NM],
                                                  const TE (&Er)[NE], const TE (&Ei)[NE], ccpx *Ut, ccpx *Vt) {
         // ---- T2 = sum_k |F_k|^2 Y^+ U_k Y + Re(F_k^2 Y^T V_k Y)
@@ -254,9 +259,11 @@ struct LnlKernel {
             for (int k = 0; k < K; k++) {
                 if constexpr (g == 0) {
                     uk[k] += Ar[k];
-                } else {
+                } else if constexpr (CHAIN) {
                     uk[k] = fma((TA)Er[g], Ar[k], uk[k]);
                     uk[k] = fma(-(TA)Ei[g], Ai[k], uk[k]);
+                } else {
+                    uk[k] += (TA)Er[g] * Ar[k] - (TA)Ei[g] * Ai[k];
                 }
             }
         });
@@ -286,10 +293,15 @@ struct LnlKernel {
                 const TA ei = (sm < 0) ? (TA)Ei[-sm] : -(TA)Ei[sm];
 #pragma unroll
                 for (int k = 0; k < K; k++) {
-                    vr[k] = fma(er, Br[k], vr[k]);
-                    vr[k] = fma(-ei, Bi[k], vr[k]);
-                    vi[k] = fma(er, Bi[k], vi[k]);
-                    vi[k] = fma(ei, Br[k], vi[k]);
+                    if constexpr (CHAIN) {
+                        vr[k] = fma(er, Br[k], vr[k]);
+                        vr[k] = fma(-ei, Bi[k], vr[k]);
+                        vi[k] = fma(er, Bi[k], vi[k]);
+                        vi[k] = fma(ei, Br[k], vi[k]);
+                    } else {
+                        vr[k] += er * Br[k] - ei * Bi[k];
+                        vi[k] += er * Bi[k] + ei * Br[k];
+                    }
                 }
             }
         });

@@ -85,7 +85,7 @@ struct TmargKernel {
             // temporaries never coexist with the loop state; FP64 (one wave per
             // SIMD, registers to spare): before it, like the pointwise kernel.
             TA T2 = (TA)0;
-            if constexpr (kT2First) T2 = LK::quad_T2(Fr, Fi, y, Er, Ei, Ut, Vt);
+            if constexpr (kT2First) T2 = LK::template quad_T2<false>(Fr, Fi, y, Er, Ei, Ut, Vt);
 
             // c_k,a = conj(F_k) y_a e^{i m_a phi}: Re(c Q) = cr Q.re - cm Q.im
             TA cr[K][NM], cm[K][NM];
@@ -201,7 +201,7 @@ struct TmargKernel {
                 // of the pair tables are not hoisted over the time loop
                 fence();
                 asm volatile("" : "+s"(Ut), "+s"(Vt));
-                T2 = LK::quad_T2(Fr, Fi, y, Er, Ei, Ut, Vt);
+                T2 = LK::template quad_T2<false>(Fr, Fi, y, Er, Ei, Ut, Vt);
             }
             double lnLt = -INFINITY;
             if (ok && mx > (TA)-INFINITY)
