@@ -41,7 +41,7 @@ LNL_BYTES = {"fp32": 40, "fp64": 80}
 # SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32 of the same probe give the FLOPs the
 # kernel executes (64 lanes x (add + mul + 2 fma + trans) per wave instruction).
 LNL_TRAFFIC = {"fetch_B_per_sample": 32.720, "write_B_per_sample": 8.000, "executed_flop_per_sample": 2527.0,
-               "src_sha256": "e0e1ff05da62e6cd252457db64713cab5499f116a98efd584437c20b70e22f23"}
+               "src_sha256": "1bf4434f18088626ebac9fd73709915a784618fbf79988cd3be9d89b3cee5159"}
 # algorithmic HBM bytes per sample of the draw (7 theta + ln p - ln p_s
 # written) and estimator (lw read) kernels
 DRAW_BYTES = {"fp32": 32, "fp64": 64}

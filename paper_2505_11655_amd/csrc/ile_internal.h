@@ -181,7 +181,10 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
         const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
         const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
-        U4 n{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        // three-input XOR in one v_bitop3_b32 (truth table 0x96: odd parity)
+        const uint32_t x1 = (uint32_t)__builtin_amdgcn_bitop3_b32(hi1, c.y, k0, 0x96);
+        const uint32_t x3 = (uint32_t)__builtin_amdgcn_bitop3_b32(hi0, c.w, k1, 0x96);
+        U4 n{x1, lo1, x3, lo0};
         c = n;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
