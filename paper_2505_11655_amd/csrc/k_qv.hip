@@ -70,20 +70,23 @@ __global__ void __launch_bounds__(kQvThreads)
 
 // Partial Q of one (time tile, column tile, band slice) on the FP64 matrix
 // cores.  A block of four waves covers 64 window times x 128 columns; each
-// wave a 32 x 64 sub-tile as 2 x 4 tiles of 16 x 16 (kQvNS = 4 column
-// tiles), with the real and the imaginary part of every tile in its own
-// accumulator.  One step of
-// v_mfma_f64_16x16x4f64 takes four band bins: lane l holds the A element
-// (time l % 16, bin l / 16) and the B element (bin l / 16, column l % 16),
-// and its four results are times l / 16 + 4 r (r = 0..3) of column l % 16.
-// Each complex product is four real ones, Re += Er Xr - Ei Xi,
-// Im += Er Xi + Ei Xr.  The phases of a stage of 32 bins x 64 times sit in
-// LDS (the two column waves of a time range share them), double-buffered:
-// every thread reads its eight phases of the next stage (one bin, eight
-// consecutive times: one 64-bit remainder, then r += m' mod n per time) from
-// the table before the stage's matrix steps and writes them after.  X is read by each wave straight from memory
-// (no other wave of the block uses it), one step ahead.  Blocks are numbered
-// so that the time tiles of one column tile run on one XCD and share its L2.
+// wave a 32 x 64 sub-tile as 2 x 4 tiles of 16 x 16 (kQvNS = 4 column tiles),
+// with the real and the imaginary part of every tile in its own accumulator.
+// One step of v_mfma_f64_16x16x4f64 takes four band bins: lane l holds the A
+// element (time l % 16, bin l / 16) and the B element (bin l / 16, column
+// l % 16), and its four results are times l / 16 + 4 r (r = 0..3) of column
+// l % 16.  Each complex product is four real ones, Re += Er Xr - Ei Xi,
+// Im += Er Xi + Ei Xr.
+// The phases of a stage of 32 bins x 64 times sit in LDS (the two column
+// waves of a time range share them), double-buffered: every thread reads its
+// eight phases of the next stage (one bin, eight consecutive times: one
+// 64-bit remainder, then r += m' mod n per time) from the table during the
+// stage's first matrix step, after that step's X reads (the memory counter
+// retires in order, so waiting for X then never waits for the table), and
+// writes them to LDS after the stage's last step.  X is read by each wave
+// straight from memory (no other wave of the block uses it), one step ahead.
+// Blocks are numbered so that the time tiles of one column tile run on one
+// XCD and share its L2.
 typedef double qv_d4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(kQvThreads)
