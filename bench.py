@@ -73,6 +73,46 @@ def make_problems(n_points, seed):
     return probs
 
 
+def config_problems(name, n_points=1, snr=None):
+    """The other configurations of the workload: C1 (HL, 5 modes, SNR 20) and
+    C3 (HLV, 17 modes, mass ratio 20, SNR 100 by default)."""
+    import chirpgen
+    recs = chirpgen.load_injections()
+    rng = np.random.default_rng(7)
+    if name == "c1":
+        templates = [(30.0, 2.0)] + [(float(rng.uniform(25, 35)), float(rng.uniform(1.5, 2.5)))
+                                     for _ in range(n_points - 1)]
+        probs, _ = chirpgen.build_event(recs["c1"], ["H", "L"], 5, 30.0, 2.0, 20.0 if snr is None else snr,
+                                        noise_seed=chirpgen.BASE_SEED + 11, templates=templates)
+    else:
+        templates = [(30.0, 20.0)] + [(float(rng.uniform(28, 32)), float(rng.uniform(15, 25)))
+                                      for _ in range(n_points - 1)]
+        probs, _ = chirpgen.build_event(recs["c3"], ["H", "L", "V"], 17, 30.0, 20.0, 100.0 if snr is None else snr,
+                                        noise_seed=chirpgen.BASE_SEED + 13, templates=templates)
+    return probs
+
+
+def configs_leg(ile, torch, ctx, stream):
+    """Draw + lnL + estimator throughput of the C1 and C3 configurations, per
+    precision policy (the same step as the C2 benchmark)."""
+    c1 = config_problems("c1")
+    c3 = config_problems("c3", n_points=16)
+    out = {}
+    pols = (("fp32", ile.ILE_FP32), ("fp64", ile.ILE_FP64), ("fp32c64", ile.ILE_FP32_CANCEL64))
+    for label, probs, n_per, steps, warm in (("c1_hl5_1x2e17", c1, 1 << 17, 50, 5),
+                                             ("c1_hl5_1x2e24", c1, 1 << 24, 5, 1),
+                                             ("c3_hlv17_snr100_16x2e20", c3, 1 << 20, 5, 1)):
+        out[label] = {}
+        for name, pol in pols:
+            if label.startswith("c1") and name == "fp32c64":
+                continue
+            r = run_policy(ile, torch, ctx, probs, pol, n_per, steps, warm, stream)
+            out[label][name] = {"samples_per_s": r["samples_per_s"], "ms_per_step": r["ms_per_step"],
+                                "kernel_ms": r["kernel_ms"], "samples": r["N"]}
+            log(f"{label} {name} {out[label][name]}")
+    return out
+
+
 def run_policy(ile, torch, ctx, probs, policy, n_per, steps, warmup, stream, tmarg_R=None):
     """One step = draws + batched lnL (time-marginalised when tmarg_R is set) + batched estimator."""
     # theta (and ln p - ln p_s) in the policy's theta type; lnL and lw in its
@@ -275,9 +315,23 @@ def cpu_baseline(probs, budget_s=15.0):
     lw = oracle.lnL(probs[1 % len(probs)], th, threads=threads)
     oracle.marginalize(lw)
     dt = time.perf_counter() - t0
+    per_config = {}
+    for label, cp, m1 in (("c1_hl5", config_problems("c1")[0], 1 << 20),
+                          ("c3_hlv17_snr100", config_problems("c3")[0], 1 << 18)):
+        thc = chirpgen.prior_samples(rng, m1)
+        t1 = time.perf_counter()
+        oracle.marginalize(oracle.lnL(cp, thc, threads=threads))
+        d_all = time.perf_counter() - t1
+        m_one = max(m1 >> 4, 1024)
+        t1 = time.perf_counter()
+        oracle.lnL(cp, thc[:, :m_one], threads=1)
+        d_one = time.perf_counter() - t1
+        per_config[label] = {"samples_per_s_all_cores": m1 / d_all, "samples_per_s_one_thread": m_one / d_one,
+                             "samples": m1}
     return {"value": n / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} prior samples of one intrinsic point of the same workload (lnL + estimator), "
-                      f"FP64, OpenMP {threads} threads, {dt:.1f} s"}
+                      f"FP64, OpenMP {threads} threads, {dt:.1f} s",
+            "per_config": per_config}
 
 
 def main():
@@ -307,6 +361,9 @@ def main():
                     help="run only the Q, U, V precompute leg (256 points) and print its summary")
     ap.add_argument("--adaptive-integrator", choices=["gmm", "av", "ac", "all"], default="all",
                     help="proposal of the adaptive serving leg(s)")
+    ap.add_argument("--configs-only", action="store_true",
+                    help="run only the C1 / C3 configuration legs and print their summary")
+    ap.add_argument("--no-configs", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the path shards by "
@@ -336,6 +393,9 @@ def main():
         return
     if a.overlaps_only:
         print(json.dumps({"overlaps": overlaps_leg(ile, torch, ctx, stream)}), flush=True)
+        return
+    if a.configs_only:
+        print(json.dumps({"configs": configs_leg(ile, torch, ctx, stream)}), flush=True)
         return
     integrators = {"gmm": [0], "av": [1], "ac": [2], "all": [0, 1, 2]}[a.adaptive_integrator]
     leg_name = {0: "adaptive_saturated", 1: "adaptive_av_saturated", 2: "adaptive_ac_saturated"}
@@ -375,6 +435,10 @@ def main():
             tmarg[name] = {"samples_per_s": rt["samples_per_s"], "nodes_per_s": rt["samples_per_s"] * nodes,
                            "ms_per_step": rt["ms_per_step"], "kernel_ms": rt["kernel_ms"],
                            "lnL_marg_first": rt["lnL_marg_first"]}
+    configs = None
+    if not a.no_configs:
+        log("configurations C1, C3 ...")
+        configs = configs_leg(ile, torch, ctx, stream)
     log("fair draws ...")
     fair = fair_leg(ile, torch, ctx, probs[0], stream)
     log(f"fair {fair}")
@@ -451,6 +515,7 @@ def main():
             "value": rmx["samples_per_s"], "ms_per_step": rmx["ms_per_step"], "kernel_ms": rmx["kernel_ms"],
             "max_abs_dlnL_marg_vs_fp64": float(np.max(np.abs(np.array(rmx["lnL_marg"]) - np.array(r64["lnL_marg"]))))},
         "time_marginalised": tmarg,
+        "configs": configs,
         "fair_draws": fair,
         "overlaps": qv,
         "serving": serving,
