@@ -748,7 +748,14 @@ ile_status eval_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, hipStre
         }
         const int64_t cus = 256;
         const bool lds = lds_ok && total >= (int64_t)2 * cus * 16384 && total / (int64_t)idx.size() >= 65536;
-        const int64_t tile = lds ? 65536 : 8192;
+        // without LDS staging: about four 256-thread blocks per CU over the
+        // whole batch (small batches would otherwise leave most CUs idle),
+        // 256 to 8192 samples per tile
+        int64_t tile = 65536;
+        if (!lds) {
+            tile = (total + 4 * cus - 1) / (4 * cus);
+            tile = std::min<int64_t>(std::max<int64_t>((tile + 255) / 256 * 256, 256), 8192);
+        }
         std::vector<EvalJob> ej;
         std::vector<Tile> tiles;
         for (int i : idx) {
@@ -848,7 +855,6 @@ ile_status draw_batch(ile_ctx *ctx, int policy, const std::vector<DrawJob> &jobs
 
 // ================================================================ marginalise
 namespace ile {
-constexpr int64_t kMargTile = 16384;
 
 void marg_from_state(const MargState &m, ile_marg *out) {
     out->n = m.n;
@@ -876,7 +882,8 @@ void marg_from_state(const MargState &m, ile_marg *out) {
 
 ile_status job_marg_launch(ile_job *job, int64_t n, const void *lw, bool reset, hipStream_t st) {
     ile_ctx *ctx = job->ctx;
-    const int64_t np = std::max<int64_t>(1, (n + kMargTile - 1) / kMargTile);
+    const int64_t tile = marg_tile(n);
+    const int64_t np = std::max<int64_t>(1, (n + tile - 1) / tile);
     if ((size_t)np > job->part_cap) {
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) return dev_fail(ctx, e, "sync before partials growth");
@@ -888,7 +895,7 @@ ile_status job_marg_launch(ile_job *job, int64_t n, const void *lw, bool reset, 
         job->part_cap = (size_t)np;
     }
     hipError_t e = hipSuccess;
-    if (n > 0) e = launch_marg_partials(job->policy, lw, n, kMargTile, job->d_part, st);
+    if (n > 0) e = launch_marg_partials(job->policy, lw, n, tile, job->d_part, st);
     if (e != hipSuccess) return dev_fail(ctx, e, "marginal partials");
     e = launch_marg_combine(job->d_part, n > 0 ? (int)np : 0, n, job->d_ms, reset ? 1 : 0, st);
     if (e != hipSuccess) return dev_fail(ctx, e, "marginal combine");

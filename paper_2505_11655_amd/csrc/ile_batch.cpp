@@ -15,7 +15,6 @@
 using namespace ile;
 
 namespace ile {
-constexpr int64_t kMargTileB = 16384;  // must equal the single-job tile
 
 ile_status marg_batch(ile_ctx *ctx, ile_job *const *jobs, int n_jobs, const int64_t *n, const void *const *lw,
                       const uint32_t *flags, ile_marg *out, hipStream_t st) {
@@ -28,7 +27,8 @@ ile_status marg_batch(ile_ctx *ctx, ile_job *const *jobs, int n_jobs, const int6
         mj[j].lw = lw[j];
         mj[j].n = n[j];
         mj[j].tile_begin = (int32_t)tiles.size();
-        for (int64_t t = 0; t < n[j]; t += kMargTileB) tiles.push_back(Tile{j, 0, t, std::min(t + kMargTileB, n[j])});
+        const int64_t mt = marg_tile(n[j]);   // the single-job tile
+        for (int64_t t = 0; t < n[j]; t += mt) tiles.push_back(Tile{j, 0, t, std::min(t + mt, n[j])});
         mj[j].tile_end = (int32_t)tiles.size();
         mj[j].state = jobs[j]->d_ms;
         mj[j].out_idx = out ? j : -1;

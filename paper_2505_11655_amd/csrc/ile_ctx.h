@@ -201,5 +201,14 @@ ile_status ac_batch(ile_ctx *ctx, bool update, int policy, const std::vector<AcJ
 void eval_geometry(const ile_job *job, int64_t n, size_t *lds, int64_t *tile, int *block);
 size_t theta_size(int policy);
 size_t out_size(int policy);
+// Samples per stage-1 tile of the estimator for a job of n samples: at least
+// 64 tiles while a tile keeps one 2048-sample step of a block (small jobs
+// spread over the CUs), at most eight steps (16384 samples, from n = 2^20 up:
+// large batches keep few, long tiles).  A function of n alone: the single-job
+// and the batched estimator use it and agree to the bit.
+inline int64_t marg_tile(int64_t n) {
+    const int64_t t = ((n + 63) / 64 + 2047) / 2048 * 2048;
+    return t < 2048 ? 2048 : (t > 16384 ? 16384 : t);
+}
 
 }  // namespace ile
