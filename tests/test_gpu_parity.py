@@ -255,6 +255,34 @@ def test_marginalize_parity(orc, policy):
         ile.ile_job_release(job)
 
 
+@pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
+def test_marginalize_batch_equals_single(policy):
+    """The batched estimator and the single-job one use the same tile for a
+    job of n samples (2048 up to 16384, by n), so they agree to the bit: job
+    sizes from one sample to 3 * 2^20 cover every tile size and ragged
+    tails, all in one batch."""
+    rng = np.random.default_rng(27)
+    sizes = [1, 2047, 2048 * 64 + 5, (1 << 18) + 3, (1 << 20) + 7, 3 << 20]
+    dt = torch.float32 if policy == ile.ILE_FP32 else torch.float64
+    jobs, bufs = [], []
+    try:
+        for k, n in enumerate(sizes):
+            p = chirpgen.random_problem(rng, 5, ["H", "L"])
+            jobs.append(ile.ile_prepare(gu.ctx(), ile.ProblemHost(p, precision=policy)))
+            lw = rng.normal(size=n) * 20 - 50 * k
+            lw[rng.integers(0, n, size=min(n, 3))] = -np.inf
+            bufs.append(torch.from_numpy(lw).to(device="cuda", dtype=dt))
+        batch = ile.ile_marginalize_batch(jobs, sizes, bufs, ile.ILE_MARG_RESET)
+        torch.cuda.synchronize()
+        for job, n, buf, rb in zip(jobs, sizes, bufs, batch):
+            rs = ile.ile_marginalize(job, n, buf, ile.ILE_MARG_RESET)
+            for key in ("n", "n_nonfinite", "argmax", "ln_L", "n_eff", "n_ess", "max_lw"):
+                assert rs[key] == rb[key], (n, key, rs[key], rb[key])
+    finally:
+        for j in jobs:
+            ile.ile_job_release(j)
+
+
 @pytest.mark.parametrize("noise_seed", [9, 1, 4])
 def test_eval_then_marginalize_matches_oracle(orc, recs, noise_seed):
     """End to end on the small workload: GPU lnL + estimator vs oracle on the
