@@ -119,7 +119,7 @@ __device__ __forceinline__ double gmm_comp_logpdf(const GmmDev &g, const PriorDe
 
 // ln p_s(x) by a running log-sum-exp over the live components and the
 // defensive prior term.
-__device__ __noinline__ double gmm_ln_ps(const GmmDev &g, const PriorDev &pr, const double th[7]) {
+__device__ __forceinline__ double gmm_ln_ps(const GmmDev &g, const PriorDev &pr, const double th[7]) {
     double m = -INFINITY, s = 0.0;
     auto add = [&](double t) {
         if (!(t > -INFINITY)) return;
@@ -188,7 +188,7 @@ __device__ __forceinline__ bool gmm_candidate(const GmmDev &g, const PriorDev &p
 }
 
 // Mixture draw of sample idx: th and ln p - ln p_s.
-__device__ __noinline__ void draw_mix(const DrawJob &J, uint64_t idx, double th[7], double &lr) {
+__device__ __forceinline__ void draw_mix(const DrawJob &J, uint64_t idx, double th[7], double &lr) {
     const GmmDev &g = *J.gmm;
     uint32_t w[20];
     words(J.seed, idx, J.round, 0, 0, 5, w);
