@@ -29,7 +29,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kEmThreads = 256;
 constexpr int kTopThreads = 128;
 constexpr int kTopK = 2 * kMaxComp;
-constexpr int64_t kEmTile = 4096;
+constexpr int64_t kEmTile = 8192;
 constexpr int kBetaGrid = 48;   // beta_k = 2^(-k/4)
 constexpr int kBetaChunk = 8;   // grid values per block reduction
 
