@@ -256,6 +256,57 @@ def test_marginalize_parity(orc, policy):
 
 
 @pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
+def test_eval_batch_equals_single(policy):
+    """The batched likelihood sizes its tiles from the batch total (256 to
+    8192 samples); every sample's lnL and lw equal the single-job call's, for
+    one-job batches of 1, 300, 2^17 + 5 and 2^21 + 3 samples and for all four
+    in one batch (below the LDS-staging threshold).  The two entry points
+    are separately compiled copies of the same code (job descriptor by value
+    or from memory): FP64 agrees to the bit, FP32 to its rounding, where a
+    misplaced tile would show O(1) differences."""
+    rng = np.random.default_rng(28)
+    sizes = [1, 300, (1 << 17) + 5, (1 << 21) + 3]
+    dt = torch.float64 if policy == ile.ILE_FP64 else torch.float32
+    ot = gu.out_dtype(policy)
+    p = chirpgen.random_problem(rng, 5, ["H", "L"])
+    job = ile.ile_prepare(gu.ctx(), ile.ProblemHost(p, precision=policy))
+    try:
+        ths = [torch.from_numpy(np.ascontiguousarray(chirpgen.prior_samples(rng, n))).to(device="cuda", dtype=dt)
+               for n in sizes]
+        lrs = [torch.from_numpy(rng.normal(size=n)).to(device="cuda", dtype=dt) for n in sizes]
+        single = []
+        for n, th, lr in zip(sizes, ths, lrs):
+            L = torch.empty(n, dtype=ot, device="cuda")
+            W = torch.empty(n, dtype=ot, device="cuda")
+            ile.ile_eval_lnL(job, n, th, n, lr, L, W)
+            single.append((L, W))
+
+        def batch(idx):
+            Ls = [torch.empty(sizes[i], dtype=ot, device="cuda") for i in idx]
+            Ws = [torch.empty(sizes[i], dtype=ot, device="cuda") for i in idx]
+            ile.ile_eval_lnL_batch([job] * len(idx), [sizes[i] for i in idx], [ths[i] for i in idx],
+                                   [sizes[i] for i in idx], [lrs[i] for i in idx], Ls, Ws)
+            return Ls, Ws
+
+        runs = [([i], batch([i])) for i in range(len(sizes))] + [(list(range(len(sizes))), batch(range(len(sizes))))]
+        torch.cuda.synchronize()
+        for idx, (Ls, Ws) in runs:
+            for i, L, W in zip(idx, Ls, Ws):
+                for got, ref in ((L, single[i][0]), (W, single[i][1])):
+                    g, r = got.double().cpu().numpy(), ref.double().cpu().numpy()
+                    assert np.array_equal(np.isfinite(g), np.isfinite(r)), (idx, sizes[i])
+                    f = np.isfinite(r)
+                    if policy == ile.ILE_FP64:
+                        assert np.array_equal(g[f], r[f]), (idx, sizes[i])
+                    else:
+                        d = np.abs(g[f] - r[f]) / np.maximum(1.0, np.abs(r[f]))
+                        print("fp32 batch vs single, n", sizes[i], "max rel diff", d.max() if d.size else 0.0)
+                        assert d.size == 0 or d.max() <= 1e-6, (idx, sizes[i], d.max())
+    finally:
+        ile.ile_job_release(job)
+
+
+@pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
 def test_marginalize_batch_equals_single(policy):
     """The batched estimator and the single-job one use the same tile for a
     job of n samples (2048 up to 16384, by n), so they agree to the bit: job
