@@ -477,7 +477,9 @@ __global__ void __launch_bounds__(kEmThreads) k_em_resp(const EmJob *__restrict_
         const double w = sample_weight((double)lw[i], mlw, beta);
         double x[7];
 #pragma unroll
-        for (int a = 0; a < 7; a++) x[a] = a < d ? load_col(th, J.ld, col[a], i) : 0.0;
+        for (int a = 0; a < 7; a++) x[a] = load_col(th, J.ld, col[a], i);   // col[a] valid: loads in flight together
+#pragma unroll
+        for (int a = 0; a < 7; a++) x[a] = a < d ? x[a] : 0.0;
         double m = -INFINITY;
 #pragma unroll 1
         for (int j = 0; j < nc; j++) {
@@ -541,9 +543,14 @@ __global__ void __launch_bounds__(kEmThreads) k_em_stat(const EmJob *__restrict_
     const int64_t b0 = (int64_t)blockIdx.x * kEmTile, b1 = min(b0 + kEmTile, J.n);
     for (int64_t i = b0 + threadIdx.x; i < b1; i += kEmThreads) {
         const double r = R[(size_t)j * J.n + i];
+        // all seven column loads first (col[a] is a valid column, 0 beyond
+        // d), so that they are in flight together
+        double v[7];
+#pragma unroll
+        for (int a = 0; a < 7; a++) v[a] = load_col(th, J.ld, col[a], i);
         double x[7];
 #pragma unroll
-        for (int a = 0; a < 7; a++) x[a] = (a < d) ? wrapd(load_col(th, J.ld, col[a], i) - mu[a], P[a]) : 0.0;
+        for (int a = 0; a < 7; a++) x[a] = (a < d) ? wrapd(v[a] - mu[a], P[a]) : 0.0;
         acc[0] += r;
         int k = 1;
 #pragma unroll
