@@ -108,6 +108,8 @@ def lib():
         L.orc_gmm_comp_logpdf.restype = C.c_double
         L.orc_gmm_ln_ps.argtypes = [C.POINTER(_Prior), C.POINTER(_Gmm), dp]
         L.orc_gmm_ln_ps.restype = C.c_double
+        L.orc_gmm_ln_ps_n.argtypes = [C.POINTER(_Prior), C.POINTER(_Gmm), dp, C.c_int]
+        L.orc_gmm_ln_ps_n.restype = C.c_double
         L.orc_draw_gmm.argtypes = [C.POINTER(_Prior), C.POINTER(_Gmm), C.c_uint64, C.c_uint32,
                                    C.c_int64, C.c_int64, dp, C.c_int64, dp]
         L.orc_gmm_inbox_mass.argtypes = [C.POINTER(_Prior), C.POINTER(_Gmm), C.c_int, C.c_uint64,
@@ -306,9 +308,13 @@ def gmm_comp_logpdf(prior, g, j, th7):
     return lib().orc_gmm_comp_logpdf(C.byref(prior), C.byref(g), j, _dp(t))
 
 
-def gmm_ln_ps(prior, g, th7):
+def gmm_ln_ps(prior, g, th7, attempts=64):
+    """ln of the density of a ``draw_gmm`` draw: the mixture term of each
+    component scaled by 1 - (1 - Z_j)^attempts, the prior term carrying the
+    defensive weight plus the draws whose attempts all failed
+    (attempts <= 0: unlimited attempts)."""
     t = np.ascontiguousarray(th7, dtype=np.float64)
-    return lib().orc_gmm_ln_ps(C.byref(prior), C.byref(g), _dp(t))
+    return lib().orc_gmm_ln_ps_n(C.byref(prior), C.byref(g), _dp(t), int(attempts))
 
 
 def draw_gmm(prior, g, seed, rnd, i0, n):
@@ -600,16 +606,24 @@ def _logpdf_rows(D, cov):
     return -0.5 * np.sum(y * y, axis=0) - np.sum(np.log(np.diag(Lc))) - 0.5 * D.shape[1] * math.log(2 * math.pi)
 
 
+def first_fit_candidates(n_comp):
+    """How many of the highest-weight samples the first fit scans for
+    distinct means (a bounded top-k selection)."""
+    return 2 * n_comp
+
+
 def em_init(theta, lw, dims, n_comp=8, **rng_kw):
     """First fit: means at the highest-weight distinct samples among the
-    2 n_comp highest-weight ones (ties: lower index first), common weighted
-    covariance (differences wrapped about the best sample), equal weights."""
+    2 n_comp highest-weight ones (ties: lower index first), scanned in that
+    order; if fewer than n_comp are distinct the last one found is repeated.
+    Common weighted covariance (differences wrapped about the best sample),
+    equal weights."""
     X = np.asarray(theta, dtype=np.float64)[dims].T
     lw = np.asarray(lw, dtype=np.float64)
     fin = np.isfinite(lw)
     w = np.where(fin, np.exp(np.where(fin, lw, -np.inf) - np.max(lw[fin])), 0.0)
     key = np.where(fin, lw, -np.inf)
-    order = np.argsort(-key, kind="stable")[:2 * n_comp]
+    order = np.argsort(-key, kind="stable")[:first_fit_candidates(n_comp)]
     means = []
     for i in order:
         if not fin[i]:

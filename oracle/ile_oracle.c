@@ -538,17 +538,56 @@ double orc_gmm_comp_logpdf(const orc_prior *pr, const orc_gmm *g, int j, const d
     return -0.5 * q - ld - 0.5 * d * log(2.0 * ORC_PI);
 }
 
-/* ln p_s(x) = ln[(1-eps) sum_j pi_j N_j(x)/Z_j + eps p(x)]. */
-double orc_gmm_ln_ps(const orc_prior *pr, const orc_gmm *g, const double th[7])
+/* Prior density of one column (the prior is a product over columns). */
+static double orc_ln_prior_col(const orc_prior *pr, int c, const double th[7])
+{
+    switch (c) {
+    case 0: return -log(2.0 * ORC_PI);
+    case 1: return log(0.5 * cos(th[1]));
+    case 2: return -log(2.0 * pr->t_window);
+    case 3: return pr->dist_marg ? 0.0 : log(3.0 * th[3] * th[3] / (pow(pr->d_max, 3) - pow(pr->d_min, 3)));
+    case 4: return -log(2.0);
+    case 5: return -log(2.0 * ORC_PI);
+    default: return -log(ORC_PI);
+    }
+}
+
+/* Density of one draw of orc_draw_gmm below.  The selector picks the prior
+ * with probability eps, else component j with probability
+ * pi_j = weight_j / sum weight.  A component then makes up to `attempts`
+ * independent candidates; the first accepted one has density N_j(x)/Z_j on
+ * the mixture columns (Z_j its acceptance probability), and if all fail
+ * (probability r_j = (1 - Z_j)^attempts) the independent prior draw is kept.
+ * Columns outside the mixture always come from the prior draw.  So
+ *   p_s(x) = eps p(x) + (1-eps) sum_j pi_j [ (1 - r_j) N_j(x) p_rest(x) / Z_j
+ *                                            + r_j p(x) ],
+ * p_rest the prior of the columns outside the mixture.  attempts <= 0 stands
+ * for unlimited attempts (r_j = 0). */
+double orc_gmm_ln_ps_n(const orc_prior *pr, const orc_gmm *g, const double th[7], int attempts)
 {
     double lp = orc_ln_prior(pr, th);
+    double lrest = 0.0;
+    for (int c = 0; c < 7; c++) {
+        int in = 0;
+        for (int a = 0; a < g->n_dim; a++) in |= (g->dims[a] == c);
+        if (!in) lrest += orc_ln_prior_col(pr, c, th);
+    }
+    double tot = 0.0;
+    for (int j = 0; j < g->n_comp; j++)
+        if (g->weight[j] > 0) tot += g->weight[j];
     double terms[ORC_GMM_MAXC + 1];
     int nt = 0;
+    double fallback = g->eps_def;
     for (int j = 0; j < g->n_comp; j++) {
         if (!(g->weight[j] > 0)) continue;
-        terms[nt++] = log(1.0 - g->eps_def) + log(g->weight[j]) + orc_gmm_comp_logpdf(pr, g, j, th) - g->ln_Z[j];
+        double pi = g->weight[j] / tot;
+        double Z = exp(g->ln_Z[j]);
+        double r = attempts > 0 ? pow(1.0 - (Z < 1.0 ? Z : 1.0), attempts) : 0.0;
+        fallback += (1.0 - g->eps_def) * pi * r;
+        terms[nt++] = log((1.0 - g->eps_def) * pi * (1.0 - r)) + orc_gmm_comp_logpdf(pr, g, j, th)
+                      + lrest - g->ln_Z[j];
     }
-    if (g->eps_def > 0) terms[nt++] = log(g->eps_def) + lp;
+    if (fallback > 0) terms[nt++] = log(fallback) + lp;
     double m = -INFINITY;
     for (int t = 0; t < nt; t++) if (terms[t] > m) m = terms[t];
     if (!isfinite(m)) return m;
@@ -591,11 +630,18 @@ static int orc_gmm_candidate(const orc_prior *pr, const orc_gmm *g, int j,
 
 #define ORC_GMM_MAX_ATTEMPTS 64
 
+/* ln p_s of the draws below (64 attempts per component). */
+double orc_gmm_ln_ps(const orc_prior *pr, const orc_gmm *g, const double th[7])
+{
+    return orc_gmm_ln_ps_n(pr, g, th, ORC_GMM_MAX_ATTEMPTS);
+}
+
 /* Draw from p_s: block 0 of attempt 0 selects prior (u < eps) or a component
- * by cumulative weight; a component is then sampled by rejection, attempt a
- * using blocks 1..4 of attempt a.  Columns outside the GMM come from the prior
- * draw of attempt 0 (blocks 1..4).  If no attempt is accepted the prior draw is
- * used.  Returns ln p - ln p_s per sample. */
+ * by cumulative weight; a component is then sampled by rejection, attempt
+ * a = 1..64 using blocks 1..4 of attempt a.  Columns outside the GMM come from
+ * the prior draw of attempt 0 (blocks 1..4), whose words no candidate uses.
+ * If no attempt is accepted the prior draw is used.  Returns ln p - ln p_s
+ * per sample. */
 void orc_draw_gmm(const orc_prior *pr, const orc_gmm *g, uint64_t seed, uint32_t round,
                   int64_t i0, int64_t n, double *theta, int64_t ld, double *lnpmps)
 {
@@ -626,7 +672,7 @@ void orc_draw_gmm(const orc_prior *pr, const orc_gmm *g, uint64_t seed, uint32_t
                 jsel = j;
                 if (v < acc) break;
             }
-            for (int a = 0; a < ORC_GMM_MAX_ATTEMPTS && jsel >= 0; a++) {
+            for (int a = 1; a <= ORC_GMM_MAX_ATTEMPTS && jsel >= 0; a++) {
                 uint32_t wa[20];
                 orc_words(seed, idx, round, (uint32_t)a, 5, wa);
                 double cand[7];

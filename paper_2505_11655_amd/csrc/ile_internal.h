@@ -271,6 +271,11 @@ struct GmmDev {
     double Linv[kMaxComp][7][7];          // inverse of L (lower)
     double logdet_half[kMaxComp];         // sum ln L_dd
     double lnZ[kMaxComp];
+    // density of a mixture draw (set with the in-support masses): component
+    // j contributes e^{lnc_j} N_j(x) p_rest(x), the prior p(x) is weighted by
+    // e^{ln_fb} (defensive draws plus components whose 64 attempts all failed)
+    double lnc[kMaxComp];                 // ln[(1-eps) pi_j/sum pi (1 - (1-Z_j)^64) / Z_j]
+    double ln_fb;                         // ln[eps + (1-eps) sum_j pi_j/sum pi (1-Z_j)^64]
 };
 
 struct PriorDev {

@@ -6,10 +6,16 @@
 // Prior draw: 7 uniforms from blocks 0..3 of attempt 0 (words 2c, 2c+1),
 // mapped by inverse CDFs.  Mixture draw: the selector is the first uniform of
 // block 0 (attempt 0); the prior fallback and the non-mixture columns use
-// blocks 1..4 of attempt 0; attempt a of a component draws z from four
-// Box-Muller pairs of blocks 1..4 of attempt a and accepts x = mu + L z if
-// every bounded column is inside its interval and every periodic offset lies
-// in (-P/2, P/2]; after 64 rejected attempts the prior draw is kept.
+// blocks 1..4 of attempt 0; attempt a = 1..64 of a component draws z from
+// four Box-Muller pairs of blocks 1..4 of attempt a (never the words of the
+// prior draw, so the fallback is independent of the rejections) and accepts
+// x = mu + L z if every bounded column is inside its interval and every
+// periodic offset lies in (-P/2, P/2]; after 64 rejected attempts the prior
+// draw is kept.  The density of the draw is therefore
+//   p_s(x) = [eps + (1-eps) sum_j pi_j r_j] p(x)
+//          + (1-eps) sum_j pi_j (1 - r_j) N_j(x) p_rest(x) / Z_j,
+// r_j = (1 - Z_j)^64 the chance that all attempts fail, p_rest the prior of
+// the columns outside the mixture (pi_j normalised).
 //
 // Two instantiations per sample type: prior-only launches (no mixture code,
 // so the kernel stays small and occupancy high) and launches where some job
@@ -117,8 +123,25 @@ __device__ __forceinline__ double gmm_comp_logpdf(const GmmDev &g, const PriorDe
     return -0.5 * q - g.logdet_half[j] - 0.5 * d * log(2 * kPi);
 }
 
-// ln p_s(x) by a running log-sum-exp over the live components and the
-// defensive prior term.
+// ln of the prior density of one column (the prior factorises by column).
+__device__ __forceinline__ double ln_prior_col(const PriorDev &pr, int c, const double th[7]) {
+    switch (c) {
+    case 0: return -log(2 * kPi);
+    case 1: return log(0.5 * cos(th[1]));
+    case 2: return -log(2.0 * pr.t_window);
+    case 3: {
+        if (pr.dist_marg) return 0.0;
+        const double a3 = pr.d_min * pr.d_min * pr.d_min, b3 = pr.d_max * pr.d_max * pr.d_max;
+        return log(3.0 * th[3] * th[3] / (b3 - a3));
+    }
+    case 4: return -log(2.0);
+    case 5: return -log(2 * kPi);
+    default: return -log(kPi);
+    }
+}
+
+// ln p_s(x) (the density of a mixture draw, above) by a running log-sum-exp
+// over the live components and the prior term.
 __device__ __forceinline__ double gmm_ln_ps(const GmmDev &g, const PriorDev &pr, const double th[7]) {
     double m = -INFINITY, s = 0.0;
     auto add = [&](double t) {
@@ -130,12 +153,18 @@ __device__ __forceinline__ double gmm_ln_ps(const GmmDev &g, const PriorDev &pr,
             s += exp(t - m);
         }
     };
-    const double l1e = log1p(-g.eps_def);
-    for (int j = 0; j < g.n_comp; j++) {
-        if (g.logw[j] == -INFINITY) continue;
-        add(l1e + g.logw[j] + gmm_comp_logpdf(g, pr, j, th) - g.lnZ[j]);
+    // prior of the columns outside the mixture
+    double lrest = 0.0;
+    for (int c = 0; c < 7; c++) {
+        bool in = false;
+        for (int a = 0; a < g.n_dim; a++) in = in || (g.dims[a] == c);
+        if (!in) lrest += ln_prior_col(pr, c, th);
     }
-    if (g.eps_def > 0.0) add(log(g.eps_def) + ln_prior(pr, th));
+    for (int j = 0; j < g.n_comp; j++) {
+        if (g.lnc[j] == -INFINITY) continue;
+        add(g.lnc[j] + gmm_comp_logpdf(g, pr, j, th) + lrest);
+    }
+    add(g.ln_fb + ln_prior(pr, th));
     if (!(m > -INFINITY)) return m;
     return m + log(s);
 }
@@ -206,7 +235,7 @@ __device__ __forceinline__ void draw_mix(const DrawJob &J, uint64_t idx, double 
             jsel = j;
             if (v < acc) break;
         }
-        for (int a = 0; a < kMaxAttempts && jsel >= 0; a++) {
+        for (int a = 1; a <= kMaxAttempts && jsel >= 0; a++) {
             uint32_t wa[16];
             words(J.seed, idx, J.round, (uint32_t)a, 1, 4, wa);
             if (gmm_candidate(g, J.pr, jsel, wa, th)) break;
@@ -320,6 +349,26 @@ __global__ void k_gmm_setz(const EmJob *__restrict__ jobs) {
         const double c = (double)J.zcount[j];
         g->lnZ[j] = log((c > 0 ? c : 0.5) / (double)J.z_draws);
     }
+    __syncthreads();
+    if (j != 0) return;
+    // constants of the draw density: r_j = (1 - Z_j)^64, pi_j normalised
+    double tot = 0.0;
+    for (int q = 0; q < g->n_comp; q++) tot += g->w[q] > 0.0 ? g->w[q] : 0.0;
+    const double eps = g->eps_def;
+    double fb = eps;
+    for (int q = 0; q < kMaxComp; q++) {
+        if (q >= g->n_comp || !(g->w[q] > 0.0) || !(tot > 0.0)) {
+            g->lnc[q] = -INFINITY;
+            continue;
+        }
+        const double pi = g->w[q] / tot, z = exp(g->lnZ[q]);
+        const double lr = (double)kMaxAttempts * log1p(-(z < 1.0 ? z : 1.0));   // ln r_j
+        fb += (1.0 - eps) * pi * exp(lr);
+        // ln(1 - r_j), accurate on both sides of r_j = 1/2
+        const double l1mr = lr > -0.69314718055994531 ? log(-expm1(lr)) : log1p(-exp(lr));
+        g->lnc[q] = log1p(-eps) + log(pi) + l1mr - g->lnZ[q];
+    }
+    g->ln_fb = fb > 0.0 ? log(fb) : -INFINITY;
 }
 
 }  // namespace

@@ -336,8 +336,11 @@ __global__ void k_em_top_final(const EmJob *__restrict__ jobs) {
     g->valid = 1;
     const TT *th = (const TT *)J.theta;
     const int d = J.n_dim, nc = J.n_comp;
+    // candidates: the 2 n_comp highest-weight samples (kTopK = 2 kMaxComp
+    // holds them for every n_comp), scanned in that order
+    const int ncand = 2 * nc < kTopK ? 2 * nc : kTopK;
     int got = 0;
-    for (int k = 0; k < kTopK && got < nc; k++) {
+    for (int k = 0; k < ncand && got < nc; k++) {
         if (!(cur[k].v > -INFINITY)) break;
         double x[7];
         for (int a = 0; a < d; a++) x[a] = load_col(th, J.ld, J.dims[a], cur[k].i);

@@ -29,22 +29,33 @@ def _job(policy, dist_marg=False):
     return ile.ile_prepare(gu.ctx(), ile.ProblemHost(p, precision=policy, dist_marg=dist_marg)), p
 
 
+# a third component centred outside the time window: in-support mass ~1 %,
+# so all 64 rejection attempts fail for about half of its draws
+MEAN_OUT = [3.0, 0.1, 0.055, 1000.0, 0.0, 2.0, 1.0]
+COV_OUT = np.diag([0.3, 0.1, 1.44e-4, 4e4, 0.2, 0.5, 0.3])
+
+
+@pytest.mark.parametrize("outside", [False, True])
 @pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
-def test_proposal_mass_and_draws(orc, policy):
+def test_proposal_mass_and_draws(orc, policy, outside):
     job, _ = _job(policy)
     zseed, zround, m = 1234567, 2, 1 << 16
+    wts, means, covs = [0.6, 0.4], MEANS, COVS
+    if outside:
+        wts, means, covs = [3.0, 2.0, 5.0], MEANS + [MEAN_OUT], COVS + [COV_OUT]
+    nc = len(wts)
     try:
-        ile.ile_set_proposal(job, ile.gmm_params([0.6, 0.4], MEANS, COVS), ile.gmm_opts(seed=zseed, rnd=zround,
-                                                                                       z_draws=m))
+        ile.ile_set_proposal(job, ile.gmm_params(wts, means, covs), ile.gmm_opts(seed=zseed, rnd=zround,
+                                                                                 z_draws=m))
         got = ile.ile_get_proposal(job)
         prior = orc.make_prior()
-        g = orc.make_gmm([0.6, 0.4], MEANS, COVS, list(range(7)))
+        g = orc.make_gmm(wts, means, covs, list(range(7)))
         lz = []
-        for j in range(2):
+        for j in range(nc):
             z = orc.gmm_inbox_mass(prior, g, j, zseed, zround, m)
             lz.append(math.log(max(z, 0.5 / m)))
             assert abs(got.ln_Z[j] - lz[j]) <= 1e-12, (got.ln_Z[j], lz[j])
-        g = orc.make_gmm([0.6, 0.4], MEANS, COVS, list(range(7)), ln_Z=lz)
+        g = orc.make_gmm(wts, means, covs, list(range(7)), ln_Z=lz)
         n, seed, rnd, first = 30011, 99, 1, 777
         th = torch.empty((7, n), dtype=gu.torch_dtype(policy), device="cuda")
         lr = torch.empty((n,), dtype=gu.torch_dtype(policy), device="cuda")
@@ -124,6 +135,36 @@ def test_em_mixture_matches_oracle(orc, policy, temper):
         assert np.allclose(gw, w, rtol=1e-7, atol=1e-10)
         assert np.allclose(gm, m, rtol=1e-7, atol=1e-9)
         assert np.allclose(gc, c, rtol=1e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
+def test_em_first_fit_with_duplicates_matches_oracle(orc, policy):
+    """Duplicate-heavy samples (as fair redraws produce): the 24 highest-weight
+    samples hold only three distinct points, so the first fit must repeat the
+    third mean (candidates: the 2 n_comp highest-weight samples only), then
+    eight EM iterations; device and oracle agree."""
+    th, lw = _weighted_samples(1 << 16, 44, policy)
+    lw = (lw * 40).astype(lw.dtype)
+    order = np.argsort(-lw.astype(np.float64), kind="stable")
+    for r, i in enumerate(order[3:24]):
+        th[:, i] = th[:, order[r % 3]]
+    job, _ = _job(policy)
+    try:
+        o = ile.gmm_opts(n_comp=8, n_iter=8, temper_ess=1.0 / 16.0)
+        p = ile.ile_adapt_proposal(job, th.shape[1], torch.from_numpy(th).cuda(), th.shape[1],
+                                   torch.from_numpy(lw).cuda(), o)
+    finally:
+        ile.ile_job_release(job)
+    th64, lw64 = th.astype(np.float64), lw.astype(np.float64)
+    init = orc.em_init(th64, lw64 * orc.temper_beta(lw64, 1.0 / 16.0), list(range(7)), n_comp=8)
+    assert len({tuple(m) for m in init[1]}) == 3
+    w, m, c = orc.em_fit(th64, lw64, list(range(7)), n_iter=8, n_comp=8, temper_ess=1.0 / 16.0)
+    gw = np.array([p.weight[j] for j in range(8)])
+    gm = np.array([[p.mean[j][a] for a in range(7)] for j in range(8)])
+    gc = np.array([[[p.cov[j][a][b] for b in range(7)] for a in range(7)] for j in range(8)])
+    assert np.allclose(gw, w, rtol=1e-7, atol=1e-10)
+    assert np.allclose(gm, m, rtol=1e-7, atol=1e-9)
+    assert np.allclose(gc, c, rtol=1e-6, atol=1e-12)
 
 
 @pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])

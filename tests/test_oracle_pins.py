@@ -402,6 +402,69 @@ def test_P13_em_single_component_is_weighted_moments(orc):
     assert nw[0] == 1.0
 
 
+def _first_fit_case(orc, case):
+    """Samples whose first fit has a closed form (dims dec, t, D; all
+    non-periodic).  Every top sample has lw = 0 (equal weights, ties by
+    index); the rest lw = -800, finite (so candidates) but of weight exactly
+    zero in FP64.  Returns (theta, lw, expected means, expected covariance)."""
+    dims = [1, 2, 3]
+    c = np.array([0.1, 0.001, 1000.0])
+    a, b, g = 0.05, 0.002, 100.0
+    e = np.eye(3)
+    if case == 0:
+        # eight distinct points, each twice: found within the top 16
+        pts = [c, c + a * e[0], c - a * e[0], c + b * e[1], c - b * e[1], c + g * e[2], c - g * e[2],
+               c + a * e[0] + b * e[1]]
+        top = [p for p in pts for _ in range(2)]
+        means = pts
+        cov = np.array([[23 * a * a / 64, 7 * a * b / 64, 0.0],
+                        [7 * a * b / 64, 23 * b * b / 64, 0.0],
+                        [0.0, 0.0, g * g / 4]])
+    else:
+        # five distinct points fill the top 16 (4 + 3 + 3 + 3 + 3): the rule
+        # repeats the fifth and never reaches the lower samples
+        pts = [c, c + a * e[0], c - a * e[0], c + b * e[1], c - b * e[1]]
+        top = [pts[0]] * 4 + [p for p in pts[1:] for _ in range(3)]
+        means = pts + [pts[-1]] * 3
+        cov = np.diag([6 * a * a / 16, 6 * b * b / 16, 0.0])
+    rng = np.random.default_rng(21 + case)
+    low = [c + rng.normal(size=3) * np.array([0.3, 0.01, 300.0]) for _ in range(20)]
+    X = np.array(top + low)
+    lw = np.concatenate([np.zeros(len(top)), np.full(len(low), -800.0)])
+    th = np.zeros((7, len(X)))
+    th[dims] = X.T
+    cov = cov + np.diag([1e-8 * orc.col_range(cc) ** 2 for cc in dims])
+    return th, lw, dims, np.array(means), cov
+
+
+def _first_fit_holds(orc, case):
+    th, lw, dims, means, cov = _first_fit_case(orc, case)
+    w, m, C = orc.em_init(th, lw, dims, n_comp=8)
+    return (np.array_equal(m, means) and np.allclose(w, 1.0 / 8, rtol=0, atol=0)
+            and all(np.allclose(C[j], cov, rtol=1e-12, atol=1e-18) for j in range(8)))
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_P13_em_first_fit_closed_form(orc, case):
+    """First fit on duplicate-heavy samples: the means are the distinct points
+    among the 2 n_comp highest-weight samples in weight order (the last one
+    repeated when fewer are distinct), the common covariance the weighted
+    covariance of the differences about the best sample (closed form), the
+    weights 1/n_comp."""
+    assert _first_fit_holds(orc, case)
+
+
+def test_P13_em_first_fit_pin_rejects_other_rules(orc, monkeypatch):
+    """Planted mistakes in the oracle's candidate rule fail the pin: scanning
+    only the top n_comp samples (case 0: four distinct means), or every
+    sample (case 1: the lower samples become means)."""
+    monkeypatch.setattr(orc, "first_fit_candidates", lambda nc: nc)
+    assert not _first_fit_holds(orc, 0)
+    monkeypatch.setattr(orc, "first_fit_candidates", lambda nc: 10 ** 9)
+    assert _first_fit_holds(orc, 0)
+    assert not _first_fit_holds(orc, 1)
+
+
 def test_P13_component_logpdf_matches_scipy(orc):
     from scipy.stats import multivariate_normal
     rng = np.random.default_rng(14)
@@ -577,6 +640,35 @@ def test_gmm_draws_follow_ps(orc):
     z = orc.gmm_inbox_mass(prior, g1, 0, 5, 0, 1 << 16)
     ref = 0.5 * (erf((0.028 - 0.02) / (0.01 * math.sqrt(2))) - erf((-0.028 - 0.02) / (0.01 * math.sqrt(2))))
     assert abs(z - ref) < 4 * math.sqrt(ref * (1 - ref) / (1 << 16))
+
+
+def test_gmm_draw_density_counts_failed_attempts(orc):
+    """A component that lies mostly outside the support (in-support mass
+    Z ~ 0.012, so its 64 rejection attempts all fail ~46 % of the time) beside
+    one inside it, on the t column alone (the other six columns come from the
+    prior draw), unnormalised weights.  With the exact in-support masses
+    (erf closed form) the importance identity E_{p_s}[p / p_s] = 1 must hold
+    for the draws; a density without the failed-attempt mass (the oracle's
+    own ln p_s with unlimited attempts) must fail it."""
+    from scipy.special import erf
+    prior = orc.make_prior()
+    tw = 0.028
+    comps = [(0.055, 0.012), (0.0, 0.006)]
+
+    def zmass(mu, sd):
+        return 0.5 * (erf((tw - mu) / (sd * math.sqrt(2))) - erf((-tw - mu) / (sd * math.sqrt(2))))
+
+    lz = [math.log(zmass(mu, sd)) for mu, sd in comps]
+    g = orc.make_gmm([3.0, 1.0], [[mu] for mu, _ in comps], [[[sd * sd]] for _, sd in comps], [2], ln_Z=lz)
+    n = 40000
+    th, lr = orc.draw_gmm(prior, g, 2024, 3, 0, n)
+    r = np.exp(lr)
+    assert abs(r.mean() - 1) < 4 * r.std() / math.sqrt(n)
+    # the same draws scored without the failed-attempt mass
+    lr0 = np.array([orc.ln_prior(prior, th[:, i]) - orc.gmm_ln_ps(prior, g, th[:, i], attempts=0)
+                    for i in range(n)])
+    r0 = np.exp(lr0)
+    assert abs(r0.mean() - 1) > 10 * r0.std() / math.sqrt(n)
 
 
 # ------------------------------------------------ time-marginalised lnL
