@@ -184,6 +184,20 @@ ile_status ile_marginalize_batch(ile_job *const *jobs, int32_t n_jobs, const int
                                  const void *const *lw, uint32_t flags, ile_marg *out,
                                  ile_stream stream);
 
+/* ile_marginalize for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels, tiles and result (bitwise that of ile_marginalize), but
+ * the per-tile partials live in a fixed 1 MiB device array that the library
+ * holds on each GPU until the process ends, so this call allocates nothing.
+ * n above ile_marginalize_noalloc_max() samples gives ILE_E_TOO_BIG.  All
+ * calls on one GPU share that array: calls that overlap in time on one GPU
+ * (other streams, other threads) race and must be serialised by the caller.
+ * out (host, may be NULL): as for ile_marginalize (copied through the job's
+ * pinned buffer; the stream is synchronised). */
+ile_status ile_marginalize_noalloc(ile_job *job, int64_t n, const void *lw, uint32_t flags,
+                                   ile_marg *out, ile_stream stream);
+size_t ile_marginalize_noalloc_max(void);
+
 /* Counter-based draws (Philox-4x32-10) of samples first_index .. first_index+n-1
  * of round `round` under key `seed`: from the prior while the job has no
  * proposal, else from the mixture proposal p_s.  theta_out: device [7][ld];

@@ -136,6 +136,9 @@ EXPORTS = {
                                            C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32, C.c_void_p]),
     "ile_marginalize": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_uint32, C.POINTER(ile_marg),
                                   C.c_void_p]),
+    "ile_marginalize_noalloc": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_uint32, C.POINTER(ile_marg),
+                                          C.c_void_p]),
+    "ile_marginalize_noalloc_max": (C.c_size_t, []),
     "ile_marginalize_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int64),
                                         C.POINTER(C.c_void_p), C.c_uint32, C.POINTER(ile_marg), C.c_void_p]),
     "ile_draw": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
@@ -311,6 +314,17 @@ def ile_marginalize(job, n, lw, flags=ILE_MARG_RESET, want=True, stream=None):
     out = ile_marg() if want else None
     _chk(lib().ile_marginalize(job, n, _p(lw), flags, C.byref(out) if out is not None else None, _s(stream)))
     return out.as_dict() if out is not None else None
+
+
+def ile_marginalize_noalloc(job, n, lw, flags=ILE_MARG_RESET, want=True, stream=None):
+    out = ile_marg() if want else None
+    _chk(lib().ile_marginalize_noalloc(job, n, _p(lw), flags, C.byref(out) if out is not None else None,
+                                       _s(stream)))
+    return out.as_dict() if out is not None else None
+
+
+def ile_marginalize_noalloc_max():
+    return int(lib().ile_marginalize_noalloc_max())
 
 
 def ile_marginalize_batch(jobs, n, lw, flags=ILE_MARG_RESET, want=True, stream=None):

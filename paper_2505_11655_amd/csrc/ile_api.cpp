@@ -265,6 +265,9 @@ extern "C" ile_status ile_ctx_create(int hip_device, size_t hbm_budget_bytes, il
     if (hip_device < 0 || hip_device >= n) return set_err(ILE_E_INVALID, "device index out of range");
     e = hipSetDevice(hip_device);
     if (e != hipSuccess) return dev_fail(nullptr, e, "hipSetDevice");
+    // this device's copy of the no-alloc estimator's scratch array
+    ile_status sc = noalloc_init_device(hip_device);
+    if (sc != ILE_OK) return sc;
     ile_ctx *c = new ile_ctx();
     c->device = hip_device;
     size_t fr = 0, tot = 0;

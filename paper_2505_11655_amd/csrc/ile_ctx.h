@@ -186,6 +186,9 @@ struct AdaptItem {
 ile_status adapt_batch(ile_ctx *ctx, int policy, const std::vector<AdaptItem> &items, const ile_gmm_opts *o,
                        hipStream_t st);
 void marg_from_state(const MargState &m, ile_marg *out);
+// Look up the no-alloc estimator's scratch address on a device (the device
+// must be current); done once per device, by ile_ctx_create.
+ile_status noalloc_init_device(int device);
 // Adaptive volume: buffers for updates of up to `cap` samples (the first call
 // also installs the whole-cube grid over the job's sampled columns); bytes a
 // job's AV buffers take for that cap.

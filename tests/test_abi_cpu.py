@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "ile.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:ile_status|void|const char \*)\s*\*?\s*(ile_\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:ile_status|void|size_t|const char \*)\s*\*?\s*(ile_\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 
