@@ -177,6 +177,45 @@ def run_policy(ile, torch, ctx, probs, policy, n_per, steps, warmup, stream, tma
                 lnL_marg_first=out[0]["ln_L"], n_eff_first=out[0]["n_eff"], lnL_marg=ln_marg)
 
 
+def same_draw_marginals(ile, torch, ctx, probs, n_per, seed, stream):
+    """ln L of every point under each policy on ONE set of draws: the FP32
+    prior draws (float theta), upcast exactly to double for the FP64 policy,
+    so the differences are the arithmetic's alone (the parity protocol:
+    identical samples on both sides)."""
+    J = len(probs)
+    N = J * n_per
+    th32 = torch.empty((7, N), dtype=torch.float32, device="cuda")
+    lr32 = torch.empty((N,), dtype=torch.float32, device="cuda")
+    out = {}
+    for name, pol in (("fp32", ile.ILE_FP32), ("fp64", ile.ILE_FP64), ("fp32c64", ile.ILE_FP32_CANCEL64)):
+        jobs = [ile.ile_prepare(ctx, ile.ProblemHost(p, precision=pol)) for p in probs]
+        if name == "fp32":
+            ile.ile_draw(jobs[0], seed, 0, 0, N, th32, N, lr32, stream=stream)
+        th = th32.double() if pol == ile.ILE_FP64 else th32
+        lr = lr32.double() if pol == ile.ILE_FP64 else lr32
+        ot = torch.float32 if pol == ile.ILE_FP32 else torch.float64
+        L = torch.empty((N,), dtype=ot, device="cuda")
+        W = torch.empty((N,), dtype=ot, device="cuda")
+        esz, osz = th.element_size(), L.element_size()
+        ile.ile_eval_lnL_batch(jobs, [n_per] * J, [th.data_ptr() + j * n_per * esz for j in range(J)], [N] * J,
+                               [lr.data_ptr() + j * n_per * esz for j in range(J)],
+                               [L.data_ptr() + j * n_per * osz for j in range(J)],
+                               [W.data_ptr() + j * n_per * osz for j in range(J)], stream=stream)
+        res = ile.ile_marginalize_batch(jobs, [n_per] * J, [W.data_ptr() + j * n_per * osz for j in range(J)],
+                                        ile.ILE_MARG_RESET, want=True, stream=stream)
+        torch.cuda.synchronize()
+        out[name] = np.array([r["ln_L"] for r in res])
+        for j in jobs:
+            ile.ile_job_release(j)
+        del th, lr, L, W
+    del th32, lr32
+    torch.cuda.empty_cache()
+    return {"max_abs_dlnL_marg_fp32_vs_fp64": float(np.max(np.abs(out["fp32"] - out["fp64"]))),
+            "max_abs_dlnL_marg_fp32c64_vs_fp64": float(np.max(np.abs(out["fp32c64"] - out["fp64"]))),
+            "points": J, "samples_per_point": n_per,
+            "draws": "one set of FP32 prior draws; the FP64 policy evaluates them upcast exactly"}
+
+
 def serving_pool(per_class, seed):
     """Events of every (modes, detectors) class; each job of the stream picks one."""
     import chirpgen
@@ -420,6 +459,11 @@ def main():
         log("fp32 + fp64 cancellation ...")
         rmx = run_policy(ile, torch, ctx, probs, ile.ILE_FP32_CANCEL64, n_per, a.steps, a.warmup, stream)
         log(f"fp32c64 {dict((k, v) for k, v in rmx.items() if k != 'lnL_marg')}")
+    same = None
+    if not a.no_fp64:
+        log("marginals of all policies on one set of draws ...")
+        same = same_draw_marginals(ile, torch, ctx, probs, n_per, 4242, stream)
+        log(f"same draws {same}")
     tmarg = None
     if not a.no_tmarg:
         R = 4
@@ -506,14 +550,17 @@ def main():
         "fp64": None if r64 is None else {"value": r64["samples_per_s"], "ms_per_step": r64["ms_per_step"],
                                           "kernel_ms": r64["kernel_ms"],
                                           "fp32_over_fp64": r32["samples_per_s"] / r64["samples_per_s"],
-                                          # the same seeds draw the same samples in every policy (rounded
-                                          # to float in the FP32 ones): the marginal ln L of each point
-                                          # compares directly
-                                          "max_abs_dlnL_marg_fp32_vs_fp64": float(np.max(np.abs(
+                                          # the arithmetic's error: every policy on the same draws
+                                          "max_abs_dlnL_marg_fp32_vs_fp64": same["max_abs_dlnL_marg_fp32_vs_fp64"],
+                                          "marginal_comparison": same,
+                                          # the timed steps' own draws: the FP64 run's draws are the FP32
+                                          # run's before rounding to float, so these differ by where the
+                                          # samples sit as well as by the arithmetic
+                                          "max_abs_dlnL_marg_fp32_vs_fp64_own_draws": float(np.max(np.abs(
                                               np.array(r32["lnL_marg"]) - np.array(r64["lnL_marg"]))))},
         "fp32_cancel64": None if rmx is None else {
             "value": rmx["samples_per_s"], "ms_per_step": rmx["ms_per_step"], "kernel_ms": rmx["kernel_ms"],
-            "max_abs_dlnL_marg_vs_fp64": float(np.max(np.abs(np.array(rmx["lnL_marg"]) - np.array(r64["lnL_marg"]))))},
+            "max_abs_dlnL_marg_vs_fp64": same["max_abs_dlnL_marg_fp32c64_vs_fp64"]},
         "time_marginalised": tmarg,
         "configs": configs,
         "fair_draws": fair,

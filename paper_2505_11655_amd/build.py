@@ -19,7 +19,10 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libile.so")
 
 ARCH = "gfx950"
-COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+# -ffp-contract=on: a * b + c is fused only within one source expression, so
+# every compiled copy of the same code (single-job and batched descriptors,
+# LDS-staged or not) makes the same fusions and rounds identically.
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=on",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
           "-Wall", "-Wno-unused-function"]

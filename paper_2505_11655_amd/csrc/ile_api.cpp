@@ -53,13 +53,12 @@ size_t eval_lds_limit() {
 }
 
 hipError_t launch_eval(int set, int kdet, int policy, bool dm, size_t lds_bytes, const EvalJob *d_jobs,
-                       const Tile *d_tiles, int n_tiles, const EvalJob &single, int64_t tile, int block,
-                       hipStream_t st) {
+                       const Tile *d_tiles, int n_tiles, int block, hipStream_t st) {
 #define ILE_SP(S)                                                                                            \
     if (set == S) {                                                                                          \
-        if (policy == 0) return launch_eval_sp<S, 0>(kdet, dm, lds_bytes, d_jobs, d_tiles, n_tiles, single, tile, block, st); \
-        if (policy == 1) return launch_eval_sp<S, 1>(kdet, dm, lds_bytes, d_jobs, d_tiles, n_tiles, single, tile, block, st); \
-        if (policy == 2) return launch_eval_sp<S, 2>(kdet, dm, lds_bytes, d_jobs, d_tiles, n_tiles, single, tile, block, st); \
+        if (policy == 0) return launch_eval_sp<S, 0>(kdet, dm, lds_bytes, d_jobs, d_tiles, n_tiles, block, st); \
+        if (policy == 1) return launch_eval_sp<S, 1>(kdet, dm, lds_bytes, d_jobs, d_tiles, n_tiles, block, st); \
+        if (policy == 2) return launch_eval_sp<S, 2>(kdet, dm, lds_bytes, d_jobs, d_tiles, n_tiles, block, st); \
     }
     ILE_SP(0)
     ILE_SP(1)
@@ -70,12 +69,11 @@ hipError_t launch_eval(int set, int kdet, int policy, bool dm, size_t lds_bytes,
 }
 
 hipError_t launch_tmarg(int set, int kdet, int policy, int R, size_t lds_bytes, const EvalJob *d_jobs,
-                        const Tile *d_tiles, int n_tiles, const EvalJob &single, int64_t tile, int block,
-                        hipStream_t st) {
+                        const Tile *d_tiles, int n_tiles, int block, hipStream_t st) {
 #define ILE_TM(S)                                                                                             \
     if (set == S) {                                                                                           \
-        if (policy == 0) return launch_tmarg_sp<S, 0>(kdet, R, lds_bytes, d_jobs, d_tiles, n_tiles, single, tile, block, st); \
-        if (policy == 1) return launch_tmarg_sp<S, 1>(kdet, R, lds_bytes, d_jobs, d_tiles, n_tiles, single, tile, block, st); \
+        if (policy == 0) return launch_tmarg_sp<S, 0>(kdet, R, lds_bytes, d_jobs, d_tiles, n_tiles, block, st); \
+        if (policy == 1) return launch_tmarg_sp<S, 1>(kdet, R, lds_bytes, d_jobs, d_tiles, n_tiles, block, st); \
     }
     ILE_TM(0)
     ILE_TM(1)
@@ -597,29 +595,10 @@ extern "C" void ile_job_release(ile_job *job) {
 // ===================================================================== eval
 extern "C" ile_status ile_eval_lnL(ile_job *job, int64_t n, const void *theta, int64_t ld, const void *lnpmps,
                                    void *lnL_out, void *lw_out, ile_stream stream) {
+    // one job is a batch of one: the same kernels and descriptors, so a
+    // sample's lnL does not depend on which entry point evaluated it
     if (!job) return set_err(ILE_E_INVALID, "null job");
-    ile_status s = ctx_check(job->ctx);
-    if (s != ILE_OK) return s;
-    if (n < 0 || ld < n) return set_err(ILE_E_INVALID, "need n >= 0 and ld >= n");
-    if (n == 0) return ILE_OK;
-    if (!theta || !lnL_out) return set_err(ILE_E_INVALID, "null theta or lnL_out");
-    EvalJob ej = job->ej;
-    ej.theta = theta;
-    ej.ld = ld;
-    ej.lnpmps = lnpmps;
-    ej.lnL = lnL_out;
-    ej.lw = lw_out;
-    ej.n = n;
-    size_t lds;
-    int64_t tile;
-    int block;
-    eval_geometry(job, n, &lds, &tile, &block);
-    const int64_t nt = (n + tile - 1) / tile;
-    if (nt > INT32_MAX) return set_err(ILE_E_INVALID, "too many samples for one launch");
-    hipError_t e = launch_eval(job->set, job->kp, job->policy, job->dist_marg, lds, nullptr, nullptr, (int)nt, ej,
-                               tile, block, (hipStream_t)stream);
-    if (e != hipSuccess) return dev_fail(job->ctx, e, "eval launch");
-    return ILE_OK;
+    return ile_eval_lnL_batch(&job, 1, &n, &theta, &ld, &lnpmps, &lnL_out, &lw_out, stream);
 }
 
 extern "C" ile_status ile_eval_lnL_batch(ile_job *const *jobs, int32_t n_jobs, const int64_t *n,
@@ -721,7 +700,7 @@ ile_status tmarg_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, int R,
                                     tiles.size() * sizeof(Tile), &dj, &dt, &slot, st);
         if (s != ILE_OK) return s;
         hipError_t e = launch_tmarg(std::get<0>(g.first), std::get<1>(g.first), policy, R, lds ? win : 0,
-                                    (const EvalJob *)dj, (const Tile *)dt, (int)tiles.size(), ej[0], tile, block, st);
+                                    (const EvalJob *)dj, (const Tile *)dt, (int)tiles.size(), block, st);
         if (e != hipSuccess) return dev_fail(ctx, e, "time-marginalised eval launch");
         if ((s = batch_done(ctx, slot, st)) != ILE_OK) return s;
     }
@@ -781,8 +760,8 @@ ile_status eval_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, hipStre
         if (s != ILE_OK) return s;
         const auto &key = g.first;
         hipError_t e = launch_eval(std::get<0>(key), std::get<1>(key), std::get<2>(key), std::get<3>(key) != 0,
-                                   lds ? win : 0, (const EvalJob *)dj, (const Tile *)dt, (int)tiles.size(), ej[0],
-                                   tile, lds ? lds_block_threads(std::get<0>(key), std::get<2>(key)) : 256, st);
+                                   lds ? win : 0, (const EvalJob *)dj, (const Tile *)dt, (int)tiles.size(),
+                                   lds ? lds_block_threads(std::get<0>(key), std::get<2>(key)) : 256, st);
         if (e != hipSuccess) return dev_fail(ctx, e, "batched eval launch");
         if ((s = batch_done(ctx, slot, st)) != ILE_OK) return s;
     }

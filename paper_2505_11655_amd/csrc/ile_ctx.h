@@ -83,51 +83,51 @@ namespace ile {
 
 template <int S, int POL>
 hipError_t launch_eval_sp(int kdet, bool dm, size_t lds_bytes, const EvalJob *jobs, const Tile *tiles,
-                          int n_tiles, const EvalJob &single, int64_t tile, int nthreads, hipStream_t st);
+                          int n_tiles, int nthreads, hipStream_t st);
 extern template hipError_t launch_eval_sp<0, 0>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   const EvalJob &, int64_t, int, hipStream_t);
+                                                   int, hipStream_t);
 extern template hipError_t launch_eval_sp<0, 1>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   const EvalJob &, int64_t, int, hipStream_t);
+                                                   int, hipStream_t);
 extern template hipError_t launch_eval_sp<0, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   const EvalJob &, int64_t, int, hipStream_t);
+                                                   int, hipStream_t);
 extern template hipError_t launch_eval_sp<1, 0>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   const EvalJob &, int64_t, int, hipStream_t);
+                                                   int, hipStream_t);
 extern template hipError_t launch_eval_sp<1, 1>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   const EvalJob &, int64_t, int, hipStream_t);
+                                                   int, hipStream_t);
 extern template hipError_t launch_eval_sp<1, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   const EvalJob &, int64_t, int, hipStream_t);
+                                                   int, hipStream_t);
 extern template hipError_t launch_eval_sp<2, 0>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   const EvalJob &, int64_t, int, hipStream_t);
+                                                   int, hipStream_t);
 extern template hipError_t launch_eval_sp<2, 1>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   const EvalJob &, int64_t, int, hipStream_t);
+                                                   int, hipStream_t);
 extern template hipError_t launch_eval_sp<2, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   const EvalJob &, int64_t, int, hipStream_t);
+                                                   int, hipStream_t);
 extern template hipError_t launch_eval_sp<3, 0>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   const EvalJob &, int64_t, int, hipStream_t);
+                                                   int, hipStream_t);
 extern template hipError_t launch_eval_sp<3, 1>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   const EvalJob &, int64_t, int, hipStream_t);
+                                                   int, hipStream_t);
 extern template hipError_t launch_eval_sp<3, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   const EvalJob &, int64_t, int, hipStream_t);
+                                                   int, hipStream_t);
 
 template <int S, int POL>
 hipError_t launch_tmarg_sp(int kdet, int R, size_t lds_bytes, const EvalJob *jobs, const Tile *tiles, int n_tiles,
-                           const EvalJob &single, int64_t tile, int nthreads, hipStream_t st);
+                           int nthreads, hipStream_t st);
 extern template hipError_t launch_tmarg_sp<0, 0>(int, int, size_t, const EvalJob *, const Tile *, int,
-                                                     const EvalJob &, int64_t, int, hipStream_t);
+                                                     int, hipStream_t);
 extern template hipError_t launch_tmarg_sp<0, 1>(int, int, size_t, const EvalJob *, const Tile *, int,
-                                                     const EvalJob &, int64_t, int, hipStream_t);
+                                                     int, hipStream_t);
 extern template hipError_t launch_tmarg_sp<1, 0>(int, int, size_t, const EvalJob *, const Tile *, int,
-                                                     const EvalJob &, int64_t, int, hipStream_t);
+                                                     int, hipStream_t);
 extern template hipError_t launch_tmarg_sp<1, 1>(int, int, size_t, const EvalJob *, const Tile *, int,
-                                                     const EvalJob &, int64_t, int, hipStream_t);
+                                                     int, hipStream_t);
 extern template hipError_t launch_tmarg_sp<2, 0>(int, int, size_t, const EvalJob *, const Tile *, int,
-                                                     const EvalJob &, int64_t, int, hipStream_t);
+                                                     int, hipStream_t);
 extern template hipError_t launch_tmarg_sp<2, 1>(int, int, size_t, const EvalJob *, const Tile *, int,
-                                                     const EvalJob &, int64_t, int, hipStream_t);
+                                                     int, hipStream_t);
 extern template hipError_t launch_tmarg_sp<3, 0>(int, int, size_t, const EvalJob *, const Tile *, int,
-                                                     const EvalJob &, int64_t, int, hipStream_t);
+                                                     int, hipStream_t);
 extern template hipError_t launch_tmarg_sp<3, 1>(int, int, size_t, const EvalJob *, const Tile *, int,
-                                                     const EvalJob &, int64_t, int, hipStream_t);
+                                                     int, hipStream_t);
 
 struct BatchItem {
     ile_job *job;

@@ -317,11 +317,9 @@ struct DrawJob {
 
 // --------------------------------------------------------- launch wrappers
 // Return hipSuccess or the launch error.  All enqueue on `st`.
-// Either a device array of jobs with a tile list (batched launch), or one job
-// passed by value (d_jobs == nullptr) split into tiles of `tile` samples.
+// A device array of job descriptors with a tile list (one block per tile).
 hipError_t launch_eval(int set, int kdet, int policy, bool dist_marg, size_t lds_bytes,
-                       const EvalJob *d_jobs, const Tile *d_tiles, int n_tiles, const EvalJob &single,
-                       int64_t tile, int block, hipStream_t st);
+                       const EvalJob *d_jobs, const Tile *d_tiles, int n_tiles, int block, hipStream_t st);
 size_t eval_lds_limit();
 
 hipError_t launch_marg_partials(int policy, const void *lw, int64_t n, int64_t tile,

@@ -109,7 +109,9 @@ size_t footprint_of(const ile_server *s, const Req *r) {
     const size_t inputs = (size_t)kp * P.n_time * nm * 2 * cr + 2 * (size_t)(nm * (nm + 1) / 2) * kp * 2 * cr;
     const int64_t c = chunk_of(s, r);
     const size_t bufs = (size_t)c * (8 * theta_bytes(policy) + lw_bytes(policy));
-    size_t extra = sizeof(MargState) + ((size_t)c / 16384 + 1) * sizeof(MargPartial);
+    // the estimator's partials: one per marg_tile(c) samples of a chunk
+    const int64_t mt = marg_tile(c);
+    size_t extra = sizeof(MargState) + (size_t)((c + mt - 1) / mt + 1) * sizeof(MargPartial);
     if (r->jo.adaptive && r->jo.integrator == ILE_INT_AV)
         extra += av_bytes_for(c);
     else if (r->jo.adaptive && r->jo.integrator == ILE_INT_AC)

@@ -20,6 +20,7 @@
 #include <type_traits>
 
 #include "ile_internal.h"
+#include "ile_sincos.h"
 
 namespace ile {
 
@@ -45,10 +46,16 @@ struct PolTypes<kFP64> {
     using TA = double;  // Q/U/V contractions and the combine
     using TO = double;  // lnL, lw
 };
+// FP32: the sky direction and the delays are FP64 as well.  The stencil
+// position u = (tau - tau0)/dt is a few hundred samples, where an FP32 value
+// is quantised to 3e-5 samples, and FP32 sines of the sky angles move the
+// delays by about 1e-5 samples; either one shifts the phase of Q by enough to
+// move lnL by ~1e-4 at SNR 20.  In FP64 the position is exact to rounding;
+// its integer part picks the stencil and only the fraction becomes FP32.
 template <>
 struct PolTypes<kFP32> {
     using TT = float;
-    using TS = float;
+    using TS = double;
     using TG = float;
     using TE = float;
     using TA = float;
@@ -64,8 +71,21 @@ struct PolTypes<kMixed> {
     using TO = double;
 };
 
-__device__ __forceinline__ void dsincos(float x, float *s, float *c) { sincosf(x, s, c); }
-__device__ __forceinline__ void dsincos(double x, double *s, double *c) { sincos(x, s, c); }
+// Angles go through an FP64 Cody-Waite reduction and a truncated series
+// (ile_sincos.h): exact reduction for any angle a sample carries, and no
+// large-argument branch (the library routines compute theirs as well: 124
+// instructions for an FP32 sine and cosine).  FP32 results use an FP32 series.
+__device__ __forceinline__ void dsincos(float x, float *s, float *c) { sincos_rad(x, s, c); }
+__device__ __forceinline__ void dsincos(double x, double *s, double *c) { sincos_rad(x, s, c); }
+// Sky angles: with FP32 geometry downstream (FP32 and mixed policies) only the
+// delays need FP64, to ~1e-9 of a window sample: the shorter series.
+template <class TS, class TG>
+__device__ __forceinline__ void sky_sincos(TS x, TS *s, TS *c) {
+    if constexpr (sizeof(TS) == 8 && sizeof(TG) == 4)
+        sincos_rad_sky(x, s, c);
+    else
+        dsincos(x, s, c);
+}
 __device__ __forceinline__ float dfloor(float x) { return floorf(x); }
 __device__ __forceinline__ double dfloor(double x) { return floor(x); }
 __device__ __forceinline__ float dsqrt(float x) { return sqrtf(x); }
@@ -98,8 +118,8 @@ __device__ __forceinline__ void static_for(F &&f) {
 // The table coordinates are computed in TC (the policy's contraction type:
 // FP32 for the FP32 policy, where T1 and T2 are FP32 values themselves);
 // the FP64 table values are interpolated in FP64.
-template <class TC>
-__device__ __forceinline__ double dist_lookup(const DistTable &tb, TC T1, TC T2) {
+template <class TC, class TB>
+__device__ __forceinline__ double dist_lookup(const TB &tb, TC T1, TC T2) {
     // branch-free: an input outside the table (or T2 <= 0, or NaN) reads the
     // clamped first cell and returns -inf
     const bool pos = T2 > (TC)0;
@@ -153,15 +173,17 @@ struct LnlKernel {
     // do not fit next to the others)
     static constexpr int kG = LDS ? lds_global_dets(S, K, POL) : 0;
 
-    // Sky direction, polarisation response F_k, delays tau_k (at time tt),
-    // harmonic amplitudes y_lm(iota) and the phase table e^{i j phi}.
-    __device__ __forceinline__ static void geometry(const EvalJob &J, const TT al, const TT de, const TT tt,
+    // Sky direction, polarisation response F_k, stencil positions
+    // u_k = (tau_k - tau0)/dt in window samples with tau_k = t - x_k.n/c (at
+    // time tt), harmonic amplitudes y_lm(iota) and the phase table e^{i j phi}.
+    template <class JT>
+    __device__ __forceinline__ static void geometry(const JT &J, const TT al, const TT de, const TT tt,
                                                     const TT ci, const TT ph, const TT ps, TG (&Fr)[K], TG (&Fi)[K],
-                                                    TA (&tau)[K], TG (&y)[NM], TE (&Er)[NE], TE (&Ei)[NE]) {
+                                                    TS (&uu)[K], TG (&y)[NM], TE (&Er)[NE], TE (&Ei)[NE]) {
         // ---- sky direction, polarisation basis, delays
         TS sd, cd, sh, ch;
-        dsincos((TS)de, &sd, &cd);
-        dsincos((TS)al - pick<TS>(J.gmst, J.gmstf), &sh, &ch);
+        sky_sincos<TS, TG>((TS)de, &sd, &cd);
+        sky_sincos<TS, TG>((TS)al - pick<TS>(J.gmst, J.gmstf), &sh, &ch);
         const TS n0 = cd * ch, n1 = cd * sh, n2 = sd;
         const TG ea0 = (TG)(-sh), ea1 = (TG)ch;
         const TG ed0 = (TG)(-sd * ch), ed1 = (TG)(-sd * sh), ed2 = (TG)cd;
@@ -182,7 +204,7 @@ struct LnlKernel {
             Fi[k] = c2p * Gi - s2p * Gr;
             const TS dly = pick<TS>(J.xc[k][0], J.xcf[k][0]) * n0 + pick<TS>(J.xc[k][1], J.xcf[k][1]) * n1 +
                            pick<TS>(J.xc[k][2], J.xcf[k][2]) * n2;
-            tau[k] = (TA)((TS)tt - dly);
+            uu[k] = (((TS)tt - dly) - pick<TS>(J.tau0, J.tau0f)) * pick<TS>(J.inv_dt, J.inv_dtf);
         }
 
         // ---- harmonics y_lm(iota) and phases e^{i j phi}
@@ -314,8 +336,13 @@ struct LnlKernel {
         return T2;
     }
 
-    __device__ __forceinline__ static void run(const EvalJob &J, const int64_t begin, const int64_t end,
+    // The job descriptor as seen through the constant address space: its
+    // fields load through the scalar cache.
+    typedef __attribute__((address_space(4))) const EvalJob cjob;
+
+    __device__ __forceinline__ static void run(const EvalJob *Jp, const int64_t begin, const int64_t end,
                                                cpx<TA> *smem) {
+        const EvalJob &J = *Jp;
         const int T = J.n_time;
         const cpx<TA> *__restrict__ Qg = (const cpx<TA> *)J.Q;
         if constexpr (LDS) {
@@ -343,27 +370,34 @@ struct LnlKernel {
             // loop-variant, so the scalar loads stream per sample instead of
             // being hoisted into more SGPRs than exist (which spills them).
             asm volatile("" : "+s"(Ut), "+s"(Vt));
+            // Likewise the descriptor: its geometry constants (FP64 detector
+            // positions, response tensors, window origin) are re-read per
+            // sample through the scalar cache instead of holding scalar
+            // registers across the pair sums, which need them all.
+            cjob *Jc = (cjob *)Jp;
+            asm volatile("" : "+s"(Jc));
             const TT al = th[i], de = th[ld + i], tt = th[2 * ld + i], DD = th[3 * ld + i];
             const TT ci = th[4 * ld + i], ph = th[5 * ld + i], ps = th[6 * ld + i];
             bool ok = (DM || DD > (TT)0) && (ci >= (TT)-1 && ci <= (TT)1);
 
             TG Fr[K], Fi[K];
-            TA tau[K];
+            TS uu[K];
             TG y[NM];
             TE Er[NE], Ei[NE];
-            geometry(J, al, de, tt, ci, ph, ps, Fr, Fi, tau, y, Er, Ei);
+            geometry(*Jc, al, de, tt, ci, ph, ps, Fr, Fi, uu, y, Er, Ei);
 
             // ---- T1 = sum_k Re[conj(F_k) sum_a y_a e^{i m_a phi} Qhat_k,a]
             TA T1 = (TA)0;
 #pragma unroll
             for (int k = 0; k < K; k++) {
                 fence();
-                const TA u = (tau[k] - pick<TA>(J.tau0, J.tau0f)) * pick<TA>(J.inv_dt, J.inv_dtf);
-                const TA fl = dfloor(u);
-                ok = ok && (fl >= (TA)1) && (fl <= (TA)(T - 3));
-                const TA flc = fmin(fmax(fl, (TA)1), (TA)(T - 3));
+                // integer part of the stencil position in its own precision;
+                // the fraction (exact: u - floor(u)) in the contraction type
+                const TS fl = dfloor(uu[k]);
+                ok = ok && (fl >= (TS)1) && (fl <= (TS)(T - 3));
+                const TS flc = fmin(fmax(fl, (TS)1), (TS)(T - 3));
                 const int i0 = (int)flc;
-                const TA f = u - fl;
+                const TA f = (TA)(uu[k] - fl);
                 const TA fm1 = f - (TA)1, fm2 = f - (TA)2, fp1 = f + (TA)1;
                 const TA w0 = -f * fm1 * fm2 * (TA)(1.0 / 6.0);
                 const TA w1 = fp1 * fm1 * fm2 * (TA)0.5;
@@ -397,9 +431,9 @@ struct LnlKernel {
             // ---- combine
             TA lnL;
             if constexpr (DM) {
-                lnL = (TA)dist_lookup<TA>(J.dt, T1, T2);
+                lnL = (TA)dist_lookup<TA>(Jc->dt, T1, T2);
             } else {
-                const TA s = pick<TA>(J.d_ref, J.d_reff) / (TA)DD;
+                const TA s = pick<TA>(Jc->d_ref, Jc->d_reff) / (TA)DD;
                 lnL = s * T1 - s * s * T2 * (TA)0.25;
             }
             TO outv = ok ? (TO)lnL : (TO)-INFINITY;
@@ -419,24 +453,17 @@ constexpr int lnl_min_waves() {
 
 template <int S, int K, int POL, bool LDS, bool DM>
 __global__ void __launch_bounds__(LDS ? lds_block_threads(S, POL) : 256, (lnl_min_waves<S, POL>()))
-    k_lnl(const EvalJob *__restrict__ jobs, const Tile *__restrict__ tiles, const EvalJob single,
-          const int64_t tile) {
+    k_lnl(const EvalJob *__restrict__ jobs, const Tile *__restrict__ tiles) {
     extern __shared__ __align__(16) char ile_smem[];
     using TA = typename PolTypes<POL>::TA;
-    if (jobs != nullptr) {
-        const Tile tl = tiles[blockIdx.x];
-        LnlKernel<S, K, POL, LDS, DM>::run(jobs[tl.job], tl.begin, tl.end, (cpx<TA> *)ile_smem);
-    } else {
-        const int64_t b = (int64_t)blockIdx.x * tile;
-        const int64_t e = b + tile < single.n ? b + tile : single.n;
-        LnlKernel<S, K, POL, LDS, DM>::run(single, b, e, (cpx<TA> *)ile_smem);
-    }
+    const Tile tl = tiles[blockIdx.x];
+    LnlKernel<S, K, POL, LDS, DM>::run(jobs + tl.job, tl.begin, tl.end, (cpx<TA> *)ile_smem);
 }
 
 
 template <int S, int POL>
 hipError_t launch_eval_sp(int kdet, bool dm, size_t lds_bytes, const EvalJob *jobs, const Tile *tiles, int n_tiles,
-                          const EvalJob &single, int64_t tile, int nthreads, hipStream_t st) {
+                          int nthreads, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
     const bool lds = lds_bytes > 0;
     if (nthreads <= 0 || nthreads > (lds ? lds_block_threads(S, POL) : 256) || nthreads % 64) return hipErrorInvalidValue;
@@ -455,7 +482,7 @@ hipError_t launch_eval_sp(int kdet, bool dm, size_t lds_bytes, const EvalJob *jo
                                                    (int)lds_bytes);
                 if (e != hipSuccess) return e;
             }
-            hipLaunchKernelGGL(fn, grid, block, L ? lds_bytes : 0, st, jobs, tiles, single, tile);
+            hipLaunchKernelGGL(fn, grid, block, L ? lds_bytes : 0, st, jobs, tiles);
             return hipGetLastError();
         }
     };

@@ -3,5 +3,5 @@
 
 namespace ile {
 template hipError_t launch_eval_sp<0, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                           const EvalJob &, int64_t, int, hipStream_t);
+                                           int, hipStream_t);
 }  // namespace ile

@@ -4,7 +4,7 @@
 
 namespace ile {
 template hipError_t launch_eval_sp<2, 0>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                           const EvalJob &, int64_t, int, hipStream_t);
+                                           int, hipStream_t);
 template hipError_t launch_tmarg_sp<2, 0>(int, int, size_t, const EvalJob *, const Tile *, int,
-                                             const EvalJob &, int64_t, int, hipStream_t);
+                                             int, hipStream_t);
 }  // namespace ile

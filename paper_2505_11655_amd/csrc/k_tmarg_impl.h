@@ -24,6 +24,7 @@ struct TmargKernel {
     using LK = LnlKernel<S, K, POL, LDS, false>;
     using Tp = PolTypes<POL>;
     using TT = typename Tp::TT;
+    using TS = typename Tp::TS;
     using TG = typename Tp::TG;
     using TE = typename Tp::TE;
     using TA = typename Tp::TA;
@@ -76,10 +77,10 @@ struct TmargKernel {
             const bool ok = DD > (TT)0 && ci >= (TT)-1 && ci <= (TT)1;
 
             TG Fr[K], Fi[K];
-            TA tau[K];
+            TS uu[K];
             TG y[NM];
             TE Er[NE], Ei[NE];
-            LK::geometry(J, al, de, (TT)0, ci, ph, ps, Fr, Fi, tau, y, Er, Ei);
+            LK::geometry(J, al, de, (TT)0, ci, ph, ps, Fr, Fi, uu, y, Er, Ei);
             const TA s = pick<TA>(J.d_ref, J.d_reff) / (TA)DD;
             // T2 does not depend on t.  FP32: formed after the time loop, so its
             // temporaries never coexist with the loop state; FP64 (one wave per
@@ -113,12 +114,11 @@ struct TmargKernel {
             }
 #pragma unroll
             for (int k = 0; k < K; k++) {
-                const TA u0 = (tau[k] - pick<TA>(J.tau0, J.tau0f)) * pick<TA>(J.inv_dt, J.inv_dtf);
-                const TA fl = dfloor(u0);
+                const TS fl = dfloor(uu[k]);
                 // keep the base index representable; a sample this far out has no valid node
-                const TA flc = fmin(fmax(fl, (TA)(-4 * T)), (TA)(4 * T));
+                const TS flc = fmin(fmax(fl, (TS)(-4 * T)), (TS)(4 * T));
                 i0[k] = (int)flc;
-                const TA f0 = u0 - fl;
+                const TA f0 = (TA)(uu[k] - fl);
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     TA f = f0 + (TA)r / (TA)R;
@@ -140,20 +140,6 @@ struct TmargKernel {
                     qmax[r] = min(qmax[r], hi);
                 }
             }
-            auto Gk = [&](int k, int idx) -> TA {
-                const int ic = min(max(idx, 0), T - 1);
-                const cpx<TA> *q = (k < kGlobalDets ? Qg + (size_t)k * T * NM
-                                                    : smem + (size_t)(k - kGlobalDets) * T * NM) +
-                                   (size_t)ic * NM;
-                TA g = (TA)0;
-                static_for<0, NM>([&](auto A_) {
-                    constexpr int a = decltype(A_)::value;
-                    const cpx<TA> v = q[a];
-                    g = fma(cr[k][a], v.re, g);
-                    g = fma(-cm[k][a], v.im, g);
-                });
-                return g;
-            };
             // window G_k(i0 + q - 1 + t), t = 0..4: each step appends the
             // newest sample; the four steps before q_lo only fill the window
             // (their nodes lie below -tm_half and are masked)
@@ -166,12 +152,43 @@ struct TmargKernel {
             double sum = 0.0;
 #pragma unroll 1
             for (int q = q_lo - 4; q <= q_hi; q++) {
+                // The newest window row of the detectors.  In FP32, up to 27
+                // complex values (3 detectors x 9 modes), every detector's row
+                // is loaded before any is used: left to itself the allocator
+                // recycled one destination register and waited for every
+                // load in turn (37 against 24 ms, 256 x 2^16 samples, HLV 9
+                // modes).  Larger sets, and FP64, go one detector at a time:
+                // holding all their rows costs more registers than it saves.
+                constexpr int kGroup = (sizeof(TA) == 4 && K * NM <= 27) ? K : 1;
 #pragma unroll
-                for (int k = 0; k < K; k++) {
-                    fence();
+                for (int k0 = 0; k0 < K; k0 += kGroup) {
+                    if constexpr (kGroup == 1) fence();
+                    cpx<TA> qv[kGroup][NM];
 #pragma unroll
-                    for (int t = 0; t < 4; t++) G[k][t] = G[k][t + 1];
-                    G[k][4] = Gk(k, i0[k] + q + 3);
+                    for (int kk = 0; kk < kGroup; kk++) {
+                        const int k = k0 + kk;
+                        const int ic = min(max(i0[k] + q + 3, 0), T - 1);
+                        const cpx<TA> *qr = (k < kGlobalDets ? Qg + (size_t)k * T * NM
+                                                             : smem + (size_t)(k - kGlobalDets) * T * NM) +
+                                            (size_t)ic * NM;
+                        static_for<0, NM>([&](auto A_) {
+                            constexpr int a = decltype(A_)::value;
+                            qv[kk][a] = qr[a];
+                        });
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < kGroup; kk++) {
+                        const int k = k0 + kk;
+#pragma unroll
+                        for (int t = 0; t < 4; t++) G[k][t] = G[k][t + 1];
+                        TA g = (TA)0;
+                        static_for<0, NM>([&](auto A_) {
+                            constexpr int a = decltype(A_)::value;
+                            g = fma(cr[k][a], qv[kk][a].re, g);
+                            g = fma(-cm[k][a], qv[kk][a].im, g);
+                        });
+                        G[k][4] = g;
+                    }
                 }
                 TA x[R];
                 TA cmax = (TA)-INFINITY;
@@ -215,25 +232,18 @@ struct TmargKernel {
 
 template <int S, int K, int POL, bool LDS, int R>
 __global__ void __launch_bounds__(tmarg_block_threads(POL), 1)
-    k_lnl_tmarg(const EvalJob *__restrict__ jobs, const Tile *__restrict__ tiles, const EvalJob single,
-                const int64_t tile) {
+    k_lnl_tmarg(const EvalJob *__restrict__ jobs, const Tile *__restrict__ tiles) {
     extern __shared__ __align__(16) char ile_smem[];
     using TA = typename PolTypes<POL>::TA;
-    if (jobs != nullptr) {
-        const Tile tl = tiles[blockIdx.x];
-        TmargKernel<S, K, POL, LDS, R>::run(jobs[tl.job], tl.begin, tl.end, (cpx<TA> *)ile_smem);
-    } else {
-        const int64_t b = (int64_t)blockIdx.x * tile;
-        const int64_t e = b + tile < single.n ? b + tile : single.n;
-        TmargKernel<S, K, POL, LDS, R>::run(single, b, e, (cpx<TA> *)ile_smem);
-    }
+    const Tile tl = tiles[blockIdx.x];
+    TmargKernel<S, K, POL, LDS, R>::run(jobs[tl.job], tl.begin, tl.end, (cpx<TA> *)ile_smem);
 }
 
 // Launch the time-marginalised kernel of mode set S and policy POL (FP32 or
 // FP64) for oversampling R in {1, 4}.
 template <int S, int POL>
 hipError_t launch_tmarg_sp(int kdet, int R, size_t lds_bytes, const EvalJob *jobs, const Tile *tiles, int n_tiles,
-                           const EvalJob &single, int64_t tile, int nthreads, hipStream_t st) {
+                           int nthreads, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
     const bool lds = lds_bytes > 0;
     if (nthreads <= 0 || nthreads > tmarg_block_threads(POL) || nthreads % 64) return hipErrorInvalidValue;
@@ -251,7 +261,7 @@ hipError_t launch_tmarg_sp(int kdet, int R, size_t lds_bytes, const EvalJob *job
                                                    (int)lds_bytes);
                 if (e != hipSuccess) return e;
             }
-            hipLaunchKernelGGL(fn, grid, block, L ? lds_bytes : 0, st, jobs, tiles, single, tile);
+            hipLaunchKernelGGL(fn, grid, block, L ? lds_bytes : 0, st, jobs, tiles);
             return hipGetLastError();
         }
     };

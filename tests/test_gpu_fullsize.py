@@ -5,7 +5,8 @@ one array and evaluated by one batched launch per kernel (the LDS-staged lnL
 kernel at this size).  The oracle recomputes sampled outputs one by one: the
 draws at sampled indices, lnL of sampled draws of every point (each block
 boundary of the kernels' tiles included), and the estimator of each point on
-seeded log-weights of the full length."""
+seeded log-weights of the full length, and the marginal ln L of the GPU's
+own 2^20 draws of four points against the oracle on those draws."""
 import numpy as np
 import pytest
 
@@ -87,6 +88,25 @@ def test_fullsize_draw_and_lnL(orc, problems, policy):
             worst_s, worst_a = max(worst_s, ms), max(worst_a, ma)
         assert not torch.isnan(L).any().item()
         print(f"{PNAME[policy]} {J} x {N_PER}: max|d| scoped={worst_s:.3e} all={worst_a:.3e}")
+        # the marginal ln L of four points from the GPU's own draws, the whole
+        # 2^20 of each, against the oracle on the same draws: the two loudest
+        # points and two seeded ones
+        res = ile.ile_marginalize_batch(jobs, [N_PER] * J, [W.data_ptr() + j * N_PER * osz for j in range(J)],
+                                        ile.ILE_MARG_RESET, want=True)
+        torch.cuda.synchronize()
+        loud = np.argsort([-r["ln_L"] for r in res])[:2]
+        pick = list(dict.fromkeys([int(loud[0]), int(loud[1])] + [int(v) for v in rng.choice(J, 4, replace=False)]))[:4]
+        tol = 1e-10 if policy == ile.ILE_FP64 else 1e-4
+        worst = 0.0
+        for j in pick:
+            thj = th[:, j * N_PER:(j + 1) * N_PER].double().cpu().numpy()
+            o = orc.marginalize(orc.lnL(problems[j], thj))
+            d = abs(res[j]["ln_L"] - o["ln_L"])
+            print(f"{PNAME[policy]} point {j}: ln L gpu {res[j]['ln_L']:.9f} oracle {o['ln_L']:.9f} "
+                  f"n_eff {o['n_eff']:.1f} |d| {d:.2e}")
+            assert d <= tol, (j, d)
+            worst = max(worst, d)
+        print(f"{PNAME[policy]} marginal of the draws, 4 points: max|d ln L| = {worst:.2e}")
     finally:
         for jb in jobs:
             ile.ile_job_release(jb)

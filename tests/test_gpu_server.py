@@ -82,12 +82,38 @@ def test_mixed_equals_alone(pool):
             assert a == b or (isinstance(a, float) and np.isnan(a) and np.isnan(b)), (k, f, a, b)
 
 
-@pytest.mark.parametrize("policy,tol", [(ile.ILE_FP64, 1e-10), (ile.ILE_FP32_CANCEL64, 1e-4), (ile.ILE_FP32, 1e-3)])
+@pytest.mark.parametrize("policy", [ile.ILE_FP32, ile.ILE_FP64], ids=["fp32", "fp64"])
+def test_mixed_equals_alone_lds_regime(pool, policy):
+    """Ten 2^20-sample jobs of one class submitted together: a pass over them
+    evaluates 10.5M samples of one compiled kernel, past the batched
+    likelihood's LDS-staging threshold, while each job alone runs the
+    unstaged kernel.  Each result equals the job's solo result to the bit."""
+    specs = [(pool[1], policy, False, 1 << 20, 3000 + i, 0) for i in range(10)]
+    srv = ile.ile_server_create(gu.ctx(), max_active=64, chunk_samples=1 << 20)
+    try:
+        ids = [_submit(srv, s)[0] for s in specs]
+        mixed = [_res(ile.ile_server_wait(srv, i, 120000)) for i in ids]
+    finally:
+        ile.ile_server_destroy(srv)
+    for k, s in enumerate(specs):
+        solo = ile.ile_server_create(gu.ctx(), max_active=1, chunk_samples=1 << 20)
+        try:
+            jid, _ = _submit(solo, s)
+            alone = _res(ile.ile_server_wait(solo, jid, 120000))
+        finally:
+            ile.ile_server_destroy(solo)
+        assert mixed[k]["status"] == 0 and alone["status"] == 0
+        for f in FIELDS + ["rounds", "samples"]:
+            a, b = mixed[k][f], alone[f]
+            assert a == b or (isinstance(a, float) and np.isnan(a) and np.isnan(b)), (k, f, a, b)
+
+
+@pytest.mark.parametrize("policy,tol", [(ile.ILE_FP64, 1e-10), (ile.ILE_FP32_CANCEL64, 1e-4), (ile.ILE_FP32, 1e-4)])
 def test_plain_job_matches_oracle(orc, pool, policy, tol):
     """The server's draws are reproduced by the oracle's generator (same key,
     round 0, indices 0..n-1); the served ln L equals the oracle estimator:
-    1e-10 in FP64, 1e-4 with the FP64 cancellation terms, 1e-3 in plain FP32
-    (the pool's sources reach SNR 40, where FP32 rounding is ~eps rho^2)."""
+    1e-10 in FP64, 1e-4 in FP32 and with the FP64 cancellation terms (an
+    SNR-39 source of the pool)."""
     p = pool[1]
     n, seed = 3 * (1 << 14) + 123, 777
     srv = ile.ile_server_create(gu.ctx(), chunk_samples=1 << 14)
