@@ -54,15 +54,19 @@ typedef enum {
     ILE_E_TIMEOUT = -7
 } ile_status;
 
-/* Arithmetic policy.
+/* Arithmetic policy (eq. def:lnL:Decomposed).
  *  ILE_FP64          everything in FP64; theta, ln p - ln p_s, lnL, lw are double.
- *  ILE_FP32          everything in FP32; theta, ln p - ln p_s, lnL, lw are float.
- *  ILE_FP32_CANCEL64 theta and ln p - ln p_s are float; the sky direction and
- *                    detector delays, the interpolation weights, the Q/U/V
- *                    contractions and s T1 - s^2 T2 / 4 are FP64 (the terms whose
- *                    rounding does not cancel near the likelihood peak); the
- *                    polarisation, harmonic and phase factors are FP32;
- *                    lnL and lw are double. */
+ *  ILE_FP32          FP32 contractions, FP32 accumulation; the sky direction and
+ *                    detector delays are FP64 (an FP32 delay moves the phase of
+ *                    Q by enough to move lnL by ~1e-4 at SNR 20); theta,
+ *                    ln p - ln p_s, lnL, lw are float.
+ *  ILE_FP32_CANCEL64 lnL written about a reference point (ile_set_reference):
+ *                    the two rho^2-sized terms that cancel -- the reference
+ *                    amplitudes against the interpolated Q, and their quadratic
+ *                    form in U, V -- are FP64, as are the mode amplitudes
+ *                    s F_k Y_lm; every term in a sample's offset from the
+ *                    reference is an FP32 contraction with FP32 accumulation.
+ *                    theta and ln p - ln p_s are float; lnL and lw are double. */
 typedef enum { ILE_FP64 = 0, ILE_FP32 = 1, ILE_FP32_CANCEL64 = 2 } ile_precision;
 
 typedef struct ile_ctx ile_ctx;
@@ -128,6 +132,22 @@ const char *ile_last_error(void);
 ile_status ile_prepare(ile_ctx *ctx, const ile_problem *problem, ile_job **out);
 ile_status ile_job_info_get(const ile_job *job, ile_job_info *info);
 void ile_job_release(ile_job *job);
+
+/* Reference point of an ILE_FP32_CANCEL64 job (eq. def:lnL:Decomposed written
+ * about a reference, Section "Review of the RIFT likelihood"): that policy
+ * evaluates the two terms of size rho^2 that cancel in lnL -- Re of the
+ * reference amplitudes against the interpolated Q, and the reference's
+ * quadratic form in U, V -- in FP64, and everything that depends on a
+ * sample's offset from the reference in FP32.  lnL does not depend on the
+ * reference (up to rounding); its FP32 rounding shrinks with the samples'
+ * distance from it, so the reference should sit near the samples that carry
+ * the weight.  theta_ref: host [7] (alpha, delta, t, D, cos iota, phi_c, psi);
+ * a point outside the support clears the reference (plain FP32 arithmetic,
+ * the state after ile_prepare).  ile_set_proposal and ile_adapt_proposal set
+ * it to the mean of the mixture's heaviest component.  Built on the device on
+ * `stream` (the call waits for the small upload).  No effect for the other
+ * policies. */
+ile_status ile_set_reference(ile_job *job, const double *theta_ref, ile_stream stream);
 
 /* Per-sample lnL, eq. (def:lnL:Decomposed).
  * theta: device [7][ld] (float or double by policy), columns (alpha, delta, t,

@@ -134,6 +134,7 @@ EXPORTS = {
     "ile_eval_lnL_tmarg_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int64),
                                            C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_void_p),
                                            C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32, C.c_void_p]),
+    "ile_set_reference": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
     "ile_marginalize": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_uint32, C.POINTER(ile_marg),
                                   C.c_void_p]),
     "ile_marginalize_noalloc": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_uint32, C.POINTER(ile_marg),
@@ -308,6 +309,11 @@ def ile_eval_lnL_tmarg_batch(jobs, n, theta, ld, lnpmps, lnL_out, lw_out=None, o
         VP(*[_p(t) for t in lnpmps]) if lnpmps is not None else None,
         VP(*[_p(t) for t in lnL_out]),
         VP(*[_p(t) for t in lw_out]) if lw_out is not None else None, oversample, _s(stream)))
+
+
+def ile_set_reference(job, theta_ref, stream=None):
+    t = (C.c_double * 7)(*[float(v) for v in theta_ref])
+    _chk(lib().ile_set_reference(job, t, _s(stream)))
 
 
 def ile_marginalize(job, n, lw, flags=ILE_MARG_RESET, want=True, stream=None):

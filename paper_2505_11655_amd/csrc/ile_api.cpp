@@ -58,7 +58,8 @@ hipError_t launch_eval(int set, int kdet, int policy, bool dm, size_t lds_bytes,
     if (set == S) {                                                                                          \
         if (policy == 0) return launch_eval_sp<S, 0>(kdet, dm, lds_bytes, d_jobs, d_tiles, n_tiles, block, st); \
         if (policy == 1) return launch_eval_sp<S, 1>(kdet, dm, lds_bytes, d_jobs, d_tiles, n_tiles, block, st); \
-        if (policy == 2) return launch_eval_sp<S, 2>(kdet, dm, lds_bytes, d_jobs, d_tiles, n_tiles, block, st); \
+        if (policy == 2) return dm ? hipErrorInvalidValue                                                 \
+                                   : launch_ref_sp<S>(kdet, lds_bytes, d_jobs, d_tiles, n_tiles, block, st); \
     }
     ILE_SP(0)
     ILE_SP(1)
@@ -84,7 +85,8 @@ hipError_t launch_tmarg(int set, int kdet, int policy, int R, size_t lds_bytes, 
 }
 
 // Contraction element size of a policy (Q, U, V storage).
-static size_t creal_size(int policy) { return policy == kFP32 ? sizeof(float) : sizeof(double); }
+// (FP32 windows in the FP32 + FP64-cancellation policy as well)
+static size_t creal_size(int policy) { return policy == kFP64 ? sizeof(double) : sizeof(float); }
 size_t theta_size(int policy) { return policy == kFP64 ? sizeof(double) : sizeof(float); }
 size_t out_size(int policy) { return policy == kFP32 ? sizeof(float) : sizeof(double); }
 
@@ -98,7 +100,8 @@ static int job_global_dets(const ile_job *job, bool tmarg) {
 }
 size_t job_window_bytes(const ile_job *job, bool tmarg) {
     const int staged = job->kp - job_global_dets(job, tmarg);
-    return (size_t)std::max(staged, 0) * job->n_time * kSets[job->set].n * 2 * creal_size(job->policy);
+    const size_t series = job->policy == kMixed ? (size_t)job->kp * job->n_time * sizeof(double) : 0;
+    return (size_t)std::max(staged, 0) * job->n_time * kSets[job->set].n * 2 * creal_size(job->policy) + series;
 }
 bool job_lds_ok(const ile_job *job, bool tmarg) {
     const bool compiled = tmarg ? tmarg_lds_compiled(job->set, job->kp, job->policy)
@@ -363,6 +366,57 @@ void fill_tables(const ile_problem *P, const std::vector<int> &keep, const std::
     }
 }
 
+// FP32 + FP64-cancellation policy: U and V as full [kp][NM][NM] complex FP64
+// matrices in slot order (Hermitian / symmetric parts), and the pair weights
+// of the offset form, [kp][P] x (Ur + Vr, Ur - Vr, -Ui - Vi, Ui - Vi), doubled
+// off the diagonal, pairs a <= b in their plain order.
+void fill_mixed(const ile_problem *P, const std::vector<int> &keep, const std::vector<int> &slot, int set, int kp,
+                std::vector<double> &U64, std::vector<double> &V64, std::vector<float> &W) {
+    using cd = std::complex<double>;
+    const int NM = kSets[set].n, K = P->n_det, n = P->n_modes;
+    const PairTable pt = make_pairs(set);
+    std::vector<int> user(NM, -1);
+    for (size_t q = 0; q < keep.size(); q++) user[slot[q]] = keep[q];
+    auto U = [&](int k, int a, int b) {
+        const double *p = P->U + 2 * (((size_t)k * n + a) * n + b);
+        return cd(p[0], p[1]);
+    };
+    auto V = [&](int k, int a, int b) {
+        if (!P->V) return cd(0, 0);
+        const double *p = P->V + 2 * (((size_t)k * n + a) * n + b);
+        return cd(p[0], p[1]);
+    };
+    U64.assign((size_t)kp * NM * NM * 2, 0.0);
+    V64.assign((size_t)kp * NM * NM * 2, 0.0);
+    W.assign((size_t)kp * pt.P * 4, 0.0f);
+    for (int k = 0; k < K; k++)
+        for (int sa = 0; sa < NM; sa++)
+            for (int sb = 0; sb < NM; sb++) {
+                const int ua = user[sa], ub = user[sb];
+                if (ua < 0 || ub < 0) continue;
+                cd h = 0.5 * (U(k, ua, ub) + std::conj(U(k, ub, ua)));
+                if (sa == sb) h = cd(h.real(), 0.0);
+                const cd v = 0.5 * (V(k, ua, ub) + V(k, ub, ua));
+                const size_t o = 2 * (((size_t)k * NM + sa) * NM + sb);
+                U64[o] = h.real();
+                U64[o + 1] = h.imag();
+                V64[o] = v.real();
+                V64[o + 1] = v.imag();
+            }
+    for (int k = 0; k < K; k++)
+        for (int p = 0; p < pt.P; p++) {
+            const int sa = pt.a[p], sb = pt.b[p];
+            const size_t o = 2 * (((size_t)k * NM + sa) * NM + sb);
+            const double ur = U64[o], ui = U64[o + 1], vr = V64[o], vi = V64[o + 1];
+            const double f = sa == sb ? 1.0 : 2.0;
+            float *w = &W[4 * ((size_t)k * pt.P + p)];
+            w[0] = (float)(f * (ur + vr));
+            w[1] = (float)(f * (ur - vr));
+            w[2] = (float)(f * (-ui - vi));
+            w[3] = (float)(f * (ui - vi));
+        }
+}
+
 }  // namespace
 
 extern "C" ile_status ile_prepare(ile_ctx *ctx, const ile_problem *P, ile_job **out) {
@@ -381,6 +435,8 @@ ile_status ile::job_create(ile_ctx *ctx, const ile_problem *P, ile_job **out, hi
     if (!P->mode_l || !P->mode_m || !P->det_pos || !P->det_resp || !P->Q || !P->U)
         return set_err(ILE_E_INVALID, "null input array");
     if (P->precision < 0 || P->precision > 2) return set_err(ILE_E_INVALID, "unknown precision policy");
+    if (P->precision == kMixed && P->prior.dist_marg)
+        return set_err(ILE_E_INVALID, "the distance table is not available with ILE_FP32_CANCEL64");
     if (!(P->dt_s > 0) || !std::isfinite(P->tau0_s) || !std::isfinite(P->gmst_rad))
         return set_err(ILE_E_INVALID, "bad window or gmst");
     if (!(P->d_ref_mpc > 0)) return set_err(ILE_E_INVALID, "d_ref must be > 0");
@@ -478,12 +534,23 @@ ile_status ile::job_create(ile_ctx *ctx, const ile_problem *P, ile_job **out, hi
     job->pr = PriorDev{P->prior.t_window, P->prior.d_min, P->prior.d_max, P->d_ref_mpc, job->dist_marg ? 1 : 0};
 
     std::vector<char> Qb, Ub, Vb;
+    std::vector<double> q64, u64, v64;   // mixed policy: the reference builder's inputs
     if (job->policy == kFP32) {
         std::vector<float> q, u, v;
         fill_tables<float>(P, keep, slot, set, kp, q, u, v);
         Qb.assign((char *)q.data(), (char *)(q.data() + q.size()));
         Ub.assign((char *)u.data(), (char *)(u.data() + u.size()));
         Vb.assign((char *)v.data(), (char *)(v.data() + v.size()));
+    } else if (job->policy == kMixed) {
+        // FP32 window and offset-form pair weights for the kernel; FP64
+        // window and overlaps for the reference builder
+        std::vector<float> q, u, v, w;
+        fill_tables<float>(P, keep, slot, set, kp, q, u, v);
+        std::vector<double> ud, vd;
+        fill_tables<double>(P, keep, slot, set, kp, q64, ud, vd);
+        fill_mixed(P, keep, slot, set, kp, u64, v64, w);
+        Qb.assign((char *)q.data(), (char *)(q.data() + q.size()));
+        Ub.assign((char *)w.data(), (char *)(w.data() + w.size()));
     } else {
         std::vector<double> q, u, v;
         fill_tables<double>(P, keep, slot, set, kp, q, u, v);
@@ -500,17 +567,40 @@ ile_status ile::job_create(ile_ctx *ctx, const ile_problem *P, ile_job **out, hi
     // one blob [Q | U table | V table | estimator state], 256-byte aligned parts
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t oQ = 0, oU = al(Qb.size()), oV = oU + al(Ub.size()), oM = oV + al(Vb.size());
-    job->blob_bytes = oM + al(sizeof(MargState));
+    // mixed policy: [FP64 window | U | V | r, G (FP32) | R series | C0 | reference point]
+    const int NMs = kSets[set].n;
+    const size_t rg_bytes = job->policy == kMixed ? (size_t)2 * kp * NMs * 2 * sizeof(float) : 0;
+    const size_t R_bytes = job->policy == kMixed ? (size_t)kp * T * sizeof(double) : 0;
+    const size_t oQ64 = oM + al(sizeof(MargState)), oU64 = oQ64 + al(q64.size() * 8), oV64 = oU64 + al(u64.size() * 8);
+    const size_t org = oV64 + al(v64.size() * 8), oR = org + al(rg_bytes), oC0 = oR + al(R_bytes);
+    const size_t oTh = oC0 + (job->policy == kMixed ? 256 : 0);
+    job->blob_bytes = job->policy == kMixed ? oTh + al(7 * sizeof(double)) : oM + al(sizeof(MargState));
     if ((s = ctx_alloc(ctx, &job->d_blob, job->blob_bytes, "job inputs")) != ILE_OK) return cleanup(s);
     job->h_blob = pin_alloc(ctx, job->blob_bytes);
     job->h_ms = (MargState *)pin_alloc(ctx, sizeof(MargState));
     if (!job->h_blob || !job->h_ms) return cleanup(set_err(ILE_E_NOMEM, "pinned staging"));
     char *hb = (char *)job->h_blob;
+    std::memset(hb, 0, job->blob_bytes);      // mixed: no reference until one is set (r = 0)
     std::memcpy(hb + oQ, Qb.data(), Qb.size());
     std::memcpy(hb + oU, Ub.data(), Ub.size());
     std::memcpy(hb + oV, Vb.data(), Vb.size());
     const MargState ms0{-INFINITY, 0.0, 0.0, 0, 0, -1};
     std::memcpy(hb + oM, &ms0, sizeof ms0);
+    if (job->policy == kMixed) {
+        std::memcpy(hb + oQ64, q64.data(), q64.size() * 8);
+        std::memcpy(hb + oU64, u64.data(), u64.size() * 8);
+        std::memcpy(hb + oV64, v64.data(), v64.size() * 8);
+        char *db = (char *)job->d_blob;
+        job->rb.theta_ref = (const double *)(db + oTh);
+        job->rb.Q64 = (const double *)(db + oQ64);
+        job->rb.U64 = (const double *)(db + oU64);
+        job->rb.V64 = (const double *)(db + oV64);
+        job->rb.rg = (float *)(db + org);
+        job->rb.R = (double *)(db + oR);
+        job->rb.C0 = (double *)(db + oC0);
+        job->h_ref = (double *)pin_alloc(ctx, 7 * sizeof(double));
+        if (!job->h_ref) return cleanup(set_err(ILE_E_NOMEM, "pinned staging"));
+    }
     job->d_Q = (char *)job->d_blob + oQ;
     job->d_Ut = (char *)job->d_blob + oU;
     job->d_Vt = (char *)job->d_blob + oV;
@@ -524,6 +614,9 @@ ile_status ile::job_create(ile_ctx *ctx, const ile_problem *P, ile_job **out, hi
     ej.Q = job->d_Q;
     ej.Ut = job->d_Ut;
     ej.Vt = job->d_Vt;
+    ej.ref_rg = job->rb.rg;
+    ej.ref_R = job->rb.R;
+    ej.ref_C0 = job->rb.C0;
     ej.tau0 = P->tau0_s;
     ej.inv_dt = 1.0 / P->dt_s;
     ej.gmst = P->gmst_rad;
@@ -551,7 +644,7 @@ ile_status ile::job_create(ile_ctx *ctx, const ile_problem *P, ile_job **out, hi
     if (job->dist_marg) {
         if ((s = ctx_dist_table(ctx, job->pr, &ej.dt, nullptr)) != ILE_OK) return cleanup(s);
     }
-    job->device_bytes = Qb.size() + Ub.size() + Vb.size() + sizeof(MargState);
+    job->device_bytes = job->blob_bytes;
     *out = job;
     return ILE_OK;
 }
@@ -582,6 +675,7 @@ void ile::job_release_nosync(ile_job *job) {
     pin_free(ctx, job->h_blob, job->blob_bytes);
     pin_free(ctx, job->h_ms, sizeof(MargState));
     pin_free(ctx, job->h_gmm, sizeof(GmmDev));
+    pin_free(ctx, job->h_ref, 7 * sizeof(double));
     delete job;
 }
 
@@ -590,6 +684,39 @@ extern "C" void ile_job_release(ile_job *job) {
     (void)hipSetDevice(job->ctx->device);
     (void)hipDeviceSynchronize();   // the caller's queued work may still use the buffers
     job_release_nosync(job);
+}
+
+// ================================================================ reference
+namespace ile {
+// Rebuild a mixed-policy job's reference terms from the point at
+// job->rb.theta_ref (on the stream).
+ile_status ref_rebuild(ile_job *job, hipStream_t st) {
+    hipError_t e = launch_ref_build(job->set, job->kp, job->ej, job->rb, st);
+    if (e != hipSuccess) return dev_fail(job->ctx, e, "reference build");
+    return ILE_OK;
+}
+// Mixed-policy jobs: the reference point becomes the mean of the heaviest
+// component of the job's (device) mixture.
+ile_status ref_from_proposal(ile_job *job, hipStream_t st) {
+    if (job->policy != kMixed || !job->d_gmm) return ILE_OK;
+    hipError_t e = launch_ref_from_gmm(job->d_gmm, job->pr, (double *)job->rb.theta_ref, st);
+    if (e != hipSuccess) return dev_fail(job->ctx, e, "reference from mixture");
+    return ref_rebuild(job, st);
+}
+}  // namespace ile
+
+extern "C" ile_status ile_set_reference(ile_job *job, const double *theta_ref, ile_stream stream) {
+    if (!job || !theta_ref) return set_err(ILE_E_INVALID, "null argument");
+    ile_status s = ctx_check(job->ctx);
+    if (s != ILE_OK) return s;
+    if (job->policy != kMixed) return ILE_OK;
+    hipStream_t st = (hipStream_t)stream;
+    // the pinned staging is reused by the next call: copy and wait
+    std::memcpy(job->h_ref, theta_ref, 7 * sizeof(double));
+    hipError_t e = hipMemcpyAsync((void *)job->rb.theta_ref, job->h_ref, 7 * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return dev_fail(job->ctx, e, "reference upload");
+    return ref_rebuild(job, st);
 }
 
 // ===================================================================== eval
@@ -1011,7 +1138,7 @@ extern "C" ile_status ile_set_proposal(ile_job *job, const ile_gmm_params *p, co
         return dev_fail(job->ctx, e, "proposal readback");
     if (!job->h_gmm->valid) return set_err(ILE_E_INVALID, "a covariance is not positive definite");
     job->has_prop = true;
-    return ILE_OK;
+    return ref_from_proposal(job, st);
 }
 
 extern "C" ile_status ile_get_proposal(ile_job *job, ile_gmm_params *p, ile_stream stream) {
@@ -1098,7 +1225,11 @@ ile_status adapt_batch(ile_ctx *ctx, int policy, const std::vector<AdaptItem> &i
         if (e != hipSuccess) return dev_fail(ctx, e, "batched mixture refit");
         if ((s = batch_done(ctx, slot, st)) != ILE_OK) return s;
     }
-    for (const AdaptItem &it : items) it.job->has_prop = true;
+    for (const AdaptItem &it : items) {
+        it.job->has_prop = true;
+        ile_status s = ref_from_proposal(it.job, st);
+        if (s != ILE_OK) return s;
+    }
     return ILE_OK;
 }
 

@@ -77,6 +77,11 @@ struct ile_job {
     // fair-draw scratch (prefix sums of the sample masses), grown as needed
     void *fair_mem = nullptr;
     size_t fair_cap = 0;
+    // FP32 + FP64-cancellation policy: the FP64 window and overlaps its
+    // reference terms are built from, and where those terms live (all in the
+    // job's blob); pinned staging of a reference point set from the host
+    ile::RefBuild rb{};
+    double *h_ref = nullptr;
 };
 
 namespace ile {
@@ -88,26 +93,27 @@ extern template hipError_t launch_eval_sp<0, 0>(int, bool, size_t, const EvalJob
                                                    int, hipStream_t);
 extern template hipError_t launch_eval_sp<0, 1>(int, bool, size_t, const EvalJob *, const Tile *, int,
                                                    int, hipStream_t);
-extern template hipError_t launch_eval_sp<0, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   int, hipStream_t);
 extern template hipError_t launch_eval_sp<1, 0>(int, bool, size_t, const EvalJob *, const Tile *, int,
                                                    int, hipStream_t);
 extern template hipError_t launch_eval_sp<1, 1>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   int, hipStream_t);
-extern template hipError_t launch_eval_sp<1, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
                                                    int, hipStream_t);
 extern template hipError_t launch_eval_sp<2, 0>(int, bool, size_t, const EvalJob *, const Tile *, int,
                                                    int, hipStream_t);
 extern template hipError_t launch_eval_sp<2, 1>(int, bool, size_t, const EvalJob *, const Tile *, int,
                                                    int, hipStream_t);
-extern template hipError_t launch_eval_sp<2, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   int, hipStream_t);
 extern template hipError_t launch_eval_sp<3, 0>(int, bool, size_t, const EvalJob *, const Tile *, int,
                                                    int, hipStream_t);
 extern template hipError_t launch_eval_sp<3, 1>(int, bool, size_t, const EvalJob *, const Tile *, int,
                                                    int, hipStream_t);
-extern template hipError_t launch_eval_sp<3, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                                   int, hipStream_t);
+
+// The FP32 + FP64-cancellation policy's kernel (reference-subtracted form).
+template <int S>
+hipError_t launch_ref_sp(int kdet, size_t lds_bytes, const EvalJob *jobs, const Tile *tiles, int n_tiles,
+                         int nthreads, hipStream_t st);
+extern template hipError_t launch_ref_sp<0>(int, size_t, const EvalJob *, const Tile *, int, int, hipStream_t);
+extern template hipError_t launch_ref_sp<1>(int, size_t, const EvalJob *, const Tile *, int, int, hipStream_t);
+extern template hipError_t launch_ref_sp<2>(int, size_t, const EvalJob *, const Tile *, int, int, hipStream_t);
+extern template hipError_t launch_ref_sp<3>(int, size_t, const EvalJob *, const Tile *, int, int, hipStream_t);
 
 template <int S, int POL>
 hipError_t launch_tmarg_sp(int kdet, int R, size_t lds_bytes, const EvalJob *jobs, const Tile *tiles, int n_tiles,
@@ -186,6 +192,10 @@ struct AdaptItem {
 ile_status adapt_batch(ile_ctx *ctx, int policy, const std::vector<AdaptItem> &items, const ile_gmm_opts *o,
                        hipStream_t st);
 void marg_from_state(const MargState &m, ile_marg *out);
+// Mixed policy: rebuild the reference terms from job->rb.theta_ref, or set
+// that point from the job's mixture first (no-ops for the other policies).
+ile_status ref_rebuild(ile_job *job, hipStream_t st);
+ile_status ref_from_proposal(ile_job *job, hipStream_t st);
 // Look up the no-alloc estimator's scratch address on a device (the device
 // must be current); done once per device, by ile_ctx_create.
 ile_status noalloc_init_device(int device);

@@ -15,11 +15,14 @@ enum Policy : int { kFP64 = 0, kFP32 = 1, kMixed = 2 };
 
 // Threads per block of the LDS-staged likelihood kernel: one window per CU,
 // as many waves as the register use of the mode set (index 0..3, 5/9/17/21
-// modes) and policy allows without spilling: 1024 (128 VGPRs) only for FP32
-// with up to 9 modes, 256 for the 21-mode set (its window leaves room for one
-// block per CU anyway), 512 otherwise.
+// modes) and policy allows without spilling: 1024 (128 VGPRs) for FP32 and
+// FP32 + FP64 cancellation with up to 9 modes, 256 for the 21-mode set (its
+// window leaves room for one block per CU anyway) and for FP64 with 17 modes,
+// 512 otherwise.
 constexpr int lds_block_threads(int set, int policy) {
-    return (policy == kFP32 && set <= 1) ? 1024 : ((set >= 3 || (set == 2 && policy != kFP32)) ? 256 : 512);
+    return ((policy == kFP32 || policy == kMixed) && set <= 1) ? 1024
+           : (set >= 3 || (set == 2 && policy == kFP64))       ? 256
+                                                               : 512;
 }
 // Threads per block of the time-marginalised kernel (its per-sample state is
 // larger than the pointwise kernel's: two waves per SIMD in FP32, one in FP64).
@@ -48,10 +51,13 @@ constexpr ModeList kSets[kNumSets] = {
 // L1/L2 instead of LDS: the fewest that bring the staged part of the compiled
 // 410-sample windows within 160 KiB (kp: compiled detector count; kp when not
 // even one detector fits).
+// The FP32 + FP64-cancellation policy stages FP32 windows and, for every
+// detector, its FP64 reference series (410 doubles).
 constexpr int lds_global_dets(int set, int kp, int policy) {
-    const long per = 410L * kSets[set].n * 2 * (policy == kFP32 ? 4 : 8);
+    const long per = 410L * kSets[set].n * 2 * (policy == kFP64 ? 8 : 4);
+    const long fixed = policy == kMixed ? 410L * 8 * kp : 0;
     for (int g = 0; g < kp; g++)
-        if ((kp - g) * per <= 163840L) return g;
+        if ((kp - g) * per + fixed <= 163840L) return g;
     return kp;
 }
 // The time-marginalised kernel always reads at least the first detector
@@ -209,9 +215,13 @@ struct DistTable {
 };
 
 struct EvalJob {
-    const void *Q;        // [Kp][T][NM] complex, policy contraction type
-    const void *Ut;       // [P][Kp] complex, U-order, weighted
-    const void *Vt;       // [P][Kp] complex, V-order, weighted
+    const void *Q;        // [Kp][T][NM] complex, policy contraction type (FP32 in the mixed policy)
+    const void *Ut;       // [P][Kp] complex, U-order, weighted; mixed policy: [Kp][P] float4 pair weights
+    const void *Vt;       // [P][Kp] complex, V-order, weighted (unused by the mixed policy)
+    // mixed policy: the reference terms (written on the device by k_ref_build)
+    const float *ref_rg;  // r [Kp][NM] then G [Kp][NM], complex FP32
+    const double *ref_R;  // [Kp][T] Re(r^+ Q)
+    const double *ref_C0; // C0
     DistTable dt;
     double tau0, inv_dt, gmst, d_ref;
     double xc[3][3];      // detector position / c (seconds)
@@ -229,6 +239,16 @@ struct EvalJob {
     void *lw;
     int64_t n;            // samples of this job in the launch
     double tm_lnw;        // time-marginalised launches: ln(dt / (R 2 t_w)) per node
+};
+
+// Where the reference builder of a mixed-policy job reads and writes.
+struct RefBuild {
+    const double *theta_ref;  // [7]
+    const double *Q64;        // [Kp][T][NM] complex FP64
+    const double *U64, *V64;  // [Kp][NM][NM] complex FP64 (slot order)
+    float *rg;                // -> EvalJob::ref_rg
+    double *R;                // -> EvalJob::ref_R
+    double *C0;               // -> EvalJob::ref_C0
 };
 
 struct Tile {
@@ -321,6 +341,11 @@ struct DrawJob {
 hipError_t launch_eval(int set, int kdet, int policy, bool dist_marg, size_t lds_bytes,
                        const EvalJob *d_jobs, const Tile *d_tiles, int n_tiles, int block, hipStream_t st);
 size_t eval_lds_limit();
+// Mixed policy: rebuild a job's reference terms (one block) from the
+// reference point at rb.theta_ref; and set that point to the mean of the
+// heaviest component of a mixture (non-mixture columns: prior midpoints).
+hipError_t launch_ref_build(int set, int kdet, const EvalJob &job, const RefBuild &rb, hipStream_t st);
+hipError_t launch_ref_from_gmm(const GmmDev *g, PriorDev pr, double *theta_ref, hipStream_t st);
 
 hipError_t launch_marg_partials(int policy, const void *lw, int64_t n, int64_t tile,
                                 MargPartial *d_part, hipStream_t st);

@@ -1,7 +1,6 @@
-// Instantiations of the fused likelihood kernel: compiled mode set 3, mixed policy.
-#include "k_lnl_impl.h"
+// Instantiations of the likelihood kernel of the FP32 + FP64-cancellation policy: compiled mode set 3.
+#include "k_lnl_ref_impl.h"
 
 namespace ile {
-template hipError_t launch_eval_sp<3, 2>(int, bool, size_t, const EvalJob *, const Tile *, int,
-                                           int, hipStream_t);
+template hipError_t launch_ref_sp<3>(int, size_t, const EvalJob *, const Tile *, int, int, hipStream_t);
 }  // namespace ile

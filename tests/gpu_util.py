@@ -58,4 +58,9 @@ def tol_check(got, ref, T1, T2, s, policy, scope_abs=1e-3):
         return ok, float(d.max()), float(d.max())
     top = r >= r.max() - 50
     ok = np.all(d[top] <= scope_abs) and np.all(d <= scope_abs + 1e-6 * mag)
+    if not ok:
+        w = int(np.argmax(d / (scope_abs + 1e-6 * mag)))
+        print(f"tol_check worst: |d|={d[w]:.3e} lnL={r[w]:.6g} mag={mag[w]:.6g} "
+              f"sT1={float((s * T1)[~inf_ref][w]):.6g} s2T2/4={float((s * s * T2 / 4)[~inf_ref][w]):.6g} "
+              f"scoped={bool(top[w])}")
     return ok, float(d[top].max()), float(d.max())

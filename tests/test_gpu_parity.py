@@ -30,10 +30,12 @@ def _np_theta(th, policy):
     return np.ascontiguousarray(th.astype(np.float64 if policy == ile.ILE_FP64 else np.float32))
 
 
-def _run(orc, prob, th, policy, lnpmps=None, eps=0.0):
+def _run(orc, prob, th, policy, lnpmps=None, eps=0.0, ref=None):
     ph = ile.ProblemHost(prob, precision=policy, mode_filter_eps=eps)
     job = ile.ile_prepare(gu.ctx(), ph)
     try:
+        if ref is not None:
+            ile.ile_set_reference(job, ref)
         L, W = gu.gpu_eval(job, th, policy, lnpmps)
     finally:
         ile.ile_job_release(job)
@@ -66,8 +68,8 @@ def test_eval_prior_samples(orc, recs, policy, cfg):
 @pytest.mark.parametrize("snr", [100.0, 400.0])
 def test_eval_precision_strong_source(orc, recs, snr):
     """Loud edge-on q = 20 source, 17 modes, samples near the peak: the
-    FP32 + FP64-cancellation policy meets 1e-3 per sample (scoped); plain FP32
-    is reported for contrast."""
+    FP32 + FP64-cancellation policy, its reference at the box centre, meets
+    1e-3 per sample (scoped); plain FP32 is reported for contrast."""
     probs, _ = chirpgen.build_event(recs["c3"], ["H", "L", "V"], 17, 30.0, 20.0, snr, noise_seed=5)
     th0 = np.array(recs["c3"]["theta"])
     sc = 100.0 / snr
@@ -77,7 +79,7 @@ def test_eval_precision_strong_source(orc, recs, snr):
     res = {}
     for policy in (ile.ILE_FP32_CANCEL64, ile.ILE_FP32):
         th = _np_theta(thd, policy)
-        L, W, ref, T1, T2, s = _run(orc, probs[0], th, policy)
+        L, W, ref, T1, T2, s = _run(orc, probs[0], th, policy, ref=th0)
         ok, ms, ma = gu.tol_check(L, ref, T1, T2, s, policy)
         res[policy] = (ok, ms, ma, float(np.max(ref)))
         print(f"SNR {snr} {PNAME[policy]} max lnL={np.max(ref):.1f} max|d| scoped={ms:.3e} all={ma:.3e}")
@@ -91,10 +93,10 @@ def test_c3_marginal_matches_oracle(orc, recs, snr):
     mixture over the 7 extrinsic parameters (means scattered by sigma/2
     about the injection, covariance diag(sigma^2), sigma shrinking as 1/SNR)
     with their ln p - ln p_s.  GPU lnL + estimator against the oracle on the
-    same draws and weights: the FP32 + FP64-cancellation policy within 1e-4
-    on the marginal ln L.  Per-sample errors of both policies are reported
-    (their bounds are checked by test_eval_precision_strong_source); plain
-    FP32's lw alone is quantised to ~1e-2 at lnL ~ 8e4."""
+    same draws and weights, the mixture also set on the job (which places
+    the reference of the FP32 + FP64-cancellation policy): that policy within
+    1e-4 on the marginal ln L and 1e-3 per sample (scoped).  Plain FP32 is
+    reported; its lw alone is quantised to ~1e-2 at lnL ~ 8e4."""
     probs, _ = chirpgen.build_event(recs["c3"], ["H", "L", "V"], 17, 30.0, 20.0, snr, noise_seed=5)
     prob = probs[0]
     th0 = np.array(recs["c3"]["theta"])
@@ -111,6 +113,9 @@ def test_c3_marginal_matches_oracle(orc, recs, snr):
         lr = lrd.astype(th.dtype)
         job = ile.ile_prepare(gu.ctx(), ile.ProblemHost(prob, precision=policy))
         try:
+            # the same mixture on the job: the FP32 + FP64-cancellation policy
+            # takes its reference from it (the heaviest component's mean)
+            ile.ile_set_proposal(job, ile.gmm_params(np.full(8, 1.0 / 8), means, covs))
             L, W = gu.gpu_eval(job, th, policy, lr)
             r = _gpu_marg(job, W, ile.ILE_FP64 if policy == ile.ILE_FP32_CANCEL64 else policy)
         finally:
@@ -121,7 +126,29 @@ def test_c3_marginal_matches_oracle(orc, recs, snr):
         out[policy] = (abs(r["ln_L"] - o["ln_L"]), ok, ms)
         print(f"C3 SNR {snr} {PNAME[policy]}: ln L gpu {r['ln_L']:.6f} oracle {o['ln_L']:.6f} "
               f"|d| {out[policy][0]:.2e} n_eff {o['n_eff']:.1f} max|d lnL| scoped {ms:.2e}")
-    assert out[ile.ILE_FP32_CANCEL64][0] <= 1e-4
+    d, ok, ms = out[ile.ILE_FP32_CANCEL64]
+    assert d <= 1e-4 and ms <= 1e-3
+
+
+@pytest.mark.parametrize("where", ["none", "near", "far", "outside"])
+def test_reference_independence(orc, recs, where):
+    """FP32 + FP64 cancellation: lnL does not depend on the reference point
+    beyond rounding.  SNR-20 HLV 9-mode event, prior draws and a box about
+    the injection; reference none, at the injection, at a far prior draw, and
+    outside the support (clears it).  Every case within the per-sample bound."""
+    probs, _ = chirpgen.build_event(recs["c2"], ["H", "L", "V"], 9, 30.0, 2.0, 20.0, noise_seed=7)
+    th0 = np.array(recs["c2"]["theta"])
+    rng = np.random.default_rng(41)
+    thp = chirpgen.prior_samples(rng, 20000)
+    thb = chirpgen.box_samples(rng, 20000, th0, np.array([0.03, 0.03, 3e-4, 0.1 * th0[3], 0.05, 0.2, 0.2]))
+    thd = np.concatenate([thp, thb], axis=1)
+    ref_pt = {"none": None, "near": th0, "far": thp[:, 17].copy(),
+              "outside": np.array([1.0, 0.2, 0.0, -5.0, 0.3, 1.0, 1.0])}[where]
+    th = _np_theta(thd, ile.ILE_FP32_CANCEL64)
+    L, W, ref, T1, T2, s = _run(orc, probs[0], th, ile.ILE_FP32_CANCEL64, ref=ref_pt)
+    ok, ms, ma = gu.tol_check(L, ref, T1, T2, s, ile.ILE_FP32_CANCEL64)
+    print(f"reference {where}: max|d| scoped={ms:.3e} all={ma:.3e}")
+    assert ok
 
 
 @pytest.mark.parametrize("policy", POLICIES, ids=[PNAME[p] for p in POLICIES])
