@@ -75,7 +75,8 @@ def make_problems(n_points, seed):
 
 def config_problems(name, n_points=1, snr=None):
     """The other configurations of the workload: C1 (HL, 5 modes, SNR 20) and
-    C3 (HLV, 17 modes, mass ratio 20, SNR 100 by default)."""
+    C3 (HLV, 17 modes, mass ratio 20, SNR 100 by default, the template at the
+    injected parameters; one noise realisation per point)."""
     import chirpgen
     recs = chirpgen.load_injections()
     rng = np.random.default_rng(7)
@@ -85,41 +86,97 @@ def config_problems(name, n_points=1, snr=None):
         probs, _ = chirpgen.build_event(recs["c1"], ["H", "L"], 5, 30.0, 2.0, 20.0 if snr is None else snr,
                                         noise_seed=chirpgen.BASE_SEED + 11, templates=templates)
     else:
-        templates = [(30.0, 20.0)] + [(float(rng.uniform(28, 32)), float(rng.uniform(15, 25)))
-                                      for _ in range(n_points - 1)]
-        probs, _ = chirpgen.build_event(recs["c3"], ["H", "L", "V"], 17, 30.0, 20.0, 100.0 if snr is None else snr,
-                                        noise_seed=chirpgen.BASE_SEED + 13, templates=templates)
+        # the precision configuration has its template at the true parameters:
+        # n_points independent noise realisations of that one event
+        probs = []
+        for i in range(n_points):
+            pr, _ = chirpgen.build_event(recs["c3"], ["H", "L", "V"], 17, 30.0, 20.0, 100.0 if snr is None else snr,
+                                         noise_seed=chirpgen.BASE_SEED + 13 + 101 * i, templates=[(30.0, 20.0)])
+            probs += pr
     return probs
+
+
+def c3_proposal(snr):
+    """The precision configuration's proposal: a narrow 8-component mixture
+    over the 7 extrinsic parameters, means scattered by sigma/2 about the
+    injection, covariance diag(sigma^2), sigma shrinking as 1/SNR."""
+    import chirpgen
+    th0 = np.array(chirpgen.load_injections()["c3"]["theta"])
+    sig = np.array([0.01, 0.01, 1e-4, 0.05 * th0[3], 0.02, 0.05, 0.05]) * (100.0 / snr)
+    rng = np.random.default_rng(31)
+    means = th0[None, :] + rng.normal(size=(8, 7)) * sig[None, :] / 2
+    return np.full(8, 1.0 / 8), means, [np.diag(sig ** 2)] * 8
 
 
 def configs_leg(ile, torch, ctx, stream):
     """Draw + lnL + estimator throughput of the C1 and C3 configurations, per
-    precision policy (the same step as the C2 benchmark)."""
+    precision policy (the same step as the C2 benchmark).  C3 draws from its
+    narrow mixture proposal (set on every job; FP32 + FP64-cancellation jobs
+    then move their reference to their best pilot sample), at SNR 100 and
+    400, and compares every policy's marginal ln L with FP64's on one set of
+    draws."""
     c1 = config_problems("c1")
-    c3 = config_problems("c3", n_points=16)
     out = {}
     pols = (("fp32", ile.ILE_FP32), ("fp64", ile.ILE_FP64), ("fp32c64", ile.ILE_FP32_CANCEL64))
-    for label, probs, n_per, steps, warm in (("c1_hl5_1x2e17", c1, 1 << 17, 50, 5),
-                                             ("c1_hl5_1x2e24", c1, 1 << 24, 5, 1),
-                                             ("c3_hlv17_snr100_16x2e20", c3, 1 << 20, 5, 1)):
+    legs = [("c1_hl5_1x2e17", c1, 1 << 17, 50, 5, None), ("c1_hl5_1x2e24", c1, 1 << 24, 5, 1, None)]
+    for snr in (100.0, 400.0):
+        legs.append((f"c3_hlv17_snr{int(snr)}_16x2e20_mixture", config_problems("c3", n_points=16, snr=snr),
+                     1 << 20, 5, 1, c3_proposal(snr)))
+    for label, probs, n_per, steps, warm, prop in legs:
         out[label] = {}
         for name, pol in pols:
             if label.startswith("c1") and name == "fp32c64":
                 continue
-            r = run_policy(ile, torch, ctx, probs, pol, n_per, steps, warm, stream)
+            r = run_policy(ile, torch, ctx, probs, pol, n_per, steps, warm, stream, proposal=prop)
             out[label][name] = {"samples_per_s": r["samples_per_s"], "ms_per_step": r["ms_per_step"],
                                 "kernel_ms": r["kernel_ms"], "samples": r["N"]}
             log(f"{label} {name} {out[label][name]}")
+        if prop is not None:
+            out[label]["marginal_comparison"] = same_draw_marginals(ile, torch, ctx, probs, n_per, 4343, stream,
+                                                                    proposal=prop)
+            log(f"{label} same draws {out[label]['marginal_comparison']}")
     return out
 
 
-def run_policy(ile, torch, ctx, probs, policy, n_per, steps, warmup, stream, tmarg_R=None):
-    """One step = draws + batched lnL (time-marginalised when tmarg_R is set) + batched estimator."""
+def references_at_best(ile, torch, jobs, n_per, stream, seed=777):
+    """FP32 + FP64-cancellation jobs: one untimed pilot pass (draws, lnL,
+    estimator), then each job's reference point at its highest-weight pilot
+    sample, as a caller does before the timed evaluations.  Every template
+    peaks at its own point, so one shared reference (the proposal's) would sit
+    away from most templates' samples."""
+    J = len(jobs)
+    N = J * n_per
+    th = torch.empty((7, N), dtype=torch.float32, device="cuda")
+    lr = torch.empty((N,), dtype=torch.float32, device="cuda")
+    W = torch.empty((N,), dtype=torch.float64, device="cuda")
+    ile.ile_draw(jobs[0], seed, 0, 0, N, th, N, lr, stream=stream)
+    esz, osz = th.element_size(), W.element_size()
+    ile.ile_eval_lnL_batch(jobs, [n_per] * J, [th.data_ptr() + j * n_per * esz for j in range(J)], [N] * J,
+                           [lr.data_ptr() + j * n_per * esz for j in range(J)],
+                           [W.data_ptr() + j * n_per * osz for j in range(J)], [None] * J, stream=stream)
+    res = ile.ile_marginalize_batch(jobs, [n_per] * J, [W.data_ptr() + j * n_per * osz for j in range(J)],
+                                    ile.ILE_MARG_RESET, want=True, stream=stream)
+    torch.cuda.synchronize()
+    for j, (job, r) in enumerate(zip(jobs, res)):
+        if r["argmax"] >= 0:
+            ile.ile_set_reference(job, th[:, j * n_per + r["argmax"]].double().cpu().numpy(), stream=stream)
+    torch.cuda.synchronize()
+    del th, lr, W
+
+
+def run_policy(ile, torch, ctx, probs, policy, n_per, steps, warmup, stream, tmarg_R=None, proposal=None):
+    """One step = draws + batched lnL (time-marginalised when tmarg_R is set) + batched estimator.
+    proposal = (weights, means, covs): a mixture set on every job (draws come from it)."""
     # theta (and ln p - ln p_s) in the policy's theta type; lnL and lw in its
     # output type (FP64 for the FP64 and the FP32 + FP64-cancellation policies)
     dt = torch.float64 if policy == ile.ILE_FP64 else torch.float32
     ot = torch.float32 if policy == ile.ILE_FP32 else torch.float64
     jobs = [ile.ile_prepare(ctx, ile.ProblemHost(p, precision=policy)) for p in probs]
+    if proposal is not None:
+        for j in jobs:
+            ile.ile_set_proposal(j, ile.gmm_params(*proposal))
+        if policy == ile.ILE_FP32_CANCEL64:
+            references_at_best(ile, torch, jobs, n_per, stream)
     J = len(jobs)
     N = J * n_per
     th = torch.empty((7, N), dtype=dt, device="cuda")
@@ -177,7 +234,7 @@ def run_policy(ile, torch, ctx, probs, policy, n_per, steps, warmup, stream, tma
                 lnL_marg_first=out[0]["ln_L"], n_eff_first=out[0]["n_eff"], lnL_marg=ln_marg)
 
 
-def same_draw_marginals(ile, torch, ctx, probs, n_per, seed, stream):
+def same_draw_marginals(ile, torch, ctx, probs, n_per, seed, stream, proposal=None):
     """ln L of every point under each policy on ONE set of draws: the FP32
     prior draws (float theta), upcast exactly to double for the FP64 policy,
     so the differences are the arithmetic's alone (the parity protocol:
@@ -189,6 +246,11 @@ def same_draw_marginals(ile, torch, ctx, probs, n_per, seed, stream):
     out = {}
     for name, pol in (("fp32", ile.ILE_FP32), ("fp64", ile.ILE_FP64), ("fp32c64", ile.ILE_FP32_CANCEL64)):
         jobs = [ile.ile_prepare(ctx, ile.ProblemHost(p, precision=pol)) for p in probs]
+        if proposal is not None:
+            for j in jobs:
+                ile.ile_set_proposal(j, ile.gmm_params(*proposal))
+            if pol == ile.ILE_FP32_CANCEL64:
+                references_at_best(ile, torch, jobs, n_per, stream)
         if name == "fp32":
             ile.ile_draw(jobs[0], seed, 0, 0, N, th32, N, lr32, stream=stream)
         th = th32.double() if pol == ile.ILE_FP64 else th32
@@ -261,12 +323,20 @@ def serving_leg(ile, ctx, pool, n_jobs, adaptive, seed, policy, budget=0, rate=N
     ile.ile_server_destroy(srv)
     lat = np.array([(r.t_finish_ns - r.t_arrival_ns) * 1e-6 for r in res])
     waits = np.array([(r.t_admit_ns - r.t_arrival_ns) * 1e-6 for r in res])
+    # arrival -> first pass that includes the job, and first pass -> result
+    to_start = np.array([(r.t_start_ns - r.t_arrival_ns) * 1e-6 for r in res])
+    in_flight = np.array([(r.t_finish_ns - r.t_start_ns) * 1e-6 for r in res])
     samples = sum(r.samples for r in res)
     first = min(r.t_arrival_ns for r in res)
     last = max(r.t_finish_ns for r in res)
     out = {"jobs": n_jobs, "samples": int(samples), "samples_per_s": samples / ((last - first) * 1e-9),
            "wall_s": t1 - t0, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "admit_wait_p99_ms": float(np.percentile(waits, 99)),
+           "to_first_pass_p50_ms": float(np.percentile(to_start, 50)),
+           "to_first_pass_p99_ms": float(np.percentile(to_start, 99)),
+           "in_flight_p50_ms": float(np.percentile(in_flight, 50)),
+           "in_flight_p99_ms": float(np.percentile(in_flight, 99)),
+           "p99_jobs_samples_median": float(np.median(np.array([r.samples for r in res])[lat >= np.percentile(lat, 99)])),
            "failed": int(sum(r.status != 0 for r in res))}
     if adaptive:
         rounds = np.array([r.rounds for r in res])
@@ -492,15 +562,34 @@ def main():
     serving = None
     if not a.no_serving:
         log("serving pool ...")
-        pool = serving_pool(8, 250511655 + 4)
+        pool = serving_pool(64, 250511655 + 4)
         sat = serving_leg(ile, ctx, pool, min(2000, a.serving_jobs), False, 11, ile.ILE_FP32)
         log(f"saturated {sat}")
         e_n = (2 ** 20 - 2 ** 14) / math.log(2 ** 6)
-        rate = 0.7 * sat["samples_per_s"] / e_n
-        pois = serving_leg(ile, ctx, pool, a.serving_jobs, False, 12, ile.ILE_FP32, rate=rate)
-        log(f"poisson {pois}")
-        serving = {"plain_poisson_0.7": pois, "plain_saturated": sat, "arrival_rate_per_s": rate,
-                   "pool": f"{len(pool)} events (8 per (modes, detectors) class, SNR log-uniform 10-100), reused"}
+        serving = {"plain_saturated": sat,
+                   "pool": f"{len(pool)} events (64 per (modes, detectors) class, SNR log-uniform 10-100), reused",
+                   "arrival_rates_per_s": {}}
+        for frac in (0.5, 0.7, 0.9):
+            rate = frac * sat["samples_per_s"] / e_n
+            leg = serving_leg(ile, ctx, pool, a.serving_jobs, False, 12, ile.ILE_FP32, rate=rate)
+            log(f"poisson {frac} {leg}")
+            serving[f"plain_poisson_{frac}"] = leg
+            serving["arrival_rates_per_s"][str(frac)] = rate
+        # admission by footprint: the saturated stream under small budgets queues
+        for gib, label in ((2.0, "2GiB"), (0.25, "256MiB")):
+            leg = serving_leg(ile, ctx, pool, min(2000, a.serving_jobs), False, 11, ile.ILE_FP32,
+                              budget=int(gib * (1 << 30)))
+            log(f"saturated budget {label} {leg}")
+            serving[f"plain_saturated_budget_{label}"] = leg
+        # FP64 serving for comparison: saturated, and Poisson at 0.7 of its own saturated rate
+        sat64 = serving_leg(ile, ctx, pool, min(2000, a.serving_jobs), False, 11, ile.ILE_FP64)
+        log(f"saturated fp64 {sat64}")
+        serving["plain_saturated_fp64"] = sat64
+        rate64 = 0.7 * sat64["samples_per_s"] / e_n
+        serving["plain_poisson_0.7_fp64"] = serving_leg(ile, ctx, pool, a.serving_jobs, False, 12, ile.ILE_FP64,
+                                                        rate=rate64)
+        serving["arrival_rates_per_s"]["0.7_fp64"] = rate64
+        log(f"poisson fp64 {serving['plain_poisson_0.7_fp64']}")
         if a.adaptive_jobs > 0:
             for it in integrators:
                 ada = serving_leg(ile, ctx, pool, a.adaptive_jobs, True, 13, ile.ILE_FP32, integrator=it)

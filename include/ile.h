@@ -18,8 +18,9 @@
  *  - Q between window samples: 4-point Lagrange cubic on samples i-1..i+2,
  *    i = floor((tau - tau0)/dt), valid for 1 <= i <= n_time-3.
  *
- * Memory: every pointer in ile_problem is HOST memory and is deep-copied by
- * ile_prepare.  Sample buffers passed to ile_eval_lnL / ile_draw /
+ * Memory: the arrays of ile_problem are host memory, or device memory of the
+ * context's GPU when mem_is_device = 1; either way ile_prepare and
+ * ile_server_submit deep-copy them and the caller may free them on return.  Sample buffers passed to ile_eval_lnL / ile_draw /
  * ile_marginalize / ile_adapt_proposal are DEVICE memory owned by the caller
  * (e.g. torch tensors); the library never frees them.  Calls enqueue work on
  * the given HIP stream (NULL = the device's null stream) and return without
@@ -89,6 +90,9 @@ typedef struct {
     int32_t n_det;            /* 1..3 */
     int32_t n_modes;          /* 1..21, every l in 2..4, |m| <= l, no duplicates */
     int32_t n_time;           /* window samples, >= 4 */
+    int32_t mem_is_device;    /* 0: the arrays below are host memory; 1: device memory of
+                                 the context's GPU (copied to the host for validation and
+                                 packing, then uploaded as for host arrays) */
     const int32_t *mode_l;    /* [n_modes] */
     const int32_t *mode_m;    /* [n_modes] */
     const double *det_pos;    /* [n_det][3] metres, Earth-fixed */
@@ -123,12 +127,18 @@ typedef struct {
     size_t device_bytes;      /* resident device memory of the job */
 } ile_job_info;
 
-/* Context: one per HIP device.  hbm_budget_bytes = 0 means the whole device. */
+/* Context: one per HIP device.  hbm_budget_bytes = 0 means the whole device.
+ * (Library state, not a step of the paper's method.) */
 ile_status ile_ctx_create(int hip_device, size_t hbm_budget_bytes, ile_ctx **out);
 void ile_ctx_destroy(ile_ctx *ctx);
 const char *ile_last_error(void);
 
-/* Validate, filter modes, convert to the policy's precision and layout, upload. */
+/* Validate, filter modes, convert to the policy's precision and layout, upload:
+ * the residency of Q, U, V for one intrinsic point (Section "Review of the
+ * RIFT likelihood", eq. QUV).  U is Hermitian and V symmetric, so only the
+ * pairs a <= b are kept (Section "Reduce duplication of inner products").
+ * mode_filter_eps > 0 drops modes whose overlaps are negligible, as in
+ * Section "Disable automatic mode filtering" (0 = off, the paper's choice). */
 ile_status ile_prepare(ile_ctx *ctx, const ile_problem *problem, ile_job **out);
 ile_status ile_job_info_get(const ile_job *job, ile_job_info *info);
 void ile_job_release(ile_job *job);
@@ -220,14 +230,19 @@ size_t ile_marginalize_noalloc_max(void);
 
 /* Counter-based draws (Philox-4x32-10) of samples first_index .. first_index+n-1
  * of round `round` under key `seed`: from the prior while the job has no
- * proposal, else from the mixture proposal p_s.  theta_out: device [7][ld];
- * lnpmps_out: device [n] ln p - ln p_s (theta type), or NULL. */
+ * proposal, else from the mixture proposal p_s -- the samples and the
+ * ln p - ln p_s of the Monte Carlo estimator, eq. (lnL:MonteCarlo), with the
+ * sampling priors of Section "Evaluating the marginalized likelihood".
+ * theta_out: device [7][ld]; lnpmps_out: device [n] ln p - ln p_s (theta
+ * type), or NULL. */
 ile_status ile_draw(ile_job *job, uint64_t seed, uint32_t round, int64_t first_index, int64_t n,
                     void *theta_out, int64_t ld, void *lnpmps_out, ile_stream stream);
 
 /* Mixture proposal p_s = (1 - eps) sum_j pi_j N_j / Z_j + eps p over the sampled
  * columns (all seven, or six with dist_marg); periodic alpha, phi_c (2pi) and
- * psi (pi) use differences wrapped into (-P/2, P/2]. */
+ * psi (pi) use differences wrapped into (-P/2, P/2].  The Gaussian-mixture
+ * sampling prior of Section "Evaluating the marginalized likelihood" (its
+ * details are not printed there; this is the library's reading). */
 #define ILE_GMM_MAX_COMP 16
 typedef struct {
     int32_t n_comp;           /* 1..16 */
@@ -253,7 +268,10 @@ typedef struct {
 } ile_gmm_opts;
 
 /* Install an explicit proposal (host parameters); the library factorises the
- * covariances and estimates ln Z on the device (opts may be NULL for defaults). */
+ * covariances and estimates ln Z on the device (opts may be NULL for defaults).
+ * Section "Evaluating the marginalized likelihood" (GMM sampling prior).
+ * ILE_FP32_CANCEL64 jobs also take the heaviest component's mean as their
+ * reference point (ile_set_reference). */
 ile_status ile_set_proposal(ile_job *job, const ile_gmm_params *params, const ile_gmm_opts *opts,
                             ile_stream stream);
 ile_status ile_get_proposal(ile_job *job, ile_gmm_params *params, ile_stream stream);
@@ -261,7 +279,12 @@ ile_status ile_get_proposal(ile_job *job, ile_gmm_params *params, ile_stream str
 /* Weighted EM refit of the proposal from samples (theta [7][ld], lw [n], device):
  * first call seeds the means at the highest-weight distinct samples with a
  * common weighted covariance; later calls warm-start.  Each component gets
- * Sigma += 1e-8 diag(range^2).  Host diagnostics (may be NULL): the new params. */
+ * Sigma += 1e-8 diag(range^2).  Host diagnostics (may be NULL): the new params.
+ * The adaptive step of the GMM sampling prior (Section "Evaluating the
+ * marginalized likelihood": the proposal is refitted to the weighted samples
+ * until the effective sample size of eq. (neff) reaches its target).
+ * ILE_FP32_CANCEL64 jobs move their reference point to the refitted mixture's
+ * heaviest component. */
 ile_status ile_adapt_proposal(ile_job *job, int64_t n, const void *theta, int64_t ld,
                               const void *lw, const ile_gmm_opts *opts,
                               ile_gmm_params *out, ile_stream stream);
@@ -330,7 +353,10 @@ ile_status ile_av_update(ile_job *job, uint64_t seed, uint32_t round, int64_t fi
 ile_status ile_av_get(ile_job *job, ile_av_state *out, int32_t *cells, int64_t cap, ile_stream stream);
 
 /* ---------------------------------------------------- adaptive Cartesian */
-/* The product-form adaptive Cartesian (AC) sampling prior: one adaptive
+/* Section "Evaluating the marginalized likelihood": a sampling prior that is a
+ * product of one-dimensional distributions, each updated after a block of
+ * evaluations to follow the integrand's support.
+ * The product-form adaptive Cartesian (AC) sampling prior: one adaptive
  * 64-bin piecewise-constant marginal per sampled column of the prior's CDF
  * cube (all seven columns, or six with dist_marg, or a chosen subset; other
  * columns are drawn from the prior).  A draw inverts each marginal's CDF at
@@ -379,7 +405,10 @@ ile_status ile_overlaps(ile_ctx *ctx, const ile_qv_shape *shape, const void *hlm
                         const double *inv_psd, void *Q, void *U, void *V, ile_stream stream);
 
 /* ------------------------------------------------------------ fair draws */
-/* Fair draws from weighted samples: the final extrinsic samples of an ILE run
+/* Section "Likelihood interpolation and posterior distributions" (the final
+ * fair extrinsic draws; their before/after-resampling check is in Section
+ * "Before and after extrinsic resampling").
+ * Fair draws from weighted samples: the final extrinsic samples of an ILE run
  * are drawn fairly from its weighted Monte Carlo samples (and the posterior
  * from CIP's weighted samples the same way).  k independent draws with
  * replacement: index i with probability q_i / sum q, q_i =
@@ -395,6 +424,10 @@ ile_status ile_fair_draw(ile_job *job, int64_t n, const void *lw, uint64_t seed,
                          ile_stream stream);
 
 /* ---------------------------------------------------------------- serving */
+/* A persistent loop that evaluates many intrinsic points' marginal
+ * likelihoods at once, as one ILE process evaluates several points in turn
+ * (Appendix "Timing analysis"): jobs are admitted by device footprint and
+ * their draws, likelihoods, estimators and refits are batched per pass. */
 typedef struct {
     int32_t max_active;       /* jobs resident at once (default 64) */
     size_t hbm_budget_bytes;  /* 0: the context's budget */

@@ -35,7 +35,7 @@ class ile_prior(C.Structure):
 
 
 class ile_problem(C.Structure):
-    _fields_ = [("n_det", C.c_int32), ("n_modes", C.c_int32), ("n_time", C.c_int32),
+    _fields_ = [("n_det", C.c_int32), ("n_modes", C.c_int32), ("n_time", C.c_int32), ("mem_is_device", C.c_int32),
                 ("mode_l", C.POINTER(C.c_int32)), ("mode_m", C.POINTER(C.c_int32)),
                 ("det_pos", C.POINTER(C.c_double)), ("det_resp", C.POINTER(C.c_double)),
                 ("gmst_rad", C.c_double), ("tau0_s", C.c_double), ("dt_s", C.c_double),
@@ -251,7 +251,7 @@ class ProblemHost:
             np.asarray(prob.V, dtype=np.complex128)).view(np.float64)
         ip, dp = C.POINTER(C.c_int32), C.POINTER(C.c_double)
         self.s = ile_problem(
-            len(prob.det_pos), len(prob.modes), prob.Q.shape[-1],
+            len(prob.det_pos), len(prob.modes), prob.Q.shape[-1], 0,
             self.ml.ctypes.data_as(ip), self.mm.ctypes.data_as(ip),
             self.pos.ctypes.data_as(dp), self.resp.ctypes.data_as(dp),
             prob.gmst, prob.tau0, prob.dt,
@@ -261,9 +261,15 @@ class ProblemHost:
             ile_prior(prob.t_window, prob.d_min, prob.d_max, int(dist_marg)))
 
 
-def ile_prepare(ctx, problem: ProblemHost):
+def _problem_struct(problem):
+    """A ProblemHost's ile_problem, or an ile_problem given directly (e.g. one
+    whose arrays are device memory, mem_is_device = 1)."""
+    return problem.s if isinstance(problem, ProblemHost) else problem
+
+
+def ile_prepare(ctx, problem):
     h = C.c_void_p()
-    _chk(lib().ile_prepare(ctx, C.byref(problem.s), C.byref(h)))
+    _chk(lib().ile_prepare(ctx, C.byref(_problem_struct(problem)), C.byref(h)))
     return h
 
 
@@ -470,9 +476,9 @@ def job_opts(n_samples=1 << 16, adaptive=False, round_samples=1 << 16, max_round
                         integrator)
 
 
-def ile_server_submit(srv, problem: ProblemHost, opts):
+def ile_server_submit(srv, problem, opts):
     jid = C.c_uint64()
-    _chk(lib().ile_server_submit(srv, C.byref(problem.s), C.byref(opts), C.byref(jid)))
+    _chk(lib().ile_server_submit(srv, C.byref(_problem_struct(problem)), C.byref(opts), C.byref(jid)))
     return jid.value
 
 

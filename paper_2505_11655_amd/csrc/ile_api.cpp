@@ -419,8 +419,54 @@ void fill_mixed(const ile_problem *P, const std::vector<int> &keep, const std::v
 
 }  // namespace
 
+ile_status ile::problem_on_host(const ile_problem *P, HostProblem *out, const ile_problem **use) {
+    *use = P;
+    if (!P || !P->mem_is_device) return ILE_OK;
+    const int K = P->n_det, n = P->n_modes, T = P->n_time;
+    if (K < 1 || K > 3 || n < 1 || n > kMaxModes || T < 4) return set_err(ILE_E_INVALID, "bad shapes");
+    if (!P->mode_l || !P->mode_m || !P->det_pos || !P->det_resp || !P->Q || !P->U)
+        return set_err(ILE_E_INVALID, "null input array");
+    out->ml.resize(n);
+    out->mm.resize(n);
+    out->pos.resize(3 * (size_t)K);
+    out->resp.resize(9 * (size_t)K);
+    out->Q.resize((size_t)K * n * T * 2);
+    out->U.resize((size_t)K * n * n * 2);
+    if (P->V) out->V.resize((size_t)K * n * n * 2);
+    auto cp = [](void *dst, const void *src, size_t bytes) {
+        return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
+    };
+    hipError_t e = cp(out->ml.data(), P->mode_l, n * sizeof(int32_t));
+    if (e == hipSuccess) e = cp(out->mm.data(), P->mode_m, n * sizeof(int32_t));
+    if (e == hipSuccess) e = cp(out->pos.data(), P->det_pos, out->pos.size() * sizeof(double));
+    if (e == hipSuccess) e = cp(out->resp.data(), P->det_resp, out->resp.size() * sizeof(double));
+    if (e == hipSuccess) e = cp(out->Q.data(), P->Q, out->Q.size() * sizeof(double));
+    if (e == hipSuccess) e = cp(out->U.data(), P->U, out->U.size() * sizeof(double));
+    if (e == hipSuccess && P->V) e = cp(out->V.data(), P->V, out->V.size() * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(ILE_E_INVALID, std::string("copying device inputs: ") + hipGetErrorString(e));
+    }
+    out->p = *P;
+    out->p.mem_is_device = 0;
+    out->p.mode_l = out->ml.data();
+    out->p.mode_m = out->mm.data();
+    out->p.det_pos = out->pos.data();
+    out->p.det_resp = out->resp.data();
+    out->p.Q = out->Q.data();
+    out->p.U = out->U.data();
+    out->p.V = P->V ? out->V.data() : nullptr;
+    *use = &out->p;
+    return ILE_OK;
+}
+
 extern "C" ile_status ile_prepare(ile_ctx *ctx, const ile_problem *P, ile_job **out) {
-    return job_create(ctx, P, out, nullptr, false);
+    ile_status s = ctx_check(ctx);
+    if (s != ILE_OK) return s;
+    HostProblem hp;
+    const ile_problem *use = nullptr;
+    if ((s = problem_on_host(P, &hp, &use)) != ILE_OK) return s;
+    return job_create(ctx, use, out, nullptr, false);
 }
 
 ile_status ile::job_create(ile_ctx *ctx, const ile_problem *P, ile_job **out, hipStream_t st, bool async) {

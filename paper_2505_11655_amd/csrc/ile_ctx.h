@@ -145,6 +145,14 @@ struct BatchItem {
     void *lw;
 };
 
+// A problem whose arrays are host memory: the caller's own when they are,
+// else copies of its device arrays.
+struct HostProblem {
+    std::vector<int32_t> ml, mm;
+    std::vector<double> pos, resp, Q, U, V;
+    ile_problem p{};
+};
+ile_status problem_on_host(const ile_problem *P, HostProblem *out, const ile_problem **use);
 ile_status set_err(ile_status st, const std::string &msg);
 ile_status dev_fail(ile_ctx *ctx, hipError_t e, const char *what);
 ile_status ctx_check(ile_ctx *ctx);

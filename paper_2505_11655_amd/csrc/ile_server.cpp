@@ -403,9 +403,18 @@ extern "C" ile_status ile_server_create(ile_ctx *ctx, const ile_server_opts *opt
     return ILE_OK;
 }
 
-extern "C" ile_status ile_server_submit(ile_server *s, const ile_problem *P, const ile_job_opts *jo,
+extern "C" ile_status ile_server_submit(ile_server *s, const ile_problem *Pin, const ile_job_opts *jo,
                                         uint64_t *job_id) {
-    if (!s || !P || !jo || !job_id) return set_err(ILE_E_INVALID, "null argument");
+    if (!s || !Pin || !jo || !job_id) return set_err(ILE_E_INVALID, "null argument");
+    // device arrays are copied to the host here (the copy below keeps host data)
+    HostProblem hp;
+    const ile_problem *P = nullptr;
+    if (Pin->mem_is_device) {
+        ile_status cs = ctx_check(s->ctx);
+        if (cs != ILE_OK) return cs;
+    }
+    ile_status ps = problem_on_host(Pin, &hp, &P);
+    if (ps != ILE_OK) return ps;
     if (P->n_det < 1 || P->n_det > 3 || P->n_modes < 1 || P->n_modes > kMaxModes || P->n_time < 4 || !P->Q ||
         !P->U || !P->mode_l || !P->mode_m || !P->det_pos || !P->det_resp)
         return set_err(ILE_E_INVALID, "bad problem shape");

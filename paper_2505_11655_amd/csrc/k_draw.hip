@@ -21,6 +21,7 @@
 // so the kernel stays small and occupancy high) and launches where some job
 // carries a mixture.  Mixture columns are addressed through select chains on
 // the (uniform) column index, so every per-sample array stays in registers.
+#include "ile_sincos.h"
 #include "ile_internal.h"
 
 namespace ile {
@@ -180,7 +181,7 @@ __device__ __forceinline__ bool gmm_candidate(const GmmDev &g, const PriorDev &p
         const double u1 = u53(w[4 * p], w[4 * p + 1]), u2 = u53(w[4 * p + 2], w[4 * p + 3]);
         const double r = sqrt(-2.0 * log(u1));
         double s, c;
-        sincos(2 * kPi * u2, &s, &c);
+        sincos_rad(2 * kPi * u2, &s, &c);   // FP64 reduction + series (no large-argument path)
         z[2 * p] = r * c;
         z[2 * p + 1] = r * s;
     }

@@ -445,3 +445,50 @@ def test_prior_draw_parity(orc, policy):
     else:
         assert np.allclose(g, o.astype(np.float32).astype(np.float64), rtol=2e-7, atol=1e-12)
     assert np.all(lr.cpu().numpy() == 0.0)
+
+
+def test_prepare_from_device_arrays(orc, recs):
+    """ile_problem arrays in device memory (mem_is_device = 1) give the same
+    job as host arrays: identical lnL, bitwise, in every policy; the server
+    takes them too."""
+    import ctypes as C
+    probs, _ = chirpgen.build_event(recs["c2"], ["H", "L", "V"], 9, 30.0, 2.0, 20.0, noise_seed=3)
+    prob = probs[0]
+    rng = np.random.default_rng(61)
+    thd = chirpgen.prior_samples(rng, 5000)
+    for policy in POLICIES:
+        ph = ile.ProblemHost(prob, precision=policy)
+        # the same arrays on the device
+        keep = {}
+        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int32)
+
+        def dev(a, ctype):
+            t = torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+            keep[id(t)] = t
+            return C.cast(C.c_void_p(t.data_ptr()), ctype)
+        sd = ile.ile_problem.from_buffer_copy(ph.s)
+        sd.mem_is_device = 1
+        sd.mode_l, sd.mode_m = dev(ph.ml, ip), dev(ph.mm, ip)
+        sd.det_pos, sd.det_resp = dev(ph.pos, dp), dev(ph.resp, dp)
+        sd.Q, sd.U = dev(ph.Q, dp), dev(ph.U, dp)
+        sd.V = dev(ph.V, dp)
+        torch.cuda.synchronize()
+        jh = ile.ile_prepare(gu.ctx(), ph)
+        hd = ile.ile_prepare(gu.ctx(), sd)
+        try:
+            th = _np_theta(thd, policy)
+            Lh, _ = gu.gpu_eval(jh, th, policy)
+            Ld, _ = gu.gpu_eval(hd, th, policy)
+        finally:
+            ile.ile_job_release(jh)
+            ile.ile_job_release(hd)
+        f = np.isfinite(Lh)
+        assert np.array_equal(f, np.isfinite(Ld)) and np.array_equal(Lh[f], Ld[f]), PNAME[policy]
+    # the server copies device arrays as well
+    srv = ile.ile_server_create(gu.ctx())
+    try:
+        r = ile.ile_server_wait(srv, ile.ile_server_submit(srv, sd, ile.job_opts(n_samples=4096, seed=5)), 60000)
+        rh = ile.ile_server_wait(srv, ile.ile_server_submit(srv, ph, ile.job_opts(n_samples=4096, seed=5)), 60000)
+    finally:
+        ile.ile_server_destroy(srv)
+    assert r.status == 0 and rh.status == 0 and r.marg.ln_L == rh.marg.ln_L

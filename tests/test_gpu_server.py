@@ -2,6 +2,7 @@
 a mix; plain jobs equal the oracle on the same (reproduced) draws; admission by
 device footprint queues jobs under a small budget and rejects oversize ones;
 cancellation; adaptive jobs stop at the n_eff target or the round cap."""
+import math
 import time
 
 import numpy as np
@@ -283,3 +284,55 @@ def test_av_job_matches_oracle_loop(orc, pool):
     assert alone.rounds == len(lws)
     assert abs(alone.marg.ln_L - o["ln_L"]) <= 1e-9 * max(1.0, abs(o["ln_L"]))
     assert abs(alone.marg.n_eff - o["n_eff"]) <= 1e-8 * o["n_eff"]
+
+
+def test_mixture_job_matches_oracle_loop(orc, pool):
+    """An adaptive mixture job (FP64) runs the same rounds as an oracle loop
+    with the server's options: prior draws in round 0; after each round a
+    warm-started EM refit of 8 components (8 iterations, tempered to an
+    effective sample size of 1/16 of the round) on that round's samples, the
+    in-support masses from the server's mass key, and the next round drawn
+    from the refitted mixture (defensive weight 0.05).  Same round count,
+    pooled estimate to 1e-8; alone and in a mix of other jobs it gives
+    bitwise the same result."""
+    p = pool[3]
+    ph = ile.ProblemHost(p, precision=ile.ILE_FP64)
+    n, seed, max_rounds, target = 1 << 14, 707, 4, 1e9
+    jo = ile.job_opts(adaptive=True, round_samples=n, max_rounds=max_rounds, n_eff_target=target, seed=seed)
+    srv = ile.ile_server_create(gu.ctx())
+    try:
+        alone = ile.ile_server_wait(srv, ile.ile_server_submit(srv, ph, jo), 120000)
+        others = [_submit(srv, s) for s in _specs(pool)[:6]]
+        jid = ile.ile_server_submit(srv, ph, jo)
+        mixed = ile.ile_server_wait(srv, jid, 120000)
+        for j, _ in others:
+            ile.ile_server_wait(srv, j, 120000)
+    finally:
+        ile.ile_server_destroy(srv)
+    assert alone.status == 0 and mixed.status == 0
+    assert _res(alone) == _res(mixed)
+    pr = orc.make_prior(t_window=p.t_window, d_min=p.d_min, d_max=p.d_max)
+    dims = list(range(7))
+    zseed, m = seed ^ 0x9E3779B97F4A7C15, 1 << 16
+    g, state, lws = None, None, []
+    for rnd in range(max_rounds):
+        if g is None:
+            th, lr = orc.draw_prior(pr, seed, rnd, 0, n)
+            lr = np.zeros(n)
+        else:
+            th, lr = orc.draw_gmm(pr, g, seed, rnd, 0, n)
+        lw = orc.lnL(p, th) + lr
+        lws.append(lw)
+        o = orc.marginalize(np.concatenate(lws))
+        print(f"oracle round {rnd}: n_eff {o['n_eff']:.2f} ln L {o['ln_L']:.9f}")
+        if o["n_eff"] >= target or rnd + 1 == max_rounds:
+            break
+        state = orc.em_fit(th, lw, dims, state=state, n_iter=8, n_comp=8, temper_ess=1.0 / 16.0)
+        w, mu, cov = state
+        g0 = orc.make_gmm(w, mu, cov, dims)
+        lz = [math.log(max(orc.gmm_inbox_mass(pr, g0, j, zseed, rnd + 1, m), 0.5 / m)) for j in range(len(w))]
+        g = orc.make_gmm(w, mu, cov, dims, ln_Z=lz, eps_def=0.05)
+    print("mixture job", alone.rounds, alone.marg.ln_L, alone.marg.n_eff, "oracle", len(lws), o["ln_L"], o["n_eff"])
+    assert alone.rounds == len(lws)
+    assert abs(alone.marg.ln_L - o["ln_L"]) <= 1e-8 * max(1.0, abs(o["ln_L"]))
+    assert abs(alone.marg.n_eff - o["n_eff"]) <= 1e-6 * o["n_eff"]
