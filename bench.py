@@ -38,10 +38,11 @@ LNL_BYTES = {"fp32": 40, "fp64": 80}
 # KiB per dispatch), each scaled by the same counter's reading for the probe's
 # 1 GiB device copy (FETCH_SIZE reads half the bytes: x2.000; WRITE_SIZE x1.000).
 # The figures hold only for the kernel source they were taken on.
-# SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32 of the same probe give the FLOPs the
-# kernel executes (64 lanes x (add + mul + 2 fma + trans) per wave instruction).
-LNL_TRAFFIC = {"fetch_B_per_sample": 32.720, "write_B_per_sample": 8.000, "executed_flop_per_sample": 2527.0,
-               "src_sha256": "1bf4434f18088626ebac9fd73709915a784618fbf79988cd3be9d89b3cee5159"}
+# SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_{F32,F64} of the same probe give the FLOPs
+# the kernel executes (64 lanes x (add + mul + 2 fma + trans) per wave
+# instruction): 2,437 FP32 + 108 FP64 (sky direction and delays).
+LNL_TRAFFIC = {"fetch_B_per_sample": 32.720, "write_B_per_sample": 8.000, "executed_flop_per_sample": 2545.0,
+               "src_sha256": "15e38f3b212da11500fae58b72ce59917912917478312ddfb39fd2a26d5e708d"}
 # algorithmic HBM bytes per sample of the draw (7 theta + ln p - ln p_s
 # written) and estimator (lw read) kernels
 DRAW_BYTES = {"fp32": 32, "fp64": 64}
@@ -476,7 +477,7 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the path shards by "
-              "intrinsic point with no exchange, see DESIGN.md)", file=sys.stderr)
+              "intrinsic point with no exchange between GPUs)", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2505_11655_amd as ile
