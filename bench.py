@@ -299,7 +299,11 @@ def serving_pool(per_class, seed):
 def serving_leg(ile, ctx, pool, n_jobs, adaptive, seed, policy, budget=0, rate=None, integrator=0):
     """Submit a job stream with Poisson arrivals; returns throughput and latency.
     rate=None: all jobs at once (saturated).  integrator: the adaptive jobs'
-    proposal (0: mixture refits, 1: adaptive volume, 2: adaptive Cartesian)."""
+    proposal (0: mixture refits, 1: adaptive volume, 2: adaptive Cartesian,
+    3: mixture refits in sheared phases with the rounds pooled as draws of
+    the mixture of their proposals)."""
+    pooled = integrator == 3
+    integrator = 0 if pooled else integrator
     rng = np.random.default_rng(seed)
     hosts = {}
     srv = ile.ile_server_create(ctx, max_active=64, hbm_budget_bytes=budget, chunk_samples=1 << 20)
@@ -317,7 +321,8 @@ def serving_leg(ile, ctx, pool, n_jobs, adaptive, seed, policy, budget=0, rate=N
         if pi not in hosts:
             hosts[pi] = ile.ProblemHost(pool[pi], precision=policy, dist_marg=adaptive)
         jo = ile.job_opts(n_samples=int(sizes[k]), adaptive=adaptive, round_samples=1 << 16, max_rounds=32,
-                          n_eff_target=1000.0, seed=int(seed * 100003 + k), integrator=integrator)
+                          n_eff_target=1000.0, seed=int(seed * 100003 + k), integrator=integrator,
+                          pool=ile.ILE_POOL_MIXTURE if pooled else ile.ILE_POOL_ROUNDS, phase_shear=int(pooled))
         ids.append(ile.ile_server_submit(srv, hosts[pi], jo))
     res = [ile.ile_server_wait(srv, i, -1) for i in ids]
     t1 = time.perf_counter()
@@ -342,7 +347,10 @@ def serving_leg(ile, ctx, pool, n_jobs, adaptive, seed, policy, budget=0, rate=N
     if adaptive:
         rounds = np.array([r.rounds for r in res])
         neff = np.array([r.marg.n_eff for r in res])
-        out.update({"integrator": {0: "mixture", 1: "adaptive volume", 2: "adaptive Cartesian"}[integrator],
+        name = {0: "mixture", 1: "adaptive volume", 2: "adaptive Cartesian"}[integrator]
+        if pooled:
+            name = "mixture, sheared phases, rounds pooled as the mixture of their proposals"
+        out.update({"integrator": name,
                     "rounds_mean": float(rounds.mean()),
                     "frac_reached_neff": float(np.mean(neff >= 1000.0)),
                     "n_eff_median": float(np.median(neff)),
@@ -469,7 +477,7 @@ def main():
                     help="run only the adaptive serving leg (--adaptive-jobs jobs) and print its summary")
     ap.add_argument("--overlaps-only", action="store_true",
                     help="run only the Q, U, V precompute leg (256 points) and print its summary")
-    ap.add_argument("--adaptive-integrator", choices=["gmm", "av", "ac", "all"], default="all",
+    ap.add_argument("--adaptive-integrator", choices=["gmm", "av", "ac", "gmm_pool", "all"], default="all",
                     help="proposal of the adaptive serving leg(s)")
     ap.add_argument("--configs-only", action="store_true",
                     help="run only the C1 / C3 configuration legs and print their summary")
@@ -507,8 +515,9 @@ def main():
     if a.configs_only:
         print(json.dumps({"configs": configs_leg(ile, torch, ctx, stream)}), flush=True)
         return
-    integrators = {"gmm": [0], "av": [1], "ac": [2], "all": [0, 1, 2]}[a.adaptive_integrator]
-    leg_name = {0: "adaptive_saturated", 1: "adaptive_av_saturated", 2: "adaptive_ac_saturated"}
+    integrators = {"gmm": [0], "av": [1], "ac": [2], "gmm_pool": [3], "all": [0, 1, 2, 3]}[a.adaptive_integrator]
+    leg_name = {0: "adaptive_saturated", 1: "adaptive_av_saturated", 2: "adaptive_ac_saturated",
+                3: "adaptive_pooled_saturated"}
     if a.adaptive_only:
         pool = serving_pool(8, 250511655 + 4)
         out = {}

@@ -253,6 +253,9 @@ typedef struct {
     double mean[ILE_GMM_MAX_COMP][7];
     double cov[ILE_GMM_MAX_COMP][7][7];
     double ln_Z[ILE_GMM_MAX_COMP];  /* in-support mass (output of set/adapt) */
+    int32_t shear;            /* 0, or +1 / -1: the mixture's psi column (mean, covariance) is
+                                 y = (psi + shear phi_c) mod pi, a shear of the (phi_c, psi) torus
+                                 with unit Jacobian; draws are mapped back to psi */
 } ile_gmm_params;
 
 typedef struct {
@@ -265,6 +268,11 @@ typedef struct {
     double temper_ess;        /* 0: EM on the weights w; f in (0,1]: EM on w^beta with beta
                                  the largest of 2^(-k/4), k = 0..47, whose effective sample
                                  size (sum w^beta)^2 / sum w^(2 beta) >= f * (finite samples) */
+    int32_t phase_shear;      /* first fit only: 1 fits the mixture in sheared phases (see
+                                 ile_gmm_params.shear), sign +1 if the highest-weight sample has
+                                 cos(iota) >= 0 (face-on: the likelihood ridge runs along
+                                 psi + phi_c = const), else -1; 0 (default) leaves them as they are.
+                                 Later refits keep the first fit's shear. */
 } ile_gmm_opts;
 
 /* Install an explicit proposal (host parameters); the library factorises the
@@ -448,11 +456,28 @@ typedef struct {
     int32_t integrator;       /* adaptive: ILE_INT_GMM (mixture refits), ILE_INT_AV (adaptive volume,
                                  ile_av_update with default options after each round) or ILE_INT_AC
                                  (adaptive Cartesian, ile_ac_update with floor 0.1 after each round) */
+    int32_t pool;             /* adaptive ILE_INT_GMM: ILE_POOL_ROUNDS (default) or ILE_POOL_MIXTURE */
+    int32_t phase_shear;      /* adaptive ILE_INT_GMM: 1 fits the mixture in sheared phases
+                                 (ile_gmm_opts.phase_shear) */
 } ile_job_opts;
 
 #define ILE_INT_GMM 0
 #define ILE_INT_AV 1
 #define ILE_INT_AC 2
+
+/* How an adaptive job's rounds form one Monte Carlo estimate, eq.
+ * (lnL:MonteCarlo), with eq. (neff) on the pooled weights.
+ * ILE_POOL_ROUNDS: each sample weighted by the proposal of its own round,
+ *   w = L p / p_s,r.
+ * ILE_POOL_MIXTURE: the R rounds (equal size) taken together as draws of the
+ *   equal-weight mixture of their proposals, w = L p / ((1/R) sum_q p_s,q),
+ *   recomputed for every sample after each round; the prior (round 0) is a
+ *   member, so w <= R L.  A sample that an early proposal put where later
+ *   proposals concentrate no longer dominates the pool.  The library keeps
+ *   every round's samples (7 theta, lnL, ln sum and weight per sample) and
+ *   proposals until the job ends. */
+#define ILE_POOL_ROUNDS 0
+#define ILE_POOL_MIXTURE 1
 
 typedef struct {
     ile_marg marg;

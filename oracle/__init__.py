@@ -72,7 +72,7 @@ class _Gmm(C.Structure):
     _fields_ = [("n_comp", C.c_int), ("n_dim", C.c_int), ("dims", C.c_int * MAXD),
                 ("weight", C.c_double * MAXC), ("mean", (C.c_double * MAXD) * MAXC),
                 ("cov", ((C.c_double * MAXD) * MAXD) * MAXC), ("ln_Z", C.c_double * MAXC),
-                ("eps_def", C.c_double)]
+                ("eps_def", C.c_double), ("shear", C.c_int)]
 
 
 def lib():
@@ -115,6 +115,7 @@ def lib():
         L.orc_gmm_inbox_mass.argtypes = [C.POINTER(_Prior), C.POINTER(_Gmm), C.c_int, C.c_uint64,
                                          C.c_uint32, C.c_int64]
         L.orc_gmm_inbox_mass.restype = C.c_double
+        L.orc_gmm_ln_ps_batch.argtypes = [C.POINTER(_Prior), C.POINTER(_Gmm), C.c_int64, dp, C.c_int64, dp]
         _lib = L
     return _lib
 
@@ -286,8 +287,14 @@ def draw_prior(prior, seed, rnd, i0, n):
     return th, lp
 
 
-def make_gmm(weights, means, covs, dims, ln_Z=None, eps_def=0.05):
+def make_gmm(weights, means, covs, dims, ln_Z=None, eps_def=0.05, shear=0):
+    """Mixture over the theta columns ``dims``; with shear = +-1 (columns 5 and
+    6 both in ``dims``) the means and covariances are in the coordinates of
+    ``shear_theta``."""
+    if shear and not (5 in dims and 6 in dims):
+        raise ValueError("a sheared mixture needs both phase columns")
     g = _Gmm()
+    g.shear = int(shear)
     nc, nd = len(weights), len(dims)
     g.n_comp, g.n_dim = nc, nd
     for a, d in enumerate(dims):
@@ -322,6 +329,66 @@ def draw_gmm(prior, g, seed, rnd, i0, n):
     lr = np.empty(n)
     lib().orc_draw_gmm(C.byref(prior), C.byref(g), seed, rnd, i0, n, _dp(th), n, _dp(lr))
     return th, lr
+
+
+def gmm_ln_ps_batch(prior, g, theta):
+    """``gmm_ln_ps`` of every column of theta [7][n]."""
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+    out = np.empty(th.shape[1])
+    lib().orc_gmm_ln_ps_batch(C.byref(prior), C.byref(g), th.shape[1], _dp(th), th.shape[1], _dp(out))
+    return out
+
+
+def shear_theta(theta, shear):
+    """Mixture coordinates: column 6 replaced by (psi + shear phi_c) mod pi.
+    For a face-on source the likelihood depends on the two phases nearly only
+    through psi + phi_c (face-off: psi - phi_c), a ridge along phi_c at fixed
+    y.  The map is a shear of the (phi_c, psi) torus with unit Jacobian, so
+    densities carry over unchanged."""
+    th = np.array(theta, dtype=np.float64, copy=True)
+    if shear:
+        y = th[6] + shear * th[5]
+        th[6] = y - math.pi * np.floor(y / math.pi)
+    return th
+
+
+def phase_shear_sign(theta, lw):
+    """Sign of the shear for a first fit: +1 if the highest-weight sample
+    (lowest index among ties) is face-on (cos iota >= 0), else -1; 0 if no
+    weight is finite."""
+    lw = np.asarray(lw, dtype=np.float64)
+    if not np.any(np.isfinite(lw)):
+        return 0
+    key = np.where(np.isfinite(lw), lw, -np.inf)
+    i = int(np.argsort(-key, kind="stable")[0])
+    return 1 if float(np.asarray(theta)[4][i]) >= 0.0 else -1
+
+
+def pool_mixture_lw(prior, proposals, thetas, lnLs):
+    """Log-weights of every sample of an adaptive run pooled as draws of the
+    equal-weight mixture of the rounds' proposals: eq. (lnL:MonteCarlo) with
+    p_s(x) = (1/R) sum_q p_s,q(x) for all R rounds of equal size.  Round q
+    drew ``thetas[q]`` from ``proposals[q]`` (None: the prior) and has
+    likelihoods ``lnLs[q]``; returns the concatenated
+      lw = lnL + ln p - ln( (1/R) sum_q p_s,q ).
+    Each sample's weight is at most R times its likelihood, since the prior
+    is one of the mixture's members."""
+    R = len(thetas)
+    out = []
+    for r in range(R):
+        th = np.asarray(thetas[r], dtype=np.float64)
+        lp = np.array([ln_prior(prior, th[:, i]) for i in range(th.shape[1])])
+        terms = []
+        for q in range(R):
+            if proposals[q] is None:
+                terms.append(np.zeros(th.shape[1]))
+            else:
+                terms.append(gmm_ln_ps_batch(prior, proposals[q], th) - lp)
+        T = np.stack(terms)
+        m = np.max(T, axis=0)
+        lmix = m + np.log(np.sum(np.exp(T - m), axis=0)) - math.log(R)
+        out.append(np.asarray(lnLs[r], dtype=np.float64) - lmix)
+    return np.concatenate(out)
 
 
 def gmm_inbox_mass(prior, g, j, seed, rnd, m=1 << 16):
@@ -612,13 +679,13 @@ def first_fit_candidates(n_comp):
     return 2 * n_comp
 
 
-def em_init(theta, lw, dims, n_comp=8, **rng_kw):
+def em_init(theta, lw, dims, n_comp=8, shear=0, **rng_kw):
     """First fit: means at the highest-weight distinct samples among the
     2 n_comp highest-weight ones (ties: lower index first), scanned in that
     order; if fewer than n_comp are distinct the last one found is repeated.
     Common weighted covariance (differences wrapped about the best sample),
-    equal weights."""
-    X = np.asarray(theta, dtype=np.float64)[dims].T
+    equal weights.  shear != 0: all of it in the coordinates of ``shear_theta``."""
+    X = shear_theta(theta, shear)[dims].T
     lw = np.asarray(lw, dtype=np.float64)
     fin = np.isfinite(lw)
     w = np.where(fin, np.exp(np.where(fin, lw, -np.inf) - np.max(lw[fin])), 0.0)
@@ -643,15 +710,16 @@ def em_init(theta, lw, dims, n_comp=8, **rng_kw):
     return (np.full(n_comp, 1.0 / n_comp), np.array(means), np.array([cov] * n_comp))
 
 
-def em_step(theta, lw, dims, weights, means, covs, **rng_kw):
+def em_step(theta, lw, dims, weights, means, covs, shear=0, **rng_kw):
     """One weighted EM iteration.
 
     w_i = e^{lw_i - max lw}; responsibilities r_ij from the untruncated
     components pi_j N(wrap(x_i - mu_j); 0, Sigma_j); M-step with differences
     wrapped about the current mu_j; Sigma_j += 1e-8 diag(range^2).  A component
-    with zero total weight keeps its mean and covariance.
+    with zero total weight keeps its mean and covariance.  shear != 0: the
+    samples are taken in the coordinates of ``shear_theta``.
     """
-    X = np.asarray(theta, dtype=np.float64)[dims].T
+    X = shear_theta(theta, shear)[dims].T
     lw = np.asarray(lw, dtype=np.float64)
     fin = np.isfinite(lw)
     w = np.where(fin, np.exp(np.where(fin, lw, -np.inf) - np.max(lw[fin])), 0.0)
@@ -704,15 +772,16 @@ def temper_beta(lw, frac):
     return 2.0 ** (-47 / 4.0)
 
 
-def em_fit(theta, lw, dims, state=None, n_iter=8, n_comp=8, temper_ess=0.0, **rng_kw):
+def em_fit(theta, lw, dims, state=None, n_iter=8, n_comp=8, temper_ess=0.0, shear=0, **rng_kw):
     """Warm-started EM: ``n_iter`` iterations from ``state`` (or the first fit),
-    on the tempered log-weights beta * lw (beta from ``temper_beta``)."""
+    on the tempered log-weights beta * lw (beta from ``temper_beta``), in the
+    mixture coordinates of ``shear_theta``."""
     lw = np.asarray(lw, dtype=np.float64) * temper_beta(lw, temper_ess)
     if state is None:
-        state = em_init(theta, lw, dims, n_comp=n_comp, **rng_kw)
+        state = em_init(theta, lw, dims, n_comp=n_comp, shear=shear, **rng_kw)
     w, m, c = state
     for _ in range(n_iter):
-        w, m, c = em_step(theta, lw, dims, w, m, c, **rng_kw)
+        w, m, c = em_step(theta, lw, dims, w, m, c, shear=shear, **rng_kw)
     return w, m, c
 
 

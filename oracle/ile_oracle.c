@@ -468,7 +468,24 @@ typedef struct {
     double cov[ORC_GMM_MAXC][ORC_GMM_MAXD][ORC_GMM_MAXD];
     double ln_Z[ORC_GMM_MAXC];           /* in-support mass of each component */
     double eps_def;                      /* defensive prior weight */
+    int shear;                           /* 0, or +-1: the mixture's psi column is
+                                            (psi + shear phi_c) mod pi */
 } orc_gmm;
+
+/* Mixture coordinates of a sample.  With shear s = +-1 (columns 5 and 6 both
+ * in the mixture) column 6 becomes y = (psi + s phi_c) mod pi.  The map is a
+ * shear of the (phi_c, psi) torus onto itself with unit Jacobian, so a
+ * density in (phi_c, y) is the same density in (phi_c, psi).  For a source
+ * seen face-on the likelihood depends on phi_c and psi nearly only through
+ * psi + phi_c (face-off: psi - phi_c), so its ridge runs along phi_c at fixed y. */
+static void orc_gmm_coords(const orc_gmm *g, const double th[7], double x[7])
+{
+    for (int c = 0; c < 7; c++) x[c] = th[c];
+    if (g->shear) {
+        double y = th[6] + g->shear * th[5];
+        x[6] = y - ORC_PI * floor(y / ORC_PI);
+    }
+}
 
 /* Support of a theta column: periodic (period > 0) or bounded [lo, hi]. */
 static void orc_col_support(const orc_prior *pr, int col, double *lo, double *hi, double *period)
@@ -521,11 +538,12 @@ double orc_gmm_comp_logpdf(const orc_prior *pr, const orc_gmm *g, int j, const d
     for (int a = 0; a < d; a++)
         for (int b = 0; b < d; b++) S[a][b] = g->cov[j][a][b];
     if (!orc_cholesky(d, S, L)) return NAN;
-    double diff[ORC_GMM_MAXD], y[ORC_GMM_MAXD];
+    double diff[ORC_GMM_MAXD], y[ORC_GMM_MAXD], x[7];
+    orc_gmm_coords(g, th, x);
     for (int a = 0; a < d; a++) {
         double lo, hi, P;
         orc_col_support(pr, g->dims[a], &lo, &hi, &P);
-        diff[a] = orc_wrap_diff(th[g->dims[a]] - g->mean[j][a], P);
+        diff[a] = orc_wrap_diff(x[g->dims[a]] - g->mean[j][a], P);
     }
     double q = 0.0, ld = 0.0;
     for (int a = 0; a < d; a++) {
@@ -679,12 +697,27 @@ void orc_draw_gmm(const orc_prior *pr, const orc_gmm *g, uint64_t seed, uint32_t
                 memcpy(cand, th, sizeof cand);
                 if (orc_gmm_candidate(pr, g, jsel, L[jsel], wa + 4, cand)) {
                     memcpy(th, cand, sizeof cand);
+                    if (g->shear) {    /* back from (phi_c, y) to (phi_c, psi) */
+                        double p = cand[6] - g->shear * cand[5];
+                        th[6] = p - ORC_PI * floor(p / ORC_PI);
+                    }
                     break;
                 }
             }
         }
         for (int c = 0; c < 7; c++) theta[c * ld + s] = th[c];
         if (lnpmps) lnpmps[s] = orc_ln_prior(pr, th) - orc_gmm_ln_ps(pr, g, th);
+    }
+}
+
+/* ln p_s (64 attempts) of n samples [7][ld]. */
+void orc_gmm_ln_ps_batch(const orc_prior *pr, const orc_gmm *g, int64_t n, const double *theta, int64_t ld,
+                         double *out)
+{
+    for (int64_t i = 0; i < n; i++) {
+        double th[7];
+        for (int c = 0; c < 7; c++) th[c] = theta[c * ld + i];
+        out[i] = orc_gmm_ln_ps(pr, g, th);
     }
 }
 

@@ -65,13 +65,13 @@ class ile_gmm_params(C.Structure):
     _fields_ = [("n_comp", C.c_int32), ("n_dim", C.c_int32), ("dims", C.c_int32 * 7),
                 ("eps_def", C.c_double), ("weight", C.c_double * MAXC),
                 ("mean", (C.c_double * 7) * MAXC), ("cov", ((C.c_double * 7) * 7) * MAXC),
-                ("ln_Z", C.c_double * MAXC)]
+                ("ln_Z", C.c_double * MAXC), ("shear", C.c_int32)]
 
 
 class ile_gmm_opts(C.Structure):
     _fields_ = [("n_comp", C.c_int32), ("n_iter", C.c_int32), ("eps_def", C.c_double),
                 ("seed", C.c_uint64), ("round", C.c_uint32), ("z_draws", C.c_int64),
-                ("temper_ess", C.c_double)]
+                ("temper_ess", C.c_double), ("phase_shear", C.c_int32)]
 
 
 class ile_server_opts(C.Structure):
@@ -82,10 +82,12 @@ class ile_server_opts(C.Structure):
 class ile_job_opts(C.Structure):
     _fields_ = [("n_samples", C.c_int64), ("adaptive", C.c_int32), ("round_samples", C.c_int64),
                 ("max_rounds", C.c_int32), ("n_eff_target", C.c_double), ("seed", C.c_uint64),
-                ("tmarg_oversample", C.c_int32), ("integrator", C.c_int32)]
+                ("tmarg_oversample", C.c_int32), ("integrator", C.c_int32), ("pool", C.c_int32),
+                ("phase_shear", C.c_int32)]
 
 
 ILE_INT_GMM, ILE_INT_AV, ILE_INT_AC = 0, 1, 2
+ILE_POOL_ROUNDS, ILE_POOL_MIXTURE = 0, 1
 AC_BINS = 64
 
 
@@ -353,10 +355,11 @@ def ile_draw(job, seed, rnd, first_index, n, theta_out, ld, lnpmps_out=None, str
     _chk(lib().ile_draw(job, seed, rnd, first_index, n, _p(theta_out), ld, _p(lnpmps_out), _s(stream)))
 
 
-def gmm_params(weights, means, covs, eps_def=0.05):
+def gmm_params(weights, means, covs, eps_def=0.05, shear=0):
     p = ile_gmm_params()
     p.n_comp = len(weights)
     p.eps_def = eps_def
+    p.shear = int(shear)
     for j in range(len(weights)):
         p.weight[j] = float(weights[j])
         d = len(means[j])
@@ -367,8 +370,9 @@ def gmm_params(weights, means, covs, eps_def=0.05):
     return p
 
 
-def gmm_opts(n_comp=8, n_iter=8, eps_def=0.05, seed=0x243F6A8885A308D3, rnd=0, z_draws=65536, temper_ess=0.0):
-    return ile_gmm_opts(n_comp, n_iter, eps_def, seed, rnd, z_draws, temper_ess)
+def gmm_opts(n_comp=8, n_iter=8, eps_def=0.05, seed=0x243F6A8885A308D3, rnd=0, z_draws=65536, temper_ess=0.0,
+             phase_shear=0):
+    return ile_gmm_opts(n_comp, n_iter, eps_def, seed, rnd, z_draws, temper_ess, int(phase_shear))
 
 
 def ile_set_proposal(job, params, opts=None, stream=None):
@@ -471,9 +475,9 @@ def ile_server_create(ctx, max_active=64, hbm_budget_bytes=0, chunk_samples=1 <<
 
 
 def job_opts(n_samples=1 << 16, adaptive=False, round_samples=1 << 16, max_rounds=32, n_eff_target=1000.0,
-             seed=1, tmarg_oversample=0, integrator=ILE_INT_GMM):
+             seed=1, tmarg_oversample=0, integrator=ILE_INT_GMM, pool=ILE_POOL_ROUNDS, phase_shear=0):
     return ile_job_opts(n_samples, int(adaptive), round_samples, max_rounds, n_eff_target, seed, tmarg_oversample,
-                        integrator)
+                        integrator, int(pool), int(phase_shear))
 
 
 def ile_server_submit(srv, problem, opts):

@@ -1006,6 +1006,25 @@ ile_status draw_batch(ile_ctx *ctx, int policy, const std::vector<DrawJob> &jobs
     return batch_done(ctx, slot, st);
 }
 
+ile_status pool_batch(ile_ctx *ctx, int policy, const std::vector<PoolJob> &jobs, hipStream_t st) {
+    const int64_t tile = 2048;
+    std::vector<Tile> tiles;
+    for (size_t j = 0; j < jobs.size(); j++) {
+        const int64_t n = (int64_t)(jobs[j].round + 1) * jobs[j].n_round;
+        for (int64_t t = 0; t < n; t += tile) tiles.push_back(Tile{(int32_t)j, 0, t, std::min(t + tile, n)});
+    }
+    if (tiles.empty()) return ILE_OK;
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
+    void *dj = nullptr, *dt = nullptr;
+    int slot = -1;
+    ile_status s = batch_upload(ctx, jobs.data(), jobs.size() * sizeof(PoolJob), tiles.data(),
+                                tiles.size() * sizeof(Tile), &dj, &dt, &slot, st);
+    if (s != ILE_OK) return s;
+    hipError_t e = launch_pool_mix(policy, (const PoolJob *)dj, (const Tile *)dt, (int)tiles.size(), st);
+    if (e != hipSuccess) return dev_fail(ctx, e, "mixture pool update");
+    return batch_done(ctx, slot, st);
+}
+
 }  // namespace ile
 
 // ================================================================ marginalise
@@ -1154,6 +1173,7 @@ extern "C" ile_status ile_set_proposal(ile_job *job, const ile_gmm_params *p, co
     if (s != ILE_OK) return s;
     if (p->n_comp < 1 || p->n_comp > kMaxComp) return set_err(ILE_E_INVALID, "n_comp must be 1..16");
     if (!(p->eps_def >= 0 && p->eps_def < 1)) return set_err(ILE_E_INVALID, "eps_def must be in [0,1)");
+    if (p->shear < -1 || p->shear > 1) return set_err(ILE_E_INVALID, "shear must be -1, 0 or 1");
     if ((s = ensure_gmm(job)) != ILE_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipStreamSynchronize(st);
@@ -1163,6 +1183,7 @@ extern "C" ile_status ile_set_proposal(ile_job *job, const ile_gmm_params *p, co
     default_dims(job, &g.n_dim, g.dims);
     g.n_comp = p->n_comp;
     g.eps_def = p->eps_def;
+    g.shear = p->shear;   // the default columns always hold both phases
     double wsum = 0.0;
     for (int j = 0; j < p->n_comp; j++) {
         if (!(p->weight[j] >= 0) || !std::isfinite(p->weight[j])) return set_err(ILE_E_INVALID, "bad weight");
@@ -1202,6 +1223,7 @@ extern "C" ile_status ile_get_proposal(ile_job *job, ile_gmm_params *p, ile_stre
     p->n_dim = g.n_dim;
     for (int a = 0; a < 7; a++) p->dims[a] = a < g.n_dim ? g.dims[a] : -1;
     p->eps_def = g.eps_def;
+    p->shear = g.shear;
     for (int j = 0; j < g.n_comp; j++) {
         p->weight[j] = g.w[j];
         p->ln_Z[j] = g.lnZ[j];
@@ -1256,6 +1278,7 @@ ile_status adapt_batch(ile_ctx *ctx, int policy, const std::vector<AdaptItem> &i
         default_dims(job, &e.n_dim, e.dims);
         e.eps_def = eps;
         e.temper = temper;
+        e.shear_auto = (o && o->phase_shear) ? 1 : 0;
         e.z_seed = it.z_seed;
         e.z_round = it.z_round;
         e.z_draws = z_draws;

@@ -179,6 +179,8 @@ ile_status batch_upload(ile_ctx *ctx, const void *a, size_t na, const void *b, s
                         void **hextra = nullptr);
 ile_status batch_done(ile_ctx *ctx, int slot, hipStream_t st);
 ile_status draw_batch(ile_ctx *ctx, int policy, const std::vector<DrawJob> &jobs, hipStream_t st);
+// Mixture-pool updates of adaptive jobs of one policy (tiles of 2048 samples).
+ile_status pool_batch(ile_ctx *ctx, int policy, const std::vector<PoolJob> &jobs, hipStream_t st);
 ile_status marg_batch(ile_ctx *ctx, ile_job *const *jobs, int n_jobs, const int64_t *n, const void *const *lw,
                       const uint32_t *flags, ile_marg *out, hipStream_t st);
 ile_status job_marg_launch(ile_job *job, int64_t n, const void *lw, bool reset, hipStream_t st);

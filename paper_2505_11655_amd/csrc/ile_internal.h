@@ -282,6 +282,7 @@ struct GmmDev {
     int n_comp, n_dim;
     int dims[7];
     int valid;
+    int shear;                            // 0, or +-1: mixture column psi is (psi + shear phi_c) mod pi
     double eps_def;
     double w[kMaxComp];                   // pi_j
     double logw[kMaxComp];                // ln pi_j (-inf if pi_j = 0)
@@ -302,6 +303,36 @@ struct PriorDev {
     double t_window, d_min, d_max, d_ref;
     int dist_marg;
 };
+
+// Phase shear of a mixture's coordinates: the psi column becomes
+// y = (psi + s phi_c) mod pi (s = +-1), a shear of the (phi_c, psi) torus with
+// unit Jacobian.  A face-on source's likelihood depends on the phases nearly
+// only through psi + phi_c (face-off: psi - phi_c), a ridge along phi_c at
+// fixed y that one elongated component covers.  shear_phase(y, phi, -s)
+// maps back.
+__device__ __forceinline__ double shear_phase(double psi, double phi, int s) {
+    constexpr double kPiS = 3.14159265358979323846;
+    const double y = psi + (double)s * phi;
+    return y - kPiS * floor(y / kPiS);
+}
+
+// Mixture pool of an adaptive job after its round r: every sample of rounds
+// 0..r taken as a draw of the equal-weight mixture of the rounds' proposals
+// (round 0: the prior).  lmix[i] = ln sum_{q<=r} p_s,q(x_i)/p(x_i) is kept
+// across rounds (old samples add the newest proposal's term, the new round's
+// samples get every term), and lw[i] = lnL[i] - lmix[i] + ln(r + 1).
+struct PoolJob {
+    const void *theta;    // [7][ld] every round's samples (policy theta type)
+    int64_t ld;
+    const void *lnL;      // [(r+1) n_round] (policy output type)
+    double *lmix;         // [(r+1) n_round]
+    void *lw;             // [(r+1) n_round] (policy log-weight type)
+    const GmmDev *hist;   // hist[q]: the proposal that drew round q (q = 1..r)
+    PriorDev pr;
+    int64_t n_round;
+    int32_t round;
+};
+hipError_t launch_pool_mix(int policy, const PoolJob *d_jobs, const Tile *d_tiles, int n_tiles, hipStream_t st);
 
 // Inverse-CDF map of seven uniforms onto the prior: alpha ~ U[0, 2pi),
 // p(dec) = cos(dec)/2, t ~ U[-t_w, t_w], p(D) = 3 D^2/(D_max^3 - D_min^3)
@@ -375,6 +406,7 @@ struct EmJob {
     int dims[7];
     double eps_def;       // first fit: defensive prior fraction
     double temper;        // ESS fraction of the tempering rule (<= 0: beta = 1)
+    int shear_auto;       // first fit: shear the phases, sign from the best sample's cos(iota)
     uint64_t z_seed;      // in-support mass: Philox key, round, number of draws
     uint32_t z_round;
     int64_t z_draws;

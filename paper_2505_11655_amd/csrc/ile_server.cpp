@@ -58,6 +58,13 @@ struct Req {
     ile_job *job = nullptr;
     void *d_theta = nullptr, *d_lr = nullptr, *d_lw = nullptr;
     size_t buf_bytes = 0;
+    // mixture pool (adaptive mixture jobs with ILE_POOL_MIXTURE): every round's
+    // theta [7][pool_cap], lnL, ln sum p_s,q/p and pooled weights, and the
+    // proposal of every round
+    void *d_pth = nullptr, *d_pL = nullptr, *d_plw = nullptr;
+    double *d_plmix = nullptr;
+    GmmDev *d_hist = nullptr;
+    int64_t pool_cap = 0;
     int64_t chunk = 0;        // samples per pass
     int64_t done = 0;         // samples evaluated
     int32_t rounds = 0;
@@ -89,6 +96,12 @@ namespace {
 
 size_t theta_bytes(int policy) { return policy == kFP64 ? 8 : 4; }
 size_t lw_bytes(int policy) { return policy == kFP32 ? 4 : 8; }
+size_t lnl_bytes(int policy) { return policy == kFP32 ? 4 : 8; }
+
+bool pools_mixture(const Req *r) {
+    return r->jo.adaptive && r->jo.integrator == ILE_INT_GMM && r->jo.pool == ILE_POOL_MIXTURE;
+}
+int max_rounds_of(const Req *r) { return r->jo.max_rounds > 0 ? r->jo.max_rounds : 32; }
 
 int64_t chunk_of(const ile_server *s, const Req *r) {
     if (r->jo.adaptive) return r->jo.round_samples > 0 ? r->jo.round_samples : 65536;
@@ -118,6 +131,13 @@ size_t footprint_of(const ile_server *s, const Req *r) {
         extra += sizeof(AcDev);
     else if (r->jo.adaptive)
         extra += sizeof(GmmDev) + em_work_bytes(c) + 64 * sizeof(uint32_t);
+    if (pools_mixture(r)) {
+        const int64_t cap = (int64_t)max_rounds_of(r) * c;
+        // pooled estimator partials over the whole pool, theta, lnL, ln sum, lw, proposals
+        extra += (size_t)((cap + marg_tile(cap) - 1) / marg_tile(cap) + 1) * sizeof(MargPartial);
+        extra += (size_t)cap * (7 * theta_bytes(policy) + lnl_bytes(policy) + 8 + lw_bytes(policy)) +
+                 (size_t)(max_rounds_of(r) + 1) * sizeof(GmmDev);
+    }
     return inputs + bufs + extra;
 }
 
@@ -133,6 +153,17 @@ void finish(ile_server *s, Req *r, int status, const ile_marg *m) {
         ctx_free(s->ctx, r->d_lr, (size_t)r->chunk * theta_bytes(policy));
         ctx_free(s->ctx, r->d_lw, (size_t)r->chunk * lw_bytes(policy));
         r->d_theta = r->d_lr = r->d_lw = nullptr;
+        if (r->pool_cap) {
+            ctx_free(s->ctx, r->d_pth, (size_t)7 * r->pool_cap * theta_bytes(policy));
+            ctx_free(s->ctx, r->d_pL, (size_t)r->pool_cap * lnl_bytes(policy));
+            ctx_free(s->ctx, r->d_plmix, (size_t)r->pool_cap * sizeof(double));
+            ctx_free(s->ctx, r->d_plw, (size_t)r->pool_cap * lw_bytes(policy));
+            ctx_free(s->ctx, r->d_hist, (size_t)(max_rounds_of(r) + 1) * sizeof(GmmDev));
+            r->d_pth = r->d_pL = r->d_plw = nullptr;
+            r->d_plmix = nullptr;
+            r->d_hist = nullptr;
+            r->pool_cap = 0;
+        }
         job_release_nosync(r->job);   // the server stream has no queued work for it
         r->job = nullptr;
     }
@@ -160,6 +191,17 @@ ile_status admit(ile_server *s, Req *r) {
     if ((st = ctx_alloc(s->ctx, &r->d_theta, (size_t)7 * r->chunk * tb, "theta")) != ILE_OK) return st;
     if ((st = ctx_alloc(s->ctx, &r->d_lr, (size_t)r->chunk * tb, "ln p - ln ps")) != ILE_OK) return st;
     if ((st = ctx_alloc(s->ctx, &r->d_lw, (size_t)r->chunk * lw_bytes(policy), "lw")) != ILE_OK) return st;
+    if (pools_mixture(r)) {
+        const int64_t cap = (int64_t)max_rounds_of(r) * r->chunk;
+        r->pool_cap = cap;   // set first: finish() frees whatever was allocated
+        if ((st = ctx_alloc(s->ctx, &r->d_pth, (size_t)7 * cap * tb, "pool theta")) != ILE_OK ||
+            (st = ctx_alloc(s->ctx, &r->d_pL, (size_t)cap * lnl_bytes(policy), "pool lnL")) != ILE_OK ||
+            (st = ctx_alloc(s->ctx, (void **)&r->d_plmix, (size_t)cap * sizeof(double), "pool ln sum")) != ILE_OK ||
+            (st = ctx_alloc(s->ctx, &r->d_plw, (size_t)cap * lw_bytes(policy), "pool lw")) != ILE_OK ||
+            (st = ctx_alloc(s->ctx, (void **)&r->d_hist, (size_t)(max_rounds_of(r) + 1) * sizeof(GmmDev),
+                            "pool proposals")) != ILE_OK)
+            return st;
+    }
     r->res.t_admit_ns = now_ns();
     return ILE_OK;
 }
@@ -179,7 +221,20 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
         if (r->res.t_start_ns == 0) r->res.t_start_ns = t_start;
         const int64_t n = r->jo.adaptive ? r->chunk : std::min(r->chunk, r->jo.n_samples - r->done);
         nthis[i] = n;
-        const BatchItem bi{r->job, n, r->d_theta, n, r->d_lr, nullptr, r->d_lw};
+        // a pooled job draws straight into its pool, at this round's slice
+        void *th_out = r->d_theta;
+        int64_t ld = n;
+        void *lnl_out = nullptr;
+        if (r->pool_cap) {
+            const int policy = r->prob.precision;
+            th_out = (char *)r->d_pth + (size_t)r->rounds * r->chunk * theta_bytes(policy);
+            ld = r->pool_cap;
+            lnl_out = (char *)r->d_pL + (size_t)r->rounds * r->chunk * lnl_bytes(policy);
+            if (r->rounds >= 1 && hipMemcpyAsync(r->d_hist + r->rounds, r->job->d_gmm, sizeof(GmmDev),
+                                                 hipMemcpyDeviceToDevice, st) != hipSuccess)
+                return false;
+        }
+        const BatchItem bi{r->job, n, th_out, ld, r->d_lr, lnl_out, r->d_lw};
         (r->jo.tmarg_oversample == 4 ? tm4 : r->jo.tmarg_oversample == 1 ? tm1 : items).push_back(bi);
         if (r->jo.adaptive && r->jo.integrator == ILE_INT_AV) {
             AvJob aj{};
@@ -213,8 +268,8 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
         dj.seed = r->jo.seed;
         dj.round = r->jo.adaptive ? (uint32_t)r->rounds : 0u;
         dj.first = r->jo.adaptive ? 0 : r->done;
-        dj.theta = r->d_theta;
-        dj.ld = n;
+        dj.theta = th_out;
+        dj.ld = ld;
         dj.lnpmps = r->d_lr;
         dj.n = n;
         (r->prob.precision == kFP64 ? d64 : d32).push_back(dj);
@@ -228,6 +283,27 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
     if (!items.empty() && eval_batch(s->ctx, items, st) != ILE_OK) return false;
     if (!tm1.empty() && tmarg_batch(s->ctx, tm1, 1, st) != ILE_OK) return false;
     if (!tm4.empty() && tmarg_batch(s->ctx, tm4, 4, st) != ILE_OK) return false;
+    // mixture pools: every sample reweighted by the mixture of the rounds' proposals
+    {
+        std::vector<PoolJob> pj[3];
+        for (size_t i = 0; i < act.size(); i++) {
+            Req *r = act[i];
+            if (!r->pool_cap) continue;
+            PoolJob q{};
+            q.theta = r->d_pth;
+            q.ld = r->pool_cap;
+            q.lnL = r->d_pL;
+            q.lmix = r->d_plmix;
+            q.lw = r->d_plw;
+            q.hist = r->d_hist;
+            q.pr = r->job->pr;
+            q.n_round = r->chunk;
+            q.round = r->rounds;
+            pj[r->prob.precision].push_back(q);
+        }
+        for (int pol = 0; pol < 3; pol++)
+            if (!pj[pol].empty() && pool_batch(s->ctx, pol, pj[pol], st) != ILE_OK) return false;
+    }
     // estimator, grouped by lw type (float for FP32, double otherwise)
     std::vector<ile_marg> res(act.size());
     for (int g = 0; g < 2; g++) {
@@ -240,9 +316,15 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
             const bool f32 = act[i]->prob.precision == kFP32;
             if ((g == 0) != f32) continue;
             jobs.push_back(act[i]->job);
-            ns.push_back(nthis[i]);
-            lws.push_back(act[i]->d_lw);
-            fl.push_back(act[i]->done == 0 && act[i]->rounds == 0 ? ILE_MARG_RESET : ILE_MARG_POOL);
+            if (act[i]->pool_cap) {   // the whole pool, re-estimated from scratch
+                ns.push_back((int64_t)(act[i]->rounds + 1) * act[i]->chunk);
+                lws.push_back(act[i]->d_plw);
+                fl.push_back(ILE_MARG_RESET);
+            } else {
+                ns.push_back(nthis[i]);
+                lws.push_back(act[i]->d_lw);
+                fl.push_back(act[i]->done == 0 && act[i]->rounds == 0 ? ILE_MARG_RESET : ILE_MARG_POOL);
+            }
             idx.push_back(i);
         }
         if (jobs.empty()) continue;
@@ -322,14 +404,25 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
     o.eps_def = 0.05;
     o.z_draws = 65536;
     o.temper_ess = 1.0 / 16.0;
-    for (int pol = 0; pol < 3; pol++) {
-        std::vector<AdaptItem> items;
-        for (Req *r : refit)
-            if (r->job->policy == pol && r->jo.integrator == ILE_INT_GMM)
-                items.push_back(AdaptItem{r->job, r->chunk, r->d_theta, r->chunk, r->d_lw,
-                                          r->jo.seed ^ 0x9E3779B97F4A7C15ull, (uint32_t)r->rounds});
-        if (!items.empty() && adapt_batch(s->ctx, pol, items, &o, st) != ILE_OK) return false;
-    }
+    for (int pol = 0; pol < 3; pol++)
+        for (int sh = 0; sh < 2; sh++) {
+            std::vector<AdaptItem> items;
+            for (Req *r : refit) {
+                if (r->job->policy != pol || r->jo.integrator != ILE_INT_GMM || (r->jo.phase_shear != 0) != (sh != 0))
+                    continue;
+                // this round's samples (in the pool at slice rounds - 1) and their own weights
+                const void *th = r->d_theta;
+                int64_t ld = r->chunk;
+                if (r->pool_cap) {
+                    th = (const char *)r->d_pth + (size_t)(r->rounds - 1) * r->chunk * theta_bytes(pol);
+                    ld = r->pool_cap;
+                }
+                items.push_back(AdaptItem{r->job, r->chunk, th, ld, r->d_lw, r->jo.seed ^ 0x9E3779B97F4A7C15ull,
+                                          (uint32_t)r->rounds});
+            }
+            o.phase_shear = sh;
+            if (!items.empty() && adapt_batch(s->ctx, pol, items, &o, st) != ILE_OK) return false;
+        }
     return true;
 }
 
@@ -423,6 +516,17 @@ extern "C" ile_status ile_server_submit(ile_server *s, const ile_problem *Pin, c
         return set_err(ILE_E_INVALID, "integrator must be ILE_INT_GMM, ILE_INT_AV or ILE_INT_AC");
     if (jo->adaptive && jo->round_samples >= ((int64_t)1 << 31))
         return set_err(ILE_E_INVALID, "round_samples must be below 2^31");
+    if (jo->pool != ILE_POOL_ROUNDS && jo->pool != ILE_POOL_MIXTURE)
+        return set_err(ILE_E_INVALID, "pool must be ILE_POOL_ROUNDS or ILE_POOL_MIXTURE");
+    if ((jo->pool == ILE_POOL_MIXTURE || jo->phase_shear) && !(jo->adaptive && jo->integrator == ILE_INT_GMM))
+        return set_err(ILE_E_INVALID, "pool and phase_shear apply to adaptive mixture jobs");
+    if (jo->phase_shear != 0 && jo->phase_shear != 1) return set_err(ILE_E_INVALID, "phase_shear must be 0 or 1");
+    if (jo->pool == ILE_POOL_MIXTURE) {
+        const int64_t rs = jo->round_samples > 0 ? jo->round_samples : 65536;
+        const int64_t mr = jo->max_rounds > 0 ? jo->max_rounds : 32;
+        if (mr * rs > ((int64_t)1 << 28))
+            return set_err(ILE_E_INVALID, "a mixture pool holds at most 2^28 samples (max_rounds x round_samples)");
+    }
     if (jo->tmarg_oversample != 0) {
         if (jo->tmarg_oversample != 1 && jo->tmarg_oversample != 4)
             return set_err(ILE_E_INVALID, "tmarg_oversample must be 0, 1 or 4");

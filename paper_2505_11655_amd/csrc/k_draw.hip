@@ -161,9 +161,14 @@ __device__ __forceinline__ double gmm_ln_ps(const GmmDev &g, const PriorDev &pr,
         for (int a = 0; a < g.n_dim; a++) in = in || (g.dims[a] == c);
         if (!in) lrest += ln_prior_col(pr, c, th);
     }
+    // the mixture's own coordinates (phase shear); the prior terms use theta
+    double x[7];
+#pragma unroll
+    for (int c = 0; c < 7; c++) x[c] = th[c];
+    if (g.shear) x[6] = shear_phase(th[6], th[5], g.shear);
     for (int j = 0; j < g.n_comp; j++) {
         if (g.lnc[j] == -INFINITY) continue;
-        add(g.lnc[j] + gmm_comp_logpdf(g, pr, j, th) + lrest);
+        add(g.lnc[j] + gmm_comp_logpdf(g, pr, j, x) + lrest);
     }
     add(g.ln_fb + ln_prior(pr, th));
     if (!(m > -INFINITY)) return m;
@@ -239,7 +244,11 @@ __device__ __forceinline__ void draw_mix(const DrawJob &J, uint64_t idx, double 
         for (int a = 1; a <= kMaxAttempts && jsel >= 0; a++) {
             uint32_t wa[16];
             words(J.seed, idx, J.round, (uint32_t)a, 1, 4, wa);
-            if (gmm_candidate(g, J.pr, jsel, wa, th)) break;
+            if (gmm_candidate(g, J.pr, jsel, wa, th)) {
+                // accepted in the mixture's coordinates: back to psi
+                if (g.shear) th[6] = shear_phase(th[6], th[5], -g.shear);
+                break;
+            }
         }
     }
     lr = ln_prior(J.pr, th) - gmm_ln_ps(g, J.pr, th);
@@ -289,7 +298,67 @@ void launch_draw_t(bool mix, const DrawJob *d_jobs, const Tile *d_tiles, int n_t
                            tile);
 }
 
+// Mixture pool update (see PoolJob).  One thread per sample of rounds 0..r;
+// the proposals are read through the scalar cache (uniform per block).
+template <class TT, class TO, class TL>
+__global__ void __launch_bounds__(kDrawThreads)
+    k_pool_mix(const PoolJob *__restrict__ jobs, const Tile *__restrict__ tiles) {
+    const Tile tl = tiles[blockIdx.x];
+    const PoolJob &J = jobs[tl.job];
+    const TT *__restrict__ th = (const TT *)J.theta;
+    const TO *__restrict__ L = (const TO *)J.lnL;
+    TL *__restrict__ lw = (TL *)J.lw;
+    const int r = J.round;
+    const int64_t first_new = (int64_t)r * J.n_round;
+    const double ln_rounds = log((double)(r + 1));
+    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kDrawThreads) {
+        double x[7];
+#pragma unroll
+        for (int c = 0; c < 7; c++) x[c] = (double)th[c * J.ld + i];
+        const double lp = ln_prior(J.pr, x);
+        // running ln sum of e^{t}: the prior's term is e^0
+        double m, sum;
+        int q0;
+        if (i >= first_new) {
+            m = 0.0;
+            sum = 1.0;
+            q0 = 1;
+        } else {
+            m = J.lmix[i];
+            sum = 1.0;
+            q0 = r;
+        }
+        for (int q = q0; q <= r; q++) {
+            const double t = gmm_ln_ps(J.hist[q], J.pr, x) - lp;
+            if (!(t > -INFINITY)) continue;
+            if (t > m) {
+                sum = sum * exp(m - t) + 1.0;
+                m = t;
+            } else {
+                sum += exp(t - m);
+            }
+        }
+        const double lm = m + log(sum);
+        J.lmix[i] = lm;
+        lw[i] = (TL)((double)L[i] - lm + ln_rounds);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_pool_mix(int policy, const PoolJob *d_jobs, const Tile *d_tiles, int n_tiles, hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    if (policy == kFP64)
+        hipLaunchKernelGGL((k_pool_mix<double, double, double>), dim3(n_tiles), dim3(kDrawThreads), 0, st, d_jobs,
+                           d_tiles);
+    else if (policy == kFP32)
+        hipLaunchKernelGGL((k_pool_mix<float, float, float>), dim3(n_tiles), dim3(kDrawThreads), 0, st, d_jobs,
+                           d_tiles);
+    else
+        hipLaunchKernelGGL((k_pool_mix<float, double, double>), dim3(n_tiles), dim3(kDrawThreads), 0, st, d_jobs,
+                           d_tiles);
+    return hipGetLastError();
+}
 
 hipError_t launch_draw(int policy, const DrawJob *d_jobs, const Tile *d_tiles, int n_tiles, const DrawJob &single,
                        int64_t tile, bool mix, hipStream_t st) {

@@ -120,6 +120,14 @@ __device__ __forceinline__ double load_col(const TT *th, int64_t ld, int col, in
     return (double)th[col * ld + i];
 }
 
+// Column col of sample i in the mixture's coordinates (phase shear of column 6).
+template <class TT>
+__device__ __forceinline__ double load_mix(const TT *th, int64_t ld, int col, int64_t i, int shear) {
+    const double v = (double)th[col * ld + i];
+    if (col != 6 || shear == 0) return v;
+    return shear_phase(v, (double)th[5 * ld + i], shear);
+}
+
 __device__ __forceinline__ bool finite_d(double v) { return v > -INFINITY && v < INFINITY; }
 
 __device__ __forceinline__ double sample_weight(double lwv, double mlw, double beta) {
@@ -336,6 +344,10 @@ __global__ void k_em_top_final(const EmJob *__restrict__ jobs) {
     g->valid = 1;
     const TT *th = (const TT *)J.theta;
     const int d = J.n_dim, nc = J.n_comp;
+    // phase shear: its sign from the inclination of the best sample (face-on
+    // ridge along psi + phi_c, face-off along psi - phi_c)
+    g->shear = 0;
+    if (J.shear_auto && cur[0].v > -INFINITY) g->shear = load_col(th, J.ld, 4, cur[0].i) >= 0.0 ? 1 : -1;
     // candidates: the 2 n_comp highest-weight samples (kTopK = 2 kMaxComp
     // holds them for every n_comp), scanned in that order
     const int ncand = 2 * nc < kTopK ? 2 * nc : kTopK;
@@ -343,7 +355,7 @@ __global__ void k_em_top_final(const EmJob *__restrict__ jobs) {
     for (int k = 0; k < ncand && got < nc; k++) {
         if (!(cur[k].v > -INFINITY)) break;
         double x[7];
-        for (int a = 0; a < d; a++) x[a] = load_col(th, J.ld, J.dims[a], cur[k].i);
+        for (int a = 0; a < d; a++) x[a] = load_mix(th, J.ld, J.dims[a], cur[k].i, g->shear);
         bool dup = false;
         for (int q = 0; q < got && !dup; q++) {
             bool same = true;
@@ -382,7 +394,7 @@ __global__ void __launch_bounds__(kEmThreads) k_em_init(const EmJob *__restrict_
             x[a] = 0.0;
             if (a < d) {
                 const int col = g->dims[a];
-                x[a] = wrapd(load_col(th, J.ld, col, i) - g->mean[0][a], col_period(col));
+                x[a] = wrapd(load_mix(th, J.ld, col, i, g->shear) - g->mean[0][a], col_period(col));
             }
         }
         acc[0] += w;
@@ -475,12 +487,19 @@ __global__ void __launch_bounds__(kEmThreads) k_em_resp(const EmJob *__restrict_
         col[a] = a < d ? g->dims[a] : 0;
         P[a] = col_period(col[a]);
     }
+    const int shear = g->shear;
     const double mlw = J.work[kWMax], beta = J.work[kWBeta];
     for (int64_t i = (int64_t)blockIdx.x * kEmThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kEmThreads) {
         const double w = sample_weight((double)lw[i], mlw, beta);
         double x[7];
 #pragma unroll
         for (int a = 0; a < 7; a++) x[a] = load_col(th, J.ld, col[a], i);   // col[a] valid: loads in flight together
+        if (shear) {
+            const double phi = (double)th[5 * J.ld + i];
+#pragma unroll
+            for (int a = 0; a < 7; a++)
+                if (a < d && col[a] == 6) x[a] = shear_phase(x[a], phi, shear);
+        }
 #pragma unroll
         for (int a = 0; a < 7; a++) x[a] = a < d ? x[a] : 0.0;
         double m = -INFINITY;
@@ -540,6 +559,7 @@ __global__ void __launch_bounds__(kEmThreads) k_em_stat(const EmJob *__restrict_
         mu[a] = a < d ? g->mean[j][a] : 0.0;
         P[a] = col_period(col[a]);
     }
+    const int shear = g->shear;
     double acc[36];
 #pragma unroll
     for (int c = 0; c < 36; c++) acc[c] = 0.0;
@@ -551,6 +571,12 @@ __global__ void __launch_bounds__(kEmThreads) k_em_stat(const EmJob *__restrict_
         double v[7];
 #pragma unroll
         for (int a = 0; a < 7; a++) v[a] = load_col(th, J.ld, col[a], i);
+        if (shear) {
+            const double phi = (double)th[5 * J.ld + i];
+#pragma unroll
+            for (int a = 0; a < 7; a++)
+                if (a < d && col[a] == 6) v[a] = shear_phase(v[a], phi, shear);
+        }
         double x[7];
 #pragma unroll
         for (int a = 0; a < 7; a++) x[a] = (a < d) ? wrapd(v[a] - mu[a], P[a]) : 0.0;

@@ -20,8 +20,10 @@ __global__ void k_ref_from_gmm(const GmmDev *__restrict__ g, const PriorDev pr, 
                 wb = g->w[j];
                 jb = j;
             }
-    if (jb >= 0)
+    if (jb >= 0) {
         for (int a = 0; a < g->n_dim; a++) t[g->dims[a]] = g->mean[jb][a];
+        if (g->shear) t[6] = shear_phase(t[6], t[5], -g->shear);   // mean in the sheared phases
+    }
     for (int c = 0; c < 7; c++) theta_ref[c] = t[c];
 }
 

@@ -76,6 +76,78 @@ def test_proposal_mass_and_draws(orc, policy, outside):
     assert abs(r.mean() - 1) < 4 * r.std() / math.sqrt(n) + 2e-3
 
 
+@pytest.mark.parametrize("shear", [1, -1])
+@pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
+def test_sheared_proposal_draws(orc, policy, shear):
+    """A mixture in sheared phases (psi column = (psi + s phi_c) mod pi, the
+    second component a ridge along phi_c): in-support masses, draws mapped
+    back to psi and ln p - ln p_s equal the oracle's."""
+    job, _ = _job(policy)
+    zseed, zround, m = 4242, 1, 1 << 16
+    means = [MEANS[0], [1.0, -0.5, -0.02, 2500.0, -0.9, 3.0, 2.0]]
+    covs = [COVS[0], np.diag([0.5, 0.05, 4e-4, 3e5, 0.05, 3.0, 0.004])]
+    try:
+        ile.ile_set_proposal(job, ile.gmm_params([0.5, 0.5], means, covs, shear=shear),
+                             ile.gmm_opts(seed=zseed, rnd=zround, z_draws=m))
+        got = ile.ile_get_proposal(job)
+        assert got.shear == shear
+        prior = orc.make_prior()
+        g = orc.make_gmm([0.5, 0.5], means, covs, list(range(7)), shear=shear)
+        lz = [math.log(max(orc.gmm_inbox_mass(prior, g, j, zseed, zround, m), 0.5 / m)) for j in range(2)]
+        for j in range(2):
+            assert abs(got.ln_Z[j] - lz[j]) <= 1e-12
+        g = orc.make_gmm([0.5, 0.5], means, covs, list(range(7)), ln_Z=lz, shear=shear)
+        n, seed, rnd, first = 20011, 17, 3, 5
+        th = torch.empty((7, n), dtype=gu.torch_dtype(policy), device="cuda")
+        lr = torch.empty((n,), dtype=gu.torch_dtype(policy), device="cuda")
+        ile.ile_draw(job, seed, rnd, first, n, th, n, lr)
+        torch.cuda.synchronize()
+    finally:
+        ile.ile_job_release(job)
+    o, olr = orc.draw_gmm(prior, g, seed, rnd, first, n)
+    gth, glr = th.double().cpu().numpy(), lr.double().cpu().numpy()
+    if policy == ile.ILE_FP64:
+        assert np.allclose(gth, o, rtol=1e-12, atol=1e-12)
+        assert np.allclose(glr, olr, rtol=1e-10, atol=1e-10)
+    else:
+        assert np.allclose(gth, o.astype(np.float32), rtol=3e-7, atol=1e-6)
+        assert np.allclose(glr, olr.astype(np.float32), rtol=1e-6, atol=1e-5)
+    r = np.exp(olr)
+    assert abs(r.mean() - 1) < 4 * r.std() / math.sqrt(n) + 2e-3
+
+
+@pytest.mark.parametrize("face", [1, -1])
+@pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
+def test_em_sheared_matches_oracle(orc, policy, face):
+    """Refit with phase_shear: the first fit takes the shear sign from the best
+    sample's inclination (face = the sign forced on every cos iota), fits in
+    the sheared phases, and a warm refit keeps it; device and oracle agree."""
+    th, lw = _weighted_samples(1 << 16, 45, policy)
+    th[4] = (face * np.abs(th[4].astype(np.float64))).astype(th.dtype)
+    lw = (lw * 40).astype(lw.dtype)
+    job, _ = _job(policy)
+    try:
+        tt, ll = torch.from_numpy(th).cuda(), torch.from_numpy(lw).cuda()
+        o = ile.gmm_opts(n_comp=8, n_iter=8, temper_ess=1.0 / 16.0, phase_shear=1)
+        p1 = ile.ile_adapt_proposal(job, th.shape[1], tt, th.shape[1], ll, o)
+        p2 = ile.ile_adapt_proposal(job, th.shape[1], tt, th.shape[1], ll, o)
+    finally:
+        ile.ile_job_release(job)
+    th64, lw64 = th.astype(np.float64), lw.astype(np.float64)
+    s = orc.phase_shear_sign(th64, lw64)
+    assert s == face
+    s1 = orc.em_fit(th64, lw64, list(range(7)), n_iter=8, n_comp=8, temper_ess=1.0 / 16.0, shear=s)
+    s2 = orc.em_fit(th64, lw64, list(range(7)), state=s1, n_iter=8, n_comp=8, temper_ess=1.0 / 16.0, shear=s)
+    for p, (w, m, c) in ((p1, s1), (p2, s2)):
+        assert p.shear == s
+        gw = np.array([p.weight[j] for j in range(8)])
+        gm = np.array([[p.mean[j][a] for a in range(7)] for j in range(8)])
+        gc = np.array([[[p.cov[j][a][b] for b in range(7)] for a in range(7)] for j in range(8)])
+        assert np.allclose(gw, w, rtol=1e-7, atol=1e-10)
+        assert np.allclose(gm, m, rtol=1e-7, atol=1e-9)
+        assert np.allclose(gc, c, rtol=1e-6, atol=1e-12)
+
+
 def _weighted_samples(n, seed, policy):
     """Prior samples with log-weights from a two-blob target (as input data)."""
     rng = np.random.default_rng(seed)

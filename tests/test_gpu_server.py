@@ -336,3 +336,61 @@ def test_mixture_job_matches_oracle_loop(orc, pool):
     assert alone.rounds == len(lws)
     assert abs(alone.marg.ln_L - o["ln_L"]) <= 1e-8 * max(1.0, abs(o["ln_L"]))
     assert abs(alone.marg.n_eff - o["n_eff"]) <= 1e-6 * o["n_eff"]
+
+
+def test_pooled_sheared_mixture_job_matches_oracle_loop(orc, pool):
+    """An adaptive mixture job with the mixture pool (every sample weighted by
+    the equal-weight mixture of all rounds' proposals, the prior included) and
+    the phase shear (first fit: sign from the best sample's inclination), FP64:
+    the same rounds as an oracle loop -- draws from the last refit, lnL,
+    pooled weights from ``pool_mixture_lw``, estimator over the whole pool,
+    refit on the round's own weights in the sheared phases.  Same round
+    count, estimate to 1e-8; alone and in a mix it is bitwise the same."""
+    p = pool[3]
+    ph = ile.ProblemHost(p, precision=ile.ILE_FP64)
+    n, seed, max_rounds, target = 1 << 13, 909, 4, 1e9
+    jo = ile.job_opts(adaptive=True, round_samples=n, max_rounds=max_rounds, n_eff_target=target, seed=seed,
+                      pool=ile.ILE_POOL_MIXTURE, phase_shear=1)
+    srv = ile.ile_server_create(gu.ctx())
+    try:
+        alone = ile.ile_server_wait(srv, ile.ile_server_submit(srv, ph, jo), 120000)
+        others = [_submit(srv, s) for s in _specs(pool)[:6]]
+        jid = ile.ile_server_submit(srv, ph, jo)
+        mixed = ile.ile_server_wait(srv, jid, 120000)
+        for j, _ in others:
+            ile.ile_server_wait(srv, j, 120000)
+    finally:
+        ile.ile_server_destroy(srv)
+    assert alone.status == 0 and mixed.status == 0
+    assert _res(alone) == _res(mixed)
+    pr = orc.make_prior(t_window=p.t_window, d_min=p.d_min, d_max=p.d_max)
+    dims = list(range(7))
+    zseed, m = seed ^ 0x9E3779B97F4A7C15, 1 << 16
+    g, state, shear = None, None, 0
+    props, ths, lls = [], [], []
+    for rnd in range(max_rounds):
+        if g is None:
+            th, _ = orc.draw_prior(pr, seed, rnd, 0, n)
+            lr = np.zeros(n)
+        else:
+            th, lr = orc.draw_gmm(pr, g, seed, rnd, 0, n)
+        L = orc.lnL(p, th)
+        props.append(g)
+        ths.append(th)
+        lls.append(L)
+        o = orc.marginalize(orc.pool_mixture_lw(pr, props, ths, lls))
+        print(f"oracle round {rnd}: n_eff {o['n_eff']:.2f} ln L {o['ln_L']:.9f}")
+        if o["n_eff"] >= target or rnd + 1 == max_rounds:
+            break
+        lw = L + lr
+        if state is None:
+            shear = orc.phase_shear_sign(th, lw)
+        state = orc.em_fit(th, lw, dims, state=state, n_iter=8, n_comp=8, temper_ess=1.0 / 16.0, shear=shear)
+        w, mu, cov = state
+        g0 = orc.make_gmm(w, mu, cov, dims, shear=shear)
+        lz = [math.log(max(orc.gmm_inbox_mass(pr, g0, j, zseed, rnd + 1, m), 0.5 / m)) for j in range(len(w))]
+        g = orc.make_gmm(w, mu, cov, dims, ln_Z=lz, eps_def=0.05, shear=shear)
+    print("pooled job", alone.rounds, alone.marg.ln_L, alone.marg.n_eff, "oracle", len(ths), o["ln_L"], o["n_eff"])
+    assert alone.rounds == len(ths)
+    assert abs(alone.marg.ln_L - o["ln_L"]) <= 1e-8 * max(1.0, abs(o["ln_L"]))
+    assert abs(alone.marg.n_eff - o["n_eff"]) <= 1e-6 * o["n_eff"]

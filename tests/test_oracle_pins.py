@@ -671,6 +671,118 @@ def test_gmm_draw_density_counts_failed_attempts(orc):
     assert abs(r0.mean() - 1) > 10 * r0.std() / math.sqrt(n)
 
 
+def _phase_gmm(orc, prior, shear, dims=(0, 1, 4, 5, 6)):
+    """Two components over sky, inclination and the phases; the second is
+    wide along phi_c (a ridge at fixed psi + shear phi_c)."""
+    dims = list(dims)
+    means = [[1.0, 0.3, 0.5, 2.0, 1.0], [4.0, -0.4, -0.7, 5.0, 2.5]]
+    covs = [np.diag([0.05, 0.02, 0.01, 0.04, 0.01]), np.diag([0.2, 0.05, 0.02, 4.0, 0.003])]
+    g = orc.make_gmm([0.5, 0.5], means, covs, dims, shear=shear)
+    lz = [math.log(orc.gmm_inbox_mass(prior, g, j, 31, 0, 1 << 16)) for j in range(2)]
+    return orc.make_gmm([0.5, 0.5], means, covs, dims, ln_Z=lz, shear=shear), means, covs
+
+
+@pytest.mark.parametrize("shear", [1, -1])
+def test_PS1_sheared_mixture_is_a_density_of_its_draws(orc, shear):
+    """Phase-sheared mixture (column 6 of the mixture is (psi + s phi_c) mod pi):
+    its draws satisfy the importance identity E_{p_s}[p / p_s] = 1, prior
+    draws satisfy E_p[p_s / p] = 1 (p_s integrates to one over the support),
+    and the draws of the ridge component have y = (psi + s phi_c) mod pi
+    concentrated at the component's mean with its standard deviation while
+    psi alone spreads over its range.  A density evaluated in the unsheared
+    coordinates fails the first identity."""
+    prior = orc.make_prior()
+    g, means, covs = _phase_gmm(orc, prior, shear)
+    n = 60000
+    th, lr = orc.draw_gmm(prior, g, 77, 2, 0, n)
+    r = np.exp(lr)
+    assert abs(r.mean() - 1) < 4 * r.std() / math.sqrt(n)
+    thp, _ = orc.draw_prior(prior, 78, 0, 0, n)
+    q = np.exp(orc.gmm_ln_ps_batch(prior, g, thp) - np.array([orc.ln_prior(prior, thp[:, i]) for i in range(n)]))
+    assert abs(q.mean() - 1) < 4 * q.std() / math.sqrt(n)
+    # the ridge component: samples near its sky position (about 2 % of them
+    # defensive prior draws, hence median and median absolute deviation)
+    sel = np.abs(th[0] - means[1][0]) < 0.3
+    y = np.mod(th[6, sel] + shear * th[5, sel], math.pi)
+    med = np.median(y)
+    assert abs(med - means[1][4]) < 0.005
+    assert abs(1.4826 * np.median(np.abs(y - med)) - math.sqrt(covs[1][4][4])) < 0.005
+    assert np.std(th[6, sel]) > 0.6          # psi alone is spread (uniform: pi/sqrt(12) = 0.91)
+    # the same draws scored by a mixture with the same parameters but no shear
+    g0 = orc.make_gmm([0.5, 0.5], means, covs, [0, 1, 4, 5, 6], ln_Z=[g.ln_Z[0], g.ln_Z[1]])
+    lr0 = np.array([orc.ln_prior(prior, th[:, i]) for i in range(n)]) - orc.gmm_ln_ps_batch(prior, g0, th)
+    r0 = np.exp(lr0)
+    assert abs(r0.mean() - 1) > 10 * r0.std() / math.sqrt(n)
+
+
+def test_PS2_shear_sign_and_round_trip(orc):
+    """The shear sign follows the inclination of the best sample; shearing
+    by s then by -s returns every phase pair (mod its period)."""
+    th = np.zeros((7, 4))
+    th[4] = [0.9, -0.2, 0.3, -0.8]
+    assert orc.phase_shear_sign(th, [1.0, 5.0, 2.0, -np.inf]) == -1
+    assert orc.phase_shear_sign(th, [7.0, 5.0, 2.0, np.nan]) == 1
+    rng = np.random.default_rng(3)
+    t = np.zeros((7, 1000))
+    t[5] = rng.uniform(0, 2 * math.pi, 1000)
+    t[6] = rng.uniform(0, math.pi, 1000)
+    for s in (1, -1):
+        u = orc.shear_theta(t, s)
+        assert np.all((u[6] >= 0) & (u[6] < math.pi))
+        back = orc.shear_theta(u, -s)
+        d = np.mod(back[6] - t[6] + math.pi / 2, math.pi) - math.pi / 2
+        assert np.max(np.abs(d)) < 1e-12
+
+
+def _von_mises_rounds(orc, prior, kappa, phi0, rounds, n, seed):
+    """An adaptive-like run on L = exp(kappa cos(phi_c - phi0)): the prior,
+    then mixtures over phi_c of growing accuracy (the other columns from the
+    prior).  Returns proposals, thetas, lnLs."""
+    props, ths, lls = [None], [], []
+    for r in range(rounds):
+        g = props[r]
+        if g is None:
+            th, _ = orc.draw_prior(prior, seed, r, 0, n)
+        else:
+            th, _ = orc.draw_gmm(prior, g, seed, r, 0, n)
+        ths.append(th)
+        lls.append(kappa * np.cos(th[5] - phi0))
+        sd = 2.0 / math.sqrt(kappa) / (r + 1)     # proposals narrower than the target
+        g = orc.make_gmm([1.0], [[phi0 + 0.1 * r]], [[[sd * sd]]], [5], eps_def=0.05)
+        lz = [math.log(orc.gmm_inbox_mass(prior, g, 0, seed + 1, r, 1 << 15))]
+        props.append(orc.make_gmm([1.0], [[phi0 + 0.1 * r]], [[[sd * sd]]], [5], ln_Z=lz, eps_def=0.05))
+    return props[:rounds], ths, lls
+
+
+def test_PP1_mixture_pool_closed_form_and_bounds(orc):
+    """Samples pooled as draws of the equal-weight mixture of the rounds'
+    proposals (eq. (lnL:MonteCarlo) with that mixture as p_s): on
+    L = exp(kappa cos(phi_c - phi0)) with a uniform phi_c prior the integral is
+    the modified Bessel value I0(kappa); the pooled estimate must match it
+    within its Monte Carlo error, every weight must be at most R L (the prior
+    is a member of the mixture), and one round from the prior gives lw = lnL.
+    Scoring each sample by its own round's proposal alone also estimates I0,
+    but with a larger spread; a pool that forgets the 1/R of the mixture is
+    off by ln R."""
+    from scipy.special import i0e
+    prior = orc.make_prior()
+    kappa, phi0, R, n = 40.0, 2.0, 4, 8000
+    props, ths, lls = _von_mises_rounds(orc, prior, kappa, phi0, R, n, 404)
+    lw = orc.pool_mixture_lw(prior, props, ths, lls)
+    L = np.concatenate(lls)
+    assert np.all(lw <= L + math.log(R) + 1e-12)
+    w = np.exp(lw - kappa)
+    est, err = w.mean(), w.std() / math.sqrt(len(w))
+    exact = i0e(kappa)                       # I0(kappa) e^{-kappa}
+    assert abs(est - exact) < 4 * err
+    assert abs(math.log(est) - math.log(exact)) < 0.02
+    # one prior round
+    lw1 = orc.pool_mixture_lw(prior, props[:1], ths[:1], lls[:1])
+    assert np.array_equal(lw1, np.asarray(lls[0], dtype=np.float64))
+    # forgetting the 1/R: off by ln R, far outside the error
+    assert abs(math.log(np.exp(lw + math.log(R) - kappa).mean()) - math.log(exact)) > 20 * err / exact
+
+
 # ------------------------------------------------ time-marginalised lnL
 def test_PT1_time_constant_Q_closed_form(orc):
     """Q constant in time makes lnL independent of t, so the time integral is
