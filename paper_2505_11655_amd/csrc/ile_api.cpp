@@ -1007,20 +1007,19 @@ ile_status draw_batch(ile_ctx *ctx, int policy, const std::vector<DrawJob> &jobs
 }
 
 ile_status pool_batch(ile_ctx *ctx, int policy, const std::vector<PoolJob> &jobs, hipStream_t st) {
-    const int64_t tile = 2048;
-    std::vector<Tile> tiles;
-    for (size_t j = 0; j < jobs.size(); j++) {
-        const int64_t n = (int64_t)(jobs[j].round + 1) * jobs[j].n_round;
-        for (int64_t t = 0; t < n; t += tile) tiles.push_back(Tile{(int32_t)j, 0, t, std::min(t + tile, n)});
+    if (jobs.empty()) return ILE_OK;
+    std::vector<PoolJob> pj(jobs);
+    int64_t nt = 0;
+    for (PoolJob &q : pj) {
+        q.tile_begin = nt;
+        nt += ((int64_t)(q.round + 1) * q.n_round + kPoolTileSamples - 1) / kPoolTileSamples;
     }
-    if (tiles.empty()) return ILE_OK;
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     void *dj = nullptr, *dt = nullptr;
     int slot = -1;
-    ile_status s = batch_upload(ctx, jobs.data(), jobs.size() * sizeof(PoolJob), tiles.data(),
-                                tiles.size() * sizeof(Tile), &dj, &dt, &slot, st);
+    ile_status s = batch_upload(ctx, pj.data(), pj.size() * sizeof(PoolJob), nullptr, 0, &dj, &dt, &slot, st);
     if (s != ILE_OK) return s;
-    hipError_t e = launch_pool_mix(policy, (const PoolJob *)dj, (const Tile *)dt, (int)tiles.size(), st);
+    hipError_t e = launch_pool_mix(policy, (const PoolJob *)dj, (int)pj.size(), nt, st);
     if (e != hipSuccess) return dev_fail(ctx, e, "mixture pool update");
     return batch_done(ctx, slot, st);
 }

@@ -331,8 +331,12 @@ struct PoolJob {
     PriorDev pr;
     int64_t n_round;
     int32_t round;
+    int32_t pad_;
+    int64_t tile_begin;   // first block of this job (blocks cover the jobs in order)
 };
-hipError_t launch_pool_mix(int policy, const PoolJob *d_jobs, const Tile *d_tiles, int n_tiles, hipStream_t st);
+// Samples per tile of the pool update (one block each).
+constexpr int64_t kPoolTileSamples = 512;
+hipError_t launch_pool_mix(int policy, const PoolJob *d_jobs, int n_jobs, int64_t n_tiles, hipStream_t st);
 
 // Inverse-CDF map of seven uniforms onto the prior: alpha ~ U[0, 2pi),
 // p(dec) = cos(dec)/2, t ~ U[-t_w, t_w], p(D) = 3 D^2/(D_max^3 - D_min^3)

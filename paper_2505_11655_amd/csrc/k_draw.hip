@@ -298,47 +298,127 @@ void launch_draw_t(bool mix, const DrawJob *d_jobs, const Tile *d_tiles, int n_t
                            tile);
 }
 
-// Mixture pool update (see PoolJob).  One thread per sample of rounds 0..r;
-// the proposals are read through the scalar cache (uniform per block).
+// Mixture pool update (see PoolJob).  A block takes kPoolTile samples of one
+// job, kPoolSpt per thread held in registers in the mixture's coordinates.
+// For each proposal q and component j (uniform across the block) the mean,
+// inverse Cholesky factor and constant are read through the scalar cache and
+// applied to all of the thread's samples, each of which keeps a running
+// log-sum over components and one over proposals:
+//   t_q = ln p_s,q(x) - ln p(x) = ln[ sum_j e^{lnc_j} N_j(x) / p_mix(x) + e^{ln_fb} ],
+// p_mix the prior of the mixture columns (the other columns' prior cancels).
+constexpr int kPoolSpt = 2;
+static_assert(kPoolTileSamples == (int64_t)kPoolSpt * kDrawThreads, "pool tile = samples per thread x block");
+
+__device__ __forceinline__ void lse_add(double &m, double &s, double t) {
+    if (!(t > -INFINITY)) return;
+    if (t > m) {
+        s = s * exp(m - t) + 1.0;
+        m = t;
+    } else {
+        s += exp(t - m);
+    }
+}
+
 template <class TT, class TO, class TL>
 __global__ void __launch_bounds__(kDrawThreads)
-    k_pool_mix(const PoolJob *__restrict__ jobs, const Tile *__restrict__ tiles) {
-    const Tile tl = tiles[blockIdx.x];
-    const PoolJob &J = jobs[tl.job];
+    k_pool_mix(const PoolJob *__restrict__ jobs, const int n_jobs) {
+    typedef __attribute__((address_space(4))) const GmmDev cgmm;
+    // this block's job: the last whose first block is at or before it
+    int jb = 0;
+    for (int q = 1; q < n_jobs; q++)
+        if (jobs[q].tile_begin <= (int64_t)blockIdx.x) jb = q;
+    const PoolJob &J = jobs[jb];
+    Tile tl;
+    tl.begin = ((int64_t)blockIdx.x - J.tile_begin) * kPoolTileSamples;
+    tl.end = min(tl.begin + kPoolTileSamples, (int64_t)(J.round + 1) * J.n_round);
     const TT *__restrict__ th = (const TT *)J.theta;
     const TO *__restrict__ L = (const TO *)J.lnL;
     TL *__restrict__ lw = (TL *)J.lw;
     const int r = J.round;
     const int64_t first_new = (int64_t)r * J.n_round;
     const double ln_rounds = log((double)(r + 1));
-    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += kDrawThreads) {
+    // the mixture columns (the same for every proposal of the job)
+    cgmm *hist = (cgmm *)J.hist;
+    const int d = r > 0 ? hist[r].n_dim : 0, shear = r > 0 ? hist[r].shear : 0;
+    int col[7];
+    double P[7];
+#pragma unroll
+    for (int a = 0; a < 7; a++) {
+        col[a] = a < d ? hist[r].dims[a] : 0;
+        P[a] = (col[a] == 0 || col[a] == 5) ? 2 * kPi : (col[a] == 6 ? kPi : 0.0);
+    }
+    const double c0 = -0.5 * d * log(2 * kPi);
+    double xm[kPoolSpt][7], lpm[kPoolSpt], m[kPoolSpt], sum[kPoolSpt];
+    int q0[kPoolSpt];
+#pragma unroll
+    for (int k = 0; k < kPoolSpt; k++) {
+        const int64_t i = tl.begin + threadIdx.x + (int64_t)k * kDrawThreads;
         double x[7];
 #pragma unroll
-        for (int c = 0; c < 7; c++) x[c] = (double)th[c * J.ld + i];
-        const double lp = ln_prior(J.pr, x);
-        // running ln sum of e^{t}: the prior's term is e^0
-        double m, sum;
-        int q0;
-        if (i >= first_new) {
-            m = 0.0;
-            sum = 1.0;
-            q0 = 1;
-        } else {
-            m = J.lmix[i];
-            sum = 1.0;
-            q0 = r;
+        for (int c = 0; c < 7; c++) x[c] = i < tl.end ? (double)th[c * J.ld + i] : 0.0;
+        // ln of the prior of the mixture columns
+        double lp = 0.0;
+        for (int a = 0; a < d; a++) lp += ln_prior_col(J.pr, col[a], x);
+        if (shear) x[6] = shear_phase(x[6], x[5], shear);
+#pragma unroll
+        for (int a = 0; a < 7; a++) xm[k][a] = pick7(x, col[a]);
+        lpm[k] = lp;
+        const bool fresh = i >= first_new;
+        m[k] = (fresh || i >= tl.end) ? 0.0 : J.lmix[i];   // the prior's term, e^0, is in every sum
+        sum[k] = 1.0;
+        q0[k] = i >= tl.end ? r + 1 : (fresh ? 1 : r);
+    }
+    const int qlo = tl.end > first_new ? 1 : r;
+    for (int q = qlo; q <= r; q++) {
+        cgmm &g = hist[q];
+        const int nc = g.n_comp;
+        double mm[kPoolSpt], ss[kPoolSpt];
+#pragma unroll
+        for (int k = 0; k < kPoolSpt; k++) {
+            mm[k] = -INFINITY;
+            ss[k] = 0.0;
+            lse_add(mm[k], ss[k], g.ln_fb);
         }
-        for (int q = q0; q <= r; q++) {
-            const double t = gmm_ln_ps(J.hist[q], J.pr, x) - lp;
-            if (!(t > -INFINITY)) continue;
-            if (t > m) {
-                sum = sum * exp(m - t) + 1.0;
-                m = t;
-            } else {
-                sum += exp(t - m);
+        for (int j = 0; j < nc; j++) {
+            if (g.lnc[j] == -INFINITY) continue;
+            const double cj = g.lnc[j] - g.logdet_half[j] + c0;
+            double df[kPoolSpt][7], qf[kPoolSpt];
+#pragma unroll
+            for (int a = 0; a < 7; a++) {
+                const double mu = g.mean[j][a];
+#pragma unroll
+                for (int k = 0; k < kPoolSpt; k++) df[k][a] = a < d ? wrapd(xm[k][a] - mu, P[a]) : 0.0;
             }
+#pragma unroll
+            for (int k = 0; k < kPoolSpt; k++) qf[k] = 0.0;
+            // one row of the inverse factor at a time (a few scalar registers)
+#pragma unroll
+            for (int a = 0; a < 7; a++) {
+                if (a >= d) break;
+                double y[kPoolSpt];
+#pragma unroll
+                for (int k = 0; k < kPoolSpt; k++) y[k] = 0.0;
+#pragma unroll
+                for (int b = 0; b <= a; b++) {
+                    const double lab = g.Linv[j][a][b];
+#pragma unroll
+                    for (int k = 0; k < kPoolSpt; k++) y[k] = fma(lab, df[k][b], y[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < kPoolSpt; k++) qf[k] = fma(y[k], y[k], qf[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < kPoolSpt; k++) lse_add(mm[k], ss[k], cj - 0.5 * qf[k] - lpm[k]);
         }
-        const double lm = m + log(sum);
+#pragma unroll
+        for (int k = 0; k < kPoolSpt; k++)
+            if (q >= q0[k] && mm[k] > -INFINITY) lse_add(m[k], sum[k], mm[k] + log(ss[k]));
+    }
+#pragma unroll
+    for (int k = 0; k < kPoolSpt; k++) {
+        const int64_t i = tl.begin + threadIdx.x + (int64_t)k * kDrawThreads;
+        if (i >= tl.end) continue;
+        const double lm = m[k] + log(sum[k]);
         J.lmix[i] = lm;
         lw[i] = (TL)((double)L[i] - lm + ln_rounds);
     }
@@ -346,17 +426,16 @@ __global__ void __launch_bounds__(kDrawThreads)
 
 }  // namespace
 
-hipError_t launch_pool_mix(int policy, const PoolJob *d_jobs, const Tile *d_tiles, int n_tiles, hipStream_t st) {
-    if (n_tiles <= 0) return hipSuccess;
+hipError_t launch_pool_mix(int policy, const PoolJob *d_jobs, int n_jobs, int64_t n_tiles, hipStream_t st) {
+    if (n_tiles <= 0 || n_jobs <= 0) return hipSuccess;
+    if (n_tiles > INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)n_tiles), block(kDrawThreads);
     if (policy == kFP64)
-        hipLaunchKernelGGL((k_pool_mix<double, double, double>), dim3(n_tiles), dim3(kDrawThreads), 0, st, d_jobs,
-                           d_tiles);
+        hipLaunchKernelGGL((k_pool_mix<double, double, double>), grid, block, 0, st, d_jobs, n_jobs);
     else if (policy == kFP32)
-        hipLaunchKernelGGL((k_pool_mix<float, float, float>), dim3(n_tiles), dim3(kDrawThreads), 0, st, d_jobs,
-                           d_tiles);
+        hipLaunchKernelGGL((k_pool_mix<float, float, float>), grid, block, 0, st, d_jobs, n_jobs);
     else
-        hipLaunchKernelGGL((k_pool_mix<float, double, double>), dim3(n_tiles), dim3(kDrawThreads), 0, st, d_jobs,
-                           d_tiles);
+        hipLaunchKernelGGL((k_pool_mix<float, double, double>), grid, block, 0, st, d_jobs, n_jobs);
     return hipGetLastError();
 }
 

@@ -351,18 +351,26 @@ def test_pooled_sheared_mixture_job_matches_oracle_loop(orc, pool):
     n, seed, max_rounds, target = 1 << 13, 909, 4, 1e9
     jo = ile.job_opts(adaptive=True, round_samples=n, max_rounds=max_rounds, n_eff_target=target, seed=seed,
                       pool=ile.ILE_POOL_MIXTURE, phase_shear=1)
+    # a second pooled job with a ragged round size, in the same passes
+    ph2 = ile.ProblemHost(pool[1], precision=ile.ILE_FP64)
+    jo2 = ile.job_opts(adaptive=True, round_samples=3001, max_rounds=5, n_eff_target=target, seed=77,
+                       pool=ile.ILE_POOL_MIXTURE, phase_shear=1)
     srv = ile.ile_server_create(gu.ctx())
     try:
         alone = ile.ile_server_wait(srv, ile.ile_server_submit(srv, ph, jo), 120000)
+        alone2 = ile.ile_server_wait(srv, ile.ile_server_submit(srv, ph2, jo2), 120000)
         others = [_submit(srv, s) for s in _specs(pool)[:6]]
         jid = ile.ile_server_submit(srv, ph, jo)
+        jid2 = ile.ile_server_submit(srv, ph2, jo2)
         mixed = ile.ile_server_wait(srv, jid, 120000)
+        mixed2 = ile.ile_server_wait(srv, jid2, 120000)
         for j, _ in others:
             ile.ile_server_wait(srv, j, 120000)
     finally:
         ile.ile_server_destroy(srv)
-    assert alone.status == 0 and mixed.status == 0
+    assert alone.status == 0 and mixed.status == 0 and alone2.status == 0 and mixed2.status == 0
     assert _res(alone) == _res(mixed)
+    assert _res(alone2) == _res(mixed2) and alone2.rounds == 5
     pr = orc.make_prior(t_window=p.t_window, d_min=p.d_min, d_max=p.d_max)
     dims = list(range(7))
     zseed, m = seed ^ 0x9E3779B97F4A7C15, 1 << 16
