@@ -97,33 +97,6 @@ __device__ __forceinline__ double wrapd(double d, double P) {
     return r > 0.5 * P ? r - P : r;
 }
 
-// ln N_j(wrap(x - mu_j)) through the inverse Cholesky factor.
-__device__ __forceinline__ double gmm_comp_logpdf(const GmmDev &g, const PriorDev &pr, int j, const double th[7]) {
-    const int d = g.n_dim;
-    double diff[7];
-#pragma unroll
-    for (int a = 0; a < 7; a++) {
-        diff[a] = 0.0;
-        if (a < d) {
-            double lo, hi, P;
-            const int c = g.dims[a];
-            support(pr, c, lo, hi, P);
-            diff[a] = wrapd(pick7(th, c) - g.mean[j][a], P);
-        }
-    }
-    double q = 0.0;
-#pragma unroll
-    for (int a = 0; a < 7; a++) {
-        if (a < d) {
-            double y = 0.0;
-#pragma unroll
-            for (int b = 0; b <= a; b++) y += g.Linv[j][a][b] * diff[b];
-            q += y * y;
-        }
-    }
-    return -0.5 * q - g.logdet_half[j] - 0.5 * d * log(2 * kPi);
-}
-
 // ln of the prior density of one column (the prior factorises by column).
 __device__ __forceinline__ double ln_prior_col(const PriorDev &pr, int c, const double th[7]) {
     switch (c) {
@@ -141,38 +114,105 @@ __device__ __forceinline__ double ln_prior_col(const PriorDev &pr, int c, const 
     }
 }
 
-// ln p_s(x) (the density of a mixture draw, above) by a running log-sum-exp
-// over the live components and the prior term.
-__device__ __forceinline__ double gmm_ln_ps(const GmmDev &g, const PriorDev &pr, const double th[7]) {
-    double m = -INFINITY, s = 0.0;
-    auto add = [&](double t) {
-        if (!(t > -INFINITY)) return;
-        if (t > m) {
-            s = s * exp(m - t) + 1.0;
-            m = t;
-        } else {
-            s += exp(t - m);
-        }
-    };
-    // prior of the columns outside the mixture
-    double lrest = 0.0;
-    for (int c = 0; c < 7; c++) {
-        bool in = false;
-        for (int a = 0; a < g.n_dim; a++) in = in || (g.dims[a] == c);
-        if (!in) lrest += ln_prior_col(pr, c, th);
+typedef __attribute__((address_space(4))) const GmmDev cgmm;
+
+__device__ __forceinline__ void lse_add(double &m, double &s, double t) {
+    if (!(t > -INFINITY)) return;
+    if (t > m) {
+        s = s * exp(m - t) + 1.0;
+        m = t;
+    } else {
+        s += exp(t - m);
     }
-    // the mixture's own coordinates (phase shear); the prior terms use theta
-    double x[7];
+}
+
+// The mixture's columns (uniform): count, shear, theta column and period of
+// each mixture dimension.
+struct MixCols {
+    int d, shear;
+    int col[7];
+    double P[7], iP[7];
+};
+__device__ __forceinline__ MixCols mix_cols(cgmm &g) {
+    MixCols mc;
+    mc.d = g.n_dim;
+    mc.shear = g.shear;
 #pragma unroll
-    for (int c = 0; c < 7; c++) x[c] = th[c];
-    if (g.shear) x[6] = shear_phase(th[6], th[5], g.shear);
-    for (int j = 0; j < g.n_comp; j++) {
-        if (g.lnc[j] == -INFINITY) continue;
-        add(g.lnc[j] + gmm_comp_logpdf(g, pr, j, x) + lrest);
+    for (int a = 0; a < 7; a++) {
+        mc.col[a] = a < mc.d ? g.dims[a] : 0;
+        const int c = mc.col[a];
+        mc.P[a] = (a < mc.d && (c == 0 || c == 5)) ? 2 * kPi : ((a < mc.d && c == 6) ? kPi : 0.0);
+        mc.iP[a] = mc.P[a] > 0.0 ? 1.0 / mc.P[a] : 0.0;
     }
-    add(g.ln_fb + ln_prior(pr, th));
-    if (!(m > -INFINITY)) return m;
-    return m + log(s);
+    return mc;
+}
+// A sample's mixture coordinates (phase shear applied) and ln of the prior of
+// the mixture columns (the other columns' prior cancels in ln p_s - ln p).
+__device__ __forceinline__ void mix_coords(const MixCols &mc, const PriorDev &pr, const double th[7], double xm[7],
+                                           double &lpm) {
+    lpm = 0.0;
+#pragma unroll
+    for (int a = 0; a < 7; a++) {
+        if (a < mc.d) lpm += ln_prior_col(pr, mc.col[a], th);
+        const double v = pick7(th, mc.col[a]);
+        xm[a] = (mc.col[a] == 6 && mc.shear) ? shear_phase(th[6], th[5], mc.shear) : v;
+    }
+}
+// t_k = ln p_s(x_k) - ln p(x_k) for NS samples of one mixture (the density of
+// a mixture draw above):
+//   t = ln[ sum_j e^{lnc_j} N_j(x) / p_mix(x) + e^{ln_fb} ],
+// by a running log-sum-exp.  The mixture is read through the scalar cache
+// (the component loop is uniform) and applied row by row to every sample; a
+// periodic offset is wrapped as u - P rint(u / P) (the floor form's value
+// except at exactly half a period, where both images are equally far).
+template <int NS>
+__device__ __forceinline__ void mix_log_ratio(cgmm &g, const MixCols &mc, const double (&xm)[NS][7],
+                                              const double (&lpm)[NS], double (&t)[NS]) {
+    const int d = mc.d;
+    const double c0 = -0.5 * d * log(2 * kPi);
+    double mm[NS], ss[NS];
+#pragma unroll
+    for (int k = 0; k < NS; k++) {
+        mm[k] = -INFINITY;
+        ss[k] = 0.0;
+        lse_add(mm[k], ss[k], g.ln_fb);
+    }
+    const int nc = g.n_comp;
+    for (int j = 0; j < nc; j++) {
+        if (g.lnc[j] == -INFINITY) continue;
+        const double cj = g.lnc[j] - g.logdet_half[j] + c0;
+        double df[NS][7], qf[NS];
+#pragma unroll
+        for (int a = 0; a < 7; a++) {
+            const double mu = g.mean[j][a];
+#pragma unroll
+            for (int k = 0; k < NS; k++) {
+                const double u = xm[k][a] - mu;
+                df[k][a] = a < d ? u - mc.P[a] * rint(u * mc.iP[a]) : 0.0;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NS; k++) qf[k] = 0.0;
+#pragma unroll
+        for (int a = 0; a < 7; a++) {
+            if (a >= d) break;
+            double y[NS];
+#pragma unroll
+            for (int k = 0; k < NS; k++) y[k] = 0.0;
+#pragma unroll
+            for (int b = 0; b <= a; b++) {
+                const double lab = g.Linv[j][a][b];
+#pragma unroll
+                for (int k = 0; k < NS; k++) y[k] = fma(lab, df[k][b], y[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < NS; k++) qf[k] = fma(y[k], y[k], qf[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < NS; k++) lse_add(mm[k], ss[k], cj - 0.5 * qf[k] - lpm[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NS; k++) t[k] = mm[k] > -INFINITY ? mm[k] + log(ss[k]) : -INFINITY;
 }
 
 // One candidate from component j: words w[0..15] give four Box-Muller pairs.
@@ -222,9 +262,8 @@ __device__ __forceinline__ bool gmm_candidate(const GmmDev &g, const PriorDev &p
     return true;
 }
 
-// Mixture draw of sample idx: th and ln p - ln p_s.
-__device__ __forceinline__ void draw_mix(const DrawJob &J, uint64_t idx, double th[7], double &lr) {
-    const GmmDev &g = *J.gmm;
+// Mixture draw of sample idx (theta only; the density follows for a pair).
+__device__ __forceinline__ void draw_mix(const DrawJob &J, const GmmDev &g, uint64_t idx, double th[7]) {
     uint32_t w[20];
     words(J.seed, idx, J.round, 0, 0, 5, w);
     prior_from_words(J.pr, w + 4, th);
@@ -251,27 +290,37 @@ __device__ __forceinline__ void draw_mix(const DrawJob &J, uint64_t idx, double 
             }
         }
     }
-    lr = ln_prior(J.pr, th) - gmm_ln_ps(g, J.pr, th);
 }
 
 template <class TT, bool MIX>
 __device__ __forceinline__ void draw_range(const DrawJob &J, int64_t begin, int64_t end) {
     TT *__restrict__ th_out = (TT *)J.theta;
     TT *__restrict__ lr_out = (TT *)J.lnpmps;
-    for (int64_t s = begin + threadIdx.x; s < end; s += kDrawThreads) {
-        const uint64_t idx = (uint64_t)(J.first + s);
-        double th[7];
-        double lr = 0.0;
-        if (!MIX || J.gmm == nullptr) {
+    if (!MIX || J.gmm == nullptr) {
+        for (int64_t s = begin + threadIdx.x; s < end; s += kDrawThreads) {
+            const uint64_t idx = (uint64_t)(J.first + s);
+            double th[7];
             uint32_t w[16];
             words(J.seed, idx, J.round, 0, 0, 4, w);
             prior_from_words(J.pr, w, th);
-        } else {
-            draw_mix(J, idx, th, lr);
-        }
 #pragma unroll
-        for (int c = 0; c < 7; c++) th_out[c * J.ld + s] = (TT)th[c];
-        if (lr_out) lr_out[s] = (TT)lr;
+            for (int c = 0; c < 7; c++) th_out[c * J.ld + s] = (TT)th[c];
+            if (lr_out) lr_out[s] = (TT)0;
+        }
+        return;
+    }
+    // mixture draws: theta, then ln p - ln p_s from the mixture read through
+    // the scalar cache
+    cgmm &g = *(cgmm *)J.gmm;
+    const MixCols mc = mix_cols(g);
+    for (int64_t s = begin + threadIdx.x; s < end; s += kDrawThreads) {
+        double th[1][7], xm[1][7], lpm[1], t[1];
+        draw_mix(J, *J.gmm, (uint64_t)(J.first + s), th[0]);
+        mix_coords(mc, J.pr, th[0], xm[0], lpm[0]);
+        mix_log_ratio<1>(g, mc, xm, lpm, t);
+#pragma unroll
+        for (int c = 0; c < 7; c++) th_out[c * J.ld + s] = (TT)th[0][c];
+        if (lr_out) lr_out[s] = (TT)(-t[0]);
     }
 }
 
@@ -298,126 +347,60 @@ void launch_draw_t(bool mix, const DrawJob *d_jobs, const Tile *d_tiles, int n_t
                            tile);
 }
 
-// Mixture pool update (see PoolJob).  A block takes kPoolTile samples of one
-// job, kPoolSpt per thread held in registers in the mixture's coordinates.
-// For each proposal q and component j (uniform across the block) the mean,
-// inverse Cholesky factor and constant are read through the scalar cache and
-// applied to all of the thread's samples, each of which keeps a running
-// log-sum over components and one over proposals:
-//   t_q = ln p_s,q(x) - ln p(x) = ln[ sum_j e^{lnc_j} N_j(x) / p_mix(x) + e^{ln_fb} ],
-// p_mix the prior of the mixture columns (the other columns' prior cancels).
+// Mixture pool update (see PoolJob).  A block takes kPoolTileSamples samples
+// of one job, kPoolSpt per thread held in registers in the mixture's
+// coordinates; each proposal q adds t_q = ln p_s,q(x) - ln p(x) (mix_log_ratio)
+// to every sample's running log-sum over proposals.
 constexpr int kPoolSpt = 2;
 static_assert(kPoolTileSamples == (int64_t)kPoolSpt * kDrawThreads, "pool tile = samples per thread x block");
 
-__device__ __forceinline__ void lse_add(double &m, double &s, double t) {
-    if (!(t > -INFINITY)) return;
-    if (t > m) {
-        s = s * exp(m - t) + 1.0;
-        m = t;
-    } else {
-        s += exp(t - m);
-    }
-}
 
 template <class TT, class TO, class TL>
 __global__ void __launch_bounds__(kDrawThreads)
     k_pool_mix(const PoolJob *__restrict__ jobs, const int n_jobs) {
-    typedef __attribute__((address_space(4))) const GmmDev cgmm;
     // this block's job: the last whose first block is at or before it
     int jb = 0;
     for (int q = 1; q < n_jobs; q++)
         if (jobs[q].tile_begin <= (int64_t)blockIdx.x) jb = q;
     const PoolJob &J = jobs[jb];
-    Tile tl;
-    tl.begin = ((int64_t)blockIdx.x - J.tile_begin) * kPoolTileSamples;
-    tl.end = min(tl.begin + kPoolTileSamples, (int64_t)(J.round + 1) * J.n_round);
+    const int64_t begin = ((int64_t)blockIdx.x - J.tile_begin) * kPoolTileSamples;
+    const int64_t end = min(begin + kPoolTileSamples, (int64_t)(J.round + 1) * J.n_round);
     const TT *__restrict__ th = (const TT *)J.theta;
     const TO *__restrict__ L = (const TO *)J.lnL;
     TL *__restrict__ lw = (TL *)J.lw;
     const int r = J.round;
     const int64_t first_new = (int64_t)r * J.n_round;
     const double ln_rounds = log((double)(r + 1));
-    // the mixture columns (the same for every proposal of the job)
     cgmm *hist = (cgmm *)J.hist;
-    const int d = r > 0 ? hist[r].n_dim : 0, shear = r > 0 ? hist[r].shear : 0;
-    int col[7];
-    double P[7];
-#pragma unroll
-    for (int a = 0; a < 7; a++) {
-        col[a] = a < d ? hist[r].dims[a] : 0;
-        P[a] = (col[a] == 0 || col[a] == 5) ? 2 * kPi : (col[a] == 6 ? kPi : 0.0);
-    }
-    const double c0 = -0.5 * d * log(2 * kPi);
+    // the mixture columns are the same for every proposal of the job
+    MixCols mc{};
+    if (r > 0) mc = mix_cols(hist[r]);
     double xm[kPoolSpt][7], lpm[kPoolSpt], m[kPoolSpt], sum[kPoolSpt];
     int q0[kPoolSpt];
 #pragma unroll
     for (int k = 0; k < kPoolSpt; k++) {
-        const int64_t i = tl.begin + threadIdx.x + (int64_t)k * kDrawThreads;
+        const int64_t i = begin + threadIdx.x + (int64_t)k * kDrawThreads;
         double x[7];
 #pragma unroll
-        for (int c = 0; c < 7; c++) x[c] = i < tl.end ? (double)th[c * J.ld + i] : 0.0;
-        // ln of the prior of the mixture columns
-        double lp = 0.0;
-        for (int a = 0; a < d; a++) lp += ln_prior_col(J.pr, col[a], x);
-        if (shear) x[6] = shear_phase(x[6], x[5], shear);
-#pragma unroll
-        for (int a = 0; a < 7; a++) xm[k][a] = pick7(x, col[a]);
-        lpm[k] = lp;
+        for (int c = 0; c < 7; c++) x[c] = i < end ? (double)th[c * J.ld + i] : 0.0;
+        mix_coords(mc, J.pr, x, xm[k], lpm[k]);
         const bool fresh = i >= first_new;
-        m[k] = (fresh || i >= tl.end) ? 0.0 : J.lmix[i];   // the prior's term, e^0, is in every sum
+        m[k] = (fresh || i >= end) ? 0.0 : J.lmix[i];   // the prior's term, e^0, is in every sum
         sum[k] = 1.0;
-        q0[k] = i >= tl.end ? r + 1 : (fresh ? 1 : r);
+        q0[k] = i >= end ? r + 1 : (fresh ? 1 : r);
     }
-    const int qlo = tl.end > first_new ? 1 : r;
+    const int qlo = end > first_new ? 1 : r;
     for (int q = qlo; q <= r; q++) {
-        cgmm &g = hist[q];
-        const int nc = g.n_comp;
-        double mm[kPoolSpt], ss[kPoolSpt];
-#pragma unroll
-        for (int k = 0; k < kPoolSpt; k++) {
-            mm[k] = -INFINITY;
-            ss[k] = 0.0;
-            lse_add(mm[k], ss[k], g.ln_fb);
-        }
-        for (int j = 0; j < nc; j++) {
-            if (g.lnc[j] == -INFINITY) continue;
-            const double cj = g.lnc[j] - g.logdet_half[j] + c0;
-            double df[kPoolSpt][7], qf[kPoolSpt];
-#pragma unroll
-            for (int a = 0; a < 7; a++) {
-                const double mu = g.mean[j][a];
-#pragma unroll
-                for (int k = 0; k < kPoolSpt; k++) df[k][a] = a < d ? wrapd(xm[k][a] - mu, P[a]) : 0.0;
-            }
-#pragma unroll
-            for (int k = 0; k < kPoolSpt; k++) qf[k] = 0.0;
-            // one row of the inverse factor at a time (a few scalar registers)
-#pragma unroll
-            for (int a = 0; a < 7; a++) {
-                if (a >= d) break;
-                double y[kPoolSpt];
-#pragma unroll
-                for (int k = 0; k < kPoolSpt; k++) y[k] = 0.0;
-#pragma unroll
-                for (int b = 0; b <= a; b++) {
-                    const double lab = g.Linv[j][a][b];
-#pragma unroll
-                    for (int k = 0; k < kPoolSpt; k++) y[k] = fma(lab, df[k][b], y[k]);
-                }
-#pragma unroll
-                for (int k = 0; k < kPoolSpt; k++) qf[k] = fma(y[k], y[k], qf[k]);
-            }
-#pragma unroll
-            for (int k = 0; k < kPoolSpt; k++) lse_add(mm[k], ss[k], cj - 0.5 * qf[k] - lpm[k]);
-        }
+        double t[kPoolSpt];
+        mix_log_ratio<kPoolSpt>(hist[q], mc, xm, lpm, t);
 #pragma unroll
         for (int k = 0; k < kPoolSpt; k++)
-            if (q >= q0[k] && mm[k] > -INFINITY) lse_add(m[k], sum[k], mm[k] + log(ss[k]));
+            if (q >= q0[k]) lse_add(m[k], sum[k], t[k]);
     }
 #pragma unroll
     for (int k = 0; k < kPoolSpt; k++) {
-        const int64_t i = tl.begin + threadIdx.x + (int64_t)k * kDrawThreads;
-        if (i >= tl.end) continue;
+        const int64_t i = begin + threadIdx.x + (int64_t)k * kDrawThreads;
+        if (i >= end) continue;
         const double lm = m[k] + log(sum[k]);
         J.lmix[i] = lm;
         lw[i] = (TL)((double)L[i] - lm + ln_rounds);
