@@ -55,13 +55,14 @@ def _samples(rng, th0, n_prior, n_peak, policy, widths):
 
 @pytest.mark.parametrize("R", [1, 4])
 @pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("cfg", ["hl5", "hlv9"])
+@pytest.mark.parametrize("cfg", ["hl5", "hlv9", "hlv17"])
 def test_tmarg_matches_oracle(orc, recs, cfg, policy, R):
     """Prior samples (ragged count) plus samples near the peak of an SNR-20
-    event; HL 5 modes (window staged in LDS) and HLV 9 modes (FP32: LDS; FP64:
-    L2)."""
-    dets, n_modes, rec = {"hl5": (["H", "L"], 5, "c1"), "hlv9": (["H", "L", "V"], 9, "c2")}[cfg]
-    probs, _ = chirpgen.build_event(recs[rec], dets, n_modes, 30.0, 2.0, 20.0, noise_seed=11)
+    event; HL 5 modes (window staged in LDS), HLV 9 modes (FP32: LDS; FP64:
+    L2) and HLV 17 modes (the strong-source mode set, q = 20)."""
+    dets, n_modes, rec, q = {"hl5": (["H", "L"], 5, "c1", 2.0), "hlv9": (["H", "L", "V"], 9, "c2", 2.0),
+                             "hlv17": (["H", "L", "V"], 17, "c3", 20.0)}[cfg]
+    probs, _ = chirpgen.build_event(recs[rec], dets, n_modes, 30.0, q, 20.0, noise_seed=11)
     p = probs[0]
     th0 = np.array(recs[rec]["theta"])
     rng = np.random.default_rng(70)
