@@ -388,7 +388,6 @@ void fill_mixed(const ile_problem *P, const std::vector<int> &keep, const std::v
     };
     U64.assign((size_t)kp * NM * NM * 2, 0.0);
     V64.assign((size_t)kp * NM * NM * 2, 0.0);
-    W.assign((size_t)kp * pt.P * 4, 0.0f);
     for (int k = 0; k < K; k++)
         for (int sa = 0; sa < NM; sa++)
             for (int sb = 0; sb < NM; sb++) {
@@ -403,18 +402,34 @@ void fill_mixed(const ile_problem *P, const std::vector<int> &keep, const std::v
                 V64[o] = v.real();
                 V64[o + 1] = v.imag();
             }
-    for (int k = 0; k < K; k++)
+    // The quadratic form over the real vector v = (dr_0, di_0, dr_1, di_1, ...)
+    // of the amplitude offsets, per detector: the upper triangle (row by row)
+    // of M with M_ii the diagonal and M_ij = 2 S_ij (i < j), S the symmetric
+    // matrix of delta^+ U delta + Re(delta^T V delta).  Per pair a <= b
+    // (weight f = 2 off the diagonal, 1 on it) the coefficients of
+    // (dr_a dr_b, di_a di_b, dr_a di_b, di_a dr_b) are
+    // f (Ur + Vr, Ur - Vr, -Ui - Vi, Ui - Vi).
+    const int NV = 2 * NM, NT = NV * (NV + 1) / 2;
+    auto tri = [&](int i, int j) { return (size_t)(i * (2 * NV - i + 1)) / 2 + (size_t)(j - i); };
+    W.assign((size_t)kp * NT, 0.0f);
+    std::vector<double> Mk((size_t)NT);
+    for (int k = 0; k < K; k++) {
+        std::fill(Mk.begin(), Mk.end(), 0.0);
         for (int p = 0; p < pt.P; p++) {
             const int sa = pt.a[p], sb = pt.b[p];
             const size_t o = 2 * (((size_t)k * NM + sa) * NM + sb);
             const double ur = U64[o], ui = U64[o + 1], vr = V64[o], vi = V64[o + 1];
             const double f = sa == sb ? 1.0 : 2.0;
-            float *w = &W[4 * ((size_t)k * pt.P + p)];
-            w[0] = (float)(f * (ur + vr));
-            w[1] = (float)(f * (ur - vr));
-            w[2] = (float)(f * (-ui - vi));
-            w[3] = (float)(f * (ui - vi));
+            Mk[tri(2 * sa, 2 * sb)] += f * (ur + vr);
+            Mk[tri(2 * sa + 1, 2 * sb + 1)] += f * (ur - vr);
+            Mk[tri(2 * sa, 2 * sb + 1)] += f * (-ui - vi);
+            if (sa < sb)
+                Mk[tri(2 * sa + 1, 2 * sb)] += f * (ui - vi);
+            else
+                Mk[tri(2 * sa, 2 * sa + 1)] += f * (ui - vi);   // di_a dr_a = dr_a di_a
         }
+        for (int t = 0; t < NT; t++) W[(size_t)k * NT + t] = (float)Mk[t];
+    }
 }
 
 }  // namespace

@@ -17,7 +17,7 @@ namespace ile {
 
 namespace {
 
-constexpr int kNu = 2048, kNb = 2048;
+constexpr int kNu = 4096, kNb = 4096;
 constexpr double kAMax = 200.0, kAScale = 1.0;
 constexpr double kB0 = -13.815510557964274;   // ln 1e-6
 constexpr double kB1 = 23.025850929940457;    // ln 1e10

@@ -20,10 +20,12 @@
 // gives the same lnL up to rounding (no reference: r = 0, plain FP32
 // arithmetic); a reference near the samples gives the accuracy.
 //
-// The quadratic form over delta uses, per detector and pair a <= b, the four
-// real weights W = f (Ur + Vr, Ur - Vr, -Ui - Vi, Ui - Vi) (f = 2 for a < b,
-// 1 on the diagonal) of the products (dr_a dr_b, di_a di_b, dr_a di_b, di_a dr_b):
-// eight instructions per pair and detector.
+// The quadratic form over delta is, per detector, a real quadratic form in
+// the 2n components v = (dr_0, di_0, dr_1, ...): with M the upper triangle of
+// its matrix (off-diagonal entries doubled) it is sum_i v_i sum_{j>=i} M_ij v_j,
+// one fused multiply-add per entry plus one per row: (2n)(2n+1)/2 + 2n
+// instructions per detector (189 for 9 modes, against 8 per mode pair, 360,
+// when every product of a pair is formed on its own).
 #pragma once
 
 #include "k_lnl_impl.h"
@@ -37,11 +39,9 @@ struct RefKernel {
     static constexpr int NM = MS::n;
     static constexpr int NE = LKG::NE;
     static constexpr int kG = LDS ? lds_global_dets(S, K, kMixed) : 0;
-    struct w4 {
-        float x, y, z, w;
-    };
+    static constexpr int NV = 2 * NM, NT = NV * (NV + 1) / 2;
     typedef __attribute__((address_space(4))) const EvalJob cjob;
-    typedef __attribute__((address_space(4))) const w4 cw4;
+    typedef __attribute__((address_space(4))) const float cf1;
     typedef __attribute__((address_space(4))) const cpx<float> ccf;
 
     __device__ __forceinline__ static void run(const EvalJob *Jp, const int64_t begin, const int64_t end,
@@ -68,7 +68,7 @@ struct RefKernel {
         double *__restrict__ outL = (double *)J.lnL;
         double *__restrict__ outW = (double *)J.lw;
         const int64_t ld = J.ld;
-        cw4 *Wt = (cw4 *)J.Ut;                       // [K][P] pair weights
+        cf1 *Wt = (cf1 *)J.Ut;                       // [K][NT] quadratic-form rows
         ccf *rg = (ccf *)J.ref_rg;                   // r [K][NM], then G [K][NM]
         const double *C0p = J.ref_C0;
 
@@ -153,16 +153,18 @@ struct RefKernel {
                     B = fma(dr[a], qr - gre, B);
                     B = fma(di[a], qi - gim, B);
                 });
-                // quadratic form over the pairs a <= b
-                constexpr PairTable pt = MS::pt;
-                static_for<0, MS::P>([&](auto P_) {
-                    constexpr int p = decltype(P_)::value;
-                    constexpr int a = pt.a[p], b = pt.b[p];
-                    cw4 &w = Wt[k * MS::P + p];
-                    Cq = fma(dr[a] * dr[b], w.x, Cq);
-                    Cq = fma(di[a] * di[b], w.y, Cq);
-                    Cq = fma(dr[a] * di[b], w.z, Cq);
-                    Cq = fma(di[a] * dr[b], w.w, Cq);
+                // quadratic form, row by row of the upper triangle
+                static_for<0, NV>([&](auto I_) {
+                    constexpr int i = decltype(I_)::value;
+                    constexpr int row = (i * (2 * NV - i + 1)) / 2;
+                    const float vi = (i & 1) ? di[i >> 1] : dr[i >> 1];
+                    float t = 0.0f;
+                    static_for<i, NV>([&](auto J_) {
+                        constexpr int j = decltype(J_)::value;
+                        const float vj = (j & 1) ? di[j >> 1] : dr[j >> 1];
+                        t = fma(Wt[k * NT + row + (j - i)], vj, t);
+                    });
+                    Cq = fma(vi, t, Cq);
                 });
             }
             const double lnL = (A - *C0p) + (double)fma(-0.25f, Cq, B);

@@ -275,3 +275,62 @@ def recs_c1():
     recs = chirpgen.load_injections()
     probs, _ = chirpgen.build_event(recs["c1"], ["H", "L"], 5, 30.0, 2.0, 20.0, noise_seed=13)
     return probs[0]
+
+
+@pytest.mark.parametrize("T2,a_max", [(4.0, 200.0), (4.0e7, 150.0)])
+@pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
+def test_distance_table_near_prior_bounds(orc, policy, T2, a_max):
+    """The distance table where it is weakest: large a = T1/sqrt(T2) with the
+    best distance 2 T1/T2 crossing D_min (T2 = 4: s* runs up to 200 against
+    s_max = 100) or D_max (T2 = 4e7: s* sweeps through 1/30).  A one-detector,
+    one-mode problem with a constant Q window and U = [[u]] gives every
+    sample the same T2 and a T1 that sweeps +-|c||q| as psi turns; the lnL of
+    each sample is compared with adaptive quadrature of the distance integral
+    (a <= 195: the table covers |a| <= 200).  The bound is the table's
+    stated one in these bands (2e-3; FP32 adds its magnitude-scaled term);
+    the print gives the measured error."""
+    import chirpgen
+    pos, resp = chirpgen.detectors(["H"])
+    n_win = 410
+    th = np.zeros((7, 1200))
+    th[0], th[1], th[2], th[3], th[4], th[5] = 1.0, 0.3, 0.0, 100.0, 0.9, 0.4
+    th[6] = np.linspace(0.0, np.pi, 1200, endpoint=False)
+    # |c| at these angles (s = 1), from the oracle with a unit window
+    p0 = chirpgen.Problem(modes=[(2, 2)], det_names=["H"], det_pos=pos, det_resp=resp, gmst=0.7,
+                          Q=np.ones((1, 1, n_win), complex), U=np.ones((1, 1, 1), complex), V=None)
+    _, _, T2u = orc.lnL(p0, th[:, :1], return_terms=True)
+    c2 = T2u[0]                                   # |c|^2 with u = 1
+    u = T2 / c2
+    qmag = a_max * np.sqrt(T2) / np.sqrt(c2)      # |c| |q| = a_max sqrt(T2)
+    p = chirpgen.Problem(modes=[(2, 2)], det_names=["H"], det_pos=pos, det_resp=resp, gmst=0.7,
+                         Q=np.full((1, 1, n_win), qmag + 0j), U=np.full((1, 1, 1), u + 0j), V=None)
+    _, T1, T2s = orc.lnL(p, th, return_terms=True)
+    assert np.allclose(T2s, T2, rtol=1e-12)
+    s_star = 2 * T1 / T2s
+    sel = (np.abs(T1) / np.sqrt(T2s) >= 40.0) & (np.abs(T1) / np.sqrt(T2s) <= 195.0)   # inside the table
+    if T2 < 10:
+        sel &= (s_star > 50) & (s_star < 200)
+    else:
+        sel &= (s_star > 0.01) & (s_star < 0.1)
+    th = th[:, sel]
+    T1, T2s = T1[sel], T2s[sel]
+    assert th.shape[1] >= 100
+    job = ile.ile_prepare(gu.ctx(), ile.ProblemHost(p, precision=policy, dist_marg=True))
+    try:
+        L, _ = gu.gpu_eval(job, th.astype(np.float64 if policy == ile.ILE_FP64 else np.float32), policy)
+    finally:
+        ile.ile_job_release(job)
+    if policy == ile.ILE_FP32:   # the FP32 path's T1 from FP32 angles: compare at the same angles
+        _, T1, T2s = orc.lnL(p, th.astype(np.float32).astype(np.float64), return_terms=True)
+    ref = np.array([orc.ln_dist_marg(a, b) for a, b in zip(T1, T2s)])
+    d = np.abs(L - ref)
+    i = int(np.argmax(d))
+    print(f"T2={T2:g} policy {policy}: {th.shape[1]} samples, a in [{(T1 / np.sqrt(T2s)).min():.0f}, "
+          f"{(T1 / np.sqrt(T2s)).max():.0f}], max|d| = {d.max():.2e} at s* = {2 * T1[i] / T2s[i]:.4g}, "
+          f"median {np.median(d):.1e}")
+    # FP32: T1 and T2 carry relative errors ~1e-7; the FP32 policy's bound
+    # 1e-6 (|s T1| + s^2 T2 / 4) taken at the best distance within the prior
+    sc = np.clip(2 * T1 / T2s, 1.0 / 30.0, 100.0)
+    mag = np.abs(sc * T1) + sc * sc * T2s / 4
+    tol = 2e-3 if policy == ile.ILE_FP64 else 2e-3 + 1e-6 * mag
+    assert np.all(d <= tol)
