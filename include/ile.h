@@ -185,8 +185,13 @@ ile_status ile_eval_lnL_batch(ile_job *const *jobs, int32_t n_jobs, const int64_
  * The t column of theta is ignored; all other arguments are those of
  * ile_eval_lnL (lw_out = lnL_t + lnpmps).  oversample R: 1 or 4 (R = 4 resolves
  * a likelihood peak narrower than dt; the rule's error is O((dt/R)^2)).
- * ILE_FP32 and ILE_FP64 jobs without dist_marg only; other jobs, or another R,
- * give ILE_E_INVALID.  A node whose stencil leaves the window contributes 0;
+ * With prior.dist_marg the D column is ignored too and each node's value is
+ * the distance-marginalised one, ln L_D(T1(t_j), T2) from the distance table
+ * (T1, T2 at D = d_ref): time and distance integrated together, as the paper's
+ * timed runs integrate time (Appendix "Timing analysis") with distance
+ * marginalisation (Section "Adaptive volume integration").
+ * ILE_FP32 and ILE_FP64 jobs only; other jobs, or another R, give
+ * ILE_E_INVALID.  A node whose stencil leaves the window contributes 0;
  * no valid node gives -inf. */
 ile_status ile_eval_lnL_tmarg(ile_job *job, int64_t n, const void *theta, int64_t ld,
                               const void *lnpmps, void *lnL_out, void *lw_out, int32_t oversample,
@@ -451,8 +456,8 @@ typedef struct {
     double n_eff_target;      /* adaptive: default 1000 */
     uint64_t seed;
     int32_t tmarg_oversample; /* 0: pointwise lnL; 1 or 4: time-marginalised lnL (ile_eval_lnL_tmarg with
-                                 this R; plain ILE_FP32/ILE_FP64 jobs without dist_marg only), with
-                                 chunk_samples/16 samples per pass */
+                                 this R, distance-marginalised too with dist_marg; plain ILE_FP32 /
+                                 ILE_FP64 jobs only), with chunk_samples/16 samples per pass */
     int32_t integrator;       /* adaptive: ILE_INT_GMM (mixture refits), ILE_INT_AV (adaptive volume,
                                  ile_av_update with default options after each round) or ILE_INT_AC
                                  (adaptive Cartesian, ile_ac_update with floor 0.1 after each round) */

@@ -11,6 +11,7 @@ this module wraps it and adds definition-level numpy helpers:
   * ``lnL_exact``        - lnL with exact Q at the detector times (no window);
   * ``em_fit``           - weighted EM for the mixture proposal (see its docstring);
   * ``ln_dist_marg``     - the distance-marginalised likelihood by adaptive quadrature;
+  * ``lnL_tmarg_dist``   - the time- and distance-marginalised likelihood;
   * ``draw_av``, ``av_threshold``, ``av_refine_bins``, ``av_cells``, ``av_update``
                          - the adaptive-volume integrator (its readings are listed there);
   * ``draw_ac``, ``ac_update`` - the product-form adaptive Cartesian sampler;
@@ -223,6 +224,35 @@ def lnL_tmarg(prob, theta, oversample=4, threads=None):
     out = np.full(n, -np.inf)
     fin = np.isfinite(m)
     out[fin] = m[fin] + np.log(np.sum(np.exp(L[fin] - m[fin, None]), axis=1)) + lnw
+    return out
+
+
+def lnL_tmarg_dist(prob, theta, oversample=1, threads=None, d_min=None, d_max=None):
+    """Time- and distance-marginalised likelihood: the time nodes of
+    ``tmarg_grid`` with, at each node, the distance integral of
+    ``ln_dist_marg`` (adaptive quadrature) in place of a fixed distance:
+        ln L_{t,D} = ln sum_j (dt / (R 2 t_w)) L_D(T1(t_j), T2),
+    T1, T2 at s = 1 (D = d_ref) from the pointwise oracle.  The t and D rows
+    of theta are ignored.  Slow: one quadrature per node."""
+    th = np.array(theta, dtype=np.float64, copy=True)
+    th[3] = prob.d_ref
+    n_s = th.shape[1]
+    tj, lnw = tmarg_grid(prob, oversample)
+    nt = len(tj)
+    d_min = prob.d_min if d_min is None else d_min
+    d_max = prob.d_max if d_max is None else d_max
+    out = np.full(n_s, -np.inf)
+    for i in range(n_s):
+        big = np.repeat(th[:, i:i + 1], nt, axis=1)
+        big[2] = tj
+        L, T1, T2 = lnL(prob, big, threads=threads, return_terms=True)
+        fin = np.isfinite(L)
+        if not np.any(fin):
+            continue
+        t2 = float(T2[fin][0])
+        vals = np.array([ln_dist_marg(a, t2, d_ref=prob.d_ref, d_min=d_min, d_max=d_max) for a in T1[fin]])
+        m = np.max(vals)
+        out[i] = m + math.log(np.sum(np.exp(vals - m))) + lnw
     return out
 
 

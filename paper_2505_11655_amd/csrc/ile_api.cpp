@@ -69,12 +69,12 @@ hipError_t launch_eval(int set, int kdet, int policy, bool dm, size_t lds_bytes,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_tmarg(int set, int kdet, int policy, int R, size_t lds_bytes, const EvalJob *d_jobs,
+hipError_t launch_tmarg(int set, int kdet, int policy, int R, bool dm, size_t lds_bytes, const EvalJob *d_jobs,
                         const Tile *d_tiles, int n_tiles, int block, hipStream_t st) {
 #define ILE_TM(S)                                                                                             \
     if (set == S) {                                                                                           \
-        if (policy == 0) return launch_tmarg_sp<S, 0>(kdet, R, lds_bytes, d_jobs, d_tiles, n_tiles, block, st); \
-        if (policy == 1) return launch_tmarg_sp<S, 1>(kdet, R, lds_bytes, d_jobs, d_tiles, n_tiles, block, st); \
+        if (policy == 0) return launch_tmarg_sp<S, 0>(kdet, R, dm, lds_bytes, d_jobs, d_tiles, n_tiles, block, st); \
+        if (policy == 1) return launch_tmarg_sp<S, 1>(kdet, R, dm, lds_bytes, d_jobs, d_tiles, n_tiles, block, st); \
     }
     ILE_TM(0)
     ILE_TM(1)
@@ -841,13 +841,12 @@ namespace ile {
 // staged in LDS whenever it fits (each sample does hundreds of nodes of work).
 ile_status tmarg_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, int R, hipStream_t st) {
     if (R != 1 && R != 4) return set_err(ILE_E_INVALID, "oversample must be 1 or 4");
-    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
     for (size_t i = 0; i < items.size(); i++) {
         const ile_job *j = items[i].job;
         if (j->policy == kMixed) return set_err(ILE_E_INVALID, "time marginalisation supports FP32 and FP64 jobs");
-        if (j->dist_marg) return set_err(ILE_E_INVALID, "time marginalisation needs the distance column");
         if (items[i].n == 0) continue;
-        groups[std::make_tuple(j->set, j->kp, j->policy)].push_back((int)i);
+        groups[std::make_tuple(j->set, j->kp, j->policy, j->dist_marg ? 1 : 0)].push_back((int)i);
     }
     std::lock_guard<std::mutex> lk(ctx->batch_mu);
     for (auto &g : groups) {
@@ -887,7 +886,8 @@ ile_status tmarg_batch(ile_ctx *ctx, const std::vector<BatchItem> &items, int R,
         ile_status s = batch_upload(ctx, ej.data(), ej.size() * sizeof(EvalJob), tiles.data(),
                                     tiles.size() * sizeof(Tile), &dj, &dt, &slot, st);
         if (s != ILE_OK) return s;
-        hipError_t e = launch_tmarg(std::get<0>(g.first), std::get<1>(g.first), policy, R, lds ? win : 0,
+        hipError_t e = launch_tmarg(std::get<0>(g.first), std::get<1>(g.first), policy, R, std::get<3>(g.first) != 0,
+                                    lds ? win : 0,
                                     (const EvalJob *)dj, (const Tile *)dt, (int)tiles.size(), block, st);
         if (e != hipSuccess) return dev_fail(ctx, e, "time-marginalised eval launch");
         if ((s = batch_done(ctx, slot, st)) != ILE_OK) return s;

@@ -116,23 +116,23 @@ extern template hipError_t launch_ref_sp<2>(int, size_t, const EvalJob *, const 
 extern template hipError_t launch_ref_sp<3>(int, size_t, const EvalJob *, const Tile *, int, int, hipStream_t);
 
 template <int S, int POL>
-hipError_t launch_tmarg_sp(int kdet, int R, size_t lds_bytes, const EvalJob *jobs, const Tile *tiles, int n_tiles,
+hipError_t launch_tmarg_sp(int kdet, int R, bool dm, size_t lds_bytes, const EvalJob *jobs, const Tile *tiles, int n_tiles,
                            int nthreads, hipStream_t st);
-extern template hipError_t launch_tmarg_sp<0, 0>(int, int, size_t, const EvalJob *, const Tile *, int,
+extern template hipError_t launch_tmarg_sp<0, 0>(int, int, bool, size_t, const EvalJob *, const Tile *, int,
                                                      int, hipStream_t);
-extern template hipError_t launch_tmarg_sp<0, 1>(int, int, size_t, const EvalJob *, const Tile *, int,
+extern template hipError_t launch_tmarg_sp<0, 1>(int, int, bool, size_t, const EvalJob *, const Tile *, int,
                                                      int, hipStream_t);
-extern template hipError_t launch_tmarg_sp<1, 0>(int, int, size_t, const EvalJob *, const Tile *, int,
+extern template hipError_t launch_tmarg_sp<1, 0>(int, int, bool, size_t, const EvalJob *, const Tile *, int,
                                                      int, hipStream_t);
-extern template hipError_t launch_tmarg_sp<1, 1>(int, int, size_t, const EvalJob *, const Tile *, int,
+extern template hipError_t launch_tmarg_sp<1, 1>(int, int, bool, size_t, const EvalJob *, const Tile *, int,
                                                      int, hipStream_t);
-extern template hipError_t launch_tmarg_sp<2, 0>(int, int, size_t, const EvalJob *, const Tile *, int,
+extern template hipError_t launch_tmarg_sp<2, 0>(int, int, bool, size_t, const EvalJob *, const Tile *, int,
                                                      int, hipStream_t);
-extern template hipError_t launch_tmarg_sp<2, 1>(int, int, size_t, const EvalJob *, const Tile *, int,
+extern template hipError_t launch_tmarg_sp<2, 1>(int, int, bool, size_t, const EvalJob *, const Tile *, int,
                                                      int, hipStream_t);
-extern template hipError_t launch_tmarg_sp<3, 0>(int, int, size_t, const EvalJob *, const Tile *, int,
+extern template hipError_t launch_tmarg_sp<3, 0>(int, int, bool, size_t, const EvalJob *, const Tile *, int,
                                                      int, hipStream_t);
-extern template hipError_t launch_tmarg_sp<3, 1>(int, int, size_t, const EvalJob *, const Tile *, int,
+extern template hipError_t launch_tmarg_sp<3, 1>(int, int, bool, size_t, const EvalJob *, const Tile *, int,
                                                      int, hipStream_t);
 
 struct BatchItem {

@@ -206,7 +206,7 @@ __device__ __forceinline__ double u53(uint32_t w0, uint32_t w1) {
 // Distance-marginal table geometry: nodes u_i = u0 + i du (a = asinh(u)-grid
 // in T1/sqrt(T2)), b_j = b0 + j db (ln T2).
 struct DistTable {
-    const double *r;      // [nb][nu] residual ln L_D - E_max
+    const double *r;      // [nb][nu] residual ln L_D - a^2
     int nu, nb;
     double u0, du, b0, db;
     double s_min, s_max;  // d_ref/d_max, d_ref/d_min
@@ -216,7 +216,7 @@ struct DistTable {
 
 struct EvalJob {
     const void *Q;        // [Kp][T][NM] complex, policy contraction type (FP32 in the mixed policy)
-    const void *Ut;       // [P][Kp] complex, U-order, weighted; mixed policy: [Kp][P] float4 pair weights
+    const void *Ut;       // [P][Kp] complex, U-order, weighted; mixed policy: [Kp][NT] FP32 quadratic-form rows
     const void *Vt;       // [P][Kp] complex, V-order, weighted (unused by the mixed policy)
     // mixed policy: the reference terms (written on the device by k_ref_build)
     const float *ref_rg;  // r [Kp][NM] then G [Kp][NM], complex FP32

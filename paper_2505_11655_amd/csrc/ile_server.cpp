@@ -530,8 +530,8 @@ extern "C" ile_status ile_server_submit(ile_server *s, const ile_problem *Pin, c
     if (jo->tmarg_oversample != 0) {
         if (jo->tmarg_oversample != 1 && jo->tmarg_oversample != 4)
             return set_err(ILE_E_INVALID, "tmarg_oversample must be 0, 1 or 4");
-        if (jo->adaptive || P->prior.dist_marg || (P->precision != ILE_FP32 && P->precision != ILE_FP64))
-            return set_err(ILE_E_INVALID, "time-marginalised jobs are plain FP32/FP64 jobs without dist_marg");
+        if (jo->adaptive || (P->precision != ILE_FP32 && P->precision != ILE_FP64))
+            return set_err(ILE_E_INVALID, "time-marginalised jobs are plain FP32/FP64 jobs");
     }
     auto r = std::make_unique<Req>();
     const int K = P->n_det, n = P->n_modes, T = P->n_time;

@@ -156,6 +156,54 @@ __device__ __forceinline__ double dist_lookup(const TB &tb, TC T1, TC T2) {
     return in ? r + (double)a * (double)a : -INFINITY;
 }
 
+// The same table along one row of constant T2, for the time-marginalised
+// likelihood (a sample's T2 is the same at every time node): the b position
+// and weights are formed once, and each node costs the a-direction only.  All
+// in FP64.
+struct DistRow {
+    double inv_sqrt_T2;
+    double wb[4];
+    int ib;
+    bool ok;
+};
+template <class TB>
+__device__ __forceinline__ DistRow dist_row(const TB &tb, double T2) {
+    DistRow d;
+    d.ok = T2 > 0.0;
+    const double T2s = d.ok ? T2 : 1.0;
+    d.inv_sqrt_T2 = 1.0 / sqrt(T2s);
+    const double xb = (log(T2s) - tb.b0) * tb.inv_db;
+    double fb = floor(xb);
+    d.ok = d.ok && fb >= 1.0 && fb <= (double)(tb.nb - 3);
+    fb = d.ok ? fb : 1.0;
+    d.ib = (int)fb;
+    const double gb = xb - fb;
+    d.wb[0] = -gb * (gb - 1.0) * (gb - 2.0) / 6.0;
+    d.wb[1] = (gb + 1.0) * (gb - 1.0) * (gb - 2.0) * 0.5;
+    d.wb[2] = -(gb + 1.0) * gb * (gb - 2.0) * 0.5;
+    d.wb[3] = (gb + 1.0) * gb * (gb - 1.0) / 6.0;
+    return d;
+}
+template <class TB>
+__device__ __forceinline__ double dist_at(const TB &tb, const DistRow &d, double T1) {
+    const double a = T1 * d.inv_sqrt_T2;
+    const double xu = (asinh(a * tb.inv_a_scale) - tb.u0) * tb.inv_du;
+    double fu = floor(xu);
+    const bool in = d.ok && fu >= 1.0 && fu <= (double)(tb.nu - 3);
+    fu = in ? fu : 1.0;
+    const int iu = (int)fu;
+    const double gu = xu - fu;
+    const double wu[4] = {-gu * (gu - 1.0) * (gu - 2.0) / 6.0, (gu + 1.0) * (gu - 1.0) * (gu - 2.0) * 0.5,
+                          -(gu + 1.0) * gu * (gu - 2.0) * 0.5, (gu + 1.0) * gu * (gu - 1.0) / 6.0};
+    double r = 0.0;
+#pragma unroll
+    for (int jb = 0; jb < 4; jb++) {
+        const double *row = tb.r + (size_t)(d.ib - 1 + jb) * tb.nu + (iu - 1);
+        r += d.wb[jb] * (wu[0] * row[0] + wu[1] * row[1] + wu[2] * row[2] + wu[3] * row[3]);
+    }
+    return in ? r + a * a : -INFINITY;
+}
+
 template <int S, int K, int POL, bool LDS, bool DM>
 struct LnlKernel {
     using MS = MSet<S>;

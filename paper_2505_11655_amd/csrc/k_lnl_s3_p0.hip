@@ -5,6 +5,6 @@
 namespace ile {
 template hipError_t launch_eval_sp<3, 0>(int, bool, size_t, const EvalJob *, const Tile *, int,
                                            int, hipStream_t);
-template hipError_t launch_tmarg_sp<3, 0>(int, int, size_t, const EvalJob *, const Tile *, int,
+template hipError_t launch_tmarg_sp<3, 0>(int, int, bool, size_t, const EvalJob *, const Tile *, int,
                                              int, hipStream_t);
 }  // namespace ile

@@ -13,13 +13,18 @@
 // over nodes is a chunked log-sum-exp (one rescale per lattice step at most)
 // accumulated in FP64.  A node whose stencil leaves the window contributes
 // nothing (its pointwise lnL is -inf).
+// With the distance integrated (DM) every node's value is the table's
+// ln L_D(T1(t_j), T2) instead of s T1(t_j) - s^2 T2 / 4 (T1, T2 at s = 1):
+//   ln L_{t,D} = ln sum_j (dt / (R 2 t_w)) L_D(T1(t_j), T2),
+// the time and distance integrals taken together; the table row of T2 is
+// set up once per sample and each node interpolates along a only (FP64).
 #pragma once
 
 #include "k_lnl_impl.h"
 
 namespace ile {
 
-template <int S, int K, int POL, bool LDS, int R>
+template <int S, int K, int POL, bool LDS, int R, bool DM>
 struct TmargKernel {
     using LK = LnlKernel<S, K, POL, LDS, false>;
     using Tp = PolTypes<POL>;
@@ -32,7 +37,8 @@ struct TmargKernel {
     using ccpx = typename LK::ccpx;
     static constexpr int NM = LK::NM;
     static constexpr int NE = LK::NE;
-    static constexpr bool kT2First = sizeof(TA) == 8;
+    static constexpr bool kT2First = sizeof(TA) == 8 || DM;   // DM: the table row needs T2 first
+    using TV = std::conditional_t<DM, double, TA>;             // node values
     // With the window in LDS the G rows (a different row per lane) load the
     // LDS beyond its bandwidth; reading the first detector through L1/L2
     // instead balances the two paths (measured, 256 x 2^16 samples: HLV 9
@@ -87,6 +93,8 @@ struct TmargKernel {
             // SIMD, registers to spare): before it, like the pointwise kernel.
             TA T2 = (TA)0;
             if constexpr (kT2First) T2 = LK::template quad_T2<false>(Fr, Fi, y, Er, Ei, Ut, Vt);
+            DistRow drow{};
+            if constexpr (DM) drow = dist_row(J.dt, (double)T2);
 
             // c_k,a = conj(F_k) y_a e^{i m_a phi}: Re(c Q) = cr Q.re - cm Q.im
             TA cr[K][NM], cm[K][NM];
@@ -148,7 +156,7 @@ struct TmargKernel {
             for (int k = 0; k < K; k++)
 #pragma unroll
                 for (int t = 0; t < 5; t++) G[k][t] = (TA)0;
-            TA mx = (TA)-INFINITY;
+            TV mx = (TV)-INFINITY;
             double sum = 0.0;
 #pragma unroll 1
             for (int q = q_lo - 4; q <= q_hi; q++) {
@@ -190,8 +198,8 @@ struct TmargKernel {
                         G[k][4] = g;
                     }
                 }
-                TA x[R];
-                TA cmax = (TA)-INFINITY;
+                TV x[R];
+                TV cmax = (TV)-INFINITY;
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     const int j = R * q + r;
@@ -201,16 +209,27 @@ struct TmargKernel {
                     for (int k = 0; k < K; k++)
 #pragma unroll
                         for (int t = 0; t < 5; t++) t1 = fma(w5[k][r][t], G[k][t], t1);
-                    x[r] = valid ? s * t1 : (TA)-INFINITY;
+                    if constexpr (DM)
+                        x[r] = valid ? dist_at(J.dt, drow, (double)t1) : -INFINITY;
+                    else
+                        x[r] = valid ? s * t1 : (TA)-INFINITY;
                     cmax = fmax(cmax, x[r]);
                 }
                 if (cmax > mx) {
-                    sum = (mx > (TA)-INFINITY) ? sum * (double)expT(mx - cmax) : 0.0;
+                    if constexpr (DM)
+                        sum = (mx > -INFINITY) ? sum * exp(mx - cmax) : 0.0;
+                    else
+                        sum = (mx > (TA)-INFINITY) ? sum * (double)expT(mx - cmax) : 0.0;
                     mx = cmax;
                 }
-                TA part = (TA)0;
+                TV part = (TV)0;
 #pragma unroll
-                for (int r = 0; r < R; r++) part += (x[r] > (TA)-INFINITY) ? expT(x[r] - mx) : (TA)0;
+                for (int r = 0; r < R; r++) {
+                    if constexpr (DM)
+                        part += (x[r] > -INFINITY) ? exp(x[r] - mx) : 0.0;
+                    else
+                        part += (x[r] > (TA)-INFINITY) ? expT(x[r] - mx) : (TA)0;
+                }
                 sum += (double)part;
             }
             if constexpr (!kT2First) {
@@ -221,8 +240,12 @@ struct TmargKernel {
                 T2 = LK::template quad_T2<false>(Fr, Fi, y, Er, Ei, Ut, Vt);
             }
             double lnLt = -INFINITY;
-            if (ok && mx > (TA)-INFINITY)
-                lnLt = (double)mx + log(sum) - (double)(s * s * T2 * (TA)0.25) + J.tm_lnw;
+            if constexpr (DM) {
+                if (ok && mx > -INFINITY) lnLt = (double)mx + log(sum) + J.tm_lnw;
+            } else {
+                if (ok && mx > (TA)-INFINITY)
+                    lnLt = (double)mx + log(sum) - (double)(s * s * T2 * (TA)0.25) + J.tm_lnw;
+            }
             const TO outv = (TO)lnLt;
             if (outL) outL[i] = outv;
             if (outW) outW[i] = outv + (lr ? (TO)lr[i] : (TO)0);
@@ -230,32 +253,33 @@ struct TmargKernel {
     }
 };
 
-template <int S, int K, int POL, bool LDS, int R>
+template <int S, int K, int POL, bool LDS, int R, bool DM>
 __global__ void __launch_bounds__(tmarg_block_threads(POL), 1)
     k_lnl_tmarg(const EvalJob *__restrict__ jobs, const Tile *__restrict__ tiles) {
     extern __shared__ __align__(16) char ile_smem[];
     using TA = typename PolTypes<POL>::TA;
     const Tile tl = tiles[blockIdx.x];
-    TmargKernel<S, K, POL, LDS, R>::run(jobs[tl.job], tl.begin, tl.end, (cpx<TA> *)ile_smem);
+    TmargKernel<S, K, POL, LDS, R, DM>::run(jobs[tl.job], tl.begin, tl.end, (cpx<TA> *)ile_smem);
 }
 
 // Launch the time-marginalised kernel of mode set S and policy POL (FP32 or
-// FP64) for oversampling R in {1, 4}.
+// FP64) for oversampling R in {1, 4}, with the distance integrated (dm) or not.
 template <int S, int POL>
-hipError_t launch_tmarg_sp(int kdet, int R, size_t lds_bytes, const EvalJob *jobs, const Tile *tiles, int n_tiles,
-                           int nthreads, hipStream_t st) {
+hipError_t launch_tmarg_sp(int kdet, int R, bool dm, size_t lds_bytes, const EvalJob *jobs, const Tile *tiles,
+                           int n_tiles, int nthreads, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
     const bool lds = lds_bytes > 0;
     if (nthreads <= 0 || nthreads > tmarg_block_threads(POL) || nthreads % 64) return hipErrorInvalidValue;
     dim3 grid(n_tiles), block(nthreads);
-    auto go = [&](auto KK, auto LL, auto RR) -> hipError_t {
+    auto go2 = [&](auto KK, auto LL, auto RR, auto DD) -> hipError_t {
         constexpr int K = decltype(KK)::value;
         constexpr bool L = decltype(LL)::value;
         constexpr int RV = decltype(RR)::value;
+        constexpr bool DMV = decltype(DD)::value;
         if constexpr (L && !tmarg_lds_compiled(S, K, POL)) {
             return hipErrorInvalidValue;
         } else {
-            auto fn = k_lnl_tmarg<S, K, POL, L, RV>;
+            auto fn = k_lnl_tmarg<S, K, POL, L, RV, DMV>;
             if (L) {
                 hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                    (int)lds_bytes);
@@ -264,6 +288,9 @@ hipError_t launch_tmarg_sp(int kdet, int R, size_t lds_bytes, const EvalJob *job
             hipLaunchKernelGGL(fn, grid, block, L ? lds_bytes : 0, st, jobs, tiles);
             return hipGetLastError();
         }
+    };
+    auto go = [&](auto KK, auto LL, auto RR) -> hipError_t {
+        return dm ? go2(KK, LL, RR, std::true_type{}) : go2(KK, LL, RR, std::false_type{});
     };
     using T2 = std::integral_constant<int, 2>;
     using T3 = std::integral_constant<int, 3>;

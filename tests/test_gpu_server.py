@@ -160,9 +160,7 @@ def test_tmarg_job_rejects(pool):
     try:
         bad = [(ile.ProblemHost(p, precision=ile.ILE_FP32), ile.job_opts(n_samples=100, tmarg_oversample=2)),
                (ile.ProblemHost(p, precision=ile.ILE_FP32), ile.job_opts(adaptive=True, tmarg_oversample=4)),
-               (ile.ProblemHost(p, precision=ile.ILE_FP32_CANCEL64), ile.job_opts(n_samples=100, tmarg_oversample=4)),
-               (ile.ProblemHost(p, precision=ile.ILE_FP32, dist_marg=True),
-                ile.job_opts(n_samples=100, tmarg_oversample=4))]
+               (ile.ProblemHost(p, precision=ile.ILE_FP32_CANCEL64), ile.job_opts(n_samples=100, tmarg_oversample=4))]
         for ph, jo in bad:
             with pytest.raises(ile.IleError) as e:
                 ile.ile_server_submit(srv, ph, jo)

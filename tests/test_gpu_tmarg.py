@@ -144,10 +144,42 @@ def test_tmarg_rejects():
             ile.ile_eval_lnL_tmarg(job, 10, th, 10, None, out, oversample=2)
     finally:
         ile.ile_job_release(job)
-    for kw in ({"precision": ile.ILE_FP32_CANCEL64}, {"precision": ile.ILE_FP32, "dist_marg": True}):
+    for kw in ({"precision": ile.ILE_FP32_CANCEL64},):
         job = ile.ile_prepare(gu.ctx(), ile.ProblemHost(p, **kw))
         try:
             with pytest.raises(ile.IleError):
                 ile.ile_eval_lnL_tmarg(job, 10, th, 10, None, out, oversample=4)
         finally:
             ile.ile_job_release(job)
+
+
+@pytest.mark.parametrize("R,n_prior,n_peak", [(1, 8, 8), (4, 0, 4)])
+@pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32], ids=["fp64", "fp32"])
+def test_tmarg_with_distance_matches_oracle(orc, recs, policy, R, n_prior, n_peak):
+    """Time and distance integrated together (a dist_marg job): every node's
+    value is the distance table's ln L_D(T1(t_j), T2); the oracle takes the
+    distance integral at every node by adaptive quadrature.  HL 5 modes,
+    SNR 20; prior samples and samples near the peak (the D column ignored).
+    FP64 agrees to the table's accuracy near the peak, FP32 to the FP32
+    policy's per-sample bound."""
+    probs, _ = chirpgen.build_event(recs["c1"], ["H", "L"], 5, 30.0, 2.0, 20.0, noise_seed=11)
+    p = probs[0]
+    th0 = np.array(recs["c1"]["theta"])
+    rng = np.random.default_rng(72)
+    w = np.array([0.03, 0.03, 0.0, 0.0, 0.05, 0.1, 0.1])
+    th = _samples(rng, th0, n_prior, n_peak, policy, w)
+    th[3] = p.d_ref
+    job = ile.ile_prepare(gu.ctx(), ile.ProblemHost(p, precision=policy, dist_marg=True))
+    try:
+        L, _ = _gpu_tmarg(job, th, policy, R)
+    finally:
+        ile.ile_job_release(job)
+    ref = orc.lnL_tmarg_dist(p, th.astype(np.float64), oversample=R)
+    assert np.array_equal(np.isfinite(L), np.isfinite(ref))
+    fin = np.isfinite(ref)
+    d = np.abs(L[fin] - ref[fin])
+    print(f"tmarg+dist {PNAME[policy]} R={R}: max lnL={np.max(ref):.2f} max|d|={d.max():.2e}")
+    if policy == ile.ILE_FP64:
+        assert np.all(d <= 1e-5 * (1 + np.abs(ref[fin])))
+    else:
+        assert np.all(d <= 1e-3 + 1e-6 * np.abs(ref[fin]))

@@ -813,6 +813,29 @@ def test_PT1_single_node(orc):
     assert np.allclose(orc.lnL_tmarg(p, th, oversample=4), want, rtol=1e-13, atol=1e-11)
 
 
+def test_PTD2_time_and_distance_closed_forms(orc):
+    """Q constant in time: every node has the same T1, so the time- and
+    distance-marginalised value is ln L_D(T1, T2) + ln(N_t dt / (R 2 t_w)).
+    A distance prior squeezed onto [D0, D0 (1 + 1e-7)] turns it into the
+    time-marginalised likelihood at D = D0."""
+    rng = np.random.default_rng(62)
+    p = chirpgen.random_problem(rng, 5, ["H", "L"])
+    pc = chirpgen.random_problem(rng, 5, ["H", "L"])
+    pc.Q = np.repeat(pc.Q[:, :, 205:206], pc.Q.shape[2], axis=2)
+    th = chirpgen.prior_samples(rng, 4)
+    t0 = th.copy()
+    t0[2], t0[3] = 0.0, pc.d_ref
+    _, T1, T2 = orc.lnL(pc, t0, return_terms=True)
+    nt = 2 * int(math.floor(pc.t_window / pc.dt + 1e-9)) + 1
+    want = np.array([orc.ln_dist_marg(a, b) for a, b in zip(T1, T2)]) + math.log(nt * pc.dt / (2 * pc.t_window))
+    assert np.allclose(orc.lnL_tmarg_dist(pc, th, oversample=1), want, rtol=1e-10, atol=1e-8)
+    D0 = 400.0
+    thd = th.copy()
+    thd[3] = D0
+    narrow = orc.lnL_tmarg_dist(p, th[:, :2], oversample=1, d_min=D0, d_max=D0 * (1 + 1e-7))
+    assert np.allclose(narrow, orc.lnL_tmarg(p, thd[:, :2], oversample=1), rtol=1e-9, atol=1e-6)
+
+
 def test_PT2_node_sum_converges_to_quadrature(orc, recs):
     """Near the likelihood peak of an SNR-20 event (width in t ~80 us) the
     node sum converges to the time integral of the same interpolated
