@@ -42,7 +42,7 @@ LNL_BYTES = {"fp32": 40, "fp64": 80}
 # the kernel executes (64 lanes x (add + mul + 2 fma + trans) per wave
 # instruction): 2,437 FP32 + 108 FP64 (sky direction and delays).
 LNL_TRAFFIC = {"fetch_B_per_sample": 32.720, "write_B_per_sample": 8.000, "executed_flop_per_sample": 2545.0,
-               "src_sha256": "15e38f3b212da11500fae58b72ce59917912917478312ddfb39fd2a26d5e708d"}
+               "src_sha256": "49ca0381430112c6fa838f49740150430a22f9c69e09be241f2642f5c0f3af6a"}
 # algorithmic HBM bytes per sample of the draw (7 theta + ln p - ln p_s
 # written) and estimator (lw read) kernels
 DRAW_BYTES = {"fp32": 32, "fp64": 64}
