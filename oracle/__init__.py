@@ -382,16 +382,22 @@ def shear_theta(theta, shear):
     return th
 
 
+PHASE_SHEAR_MIN_COS = 0.5
+
+
 def phase_shear_sign(theta, lw):
-    """Sign of the shear for a first fit: +1 if the highest-weight sample
-    (lowest index among ties) is face-on (cos iota >= 0), else -1; 0 if no
-    weight is finite."""
+    """Shear of a first fit, from the highest-weight sample (lowest index
+    among ties): +1 if its cos iota >= 0.5 (face-on: the m = +2 end of each
+    multiplet dominates, ((1 + cos i)/(1 - cos i))^2 >= 9, and the likelihood
+    ridge runs along psi + phi_c = const), -1 if cos iota <= -0.5 (face-off),
+    0 otherwise (no single ridge) or if no weight is finite."""
     lw = np.asarray(lw, dtype=np.float64)
     if not np.any(np.isfinite(lw)):
         return 0
     key = np.where(np.isfinite(lw), lw, -np.inf)
     i = int(np.argsort(-key, kind="stable")[0])
-    return 1 if float(np.asarray(theta)[4][i]) >= 0.0 else -1
+    c = float(np.asarray(theta)[4][i])
+    return 1 if c >= PHASE_SHEAR_MIN_COS else (-1 if c <= -PHASE_SHEAR_MIN_COS else 0)
 
 
 def pool_mixture_lw(prior, proposals, thetas, lnLs):

@@ -344,10 +344,15 @@ __global__ void k_em_top_final(const EmJob *__restrict__ jobs) {
     g->valid = 1;
     const TT *th = (const TT *)J.theta;
     const int d = J.n_dim, nc = J.n_comp;
-    // phase shear: its sign from the inclination of the best sample (face-on
-    // ridge along psi + phi_c, face-off along psi - phi_c)
+    // phase shear from the inclination of the best sample: face-on
+    // (cos iota >= 1/2, where the m = +2 end of each multiplet dominates) the
+    // ridge runs along psi + phi_c, face-off along psi - phi_c; in between
+    // there is no single ridge and the phases stay as they are
     g->shear = 0;
-    if (J.shear_auto && cur[0].v > -INFINITY) g->shear = load_col(th, J.ld, 4, cur[0].i) >= 0.0 ? 1 : -1;
+    if (J.shear_auto && cur[0].v > -INFINITY) {
+        const double ci = load_col(th, J.ld, 4, cur[0].i);
+        g->shear = ci >= 0.5 ? 1 : (ci <= -0.5 ? -1 : 0);
+    }
     // candidates: the 2 n_comp highest-weight samples (kTopK = 2 kMaxComp
     // holds them for every n_comp), scanned in that order
     const int ncand = 2 * nc < kTopK ? 2 * nc : kTopK;

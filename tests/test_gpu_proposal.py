@@ -116,14 +116,16 @@ def test_sheared_proposal_draws(orc, policy, shear):
     assert abs(r.mean() - 1) < 4 * r.std() / math.sqrt(n) + 2e-3
 
 
-@pytest.mark.parametrize("face", [1, -1])
+@pytest.mark.parametrize("face", [1, -1, 0])
 @pytest.mark.parametrize("policy", [ile.ILE_FP64, ile.ILE_FP32])
 def test_em_sheared_matches_oracle(orc, policy, face):
-    """Refit with phase_shear: the first fit takes the shear sign from the best
-    sample's inclination (face = the sign forced on every cos iota), fits in
-    the sheared phases, and a warm refit keeps it; device and oracle agree."""
+    """Refit with phase_shear: the first fit takes the shear from the best
+    sample's inclination (face = +-1: every cos iota forced into +-[1/2, 1];
+    0: into (-1/2, 1/2), no shear), fits in the sheared phases, and a warm
+    refit keeps it; device and oracle agree."""
     th, lw = _weighted_samples(1 << 16, 45, policy)
-    th[4] = (face * np.abs(th[4].astype(np.float64))).astype(th.dtype)
+    c = np.abs(th[4].astype(np.float64))
+    th[4] = (face * (0.5 + 0.5 * c) if face else 0.49 * (2 * c - 1)).astype(th.dtype)
     lw = (lw * 40).astype(lw.dtype)
     job, _ = _job(policy)
     try:

@@ -716,12 +716,15 @@ def test_PS1_sheared_mixture_is_a_density_of_its_draws(orc, shear):
 
 
 def test_PS2_shear_sign_and_round_trip(orc):
-    """The shear sign follows the inclination of the best sample; shearing
-    by s then by -s returns every phase pair (mod its period)."""
+    """The shear follows the inclination of the best sample (none between
+    cos iota = -1/2 and 1/2); shearing by s then by -s returns every phase
+    pair (mod its period)."""
     th = np.zeros((7, 4))
     th[4] = [0.9, -0.2, 0.3, -0.8]
-    assert orc.phase_shear_sign(th, [1.0, 5.0, 2.0, -np.inf]) == -1
+    assert orc.phase_shear_sign(th, [1.0, 5.0, 2.0, -np.inf]) == 0     # |cos iota| < 1/2: no shear
     assert orc.phase_shear_sign(th, [7.0, 5.0, 2.0, np.nan]) == 1
+    assert orc.phase_shear_sign(th, [1.0, 5.0, 2.0, 6.0]) == -1
+    assert orc.phase_shear_sign(th, [-np.inf] * 4) == 0
     rng = np.random.default_rng(3)
     t = np.zeros((7, 1000))
     t[5] = rng.uniform(0, 2 * math.pi, 1000)
