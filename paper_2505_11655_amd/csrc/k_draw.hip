@@ -116,13 +116,18 @@ __device__ __forceinline__ double ln_prior_col(const PriorDev &pr, int c, const 
 
 typedef __attribute__((address_space(4))) const GmmDev cgmm;
 
+// Running log-sum-exp: m the running maximum, s the sum of e^{t - m}.
+// FAST: the exponential of the (FP64) difference taken in FP32, for sums
+// whose terms need only FP32 relative accuracy.
+template <bool FAST = false>
 __device__ __forceinline__ void lse_add(double &m, double &s, double t) {
     if (!(t > -INFINITY)) return;
+    auto ex = [](double x) { return FAST ? (double)__expf((float)x) : exp(x); };
     if (t > m) {
-        s = s * exp(m - t) + 1.0;
+        s = s * ex(m - t) + 1.0;
         m = t;
     } else {
-        s += exp(t - m);
+        s += ex(t - m);
     }
 }
 
@@ -165,7 +170,7 @@ __device__ __forceinline__ void mix_coords(const MixCols &mc, const PriorDev &pr
 // (the component loop is uniform) and applied row by row to every sample; a
 // periodic offset is wrapped as u - P rint(u / P) (the floor form's value
 // except at exactly half a period, where both images are equally far).
-template <int NS>
+template <int NS, bool FAST = false>
 __device__ __forceinline__ void mix_log_ratio(cgmm &g, const MixCols &mc, const double (&xm)[NS][7],
                                               const double (&lpm)[NS], double (&t)[NS]) {
     const int d = mc.d;
@@ -209,7 +214,7 @@ __device__ __forceinline__ void mix_log_ratio(cgmm &g, const MixCols &mc, const 
             for (int k = 0; k < NS; k++) qf[k] = fma(y[k], y[k], qf[k]);
         }
 #pragma unroll
-        for (int k = 0; k < NS; k++) lse_add(mm[k], ss[k], cj - 0.5 * qf[k] - lpm[k]);
+        for (int k = 0; k < NS; k++) lse_add<FAST>(mm[k], ss[k], cj - 0.5 * qf[k] - lpm[k]);
     }
 #pragma unroll
     for (int k = 0; k < NS; k++) t[k] = mm[k] > -INFINITY ? mm[k] + log(ss[k]) : -INFINITY;
@@ -392,10 +397,12 @@ __global__ void __launch_bounds__(kDrawThreads)
     const int qlo = end > first_new ? 1 : r;
     for (int q = qlo; q <= r; q++) {
         double t[kPoolSpt];
-        mix_log_ratio<kPoolSpt>(hist[q], mc, xm, lpm, t);
+        // the FP32 policy's pooled weights need FP32 relative accuracy only
+        constexpr bool kFast = sizeof(TO) == 4;
+        mix_log_ratio<kPoolSpt, kFast>(hist[q], mc, xm, lpm, t);
 #pragma unroll
         for (int k = 0; k < kPoolSpt; k++)
-            if (q >= q0[k]) lse_add(m[k], sum[k], t[k]);
+            if (q >= q0[k]) lse_add<kFast>(m[k], sum[k], t[k]);
     }
 #pragma unroll
     for (int k = 0; k < kPoolSpt; k++) {
