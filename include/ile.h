@@ -402,12 +402,29 @@ ile_status ile_ac_get(ile_job *job, int32_t *n_dim, int32_t *dims, double *pi, i
  * with the phase taken exactly as 2 pi ((m' (i - win_half)) mod n)/n.  U is
  * formed for a <= b and mirrored (U_ba = conj U_ab, V_ba = V_ab).  The Q and
  * U, V layouts are those ile_problem takes, one block per point.  At most
- * 1000 modes (ILE_E_INVALID beyond). */
+ * 1000 modes (ILE_E_INVALID beyond).
+ * Routes for Q (the same sums, rounded in a different order):
+ *   ILE_QV_DIRECT: the window times x band bins product as written;
+ *   ILE_QV_DECIMATED: the grid split once, n = R N2 (the first step of a
+ *     decimation-in-frequency FFT, as Section "Reduce duplication of inner
+ *     products" prefers FFTs to time-domain sums): radix-R partial sums over
+ *     the R aliases m2 + N2 a of each bin, then the product over N2 bins at
+ *     the decimated times floor((i - win_half) / R) only.  R is the smallest
+ *     of 2, 4, 8, 16 that divides n and puts the window on at most 64
+ *     decimated times; ILE_E_INVALID when there is none;
+ *   ILE_QV_AUTO: the decimated route when it applies and its estimated cost
+ *     is lower, else the direct one.
+ * The band lists are staged in pinned memory, so the call does not wait on
+ * the stream before its final synchronisation. */
+#define ILE_QV_AUTO 0
+#define ILE_QV_DIRECT 1
+#define ILE_QV_DECIMATED 2
 typedef struct {
     int32_t n_points, n_modes, n_det;
     int64_t n_freq;           /* grid length n */
     double df, f_lo, f_hi;
     int32_t n_time, win_half; /* Q window */
+    int32_t route;            /* how Q is summed; ILE_QV_AUTO (0) picks the faster */
 } ile_qv_shape;
 /* hlm: device [n_points][n_modes][n_freq] complex128; data: device
  * [n_det][n_freq] complex128; inv_psd: device [n_det][n_freq] 1/S_k(|f|) or

@@ -88,13 +88,14 @@ class ile_job_opts(C.Structure):
 
 ILE_INT_GMM, ILE_INT_AV, ILE_INT_AC = 0, 1, 2
 ILE_POOL_ROUNDS, ILE_POOL_MIXTURE = 0, 1
+ILE_QV_AUTO, ILE_QV_DIRECT, ILE_QV_DECIMATED = 0, 1, 2
 AC_BINS = 64
 
 
 class ile_qv_shape(C.Structure):
     _fields_ = [("n_points", C.c_int32), ("n_modes", C.c_int32), ("n_det", C.c_int32), ("n_freq", C.c_int64),
                 ("df", C.c_double), ("f_lo", C.c_double), ("f_hi", C.c_double), ("n_time", C.c_int32),
-                ("win_half", C.c_int32)]
+                ("win_half", C.c_int32), ("route", C.c_int32)]
 
 
 class ile_av_opts(C.Structure):
@@ -454,10 +455,12 @@ def ile_ac_get(job, stream=None):
     return [dims[k] for k in range(nd.value)], pi[:nd.value]
 
 
-def ile_overlaps(ctx, hlm, data, df, f_lo, f_hi, n_time, win_half, Q, U, V, inv_psd=None, stream=None):
-    """hlm: device [n_points][n_modes][n] complex128 (a 2-D [n_modes][n] array is one point)."""
+def ile_overlaps(ctx, hlm, data, df, f_lo, f_hi, n_time, win_half, Q, U, V, inv_psd=None, stream=None,
+                 route=0):
+    """hlm: device [n_points][n_modes][n] complex128 (a 2-D [n_modes][n] array is one point);
+    route: ILE_QV_AUTO, ILE_QV_DIRECT or ILE_QV_DECIMATED."""
     n_points, n_modes, n = (1,) + tuple(hlm.shape) if hlm.dim() == 2 else tuple(hlm.shape)
-    sh = ile_qv_shape(n_points, n_modes, data.shape[0], n, df, f_lo, f_hi, n_time, win_half)
+    sh = ile_qv_shape(n_points, n_modes, data.shape[0], n, df, f_lo, f_hi, n_time, win_half, route)
     _chk(lib().ile_overlaps(ctx, C.byref(sh), _p(hlm), _p(data), _p(inv_psd), _p(Q), _p(U), _p(V), _s(stream)))
 
 

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "ile_ctx.h"
+#include "k_qv.h"
 
 using namespace ile;
 
@@ -151,6 +152,7 @@ extern "C" ile_status ile_overlaps(ile_ctx *ctx, const ile_qv_shape *sh, const v
         sh->n_time > sh->n_freq || sh->n_modes > 1000 || !(sh->df > 0) || !(sh->f_hi >= sh->f_lo) || sh->f_lo < 0)
         return set_err(ILE_E_INVALID, "bad overlap shape");
     if (!hlm || !data || !Q || !U || !V) return set_err(ILE_E_INVALID, "null array");
+    if (sh->route < ILE_QV_AUTO || sh->route > ILE_QV_DECIMATED) return set_err(ILE_E_INVALID, "bad overlap route");
     const int64_t n = sh->n_freq;
     std::vector<int64_t> band, msig;
     for (int64_t m = 0; m < n; m++) {
@@ -162,16 +164,45 @@ extern "C" ile_status ile_overlaps(ile_ctx *ctx, const ile_qv_shape *sh, const v
         }
     }
     if (band.empty()) return set_err(ILE_E_INVALID, "no grid frequency inside the band");
+    const int64_t n_band = (int64_t)band.size();
     const int64_t cols = (int64_t)sh->n_points * sh->n_det * sh->n_modes;
-    const int ns = qv_slices((int64_t)band.size(), cols, sh->n_time);
-    const size_t need = qv_scratch_bytes(n, (int64_t)band.size(), cols, sh->n_time, ns);
+    int radix = 0;
+    if (sh->route != ILE_QV_DIRECT) {
+        radix = qv_radix(n, n_band, sh->n_time, sh->win_half, sh->route == ILE_QV_DECIMATED);
+        if (radix == 0 && sh->route == ILE_QV_DECIMATED)
+            return set_err(ILE_E_INVALID, "decimated route needs a radix in {2, 4, 8, 16} dividing n_freq that "
+                                          "puts the window on at most 64 decimated times");
+    }
+    const int ns = radix ? qv_dec_slices(n, cols, sh->n_time, sh->win_half, radix)
+                         : qv_slices(n_band, cols, sh->n_time);
+    const size_t need = radix ? qv_dec_scratch_bytes(n, n_band, cols, sh->n_time, sh->win_half, radix, ns)
+                              : qv_scratch_bytes(n, n_band, cols, sh->n_time, ns);
+    // the band lists go through pinned staging, so that nothing in the call
+    // waits for the stream before the final synchronisation
+    const size_t stage_bytes = (size_t)n_band * (radix ? 8 : 16);
+    char *stage = (char *)pin_alloc(ctx, stage_bytes);
+    if (!stage) return set_err(ILE_E_NOMEM, "pinned staging");
     void *scratch = nullptr;
-    if ((s = ctx_alloc(ctx, &scratch, need, "overlap scratch")) != ILE_OK) return s;
+    if ((s = ctx_alloc(ctx, &scratch, need, "overlap scratch")) != ILE_OK) {
+        pin_free(ctx, stage, stage_bytes);
+        return s;
+    }
+    std::memcpy(stage, band.data(), (size_t)n_band * 8);
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = launch_qv(hlm, data, inv_psd, n, sh->n_modes, sh->n_det, sh->n_points, sh->df, band.data(),
-                             msig.data(), (int64_t)band.size(), sh->n_time, sh->win_half, Q, U, V, scratch, ns, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the band lists and the scratch are released below
+    hipError_t e;
+    if (radix) {
+        e = launch_qv_dec(hlm, data, inv_psd, n, sh->n_modes, sh->n_det, sh->n_points, sh->df, sh->f_lo, sh->f_hi,
+                          (const int64_t *)stage, n_band, sh->n_time, sh->win_half, radix, Q, U, V, scratch, ns, st);
+    } else {
+        std::memcpy(stage + (size_t)n_band * 8, msig.data(), (size_t)n_band * 8);
+        e = launch_qv(hlm, data, inv_psd, n, sh->n_modes, sh->n_det, sh->n_points, sh->df, (const int64_t *)stage,
+                      (const int64_t *)(stage + (size_t)n_band * 8), n_band, sh->n_time, sh->win_half, Q, U, V,
+                      scratch, ns, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the staging and the scratch are released below
+    else (void)hipStreamSynchronize(st);
     ctx_free(ctx, scratch, need);
+    pin_free(ctx, stage, stage_bytes);
     if (e != hipSuccess) return dev_fail(ctx, e, "overlaps");
     return ILE_OK;
 }

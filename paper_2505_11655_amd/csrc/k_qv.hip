@@ -16,7 +16,20 @@
 // kernel (deterministic).  U and V use the symmetries U_ba = conj(U_ab),
 // V_ba = V_ab: only a <= b is summed (one block per pair, fixed-order tree
 // reduction).
+// The decimated route splits the DFT behind Q once (the first step of a
+// decimation-in-frequency FFT, Section "Reduce duplication of inner products"
+// weighs FFTs against the direct sum): with n = R N2, m = m2 + N2 a (m the
+// unsigned grid index, 0 <= m2 < N2, 0 <= a < R) and j = i - win_half =
+// R p + q (0 <= q < R),
+//   e^{2 pi i m j / n} = e^{2 pi i m2 p / N2} e^{2 pi i m2 q / n} e^{2 pi i a q / R},
+// so Q(j) = sum_m2 e^{2 pi i m2 p / N2} Y_q(m2) with the radix-R partial sums
+// Y_q(m2) = e^{2 pi i m2 q / n} sum_a X(m2 + N2 a) (X zero off the band).
+// Y is formed by a streaming kernel, and the remaining sum is the direct
+// route's matrix-core product over N2 bins, R columns per column and only
+// the decimated times p of the window (at most 64: one time tile).  Every
+// factor is a table value at an exact integer index.
 #include "ile_internal.h"
+#include "k_qv.h"
 
 namespace ile {
 
@@ -110,13 +123,13 @@ __global__ void __launch_bounds__(kQvThreads)
     // this thread's share of a phase stage: bin gb, times gt .. gt + 7
     const int gb = threadIdx.x >> 3, gt = (threadIdx.x & 7) * 8;
     static_assert(kQvThreads * 8 == kQvKB * kQvTT, "eight phases per thread and stage");
-    // m' of the thread's bin in the stage at bb; a bin past the slice gets
-    // m' = 0 and a zero phase (its X, read at a clamped index, is then
-    // multiplied by 0)
+    // m' of the thread's bin in the stage at bb (the bin itself when msig is
+    // null); a bin past the slice gets m' = 0 and a zero phase (its X, read
+    // at a clamped index, is then multiplied by 0)
     auto bin_m = [&](int64_t bb, double &f) -> int64_t {
         const int64_t b = bb + gb;
         f = b < b_hi ? 1.0 : 0.0;
-        return b < b_hi ? msig[b] : 0;
+        return b < b_hi ? (msig ? msig[b] : b) : 0;
     };
     // The thread's eight phases for bin m', r = m' (t - win_half) mod n,
     // then r += m' mod n per time (r stays in [0, n)).  Rows past the window
@@ -229,6 +242,103 @@ __global__ void k_qv_reduce(const double2 *__restrict__ part, int n_slices, int6
         double re = 0.0, im = 0.0;
         for (int s = 0; s < n_slices; s++) {
             const double2 v = part[(int64_t)s * total + e];
+            re += v.x;
+            im += v.y;
+        }
+        Q[e] = make_double2(re, im);
+    }
+}
+
+// Stage one of the decimated route: Y[m2][col R + q] for every column and
+// m2 in [0, N2), from the R aliases m2 + N2 a (X = 2 df conj(h) d w on the
+// band's bins, 0 elsewhere).  A block covers kDecM consecutive m2 (the lanes
+// of a wave, so that every read of a mode row, the data and the weight is
+// one contiguous run) by kDecC columns (one per wave).  The R outputs of
+// each (m2, column) go to LDS, and the tile's rows, kDecC R contiguous
+// elements each, are written out from there in contiguous runs.
+constexpr int kDecM = 64;
+constexpr int kDecC = kQvThreads / 64;
+template <int R>
+__global__ void __launch_bounds__(kQvThreads)
+    k_qv_dec1(const double2 *__restrict__ hlm, const double2 *__restrict__ data, const double *__restrict__ inv_psd,
+              const double2 *__restrict__ tw, int64_t n, int na, int nd, int np, double df, double f_lo, double f_hi,
+              int64_t n_mt, double2 *__restrict__ Y) {
+    constexpr int RW = kDecC * R + 1;   // LDS row (one element of padding)
+    __shared__ double2 sY[kDecM * RW];
+    const int64_t cols = (int64_t)np * nd * na;
+    const int64_t n2 = n / R;
+    const int64_t mt = (int64_t)blockIdx.x % n_mt, ct = (int64_t)blockIdx.x / n_mt;
+    const int64_t m2_0 = mt * kDecM, col0 = ct * kDecC;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t m2 = m2_0 + lane, col = col0 + wv;
+    if (m2 < n2 && col < cols) {
+        const int a = (int)(col % na);
+        const int k = (int)((col / na) % nd);
+        const int64_t p = col / ((int64_t)na * nd);
+        const double2 *h = hlm + (p * na + a) * n;
+        const double2 *dk = data + (int64_t)k * n;
+        const double *wk = inv_psd ? inv_psd + (int64_t)k * n : nullptr;
+        // every alias's reads are issued before any is used; the band test is
+        // the host's (|m' df| in [f_lo, f_hi], m' the signed index), and a
+        // mode value off the band is not read
+        double2 hv[R], dv[R];
+        double wv8[R];
+        bool inb[R];
+#pragma unroll
+        for (int al = 0; al < R; al++) {
+            const int64_t m = m2 + n2 * al;
+            const int64_t ms = m < (n + 1) / 2 ? m : m - n;
+            const double af = fabs((double)ms * df);
+            inb[al] = af >= f_lo && af <= f_hi;
+            hv[al] = make_double2(0.0, 0.0);
+            if (inb[al]) hv[al] = h[m];
+            dv[al] = dk[m];
+            wv8[al] = wk ? wk[m] : 1.0;
+        }
+        double2 x[R];
+#pragma unroll
+        for (int al = 0; al < R; al++) {
+            const double w = inb[al] ? 2.0 * df * wv8[al] : 0.0;
+            const double2 hh = hv[al], d = dv[al];
+            x[al] = make_double2((hh.x * d.x + hh.y * d.y) * w, (hh.x * d.y - hh.y * d.x) * w);
+        }
+#pragma unroll
+        for (int q = 0; q < R; q++) {
+            double re = 0.0, im = 0.0;
+#pragma unroll
+            for (int al = 0; al < R; al++) {
+                const double2 e = tw[(int64_t)((al * q) % R) * n2];   // e^{2 pi i a q / R}
+                re += x[al].x * e.x - x[al].y * e.y;
+                im += x[al].x * e.y + x[al].y * e.x;
+            }
+            const double2 t = tw[m2 * q];   // m2 q < n
+            sY[lane * RW + wv * R + q] = make_double2(re * t.x - im * t.y, re * t.y + im * t.x);
+        }
+    }
+    __syncthreads();
+    const int64_t nc = cols - col0 < kDecC ? (cols - col0) * R : (int64_t)kDecC * R;
+    for (int e = threadIdx.x; e < kDecM * kDecC * R; e += kQvThreads) {
+        const int row = e / (kDecC * R), c = e % (kDecC * R);
+        if (m2_0 + row < n2 && c < nc) Y[(m2_0 + row) * cols * R + col0 * R + c] = sY[row * RW + c];
+    }
+}
+
+// Q[col][i] of the decimated route: the slice partials of decimated column
+// col R + q at decimated time p - p_lo, j = i - win_half = R p + q, summed
+// in slice order.
+__global__ void k_qv_dec_reduce(const double2 *__restrict__ part, int n_slices, int64_t cols, int radix, int n_t2,
+                                int n_time, int win_half, int p_lo, double2 *__restrict__ Q) {
+    const int64_t total = cols * n_time;
+    const int64_t stride = cols * radix * n_t2;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t col = e / n_time;
+        const int j = (int)(e % n_time) - win_half;
+        const int pd = j >= 0 ? j / radix : -((-j + radix - 1) / radix);
+        const int q = j - pd * radix;
+        const int64_t src = (col * radix + q) * n_t2 + (pd - p_lo);
+        double re = 0.0, im = 0.0;
+        for (int s = 0; s < n_slices; s++) {
+            const double2 v = part[(int64_t)s * stride + src];
             re += v.x;
             im += v.y;
         }
@@ -369,6 +479,32 @@ __global__ void k_qv_uv_sum(const double *__restrict__ partial, int64_t n_pk, in
     }
 }
 
+// U and V (k_qv_uv, then k_qv_uv_sum over its band slices): band slices so
+// that the grid has about 1024 blocks, the slice partials held in `part`
+// (part_bytes long; free once Q has been reduced from it).
+void launch_uv(const void *hlm, const double *inv_psd, const int64_t *band, int64_t n_band, int64_t n, int na,
+               int nd, int np, double df, double *part, int64_t part_bytes, void *U, void *V, hipStream_t st) {
+    const int npair = na * (na + 1) / 2;
+    const int n_dg = (nd + kUvDet - 1) / kUvDet;
+    const int n_pg = (npair + kQvThreads - 1) / kQvThreads;
+    const int cb = (int)std::max<int64_t>(1, std::min<int64_t>(kUvChunk, 32768 / ((int64_t)na * 32 + kUvDet * 8)));
+    const int64_t blocks1 = (int64_t)np * n_dg * n_pg;
+    int64_t n_sl = std::max<int64_t>(1, std::min<int64_t>((1024 + blocks1 - 1) / blocks1, (n_band + 4 * cb - 1) / (4 * cb)));
+    const int64_t per_sl = (int64_t)np * nd * npair * 32;
+    n_sl = std::min<int64_t>(n_sl, std::max<int64_t>(1, part_bytes / per_sl));
+    const int64_t uslice = (n_band + n_sl - 1) / n_sl;
+    n_sl = (n_band + uslice - 1) / uslice;
+    const size_t lds = std::max<size_t>((size_t)cb * ((size_t)na * 32 + kUvDet * 8), (size_t)kQvThreads * kUvDet * 4 * 8);
+    hipLaunchKernelGGL(k_qv_uv, dim3((unsigned)np, (unsigned)n_sl, (unsigned)(n_dg * n_pg)), dim3(kQvThreads), lds, st,
+                       (const double2 *)hlm, inv_psd, band, n_band, n, na, nd, df, uslice, (int)n_sl, cb, n_dg,
+                       part, (double2 *)U, (double2 *)V);
+    if (n_sl > 1) {
+        const int64_t ue = (int64_t)np * nd * npair;
+        hipLaunchKernelGGL(k_qv_uv_sum, dim3((unsigned)std::min<int64_t>((ue + 255) / 256, 65536)), dim3(256), 0, st,
+                           part, (int64_t)np * nd, na, (int)n_sl, df, (double2 *)U, (double2 *)V);
+    }
+}
+
 }  // namespace
 
 size_t qv_scratch_bytes(int64_t n, int64_t n_band, int64_t cols, int n_time, int n_slices) {
@@ -432,28 +568,114 @@ hipError_t launch_qv(const void *hlm, const void *data, const double *inv_psd, i
     const int64_t qe = cols * n_time;
     hipLaunchKernelGGL(k_qv_reduce, dim3((unsigned)std::min<int64_t>((qe + 255) / 256, 65536)), dim3(256), 0, st,
                        part, ns, cols, n_time, (double2 *)Q);
-    // U, V: band slices so that the grid has about 1024 blocks, the slice
-    // partials held in the Q partial buffer (free once k_qv_reduce has run)
-    const int npair = na * (na + 1) / 2;
-    const int n_dg = (nd + kUvDet - 1) / kUvDet;
-    const int n_pg = (npair + kQvThreads - 1) / kQvThreads;
-    const int cb = (int)std::max<int64_t>(1, std::min<int64_t>(kUvChunk, 32768 / ((int64_t)na * 32 + kUvDet * 8)));
-    const int64_t blocks1 = (int64_t)np * n_dg * n_pg;
-    int64_t n_sl = std::max<int64_t>(1, std::min<int64_t>((1024 + blocks1 - 1) / blocks1, (n_band + 4 * cb - 1) / (4 * cb)));
-    const int64_t part_bytes = (int64_t)ns * cols * n_time * 16;
-    const int64_t per_sl = (int64_t)np * nd * npair * 32;
-    n_sl = std::min<int64_t>(n_sl, std::max<int64_t>(1, part_bytes / per_sl));
-    const int64_t uslice = (n_band + n_sl - 1) / n_sl;
-    n_sl = (n_band + uslice - 1) / uslice;
-    const size_t lds = std::max<size_t>((size_t)cb * ((size_t)na * 32 + kUvDet * 8), (size_t)kQvThreads * kUvDet * 4 * 8);
-    hipLaunchKernelGGL(k_qv_uv, dim3((unsigned)np, (unsigned)n_sl, (unsigned)(n_dg * n_pg)), dim3(kQvThreads), lds, st,
-                       (const double2 *)hlm, inv_psd, band, n_band, n, na, nd, df, uslice, (int)n_sl, cb, n_dg,
-                       (double *)part, (double2 *)U, (double2 *)V);
-    if (n_sl > 1) {
-        const int64_t ue = (int64_t)np * nd * npair;
-        hipLaunchKernelGGL(k_qv_uv_sum, dim3((unsigned)std::min<int64_t>((ue + 255) / 256, 65536)), dim3(256), 0, st,
-                           (const double *)part, (int64_t)np * nd, na, (int)n_sl, df, (double2 *)U, (double2 *)V);
+    launch_uv(hlm, inv_psd, band, n_band, n, na, nd, np, df, (double *)part, (int64_t)ns * cols * n_time * 16, U, V,
+              st);
+    return hipGetLastError();
+}
+
+namespace {
+
+int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// The decimated times p_lo .. p_lo + n_t2 - 1 that the window covers.
+void dec_window(int n_time, int win_half, int radix, int &p_lo, int &n_t2) {
+    p_lo = floor_div(-win_half, radix);
+    n_t2 = floor_div(n_time - 1 - win_half, radix) - p_lo + 1;
+}
+
+}  // namespace
+
+int qv_radix(int64_t n, int64_t n_band, int n_time, int win_half, bool force) {
+    for (int r = 2; r <= 16; r *= 2) {
+        if (n % r != 0) continue;
+        int p_lo, n_t2;
+        dec_window(n_time, win_half, r, p_lo, n_t2);
+        if (n_t2 > kQvTT) continue;
+        if (force) return r;
+        // Cost per column in complex matrix-core products: the direct sum
+        // takes (padded window) x n_band, the decimated one kQvTT x n; a
+        // 16-byte element written and read back once more (Y against X)
+        // costs about as long as 49 of them at the measured rates
+        // (6.1e12 products/s, 4 TB/s).
+        const double direct = (double)((n_time + kQvTT - 1) / kQvTT * kQvTT + 49) * (double)n_band;
+        const double dec = (double)(kQvTT + 49) * (double)n;
+        return dec < direct ? r : 0;
     }
+    return 0;
+}
+
+int qv_dec_slices(int64_t n, int64_t cols, int n_time, int win_half, int radix) {
+    int p_lo, n_t2;
+    dec_window(n_time, win_half, radix, p_lo, n_t2);
+    return qv_slices(n / radix, cols * radix, n_t2);
+}
+
+size_t qv_dec_scratch_bytes(int64_t n, int64_t n_band, int64_t cols, int n_time, int win_half, int radix,
+                            int n_slices) {
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    int p_lo, n_t2;
+    dec_window(n_time, win_half, radix, p_lo, n_t2);
+    return al((size_t)n * 16) + al((size_t)(n / radix) * 16) + al((size_t)n_band * 8) + al((size_t)n * cols * 16) + al((size_t)n_slices * cols * radix * n_t2 * 16);
+}
+
+hipError_t launch_qv_dec(const void *hlm, const void *data, const double *inv_psd, int64_t n, int na, int nd,
+                         int np, double df, double f_lo, double f_hi, const int64_t *h_band, int64_t n_band,
+                         int n_time, int win_half, int radix, void *Q, void *U, void *V, void *scratch,
+                         int n_slices, hipStream_t st) {
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    const int64_t n2 = n / radix;
+    const int64_t cols = (int64_t)np * nd * na;
+    const int64_t cols2 = cols * radix;
+    int p_lo, n_t2;
+    dec_window(n_time, win_half, radix, p_lo, n_t2);
+    char *w = (char *)scratch;
+    double2 *tw = (double2 *)w;
+    w += al((size_t)n * 16);
+    double2 *tw2 = (double2 *)w;
+    w += al((size_t)n2 * 16);
+    int64_t *band = (int64_t *)w;
+    w += al((size_t)n_band * 8);
+    double2 *Y = (double2 *)w;
+    w += al((size_t)n * cols * 16);
+    double2 *part = (double2 *)w;
+    hipError_t e = hipMemcpyAsync(band, h_band, (size_t)n_band * 8, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_qv_twiddle, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tw, n);
+    hipLaunchKernelGGL(k_qv_twiddle, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, tw2, n2);
+    const int64_t n_mt = (n2 + kDecM - 1) / kDecM;
+    const dim3 g1((unsigned)(n_mt * ((cols + kDecC - 1) / kDecC)));
+    switch (radix) {
+    case 2:
+        hipLaunchKernelGGL(k_qv_dec1<2>, g1, dim3(kQvThreads), 0, st, (const double2 *)hlm, (const double2 *)data,
+                           inv_psd, tw, n, na, nd, np, df, f_lo, f_hi, n_mt, Y);
+        break;
+    case 4:
+        hipLaunchKernelGGL(k_qv_dec1<4>, g1, dim3(kQvThreads), 0, st, (const double2 *)hlm, (const double2 *)data,
+                           inv_psd, tw, n, na, nd, np, df, f_lo, f_hi, n_mt, Y);
+        break;
+    case 8:
+        hipLaunchKernelGGL(k_qv_dec1<8>, g1, dim3(kQvThreads), 0, st, (const double2 *)hlm, (const double2 *)data,
+                           inv_psd, tw, n, na, nd, np, df, f_lo, f_hi, n_mt, Y);
+        break;
+    case 16:
+        hipLaunchKernelGGL(k_qv_dec1<16>, g1, dim3(kQvThreads), 0, st, (const double2 *)hlm, (const double2 *)data,
+                           inv_psd, tw, n, na, nd, np, df, f_lo, f_hi, n_mt, Y);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    // the product over the N2 decimated bins (m2 itself as the signed index:
+    // its phase only enters modulo N2) at decimated times p = t + p_lo
+    const int64_t slice = ((n2 + n_slices - 1) / n_slices + kQvKB - 1) / kQvKB * kQvKB;
+    const int ns = (int)((n2 + slice - 1) / slice);
+    const int n_tc = (int)((cols2 + kQvTC - 1) / kQvTC);
+    hipLaunchKernelGGL(k_qv_q, dim3((unsigned)((int64_t)n_tc * ns)), dim3(kQvThreads), 0, st, Y, tw2,
+                       (const int64_t *)nullptr, n2, n2, cols2, n_t2, -p_lo, slice, 1, n_tc, part);
+    const int64_t qe = cols * n_time;
+    hipLaunchKernelGGL(k_qv_dec_reduce, dim3((unsigned)std::min<int64_t>((qe + 255) / 256, 65536)), dim3(256), 0, st,
+                       part, ns, cols, radix, n_t2, n_time, win_half, p_lo, (double2 *)Q);
+    launch_uv(hlm, inv_psd, band, n_band, n, na, nd, np, df, (double *)part, (int64_t)ns * cols2 * n_t2 * 16, U, V,
+              st);
     return hipGetLastError();
 }
 

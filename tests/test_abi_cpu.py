@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI that need no GPU: the library loads, every
 entry point declared in include/ile.h is exported, the binding's struct
-layouts equal the C layouts, and calls fail cleanly without a device."""
+layouts and integer constants equal the C ones, and calls fail cleanly
+without a device."""
 import ctypes as C
 import os
 import re
@@ -56,6 +57,17 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(got[name]) == C.sizeof(cls), name
         for f, _ in cls._fields_:
             assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, f"{name}.{f}"
+
+
+def test_constants_match_header():
+    """Every integer #define of ile.h that the binding also names has the
+    header's value (flags, integrators, pool and overlap routes...)."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    defs = dict(re.findall(r"^#define\s+(ILE_\w+)\s+(\d+)u?\s*$", src, flags=re.M))
+    shared = [k for k in defs if hasattr(ile, k)]
+    assert {"ILE_QV_AUTO", "ILE_QV_DIRECT", "ILE_QV_DECIMATED", "ILE_POOL_MIXTURE", "ILE_INT_AC"} <= set(shared)
+    for k in shared:
+        assert getattr(ile, k) == int(defs[k]), k
 
 
 def test_no_device_is_a_clean_error():

@@ -1,7 +1,9 @@
 """Q, U, V of eq. (QUV) computed on the GPU from modes and data, against the
 oracle's definition: one event (H, L, V; 9 modes; noise), several intrinsic
 points in one call with a per-detector PSD weight, an odd grid length, and the
-precomputed inputs used for the likelihood."""
+precomputed inputs used for the likelihood; both routes for Q (the direct
+windowed sum and the decimated one) on the same inputs, every radix of the
+decimated route, and its refusal where no radix applies."""
 import numpy as np
 import pytest
 
@@ -17,7 +19,7 @@ import paper_2505_11655_amd as ile  # noqa: E402
 from tests import gpu_util as gu  # noqa: E402
 
 
-def _gpu(hlm, data, df, f_lo, f_hi, n_time, win_half, inv_psd=None):
+def _gpu(hlm, data, df, f_lo, f_hi, n_time, win_half, inv_psd=None, route=0):
     h = torch.from_numpy(np.ascontiguousarray(hlm)).to("cuda")
     d = torch.from_numpy(np.ascontiguousarray(data)).to("cuda")
     w = None if inv_psd is None else torch.from_numpy(np.ascontiguousarray(inv_psd)).to("cuda")
@@ -26,7 +28,7 @@ def _gpu(hlm, data, df, f_lo, f_hi, n_time, win_half, inv_psd=None):
     Q = torch.zeros((npnt, nd, na, n_time), dtype=torch.complex128, device="cuda")
     U = torch.zeros((npnt, nd, na, na), dtype=torch.complex128, device="cuda")
     V = torch.zeros((npnt, nd, na, na), dtype=torch.complex128, device="cuda")
-    ile.ile_overlaps(gu.ctx(), h, d, df, f_lo, f_hi, n_time, win_half, Q, U, V, inv_psd=w)
+    ile.ile_overlaps(gu.ctx(), h, d, df, f_lo, f_hi, n_time, win_half, Q, U, V, inv_psd=w, route=route)
     torch.cuda.synchronize()
     return Q.cpu().numpy(), U.cpu().numpy(), V.cpu().numpy()
 
@@ -141,3 +143,61 @@ def test_overlaps_many_modes_and_detectors(orc):
     _close(Vg[0], Vo)
     assert np.array_equal(Ug[0], np.conj(np.transpose(Ug[0], (0, 2, 1))))
     assert np.array_equal(Vg[0], np.transpose(Vg[0], (0, 2, 1)))
+
+
+@pytest.mark.parametrize("route", [ile.ILE_QV_DIRECT, ile.ILE_QV_DECIMATED])
+def test_overlaps_both_routes_event_shape(orc, route):
+    """The benchmark's shape (4 s at 4096 Hz: 16384 bins, 20-1024 Hz, the
+    410-sample window centred) for two points with a PSD weight, forced
+    through each route; the decimated one takes radix 8 here (52 decimated
+    times)."""
+    rng = np.random.default_rng(135)
+    f, df = chirpgen.freq_grid()
+    modes = chirpgen.mode_set(5)
+    hl = np.stack([chirpgen.modes_fd(f, modes, mc, q) for mc, q in ((27.0, 1.3), (35.0, 3.1))])
+    data = rng.normal(size=(3, f.size)) + 1j * rng.normal(size=(3, f.size))
+    w = 1.0 / (1.0 + (np.abs(f)[None, :] / 150.0) ** 2) * rng.uniform(0.5, 1.5, (3, 1))
+    Qg, Ug, Vg = _gpu(hl, data, df, 20.0, 1024.0, 410, 205, inv_psd=w, route=route)
+    for p in range(2):
+        Qo, Uo, Vo = orc.overlaps_qv(hl[p], data, w, df, 20.0, 1024.0, 410, 205)
+        _close(Qg[p], Qo)
+        _close(Ug[p], Uo)
+        _close(Vg[p], Vo)
+
+
+@pytest.mark.parametrize("n,df,n_time,win_half,radix", [
+    (200, 1.0, 1, 0, 2),          # one window time, N2 = 100 (one band slice)
+    (3000, 1.25, 77, 20, 2),      # off-centre window: decimated times -10 .. 28
+    (1024, 2.0, 200, 150, 4),     # window mostly before the reference time
+    (2048, 1.0, 500, 250, 8),
+    (4096, 0.5, 1000, 499, 16),   # 64 decimated times, -32 .. 31
+])
+def test_overlaps_decimated_every_radix(orc, n, df, n_time, win_half, radix):
+    """The decimated route forced on random modes and data for each radix it
+    can take (the smallest power of two in 2..16 dividing n that puts the
+    window on at most 64 decimated times), against the oracle."""
+    r = 2
+    while n % r or (n_time - 1 - win_half) // r - (-win_half) // r + 1 > 64:
+        r *= 2
+    assert r == radix
+    rng = np.random.default_rng(136 + radix)
+    hl = rng.normal(size=(3, n)) + 1j * rng.normal(size=(3, n))
+    data = rng.normal(size=(2, n)) + 1j * rng.normal(size=(2, n))
+    f_hi = 0.45 * n * df
+    Qg, Ug, Vg = _gpu(hl, data, df, 3.0 * df, f_hi, n_time, win_half, route=ile.ILE_QV_DECIMATED)
+    Qo, Uo, Vo = orc.overlaps_qv(hl, data, None, df, 3.0 * df, f_hi, n_time, win_half)
+    _close(Qg[0], Qo)
+    _close(Ug[0], Uo)
+    _close(Vg[0], Vo)
+
+
+def test_overlaps_decimated_refused_without_radix():
+    """A prime grid length has no radix: the forced decimated route is an
+    error (ILE_E_INVALID), and the automatic route still answers."""
+    rng = np.random.default_rng(140)
+    n = 3001
+    hl = rng.normal(size=(2, n)) + 1j * rng.normal(size=(2, n))
+    data = rng.normal(size=(1, n)) + 1j * rng.normal(size=(1, n))
+    with pytest.raises(Exception, match="decimated route"):
+        _gpu(hl, data, 1.0, 5.0, 900.0, 41, 20, route=ile.ILE_QV_DECIMATED)
+    _gpu(hl, data, 1.0, 5.0, 900.0, 41, 20, route=ile.ILE_QV_AUTO)
