@@ -436,8 +436,8 @@ def overlaps_leg(ile, torch, ctx, stream, n_points=256, n_modes=9, n_det=3, reps
     dq = (Qs["direct"] - Qs["decimated"]).abs().max().item() / Qs["direct"].abs().max().item()
     out["decimated_vs_direct_max_rel_diff"] = dq
     out["speedup_gpu"] = out["direct"]["ms_per_call_gpu"] / out["decimated"]["ms_per_call_gpu"]
-    out["note"] = ("direct: 410 x 8034 bins per column on the FP64 matrix cores; decimated: radix-8 partial "
-                   "sums, then 64 x 2048 bins per column (52 window times used); flop figures count the "
+    out["note"] = ("direct: 410 x 8034 bins per column on the FP64 matrix cores; decimated: radix-16 partial "
+                   "sums, then 32 x 1024 bins per column (26 decimated times used); flop figures count the "
                    "direct sum's work")
     del hlm, data, Q, U, V, Qs, busy_a
     torch.cuda.empty_cache()

@@ -409,9 +409,10 @@ ile_status ile_ac_get(ile_job *job, int32_t *n_dim, int32_t *dims, double *pi, i
  *     decimation-in-frequency FFT, as Section "Reduce duplication of inner
  *     products" prefers FFTs to time-domain sums): radix-R partial sums over
  *     the R aliases m2 + N2 a of each bin, then the product over N2 bins at
- *     the decimated times floor((i - win_half) / R) only.  R is the smallest
- *     of 2, 4, 8, 16 that divides n and puts the window on at most 64
- *     decimated times; ILE_E_INVALID when there is none;
+ *     the decimated times floor((i - win_half) / R) only.  R is taken among
+ *     2, 4, 8, 16 dividing n that put the window on at most 64 decimated
+ *     times (one 32- or 64-row tile of the product), by estimated cost;
+ *     ILE_E_INVALID when there is none;
  *   ILE_QV_AUTO: the decimated route when it applies and its estimated cost
  *     is lower, else the direct one.
  * The band lists are staged in pinned memory, so the call does not wait on

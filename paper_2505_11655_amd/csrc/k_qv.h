@@ -7,10 +7,11 @@
 namespace ile {
 
 // The radix R of the decimated route for a grid of n bins, a band of n_band
-// bins and the window (n_time, win_half): the smallest R in {2, 4, 8, 16}
-// that divides n and puts the window on at most 64 decimated times
-// floor((i - win_half) / R), or 0 when there is none.  With `force` false it
-// is also 0 when the route is estimated slower than the direct sum.
+// bins and the window (n_time, win_half): of the R in {2, 4, 8, 16} that
+// divide n and put the window on at most 64 decimated times
+// floor((i - win_half) / R) (one 32- or 64-row time tile), the one of lowest
+// estimated cost, or 0 when there is none.  With `force` false it is also 0
+// when that cost exceeds the direct sum's.
 int qv_radix(int64_t n, int64_t n_band, int n_time, int win_half, bool force);
 
 // Band slices of the decimated route's matrix-core stage and its scratch

@@ -36,9 +36,12 @@ namespace ile {
 namespace {
 
 constexpr int kQvThreads = 256;
-constexpr int kQvTT = 64;     // window times per block tile
+constexpr int kQvTT = 64;     // window times per block tile (direct route)
 constexpr int kQvNS = 4;      // 16-column tiles per wave
-constexpr int kQvTC = 32 * kQvNS;   // columns per block tile (two waves across)
+// columns per block tile: two waves across a 64-time tile, four across a
+// 32-time tile
+constexpr int qv_tc(int tt) { return tt == 64 ? 32 * kQvNS : 64 * kQvNS; }
+constexpr int kQvTC = qv_tc(kQvTT);
 constexpr int kQvKB = 32;     // band bins per LDS stage of phases
 
 __global__ void k_qv_twiddle(double2 *__restrict__ tw, int64_t n) {
@@ -82,18 +85,20 @@ __global__ void __launch_bounds__(kQvThreads)
 }
 
 // Partial Q of one (time tile, column tile, band slice) on the FP64 matrix
-// cores.  A block of four waves covers 64 window times x 128 columns; each
-// wave a 32 x 64 sub-tile as 2 x 4 tiles of 16 x 16 (kQvNS = 4 column tiles),
+// cores.  A block of four waves covers TT = 64 window times x 128 columns (two
+// waves along the times, two along the columns) or TT = 32 times x 256
+// columns (four waves along the columns); each wave a 32 x 64 sub-tile as
+// 2 x 4 tiles of 16 x 16 (kQvNS = 4 column tiles),
 // with the real and the imaginary part of every tile in its own accumulator.
 // One step of v_mfma_f64_16x16x4f64 takes four band bins: lane l holds the A
 // element (time l % 16, bin l / 16) and the B element (bin l / 16, column
 // l % 16), and its four results are times l / 16 + 4 r (r = 0..3) of column
 // l % 16.  Each complex product is four real ones, Re += Er Xr - Ei Xi,
 // Im += Er Xi + Ei Xr.
-// The phases of a stage of 32 bins x 64 times sit in LDS (the two column
-// waves of a time range share them), double-buffered: every thread reads its
-// eight phases of the next stage (one bin, eight consecutive times: one
-// 64-bit remainder, then r += m' mod n per time) from the table during the
+// The phases of a stage of 32 bins x TT times sit in LDS (the column waves of
+// a time range share them), double-buffered: every thread reads its TT / 8
+// phases of the next stage (one bin, TT / 8 consecutive times: one 64-bit
+// remainder, then r += m' mod n per time) from the table during the
 // stage's first matrix step, after that step's X reads (the memory counter
 // retires in order, so waiting for X then never waits for the table), and
 // writes them to LDS after the stage's last step.  X is read by each wave
@@ -102,11 +107,15 @@ __global__ void __launch_bounds__(kQvThreads)
 // XCD and share its L2.
 typedef double qv_d4 __attribute__((ext_vector_type(4)));
 
+template <int TT>
 __global__ void __launch_bounds__(kQvThreads)
     k_qv_q(const double2 *__restrict__ X, const double2 *__restrict__ tw, const int64_t *__restrict__ msig,
            int64_t n_band, int64_t n, int64_t cols, int n_time, int win_half, int64_t slice, int n_tt, int n_tc,
            double2 *__restrict__ part) {
-    __shared__ double2 sE[2][kQvKB][kQvTT];
+    static_assert(TT == 64 || TT == 32, "time tile of 64 or 32");
+    constexpr int TC = qv_tc(TT);
+    constexpr int PT = TT / 8;   // phases per thread and stage
+    __shared__ double2 sE[2][kQvKB][TT];
     const int64_t nb = gridDim.x;
     const int64_t h = blockIdx.x;
     const int64_t lid = nb % 8 == 0 ? (h % 8) * (nb / 8) + h / 8 : h;
@@ -115,14 +124,15 @@ __global__ void __launch_bounds__(kQvThreads)
     const int64_t z = lid / ((int64_t)n_tt * n_tc);
     const int64_t b_lo = z * slice;
     const int64_t b_hi = b_lo + slice < n_band ? b_lo + slice : n_band;
-    const int t0 = tt * kQvTT;
+    const int t0 = tt * TT;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int wt = 32 * (wv & 1);                        // the wave's first time within the tile
-    const int64_t cw = (int64_t)tc * kQvTC + 16 * kQvNS * (wv >> 1);   // the wave's first column
-    // this thread's share of a phase stage: bin gb, times gt .. gt + 7
-    const int gb = threadIdx.x >> 3, gt = (threadIdx.x & 7) * 8;
-    static_assert(kQvThreads * 8 == kQvKB * kQvTT, "eight phases per thread and stage");
+    // the wave's first time within the tile and first column
+    const int wt = TT == 64 ? 32 * (wv & 1) : 0;
+    const int64_t cw = (int64_t)tc * TC + 16 * kQvNS * (TT == 64 ? (wv >> 1) : wv);
+    // this thread's share of a phase stage: bin gb, times gt .. gt + PT - 1
+    const int gb = threadIdx.x >> 3, gt = (threadIdx.x & 7) * PT;
+    static_assert(kQvThreads * PT == kQvKB * TT, "PT phases per thread and stage");
     // m' of the thread's bin in the stage at bb (the bin itself when msig is
     // null); a bin past the slice gets m' = 0 and a zero phase (its X, read
     // at a clamped index, is then multiplied by 0)
@@ -131,16 +141,16 @@ __global__ void __launch_bounds__(kQvThreads)
         f = b < b_hi ? 1.0 : 0.0;
         return b < b_hi ? (msig ? msig[b] : b) : 0;
     };
-    // The thread's eight phases for bin m', r = m' (t - win_half) mod n,
+    // The thread's PT phases for bin m', r = m' (t - win_half) mod n,
     // then r += m' mod n per time (r stays in [0, n)).  Rows past the window
     // need no mask: they are never stored.
-    auto phase_get = [&](int64_t m, double f, double2 (&pv)[8]) {
+    auto phase_get = [&](int64_t m, double f, double2 (&pv)[PT]) {
         int64_t r = (m * (int64_t)(t0 + gt - win_half)) % n;
         r = r < 0 ? r + n : r;
         int64_t step = m % n;
         step = step < 0 ? step + n : step;
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
+        for (int q = 0; q < PT; q++) {
             const double2 w = tw[r];
             pv[q] = make_double2(w.x * f, w.y * f);
             r += step;
@@ -170,12 +180,12 @@ __global__ void __launch_bounds__(kQvThreads)
         }
     };
     {
-        double2 pv[8];
+        double2 pv[PT];
         double f;
         const int64_t m = bin_m(b_lo, f);
         phase_get(m, f, pv);
 #pragma unroll
-        for (int q = 0; q < 8; q++) sE[0][gb][gt + q] = pv[q];
+        for (int q = 0; q < PT; q++) sE[0][gb][gt + q] = pv[q];
     }
     double f_next;
     int64_t m_next = bin_m(b_lo + kQvKB, f_next);   // read one stage before it is used
@@ -186,7 +196,7 @@ __global__ void __launch_bounds__(kQvThreads)
     for (int64_t bb = b_lo; bb < b_hi; bb += kQvKB) {
         const int nk = b_hi - bb < kQvKB ? (int)(b_hi - bb) : kQvKB;
         const bool more = bb + kQvKB < b_hi;
-        double2 pv[8];
+        double2 pv[PT];
         for (int ks = 0; ks < nk; ks += 4) {
             // the next step's X is in flight while this step's products run
             double2 xn[kQvNS];
@@ -216,7 +226,7 @@ __global__ void __launch_bounds__(kQvThreads)
         }
         if (more) {
 #pragma unroll
-            for (int q = 0; q < 8; q++) sE[buf ^ 1][gb][gt + q] = pv[q];
+            for (int q = 0; q < PT; q++) sE[buf ^ 1][gb][gt + q] = pv[q];
         }
         __syncthreads();
         buf ^= 1;
@@ -253,9 +263,10 @@ __global__ void k_qv_reduce(const double2 *__restrict__ part, int n_slices, int6
 // m2 in [0, N2), from the R aliases m2 + N2 a (X = 2 df conj(h) d w on the
 // band's bins, 0 elsewhere).  A block covers kDecM consecutive m2 (the lanes
 // of a wave, so that every read of a mode row, the data and the weight is
-// one contiguous run) by kDecC columns (one per wave).  The R outputs of
-// each (m2, column) go to LDS, and the tile's rows, kDecC R contiguous
-// elements each, are written out from there in contiguous runs.
+// one contiguous run) by kDecC columns (one per wave).  The outputs of each
+// (m2, column) go through LDS, at most eight q at a time (two passes for
+// R = 16, which keeps the block's LDS near 33 KB), and the tile's rows are
+// written out from there in runs of whole cache lines.
 constexpr int kDecM = 64;
 constexpr int kDecC = kQvThreads / 64;
 template <int R>
@@ -263,7 +274,8 @@ __global__ void __launch_bounds__(kQvThreads)
     k_qv_dec1(const double2 *__restrict__ hlm, const double2 *__restrict__ data, const double *__restrict__ inv_psd,
               const double2 *__restrict__ tw, int64_t n, int na, int nd, int np, double df, double f_lo, double f_hi,
               int64_t n_mt, double2 *__restrict__ Y) {
-    constexpr int RW = kDecC * R + 1;   // LDS row (one element of padding)
+    constexpr int QC = R < 8 ? R : 8;       // q per LDS pass
+    constexpr int RW = kDecC * QC + 1;      // LDS row (one element of padding)
     __shared__ double2 sY[kDecM * RW];
     const int64_t cols = (int64_t)np * nd * na;
     const int64_t n2 = n / R;
@@ -271,7 +283,9 @@ __global__ void __launch_bounds__(kQvThreads)
     const int64_t m2_0 = mt * kDecM, col0 = ct * kDecC;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t m2 = m2_0 + lane, col = col0 + wv;
-    if (m2 < n2 && col < cols) {
+    const bool live = m2 < n2 && col < cols;
+    double2 yq[R];
+    if (live) {
         const int a = (int)(col % na);
         const int k = (int)((col / na) % nd);
         const int64_t p = col / ((int64_t)na * nd);
@@ -312,14 +326,24 @@ __global__ void __launch_bounds__(kQvThreads)
                 im += x[al].x * e.y + x[al].y * e.x;
             }
             const double2 t = tw[m2 * q];   // m2 q < n
-            sY[lane * RW + wv * R + q] = make_double2(re * t.x - im * t.y, re * t.y + im * t.x);
+            yq[q] = make_double2(re * t.x - im * t.y, re * t.y + im * t.x);
         }
     }
-    __syncthreads();
-    const int64_t nc = cols - col0 < kDecC ? (cols - col0) * R : (int64_t)kDecC * R;
-    for (int e = threadIdx.x; e < kDecM * kDecC * R; e += kQvThreads) {
-        const int row = e / (kDecC * R), c = e % (kDecC * R);
-        if (m2_0 + row < n2 && c < nc) Y[(m2_0 + row) * cols * R + col0 * R + c] = sY[row * RW + c];
+    const int64_t ncol = cols - col0 < kDecC ? cols - col0 : kDecC;
+#pragma unroll
+    for (int h = 0; h < R / QC; h++) {
+        if (h > 0) __syncthreads();   // the previous pass's reads are done
+        if (live) {
+#pragma unroll
+            for (int q = 0; q < QC; q++) sY[lane * RW + wv * QC + q] = yq[h * QC + q];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kDecM * kDecC * QC; e += kQvThreads) {
+            const int row = e / (kDecC * QC), c = e % (kDecC * QC);
+            const int cl = c / QC, q = h * QC + c % QC;
+            if (m2_0 + row < n2 && cl < ncol)
+                Y[(m2_0 + row) * cols * R + (col0 + cl) * R + q] = sY[row * RW + c];
+        }
     }
 }
 
@@ -513,12 +537,14 @@ size_t qv_scratch_bytes(int64_t n, int64_t n_band, int64_t cols, int n_time, int
            al((size_t)n_slices * cols * n_time * 16);
 }
 
+namespace {
+
 // Band slices per call: at least two rounds of resident blocks (256 CUs x 2
 // blocks of k_qv_q), at least 128 bins per slice, and the fewest slices whose
 // last round is at least 90 % full.
-int qv_slices(int64_t n_band, int64_t cols, int n_time) {
+
+int slices_for(int64_t n_band, int64_t tiles) {
     constexpr int64_t kResident = 256 * 2;
-    const int64_t tiles = (int64_t)((n_time + kQvTT - 1) / kQvTT) * ((cols + kQvTC - 1) / kQvTC);
     int64_t smax = (n_band + 127) / 128;
     smax = smax < 1 ? 1 : smax;
     int64_t best = 1;
@@ -534,6 +560,12 @@ int qv_slices(int64_t n_band, int64_t cols, int n_time) {
         }
     }
     return (int)best;
+}
+
+}  // namespace
+
+int qv_slices(int64_t n_band, int64_t cols, int n_time) {
+    return slices_for(n_band, (int64_t)((n_time + kQvTT - 1) / kQvTT) * ((cols + kQvTC - 1) / kQvTC));
 }
 
 hipError_t launch_qv(const void *hlm, const void *data, const double *inv_psd, int64_t n, int na, int nd, int np,
@@ -563,7 +595,7 @@ hipError_t launch_qv(const void *hlm, const void *data, const double *inv_psd, i
     const int ns = (int)((n_band + slice - 1) / slice);
     const int n_tt = (n_time + kQvTT - 1) / kQvTT;
     const int n_tc = (int)((cols + kQvTC - 1) / kQvTC);
-    hipLaunchKernelGGL(k_qv_q, dim3((unsigned)((int64_t)n_tt * n_tc * ns)), dim3(kQvThreads), 0, st, X, tw, msig,
+    hipLaunchKernelGGL(k_qv_q<kQvTT>, dim3((unsigned)((int64_t)n_tt * n_tc * ns)), dim3(kQvThreads), 0, st, X, tw, msig,
                        n_band, n, cols, n_time, win_half, slice, n_tt, n_tc, part);
     const int64_t qe = cols * n_time;
     hipLaunchKernelGGL(k_qv_reduce, dim3((unsigned)std::min<int64_t>((qe + 255) / 256, 65536)), dim3(256), 0, st,
@@ -583,31 +615,44 @@ void dec_window(int n_time, int win_half, int radix, int &p_lo, int &n_t2) {
     n_t2 = floor_div(n_time - 1 - win_half, radix) - p_lo + 1;
 }
 
+// The decimated times' tile height (32 or 64; 0 when they do not fit one).
+int dec_tile(int n_t2) { return n_t2 <= 32 ? 32 : (n_t2 <= 64 ? 64 : 0); }
+
+// Cost per column in complex matrix-core products: the direct sum takes
+// (padded window) x n_band; the decimated one (tile height) x n for the
+// product, about 49 per bin for the radix partial sums' 16-byte element
+// written and read back (Y against X), at the measured rates (6.1e12
+// products/s, 4 TB/s), and 2R per bin for their R-point sums on the vector
+// units.
+double dec_cost(int64_t n, int tile, int radix) { return (double)(tile + 49 + 2 * radix) * (double)n; }
+
 }  // namespace
 
 int qv_radix(int64_t n, int64_t n_band, int n_time, int win_half, bool force) {
+    int best = 0;
+    double best_cost = 0.0;
     for (int r = 2; r <= 16; r *= 2) {
         if (n % r != 0) continue;
         int p_lo, n_t2;
         dec_window(n_time, win_half, r, p_lo, n_t2);
-        if (n_t2 > kQvTT) continue;
-        if (force) return r;
-        // Cost per column in complex matrix-core products: the direct sum
-        // takes (padded window) x n_band, the decimated one kQvTT x n; a
-        // 16-byte element written and read back once more (Y against X)
-        // costs about as long as 49 of them at the measured rates
-        // (6.1e12 products/s, 4 TB/s).
-        const double direct = (double)((n_time + kQvTT - 1) / kQvTT * kQvTT + 49) * (double)n_band;
-        const double dec = (double)(kQvTT + 49) * (double)n;
-        return dec < direct ? r : 0;
+        const int tile = dec_tile(n_t2);
+        if (tile == 0) continue;
+        const double c = dec_cost(n, tile, r);
+        if (best == 0 || c < best_cost) {
+            best = r;
+            best_cost = c;
+        }
     }
-    return 0;
+    if (best == 0 || force) return best;
+    const double direct = (double)((n_time + kQvTT - 1) / kQvTT * kQvTT + 49) * (double)n_band;
+    return best_cost < direct ? best : 0;
 }
 
 int qv_dec_slices(int64_t n, int64_t cols, int n_time, int win_half, int radix) {
     int p_lo, n_t2;
     dec_window(n_time, win_half, radix, p_lo, n_t2);
-    return qv_slices(n / radix, cols * radix, n_t2);
+    const int64_t tc = qv_tc(dec_tile(n_t2));
+    return slices_for(n / radix, (cols * radix + tc - 1) / tc);
 }
 
 size_t qv_dec_scratch_bytes(int64_t n, int64_t n_band, int64_t cols, int n_time, int win_half, int radix,
@@ -668,9 +713,16 @@ hipError_t launch_qv_dec(const void *hlm, const void *data, const double *inv_ps
     // its phase only enters modulo N2) at decimated times p = t + p_lo
     const int64_t slice = ((n2 + n_slices - 1) / n_slices + kQvKB - 1) / kQvKB * kQvKB;
     const int ns = (int)((n2 + slice - 1) / slice);
-    const int n_tc = (int)((cols2 + kQvTC - 1) / kQvTC);
-    hipLaunchKernelGGL(k_qv_q, dim3((unsigned)((int64_t)n_tc * ns)), dim3(kQvThreads), 0, st, Y, tw2,
-                       (const int64_t *)nullptr, n2, n2, cols2, n_t2, -p_lo, slice, 1, n_tc, part);
+    const int tile = dec_tile(n_t2);
+    const int n_tc = (int)((cols2 + qv_tc(tile) - 1) / qv_tc(tile));
+    if (tile == 32)
+        hipLaunchKernelGGL(k_qv_q<32>, dim3((unsigned)((int64_t)n_tc * ns)), dim3(kQvThreads), 0, st, Y, tw2,
+                           (const int64_t *)nullptr, n2, n2, cols2, n_t2, -p_lo, slice, 1, n_tc, part);
+    else if (tile == 64)
+        hipLaunchKernelGGL(k_qv_q<64>, dim3((unsigned)((int64_t)n_tc * ns)), dim3(kQvThreads), 0, st, Y, tw2,
+                           (const int64_t *)nullptr, n2, n2, cols2, n_t2, -p_lo, slice, 1, n_tc, part);
+    else
+        return hipErrorInvalidValue;
     const int64_t qe = cols * n_time;
     hipLaunchKernelGGL(k_qv_dec_reduce, dim3((unsigned)std::min<int64_t>((qe + 255) / 256, 65536)), dim3(256), 0, st,
                        part, ns, cols, radix, n_t2, n_time, win_half, p_lo, (double2 *)Q);

@@ -149,8 +149,8 @@ def test_overlaps_many_modes_and_detectors(orc):
 def test_overlaps_both_routes_event_shape(orc, route):
     """The benchmark's shape (4 s at 4096 Hz: 16384 bins, 20-1024 Hz, the
     410-sample window centred) for two points with a PSD weight, forced
-    through each route; the decimated one takes radix 8 here (52 decimated
-    times)."""
+    through each route; the decimated one takes radix 16 here (26 decimated
+    times in a 32-row tile)."""
     rng = np.random.default_rng(135)
     f, df = chirpgen.freq_grid()
     modes = chirpgen.mode_set(5)
@@ -165,22 +165,36 @@ def test_overlaps_both_routes_event_shape(orc, route):
         _close(Vg[p], Vo)
 
 
-@pytest.mark.parametrize("n,df,n_time,win_half,radix", [
-    (200, 1.0, 1, 0, 2),          # one window time, N2 = 100 (one band slice)
-    (3000, 1.25, 77, 20, 2),      # off-centre window: decimated times -10 .. 28
-    (1024, 2.0, 200, 150, 4),     # window mostly before the reference time
-    (2048, 1.0, 500, 250, 8),
-    (4096, 0.5, 1000, 499, 16),   # 64 decimated times, -32 .. 31
+def _dec_choice(n, n_time, win_half):
+    """The radix and tile height the decimated route takes: of R in 2..16
+    dividing n whose decimated window fits one 32- or 64-row tile, the lowest
+    tile + 49 + 2R."""
+    best = None
+    for r in (2, 4, 8, 16):
+        if n % r:
+            continue
+        nt = (n_time - 1 - win_half) // r - (-win_half) // r + 1
+        tile = 32 if nt <= 32 else 64 if nt <= 64 else 0
+        if tile and (best is None or tile + 49 + 2 * r < best[0]):
+            best = (tile + 49 + 2 * r, r, tile)
+    return best[1:]
+
+
+@pytest.mark.parametrize("n,df,n_time,win_half,radix,tile", [
+    (200, 1.0, 1, 0, 2, 32),         # one window time, N2 = 100 (one band slice)
+    (1002, 1.0, 100, 50, 2, 64),
+    (3000, 1.25, 77, 20, 4, 32),     # off-centre window: decimated times -5 .. 14
+    (1004, 2.0, 200, 100, 4, 64),
+    (1024, 2.0, 200, 150, 8, 32),    # window mostly before the reference time
+    (3000, 1.0, 400, 200, 8, 64),
+    (2048, 1.0, 500, 250, 16, 32),
+    (4096, 0.5, 1000, 499, 16, 64),  # 64 decimated times, -32 .. 31
 ])
-def test_overlaps_decimated_every_radix(orc, n, df, n_time, win_half, radix):
-    """The decimated route forced on random modes and data for each radix it
-    can take (the smallest power of two in 2..16 dividing n that puts the
-    window on at most 64 decimated times), against the oracle."""
-    r = 2
-    while n % r or (n_time - 1 - win_half) // r - (-win_half) // r + 1 > 64:
-        r *= 2
-    assert r == radix
-    rng = np.random.default_rng(136 + radix)
+def test_overlaps_decimated_every_radix(orc, n, df, n_time, win_half, radix, tile):
+    """The decimated route forced on random modes and data for every radix
+    and both tile heights of its matrix-core product, against the oracle."""
+    assert _dec_choice(n, n_time, win_half) == (radix, tile)
+    rng = np.random.default_rng(136 + radix + tile)
     hl = rng.normal(size=(3, n)) + 1j * rng.normal(size=(3, n))
     data = rng.normal(size=(2, n)) + 1j * rng.normal(size=(2, n))
     f_hi = 0.45 * n * df
