@@ -269,6 +269,44 @@ __global__ void k_qv_reduce(const double2 *__restrict__ part, int n_slices, int6
 // written out from there in runs of whole cache lines.
 constexpr int kDecM = 64;
 constexpr int kDecC = kQvThreads / 64;
+
+// In place, v[q] <- sum_a v[a] e^{2 pi i a q / R} (R a power of two): radix-2
+// decimation in time over the bit-reversed inputs, log2 R passes of R / 2
+// butterflies, wr[r] = e^{2 pi i r / R}; a butterfly with twiddle 1 skips its
+// product.
+template <int R>
+__device__ __forceinline__ void dft_radix2(double2 (&v)[R], const double2 (&wr)[R]) {
+    constexpr int LG = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+    static_assert((1 << LG) == R, "R in {2, 4, 8, 16}");
+#pragma unroll
+    for (int a = 0; a < R; a++) {
+        int b = 0;
+#pragma unroll
+        for (int k = 0; k < LG; k++) b |= ((a >> k) & 1) << (LG - 1 - k);
+        if (a < b) {
+            const double2 t = v[a];
+            v[a] = v[b];
+            v[b] = t;
+        }
+    }
+#pragma unroll
+    for (int len = 2; len <= R; len <<= 1) {
+        const int half = len / 2, step = R / len;
+#pragma unroll
+        for (int st = 0; st < R; st += len)
+#pragma unroll
+            for (int j = 0; j < half; j++) {
+                const double2 u = v[st + j], x = v[st + j + half];
+                double2 t = x;
+                if (j != 0) {
+                    const double2 w = wr[j * step];
+                    t = make_double2(x.x * w.x - x.y * w.y, x.x * w.y + x.y * w.x);
+                }
+                v[st + j] = make_double2(u.x + t.x, u.y + t.y);
+                v[st + j + half] = make_double2(u.x - t.x, u.y - t.y);
+            }
+    }
+}
 template <int R>
 __global__ void __launch_bounds__(kQvThreads)
     k_qv_dec1(const double2 *__restrict__ hlm, const double2 *__restrict__ data, const double *__restrict__ inv_psd,
@@ -279,7 +317,12 @@ __global__ void __launch_bounds__(kQvThreads)
     __shared__ double2 sY[kDecM * RW];
     const int64_t cols = (int64_t)np * nd * na;
     const int64_t n2 = n / R;
-    const int64_t mt = (int64_t)blockIdx.x % n_mt, ct = (int64_t)blockIdx.x / n_mt;
+    // blocks numbered so that consecutive tiles run on one XCD: the columns
+    // of one mode row for the other detectors (na columns apart) then find
+    // its lines in that XCD's L2
+    const int64_t nbk = gridDim.x, hb = blockIdx.x;
+    const int64_t lid = nbk % 8 == 0 ? (hb % 8) * (nbk / 8) + hb / 8 : hb;
+    const int64_t mt = lid % n_mt, ct = lid / n_mt;
     const int64_t m2_0 = mt * kDecM, col0 = ct * kDecC;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t m2 = m2_0 + lane, col = col0 + wv;
@@ -316,17 +359,14 @@ __global__ void __launch_bounds__(kQvThreads)
             const double2 hh = hv[al], d = dv[al];
             x[al] = make_double2((hh.x * d.x + hh.y * d.y) * w, (hh.x * d.y - hh.y * d.x) * w);
         }
+        double2 wr[R];   // e^{2 pi i r / R}
+#pragma unroll
+        for (int r = 0; r < R; r++) wr[r] = tw[(int64_t)r * n2];
+        dft_radix2<R>(x, wr);
 #pragma unroll
         for (int q = 0; q < R; q++) {
-            double re = 0.0, im = 0.0;
-#pragma unroll
-            for (int al = 0; al < R; al++) {
-                const double2 e = tw[(int64_t)((al * q) % R) * n2];   // e^{2 pi i a q / R}
-                re += x[al].x * e.x - x[al].y * e.y;
-                im += x[al].x * e.y + x[al].y * e.x;
-            }
-            const double2 t = tw[m2 * q];   // m2 q < n
-            yq[q] = make_double2(re * t.x - im * t.y, re * t.y + im * t.x);
+            const double2 t = tw[m2 * q];   // e^{2 pi i m2 q / n}, m2 q < n
+            yq[q] = make_double2(x[q].x * t.x - x[q].y * t.y, x[q].x * t.y + x[q].y * t.x);
         }
     }
     const int64_t ncol = cols - col0 < kDecC ? cols - col0 : kDecC;
