@@ -418,7 +418,7 @@ __global__ void k_qv_dec_reduce(const double2 *__restrict__ part, int n_slices, 
 // in lane order, and the slices in slice order by k_qv_uv_sum (with one slice
 // the block writes U and V itself).  Deterministic for a given launch shape.
 constexpr int kUvDet = 4;
-constexpr int kUvChunk = 32;   // bins per LDS chunk (fewer for many modes)
+constexpr int kUvChunk = 128;  // bins per LDS chunk (fewer for many modes)
 
 __device__ __forceinline__ void uv_pair(int q, int na, int &a, int &b) {
     a = 0;
@@ -551,7 +551,7 @@ void launch_uv(const void *hlm, const double *inv_psd, const int64_t *band, int6
     const int npair = na * (na + 1) / 2;
     const int n_dg = (nd + kUvDet - 1) / kUvDet;
     const int n_pg = (npair + kQvThreads - 1) / kQvThreads;
-    const int cb = (int)std::max<int64_t>(1, std::min<int64_t>(kUvChunk, 32768 / ((int64_t)na * 32 + kUvDet * 8)));
+    const int cb = (int)std::max<int64_t>(1, std::min<int64_t>(kUvChunk, 49152 / ((int64_t)na * 32 + kUvDet * 8)));
     const int64_t blocks1 = (int64_t)np * n_dg * n_pg;
     int64_t n_sl = std::max<int64_t>(1, std::min<int64_t>((1024 + blocks1 - 1) / blocks1, (n_band + 4 * cb - 1) / (4 * cb)));
     const int64_t per_sl = (int64_t)np * nd * npair * 32;
