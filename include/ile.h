@@ -414,7 +414,9 @@ ile_status ile_ac_get(ile_job *job, int32_t *n_dim, int32_t *dims, double *pi, i
  *     times (one 32- or 64-row tile of the product), by estimated cost;
  *     ILE_E_INVALID when there is none;
  *   ILE_QV_AUTO: the decimated route when it applies and its estimated cost
- *     is lower, else the direct one.
+ *     is lower, else the direct one; also the direct one when the decimated
+ *     route's scratch (16 B per grid bin and column, against 16 B per band
+ *     bin and column) cannot be allocated within the context's budget.
  * The band lists are staged in pinned memory, so the call does not wait on
  * the stream before its final synchronisation. */
 #define ILE_QV_AUTO 0

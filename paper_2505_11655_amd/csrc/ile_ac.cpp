@@ -173,19 +173,31 @@ extern "C" ile_status ile_overlaps(ile_ctx *ctx, const ile_qv_shape *sh, const v
             return set_err(ILE_E_INVALID, "decimated route needs a radix in {2, 4, 8, 16} dividing n_freq that "
                                           "puts the window on at most 64 decimated times");
     }
-    const int ns = radix ? qv_dec_slices(n, cols, sh->n_time, sh->win_half, radix)
-                         : qv_slices(n_band, cols, sh->n_time);
-    const size_t need = radix ? qv_dec_scratch_bytes(n, n_band, cols, sh->n_time, sh->win_half, radix, ns)
-                              : qv_scratch_bytes(n, n_band, cols, sh->n_time, ns);
+    auto plan = [&](int r, int &ns_, size_t &need_) {
+        ns_ = r ? qv_dec_slices(n, cols, sh->n_time, sh->win_half, r) : qv_slices(n_band, cols, sh->n_time);
+        need_ = r ? qv_dec_scratch_bytes(n, n_band, cols, sh->n_time, sh->win_half, r, ns_)
+                  : qv_scratch_bytes(n, n_band, cols, sh->n_time, ns_);
+    };
+    int ns = 0;
+    size_t need = 0;
+    plan(radix, ns, need);
+    void *scratch = nullptr;
+    s = ctx_alloc(ctx, &scratch, need, "overlap scratch");
+    if (s != ILE_OK && radix && sh->route == ILE_QV_AUTO) {
+        // the decimated route's partial sums (n per column) do not fit where
+        // the direct route's X (n_band per column) may: take the direct route
+        radix = 0;
+        plan(radix, ns, need);
+        s = ctx_alloc(ctx, &scratch, need, "overlap scratch");
+    }
+    if (s != ILE_OK) return s;
     // the band lists go through pinned staging, so that nothing in the call
     // waits for the stream before the final synchronisation
     const size_t stage_bytes = (size_t)n_band * (radix ? 8 : 16);
     char *stage = (char *)pin_alloc(ctx, stage_bytes);
-    if (!stage) return set_err(ILE_E_NOMEM, "pinned staging");
-    void *scratch = nullptr;
-    if ((s = ctx_alloc(ctx, &scratch, need, "overlap scratch")) != ILE_OK) {
-        pin_free(ctx, stage, stage_bytes);
-        return s;
+    if (!stage) {
+        ctx_free(ctx, scratch, need);
+        return set_err(ILE_E_NOMEM, "pinned staging");
     }
     std::memcpy(stage, band.data(), (size_t)n_band * 8);
     hipStream_t st = (hipStream_t)stream;

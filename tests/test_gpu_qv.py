@@ -215,3 +215,39 @@ def test_overlaps_decimated_refused_without_radix():
     with pytest.raises(Exception, match="decimated route"):
         _gpu(hl, data, 1.0, 5.0, 900.0, 41, 20, route=ile.ILE_QV_DECIMATED)
     _gpu(hl, data, 1.0, 5.0, 900.0, 41, 20, route=ile.ILE_QV_AUTO)
+
+
+def test_overlaps_auto_falls_back_to_direct_within_budget(orc):
+    """A context whose device budget holds the direct route's scratch but not
+    the decimated route's: 96 points x 9 modes x 3 detectors on the
+    16384-bin event grid need about 480 MiB through the direct sum (X over
+    8034 band bins, 10 band slices) and about 700 MiB through the decimated
+    one (the partial sums over all 16384 bins), allocated in power-of-two
+    classes of 512 MiB and 1 GiB; the budget is 768 MiB.  The forced
+    decimated route reports the budget; the automatic route answers through
+    the direct sum (two points checked against the oracle)."""
+    rng = np.random.default_rng(141)
+    f, df = chirpgen.freq_grid()
+    n = f.size
+    npt, na, nd = 96, 9, 3
+    hl = rng.normal(size=(npt, na, n)) + 1j * rng.normal(size=(npt, na, n))
+    data = rng.normal(size=(nd, n)) + 1j * rng.normal(size=(nd, n))
+    ctx = ile.ile_ctx_create(0, 768 * 2 ** 20)
+    try:
+        h = torch.from_numpy(hl).to("cuda")
+        d = torch.from_numpy(data).to("cuda")
+        Q = torch.zeros((npt, nd, na, 410), dtype=torch.complex128, device="cuda")
+        U = torch.zeros((npt, nd, na, na), dtype=torch.complex128, device="cuda")
+        V = torch.zeros_like(U)
+        with pytest.raises(Exception, match="budget"):
+            ile.ile_overlaps(ctx, h, d, df, 20.0, 1024.0, 410, 205, Q, U, V, route=ile.ILE_QV_DECIMATED)
+        ile.ile_overlaps(ctx, h, d, df, 20.0, 1024.0, 410, 205, Q, U, V, route=ile.ILE_QV_AUTO)
+        torch.cuda.synchronize()
+        Qg, Ug, Vg = Q.cpu().numpy(), U.cpu().numpy(), V.cpu().numpy()
+    finally:
+        ile.ile_ctx_destroy(ctx)
+    for p in (0, npt - 1):
+        Qo, Uo, Vo = orc.overlaps_qv(hl[p], data, None, df, 20.0, 1024.0, 410, 205)
+        _close(Qg[p], Qo)
+        _close(Ug[p], Uo)
+        _close(Vg[p], Vo)
