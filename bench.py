@@ -462,6 +462,10 @@ def cpu_baseline(probs, budget_s=15.0):
     lw = oracle.lnL(probs[1 % len(probs)], th, threads=threads)
     oracle.marginalize(lw)
     dt = time.perf_counter() - t0
+    m_one = 1 << 13
+    t0 = time.perf_counter()
+    oracle.lnL(probs[1 % len(probs)], th[:, :m_one], threads=1)
+    c2_one = m_one / (time.perf_counter() - t0)
     per_config = {}
     for label, cp, m1 in (("c1_hl5", config_problems("c1")[0], 1 << 20),
                           ("c3_hlv17_snr100", config_problems("c3")[0], 1 << 18)):
@@ -475,9 +479,16 @@ def cpu_baseline(probs, budget_s=15.0):
         d_one = time.perf_counter() - t1
         per_config[label] = {"samples_per_s_all_cores": m1 / d_all, "samples_per_s_one_thread": m_one / d_one,
                              "samples": m1}
+    host = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            host = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), host)
+    except OSError:
+        pass
     return {"value": n / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} prior samples of one intrinsic point of the same workload (lnL + estimator), "
                       f"FP64, OpenMP {threads} threads, {dt:.1f} s",
+            "samples_per_s_one_thread": c2_one, "host_cpu": host,
             "per_config": per_config}
 
 
