@@ -22,6 +22,8 @@
 // carries a mixture.  Mixture columns are addressed through select chains on
 // the (uniform) column index, so every per-sample array stays in registers.
 #include "ile_sincos.h"
+#include <type_traits>
+
 #include "ile_internal.h"
 
 namespace ile {
@@ -170,10 +172,12 @@ __device__ __forceinline__ void mix_coords(const MixCols &mc, const PriorDev &pr
 // (the component loop is uniform) and applied row by row to every sample; a
 // periodic offset is wrapped as u - P rint(u / P) (the floor form's value
 // except at exactly half a period, where both images are equally far).
-template <int NS, bool FAST = false>
+// D > 0: the mixture's dimension count fixed at compile time (it must equal
+// mc.d), which removes the per-dimension tests from the unrolled loops.
+template <int NS, bool FAST = false, int D = 0>
 __device__ __forceinline__ void mix_log_ratio(cgmm &g, const MixCols &mc, const double (&xm)[NS][7],
                                               const double (&lpm)[NS], double (&t)[NS]) {
-    const int d = mc.d;
+    const int d = D > 0 ? D : mc.d;
     const double c0 = -0.5 * d * log(2 * kPi);
     double mm[NS], ss[NS];
 #pragma unroll
@@ -318,15 +322,26 @@ __device__ __forceinline__ void draw_range(const DrawJob &J, int64_t begin, int6
     // the scalar cache
     cgmm &g = *(cgmm *)J.gmm;
     const MixCols mc = mix_cols(g);
-    for (int64_t s = begin + threadIdx.x; s < end; s += kDrawThreads) {
-        double th[1][7], xm[1][7], lpm[1], t[1];
-        draw_mix(J, *J.gmm, (uint64_t)(J.first + s), th[0]);
-        mix_coords(mc, J.pr, th[0], xm[0], lpm[0]);
-        mix_log_ratio<1>(g, mc, xm, lpm, t);
+    // the common dimension counts (six with the distance integrated, seven
+    // otherwise) compiled as constants
+    auto samples = [&](auto D_) {
+        constexpr int D = decltype(D_)::value;
+        for (int64_t s = begin + threadIdx.x; s < end; s += kDrawThreads) {
+            double th[1][7], xm[1][7], lpm[1], t[1];
+            draw_mix(J, *J.gmm, (uint64_t)(J.first + s), th[0]);
+            mix_coords(mc, J.pr, th[0], xm[0], lpm[0]);
+            mix_log_ratio<1, false, D>(g, mc, xm, lpm, t);
 #pragma unroll
-        for (int c = 0; c < 7; c++) th_out[c * J.ld + s] = (TT)th[0][c];
-        if (lr_out) lr_out[s] = (TT)(-t[0]);
-    }
+            for (int c = 0; c < 7; c++) th_out[c * J.ld + s] = (TT)th[0][c];
+            if (lr_out) lr_out[s] = (TT)(-t[0]);
+        }
+    };
+    if (mc.d == 6)
+        samples(std::integral_constant<int, 6>{});
+    else if (mc.d == 7)
+        samples(std::integral_constant<int, 7>{});
+    else
+        samples(std::integral_constant<int, 0>{});
 }
 
 template <class TT, bool MIX>
@@ -395,15 +410,24 @@ __global__ void __launch_bounds__(kDrawThreads)
         q0[k] = i >= end ? r + 1 : (fresh ? 1 : r);
     }
     const int qlo = end > first_new ? 1 : r;
-    for (int q = qlo; q <= r; q++) {
-        double t[kPoolSpt];
-        // the FP32 policy's pooled weights need FP32 relative accuracy only
-        constexpr bool kFast = sizeof(TO) == 4;
-        mix_log_ratio<kPoolSpt, kFast>(hist[q], mc, xm, lpm, t);
+    // the FP32 policy's pooled weights need FP32 relative accuracy only
+    constexpr bool kFast = sizeof(TO) == 4;
+    auto proposals = [&](auto D_) {
+        constexpr int D = decltype(D_)::value;
+        for (int q = qlo; q <= r; q++) {
+            double t[kPoolSpt];
+            mix_log_ratio<kPoolSpt, kFast, D>(hist[q], mc, xm, lpm, t);
 #pragma unroll
-        for (int k = 0; k < kPoolSpt; k++)
-            if (q >= q0[k]) lse_add<kFast>(m[k], sum[k], t[k]);
-    }
+            for (int k = 0; k < kPoolSpt; k++)
+                if (q >= q0[k]) lse_add<kFast>(m[k], sum[k], t[k]);
+        }
+    };
+    if (mc.d == 6)
+        proposals(std::integral_constant<int, 6>{});
+    else if (mc.d == 7)
+        proposals(std::integral_constant<int, 7>{});
+    else
+        proposals(std::integral_constant<int, 0>{});
 #pragma unroll
     for (int k = 0; k < kPoolSpt; k++) {
         const int64_t i = begin + threadIdx.x + (int64_t)k * kDrawThreads;
