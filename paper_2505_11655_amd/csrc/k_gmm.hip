@@ -17,6 +17,8 @@
 // Every kernel serves a batch of jobs (blockIdx.z = job): the refits of all
 // jobs of a serving pass are one launch per stage.  Per-sample stages tile
 // each job's samples (kEmTile per block); per-job stages are one block each.
+#include <type_traits>
+
 #include "ile_internal.h"
 
 #include <algorithm>
@@ -460,18 +462,22 @@ __global__ void k_gmm_factor(const EmJob *__restrict__ jobs, int only_first) {
 // Responsibilities times weights, R_ij = w_i pi_j N_j(x_i) / sum_k pi_k N_k(x_i).
 // The block stages its job's mixture (means, packed inverse factors and the
 // constant ln pi_j - ln det^(1/2) - d/2 ln 2pi) in LDS.
-template <class TT, class TL>
-__global__ void __launch_bounds__(kEmThreads) k_em_resp(const EmJob *__restrict__ jobs) {
-    const EmJob &J = jobs[blockIdx.z];
+// The EM kernels take the mixture's dimension count D as a compile-time
+// constant for the common counts (six with the distance integrated, seven
+// otherwise; D = 0: the count read at run time), which removes the
+// per-dimension tests from their unrolled loops.  A kernel compiled for D
+// checks the mixture's count and runs the general body for any other.
+template <class TT, class TL, int D>
+__device__ __forceinline__ void em_resp_body(const EmJob &J, double (&s_mean)[kMaxComp][7],
+                                             double (&s_li)[kMaxComp][28], double (&s_c)[kMaxComp],
+                                             double (&s_lr)[kMaxComp][kEmThreads]) {
     const EmLayout Lo = em_layout(J.n);
     const TT *__restrict__ th = (const TT *)J.theta;
     const TL *__restrict__ lw = (const TL *)J.lw;
     const GmmDev *g = J.gmm;
     double *R = J.work + Lo.R;
     const int64_t n = J.n;
-    const int d = g->n_dim, nc = g->n_comp;
-    __shared__ double s_mean[kMaxComp][7], s_li[kMaxComp][28], s_c[kMaxComp];
-    __shared__ double s_lr[kMaxComp][kEmThreads];   // per-thread ln pi_j N_j, then e^{. - max}
+    const int d = D > 0 ? D : g->n_dim, nc = g->n_comp;
     for (int t = threadIdx.x; t < kMaxComp * 28; t += kEmThreads) {
         const int j = t / 28, k = t % 28;
         int a = 0;
@@ -543,19 +549,28 @@ __global__ void __launch_bounds__(kEmThreads) k_em_resp(const EmJob *__restrict_
     }
 }
 
+template <class TT, class TL, int D>
+__global__ void __launch_bounds__(kEmThreads) k_em_resp(const EmJob *__restrict__ jobs) {
+    const EmJob &J = jobs[blockIdx.z];
+    __shared__ double s_mean[kMaxComp][7], s_li[kMaxComp][28], s_c[kMaxComp];
+    __shared__ double s_lr[kMaxComp][kEmThreads];   // per-thread ln pi_j N_j, then e^{. - max}
+    if (D > 0 && J.gmm->n_dim == D)
+        em_resp_body<TT, TL, D>(J, s_mean, s_li, s_c, s_lr);
+    else
+        em_resp_body<TT, TL, 0>(J, s_mean, s_li, s_c, s_lr);
+}
+
 // W_j, first and second moments of the offsets D = wrap(x - mu_j) about the
 // current mean, per tile (one pass: the covariance centred on the mean offset
 // m_j is S2/W - m_j m_j^T, the same quantity as the centred two-pass sum)
-template <class TT>
-__global__ void __launch_bounds__(kEmThreads) k_em_stat(const EmJob *__restrict__ jobs) {
-    const EmJob &J = jobs[blockIdx.z];
+template <class TT, int D>
+__device__ __forceinline__ void em_stat_body(const EmJob &J) {
     const EmLayout Lo = em_layout(J.n);
     const GmmDev *g = J.gmm;
     const int j = blockIdx.y;
-    if (blockIdx.x >= Lo.nblk || j >= g->n_comp) return;
     const TT *__restrict__ th = (const TT *)J.theta;
     const double *R = J.work + Lo.R;
-    const int d = g->n_dim;
+    const int d = D > 0 ? D : g->n_dim;
     double mu[7], P[7];
     int col[7];
 #pragma unroll
@@ -587,14 +602,29 @@ __global__ void __launch_bounds__(kEmThreads) k_em_stat(const EmJob *__restrict_
         for (int a = 0; a < 7; a++) x[a] = (a < d) ? wrapd(v[a] - mu[a], P[a]) : 0.0;
         acc[0] += r;
         int k = 1;
+        // with D fixed the moments of absent dimensions are skipped: they
+        // stay 0, as the sums of r x 0 they replace
 #pragma unroll
-        for (int a = 0; a < 7; a++) acc[k++] += r * x[a];
+        for (int a = 0; a < 7; a++, k++)
+            if (D == 0 || a < D) acc[k] += r * x[a];
 #pragma unroll
         for (int a = 0; a < 7; a++)
 #pragma unroll
-            for (int b = 0; b <= a; b++) acc[k++] += r * x[a] * x[b];
+            for (int b = 0; b <= a; b++, k++)
+                if (D == 0 || a < D) acc[k] += r * x[a] * x[b];
     }
     block_sum<36>(acc, J.work + Lo.stat + ((size_t)j * Lo.nblk + blockIdx.x) * 36);
+}
+
+template <class TT, int D>
+__global__ void __launch_bounds__(kEmThreads) k_em_stat(const EmJob *__restrict__ jobs) {
+    const EmJob &J = jobs[blockIdx.z];
+    const EmLayout Lo = em_layout(J.n);
+    if (blockIdx.x >= Lo.nblk || (int)blockIdx.y >= J.gmm->n_comp) return;
+    if (D > 0 && J.gmm->n_dim == D)
+        em_stat_body<TT, D>(J);
+    else
+        em_stat_body<TT, 0>(J);
 }
 
 // M-step: weights, means (old mean + offset, wrapped into the period),
@@ -642,7 +672,7 @@ __global__ void k_em_update(const EmJob *__restrict__ jobs) {
     factor_one(*g, j);
 }
 
-template <class TT, class TL>
+template <class TT, class TL, int D>
 void launch_em_t(const EmJob *d_jobs, int n_jobs, int64_t nblk_max, int64_t rblk, bool any_first, int n_iter,
                  hipStream_t st) {
     const dim3 jz(1, 1, n_jobs), tiles(nblk_max, 1, n_jobs);
@@ -659,8 +689,8 @@ void launch_em_t(const EmJob *d_jobs, int n_jobs, int64_t nblk_max, int64_t rblk
     }
     const dim3 comp(nblk_max, kMaxComp, n_jobs);
     for (int it = 0; it < n_iter; it++) {
-        hipLaunchKernelGGL((k_em_resp<TT, TL>), dim3(rblk, 1, n_jobs), dim3(kEmThreads), 0, st, d_jobs);
-        hipLaunchKernelGGL((k_em_stat<TT>), comp, dim3(kEmThreads), 0, st, d_jobs);
+        hipLaunchKernelGGL((k_em_resp<TT, TL, D>), dim3(rblk, 1, n_jobs), dim3(kEmThreads), 0, st, d_jobs);
+        hipLaunchKernelGGL((k_em_stat<TT, D>), comp, dim3(kEmThreads), 0, st, d_jobs);
         hipLaunchKernelGGL(k_em_update, jz, dim3(64), 0, st, d_jobs);
     }
 }
@@ -689,12 +719,26 @@ hipError_t launch_em_batch(int policy, const EmJob *d_jobs, const EmJob *h_jobs,
     }
     const int64_t rblk = std::min<int64_t>((nmax + kEmThreads - 1) / kEmThreads, 4096);
     if (nblk_max > INT32_MAX) return hipErrorInvalidValue;
-    if (policy == kFP64)
-        launch_em_t<double, double>(d_jobs, n_jobs, nblk_max, rblk, any_first, n_iter, st);
-    else if (policy == kFP32)
-        launch_em_t<float, float>(d_jobs, n_jobs, nblk_max, rblk, any_first, n_iter, st);
+    // the mixtures' dimension count, when every job of the batch shares it
+    // (each mixture takes its job's default columns; the kernels check)
+    int dim = h_jobs[0].n_dim;
+    for (int k = 1; k < n_jobs; k++)
+        if (h_jobs[k].n_dim != dim) dim = 0;
+    auto go = [&](auto D_) {
+        constexpr int D = decltype(D_)::value;
+        if (policy == kFP64)
+            launch_em_t<double, double, D>(d_jobs, n_jobs, nblk_max, rblk, any_first, n_iter, st);
+        else if (policy == kFP32)
+            launch_em_t<float, float, D>(d_jobs, n_jobs, nblk_max, rblk, any_first, n_iter, st);
+        else
+            launch_em_t<float, double, D>(d_jobs, n_jobs, nblk_max, rblk, any_first, n_iter, st);
+    };
+    if (dim == 6)
+        go(std::integral_constant<int, 6>{});
+    else if (dim == 7)
+        go(std::integral_constant<int, 7>{});
     else
-        launch_em_t<float, double>(d_jobs, n_jobs, nblk_max, rblk, any_first, n_iter, st);
+        go(std::integral_constant<int, 0>{});
     return hipGetLastError();
 }
 
