@@ -227,6 +227,9 @@ __device__ __forceinline__ void mix_log_ratio(cgmm &g, const MixCols &mc, const 
 // One candidate from component j: words w[0..15] give four Box-Muller pairs.
 // On acceptance the mixture columns of th are overwritten; on rejection th is
 // left as it was.
+// D > 0: the mixture's dimension count as a compile-time constant (it must
+// equal g.n_dim).
+template <int D = 0>
 __device__ __forceinline__ bool gmm_candidate(const GmmDev &g, const PriorDev &pr, int j, const uint32_t *w,
                                               double th[7]) {
     double z[8];
@@ -239,7 +242,7 @@ __device__ __forceinline__ bool gmm_candidate(const GmmDev &g, const PriorDev &p
         z[2 * p] = r * c;
         z[2 * p + 1] = r * s;
     }
-    const int d = g.n_dim;
+    const int d = D > 0 ? D : g.n_dim;
     double x[7];
 #pragma unroll
     for (int a = 0; a < 7; a++) {
@@ -272,6 +275,7 @@ __device__ __forceinline__ bool gmm_candidate(const GmmDev &g, const PriorDev &p
 }
 
 // Mixture draw of sample idx (theta only; the density follows for a pair).
+template <int D = 0>
 __device__ __forceinline__ void draw_mix(const DrawJob &J, const GmmDev &g, uint64_t idx, double th[7]) {
     uint32_t w[20];
     words(J.seed, idx, J.round, 0, 0, 5, w);
@@ -292,7 +296,7 @@ __device__ __forceinline__ void draw_mix(const DrawJob &J, const GmmDev &g, uint
         for (int a = 1; a <= kMaxAttempts && jsel >= 0; a++) {
             uint32_t wa[16];
             words(J.seed, idx, J.round, (uint32_t)a, 1, 4, wa);
-            if (gmm_candidate(g, J.pr, jsel, wa, th)) {
+            if (gmm_candidate<D>(g, J.pr, jsel, wa, th)) {
                 // accepted in the mixture's coordinates: back to psi
                 if (g.shear) th[6] = shear_phase(th[6], th[5], -g.shear);
                 break;
@@ -328,7 +332,7 @@ __device__ __forceinline__ void draw_range(const DrawJob &J, int64_t begin, int6
         constexpr int D = decltype(D_)::value;
         for (int64_t s = begin + threadIdx.x; s < end; s += kDrawThreads) {
             double th[1][7], xm[1][7], lpm[1], t[1];
-            draw_mix(J, *J.gmm, (uint64_t)(J.first + s), th[0]);
+            draw_mix<D>(J, *J.gmm, (uint64_t)(J.first + s), th[0]);
             mix_coords(mc, J.pr, th[0], xm[0], lpm[0]);
             mix_log_ratio<1, false, D>(g, mc, xm, lpm, t);
 #pragma unroll
