@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(kQvThreads)
         // the host's (|m' df| in [f_lo, f_hi], m' the signed index), and a
         // mode value off the band is not read
         double2 hv[R], dv[R];
-        double wv8[R];
+        double wpsd[R];
         bool inb[R];
 #pragma unroll
         for (int al = 0; al < R; al++) {
@@ -350,12 +350,12 @@ __global__ void __launch_bounds__(kQvThreads)
             hv[al] = make_double2(0.0, 0.0);
             if (inb[al]) hv[al] = h[m];
             dv[al] = dk[m];
-            wv8[al] = wk ? wk[m] : 1.0;
+            wpsd[al] = wk ? wk[m] : 1.0;
         }
         double2 x[R];
 #pragma unroll
         for (int al = 0; al < R; al++) {
-            const double w = inb[al] ? 2.0 * df * wv8[al] : 0.0;
+            const double w = inb[al] ? 2.0 * df * wpsd[al] : 0.0;
             const double2 hh = hv[al], d = dv[al];
             x[al] = make_double2((hh.x * d.x + hh.y * d.y) * w, (hh.x * d.y - hh.y * d.x) * w);
         }
