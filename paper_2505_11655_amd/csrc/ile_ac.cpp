@@ -4,6 +4,7 @@
 // device memory.
 #include <cmath>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "ile_ctx.h"
@@ -182,6 +183,7 @@ extern "C" ile_status ile_overlaps(ile_ctx *ctx, const ile_qv_shape *sh, const v
     size_t need = 0;
     plan(radix, ns, need);
     void *scratch = nullptr;
+    const std::string prev_err = ile_last_error();   // kept if the fallback succeeds
     s = ctx_alloc(ctx, &scratch, need, "overlap scratch");
     if (s != ILE_OK && radix && sh->route == ILE_QV_AUTO) {
         // the decimated route's partial sums (n per column) do not fit where
@@ -189,6 +191,7 @@ extern "C" ile_status ile_overlaps(ile_ctx *ctx, const ile_qv_shape *sh, const v
         radix = 0;
         plan(radix, ns, need);
         s = ctx_alloc(ctx, &scratch, need, "overlap scratch");
+        if (s == ILE_OK) set_err(ILE_OK, prev_err);
     }
     if (s != ILE_OK) return s;
     // the band lists go through pinned staging, so that nothing in the call

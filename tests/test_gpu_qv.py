@@ -241,7 +241,13 @@ def test_overlaps_auto_falls_back_to_direct_within_budget(orc):
         V = torch.zeros_like(U)
         with pytest.raises(Exception, match="budget"):
             ile.ile_overlaps(ctx, h, d, df, 20.0, 1024.0, 410, 205, Q, U, V, route=ile.ILE_QV_DECIMATED)
+        with pytest.raises(Exception, match="bad overlap route"):
+            ile.ile_overlaps(ctx, h, d, df, 20.0, 1024.0, 410, 205, Q, U, V, route=7)
+        before = ile.lib().ile_last_error()
         ile.ile_overlaps(ctx, h, d, df, 20.0, 1024.0, 410, 205, Q, U, V, route=ile.ILE_QV_AUTO)
+        # the fallback's failed first allocation is not reported as an error:
+        # the last failing call is still the one with the bad route
+        assert ile.lib().ile_last_error() == before == b"bad overlap route"
         torch.cuda.synchronize()
         Qg, Ug, Vg = Q.cpu().numpy(), U.cpu().numpy(), V.cpu().numpy()
     finally:
