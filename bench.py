@@ -519,6 +519,8 @@ def main():
                     help="run only the Q, U, V precompute leg (256 points) and print its summary")
     ap.add_argument("--adaptive-integrator", choices=["gmm", "av", "ac", "gmm_pool", "all"], default="all",
                     help="proposal of the adaptive serving leg(s)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the saturated plain serving leg (FP32, --serving-jobs up to 2000) and print it")
     ap.add_argument("--configs-only", action="store_true",
                     help="run only the C1 / C3 configuration legs and print their summary")
     ap.add_argument("--no-configs", action="store_true")
@@ -558,6 +560,11 @@ def main():
     integrators = {"gmm": [0], "av": [1], "ac": [2], "gmm_pool": [3], "all": [0, 1, 2, 3]}[a.adaptive_integrator]
     leg_name = {0: "adaptive_saturated", 1: "adaptive_av_saturated", 2: "adaptive_ac_saturated",
                 3: "adaptive_pooled_saturated"}
+    if a.serving_only:
+        pool = serving_pool(64, 250511655 + 4)
+        sat = serving_leg(ile, ctx, pool, min(2000, a.serving_jobs), False, 11, ile.ILE_FP32)
+        print(json.dumps({"plain_saturated": sat}), flush=True)
+        return
     if a.adaptive_only:
         pool = serving_pool(8, 250511655 + 4)
         out = {}

@@ -462,7 +462,9 @@ ile_status ile_fair_draw(ile_job *job, int64_t n, const void *lw, uint64_t seed,
  * (Appendix "Timing analysis"): jobs are admitted by device footprint and
  * their draws, likelihoods, estimators and refits are batched per pass. */
 typedef struct {
-    int32_t max_active;       /* jobs resident at once (default 64) */
+    int32_t max_active;       /* jobs evaluated per pass (default 64); up to as
+                                 many more are admitted (prepared, uploaded,
+                                 holding their footprint) while a pass runs */
     size_t hbm_budget_bytes;  /* 0: the context's budget */
     int64_t chunk_samples;    /* samples per job per scheduling pass (default 1<<20) */
     int32_t record_samples;   /* 0 */
@@ -518,6 +520,8 @@ ile_status ile_server_submit(ile_server *srv, const ile_problem *problem, const 
 ile_status ile_server_poll(ile_server *srv, uint64_t job_id, ile_result *out);
 ile_status ile_server_wait(ile_server *srv, uint64_t job_id, int64_t timeout_ms, ile_result *out);
 ile_status ile_server_cancel(ile_server *srv, uint64_t job_id);
+/* active: admitted jobs (those of the current pass and those prepared for
+ * the next); queued: waiting for admission; done: finished. */
 ile_status ile_server_stats(ile_server *srv, int64_t *active, int64_t *queued, int64_t *done);
 void ile_server_destroy(ile_server *srv);
 

@@ -14,7 +14,11 @@
 //      whose round cap is hit), refit the proposal of the others from this
 //      round's samples, free finished jobs' memory, post their results.
 // Jobs that arrive while a pass runs are admitted in the next pass, so their
-// work overlaps with the jobs already on the device.  Every quantity a job
+// work overlaps with the jobs already on the device.  With a backlog, queued
+// jobs are also admitted while a pass's kernels run (before its one
+// synchronisation): their host preparation overlaps the device work, their
+// uploads follow the pass on the stream, and they join the active set at the
+// next pass in arrival order.  Every quantity a job
 // computes depends only on its own inputs, key and chunk sizes (draw counters,
 // per-sample likelihood, fixed estimator tiles), so its result is bitwise the
 // same alone or in any mix.
@@ -85,6 +89,7 @@ struct ile_server {
     bool stop = false;
     uint64_t next_id = 1;
     std::deque<Req *> queue;
+    std::vector<Req *> ready;    // admitted during a pass; active from the next one
     std::vector<Req *> active;
     std::unordered_map<uint64_t, std::unique_ptr<Req>> all;
     int64_t n_done = 0;
@@ -206,6 +211,34 @@ ile_status admit(ile_server *s, Req *r) {
     return ILE_OK;
 }
 
+int max_active_of(const ile_server *s) { return s->opts.max_active > 0 ? s->opts.max_active : 256; }
+
+// Admit queued jobs while a pass's kernels run, up to max_active of them, in
+// arrival order and within the budget (a cancelled job at the front waits for
+// the scheduler, which finishes it).  Only with a backlog of at least
+// max_active queued jobs: the preparation delays the pass's own results, which
+// pays when the device would otherwise wait for the next admissions
+// (saturated streams), not under light load, where it only adds latency.
+void pre_admit(ile_server *s) {
+    const int maxa = max_active_of(s);
+    std::unique_lock<std::mutex> lk(s->mu);
+    if ((int)s->queue.size() < maxa) return;
+    while (!s->queue.empty() && (int)s->ready.size() < maxa && !s->failed && !s->stop) {
+        Req *r = s->queue.front();
+        if (r->cancel || s->used + r->footprint > s->budget) break;
+        s->queue.pop_front();
+        s->used += r->footprint;
+        lk.unlock();
+        const ile_status st = admit(s, r);
+        lk.lock();
+        if (st != ILE_OK) {
+            finish(s, r, st, nullptr);
+            continue;
+        }
+        s->ready.push_back(r);
+    }
+}
+
 // One scheduling pass over the active set.  Returns false on a device error.
 bool run_pass(ile_server *s, std::vector<Req *> &act) {
     hipStream_t st = s->stream;
@@ -304,6 +337,8 @@ bool run_pass(ile_server *s, std::vector<Req *> &act) {
         for (int pol = 0; pol < 3; pol++)
             if (!pj[pol].empty() && pool_batch(s->ctx, pol, pj[pol], st) != ILE_OK) return false;
     }
+    // the next jobs' host preparation overlaps the kernels queued so far
+    pre_admit(s);
     // estimator, grouped by lw type (float for FP32, double otherwise)
     std::vector<ile_marg> res(act.size());
     for (int g = 0; g < 2; g++) {
@@ -432,7 +467,7 @@ void scheduler(ile_server *s) {
         std::vector<Req *> act;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
+            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->ready.empty() || !s->active.empty(); });
             if (s->stop) break;
             // cancelled jobs still in the queue
             for (auto it = s->queue.begin(); it != s->queue.end();) {
@@ -443,8 +478,21 @@ void scheduler(ile_server *s) {
                     ++it;
                 }
             }
-            const int maxa = s->opts.max_active > 0 ? s->opts.max_active : 256;
-            while (!s->queue.empty() && (int)s->active.size() < maxa && !s->failed) {
+            const int maxa = max_active_of(s);
+            // jobs admitted during the last pass join first (they arrived earlier)
+            size_t nr = 0;
+            for (; nr < s->ready.size(); nr++) {
+                Req *r = s->ready[nr];
+                if (r->cancel) {
+                    finish(s, r, ILE_E_CANCELLED, nullptr);
+                    continue;
+                }
+                if ((int)s->active.size() >= maxa) break;
+                r->state = kActive;
+                s->active.push_back(r);
+            }
+            s->ready.erase(s->ready.begin(), s->ready.begin() + (std::ptrdiff_t)nr);
+            while (s->ready.empty() && !s->queue.empty() && (int)s->active.size() < maxa && !s->failed) {
                 Req *r = s->queue.front();
                 if (s->used + r->footprint > s->budget) break;   // arrival order: wait for memory
                 s->queue.pop_front();
@@ -469,6 +517,8 @@ void scheduler(ile_server *s) {
             s->failed = true;
             for (Req *r : s->active) finish(s, r, ILE_E_DEVICE, nullptr);
             s->active.clear();
+            for (Req *r : s->ready) finish(s, r, ILE_E_DEVICE, nullptr);
+            s->ready.clear();
             for (Req *r : s->queue) finish(s, r, ILE_E_DEVICE, nullptr);
             s->queue.clear();
             s->cv_done.notify_all();
@@ -604,7 +654,7 @@ extern "C" ile_status ile_server_cancel(ile_server *s, uint64_t id) {
 extern "C" ile_status ile_server_stats(ile_server *s, int64_t *active, int64_t *queued, int64_t *done) {
     if (!s) return set_err(ILE_E_INVALID, "null server");
     std::lock_guard<std::mutex> lk(s->mu);
-    if (active) *active = (int64_t)s->active.size();
+    if (active) *active = (int64_t)(s->active.size() + s->ready.size());
     if (queued) *queued = (int64_t)s->queue.size();
     if (done) *done = s->n_done;
     return ILE_OK;
@@ -616,6 +666,7 @@ extern "C" void ile_server_destroy(ile_server *s) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
         for (Req *r : s->queue) r->cancel = true;
+        for (Req *r : s->ready) r->cancel = true;
         for (Req *r : s->active) r->cancel = true;
     }
     s->cv_work.notify_all();
@@ -625,8 +676,10 @@ extern "C" void ile_server_destroy(ile_server *s) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
         for (Req *r : s->active) finish(s, r, ILE_E_CANCELLED, nullptr);
+        for (Req *r : s->ready) finish(s, r, ILE_E_CANCELLED, nullptr);
         for (Req *r : s->queue) finish(s, r, ILE_E_CANCELLED, nullptr);
         s->active.clear();
+        s->ready.clear();
         s->queue.clear();
     }
     s->cv_done.notify_all();
