@@ -94,6 +94,15 @@ struct ile_server {
     std::unordered_map<uint64_t, std::unique_ptr<Req>> all;
     int64_t n_done = 0;
     hipStream_t stream = nullptr;
+    // Input uploads of the jobs admitted while a pass runs: a stream of their
+    // own, so that the copies run beside the pass's kernels instead of after
+    // them; the next pass waits for them through up_ev.  Jobs admitted
+    // between passes upload on `stream` itself, where a wait across streams
+    // would only add latency.  Created at the first admission during a pass,
+    // so a server that never has a backlog runs on one stream.
+    hipStream_t up = nullptr;
+    hipEvent_t up_ev = nullptr;
+    bool up_pending = false;   // uploads queued on `up` since the last wait (scheduler thread only)
     bool failed = false;
 };
 
@@ -153,6 +162,11 @@ void finish(ile_server *s, Req *r, int status, const ile_marg *m) {
     r->res.samples = r->done;
     r->res.t_finish_ns = now_ns();
     if (r->job) {
+        // a job that never joined a pass may still have its uploads in flight
+        if (r->res.t_start_ns == 0) {
+            if (s->up) (void)hipStreamSynchronize(s->up);
+            (void)hipStreamSynchronize(s->stream);
+        }
         const int policy = r->prob.precision;
         ctx_free(s->ctx, r->d_theta, (size_t)7 * r->chunk * theta_bytes(policy));
         ctx_free(s->ctx, r->d_lr, (size_t)r->chunk * theta_bytes(policy));
@@ -181,18 +195,20 @@ void finish(ile_server *s, Req *r, int status, const ile_marg *m) {
     r->V.clear(); r->V.shrink_to_fit();
 }
 
-// Admit one request: prepare its job and allocate its pass buffers.
-ile_status admit(ile_server *s, Req *r) {
+// Admit one request: prepare its job and allocate its pass buffers; its
+// uploads go on `up` (s->up during a pass, s->stream between passes).
+ile_status admit(ile_server *s, Req *r, hipStream_t up) {
     ile_job *job = nullptr;
-    ile_status st = job_create(s->ctx, &r->prob, &job, s->stream, true);
+    if (up != s->stream) s->up_pending = true;
+    ile_status st = job_create(s->ctx, &r->prob, &job, up, true);
     if (st != ILE_OK) return st;
     r->job = job;
     r->chunk = chunk_of(s, r);
     const int policy = r->prob.precision;
     const size_t tb = theta_bytes(policy);
-    if (r->jo.adaptive && r->jo.integrator == ILE_INT_AV && (st = av_ensure(job, r->chunk, s->stream)) != ILE_OK)
+    if (r->jo.adaptive && r->jo.integrator == ILE_INT_AV && (st = av_ensure(job, r->chunk, up)) != ILE_OK)
         return st;
-    if (r->jo.adaptive && r->jo.integrator == ILE_INT_AC && (st = ac_ensure(job, s->stream)) != ILE_OK) return st;
+    if (r->jo.adaptive && r->jo.integrator == ILE_INT_AC && (st = ac_ensure(job, up)) != ILE_OK) return st;
     if ((st = ctx_alloc(s->ctx, &r->d_theta, (size_t)7 * r->chunk * tb, "theta")) != ILE_OK) return st;
     if ((st = ctx_alloc(s->ctx, &r->d_lr, (size_t)r->chunk * tb, "ln p - ln ps")) != ILE_OK) return st;
     if ((st = ctx_alloc(s->ctx, &r->d_lw, (size_t)r->chunk * lw_bytes(policy), "lw")) != ILE_OK) return st;
@@ -219,6 +235,24 @@ int max_active_of(const ile_server *s) { return s->opts.max_active > 0 ? s->opts
 // max_active queued jobs: the preparation delays the pass's own results, which
 // pays when the device would otherwise wait for the next admissions
 // (saturated streams), not under light load, where it only adds latency.
+// The upload stream, created on first use; the pass stream if that fails.
+hipStream_t upload_stream(ile_server *s) {
+    if (s->up) return s->up;
+    if (hipStreamCreateWithFlags(&s->up, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        s->up = nullptr;
+        return s->stream;
+    }
+    if (hipEventCreateWithFlags(&s->up_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamDestroy(s->up);
+        s->up = nullptr;
+        s->up_ev = nullptr;
+        return s->stream;
+    }
+    return s->up;
+}
+
 void pre_admit(ile_server *s) {
     const int maxa = max_active_of(s);
     std::unique_lock<std::mutex> lk(s->mu);
@@ -229,7 +263,7 @@ void pre_admit(ile_server *s) {
         s->queue.pop_front();
         s->used += r->footprint;
         lk.unlock();
-        const ile_status st = admit(s, r);
+        const ile_status st = admit(s, r, upload_stream(s));
         lk.lock();
         if (st != ILE_OK) {
             finish(s, r, st, nullptr);
@@ -242,6 +276,11 @@ void pre_admit(ile_server *s) {
 // One scheduling pass over the active set.  Returns false on a device error.
 bool run_pass(ile_server *s, std::vector<Req *> &act) {
     hipStream_t st = s->stream;
+    if (s->up_pending) {   // the inputs of the jobs admitted since the last pass
+        if (hipEventRecord(s->up_ev, s->up) != hipSuccess || hipStreamWaitEvent(st, s->up_ev, 0) != hipSuccess)
+            return false;
+        s->up_pending = false;
+    }
     const int64_t t_start = now_ns();
     // draws, grouped by theta type
     std::vector<DrawJob> d32, d64;
@@ -498,7 +537,7 @@ void scheduler(ile_server *s) {
                 s->queue.pop_front();
                 s->used += r->footprint;
                 lk.unlock();
-                ile_status st = admit(s, r);
+                ile_status st = admit(s, r, s->stream);
                 lk.lock();
                 if (st != ILE_OK) {
                     finish(s, r, st, nullptr);
@@ -512,7 +551,9 @@ void scheduler(ile_server *s) {
         s->cv_done.notify_all();
         if (act.empty()) continue;
         if (!run_pass(s, act)) {
-            (void)hipStreamSynchronize(s->stream);   // nothing queued may still use freed buffers
+            // nothing queued may still use freed buffers
+            if (s->up) (void)hipStreamSynchronize(s->up);
+            (void)hipStreamSynchronize(s->stream);
             std::lock_guard<std::mutex> lk(s->mu);
             s->failed = true;
             for (Req *r : s->active) finish(s, r, ILE_E_DEVICE, nullptr);
@@ -672,6 +713,7 @@ extern "C" void ile_server_destroy(ile_server *s) {
     s->cv_work.notify_all();
     if (s->th.joinable()) s->th.join();
     (void)hipSetDevice(s->ctx->device);
+    if (s->up) (void)hipStreamSynchronize(s->up);
     (void)hipStreamSynchronize(s->stream);
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -683,6 +725,8 @@ extern "C" void ile_server_destroy(ile_server *s) {
         s->queue.clear();
     }
     s->cv_done.notify_all();
+    if (s->up_ev) (void)hipEventDestroy(s->up_ev);
+    if (s->up) (void)hipStreamDestroy(s->up);
     (void)hipStreamDestroy(s->stream);
     delete s;
 }
