@@ -99,7 +99,7 @@ struct ile_server {
     // them; the next pass waits for them through up_ev.  Jobs admitted
     // between passes upload on `stream` itself, where a wait across streams
     // would only add latency.  Created at the first admission during a pass,
-    // so a server that never has a backlog runs on one stream.
+    // so a server that never admits during a pass runs on one stream.
     hipStream_t up = nullptr;
     hipEvent_t up_ev = nullptr;
     bool up_pending = false;   // uploads queued on `up` since the last wait (scheduler thread only)
@@ -229,12 +229,6 @@ ile_status admit(ile_server *s, Req *r, hipStream_t up) {
 
 int max_active_of(const ile_server *s) { return s->opts.max_active > 0 ? s->opts.max_active : 256; }
 
-// Admit queued jobs while a pass's kernels run, up to max_active of them, in
-// arrival order and within the budget (a cancelled job at the front waits for
-// the scheduler, which finishes it).  Only with a backlog of at least
-// max_active queued jobs: the preparation delays the pass's own results, which
-// pays when the device would otherwise wait for the next admissions
-// (saturated streams), not under light load, where it only adds latency.
 // The upload stream, created on first use; the pass stream if that fails.
 hipStream_t upload_stream(ile_server *s) {
     if (s->up) return s->up;
@@ -253,10 +247,16 @@ hipStream_t upload_stream(ile_server *s) {
     return s->up;
 }
 
+// Admit queued jobs while a pass's kernels run, up to max_active of them, in
+// arrival order and within the budget (a cancelled job at the front waits for
+// the scheduler, which finishes it).  Every queued job would be admitted
+// before the next pass anyway; here its host preparation overlaps the pass's
+// kernels and its uploads run on the upload stream beside them, so nothing is
+// queued on the pass stream ahead of the pass's own estimator.
 void pre_admit(ile_server *s) {
     const int maxa = max_active_of(s);
     std::unique_lock<std::mutex> lk(s->mu);
-    if ((int)s->queue.size() < maxa) return;
+    if (s->queue.empty()) return;
     while (!s->queue.empty() && (int)s->ready.size() < maxa && !s->failed && !s->stop) {
         Req *r = s->queue.front();
         if (r->cancel || s->used + r->footprint > s->budget) break;
