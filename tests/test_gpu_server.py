@@ -215,6 +215,50 @@ def test_cancel(pool):
     assert rs.status == 0
 
 
+def test_cancel_admitted_during_pass(pool):
+    """Jobs admitted while a long job's passes run (inputs uploaded beside the
+    pass) and then cancelled before their first pass: their buffers go back
+    to the pool only after those uploads, so the jobs that run on, and a later
+    server on the same context, equal their solo results to the bit."""
+    specs = [(pool[k % len(pool)], ile.ILE_FP32, False, 1 << 14, 4000 + k, 0) for k in range(12)]
+    long_spec = (pool[2], ile.ILE_FP64, False, 1 << 22, 4100, 0)
+    srv = ile.ile_server_create(gu.ctx(), max_active=2, chunk_samples=1 << 14)
+    try:
+        lid, _ = _submit(srv, long_spec)
+        ids = [_submit(srv, s)[0] for s in specs]
+        for i in ids[1::2]:
+            ile.ile_server_cancel(srv, i)
+        res = [ile.ile_server_wait(srv, i, 120000) for i in ids]
+        ile.ile_server_cancel(srv, lid)
+        ile.ile_server_wait(srv, lid, 120000)
+    finally:
+        ile.ile_server_destroy(srv)
+    # a server destroyed with admitted jobs still waiting for their first pass
+    srv = ile.ile_server_create(gu.ctx(), max_active=2, chunk_samples=1 << 14)
+    try:
+        _submit(srv, long_spec)
+        for s in specs:
+            _submit(srv, s)
+        time.sleep(0.02)
+    finally:
+        ile.ile_server_destroy(srv)
+    for k, s in enumerate(specs):
+        if k % 2 == 1:
+            assert res[k].status in (0, -6)
+            continue
+        solo = ile.ile_server_create(gu.ctx(), max_active=1, chunk_samples=1 << 14)
+        try:
+            jid, _ = _submit(solo, s)
+            alone = _res(ile.ile_server_wait(solo, jid, 120000))
+        finally:
+            ile.ile_server_destroy(solo)
+        got = _res(res[k])
+        assert got["status"] == 0 and alone["status"] == 0
+        for f in FIELDS + ["rounds", "samples"]:
+            a, b = got[f], alone[f]
+            assert a == b or (isinstance(a, float) and np.isnan(a) and np.isnan(b)), (k, f, a, b)
+
+
 def test_adaptive_job():
     """Adaptive rounds: stops at n_eff >= target or at the round cap; the
     estimate agrees with a long plain prior run within the combined errors.
